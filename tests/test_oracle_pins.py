@@ -1,0 +1,438 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: brute force on a dense copy,
+exact integer arithmetic, a closed form, a library routine, or an identity the
+paper states (Section 2: NUJDS with unroll = number of diagonals is CRS in the
+permuted basis; RBJDS with block size 1 is row by row; plain JDS is the
+block-size-n limit; JDS, NUJDS and NBJDS share one storage).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def lap():
+    r, c, v, n, _ = synth.laplacian3d(20)
+    return oracle.csr_from_coo(n, n, r, c, v)
+
+
+def rand_csr(seed, n_rows=40, n_cols=50, density=0.15, integer=False, empty=0.1, long_rows=0,
+             long_len=0):
+    rng = np.random.default_rng(seed)
+    r, c, v, nr, nc = synth.random_pattern(n_rows, n_cols, density, rng, integer=integer,
+                                           empty_rows=empty, long_rows=long_rows, long_len=long_len)
+    return oracle.csr_from_coo(nr, nc, r, c, v), rng
+
+
+def dense_of(A):
+    M = np.zeros((A.n_rows, A.n_cols))
+    rows = A.row_index()
+    M[rows, A.col] = A.val
+    return M
+
+
+# --------------------------------------------------------------------------- CRS
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_crs_matches_dense_brute_force(seed):
+    """Dense y_i = sum over ascending j of A[i,j]*x[j] (nonzeros only), in Python floats."""
+    A, rng = rand_csr(seed, n_rows=int(10 + 9 * seed), n_cols=int(64 - 5 * seed))
+    x = rng.uniform(-1, 1, A.n_cols)
+    M = dense_of(A)
+    want = np.zeros(A.n_rows)
+    for i in range(A.n_rows):
+        s = 0.0
+        for j in range(A.n_cols):
+            if M[i, j] != 0.0:
+                s = s + float(M[i, j]) * float(x[j])
+        want[i] = s
+    got = oracle.spmv_crs(A, x)
+    assert np.array_equal(got, want)
+    # and numpy's dense product agrees to rounding
+    D = oracle.row_absdot(A, x)
+    assert oracle.rel_err(got, M @ x, D).max() <= 1e-14
+
+
+def test_crs_alpha_beta():
+    A, rng = rand_csr(11)
+    x = rng.uniform(-1, 1, A.n_cols)
+    y0 = rng.uniform(-1, 1, A.n_rows)
+    M = dense_of(A)
+    got = oracle.spmv_crs(A, x, y0, alpha=2.5, beta=-0.75)
+    assert np.allclose(got, 2.5 * (M @ x) - 0.75 * y0, rtol=0, atol=1e-13)
+    y_nan = np.full(A.n_rows, np.nan)
+    got0 = oracle.spmv_crs(A, x, y_nan, alpha=1.0, beta=0.0)   # beta = 0 never reads y
+    assert np.all(np.isfinite(got0))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_crs_integer_exact(seed):
+    """Small-integer values and x: every partial sum is an exact integer."""
+    A, rng = rand_csr(100 + seed, n_rows=60, n_cols=70, density=0.3, integer=True, long_rows=2,
+                      long_len=70)
+    x = synth.integer_vector(A.n_cols, rng)
+    got = oracle.spmv_crs(A, x)
+    rows = A.row_index()
+    want = [0] * A.n_rows
+    for k in range(A.nnz):
+        want[rows[k]] += int(A.val[k]) * int(x[A.col[k]])
+    assert got.tolist() == [float(w) for w in want]
+
+
+def test_crs_scipy_cross_check():
+    A, rng = rand_csr(7, n_rows=500, n_cols=400, density=0.05)
+    x = rng.uniform(-1, 1, A.n_cols)
+    S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n_rows, A.n_cols))
+    got = oracle.spmv_crs(A, x)
+    assert oracle.rel_err(got, S @ x, oracle.row_absdot(A, x)).max() <= 1e-14
+
+
+def test_spmm_columns_are_spmv():
+    A, rng = rand_csr(8, n_rows=50, n_cols=45, density=0.2, integer=True)
+    X = rng.integers(-8, 9, size=(A.n_cols, 5)).astype(np.float64)
+    Y = oracle.spmm_crs(A, X)
+    M = dense_of(A)
+    assert np.array_equal(Y, M @ X)       # integers: exact either way
+
+
+# --------------------------------------------------------------------------- Laplacian
+
+
+def sine_mode(p, q, r, m=20):
+    idx = np.arange(m ** 3)
+    i, j, k = idx % m, (idx // m) % m, idx // (m * m)
+    h = m + 1
+    return (np.sin(p * np.pi * (i + 1) / h) * np.sin(q * np.pi * (j + 1) / h)
+            * np.sin(r * np.pi * (k + 1) / h))
+
+
+def test_laplacian_structure_golden():
+    g = json.load(open(os.path.join(GOLD, "laplacian20.json")))
+    A = lap()
+    assert A.n_rows == g["n"] and A.nnz == g["nnz"]
+    counts = np.bincount(A.row_lengths())
+    assert {str(L): int(c) for L, c in enumerate(counts) if c} == g["row_length_counts"]
+    J = oracle.jds_from_csr(A)
+    assert J.jd_ptr.tolist() == g["jd_ptr"]
+
+
+def test_laplacian_sine_modes():
+    g = json.load(open(os.path.join(GOLD, "laplacian20.json")))
+    A = lap()
+    for e in g["eigen"]:
+        p, q, r = e["mode"]
+        lam = 6 - 2 * math.cos(p * math.pi / 21) - 2 * math.cos(q * math.pi / 21) - 2 * math.cos(r * math.pi / 21)
+        assert abs(lam - e["lambda"]) <= 1e-13
+        v = sine_mode(p, q, r)
+        Av = oracle.spmv_crs(A, v)
+        D = oracle.row_absdot(A, v)
+        assert oracle.rel_err(Av, lam * v, D).max() <= 1e-12
+
+
+# --------------------------------------------------------------------------- COO -> CRS
+
+
+def test_csr_from_coo_duplicates_and_order():
+    rng = np.random.default_rng(3)
+    n_rows, n_cols = 30, 25
+    k = 400
+    row = rng.integers(0, n_rows, k).astype(np.int32)
+    col = rng.integers(0, n_cols, k).astype(np.int32)   # many duplicates
+    val = rng.standard_normal(k)
+    val[::17] = 0.0                                      # explicit zeros stay
+    A = oracle.csr_from_coo(n_rows, n_cols, row, col, val)
+    # brute force: dense accumulation in input order, Python floats
+    acc = {}
+    for t in range(k):
+        key = (int(row[t]), int(col[t]))
+        acc[key] = acc[key] + float(val[t]) if key in acc else float(val[t])
+    keys = sorted(acc)
+    assert A.nnz == len(keys)
+    assert list(zip(A.row_index().tolist(), A.col.tolist())) == keys
+    assert A.val.tolist() == [acc[kk] for kk in keys]
+    # scipy agrees on the pattern and (to rounding) on the sums
+    S = sp.coo_matrix((val, (row, col)), shape=(n_rows, n_cols)).tocsr()
+    S.sum_duplicates()
+    S.sort_indices()
+    assert np.array_equal(S.indptr, A.row_ptr)
+    assert np.array_equal(S.indices, A.col)
+    assert np.allclose(S.data, A.val, rtol=0, atol=1e-14)
+
+
+def test_csr_from_coo_rejects_bad_index():
+    with pytest.raises(ValueError):
+        oracle.csr_from_coo(3, 3, np.array([0, 3], np.int32), np.array([0, 0], np.int32), np.ones(2))
+    with pytest.raises(ValueError):
+        oracle.csr_from_coo(3, 3, np.array([0, 1], np.int32), np.array([0, -1], np.int32), np.ones(2))
+
+
+def test_csr_from_coo_empty():
+    A = oracle.csr_from_coo(4, 5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert A.nnz == 0 and A.row_ptr.tolist() == [0] * 5
+    assert oracle.spmv_crs(A, np.ones(5)).tolist() == [0.0] * 4
+
+
+# --------------------------------------------------------------------------- JDS family
+
+
+def check_jds_structure(A, J):
+    n = A.n_rows
+    lens = A.row_lengths()
+    assert sorted(J.perm.tolist()) == list(range(n))
+    assert np.array_equal(J.iperm[J.perm], np.arange(n))
+    lp = lens[J.perm]
+    assert np.all(np.diff(lp) <= 0)
+    ties = np.diff(lp) == 0
+    assert np.all(np.diff(J.perm)[ties] > 0)             # stable: equal lengths keep order
+    for d in range(J.ndiag):
+        assert J.jd_ptr[d + 1] - J.jd_ptr[d] == int((lens > d).sum())
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_jds_roundtrip_and_structure(seed):
+    A, _ = rand_csr(200 + seed, n_rows=80, n_cols=80, density=0.1, long_rows=3, long_len=60)
+    J = oracle.jds_from_csr(A)
+    check_jds_structure(A, J)
+    B = oracle.jds_to_csr(J, A.n_cols)
+    assert np.array_equal(B.row_ptr, A.row_ptr)
+    assert np.array_equal(B.col, A.col)
+    assert np.array_equal(B.val, A.val)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_jds_variants_bit_identical_to_crs(seed):
+    """Paper Section 2: JDS, NUJDS, NBJDS and RBJDS keep each row's entries in CRS
+    order, so in a serial evaluation every variant adds the same terms in the
+    same order as CRS (NUJDS with unroll = Nj *is* CRS in the permuted basis,
+    RBJDS with block size 1 is row by row, plain JDS is block size n)."""
+    A, rng = rand_csr(300 + seed, n_rows=150, n_cols=150, density=0.06, long_rows=4, long_len=90)
+    x = rng.uniform(-1, 1, A.n_cols)
+    y0 = rng.uniform(-1, 1, A.n_rows)
+    want = oracle.spmv_crs(A, x, y0, alpha=1.5, beta=-0.5)
+    J = oracle.jds_from_csr(A)
+    assert np.array_equal(oracle.spmv_jds(J, x, y0, 1.5, -0.5), want)
+    for u in (1, 2, 4, J.ndiag):
+        assert np.array_equal(oracle.spmv_nujds(J, x, u, y0, 1.5, -0.5), want)
+    for b in (1, 7, 64, A.n_rows):
+        assert np.array_equal(oracle.spmv_nbjds(J, x, b, y0, 1.5, -0.5), want)
+    for C in (1, 8, 64, 256):
+        B = oracle.blocked_from_jds(J, C)
+        assert np.array_equal(oracle.spmv_blocked(B, x, y0, 1.5, -0.5), want)
+
+
+def test_jds_symperm_is_permuted_problem():
+    A, rng = rand_csr(400, n_rows=120, n_cols=120, density=0.08)
+    x = rng.uniform(-1, 1, 120)
+    y = oracle.spmv_crs(A, x)
+    J = oracle.jds_from_csr(A, symperm=True)
+    yp = oracle.spmv_jds(J, x[J.perm])          # x and y in the permuted basis
+    assert np.array_equal(yp, y[J.perm])
+
+
+def test_blocked_layout_rules():
+    A, _ = rand_csr(500, n_rows=200, n_cols=200, density=0.05, long_rows=2, long_len=100)
+    J = oracle.jds_from_csr(A)
+    lens_p = A.row_lengths()[J.perm]
+    for C in (1, 4, 64):
+        B = oracle.blocked_from_jds(J, C)
+        for s in range(B.n_slices):
+            assert B.slice_nd[s] == lens_p[s * C]
+            for rl in range(C):
+                r = s * C + rl
+                L = lens_p[r] if r < A.n_rows else 0
+                for d in range(B.slice_nd[s]):
+                    k = B.slice_ptr[s] + d * C + rl
+                    if d < L:
+                        assert B.bl_col[k] == J.jd_col[J.jd_ptr[d] + r]
+                    else:
+                        assert B.bl_col[k] == -1 and B.bl_val[k] == 0.0
+
+
+def test_sojds_keeps_rows_and_is_close():
+    A, rng = rand_csr(600, n_rows=300, n_cols=300, density=0.04, long_rows=3, long_len=40)
+    x = rng.uniform(-1, 1, 300)
+    J = oracle.jds_from_csr(A)
+    want = oracle.spmv_crs(A, x)
+    D = oracle.row_absdot(A, x)
+    for C in (1, 8, 64, 300):
+        B = oracle.blocked_from_jds(J, C, sojds=True)
+        B0 = oracle.blocked_from_jds(J, C)
+        assert np.array_equal(B.slice_ptr, B0.slice_ptr)
+        for s in range(B.n_slices):
+            for rl in range(C):
+                ks = B.slice_ptr[s] + np.arange(B.slice_nd[s]) * C + rl
+                a = sorted(zip(B.bl_col[ks].tolist(), B.bl_val[ks].tolist()))
+                b = sorted(zip(B0.bl_col[ks].tolist(), B0.bl_val[ks].tolist()))
+                assert a == b
+        assert oracle.rel_err(oracle.spmv_blocked(B, x), want, D).max() <= 1e-13
+    # the first row of a block keeps CRS order
+    B = oracle.blocked_from_jds(J, 8, sojds=True)
+    ks = B.slice_ptr[0] + np.arange(B.slice_nd[0]) * 8
+    assert np.array_equal(B.bl_col[ks], J.jd_col[J.jd_ptr[:-1]])
+
+
+def test_jds_empty_rows_and_all_empty():
+    A = oracle.csr_from_coo(5, 5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    J = oracle.jds_from_csr(A)
+    assert J.ndiag == 0 and J.jd_ptr.tolist() == [0]
+    y = oracle.spmv_jds(J, np.ones(5), np.full(5, 2.0), alpha=1.0, beta=0.5)
+    assert y.tolist() == [1.0] * 5
+
+
+# --------------------------------------------------------------------------- bf16
+
+
+def test_bf16_matches_torch_on_float_inputs():
+    """For inputs that are already floats, one RNE step from double equals
+    torch's float -> bfloat16 conversion (also round-to-nearest-even)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    v = np.concatenate([rng.standard_normal(20000), rng.standard_normal(2000) * 1e-39,
+                        rng.standard_normal(1000) * 1e38, [0.0, -0.0, 1.0, -2.5]])
+    v = v.astype(np.float32).astype(np.float64)
+    got = oracle.round_bf16_bits(v)
+    want = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, want)
+
+
+def test_bf16_ties_and_double_rounding():
+    one = 1.0
+    cases = {
+        one + 2.0 ** -8: 0x3F80,                 # tie -> even (1.0)
+        one + 3 * 2.0 ** -8: 0x3F82,             # tie -> even (1 + 2^-6)
+        one + 2.0 ** -8 + 2.0 ** -40: 0x3F81,    # just above the tie: up (a float would round first to the tie)
+        -(one + 2.0 ** -8 + 2.0 ** -40): 0xBF81,
+        2.0 ** -133: 0x0001,                     # smallest bf16 subnormal
+        2.0 ** -134: 0x0000,                     # tie between 0 and 2^-133 -> even (0)
+        3 * 2.0 ** -135: 0x0001,
+        255 * 2.0 ** 120: 0x7F7F,                # largest finite
+        511 * 2.0 ** 119: 0x7F80,                # halfway to 2^128 -> even -> infinity
+        float("inf"): 0x7F80,
+    }
+    got = oracle.round_bf16_bits(np.array(list(cases.keys())))
+    assert [int(g) for g in got] == list(cases.values())
+
+
+# --------------------------------------------------------------------------- transpose / gradients
+
+
+def test_transpose_matches_dense():
+    A, rng = rand_csr(700, n_rows=40, n_cols=55, density=0.1)
+    rowT, colT, tmap = oracle.transpose(A)
+    T = oracle.CSR(A.n_cols, A.n_rows, rowT, colT, A.val[tmap])
+    assert np.array_equal(dense_of(T), dense_of(A).T)
+    assert np.all(np.diff(colT)[np.diff(T.row_index()) == 0] > 0)     # rows of A^T ascending
+    g = rng.uniform(-1, 1, A.n_rows)
+    assert np.allclose(oracle.spmv_crs_transposed(A, g), dense_of(A).T @ g, rtol=0, atol=1e-14)
+
+
+def test_grad_vals_identities():
+    A, rng = rand_csr(800, n_rows=60, n_cols=60, density=0.1)
+    x = rng.uniform(-1, 1, 60)
+    g = rng.uniform(-1, 1, 60)
+    dv = oracle.grad_vals(A, g, x)
+    y = oracle.spmv_crs(A, x)
+    # y is linear in the values: sum_k val_k * dval_k = <g, A x>
+    assert abs(np.dot(A.val, dv) - np.dot(g, y)) <= 1e-13 * np.abs(g).sum() * oracle.row_absdot(A, x).max()
+    # adjoint: <g, A x> = <A^T g, x>
+    assert abs(np.dot(oracle.spmv_crs_transposed(A, g), x) - np.dot(g, y)) <= 1e-13 * 60
+    # central difference in one value (exact: the map is linear)
+    k = 17
+    e = 1e-3
+    Ap = oracle.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, A.val.copy())
+    Am = oracle.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, A.val.copy())
+    Ap.val[k] += e
+    Am.val[k] -= e
+    fd = (np.dot(g, oracle.spmv_crs(Ap, x)) - np.dot(g, oracle.spmv_crs(Am, x))) / (2 * e)
+    assert abs(fd - dv[k]) <= 1e-10
+
+
+# --------------------------------------------------------------------------- Chebyshev
+
+
+def test_chebyshev_closed_form_on_sine_modes():
+    g = json.load(open(os.path.join(GOLD, "laplacian20.json")))
+    A = lap()
+    # A_s = (A - 6 I) / 6 on the same pattern
+    vals = A.val / 6.0
+    diag = A.row_index() == A.col
+    vals[diag] = (A.val[diag] - 6.0) / 6.0
+    As = oracle.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, vals)
+    for e in g["chebyshev20"]:
+        v = sine_mode(*e["mode"])
+        ys = oracle.cheb_forward(As, v, 20)
+        T20 = math.cos(20 * math.acos(e["lambda_s"]))
+        assert abs(T20 - e["T20"]) <= 1e-13
+        assert np.abs(ys[20] - T20 * v).max() <= 1e-11
+        loss, dx, dval, _ = oracle.cheb_loss_grad(As, v, 20)
+        assert abs(loss - T20 ** 2 * np.dot(v, v)) <= 1e-10 * np.dot(v, v)
+        # A_s symmetric, v an eigenvector: grad_x = 2 T20(A_s)^T T20(A_s) v = 2 T20^2 v
+        assert np.abs(dx - 2 * T20 ** 2 * v).max() <= 1e-10
+
+
+def _small_c5(n=2000, seed=0):
+    rng = np.random.default_rng(seed)
+    r, c, v, nn, _ = synth.banded_uniform(n=n, band=50, dtype=np.float64)
+    A = oracle.csr_from_coo(nn, nn, r, c, v)
+    x = rng.uniform(-1, 1, nn)
+    return A, x
+
+
+def test_chebyshev_gradient_central_differences():
+    A, x = _small_c5(400)
+    steps = 20
+    loss, dx, dval, _ = oracle.cheb_loss_grad(A, x, steps)
+    rng = np.random.default_rng(9)
+    eps = 1e-3
+
+    def L(AA, xx):
+        return float(np.sum(oracle.cheb_forward(AA, xx, steps)[steps] ** 2))
+
+    # x: the loss is quadratic in x, so the central difference is exact up to rounding
+    for i in rng.choice(A.n_rows, 12, replace=False):
+        xp, xm = x.copy(), x.copy()
+        xp[i] += eps
+        xm[i] -= eps
+        fd = (L(A, xp) - L(A, xm)) / (2 * eps)
+        assert abs(fd - dx[i]) <= 1e-8 * max(1.0, abs(loss))
+    # vals: degree-40 polynomial, O(eps^2) truncation
+    for k in rng.choice(A.nnz, 12, replace=False):
+        Ap = oracle.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, A.val.copy())
+        Am = oracle.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, A.val.copy())
+        Ap.val[k] += eps
+        Am.val[k] -= eps
+        fd = (L(Ap, x) - L(Am, x)) / (2 * eps)
+        assert abs(fd - dval[k]) <= 1e-5 * max(abs(fd), 1e-3 * abs(loss))
+
+
+def test_chebyshev_directional_derivative():
+    A, x = _small_c5(600, seed=2)
+    steps = 20
+    loss, dx, dval, _ = oracle.cheb_loss_grad(A, x, steps)
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal(A.n_rows)
+    w = rng.standard_normal(A.nnz) * np.abs(A.val).mean()    # same scale as the values
+    eps = 1e-4
+
+    def L(vals, xx):
+        AA = oracle.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, vals)
+        return float(np.sum(oracle.cheb_forward(AA, xx, steps)[steps] ** 2))
+
+    def fd(e):
+        return (L(A.val + e * w, x + e * u) - L(A.val - e * w, x - e * u)) / (2 * e)
+
+    an = np.dot(dx, u) + np.dot(dval, w)
+    e1, e2 = abs(fd(eps) - an), abs(fd(eps / 2) - an)
+    assert e1 <= 1e-6 * max(abs(an), abs(loss))
+    # central differences converge at second order towards the adjoint value
+    assert e2 <= 0.35 * e1 or e2 <= 1e-9 * abs(loss)
