@@ -1,0 +1,307 @@
+/*
+ * spmv.h - C ABI of the MI355X (gfx950) CRS / JDS sparse matrix-vector library.
+ *
+ * The operations follow G. Schubert, G. Hager, H. Fehske, "Performance
+ * limitations for sparse matrix-vector multiplications on current multicore
+ * environments" (arXiv:0910.4836), Section 2 (CRS, JDS and the NBJDS, NUJDS,
+ * RBJDS and SOJDS refinements).  The library adds mixed-precision value
+ * storage, multi-vector and many-matrix forms and the derivatives needed to
+ * differentiate through y = A x.
+ *
+ * Conventions (apply to every call unless its comment says otherwise)
+ *  - Pointers are DEVICE pointers, except parameters whose name starts with
+ *    h_, which are host pointers.  `stream` is a hipStream_t (NULL = the
+ *    default stream), passed as void* so that this header needs no HIP header.
+ *  - Indices are 0-based int32; nnz counts are int64 but must stay below 2^31.
+ *  - The caller owns every buffer: inputs, outputs and workspace.  The library
+ *    never allocates or frees caller memory.  Calls that need scratch memory
+ *    take (ws, ws_bytes) and have a *_workspace_size() query.
+ *  - Setup calls (conversions, plans) may synchronise `stream` to return sizes
+ *    through h_ outputs; they cannot be captured in a HIP graph.  Compute calls
+ *    (spmv_*, spmm_*, grad, axpby, batched run) are asynchronous, do not
+ *    allocate and do not synchronise, so they can be captured.
+ *  - Compute calls validate their arguments on the host only (null pointers,
+ *    negative sizes, unsupported dtype combinations); the matrix contents are
+ *    trusted.  spmv_csr_validate() checks CRS contents on the device.
+ *  - Every call returns a spmv_status; on failure spmv_last_error() returns a
+ *    message for the calling thread.  No C++ exception crosses this boundary.
+ *  - Results are deterministic: no floating-point atomics; every output
+ *    element is produced by one fixed sequence of operations for a given
+ *    argument set.
+ *  - Vectors x and y of one call must not overlap (except where stated).
+ */
+#ifndef SPMV_H
+#define SPMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPMV_OK = 0,
+    SPMV_ERR_INVALID_ARG = 1, /* null pointer, negative size, bad flag          */
+    SPMV_ERR_BAD_FORMAT = 2,  /* index out of range, malformed row_ptr          */
+    SPMV_ERR_CAPACITY = 3,    /* an output buffer is too small (size returned)  */
+    SPMV_ERR_UNSUPPORTED = 4, /* dtype combination or size the library lacks    */
+    SPMV_ERR_HIP = 5          /* a HIP runtime call failed                      */
+} spmv_status;
+
+typedef enum {
+    SPMV_F64 = 0,  /* IEEE double                                       */
+    SPMV_F32 = 1,  /* IEEE float                                        */
+    SPMV_BF16 = 2  /* bfloat16 bit patterns (uint16_t), values only     */
+} spmv_dtype;
+
+/* flags */
+#define SPMV_SYMPERM 1u /* JDS: permute columns too (A_{p(i),p(j)}); x, y in the permuted basis */
+#define SPMV_SOJDS 2u   /* blocked JDS: sort the entries of each row for near-unit x strides   */
+
+/* Rows with more than this many entries accumulate in FP64 when the values
+ * are stored as FP32 or BF16. */
+#define SPMV_WIDE_ROW_NNZ 4096
+
+const char *spmv_status_string(spmv_status s);
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *spmv_last_error(void);
+/* Library version, e.g. "1.0.0". */
+const char *spmv_version(void);
+
+/* ======================================================================== */
+/* Setup: format construction (paper Section 2)                              */
+/* ======================================================================== */
+
+/* COO triplets -> CRS (paper Section 2: val, col_idx, row_ptr).
+ * Entries are ordered by (row, col); duplicate (row, col) pairs are summed in
+ * input order; explicit zeros are kept as stored entries.  val/val_out have
+ * dtype dt (F64 or F32; duplicates are summed in that type).
+ * Outputs: row_ptr[n_rows+1], col_idx[nnz], val_out[nnz] (nnz = input count
+ * is always enough); *h_nnz_out = stored entries.  Any row or col outside
+ * [0, n_rows) x [0, n_cols) -> SPMV_ERR_BAD_FORMAT.  Synchronises.  */
+size_t spmv_csr_from_coo_workspace_size(int32_t n_rows, int32_t n_cols, int64_t nnz);
+spmv_status spmv_csr_from_coo(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row,
+                              const int32_t *col, const void *val, spmv_dtype dt,
+                              int32_t *row_ptr, int32_t *col_idx, void *val_out,
+                              int64_t *h_nnz_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Checks a CRS structure on the device: row_ptr[0] == 0, row_ptr non-
+ * decreasing, row_ptr[n_rows] == nnz, every col_idx in [0, n_cols).
+ * *h_ok = 1 if valid, 0 otherwise.  ws: spmv_csr_validate_workspace_size().
+ * Synchronises. */
+size_t spmv_csr_validate_workspace_size(void);
+spmv_status spmv_csr_validate(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, int32_t *h_ok, void *ws, size_t ws_bytes,
+                              void *stream);
+
+/* CRS -> JDS (paper Section 2): rows are permuted by decreasing length
+ * (equal lengths keep ascending original index), each row's entries are
+ * shifted left in CRS order, and the d-th entries of all rows form jagged
+ * diagonal d, stored diagonal after diagonal.
+ *   perm[r]  = original row of permuted row r;  iperm = inverse (n each)
+ *   jd_ptr[d] = offset of diagonal d, jd_ptr[ndiag] = nnz (ndiag = max row
+ *              length); capacity jd_ptr_cap entries
+ *   jd_col, jd_val: nnz entries; with SPMV_SYMPERM jd_col = iperm[col]
+ *              (square matrices only), otherwise original column numbers.
+ * *h_ndiag = ndiag.  If jd_ptr_cap < ndiag+1 returns SPMV_ERR_CAPACITY with
+ * *h_ndiag set and nothing else written (call again with a larger buffer).
+ * h_jd_ptr (optional, may be NULL) receives a host copy of jd_ptr; the JDS
+ * compute calls take that copy to size their launch without reading device
+ * memory.  Synchronises. */
+size_t spmv_jds_from_csr_workspace_size(int32_t n, int64_t nnz);
+spmv_status spmv_jds_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                              const void *val, spmv_dtype dt, unsigned flags, int32_t *perm,
+                              int32_t *iperm, int32_t *jd_ptr, int32_t jd_ptr_cap, int32_t *jd_col,
+                              void *jd_val, int32_t *h_ndiag, int32_t *h_jd_ptr, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* JDS -> CRS in the original row order, entries of a row in diagonal order
+ * (the exact inverse of spmv_jds_from_csr).  With SPMV_SYMPERM the columns
+ * are mapped back through perm.  row_ptr[n+1], col_idx[nnz], val[nnz].
+ * ws: spmv_jds_to_csr_workspace_size(n).  Synchronises. */
+size_t spmv_jds_to_csr_workspace_size(int32_t n);
+spmv_status spmv_jds_to_csr(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag,
+                            const int32_t *jd_col, const void *jd_val, spmv_dtype dt, unsigned flags,
+                            int32_t *row_ptr, int32_t *col_idx, void *val, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* JDS -> blocked JDS (paper Section 2, RBJDS; SOJDS with SPMV_SOJDS).
+ * Blocks ("slices") are C consecutive permuted rows, C a positive multiple of
+ * 64.  All elements of a slice are stored together, diagonal by diagonal,
+ * padded to the slice's first (longest) row; padded slots hold col = -1 and
+ * value 0 and are never used.  Element (d, row r) of slice s = r / C is at
+ * slice_ptr[s] + d*C + (r - s*C).
+ *   slice_ptr[n_slices+1] (int64), slice_nd[n_slices] = diagonals in slice s,
+ *   n_slices = ceil(n / C); bl_col/bl_val hold the padded total.
+ * SPMV_SOJDS: inside each slice the entries of every row are re-assigned to
+ * diagonal slots: the slice's first row keeps CRS order; each following row,
+ * slot by slot, takes from its remaining entries the one whose column is
+ * closest to (column in the same slot of the previous row) + 1, the smaller
+ * column on a tie.
+ * *h_padded = padded total; if bl_cap < padded returns SPMV_ERR_CAPACITY and
+ * writes nothing else.  h_slice_nd (optional) receives a host copy of
+ * slice_nd.  Synchronises. */
+size_t spmv_jds_blocked_workspace_size(int32_t n, int32_t ndiag, int32_t C, unsigned flags);
+spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t ndiag,
+                                      const int32_t *jd_col, const void *jd_val, spmv_dtype dt,
+                                      int32_t C, unsigned flags, int64_t *slice_ptr, int32_t *slice_nd,
+                                      int32_t *bl_col, void *bl_val, int64_t bl_cap, int64_t *h_padded,
+                                      int32_t *h_slice_nd, void *ws, size_t ws_bytes, void *stream);
+
+/* Row-block plan for spmv_crs / spmm_crs: plan[0..n_blocks] are row
+ * boundaries.  Consecutive rows are grouped while the group holds at most
+ * block_nnz entries (0 = library default) and at most 256 rows; a longer
+ * row is a block of its own.  If plan_cap < n_blocks+1 returns
+ * SPMV_ERR_CAPACITY with *h_n_blocks set.  Synchronises (reads row_ptr). */
+spmv_status spmv_crs_plan(int32_t n_rows, const int32_t *row_ptr, int32_t block_nnz, int32_t *plan,
+                          int32_t plan_cap, int32_t *h_n_blocks, void *stream);
+
+/* CRS <-> reduced-precision value conversion: out[i] = in[i] rounded to
+ * out_dt with round-to-nearest-even in one step (F64 -> BF16 does not pass
+ * through F32).  Widening conversions are exact.  Asynchronous. */
+spmv_status spmv_convert_values(int64_t n, const void *in, spmv_dtype in_dt, void *out,
+                                spmv_dtype out_dt, void *stream);
+
+/* Structure of A^T (n_rows x n_cols A, CRS): rowT_ptr[n_cols+1], colT[nnz]
+ * (row c of A^T lists column c of A in ascending row order) and tmap[nnz]
+ * with A^T's values = val[tmap].  Synchronises. */
+size_t spmv_transpose_workspace_size(int32_t n_rows, int32_t n_cols, int64_t nnz);
+spmv_status spmv_transpose_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, int32_t *rowT_ptr, int32_t *colT, int32_t *tmap,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/* ======================================================================== */
+/* Compute                                                                   */
+/* ======================================================================== */
+/* All SpMV forms compute y = alpha * A x + beta * y.  beta == 0 never reads
+ * y.  val_dt is F64, F32 or BF16; vec_dt (x and y) is F64 or F32.
+ * Arithmetic: F64 values -> products and sums in FP64.  F32/BF16 values ->
+ * x is rounded to FP32 and products and sums are FP32, except rows with more
+ * than SPMV_WIDE_ROW_NNZ entries, which form exact FP64 products of the
+ * stored value and x and sum them in FP64.  alpha/beta are applied in FP64
+ * and y is rounded to vec_dt once. */
+
+/* CRS kernel (paper Section 2, CRS listing): y_i = alpha*sum_j val_j x_{col_j}
+ * + beta*y_i.  plan/n_blocks/block_nnz as given to and returned by
+ * spmv_crs_plan (block_nnz 0 = default); plan == NULL uses one wavefront per
+ * row. */
+spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
+                     const void *val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
+                     double alpha, double beta, const int32_t *plan, int32_t n_blocks,
+                     int32_t block_nnz, void *stream);
+
+/* JDS kernel (paper Section 2, JDS listing; NBJDS/NUJDS refinements): each
+ * lane owns one permuted row and walks the jagged diagonals that reach it,
+ * `unroll` diagonals at a time (2, 4 or 8; 0 = default).  Rows whose length
+ * exceeds `max_iters` diagonals (0 = default) have their diagonals split over
+ * up to 16 wavefronts whose partial sums are added in a fixed order.
+ * Without SPMV_SYMPERM, x is in the original basis and y[perm[r]] receives
+ * row r; with it, x and y are both in the permuted basis.
+ * h_jd_ptr: host copy of jd_ptr (ndiag+1 entries). */
+spmv_status spmv_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr,
+                     int32_t ndiag, const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt,
+                     const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                     int32_t unroll, int32_t max_iters, unsigned flags, void *stream);
+
+/* Blocked JDS kernel (RBJDS / SOJDS storage): same result as spmv_jds.
+ * rows_per_wave R in {8, 16, 32, 64} (0 = 64): a wavefront covers R rows of a
+ * slice with 64/R lanes per row striding over the diagonals.
+ * h_slice_nd: host copy of slice_nd (non-increasing, as built). */
+spmv_status spmv_jds_blocked(int32_t n, const int32_t *perm, int32_t C, int32_t n_slices,
+                             const int64_t *slice_ptr, const int32_t *slice_nd,
+                             const int32_t *h_slice_nd, const int32_t *bl_col, const void *bl_val,
+                             spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
+                             double beta, int32_t rows_per_wave, int32_t unroll, int32_t max_iters,
+                             unsigned flags, void *stream);
+
+/* Vector basis change: inverse == 0: out[r] = in[perm[r]] (to the permuted
+ * basis); inverse != 0: out[perm[r]] = in[r].  dt F64 or F32. */
+spmv_status spmv_permute_vec(int32_t n, const int32_t *perm, const void *in, void *out, spmv_dtype dt,
+                             int inverse, void *stream);
+
+/* out[i] = in[map[i]], i < n (e.g. A^T's values from tmap). */
+spmv_status spmv_gather_values(int64_t n, const int32_t *map, const void *in, void *out, spmv_dtype dt,
+                               void *stream);
+
+/* y = alpha*x + beta*y (beta == 0 never reads y); dt F64 or F32. */
+spmv_status spmv_axpby(int64_t n, double alpha, const void *x, double beta, void *y, spmv_dtype dt,
+                       void *stream);
+
+/* *out (device double) = sum_i x_i*y_i in FP64, fixed summation tree.
+ * ws: spmv_dot_workspace_size(n). */
+size_t spmv_dot_workspace_size(int64_t n);
+spmv_status spmv_dot(int64_t n, const void *x, const void *y, spmv_dtype dt, double *out, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/* Multi-vector forms: Y[:, c] = alpha*A X[:, c] + beta*Y[:, c] for c < k,
+ * X and Y column-major with leading dimensions ldx >= n_cols and ldy >= n. */
+spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
+                     const void *val, spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y,
+                     int64_t ldy, spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan,
+                     int32_t n_blocks, int32_t block_nnz, void *stream);
+spmv_status spmm_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr,
+                     int32_t ndiag, const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt,
+                     int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, spmv_dtype vec_dt,
+                     double alpha, double beta, unsigned flags, void *stream);
+
+/* Value gradient of y = A x in JDS storage order:
+ * dval[jd_ptr[d]+r] = alpha * g[row(r)] * x[jd_col[jd_ptr[d]+r]] + beta * dval[...]
+ * with row(r) = perm[r] (original basis) or r (SPMV_SYMPERM).  Computed in
+ * FP64 and rounded once to dt (the value/vector type, F64 or F32). */
+spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag,
+                               int64_t nnz, const int32_t *jd_col, const void *g, const void *x,
+                               void *dval, spmv_dtype dt, double alpha, double beta, unsigned flags,
+                               void *stream);
+
+/* ======================================================================== */
+/* Many matrices in one launch                                               */
+/* ======================================================================== */
+/* Batched blocked-JDS SpMV: y_m = A_m x_m for m < n_mat, F32 values and
+ * vectors, each matrix in blocked-JDS storage (spmv_jds_blocked_from_jds)
+ * inside shared arrays:
+ *   matrix m has h_n_rows[m] rows and slice height h_C[m] (multiple of 64);
+ *   its slices are entries h_slice_base[m] .. + ceil(n_m / C_m) - 1 of the
+ *   host copies h_slice_ptr (ABSOLUTE offsets into bl_col / bl_val) and
+ *   h_slice_nd;  its rows are y[h_row_base[m] .. + n_m) and its permutation
+ *   perm[h_row_base[m] .. + n_m) (local row numbers);  its columns index
+ *   x[h_col_base[m] + col].
+ * spmv_batched_plan cuts every matrix into tiles of rows_per_wave rows (8,
+ * 16, 32 or 64; 0 = 64), orders them longest first (stable) and writes
+ * SPMV_BATCHED_PLAN_WORDS int32 per tile into the device array `plan`
+ * (capacity plan_cap int32); *h_n_tiles returns the tile count; if the
+ * capacity is too small returns SPMV_ERR_CAPACITY.  Synchronises.
+ * spmv_batched runs all tiles in one persistent launch of n_workgroups
+ * 256-lane workgroups (0 = 8 per compute unit) whose wavefronts walk the
+ * table with a fixed stride: deterministic and capturable in a HIP graph.
+ * unroll: diagonals per trip (2, 4 or 8; 0 = 4). */
+#define SPMV_BATCHED_PLAN_WORDS 12
+spmv_status spmv_batched_plan(int32_t n_mat, const int32_t *h_n_rows, const int32_t *h_C,
+                              const int64_t *h_slice_base, const int64_t *h_row_base,
+                              const int64_t *h_col_base, const int64_t *h_slice_ptr,
+                              const int32_t *h_slice_nd, int32_t rows_per_wave, int32_t *plan,
+                              int64_t plan_cap, int64_t *h_n_tiles, void *stream);
+spmv_status spmv_batched(int64_t n_tiles, const int32_t *plan, const int32_t *perm, const int32_t *bl_col,
+                         const float *bl_val, const float *x, float *y, int32_t unroll,
+                         int32_t n_workgroups, void *stream);
+
+/* ======================================================================== */
+/* HIP graph helpers (capture of compute calls issued on `stream`)            */
+/* ======================================================================== */
+spmv_status spmv_graph_begin(void *stream);
+/* Ends the capture and instantiates it; *h_exec receives the handle. */
+spmv_status spmv_graph_end(void *stream, void **h_exec);
+spmv_status spmv_graph_launch(void *exec, void *stream);
+spmv_status spmv_graph_destroy(void *exec);
+
+/* ======================================================================== */
+/* Bandwidth probes (for rooflines): a[i] = b[i] + s*c[i]; a[i] = b[i]       */
+/* ======================================================================== */
+spmv_status spmv_stream_triad(int64_t n, const double *b, const double *c, double *a, double s,
+                              void *stream);
+spmv_status spmv_stream_copy(int64_t n, const double *b, double *a, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPMV_H */

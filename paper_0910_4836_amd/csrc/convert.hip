@@ -1,0 +1,1062 @@
+// Format construction on the GPU (paper Section 2): COO -> CRS, CRS checks,
+// CRS -> JDS (row permutation by decreasing length, jagged diagonals), JDS ->
+// CRS, JDS -> blocked JDS (RBJDS, optionally SOJDS), CRS transpose, value
+// rounding, vector permutation and gathers.
+//
+// All orderings are produced by a stable least-significant-digit radix sort
+// written here (8-bit digits, wave ballots for the in-tile ranks), so every
+// permutation is unique and reproducible; counts use integer atomics only.
+#include <vector>
+
+#include "common.hpp"
+
+namespace spmv {
+
+// ======================================================================= scan
+// Exclusive prefix sum out[i] = sum_{j<i} in[j], out[n] = total.  Three
+// phases: tile sums, (recursive) scan of the tile sums, tile scans.
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *wave_tot, T *total)
+{
+    const int lane = lane_id(), w = (int)threadIdx.x / WAVE;
+    T inc = v;
+    for (int off = 1; off < WAVE; off <<= 1) {
+        T o = __shfl_up(inc, off, WAVE);
+        if (lane >= off) inc += o;
+    }
+    if (lane == WAVE - 1) wave_tot[w] = inc;
+    __syncthreads();
+    T wbase = 0, all = 0;
+    for (int i = 0; i < SCAN_THREADS / WAVE; ++i) {
+        if (i < w) wbase += wave_tot[i];
+        all += wave_tot[i];
+    }
+    if (total) *total = all;
+    __syncthreads();
+    return wbase + inc - v;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(SCAN_THREADS) void scan_tile_sums(const TI *__restrict__ in, int64_t n,
+                                                               TO *__restrict__ sums)
+{
+    __shared__ TO wt[SCAN_THREADS / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    TO s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
+        if (i < n) s += (TO)in[i];
+    }
+    TO tot;
+    block_exclusive_scan<TO>(s, wt, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(SCAN_THREADS) void scan_tiles(const TI *__restrict__ in, int64_t n,
+                                                           const TO *__restrict__ tile_base, TO *__restrict__ out,
+                                                           bool write_total)
+{
+    __shared__ TO wt[SCAN_THREADS / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    TO v[SCAN_ITEMS];
+    TO s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        v[j] = i < n ? (TO)in[i] : (TO)0;
+        s += v[j];
+    }
+    TO tot;
+    TO run = block_exclusive_scan<TO>(s, wt, &tot) + (tile_base ? tile_base[blockIdx.x] : (TO)0);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        out[n] = (tile_base ? tile_base[blockIdx.x] : (TO)0) + tot;
+}
+
+static size_t scan_ws_elems(int64_t n)
+{
+    size_t total = 0;
+    int64_t tiles = ceil_div(n, SCAN_TILE);
+    while (tiles > 1) {
+        total += (size_t)tiles + 1;
+        tiles = ceil_div(tiles, SCAN_TILE);
+    }
+    return total + 1;
+}
+
+// out has n+1 entries; ws holds scan_ws_elems(n) TO values.
+template <typename TI, typename TO>
+static spmv_status exclusive_scan(const TI *in, int64_t n, TO *out, TO *ws, hipStream_t s)
+{
+    if (n == 0) {
+        SPMV_HIP(hipMemsetAsync(out, 0, sizeof(TO), s));
+        return SPMV_OK;
+    }
+    int64_t tiles = ceil_div(n, SCAN_TILE);
+    if (tiles == 1) {
+        scan_tiles<TI, TO><<<1, SCAN_THREADS, 0, s>>>(in, n, (const TO *)nullptr, out, true);
+        SPMV_CHECK_LAUNCH("scan");
+        return SPMV_OK;
+    }
+    TO *sums = ws;                    // tiles + 1 entries
+    TO *rest = ws + tiles + 1;
+    scan_tile_sums<TI, TO><<<(unsigned)tiles, SCAN_THREADS, 0, s>>>(in, n, sums);
+    SPMV_CHECK_LAUNCH("scan tile sums");
+    spmv_status st = exclusive_scan<TO, TO>(sums, tiles, sums, rest, s);   // in place is safe per tile
+    if (st != SPMV_OK) return st;
+    scan_tiles<TI, TO><<<(unsigned)tiles, SCAN_THREADS, 0, s>>>(in, n, sums, out, true);
+    SPMV_CHECK_LAUNCH("scan tiles");
+    return SPMV_OK;
+}
+
+// ================================================================ radix sort
+// Stable LSD radix sort of (uint32 key, int32 value) pairs, 8 bits per pass.
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / WAVE;
+constexpr int RS_ITEMS = 16;                       // per lane
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;     // 4096 keys per tile
+constexpr int RS_BINS = 256;
+
+__global__ __launch_bounds__(RS_THREADS) void radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n,
+                                                                int shift, int32_t *__restrict__ counts,
+                                                                int64_t ntiles)
+{
+    __shared__ int32_t h[RS_BINS];
+    for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS) h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xff], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS) counts[(int64_t)i * ntiles + blockIdx.x] = h[i];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(const uint32_t *__restrict__ kin,
+                                                                   const int32_t *__restrict__ vin, int64_t n,
+                                                                   int shift, const int32_t *__restrict__ offs,
+                                                                   int64_t ntiles, uint32_t *__restrict__ kout,
+                                                                   int32_t *__restrict__ vout)
+{
+    __shared__ int32_t cnt[RS_WAVES][RS_BINS];
+    for (int i = threadIdx.x; i < RS_WAVES * RS_BINS; i += RS_THREADS) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int w = (int)threadIdx.x / WAVE, lane = lane_id();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    // wave w owns keys [base_w, base_w + 64*RS_ITEMS), in rounds of 64 in order
+    const int64_t base_w = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * WAVE * RS_ITEMS;
+    uint32_t k[RS_ITEMS];
+    int32_t v[RS_ITEMS];
+    int32_t rank[RS_ITEMS];
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t i = base_w + (int64_t)j * WAVE + lane;
+        const bool in = i < n;
+        k[j] = in ? kin[i] : 0u;
+        v[j] = in ? vin[i] : 0;
+        const uint32_t dg = (k[j] >> shift) & 0xff;
+        uint64_t peers = __ballot(in);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot((dg >> b) & 1u);
+            peers &= ((dg >> b) & 1u) ? m : ~m;
+        }
+        const int before = __popcll(peers & lt_mask);
+        const int32_t start = cnt[w][dg];
+        rank[j] = start + before;
+        // the first lane of each digit group advances the wave's counter
+        if (in && before == 0) cnt[w][dg] = start + __popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: exclusive prefix over the waves (tile order = wave order)
+    for (int dg = threadIdx.x; dg < RS_BINS; dg += RS_THREADS) {
+        int32_t run = 0;
+        for (int q = 0; q < RS_WAVES; ++q) {
+            int32_t c = cnt[q][dg];
+            cnt[q][dg] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t i = base_w + (int64_t)j * WAVE + lane;
+        if (i < n) {
+            const uint32_t dg = (k[j] >> shift) & 0xff;
+            const int64_t pos = (int64_t)offs[(int64_t)dg * ntiles + blockIdx.x] + cnt[w][dg] + rank[j];
+            kout[pos] = k[j];
+            vout[pos] = v[j];
+        }
+    }
+}
+
+static size_t radix_ws_bytes(int64_t n)
+{
+    int64_t ntiles = n > 0 ? ceil_div(n, RS_TILE) : 1;
+    size_t cells = (size_t)ntiles * RS_BINS;
+    size_t b = 0;
+    b += align_up(sizeof(int32_t) * cells, 256);                 // counts
+    b += align_up(sizeof(int32_t) * (cells + 1), 256);           // offsets
+    b += align_up(sizeof(int32_t) * scan_ws_elems((int64_t)cells), 256);
+    b += 2 * align_up(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), 256);   // ping-pong keys/values
+    return b + 256;
+}
+
+// Sorts (keys, vals) by the low `bits` bits of the keys, stably.  The result
+// is left in (keys, vals); ws provides the ping-pong buffers.
+static spmv_status radix_sort_pairs(uint32_t *keys, int32_t *vals, int64_t n, int bits, void *ws, size_t ws_bytes,
+                                    hipStream_t s)
+{
+    if (n <= 1 || bits <= 0) return SPMV_OK;
+    int64_t ntiles = ceil_div(n, RS_TILE);
+    size_t cells = (size_t)ntiles * RS_BINS;
+    WsCarver wc(ws, ws_bytes);
+    int32_t *counts = wc.take<int32_t>(cells);
+    int32_t *offs = wc.take<int32_t>(cells + 1);
+    int32_t *sws = wc.take<int32_t>(scan_ws_elems((int64_t)cells));
+    uint32_t *k2 = wc.take<uint32_t>((size_t)n);
+    int32_t *v2 = wc.take<int32_t>((size_t)n);
+    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "radix sort: workspace too small");
+    uint32_t *ka = keys, *kb = k2;
+    int32_t *va = vals, *vb = v2;
+    int passes = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        radix_hist_kernel<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(ka, n, shift, counts, ntiles);
+        SPMV_CHECK_LAUNCH("radix hist");
+        spmv_status st = exclusive_scan<int32_t, int32_t>(counts, (int64_t)cells, offs, sws, s);
+        if (st != SPMV_OK) return st;
+        radix_scatter_kernel<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(ka, va, n, shift, offs, ntiles, kb, vb);
+        SPMV_CHECK_LAUNCH("radix scatter");
+        uint32_t *tk = ka; ka = kb; kb = tk;
+        int32_t *tv = va; va = vb; vb = tv;
+        ++passes;
+    }
+    if (passes & 1) {
+        SPMV_HIP(hipMemcpyAsync(keys, ka, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+        SPMV_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    }
+    return SPMV_OK;
+}
+
+static int bits_for(int64_t maxval)
+{
+    int b = 0;
+    while (b < 32 && ((int64_t)1 << b) <= maxval) ++b;
+    return b;
+}
+
+// ============================================================ small kernels
+
+#define GRID_LOOP(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+static unsigned grid_for(int64_t n)
+{
+    int64_t g = ceil_div(n, 256);
+    if (g > 65536) g = 65536;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+__global__ void iota_kernel(int32_t *out, int64_t n) { GRID_LOOP(i, n) out[i] = (int32_t)i; }
+
+__global__ void copy_u32_kernel(const int32_t *__restrict__ in, uint32_t *__restrict__ out, int64_t n)
+{
+    GRID_LOOP(i, n) out[i] = (uint32_t)in[i];
+}
+
+__global__ void gather_u32_kernel(const int32_t *__restrict__ src, const int32_t *__restrict__ idx,
+                                  uint32_t *__restrict__ out, int64_t n)
+{
+    GRID_LOOP(i, n) out[i] = (uint32_t)src[idx[i]];
+}
+
+__global__ void coo_check_kernel(const int32_t *__restrict__ row, const int32_t *__restrict__ col, int64_t n,
+                                 int32_t n_rows, int32_t n_cols, int32_t *__restrict__ bad)
+{
+    GRID_LOOP(i, n)
+    {
+        if (row[i] < 0 || row[i] >= n_rows || col[i] < 0 || col[i] >= n_cols) atomicOr(bad, 1);
+    }
+}
+
+// sorted (row, col) pairs -> 1 where a new (row, col) starts
+__global__ void head_flags_kernel(const uint32_t *__restrict__ rk, const int32_t *__restrict__ idx,
+                                  const int32_t *__restrict__ col, int64_t n, int32_t *__restrict__ flag)
+{
+    GRID_LOOP(i, n)
+    {
+        int32_t f = 1;
+        if (i > 0 && rk[i] == rk[i - 1] && col[idx[i]] == col[idx[i - 1]]) f = 0;
+        flag[i] = f;
+    }
+}
+
+// one thread per run of equal (row, col): sums the run's values in input order
+template <typename T>
+__global__ void compact_kernel(const uint32_t *__restrict__ rk, const int32_t *__restrict__ idx,
+                               const int32_t *__restrict__ col, const T *__restrict__ val,
+                               const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t n,
+                               int32_t *__restrict__ col_out, T *__restrict__ val_out, int32_t *__restrict__ row_u)
+{
+    GRID_LOOP(i, n)
+    {
+        if (!flag[i]) continue;
+        const int32_t p = pos[i];
+        T s = val[idx[i]];
+        for (int64_t j = i + 1; j < n && !flag[j]; ++j) s = s + val[idx[j]];
+        col_out[p] = col[idx[i]];
+        val_out[p] = s;
+        row_u[p] = (int32_t)rk[i];
+    }
+}
+
+// first index in sorted a[0..n) with a[idx] >= key
+template <typename T, typename K>
+__device__ __forceinline__ int64_t lower_bound_dev(const T *a, int64_t n, K key)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((K)a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void ptr_from_sorted_kernel(const T *__restrict__ sorted, int64_t n, int32_t nseg,
+                                       int32_t *__restrict__ ptr)
+{
+    GRID_LOOP(r, (int64_t)nseg + 1) ptr[r] = (int32_t)lower_bound_dev(sorted, n, (int64_t)r);
+}
+
+__global__ void validate_rows_kernel(const int32_t *__restrict__ rp, int32_t n_rows, int64_t nnz,
+                                     int32_t *__restrict__ bad)
+{
+    GRID_LOOP(r, (int64_t)n_rows)
+    {
+        if (rp[r + 1] < rp[r]) atomicOr(bad, 1);
+        if (r == 0 && rp[0] != 0) atomicOr(bad, 2);
+        if (r == n_rows - 1 && (int64_t)rp[n_rows] != nnz) atomicOr(bad, 4);
+    }
+}
+
+__global__ void validate_cols_kernel(const int32_t *__restrict__ col, int64_t nnz, int32_t n_cols,
+                                     int32_t *__restrict__ bad)
+{
+    GRID_LOOP(k, nnz)
+    {
+        if (col[k] < 0 || col[k] >= n_cols) atomicOr(bad, 8);
+    }
+}
+
+__global__ void row_len_kernel(const int32_t *__restrict__ rp, int32_t n, int32_t *__restrict__ len,
+                               int32_t *__restrict__ maxlen)
+{
+    GRID_LOOP(r, (int64_t)n)
+    {
+        int32_t l = rp[r + 1] - rp[r];
+        len[r] = l;
+        atomicMax(maxlen, l);
+    }
+}
+
+__global__ void desc_key_kernel(const int32_t *__restrict__ len, int32_t n, int32_t ndiag, uint32_t *__restrict__ key)
+{
+    GRID_LOOP(r, (int64_t)n) key[r] = (uint32_t)(ndiag - len[r]);
+}
+
+__global__ void inverse_perm_kernel(const int32_t *__restrict__ perm, int32_t n, int32_t *__restrict__ iperm)
+{
+    GRID_LOOP(r, (int64_t)n) iperm[perm[r]] = (int32_t)r;
+}
+
+// count[d] = rows longer than d = first permuted row whose length is <= d
+__global__ void diag_count_kernel(const uint32_t *__restrict__ skey, int32_t n, int32_t ndiag,
+                                  int32_t *__restrict__ count)
+{
+    GRID_LOOP(d, (int64_t)ndiag)
+    {
+        // lengths ndiag - skey[r] never increase; find first r with length <= d
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)ndiag - (int64_t)skey[mid] > d) lo = mid + 1;
+            else hi = mid;
+        }
+        count[d] = (int32_t)lo;
+    }
+}
+
+// row containing CRS entry j: last r with rp[r] <= j
+__device__ __forceinline__ int32_t row_of(const int32_t *__restrict__ rp, int32_t n, int64_t j)
+{
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)rp[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void jds_scatter_kernel(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                   const T *__restrict__ val, int32_t n, int64_t nnz, const int32_t *__restrict__ iperm,
+                                   const int32_t *__restrict__ jd_ptr, int symperm, int32_t *__restrict__ jd_col,
+                                   T *__restrict__ jd_val)
+{
+    GRID_LOOP(j, nnz)
+    {
+        const int32_t i = row_of(rp, n, j);
+        const int32_t d = (int32_t)(j - rp[i]);
+        const int64_t dst = (int64_t)jd_ptr[d] + iperm[i];
+        const int32_t c = col[j];
+        jd_col[dst] = symperm ? iperm[c] : c;
+        jd_val[dst] = val[j];
+    }
+}
+
+// length of permuted row r from the diagonal lengths
+__device__ __forceinline__ int32_t jds_len_of(const int32_t *__restrict__ jp, int32_t ndiag, int64_t r)
+{
+    int32_t lo = 0, hi = ndiag;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if ((int64_t)(jp[mid + 1] - jp[mid]) > r) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void jds_row_len_kernel(const int32_t *__restrict__ jp, int32_t ndiag, const int32_t *__restrict__ perm,
+                                   int32_t n, int32_t *__restrict__ len)
+{
+    GRID_LOOP(r, (int64_t)n) len[perm[r]] = jds_len_of(jp, ndiag, r);
+}
+
+// diagonal holding JDS entry e: last d with jp[d] <= e
+__device__ __forceinline__ int32_t diag_of(const int32_t *__restrict__ jp, int32_t ndiag, int64_t e)
+{
+    int32_t lo = 0, hi = ndiag - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)jp[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void jds_to_csr_kernel(const int32_t *__restrict__ jp, int32_t ndiag, int64_t nnz,
+                                  const int32_t *__restrict__ perm, const int32_t *__restrict__ jd_col,
+                                  const T *__restrict__ jd_val, int symperm, const int32_t *__restrict__ rp,
+                                  int32_t *__restrict__ col, T *__restrict__ val)
+{
+    GRID_LOOP(e, nnz)
+    {
+        const int32_t d = diag_of(jp, ndiag, e);
+        const int32_t r = (int32_t)(e - jp[d]);
+        const int32_t i = perm[r];
+        const int64_t dst = (int64_t)rp[i] + d;
+        const int32_t c = jd_col[e];
+        col[dst] = symperm ? perm[c] : c;
+        val[dst] = jd_val[e];
+    }
+}
+
+__global__ void slice_nd_kernel(const int32_t *__restrict__ jp, int32_t ndiag, int32_t C, int32_t n_slices,
+                                int32_t *__restrict__ nd, int64_t *__restrict__ sz)
+{
+    GRID_LOOP(s, (int64_t)n_slices)
+    {
+        int32_t l = jds_len_of(jp, ndiag, s * (int64_t)C);
+        nd[s] = l;
+        sz[s] = (int64_t)l * C;
+    }
+}
+
+template <typename T>
+__global__ void blocked_fill_kernel(const int32_t *__restrict__ jp, int32_t ndiag, const int32_t *__restrict__ jd_col,
+                                    const T *__restrict__ jd_val, int32_t n, int32_t C,
+                                    const int64_t *__restrict__ slice_ptr, int32_t n_slices, int64_t total,
+                                    int32_t *__restrict__ bl_col, T *__restrict__ bl_val)
+{
+    GRID_LOOP(k, total)
+    {
+        int32_t lo = 0, hi = n_slices - 1;
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) >> 1;
+            if (slice_ptr[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t local = k - slice_ptr[lo];
+        const int32_t d = (int32_t)(local / C);
+        const int32_t rl = (int32_t)(local - (int64_t)d * C);
+        const int64_t r = (int64_t)lo * C + rl;
+        if (r < n && (int64_t)(jp[d + 1] - jp[d]) > r) {
+            bl_col[k] = jd_col[jp[d] + r];
+            bl_val[k] = jd_val[jp[d] + r];
+        } else {
+            bl_col[k] = -1;
+            bl_val[k] = T{};
+        }
+    }
+}
+
+// SOJDS: one thread per slice re-assigns each row's entries to diagonal slots
+// (first row keeps CRS order; later rows take, slot by slot, the unused entry
+// whose column is nearest to the previous row's column in that slot plus one,
+// the smaller column on a tie).  `taken` holds one bit per entry of a row.
+template <typename T>
+__global__ void sojds_kernel(const int32_t *__restrict__ jp, int32_t ndiag, const int32_t *__restrict__ jd_col,
+                             const T *__restrict__ jd_val, int32_t n, int32_t C, const int64_t *__restrict__ slice_ptr,
+                             int32_t n_slices, int32_t words, uint32_t *__restrict__ taken_all,
+                             int32_t *__restrict__ bl_col, T *__restrict__ bl_val)
+{
+    GRID_LOOP(s, (int64_t)n_slices)
+    {
+        uint32_t *taken = taken_all + s * (int64_t)words;
+        const int64_t sp = slice_ptr[s];
+        for (int32_t rl = 1; rl < C; ++rl) {
+            const int64_t r = s * (int64_t)C + rl;
+            if (r >= n) break;
+            const int32_t len = jds_len_of(jp, ndiag, r);
+            for (int32_t q = 0; q < (len + 31) / 32; ++q) taken[q] = 0;
+            for (int32_t d = 0; d < len; ++d) {
+                const int64_t want = (int64_t)bl_col[sp + (int64_t)d * C + rl - 1] + 1;
+                int32_t pick = -1;
+                int64_t best = 0, bestc = 0;
+                for (int32_t e = 0; e < len; ++e) {
+                    if (taken[e >> 5] & (1u << (e & 31))) continue;
+                    const int64_t c = jd_col[jp[e] + r];
+                    const int64_t dist = c > want ? c - want : want - c;
+                    if (pick < 0 || dist < best || (dist == best && c < bestc)) {
+                        pick = e;
+                        best = dist;
+                        bestc = c;
+                    }
+                }
+                taken[pick >> 5] |= 1u << (pick & 31);
+                bl_col[sp + (int64_t)d * C + rl] = jd_col[jp[pick] + r];
+                bl_val[sp + (int64_t)d * C + rl] = jd_val[jp[pick] + r];
+            }
+        }
+    }
+}
+
+__global__ void transpose_cols_kernel(const int32_t *__restrict__ rp, int32_t n_rows, const int32_t *__restrict__ tmap,
+                                      int64_t nnz, int32_t *__restrict__ colT)
+{
+    GRID_LOOP(t, nnz) colT[t] = row_of(rp, n_rows, tmap[t]);
+}
+
+// one round-to-nearest-even step from double to bfloat16
+__device__ __forceinline__ uint16_t f64_to_bf16_rne(double d)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(d);
+    const uint16_t sign = (uint16_t)((b >> 48) & 0x8000u);
+    const uint64_t a = b & 0x7fffffffffffffffull;
+    if (a > 0x7ff0000000000000ull) return (uint16_t)(sign | 0x7fc0u);        // NaN
+    if (a == 0x7ff0000000000000ull) return (uint16_t)(sign | 0x7f80u);       // inf
+    const int e = (int)(a >> 52) - 1023;
+    if (e >= -126) {
+        uint64_t q = a >> 45;                        // exponent + 7 mantissa bits
+        const uint64_t rem = a & ((1ull << 45) - 1);
+        const uint64_t half = 1ull << 44;
+        if (rem > half || (rem == half && (q & 1))) ++q;
+        int64_t bits = (int64_t)q - ((int64_t)(1023 - 127) << 7);
+        if (bits >= 0x7f80) bits = 0x7f80;            // overflow to infinity
+        return (uint16_t)(sign | (uint16_t)bits);
+    }
+    // below the smallest normal: multiples of 2^-133, ties to even
+    const double m = rint(__longlong_as_double((long long)a) * 0x1p133);
+    return (uint16_t)(sign | (uint16_t)m);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7fffu + lsb) >> 16);
+}
+
+__global__ void convert_kernel(int64_t n, const void *__restrict__ in, int in_dt, void *__restrict__ out, int out_dt)
+{
+    GRID_LOOP(i, n)
+    {
+        if (in_dt == SPMV_F64) {
+            const double v = ((const double *)in)[i];
+            if (out_dt == SPMV_F32) ((float *)out)[i] = (float)v;
+            else if (out_dt == SPMV_BF16) ((uint16_t *)out)[i] = f64_to_bf16_rne(v);
+            else ((double *)out)[i] = v;
+        } else if (in_dt == SPMV_F32) {
+            const float v = ((const float *)in)[i];
+            if (out_dt == SPMV_F64) ((double *)out)[i] = (double)v;
+            else if (out_dt == SPMV_BF16) ((uint16_t *)out)[i] = f32_to_bf16_rne(v);
+            else ((float *)out)[i] = v;
+        } else {
+            const float v = __uint_as_float((uint32_t)((const uint16_t *)in)[i] << 16);
+            if (out_dt == SPMV_F64) ((double *)out)[i] = (double)v;
+            else if (out_dt == SPMV_F32) ((float *)out)[i] = v;
+            else ((uint16_t *)out)[i] = ((const uint16_t *)in)[i];
+        }
+    }
+}
+
+template <typename T>
+__global__ void permute_kernel(int32_t n, const int32_t *__restrict__ perm, const T *__restrict__ in,
+                               T *__restrict__ out, int inverse)
+{
+    GRID_LOOP(r, (int64_t)n)
+    {
+        if (inverse) out[perm[r]] = in[r];
+        else out[r] = in[perm[r]];
+    }
+}
+
+template <typename T>
+__global__ void gather_kernel(int64_t n, const int32_t *__restrict__ map, const T *__restrict__ in, T *__restrict__ out)
+{
+    GRID_LOOP(i, n) out[i] = in[map[i]];
+}
+
+// dtype-dispatched launch of a kernel templated on the element type
+template <template <typename> class K>
+struct DtDispatch;
+
+// ============================================================ host helpers
+
+static spmv_status read_flag(const int32_t *dev, int32_t *host, hipStream_t s)
+{
+    SPMV_HIP(hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+static size_t coo_ws_bytes(int32_t n_rows, int32_t n_cols, int64_t nnz)
+{
+    (void)n_rows;
+    (void)n_cols;
+    size_t n = (size_t)(nnz > 0 ? nnz : 1);
+    size_t b = 0;
+    b += align_up(sizeof(int32_t), 256);            // flag
+    b += align_up(sizeof(uint32_t) * n, 256);        // keys
+    b += align_up(sizeof(int32_t) * n, 256);         // idx
+    b += align_up(sizeof(int32_t) * n, 256);         // head flags
+    b += align_up(sizeof(int32_t) * (n + 1), 256);   // positions
+    b += align_up(sizeof(int32_t) * n, 256);         // unique rows
+    b += align_up(sizeof(int32_t) * scan_ws_elems((int64_t)n), 256);
+    b += radix_ws_bytes((int64_t)n);
+    return b + 1024;
+}
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" {
+
+size_t spmv_csr_from_coo_workspace_size(int32_t n_rows, int32_t n_cols, int64_t nnz)
+{
+    return coo_ws_bytes(n_rows, n_cols, nnz);
+}
+
+spmv_status spmv_csr_from_coo(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row, const int32_t *col,
+                              const void *val, spmv_dtype dt, int32_t *row_ptr, int32_t *col_idx, void *val_out,
+                              int64_t *h_nnz_out, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && nnz >= 0, "spmv_csr_from_coo: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_csr_from_coo: nnz >= 2^31");
+    SPMV_REQUIRE(dt == SPMV_F64 || dt == SPMV_F32, "spmv_csr_from_coo: dtype must be F64 or F32");
+    SPMV_REQUIRE(row_ptr && h_nnz_out, "spmv_csr_from_coo: null row_ptr or h_nnz_out");
+    SPMV_REQUIRE(nnz == 0 || (row && col && val && col_idx && val_out), "spmv_csr_from_coo: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= coo_ws_bytes(n_rows, n_cols, nnz), "spmv_csr_from_coo: workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    int32_t *flag_dev = wc.take<int32_t>(1);
+    uint32_t *keys = wc.take<uint32_t>((size_t)(nnz > 0 ? nnz : 1));
+    int32_t *idx = wc.take<int32_t>((size_t)(nnz > 0 ? nnz : 1));
+    int32_t *head = wc.take<int32_t>((size_t)(nnz > 0 ? nnz : 1));
+    int32_t *pos = wc.take<int32_t>((size_t)nnz + 1);
+    int32_t *row_u = wc.take<int32_t>((size_t)(nnz > 0 ? nnz : 1));
+    int32_t *sws = wc.take<int32_t>(scan_ws_elems(nnz > 0 ? nnz : 1));
+    size_t rws_bytes = radix_ws_bytes(nnz);
+    void *rws = wc.take<char>(rws_bytes);
+    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_csr_from_coo: workspace too small");
+
+    if (nnz == 0) {
+        SPMV_HIP(hipMemsetAsync(row_ptr, 0, sizeof(int32_t) * ((size_t)n_rows + 1), s));
+        SPMV_HIP(hipStreamSynchronize(s));
+        *h_nnz_out = 0;
+        return SPMV_OK;
+    }
+    SPMV_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int32_t), s));
+    coo_check_kernel<<<grid_for(nnz), 256, 0, s>>>(row, col, nnz, n_rows, n_cols, flag_dev);
+    SPMV_CHECK_LAUNCH("coo check");
+    int32_t bad = 0;
+    if (read_flag(flag_dev, &bad, s) != SPMV_OK) return SPMV_ERR_HIP;
+    if (bad) return fail(SPMV_ERR_BAD_FORMAT, "spmv_csr_from_coo: row or column index out of range");
+
+    // stable sort by column, then stably by row: order (row, col, input index)
+    copy_u32_kernel<<<grid_for(nnz), 256, 0, s>>>(col, keys, nnz);
+    iota_kernel<<<grid_for(nnz), 256, 0, s>>>(idx, nnz);
+    SPMV_CHECK_LAUNCH("coo init");
+    spmv_status st = radix_sort_pairs(keys, idx, nnz, bits_for(n_cols > 0 ? n_cols - 1 : 0), rws, rws_bytes, s);
+    if (st != SPMV_OK) return st;
+    gather_u32_kernel<<<grid_for(nnz), 256, 0, s>>>(row, idx, keys, nnz);
+    SPMV_CHECK_LAUNCH("coo gather rows");
+    st = radix_sort_pairs(keys, idx, nnz, bits_for(n_rows > 0 ? n_rows - 1 : 0), rws, rws_bytes, s);
+    if (st != SPMV_OK) return st;
+
+    head_flags_kernel<<<grid_for(nnz), 256, 0, s>>>(keys, idx, col, nnz, head);
+    SPMV_CHECK_LAUNCH("coo heads");
+    st = exclusive_scan<int32_t, int32_t>(head, nnz, pos, sws, s);
+    if (st != SPMV_OK) return st;
+    int32_t nout = 0;
+    if (read_flag(pos + nnz, &nout, s) != SPMV_OK) return SPMV_ERR_HIP;
+    if (dt == SPMV_F64)
+        compact_kernel<double><<<grid_for(nnz), 256, 0, s>>>(keys, idx, col, (const double *)val, head, pos, nnz,
+                                                             col_idx, (double *)val_out, row_u);
+    else
+        compact_kernel<float><<<grid_for(nnz), 256, 0, s>>>(keys, idx, col, (const float *)val, head, pos, nnz,
+                                                            col_idx, (float *)val_out, row_u);
+    SPMV_CHECK_LAUNCH("coo compact");
+    ptr_from_sorted_kernel<int32_t><<<grid_for((int64_t)n_rows + 1), 256, 0, s>>>(row_u, nout, n_rows, row_ptr);
+    SPMV_CHECK_LAUNCH("coo row_ptr");
+    SPMV_HIP(hipStreamSynchronize(s));
+    *h_nnz_out = nout;
+    return SPMV_OK;
+}
+
+size_t spmv_csr_validate_workspace_size(void) { return 256; }
+
+spmv_status spmv_csr_validate(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, int32_t *h_ok, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && nnz >= 0, "spmv_csr_validate: negative size");
+    SPMV_REQUIRE(h_ok && row_ptr && ws && ws_bytes >= 4, "spmv_csr_validate: null pointer");
+    SPMV_REQUIRE(nnz == 0 || col_idx, "spmv_csr_validate: null col_idx");
+    hipStream_t s = as_stream(stream);
+    int32_t *bad = (int32_t *)ws;
+    SPMV_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+    if (n_rows > 0) validate_rows_kernel<<<grid_for(n_rows), 256, 0, s>>>(row_ptr, n_rows, nnz, bad);
+    if (nnz > 0) validate_cols_kernel<<<grid_for(nnz), 256, 0, s>>>(col_idx, nnz, n_cols, bad);
+    SPMV_CHECK_LAUNCH("spmv_csr_validate");
+    int32_t b = 0;
+    if (read_flag(bad, &b, s) != SPMV_OK) return SPMV_ERR_HIP;
+    if (n_rows == 0) {
+        int32_t first = 0;
+        if (read_flag(row_ptr, &first, s) != SPMV_OK) return SPMV_ERR_HIP;
+        if (first != 0 || nnz != 0) b |= 2;
+    }
+    *h_ok = b == 0 ? 1 : 0;
+    return SPMV_OK;
+}
+
+size_t spmv_jds_from_csr_workspace_size(int32_t n, int64_t nnz)
+{
+    size_t m = (size_t)(n > 0 ? n : 1);
+    size_t b = 0;
+    b += 256;                                       // max length
+    b += align_up(sizeof(int32_t) * m, 256);        // lengths
+    b += align_up(sizeof(uint32_t) * m, 256);       // keys
+    b += align_up(sizeof(int32_t) * scan_ws_elems((int64_t)(m > (size_t)nnz ? m : (size_t)nnz)), 256);
+    b += radix_ws_bytes((int64_t)m);
+    return b + 1024;
+}
+
+spmv_status spmv_jds_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                              const void *val, spmv_dtype dt, unsigned flags, int32_t *perm, int32_t *iperm,
+                              int32_t *jd_ptr, int32_t jd_ptr_cap, int32_t *jd_col, void *jd_val, int32_t *h_ndiag,
+                              int32_t *h_jd_ptr, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && nnz >= 0, "spmv_jds_from_csr: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_jds_from_csr: nnz >= 2^31");
+    SPMV_REQUIRE(valid_dtype(dt), "spmv_jds_from_csr: bad dtype");
+    SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_jds_from_csr: unknown flag");
+    SPMV_REQUIRE(h_ndiag && row_ptr && jd_ptr, "spmv_jds_from_csr: null pointer");
+    SPMV_REQUIRE(n == 0 || (perm && iperm), "spmv_jds_from_csr: null perm");
+    SPMV_REQUIRE(nnz == 0 || (col_idx && val && jd_col && jd_val), "spmv_jds_from_csr: null arrays");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_jds_from_csr_workspace_size(n, nnz), "spmv_jds_from_csr: workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    int32_t *maxlen = wc.take<int32_t>(1);
+    int32_t *len = wc.take<int32_t>((size_t)(n > 0 ? n : 1));
+    uint32_t *keys = wc.take<uint32_t>((size_t)(n > 0 ? n : 1));
+    int32_t *sws = wc.take<int32_t>(scan_ws_elems((int64_t)n > nnz ? (int64_t)n : (nnz > 0 ? nnz : 1)));
+    size_t rws_bytes = radix_ws_bytes(n);
+    void *rws = wc.take<char>(rws_bytes);
+    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_jds_from_csr: workspace too small");
+
+    int32_t ndiag = 0;
+    if (n > 0) {
+        SPMV_HIP(hipMemsetAsync(maxlen, 0, sizeof(int32_t), s));
+        row_len_kernel<<<grid_for(n), 256, 0, s>>>(row_ptr, n, len, maxlen);
+        SPMV_CHECK_LAUNCH("jds lengths");
+        if (read_flag(maxlen, &ndiag, s) != SPMV_OK) return SPMV_ERR_HIP;
+    }
+    *h_ndiag = ndiag;
+    if (jd_ptr_cap < ndiag + 1) return fail(SPMV_ERR_CAPACITY, "spmv_jds_from_csr: jd_ptr capacity < ndiag+1");
+    if (n == 0) {
+        SPMV_HIP(hipMemsetAsync(jd_ptr, 0, sizeof(int32_t), s));
+        SPMV_HIP(hipStreamSynchronize(s));
+        if (h_jd_ptr) h_jd_ptr[0] = 0;
+        return SPMV_OK;
+    }
+    // stable sort of the rows by decreasing length: key = ndiag - length
+    desc_key_kernel<<<grid_for(n), 256, 0, s>>>(len, n, ndiag, keys);
+    iota_kernel<<<grid_for(n), 256, 0, s>>>(perm, n);
+    SPMV_CHECK_LAUNCH("jds keys");
+    spmv_status st = radix_sort_pairs(keys, perm, n, bits_for(ndiag), rws, rws_bytes, s);
+    if (st != SPMV_OK) return st;
+    inverse_perm_kernel<<<grid_for(n), 256, 0, s>>>(perm, n, iperm);
+    SPMV_CHECK_LAUNCH("jds iperm");
+    if (ndiag > 0) {
+        // diagonal lengths go into jd_ptr itself, then an in-place scan
+        diag_count_kernel<<<grid_for(ndiag), 256, 0, s>>>(keys, n, ndiag, jd_ptr);
+        SPMV_CHECK_LAUNCH("jds diagonal counts");
+        st = exclusive_scan<int32_t, int32_t>(jd_ptr, ndiag, jd_ptr, sws, s);
+        if (st != SPMV_OK) return st;
+    } else {
+        SPMV_HIP(hipMemsetAsync(jd_ptr, 0, sizeof(int32_t), s));
+    }
+    const int sym = (flags & SPMV_SYMPERM) ? 1 : 0;
+    if (nnz > 0) {
+        if (dt == SPMV_F64)
+            jds_scatter_kernel<uint64_t><<<grid_for(nnz), 256, 0, s>>>(row_ptr, col_idx, (const uint64_t *)val, n, nnz,
+                                                                     iperm, jd_ptr, sym, jd_col, (uint64_t *)jd_val);
+        else if (dt == SPMV_F32)
+            jds_scatter_kernel<uint32_t><<<grid_for(nnz), 256, 0, s>>>(row_ptr, col_idx, (const uint32_t *)val, n, nnz,
+                                                                    iperm, jd_ptr, sym, jd_col, (uint32_t *)jd_val);
+        else
+            jds_scatter_kernel<uint16_t><<<grid_for(nnz), 256, 0, s>>>(row_ptr, col_idx, (const uint16_t *)val, n,
+                                                                       nnz, iperm, jd_ptr, sym, jd_col,
+                                                                       (uint16_t *)jd_val);
+        SPMV_CHECK_LAUNCH("jds scatter");
+    }
+    if (h_jd_ptr)
+        SPMV_HIP(hipMemcpyAsync(h_jd_ptr, jd_ptr, sizeof(int32_t) * ((size_t)ndiag + 1), hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+size_t spmv_jds_to_csr_workspace_size(int32_t n)
+{
+    size_t m = (size_t)(n > 0 ? n : 1);
+    return align_up(sizeof(int32_t) * m, 256) + align_up(sizeof(int32_t) * scan_ws_elems((int64_t)m), 256) + 512;
+}
+
+spmv_status spmv_jds_to_csr(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag, const int32_t *jd_col,
+                            const void *jd_val, spmv_dtype dt, unsigned flags, int32_t *row_ptr, int32_t *col_idx,
+                            void *val, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && ndiag >= 0, "spmv_jds_to_csr: negative size");
+    SPMV_REQUIRE(valid_dtype(dt), "spmv_jds_to_csr: bad dtype");
+    SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_jds_to_csr: unknown flag");
+    SPMV_REQUIRE(row_ptr && jd_ptr, "spmv_jds_to_csr: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_jds_to_csr_workspace_size(n), "spmv_jds_to_csr: workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    int32_t *len = wc.take<int32_t>((size_t)(n > 0 ? n : 1));
+    int32_t *sws = wc.take<int32_t>(scan_ws_elems(n > 0 ? n : 1));
+    if (n == 0) {
+        SPMV_HIP(hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s));
+        return SPMV_OK;
+    }
+    SPMV_REQUIRE(perm, "spmv_jds_to_csr: null perm");
+    jds_row_len_kernel<<<grid_for(n), 256, 0, s>>>(jd_ptr, ndiag, perm, n, len);
+    SPMV_CHECK_LAUNCH("jds_to_csr lengths");
+    spmv_status st = exclusive_scan<int32_t, int32_t>(len, n, row_ptr, sws, s);
+    if (st != SPMV_OK) return st;
+    int32_t nnz = 0;
+    SPMV_HIP(hipMemcpyAsync(&nnz, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    if (nnz == 0) return SPMV_OK;
+    SPMV_REQUIRE(jd_col && jd_val && col_idx && val, "spmv_jds_to_csr: null arrays");
+    const int sym = (flags & SPMV_SYMPERM) ? 1 : 0;
+    if (dt == SPMV_F64)
+        jds_to_csr_kernel<uint64_t><<<grid_for(nnz), 256, 0, s>>>(jd_ptr, ndiag, nnz, perm, jd_col,
+                                                                (const uint64_t *)jd_val, sym, row_ptr, col_idx,
+                                                                (uint64_t *)val);
+    else if (dt == SPMV_F32)
+        jds_to_csr_kernel<uint32_t><<<grid_for(nnz), 256, 0, s>>>(jd_ptr, ndiag, nnz, perm, jd_col, (const uint32_t *)jd_val,
+                                                               sym, row_ptr, col_idx, (uint32_t *)val);
+    else
+        jds_to_csr_kernel<uint16_t><<<grid_for(nnz), 256, 0, s>>>(jd_ptr, ndiag, nnz, perm, jd_col,
+                                                                  (const uint16_t *)jd_val, sym, row_ptr, col_idx,
+                                                                  (uint16_t *)val);
+    SPMV_CHECK_LAUNCH("jds_to_csr scatter");
+    return SPMV_OK;
+}
+
+size_t spmv_jds_blocked_workspace_size(int32_t n, int32_t ndiag, int32_t C, unsigned flags)
+{
+    if (C <= 0) return 0;
+    size_t ns = (size_t)ceil_div(n > 0 ? n : 1, C);
+    size_t b = align_up(sizeof(int64_t) * ns, 256) + align_up(sizeof(int64_t) * scan_ws_elems((int64_t)ns), 256);
+    if (flags & SPMV_SOJDS) b += align_up(sizeof(uint32_t) * ns * (size_t)ceil_div(ndiag > 0 ? ndiag : 1, 32), 256);
+    return b + 1024;
+}
+
+spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t ndiag, const int32_t *jd_col,
+                                      const void *jd_val, spmv_dtype dt, int32_t C, unsigned flags, int64_t *slice_ptr,
+                                      int32_t *slice_nd, int32_t *bl_col, void *bl_val, int64_t bl_cap,
+                                      int64_t *h_padded, int32_t *h_slice_nd, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && ndiag >= 0, "spmv_jds_blocked_from_jds: negative size");
+    SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_from_jds: C must be a positive multiple of 64");
+    SPMV_REQUIRE(valid_dtype(dt), "spmv_jds_blocked_from_jds: bad dtype");
+    SPMV_REQUIRE((flags & ~SPMV_SOJDS) == 0, "spmv_jds_blocked_from_jds: unknown flag");
+    SPMV_REQUIRE(jd_ptr && slice_ptr && h_padded, "spmv_jds_blocked_from_jds: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_jds_blocked_workspace_size(n, ndiag, C, flags),
+                 "spmv_jds_blocked_from_jds: workspace too small");
+    hipStream_t s = as_stream(stream);
+    const int32_t ns = (int32_t)ceil_div(n, C);
+    WsCarver wc(ws, ws_bytes);
+    int64_t *sz = wc.take<int64_t>((size_t)(ns > 0 ? ns : 1));
+    int64_t *sws = wc.take<int64_t>(scan_ws_elems(ns > 0 ? ns : 1));
+    uint32_t *taken = (flags & SPMV_SOJDS) ? wc.take<uint32_t>((size_t)(ns > 0 ? ns : 1) *
+                                                               (size_t)ceil_div(ndiag > 0 ? ndiag : 1, 32))
+                                           : nullptr;
+    if (ns == 0) {
+        SPMV_HIP(hipMemsetAsync(slice_ptr, 0, sizeof(int64_t), s));
+        SPMV_HIP(hipStreamSynchronize(s));
+        *h_padded = 0;
+        return SPMV_OK;
+    }
+    SPMV_REQUIRE(slice_nd, "spmv_jds_blocked_from_jds: null slice_nd");
+    slice_nd_kernel<<<grid_for(ns), 256, 0, s>>>(jd_ptr, ndiag, C, ns, slice_nd, sz);
+    SPMV_CHECK_LAUNCH("blocked slice sizes");
+    spmv_status st = exclusive_scan<int64_t, int64_t>(sz, ns, slice_ptr, sws, s);
+    if (st != SPMV_OK) return st;
+    int64_t total = 0;
+    SPMV_HIP(hipMemcpyAsync(&total, slice_ptr + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (h_slice_nd) SPMV_HIP(hipMemcpyAsync(h_slice_nd, slice_nd, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    *h_padded = total;
+    if (bl_cap < total) return fail(SPMV_ERR_CAPACITY, "spmv_jds_blocked_from_jds: capacity < padded size");
+    if (total == 0) return SPMV_OK;
+    SPMV_REQUIRE(jd_col && jd_val && bl_col && bl_val, "spmv_jds_blocked_from_jds: null arrays");
+    const int32_t words = (int32_t)ceil_div(ndiag > 0 ? ndiag : 1, 32);
+#define BLK_CASE(DT, T)                                                                                             \
+    if (dt == DT) {                                                                                                 \
+        blocked_fill_kernel<T><<<grid_for(total), 256, 0, s>>>(jd_ptr, ndiag, jd_col, (const T *)jd_val, n, C,      \
+                                                               slice_ptr, ns, total, bl_col, (T *)bl_val);          \
+        SPMV_CHECK_LAUNCH("blocked fill");                                                                          \
+        if (flags & SPMV_SOJDS) {                                                                                   \
+            sojds_kernel<T><<<grid_for(ns), 64, 0, s>>>(jd_ptr, ndiag, jd_col, (const T *)jd_val, n, C, slice_ptr,  \
+                                                        ns, words, taken, bl_col, (T *)bl_val);                     \
+            SPMV_CHECK_LAUNCH("sojds");                                                                             \
+        }                                                                                                           \
+    }
+    BLK_CASE(SPMV_F64, uint64_t)
+    BLK_CASE(SPMV_F32, uint32_t)
+    BLK_CASE(SPMV_BF16, uint16_t)
+#undef BLK_CASE
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+size_t spmv_transpose_workspace_size(int32_t n_rows, int32_t n_cols, int64_t nnz)
+{
+    (void)n_rows;
+    (void)n_cols;
+    size_t n = (size_t)(nnz > 0 ? nnz : 1);
+    return align_up(sizeof(uint32_t) * n, 256) + radix_ws_bytes((int64_t)n) + 512;
+}
+
+spmv_status spmv_transpose_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, int32_t *rowT_ptr, int32_t *colT, int32_t *tmap, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && nnz >= 0, "spmv_transpose_csr: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_transpose_csr: nnz >= 2^31");
+    SPMV_REQUIRE(rowT_ptr && row_ptr, "spmv_transpose_csr: null pointer");
+    SPMV_REQUIRE(nnz == 0 || (col_idx && colT && tmap), "spmv_transpose_csr: null arrays");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_transpose_workspace_size(n_rows, n_cols, nnz),
+                 "spmv_transpose_csr: workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    uint32_t *keys = wc.take<uint32_t>((size_t)(nnz > 0 ? nnz : 1));
+    size_t rws_bytes = radix_ws_bytes(nnz);
+    void *rws = wc.take<char>(rws_bytes);
+    if (nnz == 0) {
+        SPMV_HIP(hipMemsetAsync(rowT_ptr, 0, sizeof(int32_t) * ((size_t)n_cols + 1), s));
+        SPMV_HIP(hipStreamSynchronize(s));
+        return SPMV_OK;
+    }
+    // entries are in row order, so a stable sort by column lists each column's
+    // entries by ascending row
+    copy_u32_kernel<<<grid_for(nnz), 256, 0, s>>>(col_idx, keys, nnz);
+    iota_kernel<<<grid_for(nnz), 256, 0, s>>>(tmap, nnz);
+    SPMV_CHECK_LAUNCH("transpose init");
+    spmv_status st = radix_sort_pairs(keys, tmap, nnz, bits_for(n_cols > 0 ? n_cols - 1 : 0), rws, rws_bytes, s);
+    if (st != SPMV_OK) return st;
+    transpose_cols_kernel<<<grid_for(nnz), 256, 0, s>>>(row_ptr, n_rows, tmap, nnz, colT);
+    ptr_from_sorted_kernel<uint32_t><<<grid_for((int64_t)n_cols + 1), 256, 0, s>>>(keys, nnz, n_cols, rowT_ptr);
+    SPMV_CHECK_LAUNCH("transpose structure");
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+spmv_status spmv_convert_values(int64_t n, const void *in, spmv_dtype in_dt, void *out, spmv_dtype out_dt, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_convert_values: n < 0");
+    SPMV_REQUIRE(valid_dtype(in_dt) && valid_dtype(out_dt), "spmv_convert_values: bad dtype");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(in && out, "spmv_convert_values: null pointer");
+    convert_kernel<<<grid_for(n), 256, 0, as_stream(stream)>>>(n, in, (int)in_dt, out, (int)out_dt);
+    SPMV_CHECK_LAUNCH("spmv_convert_values");
+    return SPMV_OK;
+}
+
+spmv_status spmv_permute_vec(int32_t n, const int32_t *perm, const void *in, void *out, spmv_dtype dt, int inverse,
+                             void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_permute_vec: n < 0");
+    SPMV_REQUIRE(valid_vec_dtype(dt), "spmv_permute_vec: dtype must be F64 or F32");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(perm && in && out && in != out, "spmv_permute_vec: null or aliased pointer");
+    hipStream_t s = as_stream(stream);
+    if (dt == SPMV_F64)
+        permute_kernel<uint64_t><<<grid_for(n), 256, 0, s>>>(n, perm, (const uint64_t *)in, (uint64_t *)out, inverse);
+    else
+        permute_kernel<uint32_t><<<grid_for(n), 256, 0, s>>>(n, perm, (const uint32_t *)in, (uint32_t *)out, inverse);
+    SPMV_CHECK_LAUNCH("spmv_permute_vec");
+    return SPMV_OK;
+}
+
+spmv_status spmv_gather_values(int64_t n, const int32_t *map, const void *in, void *out, spmv_dtype dt, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_gather_values: n < 0");
+    SPMV_REQUIRE(valid_dtype(dt), "spmv_gather_values: bad dtype");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(map && in && out && in != out, "spmv_gather_values: null or aliased pointer");
+    hipStream_t s = as_stream(stream);
+    if (dt == SPMV_F64)
+        gather_kernel<uint64_t><<<grid_for(n), 256, 0, s>>>(n, map, (const uint64_t *)in, (uint64_t *)out);
+    else if (dt == SPMV_F32)
+        gather_kernel<uint32_t><<<grid_for(n), 256, 0, s>>>(n, map, (const uint32_t *)in, (uint32_t *)out);
+    else
+        gather_kernel<uint16_t><<<grid_for(n), 256, 0, s>>>(n, map, (const uint16_t *)in, (uint16_t *)out);
+    SPMV_CHECK_LAUNCH("spmv_gather_values");
+    return SPMV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,393 @@
+// CRS sparse matrix-vector product (paper Section 2, the CRS kernel: each row
+// is a sparse scalar product of its stored values with the gathered x).
+//
+// gfx950 design: the rows are cut, once per matrix, into blocks of consecutive
+// rows holding at most block_nnz entries (and at most 256 rows); a row longer
+// than that is a block of its own.  One 256-lane workgroup per block:
+//   * multi-row block ("stream" mode): the lanes walk the block's entries in
+//     order - fully coalesced val/col reads, independent x gathers - and park
+//     the products in LDS; then G lanes per row (G = 256/rows, a power of two
+//     up to 64) add their row's products and combine with a fixed shuffle tree.
+//   * single-row block ("vector" mode): all 256 lanes stride over the row with
+//     fused multiply-adds, then a fixed wave tree and an ordered sum over the
+//     four waves.
+// Every y element is written once by one lane; no atomics; the summation order
+// depends only on the plan, so results are reproducible.
+// Blocks are remapped so that each XCD walks a contiguous range of rows: the
+// band part of x stays in that XCD's L2.
+#include <vector>
+
+#include "common.hpp"
+
+namespace spmv {
+
+constexpr int CRS_THREADS = 256;
+constexpr int CRS_DEFAULT_BLOCK_NNZ = 1024;
+constexpr int CRS_MAX_BLOCK_NNZ = 4096;
+constexpr int CRS_MAX_BLOCK_ROWS = 256;
+
+template <bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                               const XT *__restrict__ x, XT *__restrict__ y, int32_t row,
+                                               int32_t e0, int32_t e1, double alpha, double beta,
+                                               double *red)
+{
+    typedef typename Acc<WIDE>::T acc_t;
+    acc_t s = 0;
+    int32_t k = e0 + (int32_t)threadIdx.x;
+    constexpr int U = 4;
+    for (; k + (U - 1) * CRS_THREADS < e1; k += U * CRS_THREADS) {
+        int32_t c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = ld_stream(col + k + u * CRS_THREADS);
+            v[u] = ld_stream(val + k + u * CRS_THREADS);
+        }
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s = Acc<WIDE>::mac(s, v[u], xv[u]);
+    }
+    for (; k < e1; k += CRS_THREADS) s = Acc<WIDE>::mac(s, ld_stream(val + k), x[ld_stream(col + k)]);
+    // partials are added in the accumulator type; LDS holds them as double (exact)
+    acc_t t = group_sum(s, WAVE);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = (double)t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        acc_t tot = (acc_t)red[0];
+        for (int w = 1; w < CRS_THREADS / WAVE; ++w) tot += (acc_t)red[w];
+        write_y(y, row, (double)tot, alpha, beta);
+    }
+}
+
+template <typename VT, typename XT>
+__global__ __launch_bounds__(CRS_THREADS) void crs_block_kernel(const int32_t *__restrict__ row_ptr,
+                                                                const int32_t *__restrict__ col,
+                                                                const VT *__restrict__ val,
+                                                                const XT *__restrict__ x, XT *__restrict__ y,
+                                                                const int32_t *__restrict__ plan,
+                                                                double alpha, double beta)
+{
+    constexpr bool F64 = IsF64<VT>::value;
+    typedef typename Acc<F64>::T acc_t;
+    extern __shared__ double smem_d[];
+    __shared__ double red[CRS_THREADS / WAVE];
+    acc_t *prod = reinterpret_cast<acc_t *>(smem_d);
+
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t r0 = plan[b], r1 = plan[b + 1];
+    const int32_t e0 = row_ptr[r0], e1 = row_ptr[r1];
+    const int32_t nr = r1 - r0, ne = e1 - e0;
+
+    if (nr == 1) {
+        if (!F64 && ne > SPMV_WIDE_ROW_NNZ)
+            crs_vector_row<true>(col, val, x, y, r0, e0, e1, alpha, beta, red);
+        else
+            crs_vector_row<F64>(col, val, x, y, r0, e0, e1, alpha, beta, red);
+        return;
+    }
+
+    // stream mode: products of the whole block into LDS (ne <= block_nnz)
+    constexpr int U = 4;
+    for (int32_t k0 = 0; k0 < ne; k0 += U * CRS_THREADS) {
+        int32_t c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int32_t k = k0 + u * CRS_THREADS + (int32_t)threadIdx.x;
+            if (k < ne) {
+                c[u] = ld_stream(col + e0 + k);
+                v[u] = ld_stream(val + e0 + k);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int32_t k = k0 + u * CRS_THREADS + (int32_t)threadIdx.x;
+            if (k < ne) prod[k] = Acc<F64>::mac((acc_t)0, v[u], x[c[u]]);
+        }
+    }
+    __syncthreads();
+
+    // G lanes per row, G = largest power of two <= 256/nr, at most 64
+    int G = 64;
+    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
+    const int g = (int)threadIdx.x / G, l = (int)threadIdx.x % G;
+    acc_t s = 0;
+    if (g < nr) {
+        const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
+        for (int32_t k = rs + l; k < re; k += G) s += prod[k];
+    }
+    s = group_sum(s, G);
+    if (g < nr && l == 0) write_y(y, (int64_t)r0 + g, (double)s, alpha, beta);
+}
+
+// One wavefront per row: the default when no plan is given.
+template <typename VT, typename XT>
+__global__ __launch_bounds__(CRS_THREADS) void crs_wave_kernel(int32_t n_rows, const int32_t *__restrict__ row_ptr,
+                                                               const int32_t *__restrict__ col,
+                                                               const VT *__restrict__ val,
+                                                               const XT *__restrict__ x, XT *__restrict__ y,
+                                                               double alpha, double beta)
+{
+    constexpr bool F64 = IsF64<VT>::value;
+    const int64_t row = xcd_remap(blockIdx.x, gridDim.x) * (CRS_THREADS / WAVE) + threadIdx.x / WAVE;
+    if (row >= n_rows) return;
+    const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+    if (!F64 && e1 - e0 > SPMV_WIDE_ROW_NNZ) {
+        double s = 0;
+        for (int32_t k = e0 + lane_id(); k < e1; k += WAVE) s = Acc<true>::mac(s, val[k], x[col[k]]);
+        s = group_sum(s, WAVE);
+        if (lane_id() == 0) write_y(y, row, s, alpha, beta);
+    } else {
+        typename Acc<F64>::T s = 0;
+        for (int32_t k = e0 + lane_id(); k < e1; k += WAVE) s = Acc<F64>::mac(s, val[k], x[col[k]]);
+        s = group_sum(s, WAVE);
+        if (lane_id() == 0) write_y(y, row, (double)s, alpha, beta);
+    }
+}
+
+// Multi-vector CRS: the same row blocks; G lanes per row, each lane keeps KB
+// column accumulators so a row's entries are read once per KB columns of X.
+template <int KB, typename VT, typename XT>
+__global__ __launch_bounds__(CRS_THREADS) void spmm_crs_kernel(const int32_t *__restrict__ row_ptr,
+                                                               const int32_t *__restrict__ col,
+                                                               const VT *__restrict__ val, const XT *__restrict__ X,
+                                                               int64_t ldx, XT *__restrict__ Y, int64_t ldy, int32_t k,
+                                                               const int32_t *__restrict__ plan, double alpha,
+                                                               double beta)
+{
+    constexpr bool F64 = IsF64<VT>::value;
+    __shared__ double red[CRS_THREADS / WAVE][KB];
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int c0 = blockIdx.y * KB;
+    const int kb = k - c0 < KB ? k - c0 : KB;
+    const int32_t r0 = plan[b], r1 = plan[b + 1];
+    const int32_t nr = r1 - r0;
+    const XT *__restrict__ Xc = X + (int64_t)c0 * ldx;
+    XT *__restrict__ Yc = Y + (int64_t)c0 * ldy;
+    if (nr == 1) {
+        const int32_t e0 = row_ptr[r0], e1 = row_ptr[r1];
+        const bool wide = !F64 && e1 - e0 > SPMV_WIDE_ROW_NNZ;
+        double acc[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+        if (F64 || wide) {
+            for (int32_t e = e0 + (int32_t)threadIdx.x; e < e1; e += CRS_THREADS) {
+                const int32_t c = ld_stream(col + e);
+                const VT v = ld_stream(val + e);
+#pragma unroll
+                for (int j = 0; j < KB; ++j)
+                    if (j < kb) acc[j] = Acc<true>::mac(acc[j], v, Xc[c + (int64_t)j * ldx]);
+            }
+#pragma unroll
+            for (int j = 0; j < KB; ++j) acc[j] = group_sum(acc[j], WAVE);
+        } else {
+            float accf[KB];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) accf[j] = 0.0f;
+            for (int32_t e = e0 + (int32_t)threadIdx.x; e < e1; e += CRS_THREADS) {
+                const int32_t c = ld_stream(col + e);
+                const VT v = ld_stream(val + e);
+#pragma unroll
+                for (int j = 0; j < KB; ++j)
+                    if (j < kb) accf[j] = Acc<false>::mac(accf[j], v, Xc[c + (int64_t)j * ldx]);
+            }
+#pragma unroll
+            for (int j = 0; j < KB; ++j) acc[j] = (double)group_sum(accf[j], WAVE);
+        }
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int j = 0; j < KB; ++j) red[threadIdx.x / WAVE][j] = acc[j];
+        }
+        __syncthreads();
+        if (threadIdx.x < (unsigned)kb) {
+            const int j = (int)threadIdx.x;
+            if (F64 || wide) {
+                double t = red[0][j];
+                for (int w = 1; w < CRS_THREADS / WAVE; ++w) t += red[w][j];
+                write_y(Yc + (int64_t)j * ldy, r0, t, alpha, beta);
+            } else {
+                float t = (float)red[0][j];
+                for (int w = 1; w < CRS_THREADS / WAVE; ++w) t += (float)red[w][j];
+                write_y(Yc + (int64_t)j * ldy, r0, (double)t, alpha, beta);
+            }
+        }
+        return;
+    }
+    typedef typename Acc<F64>::T acc_t;
+    int G = 64;
+    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
+    const int g = (int)threadIdx.x / G, l = (int)threadIdx.x % G;
+    acc_t acc[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = 0;
+    if (g < nr) {
+        const int32_t rs = row_ptr[r0 + g], re = row_ptr[r0 + g + 1];
+        for (int32_t e = rs + l; e < re; e += G) {
+            const int32_t c = ld_stream(col + e);
+            const VT v = ld_stream(val + e);
+#pragma unroll
+            for (int j = 0; j < KB; ++j)
+                if (j < kb) acc[j] = Acc<F64>::mac(acc[j], v, Xc[c + (int64_t)j * ldx]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = group_sum(acc[j], G);
+    if (g < nr && l == 0) {
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            if (j < kb) write_y(Yc + (int64_t)j * ldy, (int64_t)r0 + g, (double)acc[j], alpha, beta);
+    }
+}
+
+template <typename VT, typename XT>
+static spmv_status launch_spmm_crs(const int32_t *row_ptr, const int32_t *col, const void *val, int32_t k,
+                                   const void *X, int64_t ldx, void *Y, int64_t ldy, double alpha, double beta,
+                                   const int32_t *plan, int32_t n_blocks, hipStream_t s)
+{
+    constexpr int KB = 8;
+    dim3 grid((unsigned)n_blocks, (unsigned)ceil_div(k, KB));
+    spmm_crs_kernel<KB, VT, XT><<<grid, CRS_THREADS, 0, s>>>(row_ptr, col, (const VT *)val, (const XT *)X, ldx,
+                                                            (XT *)Y, ldy, k, plan, alpha, beta);
+    SPMV_CHECK_LAUNCH("spmm_crs");
+    return SPMV_OK;
+}
+
+template <typename VT, typename XT>
+static spmv_status launch_crs(int32_t n_rows, const int32_t *row_ptr, const int32_t *col, const void *val,
+                              const void *x, void *y, double alpha, double beta, const int32_t *plan,
+                              int32_t n_blocks, int32_t block_nnz, hipStream_t s)
+{
+    if (plan) {
+        if (n_blocks == 0) return SPMV_OK;
+        size_t lds = (size_t)block_nnz * (IsF64<VT>::value ? 8 : 4);
+        crs_block_kernel<VT, XT><<<n_blocks, CRS_THREADS, lds, s>>>(row_ptr, col, (const VT *)val, (const XT *)x,
+                                                                   (XT *)y, plan, alpha, beta);
+    } else {
+        int64_t grid = ceil_div(n_rows, CRS_THREADS / WAVE);
+        crs_wave_kernel<VT, XT><<<(unsigned)grid, CRS_THREADS, 0, s>>>(n_rows, row_ptr, col, (const VT *)val,
+                                                                       (const XT *)x, (XT *)y, alpha, beta);
+    }
+    SPMV_CHECK_LAUNCH("spmv_crs");
+    return SPMV_OK;
+}
+
+int32_t crs_default_block_nnz() { return CRS_DEFAULT_BLOCK_NNZ; }
+
+// Greedy host planner shared by spmv_crs_plan and the multi-vector planner.
+void crs_plan_rows(int32_t n_rows, const int32_t *rp, int32_t T, std::vector<int32_t> &out)
+{
+    out.clear();
+    out.push_back(0);
+    int32_t start = 0;
+    int64_t cur = 0;
+    for (int32_t r = 0; r < n_rows; ++r) {
+        int64_t len = (int64_t)rp[r + 1] - rp[r];
+        int32_t nr = r - start;
+        if (nr > 0 && (cur + len > T || nr >= CRS_MAX_BLOCK_ROWS)) {
+            out.push_back(r);
+            start = r;
+            cur = 0;
+        }
+        if (len > T) {                 // a long row is a block of its own
+            out.push_back(r + 1);
+            start = r + 1;
+            cur = 0;
+            continue;
+        }
+        cur += len;
+    }
+    if (start < n_rows) out.push_back(n_rows);
+}
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" {
+
+spmv_status spmv_crs_plan(int32_t n_rows, const int32_t *row_ptr, int32_t block_nnz, int32_t *plan,
+                          int32_t plan_cap, int32_t *h_n_blocks, void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0, "spmv_crs_plan: n_rows < 0");
+    SPMV_REQUIRE(h_n_blocks, "spmv_crs_plan: null h_n_blocks");
+    SPMV_REQUIRE(row_ptr, "spmv_crs_plan: null row_ptr");
+    if (block_nnz == 0) block_nnz = CRS_DEFAULT_BLOCK_NNZ;
+    SPMV_REQUIRE(block_nnz >= CRS_THREADS && block_nnz <= CRS_MAX_BLOCK_NNZ,
+                 "spmv_crs_plan: block_nnz must be in [256, 4096]");
+    hipStream_t s = as_stream(stream);
+    std::vector<int32_t> rp((size_t)n_rows + 1);
+    SPMV_HIP(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    for (int32_t r = 0; r < n_rows; ++r)
+        if (rp[r + 1] < rp[r]) return fail(SPMV_ERR_BAD_FORMAT, "spmv_crs_plan: row_ptr decreases");
+    std::vector<int32_t> blocks;
+    crs_plan_rows(n_rows, rp.data(), block_nnz, blocks);
+    int32_t nb = (int32_t)blocks.size() - 1;
+    *h_n_blocks = nb;
+    if (!plan || plan_cap < nb + 1) return fail(SPMV_ERR_CAPACITY, "spmv_crs_plan: plan capacity < n_blocks+1");
+    SPMV_HIP(hipMemcpyAsync(plan, blocks.data(), sizeof(int32_t) * blocks.size(), hipMemcpyHostToDevice, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
+                     const void *val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
+                     double beta, const int32_t *plan, int32_t n_blocks, int32_t block_nnz, void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0, "spmv_crs: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_crs: bad dtype");
+    if (n_rows == 0) return SPMV_OK;
+    SPMV_REQUIRE(row_ptr && y, "spmv_crs: null row_ptr or y");
+    SPMV_REQUIRE(n_cols == 0 || (col_idx && val && x), "spmv_crs: null col_idx, val or x");
+    if (plan) {
+        SPMV_REQUIRE(n_blocks >= 0, "spmv_crs: n_blocks < 0");
+        if (block_nnz == 0) block_nnz = CRS_DEFAULT_BLOCK_NNZ;
+        SPMV_REQUIRE(block_nnz >= CRS_THREADS && block_nnz <= CRS_MAX_BLOCK_NNZ,
+                     "spmv_crs: block_nnz must be in [256, 4096]");
+    }
+    hipStream_t s = as_stream(stream);
+#define CRS_CASE(VDT, VT, XDT, XT)                                                                          \
+    if (val_dt == VDT && vec_dt == XDT)                                                                     \
+        return launch_crs<VT, XT>(n_rows, row_ptr, col_idx, val, x, y, alpha, beta, plan, n_blocks, block_nnz, s);
+    CRS_CASE(SPMV_F64, double, SPMV_F64, double)
+    CRS_CASE(SPMV_F32, float, SPMV_F64, double)
+    CRS_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    CRS_CASE(SPMV_F32, float, SPMV_F32, float)
+    CRS_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    CRS_CASE(SPMV_F64, double, SPMV_F32, float)
+#undef CRS_CASE
+    return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs: dtype combination");
+}
+
+spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                     spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                     spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan, int32_t n_blocks,
+                     int32_t block_nnz, void *stream)
+{
+    (void)block_nnz;
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && k >= 0, "spmm_crs: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmm_crs: bad dtype");
+    if (n_rows == 0 || k == 0) return SPMV_OK;
+    SPMV_REQUIRE(plan && n_blocks >= 0, "spmm_crs: needs a plan from spmv_crs_plan");
+    SPMV_REQUIRE(ldx >= n_cols && ldy >= n_rows, "spmm_crs: leading dimension too small");
+    SPMV_REQUIRE(row_ptr && Y, "spmm_crs: null row_ptr or Y");
+    SPMV_REQUIRE(n_cols == 0 || (col_idx && val && X), "spmm_crs: null col_idx, val or X");
+    if (n_blocks == 0) return SPMV_OK;
+    hipStream_t s = as_stream(stream);
+#define SPMM_CASE(VDT, VT, XDT, XT)           \
+    if (val_dt == VDT && vec_dt == XDT)       \
+        return launch_spmm_crs<VT, XT>(row_ptr, col_idx, val, k, X, ldx, Y, ldy, alpha, beta, plan, n_blocks, s);
+    SPMM_CASE(SPMV_F64, double, SPMV_F64, double)
+    SPMM_CASE(SPMV_F32, float, SPMV_F32, float)
+    SPMM_CASE(SPMV_F32, float, SPMV_F64, double)
+    SPMM_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    SPMM_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    SPMM_CASE(SPMV_F64, double, SPMV_F32, float)
+#undef SPMM_CASE
+    return fail(SPMV_ERR_UNSUPPORTED, "spmm_crs: dtype combination");
+}
+
+}  // extern "C"

@@ -1,0 +1,588 @@
+// JDS and blocked-JDS sparse matrix-vector products (paper Section 2: the JDS
+// kernel and its NBJDS / NUJDS / RBJDS refinements), plus the multi-vector form
+// and the value gradient in JDS order.
+//
+// gfx950 design.  Rows are in the JDS permuted order, longest first.  A
+// wavefront owns R consecutive permuted rows (R = 64: one row per lane); its
+// lanes walk the jagged diagonals that reach their rows, U diagonals per trip
+// (the NUJDS idea: more independent loads in flight per row).  Consecutive
+// lanes read consecutive entries of one diagonal, so val/col loads are fully
+// coalesced; the row's partial result stays in a register for all diagonals
+// (NBJDS with the block held in registers: no result-vector traffic per
+// diagonal).  Long rows would serialise one lane over thousands of diagonals,
+// so the host splits the rows into classes by length: a class has R rows per
+// wavefront (64/R lanes share a row and stride over its diagonals) and S
+// wavefronts per row group (each takes a contiguous range of diagonals; the S
+// partial sums meet in LDS and are added in a fixed order).  Every y element is
+// written by one lane; no atomics.
+//
+// The same kernel runs on both storages:
+//   JDS:     entry (d, r) at jd_ptr[d] + r, diagonal d reaches rows r < len_d
+//   blocked: entry (d, r) at slice_ptr[s] + d*C + (r - s*C), s = r / C, padded
+//            slots (col = -1) skipped.
+#include <vector>
+
+#include "common.hpp"
+
+namespace spmv {
+
+constexpr int JDS_WAVES = 16;                 // wavefronts per workgroup
+constexpr int JDS_THREADS = JDS_WAVES * WAVE;
+constexpr int JDS_MAX_CLASSES = 8;
+constexpr int JDS_DEFAULT_MAX_ITERS = 32;
+
+struct JdsClass {
+    int32_t wg_end;     // cumulative workgroup count up to and including this class
+    int32_t row_start;  // permuted rows [row_start, row_end)
+    int32_t row_end;
+    int32_t rlog;       // R = 1 << rlog rows per wavefront
+    int32_t slog;       // S = 1 << slog wavefronts per row group
+};
+
+struct JdsPlan {
+    JdsClass c[JDS_MAX_CLASSES];
+    int32_t ncls;
+};
+
+struct JdsArgs {
+    int32_t n;
+    const int32_t *perm;
+    const int32_t *jd_ptr;  // JDS storage
+    int32_t ndiag;
+    int32_t C;              // blocked storage
+    const int64_t *slice_ptr;
+    const int32_t *slice_nd;
+    const int32_t *col;
+    const void *val;
+    const void *x;
+    void *y;
+    int64_t ldx, ldy;       // multi-vector forms
+    int32_t k;
+    double alpha, beta;
+    int symperm;
+};
+
+enum { FMT_JDS = 0, FMT_BLOCKED = 1 };
+
+// Number of diagonals of permuted row `row` in JDS storage: the first d whose
+// diagonal is too short to reach the row (diagonal lengths never increase).
+__device__ __forceinline__ int32_t jds_row_len(const int32_t *__restrict__ jp, int32_t ndiag, int32_t row)
+{
+    int32_t lo = 0, hi = ndiag;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (jp[mid + 1] - jp[mid] > row) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Partial sum of one lane over its diagonals in [dA, dB): d = base + kk + G*u.
+// `bounded` false: stop as soon as the group's first row has no diagonal
+// (used by unsplit groups, which then never search for their length).
+template <int FMT, int U, bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ typename Acc<WIDE>::T jds_lane_sum(const JdsArgs &a, int32_t row0, int32_t r,
+                                                              bool row_ok, int kk, int G, int32_t dA,
+                                                              int32_t dB, bool bounded, int64_t xoff)
+{
+    typedef typename Acc<WIDE>::T acc_t;
+    const VT *__restrict__ val = (const VT *)a.val;
+    const XT *__restrict__ x = (const XT *)a.x + xoff;
+    const int32_t *__restrict__ col = a.col;
+    acc_t s = 0;
+    if (FMT == FMT_JDS) {
+        const int32_t *__restrict__ jp = a.jd_ptr;
+        for (int32_t base = dA; base < dB; base += G * U) {
+            if (!bounded && jp[base + 1] - jp[base] <= row0) break;
+            int32_t c[U];
+            VT v[U];
+            bool act[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t dd = base + kk + u * G;
+                act[u] = false;
+                if (row_ok && dd < dB) {
+                    const int32_t off = jp[dd];
+                    if (r < jp[dd + 1] - off) {
+                        act[u] = true;
+                        c[u] = ld_stream(col + off + r);
+                        v[u] = ld_stream(val + off + r);
+                    }
+                }
+            }
+            XT xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (act[u]) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (act[u]) s = Acc<WIDE>::mac(s, v[u], xv[u]);
+        }
+    } else {
+        const int32_t sl = row0 / a.C;
+        const int64_t sp = a.slice_ptr[sl];
+        const int32_t nd = a.slice_nd[sl];
+        const int32_t rs = r - sl * a.C;
+        if (dB > nd) dB = nd;
+        for (int32_t base = dA; base < dB; base += G * U) {
+            int32_t c[U];
+            VT v[U];
+            bool act[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t dd = base + kk + u * G;
+                act[u] = false;
+                if (row_ok && dd < dB) {
+                    const int64_t e = sp + (int64_t)dd * a.C + rs;
+                    c[u] = ld_stream(col + e);
+                    v[u] = ld_stream(val + e);
+                    act[u] = c[u] >= 0;
+                }
+            }
+            XT xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (act[u]) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (act[u]) s = Acc<WIDE>::mac(s, v[u], xv[u]);
+        }
+    }
+    return s;
+}
+
+// Lanes rl + R*kk (kk < G) hold partials of one row: fixed xor tree over kk.
+template <typename T>
+__device__ __forceinline__ T reduce_over_kk(T v, int rlog)
+{
+    for (int off = 32; off >= (1 << rlog); off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+template <int FMT, int U, typename VT, typename XT>
+__global__ __launch_bounds__(JDS_THREADS) void jds_kernel(JdsArgs a, JdsPlan P)
+{
+    __shared__ double part[JDS_WAVES][WAVE];
+    constexpr bool F64 = IsF64<VT>::value;
+
+    // No XCD remap here: the long-row classes come first and the hardware's
+    // round-robin spreads them over all XCDs.
+    const int64_t wg = blockIdx.x;
+    int ci = 0;
+    while (ci < P.ncls - 1 && wg >= P.c[ci].wg_end) ++ci;
+    const JdsClass K = P.c[ci];
+    const int64_t wg0 = ci ? P.c[ci - 1].wg_end : 0;
+    const int w = (int)threadIdx.x / WAVE, lane = lane_id();
+    const int S = 1 << K.slog, R = 1 << K.rlog, G = WAVE >> K.rlog;
+    const int64_t slot = (wg - wg0) * JDS_WAVES + w;
+    const int64_t grp = slot >> K.slog;
+    const int p = (int)(slot & (S - 1));
+    const int64_t row0l = (int64_t)K.row_start + grp * R;
+    const bool valid = row0l < K.row_end;
+    const int32_t row0 = valid ? (int32_t)row0l : K.row_start;
+    const int rl = lane & (R - 1), kk = lane >> K.rlog;
+    const int32_t r = row0 + rl;
+    const bool row_ok = valid && r < K.row_end;
+
+    // length of the group's first (longest) row: only split groups need it
+    int32_t Lmax = 0;
+    bool wide = false;
+    if (valid) {
+        if (FMT == FMT_JDS) {
+            if (S > 1) Lmax = jds_row_len(a.jd_ptr, a.ndiag, row0);
+            if (!F64) wide = a.ndiag > SPMV_WIDE_ROW_NNZ &&
+                             a.jd_ptr[SPMV_WIDE_ROW_NNZ + 1] - a.jd_ptr[SPMV_WIDE_ROW_NNZ] > row0;
+        } else {
+            Lmax = a.slice_nd[row0 / a.C];
+            if (!F64) wide = Lmax > SPMV_WIDE_ROW_NNZ;
+        }
+    }
+    int32_t dA = 0, dB = (FMT == FMT_JDS) ? a.ndiag : Lmax;
+    if (S > 1) {
+        const int32_t per = (int32_t)((((int64_t)Lmax + (int64_t)S * G - 1) / ((int64_t)S * G)) * G);
+        dA = p * per;
+        dB = dA + per < Lmax ? dA + per : Lmax;
+        if (dA > dB) dA = dB;
+    }
+    const bool bounded = (FMT == FMT_BLOCKED) || S > 1;
+
+    double td = 0.0;
+    if (valid) {
+        if (F64 || wide) {
+            double s = jds_lane_sum<FMT, U, true, VT, XT>(a, row0, r, row_ok, kk, G, dA, dB, bounded, 0);
+            td = reduce_over_kk(s, K.rlog);
+        } else {
+            float s = jds_lane_sum<FMT, U, false, VT, XT>(a, row0, r, row_ok, kk, G, dA, dB, bounded, 0);
+            td = (double)reduce_over_kk(s, K.rlog);
+        }
+    }
+    if (S > 1) {
+        if (kk == 0) part[w][rl] = td;
+        __syncthreads();
+        if (p != 0) return;
+        if (F64 || wide) {
+            double t = 0.0;
+            for (int q = 0; q < S; ++q) t += part[w + q][rl];
+            td = t;
+        } else {
+            float t = 0.0f;
+            for (int q = 0; q < S; ++q) t += (float)part[w + q][rl];
+            td = (double)t;
+        }
+    }
+    if (row_ok && kk == 0) {
+        const int32_t yi = a.symperm ? r : a.perm[r];
+        write_y((XT *)a.y, yi, td, a.alpha, a.beta);
+    }
+}
+
+// Multi-vector JDS: each lane owns one row (R = 64) and keeps k accumulators;
+// the row's entries are read once for all k columns of X.
+template <int KB, typename VT, typename XT>
+__global__ __launch_bounds__(256) void spmm_jds_kernel(JdsArgs a)
+{
+    constexpr bool F64 = IsF64<VT>::value;
+    typedef typename Acc<F64>::T acc_t;
+    const int64_t r64 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int col0 = blockIdx.y * KB;
+    const int kb = a.k - col0 < KB ? a.k - col0 : KB;
+    if (r64 >= a.n) return;
+    const int32_t r = (int32_t)r64;
+    const int32_t row0 = (int32_t)(r64 & ~(int64_t)(WAVE - 1));
+    const int32_t *__restrict__ jp = a.jd_ptr;
+    const VT *__restrict__ val = (const VT *)a.val;
+    const XT *__restrict__ X = (const XT *)a.x + (int64_t)col0 * a.ldx;
+    acc_t acc[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = 0;
+    for (int32_t d = 0; d < a.ndiag; ++d) {
+        const int32_t off = jp[d], len = jp[d + 1] - off;
+        if (len <= row0) break;
+        if (r < len) {
+            const int32_t c = ld_stream(a.col + off + r);
+            const VT v = ld_stream(val + off + r);
+#pragma unroll
+            for (int j = 0; j < KB; ++j)
+                if (j < kb) acc[j] = Acc<F64>::mac(acc[j], v, X[c + (int64_t)j * a.ldx]);
+        }
+    }
+    const int32_t yi = a.symperm ? r : a.perm[r];
+    XT *Y = (XT *)a.y + (int64_t)col0 * a.ldy;
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+        if (j < kb) write_y(Y + (int64_t)j * a.ldy, yi, (double)acc[j], a.alpha, a.beta);
+}
+
+// Value gradient in JDS storage order: dval[e] = alpha*g[row]*x[col[e]] + beta*dval[e].
+constexpr int GRAD_THREADS = 256;
+constexpr int GRAD_PER_THREAD = 8;
+
+template <typename T>
+__global__ __launch_bounds__(GRAD_THREADS) void grad_vals_jds_kernel(int64_t nnz, int32_t ndiag,
+                                                                     const int32_t *__restrict__ jp,
+                                                                     const int32_t *__restrict__ perm,
+                                                                     const int32_t *__restrict__ col,
+                                                                     const T *__restrict__ g,
+                                                                     const T *__restrict__ x, T *__restrict__ dval,
+                                                                     double alpha, double beta, int symperm)
+{
+    const int64_t tile = (int64_t)blockIdx.x * GRAD_THREADS * GRAD_PER_THREAD;
+    // diagonal holding the tile's first entry (uniform binary search)
+    int32_t lo = 0, hi = ndiag - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (jp[mid] <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    int32_t d = lo;
+    for (int t = 0; t < GRAD_PER_THREAD; ++t) {
+        const int64_t e = tile + (int64_t)t * GRAD_THREADS + threadIdx.x;
+        if (e >= nnz) break;
+        while (jp[d + 1] <= e) ++d;
+        const int32_t r = (int32_t)(e - jp[d]);
+        const int32_t row = symperm ? r : perm[r];
+        double v = alpha * (to_f64(g[row]) * to_f64(x[col[e]]));
+        if (beta != 0.0) v = fma(beta, to_f64(dval[e]), v);
+        store_from_f64(&dval[e], v);
+    }
+}
+
+// ---------------------------------------------------------------- host planning
+
+// W wavefronts per 64-row chunk, split into (R rows per wave, S waves per group).
+static void split_for(int W, int forced_rlog, int &rlog, int &slog)
+{
+    if (forced_rlog >= 0) {
+        int G = 1 << (6 - forced_rlog);
+        int S = W / G;
+        if (S < 1) S = 1;
+        if (S > JDS_WAVES) S = JDS_WAVES;
+        rlog = forced_rlog;
+        slog = 0;
+        while ((1 << slog) < S) ++slog;
+        return;
+    }
+    switch (W) {
+    case 1: rlog = 6; slog = 0; break;
+    case 2: rlog = 5; slog = 0; break;
+    case 4: rlog = 4; slog = 0; break;
+    case 8: rlog = 4; slog = 1; break;
+    case 16: rlog = 4; slog = 2; break;
+    case 32: rlog = 4; slog = 3; break;
+    case 64: rlog = 4; slog = 4; break;
+    default: rlog = 3; slog = 4; break;   // 128
+    }
+}
+
+// chunk_len(i) = length of the first row of 64-row chunk i (non-increasing).
+template <typename F>
+static JdsPlan build_plan(int32_t n, int32_t max_iters, int forced_rlog, F chunk_len)
+{
+    JdsPlan P{};
+    int64_t nchunks = ceil_div(n, 64);
+    int cls = 0;
+    int64_t wg_total = 0;
+    int64_t i = 0;
+    while (i < nchunks && cls < JDS_MAX_CLASSES) {
+        int64_t L = chunk_len(i);
+        int W = 1;
+        while (W < 128 && (int64_t)W * max_iters < L) W <<= 1;
+        int rlog, slog;
+        split_for(W, forced_rlog, rlog, slog);
+        // extend the class while the chunks want the same split
+        int64_t j = i + 1;
+        if (cls == JDS_MAX_CLASSES - 1) {
+            j = nchunks;
+        } else {
+            // binary search the last chunk with the same W (lengths never increase)
+            int64_t lo = i + 1, hi = nchunks;
+            int64_t lower = (W > 1) ? (int64_t)(W / 2) * max_iters : -1;   // L > lower keeps W
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (chunk_len(mid) > lower) lo = mid + 1;
+                else hi = mid;
+            }
+            j = lo;
+        }
+        JdsClass &K = P.c[cls];
+        K.row_start = (int32_t)(i * 64);
+        K.row_end = (int32_t)(j * 64 < n ? j * 64 : n);
+        K.rlog = rlog;
+        K.slog = slog;
+        int64_t groups = ceil_div(K.row_end - K.row_start, (int64_t)1 << rlog);
+        wg_total += ceil_div(groups << slog, JDS_WAVES);
+        K.wg_end = (int32_t)wg_total;
+        ++cls;
+        i = j;
+    }
+    P.ncls = cls;
+    return P;
+}
+
+static JdsPlan plan_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int32_t max_iters, int forced_rlog)
+{
+    // rows longer than d are the first (jd_ptr[d+1]-jd_ptr[d]) permuted rows
+    auto chunk_len = [&](int64_t i) -> int64_t {
+        int64_t row = i * 64;
+        int32_t lo = 0, hi = ndiag;
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (h_jd_ptr[mid + 1] - h_jd_ptr[mid] > row) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    return build_plan(n, max_iters, forced_rlog, chunk_len);
+}
+
+static JdsPlan plan_blocked(int32_t n, int32_t C, const int32_t *h_slice_nd, int32_t max_iters, int forced_rlog)
+{
+    auto chunk_len = [&](int64_t i) -> int64_t { return h_slice_nd[(i * 64) / C]; };
+    return build_plan(n, max_iters, forced_rlog, chunk_len);
+}
+
+template <int FMT, typename VT, typename XT>
+static spmv_status launch_jds_t(const JdsArgs &a, const JdsPlan &P, int unroll, hipStream_t s)
+{
+    if (P.ncls == 0) return SPMV_OK;
+    unsigned grid = (unsigned)P.c[P.ncls - 1].wg_end;
+    if (grid == 0) return SPMV_OK;
+    switch (unroll) {
+    case 2: jds_kernel<FMT, 2, VT, XT><<<grid, JDS_THREADS, 0, s>>>(a, P); break;
+    case 8: jds_kernel<FMT, 8, VT, XT><<<grid, JDS_THREADS, 0, s>>>(a, P); break;
+    default: jds_kernel<FMT, 4, VT, XT><<<grid, JDS_THREADS, 0, s>>>(a, P); break;
+    }
+    SPMV_CHECK_LAUNCH(FMT == FMT_JDS ? "spmv_jds" : "spmv_jds_blocked");
+    return SPMV_OK;
+}
+
+template <int FMT>
+static spmv_status launch_jds(const JdsArgs &a, const JdsPlan &P, int unroll, spmv_dtype vdt, spmv_dtype xdt,
+                              hipStream_t s)
+{
+#define JDS_CASE(VDT, VT, XDT, XT) \
+    if (vdt == VDT && xdt == XDT) return launch_jds_t<FMT, VT, XT>(a, P, unroll, s);
+    JDS_CASE(SPMV_F64, double, SPMV_F64, double)
+    JDS_CASE(SPMV_F32, float, SPMV_F64, double)
+    JDS_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    JDS_CASE(SPMV_F32, float, SPMV_F32, float)
+    JDS_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    JDS_CASE(SPMV_F64, double, SPMV_F32, float)
+#undef JDS_CASE
+    return fail(SPMV_ERR_UNSUPPORTED, "jds: dtype combination");
+}
+
+static int unroll_ok(int32_t u) { return u == 0 || u == 2 || u == 4 || u == 8; }
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" {
+
+spmv_status spmv_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr, int32_t ndiag,
+                     const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt, const void *x, void *y,
+                     spmv_dtype vec_dt, double alpha, double beta, int32_t unroll, int32_t max_iters,
+                     unsigned flags, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && ndiag >= 0, "spmv_jds: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds: bad dtype");
+    SPMV_REQUIRE(unroll_ok(unroll), "spmv_jds: unroll must be 0, 2, 4 or 8");
+    SPMV_REQUIRE(max_iters >= 0, "spmv_jds: max_iters < 0");
+    SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_jds: unknown flag");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(y && jd_ptr && h_jd_ptr, "spmv_jds: null y, jd_ptr or h_jd_ptr");
+    SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmv_jds: null perm");
+    SPMV_REQUIRE(ndiag == 0 || (jd_col && jd_val && x), "spmv_jds: null col, val or x");
+    SPMV_REQUIRE(ndiag == 0 || h_jd_ptr[0] == 0, "spmv_jds: h_jd_ptr[0] != 0");
+    JdsArgs a{};
+    a.n = n;
+    a.perm = perm;
+    a.jd_ptr = jd_ptr;
+    a.ndiag = ndiag;
+    a.C = 64;
+    a.col = jd_col;
+    a.val = jd_val;
+    a.x = x;
+    a.y = y;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
+    JdsPlan P = plan_jds(n, h_jd_ptr, ndiag, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1);
+    return launch_jds<FMT_JDS>(a, P, unroll ? unroll : 4, val_dt, vec_dt, as_stream(stream));
+}
+
+spmv_status spmv_jds_blocked(int32_t n, const int32_t *perm, int32_t C, int32_t n_slices, const int64_t *slice_ptr,
+                             const int32_t *slice_nd, const int32_t *h_slice_nd, const int32_t *bl_col,
+                             const void *bl_val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
+                             double alpha, double beta, int32_t rows_per_wave, int32_t unroll, int32_t max_iters,
+                             unsigned flags, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_jds_blocked: n < 0");
+    SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked: C must be a positive multiple of 64");
+    SPMV_REQUIRE(n_slices == (int32_t)ceil_div(n, C), "spmv_jds_blocked: n_slices != ceil(n / C)");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_blocked: bad dtype");
+    SPMV_REQUIRE(unroll_ok(unroll), "spmv_jds_blocked: unroll must be 0, 2, 4 or 8");
+    SPMV_REQUIRE(rows_per_wave == 0 || rows_per_wave == 8 || rows_per_wave == 16 || rows_per_wave == 32 ||
+                     rows_per_wave == 64,
+                 "spmv_jds_blocked: rows_per_wave must be 0, 8, 16, 32 or 64");
+    SPMV_REQUIRE(max_iters >= 0, "spmv_jds_blocked: max_iters < 0");
+    SPMV_REQUIRE((flags & ~(SPMV_SYMPERM | SPMV_SOJDS)) == 0, "spmv_jds_blocked: unknown flag");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(y && slice_ptr && slice_nd && h_slice_nd, "spmv_jds_blocked: null pointer");
+    SPMV_REQUIRE(h_slice_nd[0] == 0 || (bl_col && bl_val && x), "spmv_jds_blocked: null col, val or x");
+    SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmv_jds_blocked: null perm");
+    JdsArgs a{};
+    a.n = n;
+    a.perm = perm;
+    a.C = C;
+    a.slice_ptr = slice_ptr;
+    a.slice_nd = slice_nd;
+    a.col = bl_col;
+    a.val = bl_val;
+    a.x = x;
+    a.y = y;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
+    int forced = -1;
+    if (rows_per_wave) {
+        forced = 0;
+        while ((1 << forced) < rows_per_wave) ++forced;
+    }
+    JdsPlan P = plan_blocked(n, C, h_slice_nd, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced);
+    return launch_jds<FMT_BLOCKED>(a, P, unroll ? unroll : 4, val_dt, vec_dt, as_stream(stream));
+}
+
+spmv_status spmm_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr, int32_t ndiag,
+                     const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt, int32_t k, const void *X,
+                     int64_t ldx, void *Y, int64_t ldy, spmv_dtype vec_dt, double alpha, double beta,
+                     unsigned flags, void *stream)
+{
+    (void)h_jd_ptr;
+    SPMV_REQUIRE(n >= 0 && ndiag >= 0 && k >= 0, "spmm_jds: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmm_jds: bad dtype");
+    SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmm_jds: unknown flag");
+    if (n == 0 || k == 0) return SPMV_OK;
+    SPMV_REQUIRE(ldy >= n, "spmm_jds: ldy < n");
+    SPMV_REQUIRE(Y && jd_ptr, "spmm_jds: null Y or jd_ptr");
+    SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmm_jds: null perm");
+    SPMV_REQUIRE(ndiag == 0 || (jd_col && jd_val && X), "spmm_jds: null input");
+    JdsArgs a{};
+    a.n = n;
+    a.perm = perm;
+    a.jd_ptr = jd_ptr;
+    a.ndiag = ndiag;
+    a.col = jd_col;
+    a.val = jd_val;
+    a.x = X;
+    a.y = Y;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.k = k;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
+    constexpr int KB = 8;
+    dim3 grid((unsigned)ceil_div(n, 256), (unsigned)ceil_div(k, KB));
+    hipStream_t s = as_stream(stream);
+#define SPMM_CASE(VDT, VT, XDT, XT)                                           \
+    if (val_dt == VDT && vec_dt == XDT) {                                     \
+        spmm_jds_kernel<KB, VT, XT><<<grid, 256, 0, s>>>(a);                  \
+        SPMV_CHECK_LAUNCH("spmm_jds");                                        \
+        return SPMV_OK;                                                       \
+    }
+    SPMM_CASE(SPMV_F64, double, SPMV_F64, double)
+    SPMM_CASE(SPMV_F32, float, SPMV_F32, float)
+    SPMM_CASE(SPMV_F32, float, SPMV_F64, double)
+    SPMM_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    SPMM_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    SPMM_CASE(SPMV_F64, double, SPMV_F32, float)
+#undef SPMM_CASE
+    return fail(SPMV_ERR_UNSUPPORTED, "spmm_jds: dtype combination");
+}
+
+spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag, int64_t nnz,
+                               const int32_t *jd_col, const void *g, const void *x, void *dval, spmv_dtype dt,
+                               double alpha, double beta, unsigned flags, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && ndiag >= 0 && nnz >= 0, "spmv_grad_vals_jds: negative size");
+    SPMV_REQUIRE(valid_vec_dtype(dt), "spmv_grad_vals_jds: dtype must be F64 or F32");
+    SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_grad_vals_jds: unknown flag");
+    if (nnz == 0) return SPMV_OK;
+    SPMV_REQUIRE(ndiag > 0 && jd_ptr && jd_col && g && x && dval, "spmv_grad_vals_jds: null pointer");
+    SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmv_grad_vals_jds: null perm");
+    int64_t grid = ceil_div(nnz, (int64_t)GRAD_THREADS * GRAD_PER_THREAD);
+    hipStream_t s = as_stream(stream);
+    int sym = (flags & SPMV_SYMPERM) ? 1 : 0;
+    if (dt == SPMV_F64)
+        grad_vals_jds_kernel<double><<<(unsigned)grid, GRAD_THREADS, 0, s>>>(
+            nnz, ndiag, jd_ptr, perm, jd_col, (const double *)g, (const double *)x, (double *)dval, alpha, beta, sym);
+    else
+        grad_vals_jds_kernel<float><<<(unsigned)grid, GRAD_THREADS, 0, s>>>(
+            nnz, ndiag, jd_ptr, perm, jd_col, (const float *)g, (const float *)x, (float *)dval, alpha, beta, sym);
+    SPMV_CHECK_LAUNCH("spmv_grad_vals_jds");
+    return SPMV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+// Status strings, error plumbing, small vector kernels, HIP graph helpers and
+// bandwidth probes.
+#include <string>
+
+#include "common.hpp"
+
+namespace spmv {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+spmv_status fail(spmv_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+spmv_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SPMV_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <typename T>
+__global__ void axpby_kernel(int64_t n, double alpha, const T *__restrict__ x, double beta, T *__restrict__ y)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        double r = alpha * to_f64(x[i]);
+        if (beta != 0.0) r = fma(beta, to_f64(y[i]), r);
+        store_from_f64(&y[i], r);
+    }
+}
+
+// Dot product in FP64: each block reduces a fixed contiguous chunk with a
+// fixed tree, then one block adds the block partials in order.
+constexpr int DOT_THREADS = 256;
+constexpr int DOT_CHUNK = DOT_THREADS * 16;
+
+template <typename T>
+__global__ __launch_bounds__(DOT_THREADS) void dot_partial_kernel(int64_t n, const T *__restrict__ x,
+                                                                  const T *__restrict__ y,
+                                                                  double *__restrict__ part)
+{
+    __shared__ double red[DOT_THREADS / WAVE];
+    int64_t base = (int64_t)blockIdx.x * DOT_CHUNK;
+    double s = 0.0;
+    for (int k = 0; k < DOT_CHUNK / DOT_THREADS; ++k) {
+        int64_t i = base + (int64_t)k * DOT_THREADS + threadIdx.x;
+        if (i < n) s = fma(to_f64(x[i]), to_f64(y[i]), s);
+    }
+    s = group_sum(s, WAVE);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < DOT_THREADS / WAVE; ++w) t += red[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(DOT_THREADS) void dot_final_kernel(int64_t nparts, const double *__restrict__ part,
+                                                                double *__restrict__ out)
+{
+    __shared__ double red[DOT_THREADS / WAVE];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts; i += DOT_THREADS) s += part[i];
+    s = group_sum(s, WAVE);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < DOT_THREADS / WAVE; ++w) t += red[w];
+        *out = t;
+    }
+}
+
+__global__ void triad_kernel(int64_t n, const double *__restrict__ b, const double *__restrict__ c,
+                             double *__restrict__ a, double s)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) __builtin_nontemporal_store(fma(s, c[i], b[i]), a + i);
+}
+
+__global__ void copy_kernel(int64_t n, const double *__restrict__ b, double *__restrict__ a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) __builtin_nontemporal_store(b[i], a + i);
+}
+
+static int stream_grid(int64_t n, int per_thread)
+{
+    int64_t blocks = ceil_div(n, (int64_t)256 * per_thread);
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    return (int)blocks;
+}
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" {
+
+const char *spmv_status_string(spmv_status s)
+{
+    switch (s) {
+    case SPMV_OK: return "ok";
+    case SPMV_ERR_INVALID_ARG: return "invalid argument";
+    case SPMV_ERR_BAD_FORMAT: return "bad matrix format";
+    case SPMV_ERR_CAPACITY: return "output capacity too small";
+    case SPMV_ERR_UNSUPPORTED: return "unsupported";
+    case SPMV_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *spmv_last_error(void) { return g_last_error.c_str(); }
+
+const char *spmv_version(void) { return "1.0.0"; }
+
+spmv_status spmv_axpby(int64_t n, double alpha, const void *x, double beta, void *y, spmv_dtype dt, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_axpby: n < 0");
+    SPMV_REQUIRE(valid_vec_dtype(dt), "spmv_axpby: dtype must be F64 or F32");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(x && y, "spmv_axpby: null pointer");
+    int grid = stream_grid(n, 4);
+    if (dt == SPMV_F64)
+        axpby_kernel<double><<<grid, 256, 0, as_stream(stream)>>>(n, alpha, (const double *)x, beta, (double *)y);
+    else
+        axpby_kernel<float><<<grid, 256, 0, as_stream(stream)>>>(n, alpha, (const float *)x, beta, (float *)y);
+    SPMV_CHECK_LAUNCH("spmv_axpby");
+    return SPMV_OK;
+}
+
+size_t spmv_dot_workspace_size(int64_t n)
+{
+    int64_t parts = n > 0 ? ceil_div(n, DOT_CHUNK) : 1;
+    return (size_t)parts * sizeof(double);
+}
+
+spmv_status spmv_dot(int64_t n, const void *x, const void *y, spmv_dtype dt, double *out, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_dot: n < 0");
+    SPMV_REQUIRE(valid_vec_dtype(dt), "spmv_dot: dtype must be F64 or F32");
+    SPMV_REQUIRE(out, "spmv_dot: null output");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_dot_workspace_size(n), "spmv_dot: workspace too small");
+    SPMV_REQUIRE(n == 0 || (x && y), "spmv_dot: null input");
+    int64_t parts = n > 0 ? ceil_div(n, DOT_CHUNK) : 0;
+    double *part = (double *)ws;
+    hipStream_t s = as_stream(stream);
+    if (parts > 0) {
+        if (dt == SPMV_F64)
+            dot_partial_kernel<double><<<(unsigned)parts, DOT_THREADS, 0, s>>>(n, (const double *)x, (const double *)y, part);
+        else
+            dot_partial_kernel<float><<<(unsigned)parts, DOT_THREADS, 0, s>>>(n, (const float *)x, (const float *)y, part);
+        SPMV_CHECK_LAUNCH("spmv_dot partial");
+    }
+    dot_final_kernel<<<1, DOT_THREADS, 0, s>>>(parts, part, out);
+    SPMV_CHECK_LAUNCH("spmv_dot final");
+    return SPMV_OK;
+}
+
+spmv_status spmv_graph_begin(void *stream)
+{
+    SPMV_REQUIRE(stream, "spmv_graph_begin: capture needs a non-default stream");
+    SPMV_HIP(hipStreamBeginCapture(as_stream(stream), hipStreamCaptureModeThreadLocal));
+    return SPMV_OK;
+}
+
+spmv_status spmv_graph_end(void *stream, void **h_exec)
+{
+    SPMV_REQUIRE(stream && h_exec, "spmv_graph_end: null argument");
+    hipGraph_t graph = nullptr;
+    SPMV_HIP(hipStreamEndCapture(as_stream(stream), &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    *h_exec = (void *)exec;
+    return SPMV_OK;
+}
+
+spmv_status spmv_graph_launch(void *exec, void *stream)
+{
+    SPMV_REQUIRE(exec, "spmv_graph_launch: null graph");
+    SPMV_HIP(hipGraphLaunch((hipGraphExec_t)exec, as_stream(stream)));
+    return SPMV_OK;
+}
+
+spmv_status spmv_graph_destroy(void *exec)
+{
+    if (exec) SPMV_HIP(hipGraphExecDestroy((hipGraphExec_t)exec));
+    return SPMV_OK;
+}
+
+spmv_status spmv_stream_triad(int64_t n, const double *b, const double *c, double *a, double s, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && (n == 0 || (a && b && c)), "spmv_stream_triad: bad arguments");
+    if (n == 0) return SPMV_OK;
+    triad_kernel<<<stream_grid(n, 8), 256, 0, as_stream(stream)>>>(n, b, c, a, s);
+    SPMV_CHECK_LAUNCH("spmv_stream_triad");
+    return SPMV_OK;
+}
+
+spmv_status spmv_stream_copy(int64_t n, const double *b, double *a, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && (n == 0 || (a && b)), "spmv_stream_copy: bad arguments");
+    if (n == 0) return SPMV_OK;
+    copy_kernel<<<stream_grid(n, 8), 256, 0, as_stream(stream)>>>(n, b, a);
+    SPMV_CHECK_LAUNCH("spmv_stream_copy");
+    return SPMV_OK;
+}
+
+}  // extern "C"

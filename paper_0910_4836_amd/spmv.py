@@ -1,0 +1,513 @@
+"""Python binding of libspmv.so: torch tensors in, C ABI calls out.
+
+Each function has the name of the C entry point it wraps and only marshals
+arguments: device pointers of torch tensors, sizes, dtype codes and the
+current HIP stream.  Every computation runs in the library's HIP kernels.
+Workspace and output buffers are allocated here as torch tensors (the library
+itself never allocates).
+
+Matrix containers:
+  CSR      n_rows, n_cols, row_ptr, col_idx, val     (paper Section 2, CRS)
+  JDS      perm, iperm, jd_ptr (+ host copy), jd_col, jd_val   (Section 2, JDS)
+  Blocked  slice_ptr, slice_nd (+ host copy), bl_col, bl_val   (RBJDS / SOJDS)
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BF16, F32, F64, SOJDS, SYMPERM, SpmvError, call
+
+_DTYPE_CODE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+_I32 = torch.int32
+
+
+def dtype_code(t: torch.dtype) -> int:
+    try:
+        return _DTYPE_CODE[t]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t}") from None
+
+
+def _p(t: Optional[torch.Tensor]):
+    if t is None or t.data_ptr() == 0:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(device=None):
+    return torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+
+
+def _ws(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _h_i32(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _h_i64(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on the GPU")
+        if t is not None and not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def version() -> str:
+    return _lib.load().spmv_version().decode()
+
+
+# --------------------------------------------------------------------------- containers
+
+
+@dataclass
+class CSR:
+    n_rows: int
+    n_cols: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val: torch.Tensor
+    plan: Optional[torch.Tensor] = None
+    n_blocks: int = 0
+    block_nnz: int = 0
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    @property
+    def device(self):
+        return self.row_ptr.device
+
+    def with_values(self, val: torch.Tensor) -> "CSR":
+        return CSR(self.n_rows, self.n_cols, self.row_ptr, self.col_idx, val, self.plan, self.n_blocks,
+                   self.block_nnz)
+
+
+@dataclass
+class JDS:
+    n: int
+    n_cols: int
+    perm: torch.Tensor
+    iperm: torch.Tensor
+    jd_ptr: torch.Tensor
+    h_jd_ptr: np.ndarray
+    jd_col: torch.Tensor
+    jd_val: torch.Tensor
+    symperm: bool = False
+
+    @property
+    def ndiag(self) -> int:
+        return len(self.h_jd_ptr) - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.h_jd_ptr[-1])
+
+    @property
+    def flags(self) -> int:
+        return SYMPERM if self.symperm else 0
+
+    def with_values(self, val: torch.Tensor) -> "JDS":
+        return JDS(self.n, self.n_cols, self.perm, self.iperm, self.jd_ptr, self.h_jd_ptr, self.jd_col, val,
+                   self.symperm)
+
+
+@dataclass
+class Blocked:
+    n: int
+    n_cols: int
+    C: int
+    perm: torch.Tensor
+    slice_ptr: torch.Tensor
+    slice_nd: torch.Tensor
+    h_slice_nd: np.ndarray
+    bl_col: torch.Tensor
+    bl_val: torch.Tensor
+    padded: int
+    symperm: bool = False
+    sojds: bool = False
+
+    @property
+    def n_slices(self) -> int:
+        return len(self.h_slice_nd)
+
+    def with_values(self, val: torch.Tensor) -> "Blocked":
+        return Blocked(self.n, self.n_cols, self.C, self.perm, self.slice_ptr, self.slice_nd, self.h_slice_nd,
+                       self.bl_col, val, self.padded, self.symperm, self.sojds)
+
+
+# --------------------------------------------------------------------------- setup
+
+
+def csr_from_coo(n_rows: int, n_cols: int, row: torch.Tensor, col: torch.Tensor, val: torch.Tensor) -> CSR:
+    """COO -> CRS on the GPU (spmv_csr_from_coo): sorted, duplicates summed in input order."""
+    _check_dev(row, col, val)
+    dev = row.device
+    nnz = int(row.numel())
+    ws = _ws(_lib.load().spmv_csr_from_coo_workspace_size(n_rows, n_cols, nnz), dev)
+    row_ptr = torch.empty(n_rows + 1, dtype=_I32, device=dev)
+    col_out = torch.empty(max(nnz, 1), dtype=_I32, device=dev)
+    val_out = torch.empty(max(nnz, 1), dtype=val.dtype, device=dev)
+    h_nnz = C.c_int64(0)
+    call("spmv_csr_from_coo", n_rows, n_cols, nnz, _p(row), _p(col), _p(val), dtype_code(val.dtype), _p(row_ptr),
+         _p(col_out), _p(val_out), C.byref(h_nnz), _p(ws), ws.numel(), _stream())
+    k = h_nnz.value
+    return CSR(n_rows, n_cols, row_ptr, col_out[:k], val_out[:k])
+
+
+def spmv_csr_validate(A: CSR) -> bool:
+    ws = _ws(_lib.load().spmv_csr_validate_workspace_size(), A.device)
+    ok = C.c_int32(0)
+    call("spmv_csr_validate", A.n_rows, A.n_cols, A.nnz, _p(A.row_ptr), _p(A.col_idx), C.byref(ok), _p(ws),
+         ws.numel(), _stream())
+    return bool(ok.value)
+
+
+def spmv_crs_plan(A: CSR, block_nnz: int = 0) -> CSR:
+    """Builds (and stores on A) the row-block plan used by spmv_crs / spmm_crs."""
+    nb = C.c_int32(0)
+    st = _lib.load().spmv_crs_plan(A.n_rows, _p(A.row_ptr), block_nnz, None, 0, C.byref(nb), _stream())
+    if st not in (0, 3):
+        call("spmv_crs_plan", A.n_rows, _p(A.row_ptr), block_nnz, None, 0, C.byref(nb), _stream())
+    plan = torch.empty(nb.value + 1, dtype=_I32, device=A.device)
+    call("spmv_crs_plan", A.n_rows, _p(A.row_ptr), block_nnz, _p(plan), plan.numel(), C.byref(nb), _stream())
+    A.plan, A.n_blocks, A.block_nnz = plan, nb.value, block_nnz
+    return A
+
+
+def jds_from_csr(A: CSR, symperm: bool = False) -> JDS:
+    """CRS -> JDS on the GPU (spmv_jds_from_csr)."""
+    lib = _lib.load()
+    dev = A.device
+    n, nnz = A.n_rows, A.nnz
+    flags = SYMPERM if symperm else 0
+    ws = _ws(lib.spmv_jds_from_csr_workspace_size(n, nnz), dev)
+    perm = torch.empty(max(n, 1), dtype=_I32, device=dev)
+    iperm = torch.empty(max(n, 1), dtype=_I32, device=dev)
+    jd_col = torch.empty(max(nnz, 1), dtype=_I32, device=dev)
+    jd_val = torch.empty(max(nnz, 1), dtype=A.val.dtype, device=dev)
+    nd = C.c_int32(0)
+    args = lambda cap, jp, hjp: (n, nnz, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), flags,
+                                 _p(perm), _p(iperm), jp, cap, _p(jd_col), _p(jd_val), C.byref(nd), hjp, _p(ws),
+                                 ws.numel(), _stream())
+    st = lib.spmv_jds_from_csr(*args(0, None, None))
+    if st not in (0, 3):
+        call("spmv_jds_from_csr", *args(0, None, None))
+    jd_ptr = torch.empty(nd.value + 1, dtype=_I32, device=dev)
+    h_jd_ptr = np.zeros(nd.value + 1, dtype=np.int32)
+    call("spmv_jds_from_csr", *args(nd.value + 1, _p(jd_ptr), _h_i32(h_jd_ptr)))
+    return JDS(n, A.n_cols, perm[:n], iperm[:n], jd_ptr, h_jd_ptr, jd_col[:nnz], jd_val[:nnz], symperm)
+
+
+def jds_to_csr(J: JDS) -> CSR:
+    lib = _lib.load()
+    dev = J.jd_ptr.device
+    ws = _ws(lib.spmv_jds_to_csr_workspace_size(J.n), dev)
+    row_ptr = torch.empty(J.n + 1, dtype=_I32, device=dev)
+    col = torch.empty(max(J.nnz, 1), dtype=_I32, device=dev)
+    val = torch.empty(max(J.nnz, 1), dtype=J.jd_val.dtype, device=dev)
+    call("spmv_jds_to_csr", J.n, _p(J.perm), _p(J.jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val),
+         dtype_code(J.jd_val.dtype), J.flags, _p(row_ptr), _p(col), _p(val), _p(ws), ws.numel(), _stream())
+    return CSR(J.n, J.n_cols, row_ptr, col[:J.nnz], val[:J.nnz])
+
+
+def jds_blocked_from_jds(J: JDS, C_: int = 64, sojds: bool = False) -> Blocked:
+    """JDS -> blocked JDS with slices of C_ rows (spmv_jds_blocked_from_jds)."""
+    lib = _lib.load()
+    dev = J.jd_ptr.device
+    flags = SOJDS if sojds else 0
+    ns = -(-J.n // C_)
+    ws = _ws(lib.spmv_jds_blocked_workspace_size(J.n, J.ndiag, C_, flags), dev)
+    slice_ptr = torch.empty(ns + 1, dtype=torch.int64, device=dev)
+    slice_nd = torch.empty(max(ns, 1), dtype=_I32, device=dev)
+    h_slice_nd = np.zeros(max(ns, 1), dtype=np.int32)
+    padded = C.c_int64(0)
+    args = lambda cap, bc, bv: (J.n, _p(J.jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val), dtype_code(J.jd_val.dtype),
+                                C_, flags, _p(slice_ptr), _p(slice_nd), bc, bv, cap, C.byref(padded),
+                                _h_i32(h_slice_nd), _p(ws), ws.numel(), _stream())
+    st = lib.spmv_jds_blocked_from_jds(*args(0, None, None))
+    if st not in (0, 3):
+        call("spmv_jds_blocked_from_jds", *args(0, None, None))
+    tot = padded.value
+    bl_col = torch.empty(max(tot, 1), dtype=_I32, device=dev)
+    bl_val = torch.empty(max(tot, 1), dtype=J.jd_val.dtype, device=dev)
+    if tot > 0:
+        call("spmv_jds_blocked_from_jds", *args(tot, _p(bl_col), _p(bl_val)))
+    return Blocked(J.n, J.n_cols, C_, J.perm, slice_ptr, slice_nd[:ns], h_slice_nd[:ns].copy(), bl_col[:tot],
+                   bl_val[:tot], tot, J.symperm, sojds)
+
+
+def spmv_convert_values(t: torch.Tensor, dtype: torch.dtype) -> torch.Tensor:
+    """Rounds (round-to-nearest-even, one step) or widens values to ``dtype``."""
+    _check_dev(t)
+    out = torch.empty(t.shape, dtype=dtype, device=t.device)
+    call("spmv_convert_values", t.numel(), _p(t), dtype_code(t.dtype), _p(out), dtype_code(dtype), _stream())
+    return out
+
+
+def spmv_transpose_csr(A: CSR):
+    """Returns (rowT_ptr, colT, tmap): A^T's pattern, its values being A.val[tmap]."""
+    lib = _lib.load()
+    dev = A.device
+    ws = _ws(lib.spmv_transpose_workspace_size(A.n_rows, A.n_cols, A.nnz), dev)
+    rowT = torch.empty(A.n_cols + 1, dtype=_I32, device=dev)
+    colT = torch.empty(max(A.nnz, 1), dtype=_I32, device=dev)
+    tmap = torch.empty(max(A.nnz, 1), dtype=_I32, device=dev)
+    call("spmv_transpose_csr", A.n_rows, A.n_cols, A.nnz, _p(A.row_ptr), _p(A.col_idx), _p(rowT), _p(colT),
+         _p(tmap), _p(ws), ws.numel(), _stream())
+    return rowT, colT[:A.nnz], tmap[:A.nnz]
+
+
+# --------------------------------------------------------------------------- compute
+
+
+def _out_vec(y, n, like, beta):
+    if y is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs y")
+        return torch.empty(n, dtype=like.dtype, device=like.device)
+    _check_dev(y)
+    return y
+
+
+def spmv_crs(A: CSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
+             use_plan: bool = True) -> torch.Tensor:
+    """y = alpha*A x + beta*y with the CRS kernels (spmv_crs)."""
+    _check_dev(x)
+    if use_plan and A.plan is None:
+        spmv_crs_plan(A)
+    y = _out_vec(y, A.n_rows, x, beta)
+    plan = A.plan if use_plan else None
+    call("spmv_crs", A.n_rows, A.n_cols, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(x),
+         _p(y), dtype_code(x.dtype), float(alpha), float(beta), _p(plan), A.n_blocks if use_plan else 0,
+         A.block_nnz if use_plan else 0, _stream())
+    return y
+
+
+def spmv_jds(J: JDS, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
+             unroll: int = 0, max_iters: int = 0) -> torch.Tensor:
+    """y = alpha*A x + beta*y with the JDS kernel (spmv_jds)."""
+    _check_dev(x)
+    y = _out_vec(y, J.n, x, beta)
+    call("spmv_jds", J.n, _p(J.perm), _p(J.jd_ptr), _h_i32(J.h_jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val),
+         dtype_code(J.jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll, max_iters,
+         J.flags, _stream())
+    return y
+
+
+def spmv_jds_blocked(B: Blocked, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                     beta: float = 0.0, rows_per_wave: int = 0, unroll: int = 0, max_iters: int = 0) -> torch.Tensor:
+    """y = alpha*A x + beta*y with the blocked-JDS kernel (spmv_jds_blocked)."""
+    _check_dev(x)
+    y = _out_vec(y, B.n, x, beta)
+    flags = (SYMPERM if B.symperm else 0) | (SOJDS if B.sojds else 0)
+    call("spmv_jds_blocked", B.n, _p(B.perm), B.C, B.n_slices, _p(B.slice_ptr), _p(B.slice_nd),
+         _h_i32(B.h_slice_nd), _p(B.bl_col), _p(B.bl_val), dtype_code(B.bl_val.dtype), _p(x), _p(y),
+         dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave, unroll, max_iters, flags, _stream())
+    return y
+
+
+def colmajor(n: int, k: int, dtype, device) -> torch.Tensor:
+    """An n x k column-major block (a transposed view of a (k, n) tensor)."""
+    return torch.empty(k, n, dtype=dtype, device=device).t()
+
+
+def _ld(X: torch.Tensor, n: int) -> int:
+    if X.dim() != 2 or X.stride(0) != 1 or X.shape[0] != n:
+        raise ValueError("multi-vector blocks must be column-major (n, k) with unit row stride")
+    return X.stride(1) if X.shape[1] > 1 else n
+
+
+def spmm_crs(A: CSR, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0,
+             beta: float = 0.0) -> torch.Tensor:
+    if A.plan is None:
+        spmv_crs_plan(A)
+    k = X.shape[1]
+    if Y is None:
+        Y = colmajor(A.n_rows, k, X.dtype, X.device)
+    call("spmm_crs", A.n_rows, A.n_cols, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), k, _p(X),
+         _ld(X, A.n_cols), _p(Y), _ld(Y, A.n_rows), dtype_code(X.dtype), float(alpha), float(beta), _p(A.plan),
+         A.n_blocks, A.block_nnz, _stream())
+    return Y
+
+
+def spmm_jds(J: JDS, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0,
+             beta: float = 0.0) -> torch.Tensor:
+    k = X.shape[1]
+    if Y is None:
+        Y = colmajor(J.n, k, X.dtype, X.device)
+    call("spmm_jds", J.n, _p(J.perm), _p(J.jd_ptr), _h_i32(J.h_jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val),
+         dtype_code(J.jd_val.dtype), k, _p(X), _ld(X, J.n_cols), _p(Y), _ld(Y, J.n), dtype_code(X.dtype),
+         float(alpha), float(beta), J.flags, _stream())
+    return Y
+
+
+def spmv_permute_vec(perm: torch.Tensor, v: torch.Tensor, inverse: bool = False) -> torch.Tensor:
+    out = torch.empty_like(v)
+    call("spmv_permute_vec", v.numel(), _p(perm), _p(v), _p(out), dtype_code(v.dtype), int(inverse), _stream())
+    return out
+
+
+def spmv_gather_values(map_: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
+    """out[i] = v[map_[i]]; 4-byte and 8-byte payloads move bit for bit."""
+    dt = v.dtype
+    src = v
+    if dt == torch.int32:
+        src, dt = v.view(torch.float32), torch.float32
+    out = torch.empty(map_.numel(), dtype=dt, device=v.device)
+    call("spmv_gather_values", map_.numel(), _p(map_), _p(src), _p(out), dtype_code(dt), _stream())
+    return out.view(v.dtype) if v.dtype == torch.int32 else out
+
+
+def spmv_axpby(alpha: float, x: torch.Tensor, beta: float, y: torch.Tensor) -> torch.Tensor:
+    """y = alpha*x + beta*y in place (beta == 0 never reads y)."""
+    call("spmv_axpby", x.numel(), float(alpha), _p(x), float(beta), _p(y), dtype_code(x.dtype), _stream())
+    return y
+
+
+def spmv_dot(x: torch.Tensor, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """sum_i x_i y_i in FP64 with a fixed summation tree; a 1-element device tensor."""
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    ws = _ws(_lib.load().spmv_dot_workspace_size(x.numel()), x.device)
+    call("spmv_dot", x.numel(), _p(x), _p(y), dtype_code(x.dtype), _p(out), _p(ws), ws.numel(), _stream())
+    return out
+
+
+def spmv_grad_vals_jds(J: JDS, g: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+                       alpha: float = 1.0, beta: float = 0.0) -> torch.Tensor:
+    """dval[e] = alpha*g[row_e]*x[col_e] + beta*dval[e] over the JDS entries."""
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        out = torch.empty(J.nnz, dtype=g.dtype, device=g.device)
+    call("spmv_grad_vals_jds", J.n, _p(J.perm), _p(J.jd_ptr), J.ndiag, J.nnz, _p(J.jd_col), _p(g), _p(x), _p(out),
+         dtype_code(g.dtype), float(alpha), float(beta), J.flags, _stream())
+    return out
+
+
+def spmv_stream_triad(a, b, c, s: float):
+    call("spmv_stream_triad", a.numel(), _p(b), _p(c), _p(a), float(s), _stream())
+
+
+def spmv_stream_copy(a, b):
+    call("spmv_stream_copy", a.numel(), _p(b), _p(a), _stream())
+
+
+# --------------------------------------------------------------------------- many matrices
+
+
+class Batched:
+    """Many blocked-JDS matrices (float32) run by one persistent launch (spmv_batched).
+
+    ``mats`` is a list of Blocked matrices (float32 values).  Their arrays are
+    concatenated once; x and y of all matrices are concatenated in order.
+    """
+
+    def __init__(self, mats, rows_per_wave: int = 64, unroll: int = 0, n_workgroups: int = 0):
+        if not mats:
+            raise ValueError("no matrices")
+        dev = mats[0].bl_val.device
+        for B in mats:
+            if B.bl_val.dtype != torch.float32:
+                raise TypeError("batched form takes float32 values")
+        self.n_mat = len(mats)
+        self.n_rows = np.array([B.n for B in mats], dtype=np.int32)
+        self.n_cols = np.array([B.n_cols for B in mats], dtype=np.int64)
+        self.C = np.array([B.C for B in mats], dtype=np.int32)
+        self.row_base = np.concatenate([[0], np.cumsum(self.n_rows.astype(np.int64))[:-1]]).astype(np.int64)
+        self.col_base = np.concatenate([[0], np.cumsum(self.n_cols)[:-1]]).astype(np.int64)
+        self.total_rows = int(self.n_rows.astype(np.int64).sum())
+        self.total_cols = int(self.n_cols.sum())
+        ns = np.array([B.n_slices for B in mats], dtype=np.int64)
+        self.slice_base = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+        el_base = np.concatenate([[0], np.cumsum([B.padded for B in mats])[:-1]]).astype(np.int64)
+        # absolute slice offsets on the host, from each matrix's device slice_ptr
+        self.h_slice_ptr = np.concatenate(
+            [B.slice_ptr[:-1].cpu().numpy() + el_base[m] for m, B in enumerate(mats)]).astype(np.int64)
+        self.h_slice_nd = np.concatenate([B.h_slice_nd for B in mats]).astype(np.int32)
+        self.bl_col = torch.cat([B.bl_col for B in mats])
+        self.bl_val = torch.cat([B.bl_val for B in mats])
+        self.perm = torch.cat([B.perm for B in mats])
+        self.rows_per_wave, self.unroll, self.n_workgroups = rows_per_wave, unroll, n_workgroups
+        self.nnz_padded = int(self.bl_val.numel())
+        self._plan(dev)
+
+    def _plan(self, dev):
+        lib = _lib.load()
+        nt = C.c_int64(0)
+        args = lambda p, cap: (self.n_mat, _h_i32(self.n_rows), _h_i32(self.C), _h_i64(self.slice_base),
+                               _h_i64(self.row_base), _h_i64(self.col_base), _h_i64(self.h_slice_ptr),
+                               _h_i32(self.h_slice_nd), self.rows_per_wave, p, cap, C.byref(nt), _stream())
+        st = lib.spmv_batched_plan(*args(None, 0))
+        if st not in (0, 3):
+            call("spmv_batched_plan", *args(None, 0))
+        self.n_tiles = nt.value
+        self.plan = torch.empty(max(self.n_tiles * _lib.BATCHED_PLAN_WORDS, 1), dtype=_I32, device=dev)
+        call("spmv_batched_plan", *args(_p(self.plan), self.plan.numel()))
+
+    def __call__(self, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if y is None:
+            y = torch.empty(self.total_rows, dtype=torch.float32, device=x.device)
+        call("spmv_batched", self.n_tiles, _p(self.plan), _p(self.perm), _p(self.bl_col), _p(self.bl_val), _p(x),
+             _p(y), self.unroll, self.n_workgroups, _stream())
+        return y
+
+
+# --------------------------------------------------------------------------- HIP graphs
+
+
+class Graph:
+    """Captures the library calls made inside ``with g.capture():`` on a side stream."""
+
+    def __init__(self):
+        self.exec = None
+        self.stream = torch.cuda.Stream()
+
+    def capture(self):
+        g = self
+
+        class _Ctx:
+            def __enter__(self_):
+                g.stream.wait_stream(torch.cuda.current_stream())
+                self_.ctx = torch.cuda.stream(g.stream)
+                self_.ctx.__enter__()
+                call("spmv_graph_begin", C.c_void_p(g.stream.cuda_stream))
+
+            def __exit__(self_, et, ev, tb):
+                h = C.c_void_p()
+                try:
+                    call("spmv_graph_end", C.c_void_p(g.stream.cuda_stream), C.byref(h))
+                finally:
+                    self_.ctx.__exit__(et, ev, tb)
+                torch.cuda.current_stream().wait_stream(g.stream)
+                g.exec = h
+                return False
+
+        return _Ctx()
+
+    def replay(self):
+        call("spmv_graph_launch", self.exec, _stream())
+
+    def __del__(self):
+        if getattr(self, "exec", None):
+            try:
+                _lib.load().spmv_graph_destroy(self.exec)
+            except Exception:
+                pass

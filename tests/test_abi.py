@@ -1,0 +1,73 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry point,
+the Python binding declares them all, and the product path never touches the oracle."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spmv.h")
+PKG = os.path.join(ROOT, "paper_0910_4836_amd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b((?:spmv|spmm)_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["spmv_csr_from_coo", "spmv_jds_from_csr", "spmv_crs", "spmv_jds", "spmv_jds_blocked",
+                 "spmv_jds_blocked_from_jds", "spmm_crs", "spmm_jds", "spmv_batched", "spmv_batched_plan",
+                 "spmv_transpose_csr", "spmv_grad_vals_jds", "spmv_convert_values"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_0910_4836_amd import _lib
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_symbol():
+    from paper_0910_4836_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared_functions()
+    lib = _lib.load()
+    assert lib.spmv_version().decode() == "1.0.0"
+    assert lib.spmv_status_string(3).decode() == "output capacity too small"
+
+
+def test_host_side_validation_without_gpu():
+    """Argument checks run on the host before any device work."""
+    from paper_0910_4836_amd import _lib
+    lib = _lib.load()
+    st = lib.spmv_crs(-1, 0, None, None, None, 0, None, None, 0, 1.0, 0.0, None, 0, 0, None)
+    assert st == 1 and b"negative" in lib.spmv_last_error()
+    st = lib.spmv_jds(10, None, None, None, 0, None, None, 0, None, None, 0, 1.0, 0.0, 3, 0, 0, None)
+    assert st == 1 and b"unroll" in lib.spmv_last_error()
+    st = lib.spmv_jds_blocked(10, None, 96, 1, None, None, None, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, 0,
+                              0, None)
+    assert st == 1 and b"multiple of 64" in lib.spmv_last_error()
+    st = lib.spmv_crs(10, 10, None, None, None, 7, None, None, 0, 1.0, 0.0, None, 0, 0, None)
+    assert st == 1 and b"dtype" in lib.spmv_last_error()
+
+
+def test_product_path_does_not_use_the_oracle():
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\boracle\b", text), f"{f} mentions the oracle"
+                assert "synth" not in text, f"{f} imports the input generator"
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    from paper_0910_4836_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError):
+        _lib.load()

@@ -1,0 +1,142 @@
+"""GPU format construction (COO -> CRS, CRS -> JDS, JDS -> blocked JDS, transpose)
+against the oracle: integer and index work must be bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import gpu_csr, rand_coo, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_0910_4836_amd")
+
+
+def test_csr_from_coo_shuffled_duplicates():
+    rng = np.random.default_rng(1)
+    n_rows, n_cols, k = 3000, 2500, 60000
+    row = rng.integers(0, n_rows, k).astype(np.int32)
+    col = rng.integers(0, n_cols, k).astype(np.int32)
+    row[:500] = 7                      # a long row and many duplicates
+    col[:500] = rng.integers(0, 40, 500)
+    val = rng.standard_normal(k)
+    val[::13] = 0.0
+    A = gpu_csr(sp, row, col, val, n_rows, n_cols)
+    R = oracle.csr_from_coo(n_rows, n_cols, row, col, val)
+    assert np.array_equal(to_np(A.row_ptr), R.row_ptr)
+    assert np.array_equal(to_np(A.col_idx), R.col)
+    assert np.array_equal(to_np(A.val), R.val)      # sums in input order: bit-exact
+    assert sp.spmv_csr_validate(A)
+
+
+def test_csr_from_coo_float32_and_empty_and_errors():
+    r, c, v, nr, nc, _ = rand_coo(2, 700, 900, 0.02, empty_rows=0.3)
+    order = np.random.default_rng(3).permutation(len(r))
+    A = gpu_csr(sp, r[order], c[order], v[order], nr, nc, torch.float32)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    assert np.array_equal(to_np(A.row_ptr), R.row_ptr)
+    assert np.array_equal(to_np(A.col_idx), R.col)
+    assert np.array_equal(to_np(A.val), R.val.astype(np.float32))
+    E = sp.csr_from_coo(5, 5, to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0, np.int32)),
+                        to_dev(np.zeros(0)))
+    assert E.nnz == 0 and to_np(E.row_ptr).tolist() == [0] * 6
+    with pytest.raises(sp.SpmvError):
+        sp.csr_from_coo(3, 3, to_dev(np.array([0, 3], np.int32)), to_dev(np.array([0, 0], np.int32)),
+                        to_dev(np.ones(2)))
+
+
+def test_validate_detects_bad_structure():
+    r, c, v, nr, nc, _ = rand_coo(4, 100, 100, 0.05)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    assert sp.spmv_csr_validate(A)
+    bad = A.col_idx.clone()
+    bad[3] = nc + 5
+    assert not sp.spmv_csr_validate(A.__class__(nr, nc, A.row_ptr, bad, A.val))
+    rp = A.row_ptr.clone()
+    rp[10] = rp[11] + 5                      # row_ptr decreases at row 10
+    assert not sp.spmv_csr_validate(A.__class__(nr, nc, rp, A.col_idx, A.val))
+
+
+def check_jds(J, R):
+    assert np.array_equal(to_np(J.perm), R.perm)
+    assert np.array_equal(to_np(J.iperm), R.iperm)
+    assert np.array_equal(to_np(J.jd_ptr), R.jd_ptr)
+    assert np.array_equal(J.h_jd_ptr, R.jd_ptr)
+    assert np.array_equal(to_np(J.jd_col), R.jd_col)
+    assert np.array_equal(to_np(J.jd_val).astype(np.float64), R.jd_val)
+
+
+@pytest.mark.parametrize("symperm", [False, True])
+def test_jds_from_csr_bit_exact(symperm):
+    r, c, v, nr, nc, _ = rand_coo(5, 5000, 5000, 0.002, empty_rows=0.2, long_rows=5, long_len=700)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    Rc = oracle.csr_from_coo(nr, nc, r, c, v)
+    J = sp.jds_from_csr(A, symperm=symperm)
+    check_jds(J, oracle.jds_from_csr(Rc, symperm=symperm))
+    B = sp.jds_to_csr(J)                        # exact inverse
+    assert np.array_equal(to_np(B.row_ptr), Rc.row_ptr)
+    assert np.array_equal(to_np(B.col_idx), Rc.col)
+    assert np.array_equal(to_np(B.val), Rc.val)
+
+
+def test_jds_laplacian_jd_ptr():
+    r, c, v, n, _ = synth.laplacian3d(20)
+    J = sp.jds_from_csr(gpu_csr(sp, r, c, v, n, n))
+    assert J.h_jd_ptr.tolist() == [0, 8000, 16000, 24000, 32000, 39992, 47768, 53600]
+
+
+@pytest.mark.parametrize("C", [64, 128, 512])
+@pytest.mark.parametrize("sojds", [False, True])
+def test_blocked_from_jds_bit_exact(C, sojds):
+    r, c, v, nr, nc, _ = rand_coo(6, 3000, 3000, 0.003, empty_rows=0.1, long_rows=3, long_len=300)
+    Rc = oracle.csr_from_coo(nr, nc, r, c, v)
+    Rb = oracle.blocked_from_jds(oracle.jds_from_csr(Rc), C, sojds=sojds)
+    J = sp.jds_from_csr(gpu_csr(sp, r, c, v, nr, nc))
+    B = sp.jds_blocked_from_jds(J, C, sojds=sojds)
+    assert np.array_equal(to_np(B.slice_ptr), Rb.slice_ptr)
+    assert np.array_equal(to_np(B.slice_nd), Rb.slice_nd)
+    assert np.array_equal(B.h_slice_nd, Rb.slice_nd)
+    assert np.array_equal(to_np(B.bl_col), Rb.bl_col)
+    assert np.array_equal(to_np(B.bl_val), Rb.bl_val)
+
+
+def test_transpose_bit_exact():
+    r, c, v, nr, nc, _ = rand_coo(7, 2000, 1500, 0.004, empty_rows=0.1)
+    Rc = oracle.csr_from_coo(nr, nc, r, c, v)
+    rowT, colT, tmap = oracle.transpose(Rc)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    gr, gc, gt = sp.spmv_transpose_csr(A)
+    assert np.array_equal(to_np(gr), rowT)
+    assert np.array_equal(to_np(gc), colT)
+    assert np.array_equal(to_np(gt).astype(np.int64), tmap)
+
+
+def test_convert_values_rounding():
+    rng = np.random.default_rng(8)
+    v = np.concatenate([rng.standard_normal(100000), rng.standard_normal(1000) * 1e-39,
+                        rng.standard_normal(1000) * 3e38,
+                        [1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -8 + 2.0 ** -40, 2.0 ** -134, 511 * 2.0 ** 119,
+                         0.0, -0.0, np.inf, -np.inf]])
+    t = to_dev(v)
+    b = sp.spmv_convert_values(t, torch.bfloat16)
+    assert np.array_equal(to_np(b.view(torch.int16)).view(np.uint16), oracle.round_bf16_bits(v))
+    f = sp.spmv_convert_values(t, torch.float32)
+    assert np.array_equal(to_np(f), oracle.round_f32(v))
+    back = sp.spmv_convert_values(b, torch.float64)
+    assert np.array_equal(to_np(back), oracle.bf16_bits_to_f64(oracle.round_bf16_bits(v)))
+
+
+def test_permute_and_gather():
+    rng = np.random.default_rng(9)
+    n = 10000
+    perm = rng.permutation(n).astype(np.int32)
+    v = rng.standard_normal(n)
+    p, t = to_dev(perm), to_dev(v)
+    assert np.array_equal(to_np(sp.spmv_permute_vec(p, t)), v[perm])
+    out = np.empty(n)
+    out[perm] = v
+    assert np.array_equal(to_np(sp.spmv_permute_vec(p, t, inverse=True)), out)
+    idx = rng.integers(0, n, 3000).astype(np.int32)
+    assert np.array_equal(to_np(sp.spmv_gather_values(to_dev(idx), t)), v[idx])
+    iv = rng.integers(-2 ** 31, 2 ** 31 - 1, n).astype(np.int32)
+    assert np.array_equal(to_np(sp.spmv_gather_values(to_dev(idx), to_dev(iv))), iv[idx])

@@ -1,0 +1,140 @@
+"""GPU SpMV (CRS, JDS, blocked JDS) against the FP64 oracle.
+
+FP64 kernels: max_i |y_i - y_ref_i| / sum_j |a_ij||x_j| <= 1e-12 (two summation
+orders of an L-term row differ by at most about 2*L*2^-53 relative to that
+scale: 4.4e-13 at L = 2000).  Integer-valued inputs: bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import FP64_TOL, gpu_csr, max_err, rand_coo, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_0910_4836_amd")
+
+
+def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_iters=(0,)):
+    """Yields (name, fn(x, y, alpha, beta)) for every kernel variant on matrix A."""
+    yield "crs", lambda x, y, a, b: sp.spmv_crs(A, x, y, a, b)
+    yield "crs_wave", lambda x, y, a, b: sp.spmv_crs(A, x, y, a, b, use_plan=False)
+    J = sp.jds_from_csr(A, symperm=symperm)
+    for u in unrolls:
+        for mi in max_iters:
+            yield f"jds_u{u}_mi{mi}", (lambda J=J, u=u, mi=mi: lambda x, y, a, b: sp.spmv_jds(J, x, y, a, b, u, mi))()
+    for C in Cs:
+        B = sp.jds_blocked_from_jds(J, C)
+        for R in rows_per_wave:
+            for mi in max_iters:
+                yield f"blk_C{C}_R{R}_mi{mi}", (lambda B=B, R=R, mi=mi:
+                                                lambda x, y, a, b: sp.spmv_jds_blocked(B, x, y, a, b, R, 0, mi))()
+
+
+def run_case(r, c, v, nr, nc, x, y0=None, alpha=1.0, beta=0.0, exact=False, **kw):
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    want = oracle.spmv_crs(R, x, y0, alpha, beta)
+    D = oracle.row_absdot(R, x) * abs(alpha)
+    if y0 is not None:
+        D = D + abs(beta) * np.abs(y0)
+    xd = to_dev(x)
+    for name, fn in all_forms(A, **kw):
+        y = to_dev(y0.copy()) if y0 is not None else None
+        got = fn(xd, y, alpha, beta)
+        if exact:
+            assert np.array_equal(to_np(got), want), name
+        else:
+            e = max_err(got, want, D)
+            assert e <= FP64_TOL, f"{name}: {e:.3e}"
+
+
+def test_laplacian_all_kernels_and_sine_mode():
+    r, c, v, n, _ = synth.laplacian3d(20)
+    x = synth.uniform_vector(n, synth.rng_for(1, 1))
+    run_case(r, c, v, n, n, x, unrolls=(2, 4, 8), Cs=(64, 256), rows_per_wave=(0, 8, 16, 64))
+    # closed form: A v = lambda v for the (3, 7, 11) sine mode
+    m = 20
+    idx = np.arange(n)
+    i, j, k = idx % m, (idx // m) % m, idx // (m * m)
+    vmode = np.sin(3 * np.pi * (i + 1) / 21) * np.sin(7 * np.pi * (j + 1) / 21) * np.sin(11 * np.pi * (k + 1) / 21)
+    lam = 6 - 2 * np.cos(3 * np.pi / 21) - 2 * np.cos(7 * np.pi / 21) - 2 * np.cos(11 * np.pi / 21)
+    A = gpu_csr(sp, r, c, v, n, n)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    D = oracle.row_absdot(R, vmode)
+    for name, fn in all_forms(A):
+        got = fn(to_dev(vmode), None, 1.0, 0.0)
+        assert max_err(got, lam * vmode, D) <= FP64_TOL, name
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_ragged_with_empty_and_long_rows(seed):
+    # rows: many short, some empty, a few long (multi-class split, ragged tails)
+    r, c, v, nr, nc, rng = rand_coo(10 + seed, 9000 + 37 * seed, 7000, 0.0015, empty_rows=0.25, long_rows=40,
+                                    long_len=3000)
+    x = rng.uniform(-1, 1, nc)
+    run_case(r, c, v, nr, nc, x, unrolls=(2, 8), Cs=(64, 128), rows_per_wave=(0, 16, 64), max_iters=(0, 4))
+
+
+def test_alpha_beta_accumulate():
+    r, c, v, nr, nc, rng = rand_coo(20, 3000, 3000, 0.004, empty_rows=0.1, long_rows=5, long_len=900)
+    x = rng.uniform(-1, 1, nc)
+    y0 = rng.uniform(-1, 1, nr)
+    run_case(r, c, v, nr, nc, x, y0, alpha=-1.75, beta=0.5)
+    run_case(r, c, v, nr, nc, x, None, alpha=2.0, beta=0.0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_integer_bit_exact(seed):
+    r, c, v, nr, nc, rng = rand_coo(30 + seed, 4000, 4000, 0.003, integer=True, empty_rows=0.1, long_rows=8,
+                                    long_len=2500)
+    x = synth.integer_vector(nc, rng)
+    y0 = synth.integer_vector(nr, rng)
+    run_case(r, c, v, nr, nc, x, exact=True, unrolls=(2, 4, 8), Cs=(64, 256), rows_per_wave=(0, 8, 32),
+             max_iters=(0, 2))
+    run_case(r, c, v, nr, nc, x, y0, alpha=1.0, beta=1.0, exact=True)     # the paper's accumulate form
+
+
+def test_symperm_mode():
+    r, c, v, n, _, rng = rand_coo(40, 5000, 5000, 0.002, empty_rows=0.1, long_rows=10, long_len=500)
+    x = rng.uniform(-1, 1, n)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    want = oracle.spmv_crs(R, x)
+    D = oracle.row_absdot(R, x)
+    A = gpu_csr(sp, r, c, v, n, n)
+    J = sp.jds_from_csr(A, symperm=True)
+    perm = to_np(J.perm)
+    xp = sp.spmv_permute_vec(J.perm, to_dev(x))
+    yp = sp.spmv_jds(J, xp)
+    y = sp.spmv_permute_vec(J.perm, yp, inverse=True)
+    assert max_err(y, want, D) <= FP64_TOL
+    B = sp.jds_blocked_from_jds(J, 128)
+    yb = sp.spmv_jds_blocked(B, xp)
+    assert max_err(yb, want[perm], D[perm]) <= FP64_TOL
+
+
+def test_empty_matrix_and_single_row():
+    x = to_dev(np.ones(5))
+    A = sp.csr_from_coo(4, 5, to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0)))
+    y0 = to_dev(np.full(4, 3.0))
+    for name, fn in all_forms(A):
+        got = fn(x, y0.clone(), 1.0, 0.5)
+        assert to_np(got).tolist() == [1.5] * 4, name
+    # n = 1, one dense row of 5000 entries (a single long row)
+    nc = 5000
+    r = np.zeros(nc, np.int32)
+    c = np.arange(nc, dtype=np.int32)
+    vv = np.random.default_rng(1).standard_normal(nc)
+    xx = np.random.default_rng(2).uniform(-1, 1, nc)
+    run_case(r, c, vv, 1, nc, xx)
+
+
+def test_deterministic_repeat():
+    r, c, v, nr, nc, rng = rand_coo(50, 20000, 20000, 0.001, long_rows=20, long_len=5000)
+    x = to_dev(rng.uniform(-1, 1, nc))
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    for name, fn in all_forms(A, max_iters=(0, 8)):
+        a = to_np(fn(x, None, 1.0, 0.0))
+        b = to_np(fn(x, None, 1.0, 0.0))
+        assert np.array_equal(a, b), name
