@@ -185,7 +185,7 @@ spmv_status spmv_transpose_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, cons
 /* CRS kernel (paper Section 2, CRS listing): y_i = alpha*sum_j val_j x_{col_j}
  * + beta*y_i.  plan/n_blocks/block_nnz as given to and returned by
  * spmv_crs_plan (block_nnz 0 = default); plan == NULL uses one wavefront per
- * row. */
+ * row.  col_idx, val and x may be NULL only if the matrix stores no entry. */
 spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
                      const void *val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
                      double alpha, double beta, const int32_t *plan, int32_t n_blocks,
@@ -224,7 +224,8 @@ spmv_status spmv_permute_vec(int32_t n, const int32_t *perm, const void *in, voi
 spmv_status spmv_gather_values(int64_t n, const int32_t *map, const void *in, void *out, spmv_dtype dt,
                                void *stream);
 
-/* y = alpha*x + beta*y (beta == 0 never reads y); dt F64 or F32. */
+/* y = alpha*x + beta*y (beta == 0 never reads y, alpha == 0 never reads x);
+ * dt F64 or F32. */
 spmv_status spmv_axpby(int64_t n, double alpha, const void *x, double beta, void *y, spmv_dtype dt,
                        void *stream);
 

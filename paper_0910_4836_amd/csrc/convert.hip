@@ -790,7 +790,7 @@ spmv_status spmv_jds_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, co
     if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_jds_from_csr: nnz >= 2^31");
     SPMV_REQUIRE(valid_dtype(dt), "spmv_jds_from_csr: bad dtype");
     SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_jds_from_csr: unknown flag");
-    SPMV_REQUIRE(h_ndiag && row_ptr && jd_ptr, "spmv_jds_from_csr: null pointer");
+    SPMV_REQUIRE(h_ndiag && row_ptr && (jd_ptr || jd_ptr_cap == 0), "spmv_jds_from_csr: null pointer");
     SPMV_REQUIRE(n == 0 || (perm && iperm), "spmv_jds_from_csr: null perm");
     SPMV_REQUIRE(nnz == 0 || (col_idx && val && jd_col && jd_val), "spmv_jds_from_csr: null arrays");
     SPMV_REQUIRE(ws && ws_bytes >= spmv_jds_from_csr_workspace_size(n, nnz), "spmv_jds_from_csr: workspace too small");

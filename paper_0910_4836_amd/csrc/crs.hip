@@ -341,7 +341,6 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_crs: bad dtype");
     if (n_rows == 0) return SPMV_OK;
     SPMV_REQUIRE(row_ptr && y, "spmv_crs: null row_ptr or y");
-    SPMV_REQUIRE(n_cols == 0 || (col_idx && val && x), "spmv_crs: null col_idx, val or x");
     if (plan) {
         SPMV_REQUIRE(n_blocks >= 0, "spmv_crs: n_blocks < 0");
         if (block_nnz == 0) block_nnz = CRS_DEFAULT_BLOCK_NNZ;
@@ -374,7 +373,6 @@ spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
     SPMV_REQUIRE(plan && n_blocks >= 0, "spmm_crs: needs a plan from spmv_crs_plan");
     SPMV_REQUIRE(ldx >= n_cols && ldy >= n_rows, "spmm_crs: leading dimension too small");
     SPMV_REQUIRE(row_ptr && Y, "spmm_crs: null row_ptr or Y");
-    SPMV_REQUIRE(n_cols == 0 || (col_idx && val && X), "spmm_crs: null col_idx, val or X");
     if (n_blocks == 0) return SPMV_OK;
     hipStream_t s = as_stream(stream);
 #define SPMM_CASE(VDT, VT, XDT, XT)           \

@@ -30,7 +30,7 @@ __global__ void axpby_kernel(int64_t n, double alpha, const T *__restrict__ x, d
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) {
-        double r = alpha * to_f64(x[i]);
+        double r = alpha != 0.0 ? alpha * to_f64(x[i]) : 0.0;   // alpha == 0 never reads x
         if (beta != 0.0) r = fma(beta, to_f64(y[i]), r);
         store_from_f64(&y[i], r);
     }

@@ -1,0 +1,188 @@
+"""Multi-vector (SpMM), many-matrix (batched persistent launch, HIP graph replay),
+transposed products and value gradients on the GPU against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import FP64_TOL, gpu_csr, max_err, rand_coo, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_0910_4836_amd")
+
+U32, U64 = 2.0 ** -24, 2.0 ** -53
+
+
+def gamma(k, u):
+    return k * u / (1 - k * u)
+
+
+def colmajor_from(X_np, dtype):
+    """(n, k) numpy -> column-major device block."""
+    t = torch.from_numpy(np.ascontiguousarray(X_np.T)).to("cuda").to(dtype)
+    return t.t()
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 11, 32])
+def test_spmm_fp64(k):
+    r, c, v, nr, nc, rng = rand_coo(60 + k, 6000, 5000, 0.002, empty_rows=0.1, long_rows=6, long_len=2000)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    X = rng.uniform(-1, 1, (nc, k))
+    Y0 = rng.uniform(-1, 1, (nr, k))
+    want = oracle.spmm_crs(R, X, alpha=1.5, beta=-0.5, Y=Y0)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    J = sp.jds_from_csr(A)
+    Xd = colmajor_from(X, torch.float64)
+    for name, fn in (("crs", lambda Y: sp.spmm_crs(A, Xd, Y, 1.5, -0.5)),
+                     ("jds", lambda Y: sp.spmm_jds(J, Xd, Y, 1.5, -0.5))):
+        got = to_np(fn(colmajor_from(Y0, torch.float64)))
+        for j in range(k):
+            D = 1.5 * oracle.row_absdot(R, X[:, j]) + 0.5 * np.abs(Y0[:, j])
+            e = oracle.rel_err(got[:, j], want[:, j], D).max()
+            assert e <= FP64_TOL, (name, j, e)
+
+
+def test_spmm_integer_exact_and_fp32_bound():
+    r, c, v, nr, nc, rng = rand_coo(70, 4000, 4000, 0.003, integer=True, long_rows=4, long_len=3000)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    k = 9
+    X = rng.integers(-8, 9, (nc, k)).astype(np.float64)
+    want = oracle.spmm_crs(R, X)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    J = sp.jds_from_csr(A)
+    Xd = colmajor_from(X, torch.float64)
+    assert np.array_equal(to_np(sp.spmm_crs(A, Xd)), want)
+    assert np.array_equal(to_np(sp.spmm_jds(J, Xd)), want)
+    # float32 values and vectors
+    r, c, v, nr, nc, rng = rand_coo(71, 4000, 4000, 0.003)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    vq = oracle.round_f32(R.val).astype(np.float64)
+    Rq = oracle.CSR(nr, nc, R.row_ptr, R.col, vq)
+    X = rng.uniform(-1, 1, (nc, k)).astype(np.float32).astype(np.float64)
+    want = oracle.spmm_crs(Rq, X)
+    A = gpu_csr(sp, r, c, v, nr, nc, torch.float32)
+    J = sp.jds_from_csr(A)
+    Xd = colmajor_from(X, torch.float32)
+    L = R.row_lengths()
+    for got in (to_np(sp.spmm_crs(A, Xd)), to_np(sp.spmm_jds(J, Xd))):
+        for j in range(k):
+            D = oracle.row_absdot(Rq, X[:, j])
+            assert np.all(np.abs(got[:, j] - want[:, j]) <= (gamma(L + 1, U32) + U32) * D)
+
+
+def small_batch(count, integer=False, seed=0):
+    mats = []
+    rng = np.random.default_rng(seed)
+    for m in range(count):
+        n = int(rng.integers(30, 3000))
+        lengths = rng.integers(5, min(40, n) + 1, size=n)
+        rows = np.repeat(np.arange(n), lengths)
+        cols = np.concatenate([rng.choice(n, L, replace=False) for L in lengths])
+        if integer:
+            vals = rng.integers(-8, 9, len(rows)).astype(np.float64)
+            x = rng.integers(-8, 9, n).astype(np.float64)
+        else:
+            vals = rng.standard_normal(len(rows)).astype(np.float32).astype(np.float64)
+            x = rng.uniform(-1, 1, n).astype(np.float32).astype(np.float64)
+        mats.append((rows.astype(np.int32), cols.astype(np.int32), vals, n, x))
+    return mats
+
+
+def build_batched(mats, Cs, **kw):
+    blocked = []
+    for i, (r, c, v, n, _) in enumerate(mats):
+        A = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v).to(torch.float32))
+        blocked.append(sp.jds_blocked_from_jds(sp.jds_from_csr(A), Cs[i % len(Cs)]))
+    return sp.Batched(blocked, **kw)
+
+
+@pytest.mark.parametrize("rpw", [64, 16])
+def test_batched_matches_oracle(rpw):
+    mats = small_batch(40, seed=rpw)
+    Bt = build_batched(mats, Cs=(64, 128, 256), rows_per_wave=rpw)
+    x = torch.cat([to_dev(m[4]).to(torch.float32) for m in mats])
+    y = to_np(Bt(x)).astype(np.float64)
+    off = 0
+    for r, c, v, n, xm in mats:
+        R = oracle.csr_from_coo(n, n, r, c, v)
+        want = oracle.spmv_crs(R, xm)
+        D = oracle.row_absdot(R, xm)
+        L = R.row_lengths()
+        assert np.all(np.abs(y[off:off + n] - want) <= (gamma(L + 1, U32) + U32) * D)
+        off += n
+
+
+def test_batched_integer_exact_and_graph_replay():
+    mats = small_batch(30, integer=True, seed=5)
+    Bt = build_batched(mats, Cs=(64, 192))
+    x = torch.cat([to_dev(m[4]).to(torch.float32) for m in mats])
+    want = np.concatenate([oracle.spmv_crs(oracle.csr_from_coo(n, n, r, c, v), xm) for r, c, v, n, xm in mats])
+    eager = Bt(x)
+    assert np.array_equal(to_np(eager).astype(np.float64), want)
+    y = torch.empty_like(eager)
+    g = sp.Graph()
+    with g.capture():
+        Bt(x, y)
+    for rep in range(3):
+        y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, eager), rep
+        other = Bt(x)                       # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(other, eager)
+
+
+def test_graph_replay_of_single_matrix_kernels():
+    r, c, v, nr, nc, rng = rand_coo(80, 20000, 20000, 0.001, long_rows=10, long_len=3000)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    J = sp.jds_from_csr(A)
+    B = sp.jds_blocked_from_jds(J, 128)
+    sp.spmv_crs_plan(A)
+    x = to_dev(rng.uniform(-1, 1, nc))
+    outs = [torch.empty(nr, dtype=torch.float64, device="cuda") for _ in range(3)]
+    eager = [sp.spmv_crs(A, x), sp.spmv_jds(J, x), sp.spmv_jds_blocked(B, x)]
+    g = sp.Graph()
+    with g.capture():
+        sp.spmv_crs(A, x, outs[0])
+        sp.spmv_jds(J, x, outs[1])
+        sp.spmv_jds_blocked(B, x, outs[2])
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
+
+
+def test_transposed_product_and_value_gradient():
+    from paper_0910_4836_amd.autograd import SpMVOperator
+    r, c, v, n, _, rng = rand_coo(90, 6000, 6000, 0.002, empty_rows=0.05, long_rows=5, long_len=1500)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    A = gpu_csr(sp, r, c, v, n, n)
+    op = SpMVOperator(A)
+    vals = op.J.jd_val
+    g = rng.uniform(-1, 1, n)
+    x = rng.uniform(-1, 1, n)
+    # dx = A^T g
+    want = oracle.spmv_crs_transposed(R, g)
+    rowT, colT, tmap = oracle.transpose(R)
+    RT = oracle.CSR(n, n, rowT, colT, R.val[tmap])
+    DT = oracle.row_absdot(RT, g)
+    assert max_err(op.rmatvec(vals, to_dev(g)), want, DT) <= FP64_TOL
+    # dval in JDS order: oracle value gradient (CRS order) moved by the oracle's own JDS order
+    dv_crs = oracle.grad_vals(R, g, x)
+    Rpos = oracle.CSR(n, n, R.row_ptr, R.col, np.arange(R.nnz, dtype=np.float64))
+    order = oracle.jds_from_csr(Rpos).jd_val.astype(np.int64)
+    assert np.array_equal(to_np(op.jds_src).astype(np.int64), order)
+    got = to_np(op.grad_vals(to_dev(g), to_dev(x)))
+    assert np.array_equal(got, dv_crs[order])                      # one product each: bit-exact
+    out = to_dev(np.ones(R.nnz))
+    got2 = to_np(op.grad_vals(to_dev(g), to_dev(x), out, alpha=2.0, beta=1.0))
+    assert np.allclose(got2, 2.0 * dv_crs[order] + 1.0, rtol=0, atol=4e-16)
+    # values refreshed through the transpose map
+    assert np.array_equal(to_np(op.transposed_values(vals)), R.val[tmap][oracle.jds_from_csr(
+        oracle.CSR(n, n, rowT, colT, np.arange(R.nnz, dtype=np.float64))).jd_val.astype(np.int64)])
