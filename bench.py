@@ -210,13 +210,7 @@ def cpu_baseline(W, budget_s=20.0):
     A = oracle.csr_from_coo(n, n, r, c, v)
     J = oracle.jds_from_csr(A)
     Bk = oracle.blocked_from_jds(J, 64)
-    vq = oracle.round_f32(A.val).astype(np.float64)
-    Aq = oracle.CSR(n, n, A.row_ptr, A.col, vq)
-    Jq = oracle.JDS(J.n, J.perm, J.iperm, J.jd_ptr, J.jd_col, oracle.round_f32(J.jd_val).astype(np.float64), False)
-    Bq = oracle.Blocked(Bk.n, Bk.perm, Bk.C, Bk.slice_ptr, Bk.slice_nd, Bk.bl_col,
-                        oracle.round_f32(Bk.bl_val).astype(np.float64), False)
-    step = [lambda: oracle.spmv_crs(A, x), lambda: oracle.spmv_jds(J, x), lambda: oracle.spmv_blocked(Bk, x),
-            lambda: oracle.spmv_crs(Aq, x), lambda: oracle.spmv_jds(Jq, x), lambda: oracle.spmv_blocked(Bq, x)]
+    step = [lambda: oracle.spmv_crs(A, x), lambda: oracle.spmv_jds(J, x), lambda: oracle.spmv_blocked(Bk, x)]
     reps = 0
     t0 = time.process_time()
     w0 = time.perf_counter()
@@ -228,9 +222,10 @@ def cpu_baseline(W, budget_s=20.0):
             break
     cpu_s = time.process_time() - t0
     wall = time.perf_counter() - w0
-    flops = 6 * 2.0 * A.nnz * reps
+    flops = len(step) * 2.0 * A.nnz * reps
     return {"value": round(flops / wall / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full steps (6 products each) of the n=2,000,000 power-law matrix, "
+            "sample": f"{reps} full steps (CRS, JDS, blocked JDS products in FP64) of the n=2,000,000 "
+                      f"power-law matrix, "
                       f"{cpu_s:.1f} s CPU, serial FP64 C oracle (-O2, no FMA), one thread",
             "host_cpu": platform.processor() or platform.machine(), "host_logical_cpus": os.cpu_count()}
 
@@ -247,9 +242,11 @@ def attainable_bw(torch, sp, dev):
     a = torch.empty(n, dtype=torch.float64, device=dev)
     b = torch.ones(n, dtype=torch.float64, device=dev)
     c = torch.ones(n, dtype=torch.float64, device=dev)
+    part = torch.empty(1 << 16, dtype=torch.float64, device=dev)
     out = {}
     for name, fn, nbytes in (("triad", lambda: sp.spmv_stream_triad(a, b, c, 0.5), 24 * n),
-                             ("copy", lambda: sp.spmv_stream_copy(a, b), 16 * n)):
+                             ("copy", lambda: sp.spmv_stream_copy(a, b), 16 * n),
+                             ("read", lambda: sp.spmv_stream_read(b, part), 8 * n)):
         ms, _ = time_loop(torch, [(name, fn)], 20, 3)
         out[name + "_GBs"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
     del a, b, c
@@ -259,23 +256,175 @@ def attainable_bw(torch, sp, dev):
 # --------------------------------------------------------------------------- suite
 
 
-def suite_lines(torch, sp, dev, W, steps, warmup):
+def _kernel_entry(name, nnz_flops, bmin, ms):
+    gbs = bmin / (ms * 1e-3) / 1e9
+    return {"avg_us": round(ms * 1e3, 2), "gflops": round(nnz_flops / (ms * 1e-3) / 1e9, 1),
+            "algorithmic_GBs": round(gbs, 1), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def _rel_err_gpu(torch, sp, A64, x, y, y_ref):
+    """max_i |y_i - y_ref_i| / sum_j |a_ij||x_j|, the scale from the library's own FP64 kernel."""
+    Aabs = A64.with_values(A64.val.abs())
+    D = sp.spmv_crs(Aabs, x.abs().to(torch.float64))
+    d = (y.to(torch.float64) - y_ref).abs()
+    nz = D > 0
+    return float((d[nz] / D[nz]).max()) if bool(nz.any()) else 0.0
+
+
+def suite_laplacian(torch, sp, dev, steps):
     import synth
-    lines = []
-    x = W["x"]
-    n = W["n"]
-    # multi-vector forms on the power-law matrix
+    r, c, v, n, _ = synth.laplacian3d(20)
+    A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
+    J = sp.jds_from_csr(A)
+    B = sp.jds_blocked_from_jds(J, 64)
+    x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(1, 1))).to(dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    ks = [("crs", lambda: sp.spmv_crs(A, x, y)), ("jds", lambda: sp.spmv_jds(J, x, y)),
+          ("blocked", lambda: sp.spmv_jds_blocked(B, x, y))]
+    _, per = time_loop(torch, ks, steps, 10)
+    g = sp.Graph()
+    with g.capture():
+        for _ in range(100):
+            sp.spmv_crs(A, x, y)
+    ms_g, _ = time_loop(torch, [("graph", g.replay)], 20, 3)
+    return {"workload": "7-point Laplacian 20^3 (n=8000, nnz=53600), FP64", "note": "L2-resident: latency and "
+            "launch bound, no HBM roofline", "kernels": {k: {"avg_us": round(per[k] * 1e3, 2),
+                                                             "gflops": round(2 * A.nnz / (per[k] * 1e-3) / 1e9, 1)}
+                                                         for k, _ in ks},
+            "crs_in_hip_graph_us_per_product": round(ms_g * 1e3 / 100, 2)}
+
+
+def suite_symdiag(torch, sp, dev, steps):
+    import synth
+    r, c, v, n, _ = synth.sym_diagonals()
+    A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
+    del r, c, v
+    J = sp.jds_from_csr(A)
+    B = sp.jds_blocked_from_jds(J, 64)
+    x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(3, 1))).to(dev)
+    nnz = A.nnz
+    y_ref = sp.spmv_crs(A, x)
+    out = {"workload": f"symmetric 12 secondary diagonals + diagonal, n={n}, nnz={nnz}", "kernels": {},
+           "max_rel_err_vs_fp64": {}}
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    for vdt, sv, tag in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32val"), (torch.bfloat16, 2, "bf16val")):
+        Aq = A if vdt == torch.float64 else A.with_values(sp.spmv_convert_values(A.val, vdt))
+        Jq = J if vdt == torch.float64 else J.with_values(sp.spmv_convert_values(J.jd_val, vdt))
+        Bq = B if vdt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
+        ks = [(f"crs_{tag}", lambda Aq=Aq: sp.spmv_crs(Aq, x, y)), (f"jds_{tag}", lambda Jq=Jq: sp.spmv_jds(Jq, x, y)),
+              (f"blocked_{tag}", lambda Bq=Bq: sp.spmv_jds_blocked(Bq, x, y))]
+        _, per = time_loop(torch, ks, max(10, steps // 4), 3)
+        bm = {ks[0][0]: bytes_crs(nnz, n, n, sv, 8), ks[1][0]: bytes_jds(nnz, n, n, J.ndiag, sv, 8),
+              ks[2][0]: bytes_blocked(nnz, n, n, B.n_slices, sv, 8)}
+        for name, fn in ks:
+            out["kernels"][name] = _kernel_entry(name, 2.0 * nnz, bm[name], per[name])
+            fn()
+            out["max_rel_err_vs_fp64"][name] = _rel_err_gpu(torch, sp, A, x, y, y_ref)
+        del Aq, Jq, Bq
+    f64 = out["kernels"]["crs_f64"]["avg_us"]
+    out["speedup_vs_fp64_crs"] = {k: round(f64 / e["avg_us"], 2) for k, e in out["kernels"].items()}
+    return out
+
+
+def suite_spmm(torch, sp, dev, W, steps):
+    n, nnz = W["n"], W["nnz"]
+    out = {"workload": f"power-law n={n} nnz={nnz} times k vectors (column-major X, Y)", "kernels": {}}
     for k in (8, 32):
-        for dt, sv in ((torch.float64, 8), (torch.float32, 4)):
+        for dt, sv, tag in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32")):
             A = W["A"] if dt == torch.float64 else W["A32"]
+            J = W["J"] if dt == torch.float64 else W["J32"]
             X = sp.colmajor(n, k, dt, dev)
             X.copy_(torch.rand(n, k, dtype=dt, device=dev) * 2 - 1)
             Y = sp.colmajor(n, k, dt, dev)
-            ms, per = time_loop(torch, [("spmm_crs", lambda: sp.spmm_crs(A, X, Y))], max(5, steps // 10), 2)
-            bm = bytes_crs(W["nnz"], n, n, sv, sv, k)
-            lines.append({"workload": f"powerlaw x {k} vectors (column-major)", "kernel": f"spmm_crs_{str(dt)[6:]}",
-                          "gflops": round(2 * W["nnz"] * k / (ms * 1e-3) / 1e9, 1),
-                          "roofline": roofline_for("spmm_crs", bm, per["spmm_crs"], "spmm")})
+            ks = [(f"spmm_crs_{tag}_k{k}", lambda: sp.spmm_crs(A, X, Y)),
+                  (f"spmm_jds_{tag}_k{k}", lambda: sp.spmm_jds(J, X, Y))]
+            _, per = time_loop(torch, ks, max(5, steps // 20), 2)
+            out["kernels"][ks[0][0]] = _kernel_entry(ks[0][0], 2.0 * nnz * k, bytes_crs(nnz, n, n, sv, sv, k),
+                                                     per[ks[0][0]])
+            out["kernels"][ks[1][0]] = _kernel_entry(ks[1][0], 2.0 * nnz * k,
+                                                     bytes_jds(nnz, n, n, J.ndiag, sv, sv, k), per[ks[1][0]])
+            del X, Y
+    return out
+
+
+def suite_batched(torch, sp, dev, steps, count=512):
+    import synth
+    mats, xs = [], []
+    nnz = 0
+    rows = 0
+    for r, c, v, n, x in synth.many_matrices(count=count):
+        A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev),
+                            torch.from_numpy(v).to(dev))
+        mats.append(sp.jds_blocked_from_jds(sp.jds_from_csr(A), 64))
+        xs.append(torch.from_numpy(x).to(dev))
+        nnz += A.nnz
+        rows += n
+        del A
+    Bt = sp.Batched(mats)
+    x = torch.cat(xs)
+    y = torch.empty(Bt.total_rows, dtype=torch.float32, device=dev)
+    g = sp.Graph()
+    with g.capture():
+        Bt(x, y)
+    ms_graph, _ = time_loop(torch, [("batched_graph", g.replay)], max(5, steps // 10), 2)
+    ms_eager, _ = time_loop(torch, [("batched", lambda: Bt(x, y))], max(5, steps // 10), 2)
+    ys = [torch.empty(m.n, dtype=torch.float32, device=dev) for m in mats]
+
+    def loop():
+        for m, xm, ym in zip(mats, xs, ys):
+            sp.spmv_jds_blocked(m, xm, ym)
+    ms_loop, _ = time_loop(torch, [("per_matrix", loop)], 3, 1)
+    bm = nnz * 8 + sum(12 * m.n_slices for m in mats) + 4 * rows + 4 * 2 * rows
+    e = _kernel_entry("batched", 2.0 * nnz, bm, ms_graph)
+    return {"workload": f"{count} matrices, n log-uniform [1e3, 2e5], 5-40 entries/row, FP32; sum n={rows}, "
+                        f"sum nnz={nnz}", "persistent_graph": e,
+            "persistent_eager_us": round(ms_eager * 1e3, 1), "one_launch_per_matrix_us": round(ms_loop * 1e3, 1),
+            "tiles": Bt.n_tiles, "rows_per_wave": Bt.rows_per_wave}
+
+
+def suite_chebyshev(torch, sp, dev, steps):
+    import synth
+    from paper_0910_4836_amd import autograd as AG
+    r, c, v, n, _ = synth.banded_uniform()
+    A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
+    del r, c, v
+    nnz = A.nnz
+    op = AG.SpMVOperator(A)
+    vals = op.J.jd_val.clone()
+    x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(5, 1), np.float32)).to(dev)
+    g = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    dv = torch.empty(nnz, dtype=torch.float32, device=dev)
+    ks = [("forward_spmv", lambda: op.matvec(vals, x, y)), ("transposed_spmv", lambda: op.rmatvec(vals, g, y)),
+          ("grad_vals", lambda: op.grad_vals(g, x, dv))]
+    _, per = time_loop(torch, ks, max(10, steps // 4), 3)
+    bm = {"forward_spmv": bytes_jds(nnz, n, n, op.J.ndiag, 4, 4), "transposed_spmv": bytes_jds(nnz, n, n, op.JT.ndiag,
+                                                                                               4, 4),
+          "grad_vals": nnz * (4 + 4 + 4) + 4 * n + 4 * (op.J.ndiag + 1) + 8 * n}
+    kern = {k: _kernel_entry(k, 2.0 * nnz, bm[k], per[k]) for k, _ in ks}
+
+    def fwd_bwd():
+        vv = vals.detach().requires_grad_(True)
+        xx = x.detach().requires_grad_(True)
+        AG.chebyshev_loss(op, vv, xx, 20, 5).backward()
+    ms_fb, _ = time_loop(torch, [("cheb", fwd_bwd)], 5, 1)
+    return {"workload": f"banded+uniform n={n} nnz={nnz} FP32, 20-step Chebyshev, checkpoint every 5", "kernels": kern,
+            "loss_and_gradient_ms": round(ms_fb, 3),
+            "spmv_equivalents_per_gradient": "20 forward + 15 recomputed + 20 transposed products + 20 value gradients"}
+
+
+def suite_lines(torch, sp, dev, W, steps, warmup):
+    lines = []
+    for name, fn in (("laplacian", lambda: suite_laplacian(torch, sp, dev, steps)),
+                     ("multi-vector", lambda: suite_spmm(torch, sp, dev, W, steps)),
+                     ("symmetric-diagonals", lambda: suite_symdiag(torch, sp, dev, steps)),
+                     ("chebyshev", lambda: suite_chebyshev(torch, sp, dev, steps)),
+                     ("many-matrices", lambda: suite_batched(torch, sp, dev, steps))):
+        print(f"# suite: {name}", file=sys.stderr, flush=True)
+        rec = fn()
+        print(json.dumps(rec), flush=True)
+        torch.cuda.empty_cache()
+        lines.append(rec)
     return lines
 
 
@@ -294,32 +443,42 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     W = load_powerlaw(torch, sp, dev)
-    ks, bmin = powerlaw_kernels(sp, W, torch)
+    all_ks, bmin = powerlaw_kernels(sp, W, torch)
+    # the step: the three FP64 products of the power-law workload
+    ks = [k for k in all_ks if k[0].endswith("_f64")]
+    mixed = [k for k in all_ks if not k[0].endswith("_f64")]
     if args.only:
         keep = set(args.only.split(","))
-        ks = [k for k in ks if k[0] in keep]
+        ks = [k for k in all_ks if k[0] in keep]
+        mixed = []
     ms_step, per = time_loop(torch, ks, args.steps, args.warmup)
     flops_step = 2.0 * W["nnz"] * len(ks)
     value = flops_step / (ms_step * 1e-3) / 1e9
     dom = max(per, key=per.get)
-    kernels = {}
-    for name, _ in ks:
-        kernels[name] = {"avg_ms": round(per[name], 5),
-                         "gflops": round(2.0 * W["nnz"] / (per[name] * 1e-3) / 1e9, 1),
-                         "algorithmic_GBs": round(bmin[name] / (per[name] * 1e-3) / 1e9, 1),
-                         "frac_of_8TBs": round(bmin[name] / (per[name] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    def entry(name, ms):
+        return {"avg_ms": round(ms, 5), "gflops": round(2.0 * W["nnz"] / (ms * 1e-3) / 1e9, 1),
+                "algorithmic_GBs": round(bmin[name] / (ms * 1e-3) / 1e9, 1),
+                "frac_of_8TBs": round(bmin[name] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    kernels = {name: entry(name, per[name]) for name, _ in ks}
     out = {
         "metric": "SpMV GFLOP/s + % of HBM code-balance roofline, CRS vs JDS, FP64 vs mixed",
         "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": f"power-law n={W['n']} nnz={W['nnz']} (mean 15/row, max 2000; CRS, JDS, "
-                               f"blocked JDS C=64; FP64 values and FP32 values with FP64 vectors)",
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"power-law n={W['n']} nnz={W['nnz']} (mean 15/row, max 2000): CRS, JDS and "
+                               f"blocked JDS (C=64) products in FP64",
                    "n": W["n"], "nnz": W["nnz"], "ndiag": W["J"].ndiag, "products_per_step": len(ks)},
         "kernels": kernels,
         "roofline": roofline_for(dom, bmin[dom], per[dom], "powerlaw"),
         "setup_ms": W["setup"],
     }
+    if mixed:
+        _, per_m = time_loop(torch, mixed, max(10, args.steps // 2), 3)
+        out["mixed_precision"] = {name: dict(entry(name, per_m[name]),
+                                             speedup_vs_fp64=round(per[name.replace("_f32val", "_f64")] /
+                                                                   per_m[name], 3))
+                                  for name, _ in mixed}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)
     else:
@@ -327,8 +486,7 @@ def main():
     out["attainable_hbm"] = attainable_bw(torch, sp, dev)
     print(json.dumps(out), flush=True)
     if args.suite:
-        for line in suite_lines(torch, sp, dev, W, args.steps, args.warmup):
-            print(json.dumps(line), flush=True)
+        suite_lines(torch, sp, dev, W, args.steps, args.warmup)
 
 
 if __name__ == "__main__":

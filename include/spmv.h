@@ -236,24 +236,35 @@ spmv_status spmv_dot(int64_t n, const void *x, const void *y, spmv_dtype dt, dou
                      size_t ws_bytes, void *stream);
 
 /* Multi-vector forms: Y[:, c] = alpha*A X[:, c] + beta*Y[:, c] for c < k,
- * X and Y column-major with leading dimensions ldx >= n_cols and ldy >= n. */
+ * X and Y column-major with leading dimensions ldx >= n_cols and ldy >= n
+ * (the paper's kernels, each stored entry used for k right-hand sides).
+ * ws (spmm_workspace_size(n_cols, k, vec_dt) bytes, may be NULL): with it,
+ * X is first copied into an interleaved row-major block inside ws so that
+ * every entry gathers its k values contiguously (k <= 64); without it the
+ * kernels gather straight from the column-major X.  Same arithmetic rules as
+ * the single-vector forms.  spmm_crs takes the spmv_crs_plan row blocks;
+ * spmm_jds takes the host copy h_jd_ptr (needed on the workspace path). */
+size_t spmm_workspace_size(int32_t n_cols, int32_t k, spmv_dtype vec_dt);
 spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
                      const void *val, spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y,
                      int64_t ldy, spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan,
-                     int32_t n_blocks, int32_t block_nnz, void *stream);
-spmv_status spmm_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr,
-                     int32_t ndiag, const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt,
-                     int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, spmv_dtype vec_dt,
-                     double alpha, double beta, unsigned flags, void *stream);
+                     int32_t n_blocks, int32_t block_nnz, void *ws, size_t ws_bytes, void *stream);
+spmv_status spmm_jds(int32_t n, int32_t n_cols, const int32_t *perm, const int32_t *jd_ptr,
+                     const int32_t *h_jd_ptr, int32_t ndiag, const int32_t *jd_col, const void *jd_val,
+                     spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                     spmv_dtype vec_dt, double alpha, double beta, unsigned flags, void *ws,
+                     size_t ws_bytes, void *stream);
 
 /* Value gradient of y = A x in JDS storage order:
  * dval[jd_ptr[d]+r] = alpha * g[row(r)] * x[jd_col[jd_ptr[d]+r]] + beta * dval[...]
  * with row(r) = perm[r] (original basis) or r (SPMV_SYMPERM).  Computed in
- * FP64 and rounded once to dt (the value/vector type, F64 or F32). */
-spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag,
-                               int64_t nnz, const int32_t *jd_col, const void *g, const void *x,
-                               void *dval, spmv_dtype dt, double alpha, double beta, unsigned flags,
-                               void *stream);
+ * FP64 as (alpha*g[row])*x[col] and rounded once to dt (the value/vector
+ * type, F64 or F32).  h_jd_ptr: host copy of jd_ptr (sizes the launch like
+ * spmv_jds); nnz must equal jd_ptr[ndiag]. */
+spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr,
+                               const int32_t *h_jd_ptr, int32_t ndiag, int64_t nnz,
+                               const int32_t *jd_col, const void *g, const void *x, void *dval,
+                               spmv_dtype dt, double alpha, double beta, unsigned flags, void *stream);
 
 /* ======================================================================== */
 /* Many matrices in one launch                                               */
@@ -268,13 +279,16 @@ spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd
  *   perm[h_row_base[m] .. + n_m) (local row numbers);  its columns index
  *   x[h_col_base[m] + col].
  * spmv_batched_plan cuts every matrix into tiles of rows_per_wave rows (8,
- * 16, 32 or 64; 0 = 64), orders them longest first (stable) and writes
+ * 16, 32 or 64; 0 = 64), orders the matrices by stored slots, largest first
+ * (stable), keeps each matrix's tiles together in row order and writes
  * SPMV_BATCHED_PLAN_WORDS int32 per tile into the device array `plan`
  * (capacity plan_cap int32); *h_n_tiles returns the tile count; if the
  * capacity is too small returns SPMV_ERR_CAPACITY.  Synchronises.
  * spmv_batched runs all tiles in one persistent launch of n_workgroups
- * 256-lane workgroups (0 = 8 per compute unit) whose wavefronts walk the
- * table with a fixed stride: deterministic and capturable in a HIP graph.
+ * 256-lane workgroups (0 = 8 per compute unit; rounded to a multiple of 8):
+ * each XCD walks one contiguous eighth of the table with a fixed wavefront
+ * stride, so results are deterministic and the launch is capturable in a
+ * HIP graph.
  * unroll: diagonals per trip (2, 4 or 8; 0 = 4). */
 #define SPMV_BATCHED_PLAN_WORDS 12
 spmv_status spmv_batched_plan(int32_t n_mat, const int32_t *h_n_rows, const int32_t *h_C,
@@ -296,11 +310,16 @@ spmv_status spmv_graph_launch(void *exec, void *stream);
 spmv_status spmv_graph_destroy(void *exec);
 
 /* ======================================================================== */
-/* Bandwidth probes (for rooflines): a[i] = b[i] + s*c[i]; a[i] = b[i]       */
+/* Bandwidth probes (attainable HBM bandwidth for the rooflines; the paper's  */
+/* STREAM triad figures play this role for its CPUs)                          */
 /* ======================================================================== */
+/* a[i] = b[i] + s*c[i];  a[i] = b[i];  part[w] = sum of the elements read by
+ * workgroup w.  n even, arrays 16-byte aligned; spmv_stream_read needs
+ * part_cap >= 8 * (compute units) doubles. */
 spmv_status spmv_stream_triad(int64_t n, const double *b, const double *c, double *a, double s,
                               void *stream);
 spmv_status spmv_stream_copy(int64_t n, const double *b, double *a, void *stream);
+spmv_status spmv_stream_read(int64_t n, const double *b, double *part, int64_t part_cap, void *stream);
 
 #ifdef __cplusplus
 }

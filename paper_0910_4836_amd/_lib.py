@@ -61,11 +61,12 @@ SIGNATURES = {
     "spmv_axpby": (_int, [_i64, _f64, _p, _f64, _p, _int, _p]),
     "spmv_dot_workspace_size": (_sz, [_i64]),
     "spmv_dot": (_int, [_i64, _p, _p, _int, _p, _p, _sz, _p]),
+    "spmm_workspace_size": (_sz, [_i32, _i32, _int]),
     "spmm_crs": (_int, [_i32, _i32, _p, _p, _p, _int, _i32, _p, _i64, _p, _i64, _int, _f64, _f64, _p, _i32, _i32,
-                        _p]),
-    "spmm_jds": (_int, [_i32, _p, _p, _i32p, _i32, _p, _p, _int, _i32, _p, _i64, _p, _i64, _int, _f64, _f64, _u32,
-                        _p]),
-    "spmv_grad_vals_jds": (_int, [_i32, _p, _p, _i32, _i64, _p, _p, _p, _p, _int, _f64, _f64, _u32, _p]),
+                        _p, _sz, _p]),
+    "spmm_jds": (_int, [_i32, _i32, _p, _p, _i32p, _i32, _p, _p, _int, _i32, _p, _i64, _p, _i64, _int, _f64, _f64,
+                        _u32, _p, _sz, _p]),
+    "spmv_grad_vals_jds": (_int, [_i32, _p, _p, _i32p, _i32, _i64, _p, _p, _p, _p, _int, _f64, _f64, _u32, _p]),
     "spmv_batched_plan": (_int, [_i32, _i32p, _i32p, _i64p, _i64p, _i64p, _i64p, _i32p, _i32, _p, _i64, _i64p,
                                  _p]),
     "spmv_batched": (_int, [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _p]),
@@ -75,6 +76,7 @@ SIGNATURES = {
     "spmv_graph_destroy": (_int, [_p]),
     "spmv_stream_triad": (_int, [_i64, _p, _p, _p, _f64, _p]),
     "spmv_stream_copy": (_int, [_i64, _p, _p, _p]),
+    "spmv_stream_read": (_int, [_i64, _p, _p, _i64, _p]),
 }
 
 _lib = None

@@ -1,0 +1,157 @@
+"""Autotuner for the blocked-JDS products: slice height C, rows per wavefront R
+and diagonals per trip U, chosen per row-length signature and cached.
+
+The signature of a matrix is (log2 of its row count, its longest row, its
+mean row length rounded to a power of two); matrices that share it share the
+best layout.  Tuning times candidate layouts with HIP events (the library's
+own kernels, nothing else) on a sample of the matrices of one signature and
+keeps the fastest.  The cache is a JSON file keyed by device name and
+signature, so a later run with the same kind of matrices skips the search.
+
+Tuning is a host-side choice of launch parameters; every candidate computes
+the same y (each result is checked against the oracle in the tests).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Iterable, List, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import spmv as S
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "spmv_autotune.json")
+C_CANDIDATES = (64, 128, 256)
+R_CANDIDATES = (64, 32, 16)
+U_CANDIDATES = (2, 4, 8)
+
+
+def signature(n_rows: int, row_lengths: np.ndarray) -> str:
+    if n_rows == 0 or len(row_lengths) == 0:
+        return "empty"
+    mx = int(row_lengths.max())
+    mean = float(row_lengths.mean())
+    return f"n2^{int(math.log2(max(n_rows, 1)))}/max{mx}/mean2^{int(round(math.log2(max(mean, 1.0))))}"
+
+
+def _device_key() -> str:
+    return torch.cuda.get_device_name(torch.cuda.current_device())
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time(fn, reps=10, warm=2) -> float:
+    for _ in range(warm):
+        fn()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+class Autotuner:
+    """Chooses (C, R, U) for blocked-JDS matrices; results cached per signature."""
+
+    def __init__(self, cache_path: str = DEFAULT_CACHE, cs=C_CANDIDATES, rs=R_CANDIDATES, us=U_CANDIDATES):
+        self.cache_path = cache_path
+        self.cs, self.rs, self.us = tuple(cs), tuple(rs), tuple(us)
+        self.cache = _load(cache_path)
+        self.log: List[dict] = []
+
+    def lookup(self, sig: str):
+        ent = self.cache.get(_device_key(), {}).get(sig)
+        return None if ent is None else (ent["C"], ent["R"], ent["U"])
+
+    def _record(self, sig, best, timings):
+        self.cache.setdefault(_device_key(), {})[sig] = {"C": best[0], "R": best[1], "U": best[2],
+                                                        "ms": round(timings[best], 5)}
+        _store(self.cache_path, self.cache)
+
+    def tune_batched(self, jds_list: Sequence[S.JDS], sample: int = 16) -> Tuple[int, int, int]:
+        """Best (C, R, U) for a batch of matrices sharing one signature: builds
+        the blocked layout of up to `sample` of them for each C and times the
+        persistent launch for each (R, U)."""
+        sig = "batched:" + self._batch_signature(jds_list)
+        hit = self.lookup(sig)
+        if hit is not None:
+            return hit
+        pick = list(jds_list[:: max(1, len(jds_list) // sample)])[:sample]
+        timings: Dict[Tuple[int, int, int], float] = {}
+        xs = [torch.rand(J.n_cols, dtype=torch.float32, device=J.jd_val.device) for J in pick]
+        x = torch.cat(xs)
+        for C in self.cs:
+            mats = [S.jds_blocked_from_jds(J, C) for J in pick]
+            for R in self.rs:
+                Bt = S.Batched(mats, rows_per_wave=R)
+                y = torch.empty(Bt.total_rows, dtype=torch.float32, device=x.device)
+                for U in self.us:
+                    Bt.unroll = U
+                    timings[(C, R, U)] = _time(lambda: Bt(x, y))
+            del mats
+        best = min(timings, key=timings.get)
+        self.log.append({"signature": sig, "timings_ms": {f"C{c}_R{r}_U{u}": round(t, 5)
+                                                          for (c, r, u), t in timings.items()}})
+        self._record(sig, best, timings)
+        return best
+
+    @staticmethod
+    def _batch_signature(jds_list: Iterable[S.JDS]) -> str:
+        mx, tot, rows, nmat = 0, 0, 0, 0
+        for J in jds_list:
+            mx = max(mx, J.ndiag)
+            tot += J.nnz
+            rows += J.n
+            nmat += 1
+        mean = tot / max(rows, 1)
+        return f"mats{nmat}/max{mx}/mean2^{int(round(math.log2(max(mean, 1.0))))}"
+
+    def tune_blocked(self, J: S.JDS, x: torch.Tensor) -> Tuple[int, int, int]:
+        """Best (C, R, U) for one large matrix in blocked-JDS storage."""
+        sig = "single:" + signature(J.n, np.diff(J.h_jd_ptr))
+        hit = self.lookup(sig)
+        if hit is not None:
+            return hit
+        timings = {}
+        y = torch.empty(J.n, dtype=x.dtype, device=x.device)
+        for C in self.cs:
+            B = S.jds_blocked_from_jds(J, C)
+            for R in self.rs:
+                for U in self.us:
+                    timings[(C, R, U)] = _time(lambda: S.spmv_jds_blocked(B, x, y, rows_per_wave=R, unroll=U))
+            del B
+        best = min(timings, key=timings.get)
+        self.log.append({"signature": sig, "timings_ms": {f"C{c}_R{r}_U{u}": round(t, 5)
+                                                          for (c, r, u), t in timings.items()}})
+        self._record(sig, best, timings)
+        return best
+
+
+def build_batched(jds_list: Sequence[S.JDS], tuner: Autotuner = None, n_workgroups: int = 0) -> S.Batched:
+    """Blocked layouts and the persistent plan for many matrices, with the
+    slice height / rows per wavefront / unroll the autotuner picks."""
+    tuner = tuner or Autotuner()
+    C, R, U = tuner.tune_batched(jds_list)
+    mats = [S.jds_blocked_from_jds(J, C) for J in jds_list]
+    return S.Batched(mats, rows_per_wave=R, unroll=U, n_workgroups=n_workgroups)

@@ -2,14 +2,15 @@
 //
 // Every matrix is in blocked-JDS storage (its own slice height C_m) inside
 // shared arrays.  The host cuts all matrices into tiles of R consecutive
-// permuted rows, sorts the tiles longest first (the order in which a greedy
-// scheduler balances best: the short tiles at the end fill the gaps) and
-// writes a tile table.  A grid sized to the GPU walks the table with a fixed
-// wavefront stride: no atomics, no queue to reset, so the result does not
-// depend on timing and the launch can be captured in a HIP graph and replayed.
-// This is the paper's static-versus-dynamic scheduling question (Section 5)
-// answered for a GPU: the balance comes from the longest-first order, the
-// determinism from the fixed assignment.
+// permuted rows and writes a tile table: matrices largest first, each
+// matrix's tiles together and in row order.  A grid sized to the GPU walks
+// the table: each XCD takes one contiguous eighth of it and its wavefronts
+// step through that range with a fixed stride.  No atomics, no queue to
+// reset, so the result does not depend on timing and the launch can be
+// captured in a HIP graph and replayed.  This is the paper's
+// static-versus-dynamic scheduling question (Section 5) answered for a GPU:
+// static assignment, as the paper found best, with locality (one matrix's x
+// per L2 at a time) taking the place of first-touch page placement.
 #include <algorithm>
 #include <numeric>
 #include <vector>
@@ -74,9 +75,17 @@ __global__ __launch_bounds__(B_THREADS) void batched_kernel(int64_t n_tiles, con
                                                             const float *__restrict__ val,
                                                             const float *__restrict__ x, float *__restrict__ y)
 {
+    // Workgroups are dealt to the 8 XCDs round-robin (the host launches a
+    // multiple of 8).  Each XCD owns one contiguous eighth of the tile table, so
+    // its L2 holds the x of the one or two matrices it is working on; inside
+    // that range its wavefronts take tiles with a fixed stride.
+    constexpr int NX = 8;
     const int w = (int)threadIdx.x / WAVE, lane = lane_id();
-    const int64_t stride = (int64_t)gridDim.x * B_WAVES;
-    for (int64_t t = (int64_t)blockIdx.x * B_WAVES + w; t < n_tiles; t += stride) {
+    const int xcd = (int)(blockIdx.x % NX);
+    const int64_t local = blockIdx.x / NX;
+    const int64_t waves_per_xcd = (int64_t)(gridDim.x / NX) * B_WAVES;
+    const int64_t t_begin = n_tiles * xcd / NX, t_end = n_tiles * (xcd + 1) / NX;
+    for (int64_t t = t_begin + local * B_WAVES + w; t < t_end; t += waves_per_xcd) {
         const BTile T = tiles[t];
         const int R = 1 << T.rlog, G = WAVE >> T.rlog;
         const int rl = lane & (R - 1), kk = lane >> T.rlog;
@@ -119,10 +128,21 @@ spmv_status spmv_batched_plan(int32_t n_mat, const int32_t *h_n_rows, const int3
                  "spmv_batched_plan: null descriptor");
     int rlog = 0;
     while ((1 << rlog) < rows_per_wave) ++rlog;
-    std::vector<BTile> tiles;
+    // matrices ordered by stored slots, largest first (stable); each matrix's
+    // tiles stay together in row order so that the wavefronts working at one
+    // time share that matrix's x in L2
+    std::vector<int64_t> work(n_mat, 0);
     for (int32_t m = 0; m < n_mat; ++m) {
         const int32_t n = h_n_rows[m], C = h_C[m];
         SPMV_REQUIRE(n >= 0 && C > 0 && C % 64 == 0, "spmv_batched_plan: bad n_rows or C");
+        for (int64_t s = 0; s < ceil_div(n, C); ++s) work[m] += (int64_t)h_slice_nd[h_slice_base[m] + s] * C;
+    }
+    std::vector<int32_t> order(n_mat);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+    std::vector<BTile> tiles;
+    for (int32_t m : order) {
+        const int32_t n = h_n_rows[m], C = h_C[m];
         const int64_t ns = ceil_div(n, C);
         for (int64_t s = 0; s < ns; ++s) {
             const int64_t sp = h_slice_ptr[h_slice_base[m] + s];
@@ -143,8 +163,6 @@ spmv_status spmv_batched_plan(int32_t n_mat, const int32_t *h_n_rows, const int3
             }
         }
     }
-    // longest first; ties keep matrix / row order (stable)
-    std::stable_sort(tiles.begin(), tiles.end(), [](const BTile &a, const BTile &b) { return a.nd > b.nd; });
     *h_n_tiles = (int64_t)tiles.size();
     const int64_t words = (int64_t)tiles.size() * SPMV_BATCHED_PLAN_WORDS;
     if (!plan || plan_cap < words) return fail(SPMV_ERR_CAPACITY, "spmv_batched_plan: plan capacity too small");
@@ -170,8 +188,11 @@ spmv_status spmv_batched(int64_t n_tiles, const int32_t *plan, const int32_t *pe
         SPMV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         n_workgroups = cus * 8;
     }
+    // a multiple of 8 workgroups: every XCD gets the same number
     const int64_t need = ceil_div(n_tiles, B_WAVES);
-    const unsigned grid = (unsigned)std::min<int64_t>(n_workgroups, need);
+    int64_t g = std::min<int64_t>(n_workgroups, need);
+    g = std::max<int64_t>(8, g / 8 * 8);
+    const unsigned grid = (unsigned)g;
     const BTile *tiles = reinterpret_cast<const BTile *>(plan);
     hipStream_t s = as_stream(stream);
     switch (unroll) {

@@ -35,6 +35,17 @@ spmv_status hip_fail(hipError_t e, const char *what);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Column-major multi-vector kernels (crs.hip, jds.hip), the no-workspace path
+// of spmm_crs / spmm_jds (spmm.hip).
+spmv_status spmm_crs_colmajor(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
+                              const void *val, spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y,
+                              int64_t ldy, spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan,
+                              int32_t n_blocks, hipStream_t s);
+spmv_status spmm_jds_colmajor(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag,
+                              const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt, int32_t k, const void *X,
+                              int64_t ldx, void *Y, int64_t ldy, spmv_dtype vec_dt, double alpha, double beta,
+                              unsigned flags, hipStream_t s);
+
 inline size_t dtype_size(spmv_dtype dt)
 {
     return dt == SPMV_F64 ? 8 : dt == SPMV_F32 ? 4 : 2;

@@ -361,20 +361,18 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
     return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs: dtype combination");
 }
 
-spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
-                     spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
-                     spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan, int32_t n_blocks,
-                     int32_t block_nnz, void *stream)
+}  // extern "C"
+
+// Multi-vector CRS straight from the column-major X (no workspace); called by
+// spmm_crs, which validated the arguments.
+spmv_status spmv::spmm_crs_colmajor(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
+                                    const void *val, spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx,
+                                    void *Y, int64_t ldy, spmv_dtype vec_dt, double alpha, double beta,
+                                    const int32_t *plan, int32_t n_blocks, hipStream_t s)
 {
-    (void)block_nnz;
-    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && k >= 0, "spmm_crs: negative size");
-    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmm_crs: bad dtype");
-    if (n_rows == 0 || k == 0) return SPMV_OK;
-    SPMV_REQUIRE(plan && n_blocks >= 0, "spmm_crs: needs a plan from spmv_crs_plan");
-    SPMV_REQUIRE(ldx >= n_cols && ldy >= n_rows, "spmm_crs: leading dimension too small");
-    SPMV_REQUIRE(row_ptr && Y, "spmm_crs: null row_ptr or Y");
+    (void)n_rows;
+    (void)n_cols;
     if (n_blocks == 0) return SPMV_OK;
-    hipStream_t s = as_stream(stream);
 #define SPMM_CASE(VDT, VT, XDT, XT)           \
     if (val_dt == VDT && vec_dt == XDT)       \
         return launch_spmm_crs<VT, XT>(row_ptr, col_idx, val, k, X, ldx, Y, ldy, alpha, beta, plan, n_blocks, s);
@@ -387,5 +385,3 @@ spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
 #undef SPMM_CASE
     return fail(SPMV_ERR_UNSUPPORTED, "spmm_crs: dtype combination");
 }
-
-}  // extern "C"

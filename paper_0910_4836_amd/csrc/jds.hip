@@ -60,6 +60,8 @@ struct JdsArgs {
     int32_t k;
     double alpha, beta;
     int symperm;
+    const void *g;          // value gradient: dL/dy
+    void *dval;             // value gradient output (JDS order)
 };
 
 enum { FMT_JDS = 0, FMT_BLOCKED = 1 };
@@ -159,12 +161,19 @@ __device__ __forceinline__ T reduce_over_kk(T v, int rlog)
     return v;
 }
 
-template <int FMT, int U, typename VT, typename XT>
-__global__ __launch_bounds__(JDS_THREADS) void jds_kernel(JdsArgs a, JdsPlan P)
-{
-    __shared__ double part[JDS_WAVES][WAVE];
-    constexpr bool F64 = IsF64<VT>::value;
+// What one wavefront does: R rows starting at row0 (lane = rl + R*kk owns row
+// row0 + rl and every G-th diagonal from dA + kk), diagonals [dA, dB) of
+// part p of S.
+struct WaveTask {
+    bool valid, row_ok, bounded, wide;
+    int32_t row0, r, dA, dB;
+    int w, rl, kk, G, S, p, rlog;
+};
 
+template <int FMT>
+__device__ __forceinline__ WaveTask wave_task(const JdsArgs &a, const JdsPlan &P, bool reduced_values)
+{
+    WaveTask t;
     // No XCD remap here: the long-row classes come first and the hardware's
     // round-robin spreads them over all XCDs.
     const int64_t wg = blockIdx.x;
@@ -172,39 +181,60 @@ __global__ __launch_bounds__(JDS_THREADS) void jds_kernel(JdsArgs a, JdsPlan P)
     while (ci < P.ncls - 1 && wg >= P.c[ci].wg_end) ++ci;
     const JdsClass K = P.c[ci];
     const int64_t wg0 = ci ? P.c[ci - 1].wg_end : 0;
-    const int w = (int)threadIdx.x / WAVE, lane = lane_id();
-    const int S = 1 << K.slog, R = 1 << K.rlog, G = WAVE >> K.rlog;
-    const int64_t slot = (wg - wg0) * JDS_WAVES + w;
+    t.w = (int)threadIdx.x / WAVE;
+    const int lane = lane_id();
+    t.rlog = K.rlog;
+    t.S = 1 << K.slog;
+    const int R = 1 << K.rlog;
+    t.G = WAVE >> K.rlog;
+    const int64_t slot = (wg - wg0) * JDS_WAVES + t.w;
     const int64_t grp = slot >> K.slog;
-    const int p = (int)(slot & (S - 1));
+    t.p = (int)(slot & (t.S - 1));
     const int64_t row0l = (int64_t)K.row_start + grp * R;
-    const bool valid = row0l < K.row_end;
-    const int32_t row0 = valid ? (int32_t)row0l : K.row_start;
-    const int rl = lane & (R - 1), kk = lane >> K.rlog;
-    const int32_t r = row0 + rl;
-    const bool row_ok = valid && r < K.row_end;
+    t.valid = row0l < K.row_end;
+    t.row0 = t.valid ? (int32_t)row0l : K.row_start;
+    t.rl = lane & (R - 1);
+    t.kk = lane >> K.rlog;
+    t.r = t.row0 + t.rl;
+    t.row_ok = t.valid && t.r < K.row_end;
 
     // length of the group's first (longest) row: only split groups need it
     int32_t Lmax = 0;
-    bool wide = false;
-    if (valid) {
+    t.wide = false;
+    if (t.valid) {
         if (FMT == FMT_JDS) {
-            if (S > 1) Lmax = jds_row_len(a.jd_ptr, a.ndiag, row0);
-            if (!F64) wide = a.ndiag > SPMV_WIDE_ROW_NNZ &&
-                             a.jd_ptr[SPMV_WIDE_ROW_NNZ + 1] - a.jd_ptr[SPMV_WIDE_ROW_NNZ] > row0;
+            if (t.S > 1) Lmax = jds_row_len(a.jd_ptr, a.ndiag, t.row0);
+            if (reduced_values)
+                t.wide = a.ndiag > SPMV_WIDE_ROW_NNZ &&
+                         a.jd_ptr[SPMV_WIDE_ROW_NNZ + 1] - a.jd_ptr[SPMV_WIDE_ROW_NNZ] > t.row0;
         } else {
-            Lmax = a.slice_nd[row0 / a.C];
-            if (!F64) wide = Lmax > SPMV_WIDE_ROW_NNZ;
+            Lmax = a.slice_nd[t.row0 / a.C];
+            if (reduced_values) t.wide = Lmax > SPMV_WIDE_ROW_NNZ;
         }
     }
-    int32_t dA = 0, dB = (FMT == FMT_JDS) ? a.ndiag : Lmax;
-    if (S > 1) {
-        const int32_t per = (int32_t)((((int64_t)Lmax + (int64_t)S * G - 1) / ((int64_t)S * G)) * G);
-        dA = p * per;
-        dB = dA + per < Lmax ? dA + per : Lmax;
-        if (dA > dB) dA = dB;
+    t.dA = 0;
+    t.dB = (FMT == FMT_JDS) ? a.ndiag : Lmax;
+    if (t.S > 1) {
+        const int64_t SG = (int64_t)t.S * t.G;
+        const int32_t per = (int32_t)(((int64_t)Lmax + SG - 1) / SG * t.G);
+        t.dA = t.p * per;
+        t.dB = t.dA + per < Lmax ? t.dA + per : Lmax;
+        if (t.dA > t.dB) t.dA = t.dB;
     }
-    const bool bounded = (FMT == FMT_BLOCKED) || S > 1;
+    t.bounded = (FMT == FMT_BLOCKED) || t.S > 1;
+    return t;
+}
+
+template <int FMT, int U, typename VT, typename XT>
+__global__ __launch_bounds__(JDS_THREADS) void jds_kernel(JdsArgs a, JdsPlan P)
+{
+    __shared__ double part[JDS_WAVES][WAVE];
+    constexpr bool F64 = IsF64<VT>::value;
+    const WaveTask t = wave_task<FMT>(a, P, !F64);
+    const bool valid = t.valid, row_ok = t.row_ok, wide = t.wide, bounded = t.bounded;
+    const int32_t row0 = t.row0, r = t.r, dA = t.dA, dB = t.dB;
+    const int w = t.w, rl = t.rl, kk = t.kk, G = t.G, S = t.S, p = t.p;
+    const JdsClass K{0, 0, 0, t.rlog, 0};
 
     double td = 0.0;
     if (valid) {
@@ -273,37 +303,46 @@ __global__ __launch_bounds__(256) void spmm_jds_kernel(JdsArgs a)
         if (j < kb) write_y(Y + (int64_t)j * a.ldy, yi, (double)acc[j], a.alpha, a.beta);
 }
 
-// Value gradient in JDS storage order: dval[e] = alpha*g[row]*x[col[e]] + beta*dval[e].
-constexpr int GRAD_THREADS = 256;
-constexpr int GRAD_PER_THREAD = 8;
-
-template <typename T>
-__global__ __launch_bounds__(GRAD_THREADS) void grad_vals_jds_kernel(int64_t nnz, int32_t ndiag,
-                                                                     const int32_t *__restrict__ jp,
-                                                                     const int32_t *__restrict__ perm,
-                                                                     const int32_t *__restrict__ col,
-                                                                     const T *__restrict__ g,
-                                                                     const T *__restrict__ x, T *__restrict__ dval,
-                                                                     double alpha, double beta, int symperm)
+// Value gradient in JDS storage order: dval[e] = alpha*g[row]*x[col[e]] +
+// beta*dval[e], computed in FP64 and rounded once.  Same wavefront layout as
+// the product (each lane walks its row's diagonals; writes of consecutive lanes
+// are consecutive), with no reduction: every entry is its own output.
+template <int U, typename T>
+__global__ __launch_bounds__(JDS_THREADS) void jds_grad_kernel(JdsArgs a, JdsPlan P)
 {
-    const int64_t tile = (int64_t)blockIdx.x * GRAD_THREADS * GRAD_PER_THREAD;
-    // diagonal holding the tile's first entry (uniform binary search)
-    int32_t lo = 0, hi = ndiag - 1;
-    while (lo < hi) {
-        int32_t mid = (lo + hi + 1) >> 1;
-        if (jp[mid] <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    int32_t d = lo;
-    for (int t = 0; t < GRAD_PER_THREAD; ++t) {
-        const int64_t e = tile + (int64_t)t * GRAD_THREADS + threadIdx.x;
-        if (e >= nnz) break;
-        while (jp[d + 1] <= e) ++d;
-        const int32_t r = (int32_t)(e - jp[d]);
-        const int32_t row = symperm ? r : perm[r];
-        double v = alpha * (to_f64(g[row]) * to_f64(x[col[e]]));
-        if (beta != 0.0) v = fma(beta, to_f64(dval[e]), v);
-        store_from_f64(&dval[e], v);
+    const WaveTask t = wave_task<FMT_JDS>(a, P, false);
+    if (!t.row_ok) return;
+    const int32_t *__restrict__ jp = a.jd_ptr;
+    const int32_t *__restrict__ col = a.col;
+    const T *__restrict__ x = (const T *)a.x;
+    T *__restrict__ dval = (T *)a.dval;
+    const int32_t row = a.symperm ? t.r : a.perm[t.r];
+    const double gv = a.alpha * to_f64(((const T *)a.g)[row]);
+    for (int32_t base = t.dA; base < t.dB; base += t.G * U) {
+        if (!t.bounded && jp[base + 1] - jp[base] <= t.row0) break;
+        int32_t c[U];
+        int64_t e[U];
+        bool act[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t dd = base + t.kk + u * t.G;
+            act[u] = false;
+            if (dd < t.dB) {
+                const int32_t off = jp[dd];
+                if (t.r < jp[dd + 1] - off) {
+                    act[u] = true;
+                    e[u] = (int64_t)off + t.r;
+                    c[u] = ld_stream(col + e[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!act[u]) continue;
+            double v = gv * to_f64(x[c[u]]);
+            if (a.beta != 0.0) v = fma(a.beta, to_f64(dval[e[u]]), v);
+            store_from_f64(&dval[e[u]], v);
+        }
     }
 }
 
@@ -514,20 +553,15 @@ spmv_status spmv_jds_blocked(int32_t n, const int32_t *perm, int32_t C, int32_t 
     return launch_jds<FMT_BLOCKED>(a, P, unroll ? unroll : 4, val_dt, vec_dt, as_stream(stream));
 }
 
-spmv_status spmm_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr, int32_t ndiag,
-                     const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt, int32_t k, const void *X,
-                     int64_t ldx, void *Y, int64_t ldy, spmv_dtype vec_dt, double alpha, double beta,
-                     unsigned flags, void *stream)
+}  // extern "C"
+
+// Multi-vector JDS straight from the column-major X (no workspace); called by
+// spmm_jds, which validated the arguments.
+spmv_status spmv::spmm_jds_colmajor(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag,
+                                    const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt, int32_t k,
+                                    const void *X, int64_t ldx, void *Y, int64_t ldy, spmv_dtype vec_dt,
+                                    double alpha, double beta, unsigned flags, hipStream_t s)
 {
-    (void)h_jd_ptr;
-    SPMV_REQUIRE(n >= 0 && ndiag >= 0 && k >= 0, "spmm_jds: negative size");
-    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmm_jds: bad dtype");
-    SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmm_jds: unknown flag");
-    if (n == 0 || k == 0) return SPMV_OK;
-    SPMV_REQUIRE(ldy >= n, "spmm_jds: ldy < n");
-    SPMV_REQUIRE(Y && jd_ptr, "spmm_jds: null Y or jd_ptr");
-    SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmm_jds: null perm");
-    SPMV_REQUIRE(ndiag == 0 || (jd_col && jd_val && X), "spmm_jds: null input");
     JdsArgs a{};
     a.n = n;
     a.perm = perm;
@@ -545,7 +579,6 @@ spmv_status spmm_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, cons
     a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
     constexpr int KB = 8;
     dim3 grid((unsigned)ceil_div(n, 256), (unsigned)ceil_div(k, KB));
-    hipStream_t s = as_stream(stream);
 #define SPMM_CASE(VDT, VT, XDT, XT)                                           \
     if (val_dt == VDT && vec_dt == XDT) {                                     \
         spmm_jds_kernel<KB, VT, XT><<<grid, 256, 0, s>>>(a);                  \
@@ -562,25 +595,39 @@ spmv_status spmm_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, cons
     return fail(SPMV_ERR_UNSUPPORTED, "spmm_jds: dtype combination");
 }
 
-spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag, int64_t nnz,
-                               const int32_t *jd_col, const void *g, const void *x, void *dval, spmv_dtype dt,
-                               double alpha, double beta, unsigned flags, void *stream)
+extern "C" {
+
+spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr,
+                               int32_t ndiag, int64_t nnz, const int32_t *jd_col, const void *g, const void *x,
+                               void *dval, spmv_dtype dt, double alpha, double beta, unsigned flags, void *stream)
 {
     SPMV_REQUIRE(n >= 0 && ndiag >= 0 && nnz >= 0, "spmv_grad_vals_jds: negative size");
     SPMV_REQUIRE(valid_vec_dtype(dt), "spmv_grad_vals_jds: dtype must be F64 or F32");
     SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_grad_vals_jds: unknown flag");
     if (nnz == 0) return SPMV_OK;
-    SPMV_REQUIRE(ndiag > 0 && jd_ptr && jd_col && g && x && dval, "spmv_grad_vals_jds: null pointer");
+    SPMV_REQUIRE(ndiag > 0 && jd_ptr && h_jd_ptr && jd_col && g && x && dval, "spmv_grad_vals_jds: null pointer");
     SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmv_grad_vals_jds: null perm");
-    int64_t grid = ceil_div(nnz, (int64_t)GRAD_THREADS * GRAD_PER_THREAD);
+    SPMV_REQUIRE(h_jd_ptr[0] == 0 && (int64_t)h_jd_ptr[ndiag] == nnz, "spmv_grad_vals_jds: nnz != jd_ptr[ndiag]");
+    JdsArgs a{};
+    a.n = n;
+    a.perm = perm;
+    a.jd_ptr = jd_ptr;
+    a.ndiag = ndiag;
+    a.col = jd_col;
+    a.x = x;
+    a.g = g;
+    a.dval = dval;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
+    const JdsPlan P = plan_jds(n, h_jd_ptr, ndiag, JDS_DEFAULT_MAX_ITERS, -1);
+    if (P.ncls == 0) return SPMV_OK;
+    const unsigned grid = (unsigned)P.c[P.ncls - 1].wg_end;
     hipStream_t s = as_stream(stream);
-    int sym = (flags & SPMV_SYMPERM) ? 1 : 0;
     if (dt == SPMV_F64)
-        grad_vals_jds_kernel<double><<<(unsigned)grid, GRAD_THREADS, 0, s>>>(
-            nnz, ndiag, jd_ptr, perm, jd_col, (const double *)g, (const double *)x, (double *)dval, alpha, beta, sym);
+        jds_grad_kernel<4, double><<<grid, JDS_THREADS, 0, s>>>(a, P);
     else
-        grad_vals_jds_kernel<float><<<(unsigned)grid, GRAD_THREADS, 0, s>>>(
-            nnz, ndiag, jd_ptr, perm, jd_col, (const float *)g, (const float *)x, (float *)dval, alpha, beta, sym);
+        jds_grad_kernel<4, float><<<grid, JDS_THREADS, 0, s>>>(a, P);
     SPMV_CHECK_LAUNCH("spmv_grad_vals_jds");
     return SPMV_OK;
 }

@@ -1,0 +1,405 @@
+// Multi-vector products Y = alpha*A X + beta*Y, X and Y column-major (k columns).
+//
+// A column-major X makes every stored entry gather k separate 8-byte values
+// from k far-apart columns: k L2 lines per entry.  With a workspace the
+// library first copies X into an interleaved (row-major) block Xr, one
+// transposing pass at streaming speed, and then every entry gathers its k
+// values as one contiguous run of k*8 bytes.  Each row is handled by a group
+// of K2 lanes (K2 = k rounded up to a power of two, at most 64), lane j owning
+// column j: val/col are read once per entry for all k columns and the loads of
+// a group are contiguous.  Long rows get several groups whose partial sums
+// meet in LDS and are added in a fixed order.  Y is written column-major
+// directly.
+//
+// Without a workspace the column-major kernels of crs.hip / jds.hip run.
+#include <vector>
+
+#include "common.hpp"
+
+namespace spmv {
+
+constexpr int MM_THREADS = 256;
+constexpr int MM_MAX_K2 = 64;
+
+// Xr[c*k + j] = X[c + j*ldx]: 64 x 64 tiles through LDS, coalesced both ways.
+template <typename T>
+__global__ __launch_bounds__(256) void stage_rowmajor_kernel(int64_t n, int32_t k, const T *__restrict__ X, int64_t ldx,
+                                                             T *__restrict__ Xr)
+{
+    __shared__ T tile[64][65];
+    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 64;
+    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+    for (int jj = ty; jj < 64; jj += 4) {
+        const int j = j0 + jj;
+        const int64_t c = c0 + tx;
+        if (j < k && c < n) tile[jj][tx] = X[c + (int64_t)j * ldx];
+    }
+    __syncthreads();
+    for (int cc = ty; cc < 64; cc += 4) {
+        const int64_t c = c0 + cc;
+        const int j = j0 + tx;
+        if (j < k && c < n) Xr[c * k + j] = tile[tx][cc];
+    }
+}
+
+// One group of K2 lanes per (row, part): lane j accumulates column j.
+template <int K2, bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ typename Acc<WIDE>::T mm_group_sum(const int32_t *__restrict__ col,
+                                                              const VT *__restrict__ val,
+                                                              const XT *__restrict__ Xr, int32_t k, int j,
+                                                              int64_t e_begin, int64_t e_end, int64_t e_step)
+{
+    typedef typename Acc<WIDE>::T acc_t;
+    acc_t s = 0;
+    const bool jok = j < k;
+    constexpr int U = 4;
+    int64_t e = e_begin;
+    for (; e + (U - 1) * e_step < e_end; e += U * e_step) {
+        int32_t c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = col[e + u * e_step];
+            v[u] = val[e + u * e_step];
+        }
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = jok ? Xr[(int64_t)c[u] * k + j] : XT(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) s = Acc<WIDE>::mac(s, v[u], xv[u]);
+    }
+    for (; e < e_end; e += e_step) {
+        const int32_t c = col[e];
+        const XT xv = jok ? Xr[(int64_t)c * k + j] : XT(0);
+        s = Acc<WIDE>::mac(s, val[e], xv);
+    }
+    return s;
+}
+
+// CRS, interleaved X.  One workgroup per plan block of nr rows: GPR groups
+// per row (GPR = largest power of two <= NG/nr), the row's entries dealt to
+// its groups with stride GPR; the GPR partials are added in group order.
+template <int K2, typename VT, typename XT>
+__global__ __launch_bounds__(MM_THREADS) void spmm_crs_il_kernel(const int32_t *__restrict__ row_ptr,
+                                                                 const int32_t *__restrict__ col,
+                                                                 const VT *__restrict__ val,
+                                                                 const XT *__restrict__ Xr, int32_t k,
+                                                                 XT *__restrict__ Y, int64_t ldy,
+                                                                 const int32_t *__restrict__ plan, double alpha,
+                                                                 double beta)
+{
+    constexpr int NG = MM_THREADS / K2;
+    constexpr bool F64 = IsF64<VT>::value;
+    __shared__ double part[NG][K2];
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t r0 = plan[b], r1 = plan[b + 1];
+    const int32_t nr = r1 - r0;
+    const int g = (int)threadIdx.x / K2, j = (int)threadIdx.x % K2;
+    int GPR = 1;
+    while (GPR * 2 * nr <= NG) GPR *= 2;
+    const int sub = g % GPR;
+    const int rows_per_round = NG / GPR;
+    const bool wide = !F64 && nr == 1 && row_ptr[r1] - row_ptr[r0] > SPMV_WIDE_ROW_NNZ;
+    for (int32_t rbase = r0; rbase < r1; rbase += rows_per_round) {
+        const int32_t row = rbase + g / GPR;
+        double td = 0.0;
+        if (row < r1) {
+            const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+            if (F64 || wide) td = mm_group_sum<K2, true, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR);
+            else td = (double)mm_group_sum<K2, false, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR);
+        }
+        if (GPR > 1) {
+            part[g][j] = td;
+            __syncthreads();
+            if (sub == 0 && row < r1) {
+                if (F64 || wide) {
+                    double t = 0.0;
+                    for (int q = 0; q < GPR; ++q) t += part[g + q][j];
+                    td = t;
+                } else {
+                    float t = 0.0f;
+                    for (int q = 0; q < GPR; ++q) t += (float)part[g + q][j];
+                    td = (double)t;
+                }
+            }
+            __syncthreads();
+        }
+        if (sub == 0 && row < r1 && j < k) write_y(Y + (int64_t)j * ldy, row, td, alpha, beta);
+    }
+}
+
+// JDS, interleaved X.  The host splits the permuted rows (longest first) into
+// classes with GPR groups per row (enough that each group handles at most
+// about 32 of the row's diagonals); a workgroup holds NG/GPR rows of a class.
+struct MmClass {
+    int32_t wg_end, row_start, row_end, gpr;
+};
+struct MmPlan {
+    MmClass c[8];
+    int32_t ncls;
+};
+
+template <int K2, typename VT, typename XT>
+__global__ __launch_bounds__(MM_THREADS) void spmm_jds_il_kernel(int32_t ndiag, const int32_t *__restrict__ jp,
+                                                                 const int32_t *__restrict__ perm, int symperm,
+                                                                 const int32_t *__restrict__ col,
+                                                                 const VT *__restrict__ val,
+                                                                 const XT *__restrict__ Xr, int32_t k,
+                                                                 XT *__restrict__ Y, int64_t ldy, MmPlan P,
+                                                                 double alpha, double beta)
+{
+    constexpr int NG = MM_THREADS / K2;
+    constexpr bool F64 = IsF64<VT>::value;
+    __shared__ double part[NG][K2];
+    const int64_t wg = blockIdx.x;
+    int ci = 0;
+    while (ci < P.ncls - 1 && wg >= P.c[ci].wg_end) ++ci;
+    const MmClass K = P.c[ci];
+    const int64_t wg0 = ci ? P.c[ci - 1].wg_end : 0;
+    const int GPR = K.gpr;
+    const int g = (int)threadIdx.x / K2, j = (int)threadIdx.x % K2;
+    const int sub = g % GPR;
+    const int64_t row64 = (int64_t)K.row_start + (wg - wg0) * (NG / GPR) + g / GPR;
+    const bool ok = row64 < K.row_end;
+    const int32_t r = (int32_t)(ok ? row64 : 0);
+    // the row's length: first diagonal too short to reach it
+    int32_t len = 0;
+    if (ok) {
+        int32_t lo = 0, hi = ndiag;
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (jp[mid + 1] - jp[mid] > r) lo = mid + 1;
+            else hi = mid;
+        }
+        len = lo;
+    }
+    const bool wide = !F64 && len > SPMV_WIDE_ROW_NNZ;
+    double td = 0.0;
+    if (ok) {
+        typedef double accd;
+        const bool jok = j < k;
+        if (F64 || wide) {
+            accd s = 0.0;
+            for (int32_t d = sub; d < len; d += GPR) {
+                const int64_t e = (int64_t)jp[d] + r;
+                const XT xv = jok ? Xr[(int64_t)col[e] * k + j] : XT(0);
+                s = Acc<true>::mac(s, val[e], xv);
+            }
+            td = s;
+        } else {
+            float s = 0.0f;
+            for (int32_t d = sub; d < len; d += GPR) {
+                const int64_t e = (int64_t)jp[d] + r;
+                const XT xv = jok ? Xr[(int64_t)col[e] * k + j] : XT(0);
+                s = Acc<false>::mac(s, val[e], xv);
+            }
+            td = (double)s;
+        }
+    }
+    if (GPR > 1) {
+        part[g][j] = td;
+        __syncthreads();
+        if (sub == 0 && ok) {
+            if (F64 || wide) {
+                double t = 0.0;
+                for (int q = 0; q < GPR; ++q) t += part[g + q][j];
+                td = t;
+            } else {
+                float t = 0.0f;
+                for (int q = 0; q < GPR; ++q) t += (float)part[g + q][j];
+                td = (double)t;
+            }
+        }
+    }
+    if (sub == 0 && ok && j < k) write_y(Y + (int64_t)j * ldy, symperm ? r : perm[r], td, alpha, beta);
+}
+
+static int k2_for(int32_t k)
+{
+    int K2 = 1;
+    while (K2 < k && K2 < MM_MAX_K2) K2 *= 2;
+    return K2;
+}
+
+static MmPlan plan_mm_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int NG)
+{
+    constexpr int64_t LT = 32;   // target diagonals per group
+    MmPlan P{};
+    auto len_of = [&](int64_t row) -> int64_t {
+        int32_t lo = 0, hi = ndiag;
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (h_jd_ptr[mid + 1] - h_jd_ptr[mid] > row) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    auto gpr_of = [&](int64_t L) {
+        int gpr = 1;
+        while (gpr < NG && gpr * LT < L) gpr *= 2;
+        return gpr;
+    };
+    int64_t row = 0, wgs = 0;
+    int cls = 0;
+    while (row < n && cls < 8) {
+        const int gpr = gpr_of(len_of(row));
+        int64_t end = n;
+        if (cls < 7 && gpr > 1) {
+            // rows needing this many groups: length > (gpr/2)*LT; lengths never increase
+            const int64_t lower = (int64_t)(gpr / 2) * LT;
+            int64_t lo = row + 1, hi = n;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (len_of(mid) > lower) lo = mid + 1;
+                else hi = mid;
+            }
+            end = lo;
+        }
+        MmClass &K = P.c[cls++];
+        K.row_start = (int32_t)row;
+        K.row_end = (int32_t)end;
+        K.gpr = gpr;
+        wgs += ceil_div(end - row, NG / gpr);
+        K.wg_end = (int32_t)wgs;
+        row = end;
+    }
+    P.ncls = cls;
+    return P;
+}
+
+template <typename T>
+static spmv_status stage(int64_t n, int32_t k, const void *X, int64_t ldx, void *Xr, hipStream_t s)
+{
+    dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(k, 64));
+    stage_rowmajor_kernel<T><<<grid, 256, 0, s>>>(n, k, (const T *)X, ldx, (T *)Xr);
+    SPMV_CHECK_LAUNCH("spmm staging");
+    return SPMV_OK;
+}
+
+template <int K2, typename VT, typename XT>
+static void launch_crs_il(const int32_t *row_ptr, const int32_t *col, const void *val, const void *Xr, int32_t k,
+                          void *Y, int64_t ldy, const int32_t *plan, int32_t nb, double alpha, double beta,
+                          hipStream_t s)
+{
+    spmm_crs_il_kernel<K2, VT, XT><<<nb, MM_THREADS, 0, s>>>(row_ptr, col, (const VT *)val, (const XT *)Xr, k,
+                                                            (XT *)Y, ldy, plan, alpha, beta);
+}
+
+template <int K2, typename VT, typename XT>
+static void launch_jds_il(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, const int32_t *jp, const int32_t *perm,
+                          int symperm, const int32_t *col, const void *val, const void *Xr, int32_t k, void *Y,
+                          int64_t ldy, double alpha, double beta, hipStream_t s)
+{
+    const MmPlan P = plan_mm_jds(n, h_jd_ptr, ndiag, MM_THREADS / K2);
+    if (P.ncls == 0) return;
+    spmm_jds_il_kernel<K2, VT, XT><<<(unsigned)P.c[P.ncls - 1].wg_end, MM_THREADS, 0, s>>>(
+        ndiag, jp, perm, symperm, col, (const VT *)val, (const XT *)Xr, k, (XT *)Y, ldy, P, alpha, beta);
+}
+
+#define K2_SWITCH(K2VAR, CALL)          \
+    switch (K2VAR) {                    \
+    case 1: { constexpr int K2 = 1; CALL; } break;   \
+    case 2: { constexpr int K2 = 2; CALL; } break;   \
+    case 4: { constexpr int K2 = 4; CALL; } break;   \
+    case 8: { constexpr int K2 = 8; CALL; } break;   \
+    case 16: { constexpr int K2 = 16; CALL; } break; \
+    case 32: { constexpr int K2 = 32; CALL; } break; \
+    default: { constexpr int K2 = 64; CALL; } break; \
+    }
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" {
+
+size_t spmm_workspace_size(int32_t n_cols, int32_t k, spmv_dtype vec_dt)
+{
+    if (n_cols < 0 || k < 0) return 0;
+    return align_up((size_t)n_cols * (size_t)k * dtype_size(vec_dt), 256) + 256;
+}
+
+spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                     spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                     spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan, int32_t n_blocks,
+                     int32_t block_nnz, void *ws, size_t ws_bytes, void *stream)
+{
+    (void)block_nnz;
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && k >= 0, "spmm_crs: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmm_crs: bad dtype");
+    if (n_rows == 0 || k == 0) return SPMV_OK;
+    SPMV_REQUIRE(plan && n_blocks >= 0, "spmm_crs: needs a plan from spmv_crs_plan");
+    SPMV_REQUIRE(ldx >= n_cols && ldy >= n_rows, "spmm_crs: leading dimension too small");
+    SPMV_REQUIRE(row_ptr && Y, "spmm_crs: null row_ptr or Y");
+    hipStream_t s = as_stream(stream);
+    if (!ws || k > MM_MAX_K2)
+        return spmm_crs_colmajor(n_rows, n_cols, row_ptr, col_idx, val, val_dt, k, X, ldx, Y, ldy, vec_dt, alpha,
+                                 beta, plan, n_blocks, s);
+    SPMV_REQUIRE(ws_bytes >= spmm_workspace_size(n_cols, k, vec_dt), "spmm_crs: workspace too small");
+    if (n_blocks == 0) return SPMV_OK;
+    if (n_cols > 0) {
+        spmv_status st = vec_dt == SPMV_F64 ? stage<double>(n_cols, k, X, ldx, ws, s)
+                                            : stage<float>(n_cols, k, X, ldx, ws, s);
+        if (st != SPMV_OK) return st;
+    }
+    const int K2v = k2_for(k);
+#define CRS_IL(VDT, VT, XDT, XT)                                                                              \
+    if (val_dt == VDT && vec_dt == XDT) {                                                                     \
+        K2_SWITCH(K2v, (launch_crs_il<K2, VT, XT>(row_ptr, col_idx, val, ws, k, Y, ldy, plan, n_blocks, alpha, \
+                                                  beta, s)));                                                 \
+        SPMV_CHECK_LAUNCH("spmm_crs");                                                                        \
+        return SPMV_OK;                                                                                       \
+    }
+    CRS_IL(SPMV_F64, double, SPMV_F64, double)
+    CRS_IL(SPMV_F32, float, SPMV_F32, float)
+    CRS_IL(SPMV_F32, float, SPMV_F64, double)
+    CRS_IL(SPMV_BF16, bf16, SPMV_F32, float)
+    CRS_IL(SPMV_BF16, bf16, SPMV_F64, double)
+    CRS_IL(SPMV_F64, double, SPMV_F32, float)
+#undef CRS_IL
+    return fail(SPMV_ERR_UNSUPPORTED, "spmm_crs: dtype combination");
+}
+
+spmv_status spmm_jds(int32_t n, int32_t n_cols, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr,
+                     int32_t ndiag, const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt, int32_t k,
+                     const void *X, int64_t ldx, void *Y, int64_t ldy, spmv_dtype vec_dt, double alpha, double beta,
+                     unsigned flags, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && n_cols >= 0 && ndiag >= 0 && k >= 0, "spmm_jds: negative size");
+    SPMV_REQUIRE(ldx >= n_cols, "spmm_jds: ldx < n_cols");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmm_jds: bad dtype");
+    SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmm_jds: unknown flag");
+    if (n == 0 || k == 0) return SPMV_OK;
+    SPMV_REQUIRE(ldy >= n, "spmm_jds: ldy < n");
+    SPMV_REQUIRE(Y && jd_ptr, "spmm_jds: null Y or jd_ptr");
+    SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmm_jds: null perm");
+    SPMV_REQUIRE(ndiag == 0 || (jd_col && jd_val && X), "spmm_jds: null input");
+    hipStream_t s = as_stream(stream);
+    if (!ws || k > MM_MAX_K2)
+        return spmm_jds_colmajor(n, perm, jd_ptr, ndiag, jd_col, jd_val, val_dt, k, X, ldx, Y, ldy, vec_dt, alpha,
+                                 beta, flags, s);
+    SPMV_REQUIRE(h_jd_ptr, "spmm_jds: the interleaved path needs h_jd_ptr");
+    SPMV_REQUIRE(ws_bytes >= spmm_workspace_size(n_cols, k, vec_dt), "spmm_jds: workspace too small");
+    spmv_status st = vec_dt == SPMV_F64 ? stage<double>(n_cols, k, X, ldx, ws, s) : stage<float>(n_cols, k, X, ldx, ws, s);
+    if (st != SPMV_OK) return st;
+    const int K2v = k2_for(k);
+    const int sym = (flags & SPMV_SYMPERM) ? 1 : 0;
+#define JDS_IL(VDT, VT, XDT, XT)                                                                                 \
+    if (val_dt == VDT && vec_dt == XDT) {                                                                        \
+        K2_SWITCH(K2v, (launch_jds_il<K2, VT, XT>(n, h_jd_ptr, ndiag, jd_ptr, perm, sym, jd_col, jd_val, ws, k, Y, \
+                                                  ldy, alpha, beta, s)));                                        \
+        SPMV_CHECK_LAUNCH("spmm_jds");                                                                           \
+        return SPMV_OK;                                                                                          \
+    }
+    JDS_IL(SPMV_F64, double, SPMV_F64, double)
+    JDS_IL(SPMV_F32, float, SPMV_F32, float)
+    JDS_IL(SPMV_F32, float, SPMV_F64, double)
+    JDS_IL(SPMV_BF16, bf16, SPMV_F32, float)
+    JDS_IL(SPMV_BF16, bf16, SPMV_F64, double)
+    JDS_IL(SPMV_F64, double, SPMV_F32, float)
+#undef JDS_IL
+    return fail(SPMV_ERR_UNSUPPORTED, "spmm_jds: dtype combination");
+}
+
+}  // extern "C"

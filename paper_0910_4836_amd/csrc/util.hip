@@ -79,19 +79,79 @@ __global__ __launch_bounds__(DOT_THREADS) void dot_final_kernel(int64_t nparts, 
     }
 }
 
-__global__ void triad_kernel(int64_t n, const double *__restrict__ b, const double *__restrict__ c,
-                             double *__restrict__ a, double s)
+// Bandwidth probes: 16-byte accesses, four independent ones in flight per
+// lane, grid-stride over 16-byte units (the host checks that n is even and
+// the arrays 16-byte aligned).
+constexpr int PROBE_UNROLL = 4;
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__global__ void triad_kernel(int64_t n2, const v2d *__restrict__ b, const v2d *__restrict__ c,
+                             v2d *__restrict__ a, double s)
 {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) __builtin_nontemporal_store(fma(s, c[i], b[i]), a + i);
+    for (; i + (PROBE_UNROLL - 1) * stride < n2; i += PROBE_UNROLL * stride) {
+        v2d bb[PROBE_UNROLL], cc[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) {
+            bb[u] = __builtin_nontemporal_load(b + i + u * stride);
+            cc[u] = __builtin_nontemporal_load(c + i + u * stride);
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) {
+            const v2d r = {fma(s, cc[u].x, bb[u].x), fma(s, cc[u].y, bb[u].y)};
+            __builtin_nontemporal_store(r, a + i + u * stride);
+        }
+    }
+    for (; i < n2; i += stride) {
+        const v2d r = {fma(s, c[i].x, b[i].x), fma(s, c[i].y, b[i].y)};
+        a[i] = r;
+    }
 }
 
-__global__ void copy_kernel(int64_t n, const double *__restrict__ b, double *__restrict__ a)
+__global__ void copy_kernel(int64_t n2, const v2d *__restrict__ b, v2d *__restrict__ a)
 {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) __builtin_nontemporal_store(b[i], a + i);
+    for (; i + (PROBE_UNROLL - 1) * stride < n2; i += PROBE_UNROLL * stride) {
+        v2d bb[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) bb[u] = __builtin_nontemporal_load(b + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) __builtin_nontemporal_store(bb[u], a + i + u * stride);
+    }
+    for (; i < n2; i += stride) a[i] = b[i];
+}
+
+// Read-only probe: per-block partial sums (keeps the loads alive).
+__global__ __launch_bounds__(256) void read_kernel(int64_t n2, const v2d *__restrict__ b,
+                                                   double *__restrict__ part)
+{
+    __shared__ double red[256 / WAVE];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    for (; i + (PROBE_UNROLL - 1) * stride < n2; i += PROBE_UNROLL * stride) {
+        v2d bb[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) bb[u] = __builtin_nontemporal_load(b + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) s += bb[u].x + bb[u].y;
+    }
+    for (; i < n2; i += stride) s += b[i].x + b[i].y;
+    s = group_sum(s, WAVE);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+static int probe_grid()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus * 8;
 }
 
 static int stream_grid(int64_t n, int per_thread)
@@ -101,6 +161,8 @@ static int stream_grid(int64_t n, int per_thread)
     if (blocks < 1) blocks = 1;
     return (int)blocks;
 }
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 }  // namespace spmv
 
@@ -205,8 +267,11 @@ spmv_status spmv_graph_destroy(void *exec)
 spmv_status spmv_stream_triad(int64_t n, const double *b, const double *c, double *a, double s, void *stream)
 {
     SPMV_REQUIRE(n >= 0 && (n == 0 || (a && b && c)), "spmv_stream_triad: bad arguments");
+    SPMV_REQUIRE(n % 2 == 0 && aligned16(a) && aligned16(b) && aligned16(c),
+                 "spmv_stream_triad: n must be even and the arrays 16-byte aligned");
     if (n == 0) return SPMV_OK;
-    triad_kernel<<<stream_grid(n, 8), 256, 0, as_stream(stream)>>>(n, b, c, a, s);
+    triad_kernel<<<probe_grid(), 256, 0, as_stream(stream)>>>(n / 2, (const v2d *)b, (const v2d *)c,
+                                                              (v2d *)a, s);
     SPMV_CHECK_LAUNCH("spmv_stream_triad");
     return SPMV_OK;
 }
@@ -214,9 +279,23 @@ spmv_status spmv_stream_triad(int64_t n, const double *b, const double *c, doubl
 spmv_status spmv_stream_copy(int64_t n, const double *b, double *a, void *stream)
 {
     SPMV_REQUIRE(n >= 0 && (n == 0 || (a && b)), "spmv_stream_copy: bad arguments");
+    SPMV_REQUIRE(n % 2 == 0 && aligned16(a) && aligned16(b),
+                 "spmv_stream_copy: n must be even and the arrays 16-byte aligned");
     if (n == 0) return SPMV_OK;
-    copy_kernel<<<stream_grid(n, 8), 256, 0, as_stream(stream)>>>(n, b, a);
+    copy_kernel<<<probe_grid(), 256, 0, as_stream(stream)>>>(n / 2, (const v2d *)b, (v2d *)a);
     SPMV_CHECK_LAUNCH("spmv_stream_copy");
+    return SPMV_OK;
+}
+
+spmv_status spmv_stream_read(int64_t n, const double *b, double *part, int64_t part_cap, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && (n == 0 || (b && part)), "spmv_stream_read: bad arguments");
+    SPMV_REQUIRE(n % 2 == 0 && aligned16(b), "spmv_stream_read: n must be even and b 16-byte aligned");
+    if (n == 0) return SPMV_OK;
+    const int grid = probe_grid();
+    SPMV_REQUIRE(part_cap >= grid, "spmv_stream_read: part needs one double per workgroup (8 per CU)");
+    read_kernel<<<grid, 256, 0, as_stream(stream)>>>(n / 2, (const v2d *)b, part);
+    SPMV_CHECK_LAUNCH("spmv_stream_read");
     return SPMV_OK;
 }
 

@@ -334,27 +334,40 @@ def _ld(X: torch.Tensor, n: int) -> int:
     return X.stride(1) if X.shape[1] > 1 else n
 
 
-def spmm_crs(A: CSR, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0,
-             beta: float = 0.0) -> torch.Tensor:
+def spmm_workspace(n_cols: int, k: int, dtype, device) -> torch.Tensor:
+    """Workspace for the interleaved multi-vector path (a row-major copy of X)."""
+    return _ws(_lib.load().spmm_workspace_size(n_cols, k, dtype_code(dtype)), device)
+
+
+def spmm_crs(A: CSR, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
+             ws: Optional[torch.Tensor] = None, interleave: bool = True) -> torch.Tensor:
+    """Y = alpha*A X + beta*Y for a column-major block X (spmm_crs)."""
     if A.plan is None:
         spmv_crs_plan(A)
     k = X.shape[1]
     if Y is None:
         Y = colmajor(A.n_rows, k, X.dtype, X.device)
+    if interleave and ws is None:
+        ws = spmm_workspace(A.n_cols, k, X.dtype, X.device)
     call("spmm_crs", A.n_rows, A.n_cols, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), k, _p(X),
          _ld(X, A.n_cols), _p(Y), _ld(Y, A.n_rows), dtype_code(X.dtype), float(alpha), float(beta), _p(A.plan),
-         A.n_blocks, A.block_nnz, _stream())
+         A.n_blocks, A.block_nnz, _p(ws) if interleave else None, ws.numel() if (interleave and ws is not None) else 0,
+         _stream())
     return Y
 
 
-def spmm_jds(J: JDS, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0,
-             beta: float = 0.0) -> torch.Tensor:
+def spmm_jds(J: JDS, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
+             ws: Optional[torch.Tensor] = None, interleave: bool = True) -> torch.Tensor:
+    """Y = alpha*A X + beta*Y for a column-major block X (spmm_jds)."""
     k = X.shape[1]
     if Y is None:
         Y = colmajor(J.n, k, X.dtype, X.device)
-    call("spmm_jds", J.n, _p(J.perm), _p(J.jd_ptr), _h_i32(J.h_jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val),
-         dtype_code(J.jd_val.dtype), k, _p(X), _ld(X, J.n_cols), _p(Y), _ld(Y, J.n), dtype_code(X.dtype),
-         float(alpha), float(beta), J.flags, _stream())
+    if interleave and ws is None:
+        ws = spmm_workspace(J.n_cols, k, X.dtype, X.device)
+    call("spmm_jds", J.n, J.n_cols, _p(J.perm), _p(J.jd_ptr), _h_i32(J.h_jd_ptr), J.ndiag, _p(J.jd_col),
+         _p(J.jd_val), dtype_code(J.jd_val.dtype), k, _p(X), _ld(X, J.n_cols), _p(Y), _ld(Y, J.n), dtype_code(X.dtype),
+         float(alpha), float(beta), J.flags, _p(ws) if interleave else None,
+         ws.numel() if (interleave and ws is not None) else 0, _stream())
     return Y
 
 
@@ -397,8 +410,8 @@ def spmv_grad_vals_jds(J: JDS, g: torch.Tensor, x: torch.Tensor, out: Optional[t
         if beta != 0.0:
             raise ValueError("beta != 0 needs out")
         out = torch.empty(J.nnz, dtype=g.dtype, device=g.device)
-    call("spmv_grad_vals_jds", J.n, _p(J.perm), _p(J.jd_ptr), J.ndiag, J.nnz, _p(J.jd_col), _p(g), _p(x), _p(out),
-         dtype_code(g.dtype), float(alpha), float(beta), J.flags, _stream())
+    call("spmv_grad_vals_jds", J.n, _p(J.perm), _p(J.jd_ptr), _h_i32(J.h_jd_ptr), J.ndiag, J.nnz, _p(J.jd_col),
+         _p(g), _p(x), _p(out), dtype_code(g.dtype), float(alpha), float(beta), J.flags, _stream())
     return out
 
 
@@ -408,6 +421,10 @@ def spmv_stream_triad(a, b, c, s: float):
 
 def spmv_stream_copy(a, b):
     call("spmv_stream_copy", a.numel(), _p(b), _p(a), _stream())
+
+
+def spmv_stream_read(b, part):
+    call("spmv_stream_read", b.numel(), _p(b), _p(part), part.numel(), _stream())
 
 
 # --------------------------------------------------------------------------- many matrices
@@ -446,6 +463,7 @@ class Batched:
         self.bl_val = torch.cat([B.bl_val for B in mats])
         self.perm = torch.cat([B.perm for B in mats])
         self.rows_per_wave, self.unroll, self.n_workgroups = rows_per_wave, unroll, n_workgroups
+        self.mats_C = int(self.C[0]) if bool((self.C == self.C[0]).all()) else None
         self.nnz_padded = int(self.bl_val.numel())
         self._plan(dev)
 

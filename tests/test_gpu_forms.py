@@ -35,7 +35,9 @@ def test_spmm_fp64(k):
     J = sp.jds_from_csr(A)
     Xd = colmajor_from(X, torch.float64)
     for name, fn in (("crs", lambda Y: sp.spmm_crs(A, Xd, Y, 1.5, -0.5)),
-                     ("jds", lambda Y: sp.spmm_jds(J, Xd, Y, 1.5, -0.5))):
+                     ("jds", lambda Y: sp.spmm_jds(J, Xd, Y, 1.5, -0.5)),
+                     ("crs_colmajor", lambda Y: sp.spmm_crs(A, Xd, Y, 1.5, -0.5, interleave=False)),
+                     ("jds_colmajor", lambda Y: sp.spmm_jds(J, Xd, Y, 1.5, -0.5, interleave=False))):
         got = to_np(fn(colmajor_from(Y0, torch.float64)))
         for j in range(k):
             D = 1.5 * oracle.row_absdot(R, X[:, j]) + 0.5 * np.abs(Y0[:, j])
@@ -52,8 +54,22 @@ def test_spmm_integer_exact_and_fp32_bound():
     A = gpu_csr(sp, r, c, v, nr, nc)
     J = sp.jds_from_csr(A)
     Xd = colmajor_from(X, torch.float64)
-    assert np.array_equal(to_np(sp.spmm_crs(A, Xd)), want)
-    assert np.array_equal(to_np(sp.spmm_jds(J, Xd)), want)
+    for il in (True, False):
+        assert np.array_equal(to_np(sp.spmm_crs(A, Xd, interleave=il)), want)
+        assert np.array_equal(to_np(sp.spmm_jds(J, Xd, interleave=il)), want)
+    # a long row (> 4096 entries) on the interleaved path, k > 64 falls back to column-major
+    r2, c2, v2, nr, nc, _ = rand_coo(72, 300, 6000, 0.01, integer=True)
+    rr = np.concatenate([r2, np.full(4500, 7, np.int32)])
+    cc = np.concatenate([c2, rng.choice(nc, 4500, replace=False).astype(np.int32)])
+    vv = np.concatenate([v2, rng.integers(-8, 9, 4500).astype(np.float64)])
+    R2 = oracle.csr_from_coo(nr, nc, rr, cc, vv)
+    A2 = gpu_csr(sp, rr, cc, vv, nr, nc)
+    X2 = rng.integers(-8, 9, (nc, 70)).astype(np.float64)
+    want2 = oracle.spmm_crs(R2, X2)
+    assert np.array_equal(to_np(sp.spmm_crs(A2, colmajor_from(X2, torch.float64))), want2)
+    assert np.array_equal(to_np(sp.spmm_crs(A2, colmajor_from(X2[:, :5], torch.float64))), want2[:, :5])
+    assert np.array_equal(to_np(sp.spmm_jds(sp.jds_from_csr(A2), colmajor_from(X2[:, :17], torch.float64))),
+                          want2[:, :17])
     # float32 values and vectors
     r, c, v, nr, nc, rng = rand_coo(71, 4000, 4000, 0.003)
     R = oracle.csr_from_coo(nr, nc, r, c, v)
@@ -186,3 +202,28 @@ def test_transposed_product_and_value_gradient():
     # values refreshed through the transpose map
     assert np.array_equal(to_np(op.transposed_values(vals)), R.val[tmap][oracle.jds_from_csr(
         oracle.CSR(n, n, rowT, colT, np.arange(R.nnz, dtype=np.float64))).jd_val.astype(np.int64)])
+
+
+def test_autotuner_batched_and_cache(tmp_path):
+    from paper_0910_4836_amd import autotune
+    mats = small_batch(12, seed=9)
+    jds = []
+    for r, c, v, n, _ in mats:
+        A = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v).to(torch.float32))
+        jds.append(sp.jds_from_csr(A))
+    cache = str(tmp_path / "tune.json")
+    tuner = autotune.Autotuner(cache, cs=(64, 128), rs=(64, 16), us=(2, 4))
+    Bt = autotune.build_batched(jds, tuner)
+    assert tuner.log and len(tuner.log[0]["timings_ms"]) == 8
+    x = torch.cat([to_dev(m[4]).to(torch.float32) for m in mats])
+    y = to_np(Bt(x)).astype(np.float64)
+    off = 0
+    for r, c, v, n, xm in mats:
+        R = oracle.csr_from_coo(n, n, r, c, v)
+        want = oracle.spmv_crs(R, xm)
+        D = oracle.row_absdot(R, xm)
+        assert np.all(np.abs(y[off:off + n] - want) <= (gamma(R.row_lengths() + 1, U32) + U32) * D)
+        off += n
+    # a second tuner reads the cached choice without timing anything
+    t2 = autotune.Autotuner(cache, cs=(64, 128), rs=(64, 16), us=(2, 4))
+    assert t2.tune_batched(jds) == (Bt.mats_C, Bt.rows_per_wave, Bt.unroll) and not t2.log
