@@ -9,7 +9,7 @@ keeps the fastest.  The cache is a JSON file keyed by device name and
 signature, so a later run with the same kind of matrices skips the search.
 
 Tuning is a host-side choice of launch parameters; every candidate computes
-the same y (each result is checked against the oracle in the tests).
+the same y up to summation order.
 """
 from __future__ import annotations
 
