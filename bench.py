@@ -3,12 +3,13 @@
 
 Default run (the headline line): the power-law workload (n = 2,000,000 rows,
 row lengths ~ L^-1.6929 on [1, 2000], mean 15 entries, half band / half uniform
-columns, N(0,1) values, x ~ U[-1, 1]).  One step = the six products
-  CRS, JDS, blocked JDS  x  {FP64 values, FP32 values with FP64 vectors}
-on that matrix, inputs resident in HBM.  Prints ONE JSON line with GFLOP/s
-(2 flops per stored entry), the per-kernel split, the roofline of the
-dominant kernel (algorithmic bytes / its average launch time, against 8 TB/s)
-and the serial CPU oracle timed on the host as a reported baseline.
+columns, N(0,1) values, x ~ U[-1, 1]).  One step = the three FP64 products
+CRS, JDS and blocked JDS (C = 64) on that matrix, inputs resident in HBM.
+Prints ONE JSON line with GFLOP/s (2 flops per stored entry), the per-kernel
+times, the roofline of the dominant kernel (algorithmic bytes / its average
+launch time, against 8 TB/s) and the serial CPU oracle timed on the host as a
+reported baseline.  Beside the step (not in it) the same line reports the
+FP32-value products and the column-split forms of all three.
 
 --suite adds one JSON line per other workload (Laplacian, symmetric diagonals
 in FP64/FP32/BF16, multi-vector, many matrices, Chebyshev backward).
@@ -172,9 +173,12 @@ def load_powerlaw(torch, sp, dev):
     A32 = A.with_values(sp.spmv_convert_values(A.val, torch.float32))
     J32 = J.with_values(sp.spmv_convert_values(J.jd_val, torch.float32))
     B32 = B.with_values(sp.spmv_convert_values(B.bl_val, torch.float32))
+    S = timed("split_columns_ms", lambda: sp.Split(A))
+    timed("split_jds_parts_ms", lambda: S.jds_parts())
+    timed("split_blocked_parts_ms", lambda: S.blocked_parts(64))
     xd = torch.from_numpy(x).to(dev)
     host = (r, c, v, n, x)
-    return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, x=xd, n=n, nnz=A.nnz, setup=setup, gen_s=gen_s,
+    return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, S=S, x=xd, n=n, nnz=A.nnz, setup=setup, gen_s=gen_s,
                 host=host)
 
 
@@ -191,6 +195,16 @@ def powerlaw_kernels(sp, W, torch):
         ("jds_f32val", lambda: sp.spmv_jds(W["J32"], x, y)),
         ("blocked_f32val", lambda: sp.spmv_jds_blocked(W["B32"], x, y)),
     ]
+    S = W["S"]
+    S32 = W.setdefault("S32", S.with_values(sp.spmv_convert_values(S.val, torch.float32)))
+    ks += [
+        ("crs_split_f64", lambda: sp.spmv_crs_split(S, x, y)),
+        ("jds_split_f64", lambda: sp.spmv_jds_split(S, x, y)),
+        ("blocked_split_f64", lambda: sp.spmv_jds_blocked_split(S, x, y)),
+        ("crs_split_f32val", lambda: sp.spmv_crs_split(S32, x, y)),
+        ("jds_split_f32val", lambda: sp.spmv_jds_split(S32, x, y)),
+        ("blocked_split_f32val", lambda: sp.spmv_jds_blocked_split(S32, x, y)),
+    ]
     bmin = {
         "crs_f64": bytes_crs(nnz, n, n, 8, 8),
         "jds_f64": bytes_jds(nnz, n, n, J.ndiag, 8, 8),
@@ -199,6 +213,10 @@ def powerlaw_kernels(sp, W, torch):
         "jds_f32val": bytes_jds(nnz, n, n, J.ndiag, 4, 8),
         "blocked_f32val": bytes_blocked(nnz, n, n, B.n_slices, 4, 8),
     }
+    # the column-split forms move the same algorithmic bytes as the unsplit ones
+    for k in list(bmin):
+        base, tag = k.split("_", 1)
+        bmin[f"{base}_split_{tag}"] = bmin[k]
     return ks, bmin
 
 
@@ -445,12 +463,14 @@ def main():
     W = load_powerlaw(torch, sp, dev)
     all_ks, bmin = powerlaw_kernels(sp, W, torch)
     # the step: the three FP64 products of the power-law workload
-    ks = [k for k in all_ks if k[0].endswith("_f64")]
-    mixed = [k for k in all_ks if not k[0].endswith("_f64")]
+    ks = [k for k in all_ks if k[0].endswith("_f64") and "_split" not in k[0]]
+    mixed = [k for k in all_ks if not k[0].endswith("_f64") and "_split" not in k[0]]
+    split = [k for k in all_ks if "_split" in k[0]]
     if args.only:
         keep = set(args.only.split(","))
         ks = [k for k in all_ks if k[0] in keep]
         mixed = []
+        split = []
     ms_step, per = time_loop(torch, ks, args.steps, args.warmup)
     flops_step = 2.0 * W["nnz"] * len(ks)
     value = flops_step / (ms_step * 1e-3) / 1e9
@@ -479,6 +499,13 @@ def main():
                                              speedup_vs_fp64=round(per[name.replace("_f32val", "_f64")] /
                                                                    per_m[name], 3))
                                   for name, _ in mixed}
+    if split:
+        _, per_s = time_loop(torch, split, max(10, args.steps // 2), 3)
+        unsplit = dict(per, **(per_m if mixed else {}))
+        out["column_split"] = {name: dict(entry(name, per_s[name]),
+                                          speedup_vs_unsplit=round(unsplit[name.replace("_split", "")] / per_s[name],
+                                                                   3))
+                               for name, _ in split}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)
     else:

@@ -267,6 +267,63 @@ spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd
                                spmv_dtype dt, double alpha, double beta, unsigned flags, void *stream);
 
 /* ======================================================================== */
+/* Column-split products                                                     */
+/* ======================================================================== */
+/* The paper (Section 2) names the irregular access to the input vector as
+ * the bottleneck that its row blocking cannot remove.  These forms block the
+ * columns instead: A = sum_k A_k, A_k holding the entries whose column lies
+ * in [k*width, (k+1)*width), k < SPMV_SPLIT_PARTS (= the MI355X's 8 XCDs).
+ * Part k is processed on XCD k, so its x gathers stay inside one 1/8 slice
+ * of x that fits that XCD's L2; each part writes an FP64 partial result and
+ * a last kernel forms y = alpha * sum_k partial_k + beta * y, adding the
+ * partials in order k = 0, 1, ... (deterministic).  Each A_k is an ordinary
+ * CRS, JDS or blocked-JDS matrix.  Every part accumulates in FP64 whatever
+ * the value type (FP32 / BF16 values are widened exactly, FP32 vectors are
+ * read as stored): a part sees only a piece of each row, so the rule "rows
+ * longer than SPMV_WIDE_ROW_NNZ entries accumulate in FP64" of the unsplit
+ * calls could not be applied per part; FP64 throughout satisfies it and the
+ * bound of the FP32 rule for the shorter rows.
+ *
+ * spmv_split_columns (setup, synchronises): reorders a CRS matrix part by
+ * part (each part keeps its entries in CRS order): col_out[nnz], val_out[nnz]
+ * and row_ptr_all[SPMV_SPLIT_PARTS*(n_rows+1)].  h_bounds[0..8] returns the
+ * part offsets; part k is the CRS matrix (row_ptr_all + k*(n_rows+1),
+ * col_out + h_bounds[k], val_out + h_bounds[k]) with h_bounds[k+1] -
+ * h_bounds[k] entries (its row_ptr starts at 0).  width = 0 picks
+ * ceil(n_cols/8) rounded up to 64.  Compute calls need ws of
+ * spmv_split_workspace_size(n) bytes for the partial results (not SYMPERM). */
+#define SPMV_SPLIT_PARTS 8
+size_t spmv_split_columns_workspace_size(int32_t n_rows, int64_t nnz);
+spmv_status spmv_split_columns(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t width,
+                               int32_t *row_ptr_all, int32_t *col_out, void *val_out, int64_t *h_bounds,
+                               void *ws, size_t ws_bytes, void *stream);
+size_t spmv_split_workspace_size(int32_t n_rows);
+/* CRS parts as returned by spmv_split_columns; plan_all holds the
+ * spmv_crs_plan of every part one after the other (part k's at plan_all +
+ * h_plan_off[k], h_n_blocks[k] blocks, built with block_nnz). */
+spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr_all, const int32_t *col_idx,
+                           const void *val, const int64_t *h_bounds, spmv_dtype val_dt, const int32_t *plan_all,
+                           const int32_t *h_plan_off, const int32_t *h_n_blocks, int32_t block_nnz,
+                           const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, void *ws,
+                           size_t ws_bytes, void *stream);
+/* JDS parts (each from spmv_jds_from_csr of part k, without SYMPERM): host
+ * arrays of SPMV_SPLIT_PARTS device pointers (h_perm, h_jd_ptr, h_jd_col,
+ * h_jd_val), of host pointers (h_jd_ptr_host) and of sizes (h_ndiag). */
+spmv_status spmv_jds_split(int32_t n, const int32_t *const *h_perm, const int32_t *const *h_jd_ptr,
+                           const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag,
+                           const int32_t *const *h_jd_col, const void *const *h_jd_val, spmv_dtype val_dt,
+                           const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, int32_t unroll,
+                           int32_t max_iters, void *ws, size_t ws_bytes, void *stream);
+/* Blocked-JDS parts (slice height C for all parts). */
+spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *const *h_perm,
+                                   const int64_t *const *h_slice_ptr, const int32_t *const *h_slice_nd,
+                                   const int32_t *const *h_slice_nd_host, const int32_t *const *h_bl_col,
+                                   const void *const *h_bl_val, spmv_dtype val_dt, const void *x, void *y,
+                                   spmv_dtype vec_dt, double alpha, double beta, int32_t rows_per_wave,
+                                   int32_t unroll, int32_t max_iters, void *ws, size_t ws_bytes, void *stream);
+
+/* ======================================================================== */
 /* Many matrices in one launch                                               */
 /* ======================================================================== */
 /* Batched blocked-JDS SpMV: y_m = A_m x_m for m < n_mat, F32 values and

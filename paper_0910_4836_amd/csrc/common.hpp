@@ -35,6 +35,11 @@ spmv_status hip_fail(hipError_t e, const char *what);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// y = alpha * sum_k part[k*n + i] + beta * y (k = 0 .. SPMV_SPLIT_PARTS-1 in
+// order, FP64), the last step of the column-split products (util.hip).
+spmv_status launch_combine(int32_t n, const double *part, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                           hipStream_t s);
+
 // Column-major multi-vector kernels (crs.hip, jds.hip), the no-workspace path
 // of spmm_crs / spmm_jds (spmm.hip).
 spmv_status spmm_crs_colmajor(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
@@ -140,6 +145,10 @@ __device__ __forceinline__ void write_y(XT *y, int64_t i, double acc, double alp
 // ---------------------------------------------------------------- wave helpers
 
 constexpr int WAVE = 64;
+
+// Column-split products: one part per XCD (MI355X has 8; workgroup b runs on
+// XCD b % 8).
+constexpr int SPLIT_PARTS = SPMV_SPLIT_PARTS;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 

@@ -559,6 +559,50 @@ __global__ void sojds_kernel(const int32_t *__restrict__ jp, int32_t ndiag, cons
     }
 }
 
+// ---- column split: part k = entries whose column lies in [k*width, (k+1)*width)
+
+__global__ void row_of_entries_kernel(const int32_t *__restrict__ rp, int32_t n, int64_t nnz, int32_t *__restrict__ rowid)
+{
+    GRID_LOOP(j, nnz) rowid[j] = row_of(rp, n, j);
+}
+
+__global__ void part_key_kernel(const int32_t *__restrict__ col, int64_t nnz, int32_t width, uint32_t *__restrict__ key)
+{
+    GRID_LOOP(j, nnz) key[j] = (uint32_t)(col[j] / width);
+}
+
+template <typename T>
+__global__ void gather_split_kernel(const int32_t *__restrict__ perm, int64_t nnz, const int32_t *__restrict__ col,
+                                    const T *__restrict__ val, const int32_t *__restrict__ rowid,
+                                    int32_t *__restrict__ col_out, T *__restrict__ val_out,
+                                    int32_t *__restrict__ rowid_out)
+{
+    GRID_LOOP(i, nnz)
+    {
+        const int32_t j = perm[i];
+        col_out[i] = col[j];
+        val_out[i] = val[j];
+        rowid_out[i] = rowid[j];
+    }
+}
+
+__global__ void part_bounds_kernel(const uint32_t *__restrict__ skey, int64_t nnz, int64_t *__restrict__ bounds)
+{
+    GRID_LOOP(p, (int64_t)SPLIT_PARTS + 1) bounds[p] = lower_bound_dev(skey, nnz, (int64_t)p);
+}
+
+// row_ptr of part k, relative to the part's first entry
+__global__ void split_row_ptr_kernel(const int32_t *__restrict__ rowid_sorted, const int64_t *__restrict__ bounds,
+                                     int32_t n, int32_t *__restrict__ row_ptr_all)
+{
+    GRID_LOOP(t, (int64_t)SPLIT_PARTS * (n + 1))
+    {
+        const int64_t k = t / (n + 1), r = t % (n + 1);
+        const int64_t lo = bounds[k], hi = bounds[k + 1];
+        row_ptr_all[t] = (int32_t)lower_bound_dev(rowid_sorted + lo, hi - lo, r);
+    }
+}
+
 __global__ void transpose_cols_kernel(const int32_t *__restrict__ rp, int32_t n_rows, const int32_t *__restrict__ tmap,
                                       int64_t nnz, int32_t *__restrict__ colT)
 {
@@ -969,6 +1013,68 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
     BLK_CASE(SPMV_F32, uint32_t)
     BLK_CASE(SPMV_BF16, uint16_t)
 #undef BLK_CASE
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+size_t spmv_split_columns_workspace_size(int32_t n_rows, int64_t nnz)
+{
+    (void)n_rows;
+    const size_t n = (size_t)(nnz > 0 ? nnz : 1);
+    return 4 * align_up(sizeof(int32_t) * n, 256) + align_up(sizeof(int64_t) * (SPLIT_PARTS + 1), 256) +
+           radix_ws_bytes((int64_t)n) + 1024;
+}
+
+spmv_status spmv_split_columns(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t width,
+                               int32_t *row_ptr_all, int32_t *col_out, void *val_out, int64_t *h_bounds, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && nnz >= 0, "spmv_split_columns: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_split_columns: nnz >= 2^31");
+    SPMV_REQUIRE(valid_dtype(dt), "spmv_split_columns: bad dtype");
+    if (width == 0) width = (int32_t)(ceil_div(ceil_div(n_cols > 0 ? n_cols : 1, SPLIT_PARTS), 64) * 64);
+    SPMV_REQUIRE(width > 0 && (int64_t)width * SPLIT_PARTS >= n_cols,
+                 "spmv_split_columns: width * SPMV_SPLIT_PARTS must cover the columns");
+    SPMV_REQUIRE(row_ptr && row_ptr_all && h_bounds, "spmv_split_columns: null pointer");
+    SPMV_REQUIRE(nnz == 0 || (col_idx && val && col_out && val_out), "spmv_split_columns: null arrays");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_columns_workspace_size(n_rows, nnz),
+                 "spmv_split_columns: workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    const size_t m = (size_t)(nnz > 0 ? nnz : 1);
+    int32_t *rowid = wc.take<int32_t>(m);
+    int32_t *rowid_s = wc.take<int32_t>(m);
+    uint32_t *keys = wc.take<uint32_t>(m);
+    int32_t *perm = wc.take<int32_t>(m);
+    int64_t *bounds = wc.take<int64_t>(SPLIT_PARTS + 1);
+    const size_t rws_bytes = radix_ws_bytes((int64_t)m);
+    void *rws = wc.take<char>(rws_bytes);
+    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_split_columns: workspace too small");
+    if (nnz > 0) {
+        row_of_entries_kernel<<<grid_for(nnz), 256, 0, s>>>(row_ptr, n_rows, nnz, rowid);
+        part_key_kernel<<<grid_for(nnz), 256, 0, s>>>(col_idx, nnz, width, keys);
+        iota_kernel<<<grid_for(nnz), 256, 0, s>>>(perm, nnz);
+        SPMV_CHECK_LAUNCH("split keys");
+        // stable: each part keeps the row-major order of its entries
+        spmv_status st = radix_sort_pairs(keys, perm, nnz, bits_for(SPLIT_PARTS - 1), rws, rws_bytes, s);
+        if (st != SPMV_OK) return st;
+        if (dt == SPMV_F64)
+            gather_split_kernel<uint64_t><<<grid_for(nnz), 256, 0, s>>>(perm, nnz, col_idx, (const uint64_t *)val, rowid,
+                                                                         col_out, (uint64_t *)val_out, rowid_s);
+        else if (dt == SPMV_F32)
+            gather_split_kernel<uint32_t><<<grid_for(nnz), 256, 0, s>>>(perm, nnz, col_idx, (const uint32_t *)val, rowid,
+                                                                         col_out, (uint32_t *)val_out, rowid_s);
+        else
+            gather_split_kernel<uint16_t><<<grid_for(nnz), 256, 0, s>>>(perm, nnz, col_idx, (const uint16_t *)val, rowid,
+                                                                         col_out, (uint16_t *)val_out, rowid_s);
+        SPMV_CHECK_LAUNCH("split gather");
+    }
+    part_bounds_kernel<<<1, 64, 0, s>>>(keys, nnz, bounds);
+    split_row_ptr_kernel<<<grid_for((int64_t)SPLIT_PARTS * (n_rows + 1)), 256, 0, s>>>(rowid_s, bounds, n_rows,
+                                                                                       row_ptr_all);
+    SPMV_CHECK_LAUNCH("split row_ptr");
+    SPMV_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost, s));
     SPMV_HIP(hipStreamSynchronize(s));
     return SPMV_OK;
 }

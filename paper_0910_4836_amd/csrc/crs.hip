@@ -15,6 +15,7 @@
 // depends only on the plan, so results are reproducible.
 // Blocks are remapped so that each XCD walks a contiguous range of rows: the
 // band part of x stays in that XCD's L2.
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -26,9 +27,9 @@ constexpr int CRS_DEFAULT_BLOCK_NNZ = 1024;
 constexpr int CRS_MAX_BLOCK_NNZ = 4096;
 constexpr int CRS_MAX_BLOCK_ROWS = 256;
 
-template <bool WIDE, typename VT, typename XT>
+template <bool WIDE, typename VT, typename XT, typename OT>
 __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, const VT *__restrict__ val,
-                                               const XT *__restrict__ x, XT *__restrict__ y, int32_t row,
+                                               const XT *__restrict__ x, OT *__restrict__ y, int32_t row,
                                                int32_t e0, int32_t e1, double alpha, double beta,
                                                double *red)
 {
@@ -62,30 +63,27 @@ __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, 
     }
 }
 
-template <typename VT, typename XT>
-__global__ __launch_bounds__(CRS_THREADS) void crs_block_kernel(const int32_t *__restrict__ row_ptr,
-                                                                const int32_t *__restrict__ col,
-                                                                const VT *__restrict__ val,
-                                                                const XT *__restrict__ x, XT *__restrict__ y,
-                                                                const int32_t *__restrict__ plan,
-                                                                double alpha, double beta)
+// One plan block b (rows plan[b] .. plan[b+1]) of y = alpha*A x + beta*y.
+// WIDE_ALL: accumulate every row in FP64 (the column-split parts, whose rows
+// are pieces of rows whose full length the block does not see).
+template <typename VT, typename XT, typename OT, bool WIDE_ALL = false>
+__device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                               const VT *__restrict__ val, const XT *__restrict__ x,
+                                               OT *__restrict__ y, const int32_t *__restrict__ plan, int64_t b,
+                                               double alpha, double beta, double *smem_d, double *red)
 {
-    constexpr bool F64 = IsF64<VT>::value;
+    constexpr bool F64 = IsF64<VT>::value || WIDE_ALL;
     typedef typename Acc<F64>::T acc_t;
-    extern __shared__ double smem_d[];
-    __shared__ double red[CRS_THREADS / WAVE];
     acc_t *prod = reinterpret_cast<acc_t *>(smem_d);
-
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int32_t r0 = plan[b], r1 = plan[b + 1];
     const int32_t e0 = row_ptr[r0], e1 = row_ptr[r1];
     const int32_t nr = r1 - r0, ne = e1 - e0;
 
     if (nr == 1) {
         if (!F64 && ne > SPMV_WIDE_ROW_NNZ)
-            crs_vector_row<true>(col, val, x, y, r0, e0, e1, alpha, beta, red);
+            crs_vector_row<true, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, red);
         else
-            crs_vector_row<F64>(col, val, x, y, r0, e0, e1, alpha, beta, red);
+            crs_vector_row<F64, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, red);
         return;
     }
 
@@ -121,6 +119,46 @@ __global__ __launch_bounds__(CRS_THREADS) void crs_block_kernel(const int32_t *_
     }
     s = group_sum(s, G);
     if (g < nr && l == 0) write_y(y, (int64_t)r0 + g, (double)s, alpha, beta);
+}
+
+template <typename VT, typename XT>
+__global__ __launch_bounds__(CRS_THREADS) void crs_block_kernel(const int32_t *__restrict__ row_ptr,
+                                                                const int32_t *__restrict__ col,
+                                                                const VT *__restrict__ val,
+                                                                const XT *__restrict__ x, XT *__restrict__ y,
+                                                                const int32_t *__restrict__ plan,
+                                                                double alpha, double beta)
+{
+    extern __shared__ double smem_d[];
+    __shared__ double red[CRS_THREADS / WAVE];
+    crs_block_body<VT, XT, XT>(row_ptr, col, val, x, y, plan, xcd_remap(blockIdx.x, gridDim.x), alpha, beta, smem_d,
+                               red);
+}
+
+// Column-split CRS: part k (columns of the k-th eighth) runs on XCD k
+// (workgroup b -> part b % 8) and writes its partial result part_y[k][:].
+struct CrsSplitTab {
+    int64_t base[SPLIT_PARTS];        // part k's first entry in col / val
+    int32_t plan_off[SPLIT_PARTS];
+    int32_t n_blocks[SPLIT_PARTS];
+};
+
+template <typename VT, typename XT>
+__global__ __launch_bounds__(CRS_THREADS) void crs_split_kernel(int32_t n_rows, const int32_t *__restrict__ row_ptr_all,
+                                                                const int32_t *__restrict__ col,
+                                                                const VT *__restrict__ val,
+                                                                const XT *__restrict__ x,
+                                                                double *__restrict__ part_y,
+                                                                const int32_t *__restrict__ plan_all, CrsSplitTab T)
+{
+    extern __shared__ double smem_d[];
+    __shared__ double red[CRS_THREADS / WAVE];
+    const int k = (int)(blockIdx.x % SPLIT_PARTS);
+    const int64_t b = blockIdx.x / SPLIT_PARTS;
+    if (b >= T.n_blocks[k]) return;
+    crs_block_body<VT, XT, double, true>(row_ptr_all + (int64_t)k * (n_rows + 1), col + T.base[k], val + T.base[k],
+                                         x, part_y + (int64_t)k * n_rows, plan_all + T.plan_off[k], b, 1.0, 0.0,
+                                         smem_d, red);
 }
 
 // One wavefront per row: the default when no plan is given.
@@ -359,6 +397,52 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
     CRS_CASE(SPMV_F64, double, SPMV_F32, float)
 #undef CRS_CASE
     return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs: dtype combination");
+}
+
+spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr_all, const int32_t *col_idx,
+                           const void *val, const int64_t *h_bounds, spmv_dtype val_dt, const int32_t *plan_all,
+                           const int32_t *h_plan_off, const int32_t *h_n_blocks, int32_t block_nnz, const void *x,
+                           void *y, spmv_dtype vec_dt, double alpha, double beta, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0, "spmv_crs_split: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_crs_split: bad dtype");
+    if (n_rows == 0) return SPMV_OK;
+    SPMV_REQUIRE(row_ptr_all && plan_all && h_plan_off && h_n_blocks && h_bounds && y, "spmv_crs_split: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(n_rows), "spmv_crs_split: workspace too small");
+    if (block_nnz == 0) block_nnz = CRS_DEFAULT_BLOCK_NNZ;
+    SPMV_REQUIRE(block_nnz >= CRS_THREADS && block_nnz <= CRS_MAX_BLOCK_NNZ,
+                 "spmv_crs_split: block_nnz must be in [256, 4096]");
+    CrsSplitTab T{};
+    int64_t max_nb = 0;
+    for (int k = 0; k < SPLIT_PARTS; ++k) {
+        SPMV_REQUIRE(h_n_blocks[k] >= 0 && h_plan_off[k] >= 0, "spmv_crs_split: bad part plan");
+        T.base[k] = h_bounds[k];
+        T.plan_off[k] = h_plan_off[k];
+        T.n_blocks[k] = h_n_blocks[k];
+        max_nb = std::max<int64_t>(max_nb, h_n_blocks[k]);
+    }
+    hipStream_t s = as_stream(stream);
+    double *part = (double *)ws;
+    const unsigned grid = (unsigned)(max_nb * SPLIT_PARTS);
+    if (grid) {
+#define CSPLIT_CASE(VDT, VT, XDT, XT)                                                                         \
+    if (val_dt == VDT && vec_dt == XDT) {                                                                     \
+        const size_t lds = (size_t)block_nnz * 8;                                                             \
+        crs_split_kernel<VT, XT><<<grid, CRS_THREADS, lds, s>>>(n_rows, row_ptr_all, col_idx, (const VT *)val, \
+                                                               (const XT *)x, part, plan_all, T);             \
+    } else
+        CSPLIT_CASE(SPMV_F64, double, SPMV_F64, double)
+        CSPLIT_CASE(SPMV_F32, float, SPMV_F64, double)
+        CSPLIT_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+        CSPLIT_CASE(SPMV_F32, float, SPMV_F32, float)
+        CSPLIT_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+        CSPLIT_CASE(SPMV_F64, double, SPMV_F32, float)
+        return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs_split: dtype combination");
+#undef CSPLIT_CASE
+        SPMV_CHECK_LAUNCH("spmv_crs_split");
+    }
+    return launch_combine(n_rows, part, y, vec_dt, alpha, beta, s);
 }
 
 }  // extern "C"

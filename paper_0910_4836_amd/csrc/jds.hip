@@ -20,6 +20,7 @@
 //   JDS:     entry (d, r) at jd_ptr[d] + r, diagonal d reaches rows r < len_d
 //   blocked: entry (d, r) at slice_ptr[s] + d*C + (r - s*C), s = r / C, padded
 //            slots (col = -1) skipped.
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -171,12 +172,9 @@ struct WaveTask {
 };
 
 template <int FMT>
-__device__ __forceinline__ WaveTask wave_task(const JdsArgs &a, const JdsPlan &P, bool reduced_values)
+__device__ __forceinline__ WaveTask wave_task(const JdsArgs &a, const JdsPlan &P, bool reduced_values, int64_t wg)
 {
     WaveTask t;
-    // No XCD remap here: the long-row classes come first and the hardware's
-    // round-robin spreads them over all XCDs.
-    const int64_t wg = blockIdx.x;
     int ci = 0;
     while (ci < P.ncls - 1 && wg >= P.c[ci].wg_end) ++ci;
     const JdsClass K = P.c[ci];
@@ -225,12 +223,15 @@ __device__ __forceinline__ WaveTask wave_task(const JdsArgs &a, const JdsPlan &P
     return t;
 }
 
-template <int FMT, int U, typename VT, typename XT>
-__global__ __launch_bounds__(JDS_THREADS) void jds_kernel(JdsArgs a, JdsPlan P)
+// Workgroup wg of plan P: y (or a partial result of type OT) for its rows.
+// WIDE_ALL: accumulate every row in FP64 (the column-split parts, whose rows
+// are pieces of rows whose full length the workgroup does not see).
+template <int FMT, int U, typename VT, typename XT, typename OT, bool WIDE_ALL = false>
+__device__ __forceinline__ void jds_body(const JdsArgs &a, const JdsPlan &P, int64_t wg,
+                                         double (*part)[WAVE])
 {
-    __shared__ double part[JDS_WAVES][WAVE];
-    constexpr bool F64 = IsF64<VT>::value;
-    const WaveTask t = wave_task<FMT>(a, P, !F64);
+    constexpr bool F64 = IsF64<VT>::value || WIDE_ALL;
+    const WaveTask t = wave_task<FMT>(a, P, !F64, wg);
     const bool valid = t.valid, row_ok = t.row_ok, wide = t.wide, bounded = t.bounded;
     const int32_t row0 = t.row0, r = t.r, dA = t.dA, dB = t.dB;
     const int w = t.w, rl = t.rl, kk = t.kk, G = t.G, S = t.S, p = t.p;
@@ -262,8 +263,37 @@ __global__ __launch_bounds__(JDS_THREADS) void jds_kernel(JdsArgs a, JdsPlan P)
     }
     if (row_ok && kk == 0) {
         const int32_t yi = a.symperm ? r : a.perm[r];
-        write_y((XT *)a.y, yi, td, a.alpha, a.beta);
+        write_y((OT *)a.y, yi, td, a.alpha, a.beta);
     }
+}
+
+template <int FMT, int U, typename VT, typename XT>
+__global__ __launch_bounds__(JDS_THREADS) void jds_kernel(JdsArgs a, JdsPlan P)
+{
+    __shared__ double part[JDS_WAVES][WAVE];
+    // No XCD remap here: the long-row classes come first and the hardware's
+    // round-robin spreads them over all XCDs.
+    jds_body<FMT, U, VT, XT, XT>(a, P, blockIdx.x, part);
+}
+
+// Column-split JDS / blocked JDS: part k (the matrix restricted to the k-th
+// eighth of the columns, with its own permutation) runs on XCD k (workgroup
+// b -> part b % 8) and writes its partial result as FP64 into a[k].y.  All
+// rows accumulate in FP64, reduced-precision values included.
+struct JdsSplitArgs {
+    JdsArgs a[SPLIT_PARTS];
+    JdsPlan P[SPLIT_PARTS];
+};
+
+template <int FMT, int U, typename VT, typename XT>
+__global__ __launch_bounds__(JDS_THREADS) void jds_split_kernel(JdsSplitArgs S)
+{
+    __shared__ double part[JDS_WAVES][WAVE];
+    const int k = (int)(blockIdx.x % SPLIT_PARTS);
+    const int64_t wg = blockIdx.x / SPLIT_PARTS;
+    const JdsPlan &P = S.P[k];
+    if (P.ncls == 0 || wg >= P.c[P.ncls - 1].wg_end) return;
+    jds_body<FMT, U, VT, XT, double, true>(S.a[k], P, wg, part);
 }
 
 // Multi-vector JDS: each lane owns one row (R = 64) and keeps k accumulators;
@@ -310,7 +340,7 @@ __global__ __launch_bounds__(256) void spmm_jds_kernel(JdsArgs a)
 template <int U, typename T>
 __global__ __launch_bounds__(JDS_THREADS) void jds_grad_kernel(JdsArgs a, JdsPlan P)
 {
-    const WaveTask t = wave_task<FMT_JDS>(a, P, false);
+    const WaveTask t = wave_task<FMT_JDS>(a, P, false, blockIdx.x);
     if (!t.row_ok) return;
     const int32_t *__restrict__ jp = a.jd_ptr;
     const int32_t *__restrict__ col = a.col;
@@ -630,6 +660,132 @@ spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd
         jds_grad_kernel<4, float><<<grid, JDS_THREADS, 0, s>>>(a, P);
     SPMV_CHECK_LAUNCH("spmv_grad_vals_jds");
     return SPMV_OK;
+}
+
+spmv_status spmv_jds_split(int32_t n, const int32_t *const *h_perm, const int32_t *const *h_jd_ptr,
+                           const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag, const int32_t *const *h_jd_col,
+                           const void *const *h_jd_val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
+                           double alpha, double beta, int32_t unroll, int32_t max_iters, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_jds_split: n < 0");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_split: bad dtype");
+    SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_split: bad unroll or max_iters");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(h_perm && h_jd_ptr && h_jd_ptr_host && h_ndiag && h_jd_col && h_jd_val && x && y,
+                 "spmv_jds_split: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(n), "spmv_jds_split: workspace too small");
+    JdsSplitArgs S{};
+    double *part = (double *)ws;
+    int64_t max_wg = 0;
+    for (int k = 0; k < SPLIT_PARTS; ++k) {
+        SPMV_REQUIRE(h_perm[k] && h_jd_ptr[k] && h_jd_ptr_host[k] && h_ndiag[k] >= 0, "spmv_jds_split: null part");
+        SPMV_REQUIRE(h_ndiag[k] == 0 || (h_jd_col[k] && h_jd_val[k]), "spmv_jds_split: null part arrays");
+        JdsArgs &a = S.a[k];
+        a.n = n;
+        a.perm = h_perm[k];
+        a.jd_ptr = h_jd_ptr[k];
+        a.ndiag = h_ndiag[k];
+        a.C = 64;
+        a.col = h_jd_col[k];
+        a.val = h_jd_val[k];
+        a.x = x;
+        a.y = part + (int64_t)k * n;
+        a.alpha = 1.0;
+        a.beta = 0.0;
+        S.P[k] = plan_jds(n, h_jd_ptr_host[k], h_ndiag[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1);
+        if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
+    }
+    hipStream_t s = as_stream(stream);
+    const unsigned grid = (unsigned)(max_wg * SPLIT_PARTS);
+    if (grid) {
+        const int u = unroll ? unroll : 4;
+#define JSPLIT_CASE(VDT, VT, XDT, XT)                                                              \
+    if (val_dt == VDT && vec_dt == XDT) {                                                          \
+        if (u == 2) jds_split_kernel<FMT_JDS, 2, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);          \
+        else if (u == 8) jds_split_kernel<FMT_JDS, 8, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);     \
+        else jds_split_kernel<FMT_JDS, 4, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);                 \
+    } else
+        JSPLIT_CASE(SPMV_F64, double, SPMV_F64, double)
+        JSPLIT_CASE(SPMV_F32, float, SPMV_F64, double)
+        JSPLIT_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+        JSPLIT_CASE(SPMV_F32, float, SPMV_F32, float)
+        JSPLIT_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+        JSPLIT_CASE(SPMV_F64, double, SPMV_F32, float)
+        return fail(SPMV_ERR_UNSUPPORTED, "spmv_jds_split: dtype combination");
+#undef JSPLIT_CASE
+        SPMV_CHECK_LAUNCH("spmv_jds_split");
+    }
+    return launch_combine(n, part, y, vec_dt, alpha, beta, s);
+}
+
+spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *const *h_perm, const int64_t *const *h_slice_ptr,
+                                   const int32_t *const *h_slice_nd, const int32_t *const *h_slice_nd_host,
+                                   const int32_t *const *h_bl_col, const void *const *h_bl_val, spmv_dtype val_dt,
+                                   const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                                   int32_t rows_per_wave, int32_t unroll, int32_t max_iters, void *ws,
+                                   size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_jds_blocked_split: n < 0");
+    SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_split: C must be a positive multiple of 64");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_blocked_split: bad dtype");
+    SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_blocked_split: bad unroll or max_iters");
+    SPMV_REQUIRE(rows_per_wave == 0 || rows_per_wave == 8 || rows_per_wave == 16 || rows_per_wave == 32 ||
+                     rows_per_wave == 64,
+                 "spmv_jds_blocked_split: rows_per_wave must be 0, 8, 16, 32 or 64");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(h_perm && h_slice_ptr && h_slice_nd && h_slice_nd_host && h_bl_col && h_bl_val && x && y,
+                 "spmv_jds_blocked_split: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(n), "spmv_jds_blocked_split: workspace too small");
+    int forced = -1;
+    if (rows_per_wave) {
+        forced = 0;
+        while ((1 << forced) < rows_per_wave) ++forced;
+    }
+    JdsSplitArgs S{};
+    double *part = (double *)ws;
+    int64_t max_wg = 0;
+    for (int k = 0; k < SPLIT_PARTS; ++k) {
+        SPMV_REQUIRE(h_perm[k] && h_slice_ptr[k] && h_slice_nd[k] && h_slice_nd_host[k],
+                     "spmv_jds_blocked_split: null part");
+        SPMV_REQUIRE(h_slice_nd_host[k][0] == 0 || (h_bl_col[k] && h_bl_val[k]),
+                     "spmv_jds_blocked_split: null part arrays");
+        JdsArgs &a = S.a[k];
+        a.n = n;
+        a.perm = h_perm[k];
+        a.C = C;
+        a.slice_ptr = h_slice_ptr[k];
+        a.slice_nd = h_slice_nd[k];
+        a.col = h_bl_col[k];
+        a.val = h_bl_val[k];
+        a.x = x;
+        a.y = part + (int64_t)k * n;
+        a.alpha = 1.0;
+        a.beta = 0.0;
+        S.P[k] = plan_blocked(n, C, h_slice_nd_host[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced);
+        if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
+    }
+    hipStream_t s = as_stream(stream);
+    const unsigned grid = (unsigned)(max_wg * SPLIT_PARTS);
+    if (grid) {
+        const int u = unroll ? unroll : 4;
+#define BSPLIT_CASE(VDT, VT, XDT, XT)                                                                  \
+    if (val_dt == VDT && vec_dt == XDT) {                                                              \
+        if (u == 2) jds_split_kernel<FMT_BLOCKED, 2, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);          \
+        else if (u == 8) jds_split_kernel<FMT_BLOCKED, 8, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);     \
+        else jds_split_kernel<FMT_BLOCKED, 4, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);                 \
+    } else
+        BSPLIT_CASE(SPMV_F64, double, SPMV_F64, double)
+        BSPLIT_CASE(SPMV_F32, float, SPMV_F64, double)
+        BSPLIT_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+        BSPLIT_CASE(SPMV_F32, float, SPMV_F32, float)
+        BSPLIT_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+        BSPLIT_CASE(SPMV_F64, double, SPMV_F32, float)
+        return fail(SPMV_ERR_UNSUPPORTED, "spmv_jds_blocked_split: dtype combination");
+#undef BSPLIT_CASE
+        SPMV_CHECK_LAUNCH("spmv_jds_blocked_split");
+    }
+    return launch_combine(n, part, y, vec_dt, alpha, beta, s);
 }
 
 }  // extern "C"

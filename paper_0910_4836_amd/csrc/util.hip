@@ -164,6 +164,33 @@ static int stream_grid(int64_t n, int per_thread)
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+template <typename T>
+__global__ void combine_kernel(int32_t n, const double *__restrict__ part, T *__restrict__ y, double alpha,
+                               double beta)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < SPLIT_PARTS; ++k) s += __builtin_nontemporal_load(part + (int64_t)k * n + i);
+        write_y(y, i, s, alpha, beta);
+    }
+}
+
+spmv_status launch_combine(int32_t n, const double *part, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                           hipStream_t s)
+{
+    if (n == 0) return SPMV_OK;
+    const int grid = stream_grid(n, 4);
+    if (vec_dt == SPMV_F64)
+        combine_kernel<double><<<grid, 256, 0, s>>>(n, part, (double *)y, alpha, beta);
+    else
+        combine_kernel<float><<<grid, 256, 0, s>>>(n, part, (float *)y, alpha, beta);
+    SPMV_CHECK_LAUNCH("split combine");
+    return SPMV_OK;
+}
+
 }  // namespace spmv
 
 using namespace spmv;
@@ -200,6 +227,11 @@ spmv_status spmv_axpby(int64_t n, double alpha, const void *x, double beta, void
         axpby_kernel<float><<<grid, 256, 0, as_stream(stream)>>>(n, alpha, (const float *)x, beta, (float *)y);
     SPMV_CHECK_LAUNCH("spmv_axpby");
     return SPMV_OK;
+}
+
+size_t spmv_split_workspace_size(int32_t n_rows)
+{
+    return (size_t)(n_rows > 0 ? n_rows : 1) * SPLIT_PARTS * sizeof(double) + 256;
 }
 
 size_t spmv_dot_workspace_size(int64_t n)

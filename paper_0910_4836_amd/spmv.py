@@ -427,6 +427,107 @@ def spmv_stream_read(b, part):
     call("spmv_stream_read", b.numel(), _p(b), _p(part), part.numel(), _stream())
 
 
+# --------------------------------------------------------------------------- column-split forms
+
+
+def _ptr_array(ts):
+    return (C.c_void_p * len(ts))(*[t.data_ptr() if t is not None and t.data_ptr() else None for t in ts])
+
+
+class Split:
+    """A matrix cut into SPLIT_PARTS column blocks (spmv_split_columns); part k
+    is an ordinary CRS matrix and gets JDS / blocked-JDS forms on demand."""
+
+    def __init__(self, A: CSR, width: int = 0):
+        lib = _lib.load()
+        P = _lib.SPLIT_PARTS
+        dev = A.device
+        self.n, self.n_cols = A.n_rows, A.n_cols
+        nnz = A.nnz
+        ws = _ws(lib.spmv_split_columns_workspace_size(A.n_rows, nnz), dev)
+        self.row_ptr_all = torch.empty(P * (A.n_rows + 1), dtype=_I32, device=dev)
+        self.col = torch.empty(max(nnz, 1), dtype=_I32, device=dev)
+        self.val = torch.empty(max(nnz, 1), dtype=A.val.dtype, device=dev)
+        self.bounds = np.zeros(P + 1, dtype=np.int64)
+        call("spmv_split_columns", A.n_rows, A.n_cols, nnz, _p(A.row_ptr), _p(A.col_idx), _p(A.val),
+             dtype_code(A.val.dtype), width, _p(self.row_ptr_all), _p(self.col), _p(self.val),
+             _h_i64(self.bounds), _p(ws), ws.numel(), _stream())
+        self.ws = _ws(lib.spmv_split_workspace_size(A.n_rows), dev)
+        self.parts = [self.part_csr(k) for k in range(P)]
+        # CRS plans of the parts, one after the other
+        plans, self.plan_off, self.n_blocks = [], np.zeros(P, np.int32), np.zeros(P, np.int32)
+        off = 0
+        for k, Ak in enumerate(self.parts):
+            spmv_crs_plan(Ak)
+            plans.append(Ak.plan[:Ak.n_blocks + 1])
+            self.plan_off[k], self.n_blocks[k] = off, Ak.n_blocks
+            off += Ak.n_blocks + 1
+        self.plan_all = torch.cat(plans)
+        self.block_nnz = 0
+        self.jds = None
+        self.blocked = {}
+
+    def part_csr(self, k: int) -> CSR:
+        n = self.n
+        a, b = int(self.bounds[k]), int(self.bounds[k + 1])
+        return CSR(n, self.n_cols, self.row_ptr_all[k * (n + 1):(k + 1) * (n + 1)], self.col[a:b], self.val[a:b])
+
+    def with_values(self, val: torch.Tensor) -> "Split":
+        """Same structure, values (part-major order) of another dtype."""
+        S = Split.__new__(Split)
+        S.__dict__.update(self.__dict__)
+        S.val = val
+        S.parts = [S.part_csr(k) for k in range(_lib.SPLIT_PARTS)]
+        for Ak, A0 in zip(S.parts, self.parts):
+            Ak.plan, Ak.n_blocks, Ak.block_nnz = A0.plan, A0.n_blocks, A0.block_nnz
+        S.jds = None
+        S.blocked = {}
+        return S
+
+    def jds_parts(self):
+        if self.jds is None:
+            self.jds = [jds_from_csr(Ak) for Ak in self.parts]
+        return self.jds
+
+    def blocked_parts(self, C_: int = 64):
+        if C_ not in self.blocked:
+            self.blocked[C_] = [jds_blocked_from_jds(J, C_) for J in self.jds_parts()]
+        return self.blocked[C_]
+
+
+def spmv_crs_split(S: Split, x, y=None, alpha=1.0, beta=0.0):
+    y = _out_vec(y, S.n, x, beta)
+    call("spmv_crs_split", S.n, S.n_cols, _p(S.row_ptr_all), _p(S.col), _p(S.val), _h_i64(S.bounds),
+         dtype_code(S.val.dtype), _p(S.plan_all), _h_i32(S.plan_off), _h_i32(S.n_blocks), S.block_nnz, _p(x), _p(y),
+         dtype_code(x.dtype), float(alpha), float(beta), _p(S.ws), S.ws.numel(), _stream())
+    return y
+
+
+def spmv_jds_split(S: Split, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0):
+    Js = S.jds_parts()
+    y = _out_vec(y, S.n, x, beta)
+    S._keep = [J.h_jd_ptr for J in Js]
+    hptr = (C.c_void_p * len(Js))(*[J.h_jd_ptr.ctypes.data for J in Js])
+    ndiag = np.array([J.ndiag for J in Js], dtype=np.int32)
+    call("spmv_jds_split", S.n, _ptr_array([J.perm for J in Js]), _ptr_array([J.jd_ptr for J in Js]), hptr,
+         _h_i32(ndiag), _ptr_array([J.jd_col for J in Js]), _ptr_array([J.jd_val for J in Js]),
+         dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll,
+         max_iters, _p(S.ws), S.ws.numel(), _stream())
+    return y
+
+
+def spmv_jds_blocked_split(S: Split, x, y=None, alpha=1.0, beta=0.0, C_=64, rows_per_wave=0, unroll=0,
+                           max_iters=0):
+    Bs = S.blocked_parts(C_)
+    y = _out_vec(y, S.n, x, beta)
+    hnd = (C.c_void_p * len(Bs))(*[B.h_slice_nd.ctypes.data for B in Bs])
+    call("spmv_jds_blocked_split", S.n, C_, _ptr_array([B.perm for B in Bs]), _ptr_array([B.slice_ptr for B in Bs]),
+         _ptr_array([B.slice_nd for B in Bs]), hnd, _ptr_array([B.bl_col for B in Bs]),
+         _ptr_array([B.bl_val for B in Bs]), dtype_code(Bs[0].bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype),
+         float(alpha), float(beta), rows_per_wave, unroll, max_iters, _p(S.ws), S.ws.numel(), _stream())
+    return y
+
+
 # --------------------------------------------------------------------------- many matrices
 
 

@@ -45,7 +45,11 @@ def quantised(R, dt):
 def kernels(A, vt):
     J = sp.jds_from_csr(A)
     B = sp.jds_blocked_from_jds(J, 64)
+    S = sp.Split(A)
     return {
+        "crs_split": lambda x: sp.spmv_crs_split(S, x),
+        "jds_split": lambda x: sp.spmv_jds_split(S, x),
+        "blocked_split": lambda x: sp.spmv_jds_blocked_split(S, x),
         "crs": lambda x: sp.spmv_crs(A, x),
         "crs_wave": lambda x: sp.spmv_crs(A, x, use_plan=False),
         "jds": lambda x: sp.spmv_jds(J, x),

@@ -16,10 +16,15 @@ pytestmark = pytest.mark.gpu
 sp = pytest.importorskip("paper_0910_4836_amd")
 
 
-def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_iters=(0,)):
+def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_iters=(0,), split=True):
     """Yields (name, fn(x, y, alpha, beta)) for every kernel variant on matrix A."""
     yield "crs", lambda x, y, a, b: sp.spmv_crs(A, x, y, a, b)
     yield "crs_wave", lambda x, y, a, b: sp.spmv_crs(A, x, y, a, b, use_plan=False)
+    if split and not symperm:
+        S = sp.Split(A)
+        yield "crs_split", lambda x, y, a, b: sp.spmv_crs_split(S, x, y, a, b)
+        yield "jds_split", lambda x, y, a, b: sp.spmv_jds_split(S, x, y, a, b)
+        yield "blocked_split", lambda x, y, a, b: sp.spmv_jds_blocked_split(S, x, y, a, b, C_=Cs[-1])
     J = sp.jds_from_csr(A, symperm=symperm)
     for u in unrolls:
         for mi in max_iters:
@@ -128,6 +133,22 @@ def test_empty_matrix_and_single_row():
     vv = np.random.default_rng(1).standard_normal(nc)
     xx = np.random.default_rng(2).uniform(-1, 1, nc)
     run_case(r, c, vv, 1, nc, xx)
+
+
+def test_split_structure_is_a_column_partition():
+    """Every part holds exactly the entries of its column range, in CRS order."""
+    r, c, v, nr, nc, _ = rand_coo(60, 3000, 5000, 0.004, empty_rows=0.1, long_rows=4, long_len=3000)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    S = sp.Split(gpu_csr(sp, r, c, v, nr, nc))
+    width = -(-(-(-nc // 8)) // 64) * 64
+    rows = R.row_index()
+    for k in range(8):
+        Pk = S.parts[k]
+        sel = (R.col // width) == k
+        want_ptr = np.concatenate([[0], np.cumsum(np.bincount(rows[sel], minlength=nr))])
+        assert np.array_equal(to_np(Pk.row_ptr), want_ptr)
+        assert np.array_equal(to_np(Pk.col_idx), R.col[sel])
+        assert np.array_equal(to_np(Pk.val), R.val[sel])
 
 
 def test_deterministic_repeat():
