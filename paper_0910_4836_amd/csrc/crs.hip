@@ -2,12 +2,14 @@
 // is a sparse scalar product of its stored values with the gathered x).
 //
 // gfx950 design: the rows are cut, once per matrix, into blocks of consecutive
-// rows holding at most block_nnz entries (and at most 256 rows); a row longer
-// than that is a block of its own.  One 256-lane workgroup per block:
+// rows holding at most block_nnz entries and at most 256 rows (2048 rows when
+// none of them has more than 16 entries); a row longer than block_nnz is a
+// block of its own.  One 256-lane workgroup per block:
 //   * multi-row block ("stream" mode): the lanes walk the block's entries in
 //     order - fully coalesced val/col reads, independent x gathers - and park
 //     the products in LDS; then G lanes per row (G = 256/rows, a power of two
-//     up to 64) add their row's products and combine with a fixed shuffle tree.
+//     up to 64) add their row's products and combine with a fixed shuffle tree,
+//     or, in a block of more than 256 short rows, one lane adds each row.
 //   * single-row block ("vector" mode): all 256 lanes stride over the row with
 //     fused multiply-adds, then a fixed wave tree and an ordered sum over the
 //     four waves.
@@ -25,7 +27,9 @@ namespace spmv {
 constexpr int CRS_THREADS = 256;
 constexpr int CRS_DEFAULT_BLOCK_NNZ = 1024;
 constexpr int CRS_MAX_BLOCK_NNZ = 4096;
-constexpr int CRS_MAX_BLOCK_ROWS = 256;
+constexpr int CRS_MAX_BLOCK_ROWS = 256;         // rows of a block in general
+constexpr int CRS_MAX_SHORT_BLOCK_ROWS = 2048;  // rows of a block of short rows only
+constexpr int CRS_SHORT_ROW = 16;               // "short": at most this many entries
 
 template <bool WIDE, typename VT, typename XT, typename OT>
 __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, const VT *__restrict__ val,
@@ -87,27 +91,48 @@ __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_p
         return;
     }
 
-    // stream mode: products of the whole block into LDS (ne <= block_nnz)
-    constexpr int U = 4;
+    // stream mode: products of the whole block into LDS (ne <= block_nnz).
+    // Each lane first issues all U loads of val/col, then all U gathers, so a
+    // workgroup keeps U*256 independent reads in flight.
+    constexpr int U = 8;
     for (int32_t k0 = 0; k0 < ne; k0 += U * CRS_THREADS) {
         int32_t c[U];
         VT v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int32_t k = k0 + u * CRS_THREADS + (int32_t)threadIdx.x;
+            c[u] = 0;
+            v[u] = VT{};
             if (k < ne) {
                 c[u] = ld_stream(col + e0 + k);
                 v[u] = ld_stream(val + e0 + k);
             }
         }
+        XT xv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int32_t k = k0 + u * CRS_THREADS + (int32_t)threadIdx.x;
-            if (k < ne) prod[k] = Acc<F64>::mac((acc_t)0, v[u], x[c[u]]);
+            xv[u] = k < ne ? x[c[u]] : XT(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int32_t k = k0 + u * CRS_THREADS + (int32_t)threadIdx.x;
+            if (k < ne) prod[k] = Acc<F64>::mac((acc_t)0, v[u], xv[u]);
         }
     }
     __syncthreads();
 
+    if (nr > CRS_THREADS) {
+        // many short rows: one lane per row, rows t, t+256, ... (the planner
+        // admits more than 256 rows only when every row is short)
+        for (int32_t g = (int32_t)threadIdx.x; g < nr; g += CRS_THREADS) {
+            const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
+            acc_t s = 0;
+            for (int32_t k = rs; k < re; ++k) s += prod[k];
+            write_y(y, (int64_t)r0 + g, (double)s, alpha, beta);
+        }
+        return;
+    }
     // G lanes per row, G = largest power of two <= 256/nr, at most 64
     int G = 64;
     while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
@@ -257,26 +282,29 @@ __global__ __launch_bounds__(CRS_THREADS) void spmm_crs_kernel(const int32_t *__
     typedef typename Acc<F64>::T acc_t;
     int G = 64;
     while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
-    const int g = (int)threadIdx.x / G, l = (int)threadIdx.x % G;
-    acc_t acc[KB];
+    const int l = (int)threadIdx.x % G;
+    // blocks of more than 256 (short) rows take several rounds of 256 rows
+    for (int32_t g = (int32_t)threadIdx.x / G; g - (int32_t)threadIdx.x / G < nr; g += CRS_THREADS / G) {
+        acc_t acc[KB];
 #pragma unroll
-    for (int j = 0; j < KB; ++j) acc[j] = 0;
-    if (g < nr) {
-        const int32_t rs = row_ptr[r0 + g], re = row_ptr[r0 + g + 1];
-        for (int32_t e = rs + l; e < re; e += G) {
-            const int32_t c = ld_stream(col + e);
-            const VT v = ld_stream(val + e);
+        for (int j = 0; j < KB; ++j) acc[j] = 0;
+        if (g < nr) {
+            const int32_t rs = row_ptr[r0 + g], re = row_ptr[r0 + g + 1];
+            for (int32_t e = rs + l; e < re; e += G) {
+                const int32_t c = ld_stream(col + e);
+                const VT v = ld_stream(val + e);
+#pragma unroll
+                for (int j = 0; j < KB; ++j)
+                    if (j < kb) acc[j] = Acc<F64>::mac(acc[j], v, Xc[c + (int64_t)j * ldx]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] = group_sum(acc[j], G);
+        if (g < nr && l == 0) {
 #pragma unroll
             for (int j = 0; j < KB; ++j)
-                if (j < kb) acc[j] = Acc<F64>::mac(acc[j], v, Xc[c + (int64_t)j * ldx]);
+                if (j < kb) write_y(Yc + (int64_t)j * ldy, (int64_t)r0 + g, (double)acc[j], alpha, beta);
         }
-    }
-#pragma unroll
-    for (int j = 0; j < KB; ++j) acc[j] = group_sum(acc[j], G);
-    if (g < nr && l == 0) {
-#pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < kb) write_y(Yc + (int64_t)j * ldy, (int64_t)r0 + g, (double)acc[j], alpha, beta);
     }
 }
 
@@ -320,22 +348,27 @@ void crs_plan_rows(int32_t n_rows, const int32_t *rp, int32_t T, std::vector<int
     out.clear();
     out.push_back(0);
     int32_t start = 0;
-    int64_t cur = 0;
+    int64_t cur = 0, longest = 0;
     for (int32_t r = 0; r < n_rows; ++r) {
-        int64_t len = (int64_t)rp[r + 1] - rp[r];
-        int32_t nr = r - start;
-        if (nr > 0 && (cur + len > T || nr >= CRS_MAX_BLOCK_ROWS)) {
+        const int64_t len = (int64_t)rp[r + 1] - rp[r];
+        const int32_t nr = r - start;
+        const int64_t lg = std::max(longest, len);
+        const int32_t row_cap = lg <= CRS_SHORT_ROW ? CRS_MAX_SHORT_BLOCK_ROWS : CRS_MAX_BLOCK_ROWS;
+        if (nr > 0 && (cur + len > T || nr >= row_cap)) {
             out.push_back(r);
             start = r;
             cur = 0;
+            longest = 0;
         }
         if (len > T) {                 // a long row is a block of its own
             out.push_back(r + 1);
             start = r + 1;
             cur = 0;
+            longest = 0;
             continue;
         }
         cur += len;
+        longest = std::max(longest, len);
     }
     if (start < n_rows) out.push_back(n_rows);
 }

@@ -438,7 +438,7 @@ class Split:
     """A matrix cut into SPLIT_PARTS column blocks (spmv_split_columns); part k
     is an ordinary CRS matrix and gets JDS / blocked-JDS forms on demand."""
 
-    def __init__(self, A: CSR, width: int = 0):
+    def __init__(self, A: CSR, width: int = 0, block_nnz: int = 0):
         lib = _lib.load()
         P = _lib.SPLIT_PARTS
         dev = A.device
@@ -458,12 +458,12 @@ class Split:
         plans, self.plan_off, self.n_blocks = [], np.zeros(P, np.int32), np.zeros(P, np.int32)
         off = 0
         for k, Ak in enumerate(self.parts):
-            spmv_crs_plan(Ak)
+            spmv_crs_plan(Ak, block_nnz)
             plans.append(Ak.plan[:Ak.n_blocks + 1])
             self.plan_off[k], self.n_blocks[k] = off, Ak.n_blocks
             off += Ak.n_blocks + 1
         self.plan_all = torch.cat(plans)
-        self.block_nnz = 0
+        self.block_nnz = block_nnz
         self.jds = None
         self.blocked = {}
 

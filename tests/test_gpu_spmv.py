@@ -20,6 +20,9 @@ def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_
     """Yields (name, fn(x, y, alpha, beta)) for every kernel variant on matrix A."""
     yield "crs", lambda x, y, a, b: sp.spmv_crs(A, x, y, a, b)
     yield "crs_wave", lambda x, y, a, b: sp.spmv_crs(A, x, y, a, b, use_plan=False)
+    for bn in (256, 4096):
+        Ab = sp.spmv_crs_plan(sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
+        yield f"crs_b{bn}", (lambda Ab=Ab: lambda x, y, a, b: sp.spmv_crs(Ab, x, y, a, b))()
     if split and not symperm:
         S = sp.Split(A)
         yield "crs_split", lambda x, y, a, b: sp.spmv_crs_split(S, x, y, a, b)
@@ -133,6 +136,47 @@ def test_empty_matrix_and_single_row():
     vv = np.random.default_rng(1).standard_normal(nc)
     xx = np.random.default_rng(2).uniform(-1, 1, nc)
     run_case(r, c, vv, 1, nc, xx)
+
+
+@pytest.mark.parametrize("block_nnz", [256, 1024, 4096])
+def test_blocks_of_many_short_rows(block_nnz):
+    """Rows of 0-3 entries (blocks of up to 2048 rows, one lane per row) mixed
+    with runs of 17-entry rows (256-row cap) and a few long rows."""
+    rng = np.random.default_rng(70 + block_nnz)
+    nr, nc = 30000, 20000
+    lens = rng.integers(0, 4, nr)
+    lens[10000:11000] = 17                      # a run of rows just above "short"
+    lens[rng.choice(nr, 30, replace=False)] = rng.integers(4, 40, 30)
+    lens[rng.choice(nr, 5, replace=False)] = 5000
+    r = np.repeat(np.arange(nr, dtype=np.int32), lens)
+    c = np.concatenate([rng.choice(nc, L, replace=False) for L in lens]).astype(np.int32)
+    v = rng.standard_normal(len(r))
+    x = rng.uniform(-1, 1, nc)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    want = oracle.spmv_crs(R, x)
+    D = oracle.row_absdot(R, x)
+    A = sp.spmv_crs_plan(gpu_csr(sp, r, c, v, nr, nc), block_nnz)
+    plan = to_np(A.plan)
+    sizes = np.diff(plan)
+    if block_nnz >= 1024:
+        assert sizes.max() > 256                  # the many-short-row path is taken
+    rp = to_np(A.row_ptr)
+    for b in np.nonzero(sizes > 256)[0]:          # ... only for blocks of short rows
+        assert np.diff(rp[plan[b]:plan[b + 1] + 1]).max() <= 16 and sizes[b] <= 2048
+    assert max_err(sp.spmv_crs(A, to_dev(x)), want, D) <= FP64_TOL
+    X = rng.uniform(-1, 1, (nc, 9))
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda").t()        # column-major (n, k)
+    want_X = oracle.spmm_crs(R, X)
+    for il in (True, False):
+        Y = to_np(sp.spmm_crs(A, Xd, interleave=il))
+        for j in range(9):
+            e = oracle.rel_err(Y[:, j], want_X[:, j], oracle.row_absdot(R, X[:, j])).max()
+            assert e <= FP64_TOL, (il, j, e)
+    # integer values: bit-exact
+    vi = rng.integers(-8, 9, len(r)).astype(np.float64)
+    xi = synth.integer_vector(nc, rng)
+    Ai = sp.spmv_crs_plan(gpu_csr(sp, r, c, vi, nr, nc), block_nnz)
+    assert np.array_equal(to_np(sp.spmv_crs(Ai, to_dev(xi))), oracle.spmv_crs(oracle.csr_from_coo(nr, nc, r, c, vi), xi))
 
 
 def test_split_structure_is_a_column_partition():
