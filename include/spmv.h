@@ -151,11 +151,9 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
 
 /* Row-block plan for spmv_crs / spmm_crs: plan[0..n_blocks] are row
  * boundaries.  Consecutive rows are grouped while the group holds at most
- * block_nnz entries (0 = library default) and at most 256 rows, or at most
- * 2048 rows if none of them has more than 16 entries; a row longer than
- * block_nnz is a block of its own.  The kernels accept any plan whose blocks
- * are either a single row or hold at most block_nnz entries; a block of
- * more than 256 rows is summed one lane per row.  If plan_cap < n_blocks+1 returns
+ * block_nnz entries (0 = library default, 1024) and at most 2048 rows; a row
+ * longer than block_nnz is a block of its own.  The kernels accept any plan
+ * whose blocks are either a single row or hold at most block_nnz entries.  If plan_cap < n_blocks+1 returns
  * SPMV_ERR_CAPACITY with *h_n_blocks set.  Synchronises (reads row_ptr). */
 spmv_status spmv_crs_plan(int32_t n_rows, const int32_t *row_ptr, int32_t block_nnz, int32_t *plan,
                           int32_t plan_cap, int32_t *h_n_blocks, void *stream);
@@ -277,54 +275,72 @@ spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd
  * columns instead: A = sum_k A_k, A_k holding the entries whose column lies
  * in [k*width, (k+1)*width), k < SPMV_SPLIT_PARTS (= the MI355X's 8 XCDs).
  * Part k is processed on XCD k, so its x gathers stay inside one 1/8 slice
- * of x that fits that XCD's L2; each part writes an FP64 partial result and
- * a last kernel forms y = alpha * sum_k partial_k + beta * y, adding the
- * partials in order k = 0, 1, ... (deterministic).  Each A_k is an ordinary
- * CRS, JDS or blocked-JDS matrix.  Every part accumulates in FP64 whatever
- * the value type (FP32 / BF16 values are widened exactly, FP32 vectors are
- * read as stored): a part sees only a piece of each row, so the rule "rows
- * longer than SPMV_WIDE_ROW_NNZ entries accumulate in FP64" of the unsplit
- * calls could not be applied per part; FP64 throughout satisfies it and the
- * bound of the FP32 rule for the shorter rows.
+ * of x that fits that XCD's L2.  A_k keeps only the rows that hold at least
+ * one of its entries ("compressed rows", in ascending row order); each of
+ * them owns one FP64 "slot" for its partial result.  The slots of row i are
+ * slot_ptr[i] .. slot_ptr[i+1]-1, one per part present in the row, in part
+ * order, and a last kernel forms y_i = alpha * (sum of row i's slots, in
+ * slot order) + beta * y_i (deterministic).  Every part accumulates in FP64
+ * whatever the value type (FP32 / BF16 values are widened exactly, FP32
+ * vectors are read as stored): a part sees only a piece of each row, so the
+ * rule "rows longer than SPMV_WIDE_ROW_NNZ entries accumulate in FP64" of
+ * the unsplit calls could not be applied per part; FP64 throughout
+ * satisfies it and the bound of the FP32 rule for the shorter rows.
  *
- * spmv_split_columns (setup, synchronises): reorders a CRS matrix part by
- * part (each part keeps its entries in CRS order): col_out[nnz], val_out[nnz]
- * and row_ptr_all[SPMV_SPLIT_PARTS*(n_rows+1)].  h_bounds[0..8] returns the
- * part offsets; part k is the CRS matrix (row_ptr_all + k*(n_rows+1),
- * col_out + h_bounds[k], val_out + h_bounds[k]) with h_bounds[k+1] -
- * h_bounds[k] entries (its row_ptr starts at 0).  width = 0 picks
- * ceil(n_cols/8) rounded up to 64.  Compute calls need ws of
- * spmv_split_workspace_size(n) bytes for the partial results (not SYMPERM). */
+ * spmv_split_columns (setup, synchronises) reorders a CRS matrix part by
+ * part.  With cap = min(nnz, SPMV_SPLIT_PARTS*n_rows):
+ *   col_out[nnz], val_out[nnz]: part k's entries at h_bounds[k] ..
+ *       h_bounds[k+1]-1, in CRS order;
+ *   h_row_off[0..8]: part k's compressed rows are numbers h_row_off[k] ..
+ *       h_row_off[k+1]-1; h_row_off[8] = n_slots (<= cap);
+ *   row_ptr_all[cap + SPMV_SPLIT_PARTS]: part k's compressed row pointer,
+ *       h_row_off[k+1]-h_row_off[k]+1 entries at row_ptr_all + h_row_off[k]
+ *       + k, relative to h_bounds[k];
+ *   dest_all[cap]: slot of each compressed row (part k's at dest_all +
+ *       h_row_off[k]);
+ *   slot_ptr[n_rows+1].
+ * So part k is the CRS matrix (h_row_off[k+1]-h_row_off[k] rows, row_ptr_all +
+ * h_row_off[k] + k, col_out + h_bounds[k], val_out + h_bounds[k]) whose row j
+ * writes slot dest_all[h_row_off[k] + j].  width = 0 picks ceil(n_cols/8)
+ * rounded up to 64.  Compute calls need ws of spmv_split_workspace_size(
+ * n_slots) bytes for the slots; calls sharing one ws must not overlap. */
 #define SPMV_SPLIT_PARTS 8
 size_t spmv_split_columns_workspace_size(int32_t n_rows, int64_t nnz);
 spmv_status spmv_split_columns(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                                const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t width,
-                               int32_t *row_ptr_all, int32_t *col_out, void *val_out, int64_t *h_bounds,
-                               void *ws, size_t ws_bytes, void *stream);
-size_t spmv_split_workspace_size(int32_t n_rows);
+                               int32_t *row_ptr_all, int32_t *dest_all, int32_t *slot_ptr, int32_t *col_out,
+                               void *val_out, int64_t *h_bounds, int64_t *h_row_off, void *ws, size_t ws_bytes,
+                               void *stream);
+size_t spmv_split_workspace_size(int64_t n_slots);
 /* CRS parts as returned by spmv_split_columns; plan_all holds the
  * spmv_crs_plan of every part one after the other (part k's at plan_all +
  * h_plan_off[k], h_n_blocks[k] blocks, built with block_nnz). */
-spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr_all, const int32_t *col_idx,
-                           const void *val, const int64_t *h_bounds, spmv_dtype val_dt, const int32_t *plan_all,
+spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr_all, const int32_t *dest_all,
+                           const int32_t *slot_ptr, const int32_t *col_idx, const void *val, const int64_t *h_bounds,
+                           const int64_t *h_row_off, spmv_dtype val_dt, const int32_t *plan_all,
                            const int32_t *h_plan_off, const int32_t *h_n_blocks, int32_t block_nnz,
                            const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, void *ws,
                            size_t ws_bytes, void *stream);
-/* JDS parts (each from spmv_jds_from_csr of part k, without SYMPERM): host
- * arrays of SPMV_SPLIT_PARTS device pointers (h_perm, h_jd_ptr, h_jd_col,
- * h_jd_val), of host pointers (h_jd_ptr_host) and of sizes (h_ndiag). */
-spmv_status spmv_jds_split(int32_t n, const int32_t *const *h_perm, const int32_t *const *h_jd_ptr,
-                           const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag,
+/* JDS parts: part k is spmv_jds_from_csr of the CRS part k (without
+ * SYMPERM) whose perm has been mapped through the part's dest entries, i.e.
+ * h_perm[k][r] = dest_all[h_row_off[k] + perm_k[r]] is the slot of permuted
+ * row r.  Host arrays of SPMV_SPLIT_PARTS device pointers (h_perm, h_jd_ptr,
+ * h_jd_col, h_jd_val), of host pointers (h_jd_ptr_host) and of sizes
+ * (h_ndiag). */
+spmv_status spmv_jds_split(int32_t n, const int32_t *slot_ptr, const int64_t *h_row_off, const int32_t *const *h_perm,
+                           const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag,
                            const int32_t *const *h_jd_col, const void *const *h_jd_val, spmv_dtype val_dt,
                            const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, int32_t unroll,
                            int32_t max_iters, void *ws, size_t ws_bytes, void *stream);
-/* Blocked-JDS parts (slice height C for all parts). */
-spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *const *h_perm,
-                                   const int64_t *const *h_slice_ptr, const int32_t *const *h_slice_nd,
-                                   const int32_t *const *h_slice_nd_host, const int32_t *const *h_bl_col,
-                                   const void *const *h_bl_val, spmv_dtype val_dt, const void *x, void *y,
-                                   spmv_dtype vec_dt, double alpha, double beta, int32_t rows_per_wave,
-                                   int32_t unroll, int32_t max_iters, void *ws, size_t ws_bytes, void *stream);
+/* Blocked-JDS parts (slice height C for all parts), built from the JDS parts
+ * above, so their perm gives slots too. */
+spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *slot_ptr, const int64_t *h_row_off,
+                                   const int32_t *const *h_perm, const int64_t *const *h_slice_ptr,
+                                   const int32_t *const *h_slice_nd, const int32_t *const *h_slice_nd_host,
+                                   const int32_t *const *h_bl_col, const void *const *h_bl_val, spmv_dtype val_dt,
+                                   const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                                   int32_t rows_per_wave, int32_t unroll, int32_t max_iters, void *ws,
+                                   size_t ws_bytes, void *stream);
 
 /* ======================================================================== */
 /* Many matrices in one launch                                               */

@@ -69,14 +69,15 @@ SIGNATURES = {
                         _u32, _p, _sz, _p]),
     "spmv_grad_vals_jds": (_int, [_i32, _p, _p, _i32p, _i32, _i64, _p, _p, _p, _p, _int, _f64, _f64, _u32, _p]),
     "spmv_split_columns_workspace_size": (_sz, [_i32, _i64]),
-    "spmv_split_columns": (_int, [_i32, _i32, _i64, _p, _p, _p, _int, _i32, _p, _p, _p, _i64p, _p, _sz, _p]),
-    "spmv_split_workspace_size": (_sz, [_i32]),
-    "spmv_crs_split": (_int, [_i32, _i32, _p, _p, _p, _i64p, _int, _p, _i32p, _i32p, _i32, _p, _p, _int, _f64, _f64,
-                              _p, _sz, _p]),
-    "spmv_jds_split": (_int, [_i32, _vpp, _vpp, _vpp, _i32p, _vpp, _vpp, _int, _p, _p, _int, _f64, _f64, _i32, _i32,
-                              _p, _sz, _p]),
-    "spmv_jds_blocked_split": (_int, [_i32, _i32, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, _int, _p, _p, _int, _f64, _f64,
-                                      _i32, _i32, _i32, _p, _sz, _p]),
+    "spmv_split_columns": (_int, [_i32, _i32, _i64, _p, _p, _p, _int, _i32, _p, _p, _p, _p, _p, _i64p, _i64p, _p, _sz,
+                                  _p]),
+    "spmv_split_workspace_size": (_sz, [_i64]),
+    "spmv_crs_split": (_int, [_i32, _i32, _p, _p, _p, _p, _p, _i64p, _i64p, _int, _p, _i32p, _i32p, _i32, _p, _p, _int,
+                              _f64, _f64, _p, _sz, _p]),
+    "spmv_jds_split": (_int, [_i32, _p, _i64p, _vpp, _vpp, _vpp, _i32p, _vpp, _vpp, _int, _p, _p, _int, _f64, _f64,
+                              _i32, _i32, _p, _sz, _p]),
+    "spmv_jds_blocked_split": (_int, [_i32, _i32, _p, _i64p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, _int, _p, _p, _int,
+                                      _f64, _f64, _i32, _i32, _i32, _p, _sz, _p]),
     "spmv_batched_plan": (_int, [_i32, _i32p, _i32p, _i64p, _i64p, _i64p, _i64p, _i32p, _i32, _p, _i64, _i64p,
                                  _p]),
     "spmv_batched": (_int, [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _p]),

@@ -35,10 +35,10 @@ spmv_status hip_fail(hipError_t e, const char *what);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-// y = alpha * sum_k part[k*n + i] + beta * y (k = 0 .. SPMV_SPLIT_PARTS-1 in
-// order, FP64), the last step of the column-split products (util.hip).
-spmv_status launch_combine(int32_t n, const double *part, void *y, spmv_dtype vec_dt, double alpha, double beta,
-                           hipStream_t s);
+// y_i = alpha * sum of slots[slot_ptr[i] .. slot_ptr[i+1]) (in slot order,
+// FP64) + beta * y_i: the last step of the column-split products (util.hip).
+spmv_status launch_combine(int32_t n, const int32_t *slot_ptr, const double *slots, void *y, spmv_dtype vec_dt,
+                           double alpha, double beta, hipStream_t s);
 
 // Column-major multi-vector kernels (crs.hip, jds.hip), the no-workspace path
 // of spmm_crs / spmm_jds (spmm.hip).

@@ -591,15 +591,56 @@ __global__ void part_bounds_kernel(const uint32_t *__restrict__ skey, int64_t nn
     GRID_LOOP(p, (int64_t)SPLIT_PARTS + 1) bounds[p] = lower_bound_dev(skey, nnz, (int64_t)p);
 }
 
-// row_ptr of part k, relative to the part's first entry
-__global__ void split_row_ptr_kernel(const int32_t *__restrict__ rowid_sorted, const int64_t *__restrict__ bounds,
-                                     int32_t n, int32_t *__restrict__ row_ptr_all)
+// Compressed rows: a part keeps only the rows holding at least one of its
+// entries.  head[i] = 1 where entry i (part-major order) opens a (row, part)
+// group; the exclusive scan of head numbers the compressed rows.
+__global__ void split_head_kernel(const uint32_t *__restrict__ skey, const int32_t *__restrict__ rowid_s, int64_t nnz,
+                                  int32_t *__restrict__ head)
 {
-    GRID_LOOP(t, (int64_t)SPLIT_PARTS * (n + 1))
+    GRID_LOOP(i, nnz) head[i] = (i == 0 || skey[i] != skey[i - 1] || rowid_s[i] != rowid_s[i - 1]) ? 1 : 0;
+}
+
+// row pointer of each compressed row (relative to its part's first entry) and
+// the parts present in each original row (bit k of mask[row])
+__global__ void split_rows_kernel(const uint32_t *__restrict__ skey, const int32_t *__restrict__ rowid_s,
+                                  const int32_t *__restrict__ head, const int32_t *__restrict__ qidx, int64_t nnz,
+                                  const int64_t *__restrict__ bounds, int32_t *__restrict__ row_ptr_all,
+                                  uint32_t *__restrict__ mask)
+{
+    GRID_LOOP(i, nnz)
     {
-        const int64_t k = t / (n + 1), r = t % (n + 1);
-        const int64_t lo = bounds[k], hi = bounds[k + 1];
-        row_ptr_all[t] = (int32_t)lower_bound_dev(rowid_sorted + lo, hi - lo, r);
+        if (!head[i]) continue;
+        const uint32_t k = skey[i];
+        row_ptr_all[qidx[i] + k] = (int32_t)(i - bounds[k]);
+        atomicOr(mask + rowid_s[i], 1u << k);
+    }
+}
+
+__global__ void split_terminators_kernel(const int64_t *__restrict__ bounds, const int32_t *__restrict__ qidx,
+                                         int32_t *__restrict__ row_ptr_all, int64_t *__restrict__ row_off)
+{
+    const int k = (int)threadIdx.x;
+    if (k <= SPLIT_PARTS) row_off[k] = qidx[bounds[k]];
+    if (k < SPLIT_PARTS) row_ptr_all[qidx[bounds[k + 1]] + k] = (int32_t)(bounds[k + 1] - bounds[k]);
+}
+
+__global__ void popcount_kernel(const uint32_t *__restrict__ mask, int32_t n, int32_t *__restrict__ cnt)
+{
+    GRID_LOOP(i, (int64_t)n) cnt[i] = __popc(mask[i]);
+}
+
+// slot of compressed row (row, k): row's slots are ordered by part
+__global__ void split_dest_kernel(const uint32_t *__restrict__ skey, const int32_t *__restrict__ rowid_s,
+                                  const int32_t *__restrict__ head, const int32_t *__restrict__ qidx, int64_t nnz,
+                                  const uint32_t *__restrict__ mask, const int32_t *__restrict__ slot_ptr,
+                                  int32_t *__restrict__ dest_all)
+{
+    GRID_LOOP(i, nnz)
+    {
+        if (!head[i]) continue;
+        const uint32_t k = skey[i];
+        const int32_t r = rowid_s[i];
+        dest_all[qidx[i]] = slot_ptr[r] + __popc(mask[r] & ((1u << k) - 1u));
     }
 }
 
@@ -1019,16 +1060,19 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
 
 size_t spmv_split_columns_workspace_size(int32_t n_rows, int64_t nnz)
 {
-    (void)n_rows;
-    const size_t n = (size_t)(nnz > 0 ? nnz : 1);
-    return 4 * align_up(sizeof(int32_t) * n, 256) + align_up(sizeof(int64_t) * (SPLIT_PARTS + 1), 256) +
-           radix_ws_bytes((int64_t)n) + 1024;
+    const size_t m = (size_t)(nnz > 0 ? nnz : 1);
+    const size_t n = (size_t)(n_rows > 0 ? n_rows : 1);
+    const size_t sc = scan_ws_elems((int64_t)std::max(m + 1, n + 1));
+    return 5 * align_up(sizeof(int32_t) * m, 256) + align_up(sizeof(int32_t) * (m + 1), 256) +
+           2 * align_up(sizeof(int32_t) * n, 256) + 2 * align_up(sizeof(int64_t) * (SPLIT_PARTS + 1), 256) +
+           align_up(sizeof(int32_t) * sc, 256) + radix_ws_bytes((int64_t)m) + 2048;
 }
 
 spmv_status spmv_split_columns(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                                const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t width,
-                               int32_t *row_ptr_all, int32_t *col_out, void *val_out, int64_t *h_bounds, void *ws,
-                               size_t ws_bytes, void *stream)
+                               int32_t *row_ptr_all, int32_t *dest_all, int32_t *slot_ptr, int32_t *col_out,
+                               void *val_out, int64_t *h_bounds, int64_t *h_row_off, void *ws, size_t ws_bytes,
+                               void *stream)
 {
     SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && nnz >= 0, "spmv_split_columns: negative size");
     if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_split_columns: nnz >= 2^31");
@@ -1036,21 +1080,29 @@ spmv_status spmv_split_columns(int32_t n_rows, int32_t n_cols, int64_t nnz, cons
     if (width == 0) width = (int32_t)(ceil_div(ceil_div(n_cols > 0 ? n_cols : 1, SPLIT_PARTS), 64) * 64);
     SPMV_REQUIRE(width > 0 && (int64_t)width * SPLIT_PARTS >= n_cols,
                  "spmv_split_columns: width * SPMV_SPLIT_PARTS must cover the columns");
-    SPMV_REQUIRE(row_ptr && row_ptr_all && h_bounds, "spmv_split_columns: null pointer");
-    SPMV_REQUIRE(nnz == 0 || (col_idx && val && col_out && val_out), "spmv_split_columns: null arrays");
+    SPMV_REQUIRE(row_ptr && row_ptr_all && slot_ptr && h_bounds && h_row_off, "spmv_split_columns: null pointer");
+    SPMV_REQUIRE(nnz == 0 || (col_idx && val && col_out && val_out && dest_all), "spmv_split_columns: null arrays");
     SPMV_REQUIRE(ws && ws_bytes >= spmv_split_columns_workspace_size(n_rows, nnz),
                  "spmv_split_columns: workspace too small");
     hipStream_t s = as_stream(stream);
     WsCarver wc(ws, ws_bytes);
     const size_t m = (size_t)(nnz > 0 ? nnz : 1);
+    const size_t nn = (size_t)(n_rows > 0 ? n_rows : 1);
     int32_t *rowid = wc.take<int32_t>(m);
     int32_t *rowid_s = wc.take<int32_t>(m);
     uint32_t *keys = wc.take<uint32_t>(m);
     int32_t *perm = wc.take<int32_t>(m);
+    int32_t *head = wc.take<int32_t>(m);
+    int32_t *qidx = wc.take<int32_t>(m + 1);
+    uint32_t *mask = wc.take<uint32_t>(nn);
+    int32_t *cnt = wc.take<int32_t>(nn);
     int64_t *bounds = wc.take<int64_t>(SPLIT_PARTS + 1);
+    int64_t *row_off = wc.take<int64_t>(SPLIT_PARTS + 1);
+    int32_t *scan_ws = wc.take<int32_t>(scan_ws_elems((int64_t)std::max(m + 1, nn + 1)));
     const size_t rws_bytes = radix_ws_bytes((int64_t)m);
     void *rws = wc.take<char>(rws_bytes);
     if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_split_columns: workspace too small");
+    if (n_rows > 0) SPMV_HIP(hipMemsetAsync(mask, 0, sizeof(uint32_t) * n_rows, s));
     if (nnz > 0) {
         row_of_entries_kernel<<<grid_for(nnz), 256, 0, s>>>(row_ptr, n_rows, nnz, rowid);
         part_key_kernel<<<grid_for(nnz), 256, 0, s>>>(col_idx, nnz, width, keys);
@@ -1069,12 +1121,28 @@ spmv_status spmv_split_columns(int32_t n_rows, int32_t n_cols, int64_t nnz, cons
             gather_split_kernel<uint16_t><<<grid_for(nnz), 256, 0, s>>>(perm, nnz, col_idx, (const uint16_t *)val, rowid,
                                                                          col_out, (uint16_t *)val_out, rowid_s);
         SPMV_CHECK_LAUNCH("split gather");
+        split_head_kernel<<<grid_for(nnz), 256, 0, s>>>(keys, rowid_s, nnz, head);
+        SPMV_CHECK_LAUNCH("split heads");
     }
+    spmv_status st = exclusive_scan<int32_t, int32_t>(head, nnz, qidx, scan_ws, s);
+    if (st != SPMV_OK) return st;
     part_bounds_kernel<<<1, 64, 0, s>>>(keys, nnz, bounds);
-    split_row_ptr_kernel<<<grid_for((int64_t)SPLIT_PARTS * (n_rows + 1)), 256, 0, s>>>(rowid_s, bounds, n_rows,
-                                                                                       row_ptr_all);
-    SPMV_CHECK_LAUNCH("split row_ptr");
+    SPMV_CHECK_LAUNCH("split bounds");
+    if (nnz > 0) {
+        split_rows_kernel<<<grid_for(nnz), 256, 0, s>>>(keys, rowid_s, head, qidx, nnz, bounds, row_ptr_all, mask);
+        SPMV_CHECK_LAUNCH("split rows");
+    }
+    split_terminators_kernel<<<1, 64, 0, s>>>(bounds, qidx, row_ptr_all, row_off);
+    popcount_kernel<<<grid_for(n_rows), 256, 0, s>>>(mask, n_rows, cnt);
+    SPMV_CHECK_LAUNCH("split slots");
+    st = exclusive_scan<int32_t, int32_t>(cnt, n_rows, slot_ptr, scan_ws, s);
+    if (st != SPMV_OK) return st;
+    if (nnz > 0) {
+        split_dest_kernel<<<grid_for(nnz), 256, 0, s>>>(keys, rowid_s, head, qidx, nnz, mask, slot_ptr, dest_all);
+        SPMV_CHECK_LAUNCH("split dest");
+    }
     SPMV_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipMemcpyAsync(h_row_off, row_off, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost, s));
     SPMV_HIP(hipStreamSynchronize(s));
     return SPMV_OK;
 }

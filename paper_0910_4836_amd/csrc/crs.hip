@@ -2,14 +2,14 @@
 // is a sparse scalar product of its stored values with the gathered x).
 //
 // gfx950 design: the rows are cut, once per matrix, into blocks of consecutive
-// rows holding at most block_nnz entries and at most 256 rows (2048 rows when
-// none of them has more than 16 entries); a row longer than block_nnz is a
-// block of its own.  One 256-lane workgroup per block:
+// rows holding at most block_nnz entries and at most 2048 rows; a row longer
+// than block_nnz is a block of its own.  One 256-lane workgroup per block:
 //   * multi-row block ("stream" mode): the lanes walk the block's entries in
 //     order - fully coalesced val/col reads, independent x gathers - and park
-//     the products in LDS; then G lanes per row (G = 256/rows, a power of two
-//     up to 64) add their row's products and combine with a fixed shuffle tree,
-//     or, in a block of more than 256 short rows, one lane adds each row.
+//     the products in LDS, while the block's row offsets are staged in LDS
+//     too; then one lane adds each row of at most 16 entries in order, and a
+//     whole wavefront takes each longer row (strided partial sums, a fixed
+//     shuffle tree), so no lane serialises over a long row.
 //   * single-row block ("vector" mode): all 256 lanes stride over the row with
 //     fused multiply-adds, then a fixed wave tree and an ordered sum over the
 //     four waves.
@@ -27,15 +27,15 @@ namespace spmv {
 constexpr int CRS_THREADS = 256;
 constexpr int CRS_DEFAULT_BLOCK_NNZ = 1024;
 constexpr int CRS_MAX_BLOCK_NNZ = 4096;
-constexpr int CRS_MAX_BLOCK_ROWS = 256;         // rows of a block in general
-constexpr int CRS_MAX_SHORT_BLOCK_ROWS = 2048;  // rows of a block of short rows only
-constexpr int CRS_SHORT_ROW = 16;               // "short": at most this many entries
+constexpr int CRS_MAX_BLOCK_ROWS = 2048;     // rows of a multi-row block
+constexpr int CRS_LANE_ROW = 16;             // rows up to this length are summed by one lane
+constexpr int CRS_MAX_LONG_ROWS = CRS_MAX_BLOCK_NNZ / (CRS_LANE_ROW + 1) + 1;
 
 template <bool WIDE, typename VT, typename XT, typename OT>
 __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, const VT *__restrict__ val,
                                                const XT *__restrict__ x, OT *__restrict__ y, int32_t row,
                                                int32_t e0, int32_t e1, double alpha, double beta,
-                                               double *red)
+                                               double *red, const int32_t *__restrict__ out_idx)
 {
     typedef typename Acc<WIDE>::T acc_t;
     acc_t s = 0;
@@ -63,18 +63,28 @@ __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, 
     if (threadIdx.x == 0) {
         acc_t tot = (acc_t)red[0];
         for (int w = 1; w < CRS_THREADS / WAVE; ++w) tot += (acc_t)red[w];
-        write_y(y, row, (double)tot, alpha, beta);
+        write_y(y, out_idx ? out_idx[row] : row, (double)tot, alpha, beta);
     }
 }
 
-// One plan block b (rows plan[b] .. plan[b+1]) of y = alpha*A x + beta*y.
+// Shared memory of a CRS block workgroup besides the LDS products.
+struct CrsShared {
+    int32_t rofs[CRS_MAX_BLOCK_ROWS + 1];   // row offsets of the block, relative to its first entry
+    int32_t longl[CRS_MAX_LONG_ROWS];       // rows summed by a whole wavefront
+    int32_t nlong;
+    double red[CRS_THREADS / WAVE];
+};
+
+// One plan block b (rows plan[b] .. plan[b+1]) of y = alpha*A x + beta*y;
+// row r's result goes to y[out_idx[r]] if out_idx is given, else to y[r].
 // WIDE_ALL: accumulate every row in FP64 (the column-split parts, whose rows
 // are pieces of rows whose full length the block does not see).
 template <typename VT, typename XT, typename OT, bool WIDE_ALL = false>
 __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                const VT *__restrict__ val, const XT *__restrict__ x,
                                                OT *__restrict__ y, const int32_t *__restrict__ plan, int64_t b,
-                                               double alpha, double beta, double *smem_d, double *red)
+                                               double alpha, double beta, double *smem_d, CrsShared &sh,
+                                               const int32_t *__restrict__ out_idx = nullptr)
 {
     constexpr bool F64 = IsF64<VT>::value || WIDE_ALL;
     typedef typename Acc<F64>::T acc_t;
@@ -82,14 +92,19 @@ __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_p
     const int32_t r0 = plan[b], r1 = plan[b + 1];
     const int32_t e0 = row_ptr[r0], e1 = row_ptr[r1];
     const int32_t nr = r1 - r0, ne = e1 - e0;
+    const int t = (int)threadIdx.x;
 
     if (nr == 1) {
         if (!F64 && ne > SPMV_WIDE_ROW_NNZ)
-            crs_vector_row<true, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, red);
+            crs_vector_row<true, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, sh.red, out_idx);
         else
-            crs_vector_row<F64, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, red);
+            crs_vector_row<F64, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, sh.red, out_idx);
         return;
     }
+    const bool staged = nr <= CRS_MAX_BLOCK_ROWS;
+    if (staged)
+        for (int32_t g = t; g <= nr; g += CRS_THREADS) sh.rofs[g] = row_ptr[r0 + g] - e0;
+    if (t == 0) sh.nlong = 0;
 
     // stream mode: products of the whole block into LDS (ne <= block_nnz).
     // Each lane first issues all U loads of val/col, then all U gathers, so a
@@ -100,7 +115,7 @@ __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_p
         VT v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int32_t k = k0 + u * CRS_THREADS + (int32_t)threadIdx.x;
+            int32_t k = k0 + u * CRS_THREADS + t;
             c[u] = 0;
             v[u] = VT{};
             if (k < ne) {
@@ -111,39 +126,56 @@ __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_p
         XT xv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int32_t k = k0 + u * CRS_THREADS + (int32_t)threadIdx.x;
+            int32_t k = k0 + u * CRS_THREADS + t;
             xv[u] = k < ne ? x[c[u]] : XT(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int32_t k = k0 + u * CRS_THREADS + (int32_t)threadIdx.x;
+            int32_t k = k0 + u * CRS_THREADS + t;
             if (k < ne) prod[k] = Acc<F64>::mac((acc_t)0, v[u], xv[u]);
         }
     }
     __syncthreads();
 
-    if (nr > CRS_THREADS) {
-        // many short rows: one lane per row, rows t, t+256, ... (the planner
-        // admits more than 256 rows only when every row is short)
-        for (int32_t g = (int32_t)threadIdx.x; g < nr; g += CRS_THREADS) {
+    if (!staged) {
+        // a block of more rows than the planner makes: one lane per row
+        for (int32_t g = t; g < nr; g += CRS_THREADS) {
             const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
             acc_t s = 0;
             for (int32_t k = rs; k < re; ++k) s += prod[k];
-            write_y(y, (int64_t)r0 + g, (double)s, alpha, beta);
+            const int32_t row = r0 + g;
+            write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
         }
         return;
     }
-    // G lanes per row, G = largest power of two <= 256/nr, at most 64
-    int G = 64;
-    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
-    const int g = (int)threadIdx.x / G, l = (int)threadIdx.x % G;
-    acc_t s = 0;
-    if (g < nr) {
-        const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
-        for (int32_t k = rs + l; k < re; k += G) s += prod[k];
+    // rows of at most CRS_LANE_ROW entries: one lane each, in order; longer
+    // rows are queued for whole wavefronts (at most ne / (CRS_LANE_ROW + 1) of
+    // them, which fits longl).  Which wavefront takes which row does not
+    // change any row's summation order.
+    for (int32_t g = t; g < nr; g += CRS_THREADS) {
+        const int32_t rs = sh.rofs[g], re = sh.rofs[g + 1];
+        if (re - rs <= CRS_LANE_ROW) {
+            acc_t s = 0;
+            for (int32_t k = rs; k < re; ++k) s += prod[k];
+            const int32_t row = r0 + g;
+            write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
+        } else {
+            sh.longl[atomicAdd(&sh.nlong, 1)] = g;
+        }
     }
-    s = group_sum(s, G);
-    if (g < nr && l == 0) write_y(y, (int64_t)r0 + g, (double)s, alpha, beta);
+    __syncthreads();
+    const int nl = sh.nlong, lane = lane_id();
+    for (int i = t / WAVE; i < nl; i += CRS_THREADS / WAVE) {
+        const int32_t g = sh.longl[i];
+        const int32_t rs = sh.rofs[g], re = sh.rofs[g + 1];
+        acc_t s = 0;
+        for (int32_t k = rs + lane; k < re; k += WAVE) s += prod[k];
+        s = group_sum(s, WAVE);
+        if (lane == 0) {
+            const int32_t row = r0 + g;
+            write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
+        }
+    }
 }
 
 template <typename VT, typename XT>
@@ -155,35 +187,38 @@ __global__ __launch_bounds__(CRS_THREADS) void crs_block_kernel(const int32_t *_
                                                                 double alpha, double beta)
 {
     extern __shared__ double smem_d[];
-    __shared__ double red[CRS_THREADS / WAVE];
+    __shared__ CrsShared sh;
     crs_block_body<VT, XT, XT>(row_ptr, col, val, x, y, plan, xcd_remap(blockIdx.x, gridDim.x), alpha, beta, smem_d,
-                               red);
+                               sh);
 }
 
-// Column-split CRS: part k (columns of the k-th eighth) runs on XCD k
-// (workgroup b -> part b % 8) and writes its partial result part_y[k][:].
+// Column-split CRS: part k (columns of the k-th eighth, compressed to the rows
+// that hold one of its entries) runs on XCD k (workgroup b -> part b % 8) and
+// writes each row's partial result into its slot.
 struct CrsSplitTab {
     int64_t base[SPLIT_PARTS];        // part k's first entry in col / val
+    int32_t row_off[SPLIT_PARTS];     // part k's first compressed row
     int32_t plan_off[SPLIT_PARTS];
     int32_t n_blocks[SPLIT_PARTS];
 };
 
 template <typename VT, typename XT>
-__global__ __launch_bounds__(CRS_THREADS) void crs_split_kernel(int32_t n_rows, const int32_t *__restrict__ row_ptr_all,
+__global__ __launch_bounds__(CRS_THREADS) void crs_split_kernel(const int32_t *__restrict__ row_ptr_all,
+                                                                const int32_t *__restrict__ dest_all,
                                                                 const int32_t *__restrict__ col,
                                                                 const VT *__restrict__ val,
                                                                 const XT *__restrict__ x,
-                                                                double *__restrict__ part_y,
+                                                                double *__restrict__ slots,
                                                                 const int32_t *__restrict__ plan_all, CrsSplitTab T)
 {
     extern __shared__ double smem_d[];
-    __shared__ double red[CRS_THREADS / WAVE];
+    __shared__ CrsShared sh;
     const int k = (int)(blockIdx.x % SPLIT_PARTS);
     const int64_t b = blockIdx.x / SPLIT_PARTS;
     if (b >= T.n_blocks[k]) return;
-    crs_block_body<VT, XT, double, true>(row_ptr_all + (int64_t)k * (n_rows + 1), col + T.base[k], val + T.base[k],
-                                         x, part_y + (int64_t)k * n_rows, plan_all + T.plan_off[k], b, 1.0, 0.0,
-                                         smem_d, red);
+    crs_block_body<VT, XT, double, true>(row_ptr_all + T.row_off[k] + k, col + T.base[k], val + T.base[k], x, slots,
+                                         plan_all + T.plan_off[k], b, 1.0, 0.0, smem_d, sh,
+                                         dest_all + T.row_off[k]);
 }
 
 // One wavefront per row: the default when no plan is given.
@@ -348,27 +383,22 @@ void crs_plan_rows(int32_t n_rows, const int32_t *rp, int32_t T, std::vector<int
     out.clear();
     out.push_back(0);
     int32_t start = 0;
-    int64_t cur = 0, longest = 0;
+    int64_t cur = 0;
     for (int32_t r = 0; r < n_rows; ++r) {
         const int64_t len = (int64_t)rp[r + 1] - rp[r];
         const int32_t nr = r - start;
-        const int64_t lg = std::max(longest, len);
-        const int32_t row_cap = lg <= CRS_SHORT_ROW ? CRS_MAX_SHORT_BLOCK_ROWS : CRS_MAX_BLOCK_ROWS;
-        if (nr > 0 && (cur + len > T || nr >= row_cap)) {
+        if (nr > 0 && (cur + len > T || nr >= CRS_MAX_BLOCK_ROWS)) {
             out.push_back(r);
             start = r;
             cur = 0;
-            longest = 0;
         }
         if (len > T) {                 // a long row is a block of its own
             out.push_back(r + 1);
             start = r + 1;
             cur = 0;
-            longest = 0;
             continue;
         }
         cur += len;
-        longest = std::max(longest, len);
     }
     if (start < n_rows) out.push_back(n_rows);
 }
@@ -432,8 +462,9 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
     return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs: dtype combination");
 }
 
-spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr_all, const int32_t *col_idx,
-                           const void *val, const int64_t *h_bounds, spmv_dtype val_dt, const int32_t *plan_all,
+spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr_all, const int32_t *dest_all,
+                           const int32_t *slot_ptr, const int32_t *col_idx, const void *val, const int64_t *h_bounds,
+                           const int64_t *h_row_off, spmv_dtype val_dt, const int32_t *plan_all,
                            const int32_t *h_plan_off, const int32_t *h_n_blocks, int32_t block_nnz, const void *x,
                            void *y, spmv_dtype vec_dt, double alpha, double beta, void *ws, size_t ws_bytes,
                            void *stream)
@@ -441,8 +472,12 @@ spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_pt
     SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0, "spmv_crs_split: negative size");
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_crs_split: bad dtype");
     if (n_rows == 0) return SPMV_OK;
-    SPMV_REQUIRE(row_ptr_all && plan_all && h_plan_off && h_n_blocks && h_bounds && y, "spmv_crs_split: null pointer");
-    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(n_rows), "spmv_crs_split: workspace too small");
+    SPMV_REQUIRE(row_ptr_all && slot_ptr && plan_all && h_plan_off && h_n_blocks && h_bounds && h_row_off && y,
+                 "spmv_crs_split: null pointer");
+    const int64_t n_slots = h_row_off[SPLIT_PARTS];
+    SPMV_REQUIRE(n_slots >= 0 && n_slots <= (int64_t)SPLIT_PARTS * n_rows, "spmv_crs_split: bad h_row_off");
+    SPMV_REQUIRE(n_slots == 0 || dest_all, "spmv_crs_split: null dest_all");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(n_slots), "spmv_crs_split: workspace too small");
     if (block_nnz == 0) block_nnz = CRS_DEFAULT_BLOCK_NNZ;
     SPMV_REQUIRE(block_nnz >= CRS_THREADS && block_nnz <= CRS_MAX_BLOCK_NNZ,
                  "spmv_crs_split: block_nnz must be in [256, 4096]");
@@ -450,20 +485,23 @@ spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_pt
     int64_t max_nb = 0;
     for (int k = 0; k < SPLIT_PARTS; ++k) {
         SPMV_REQUIRE(h_n_blocks[k] >= 0 && h_plan_off[k] >= 0, "spmv_crs_split: bad part plan");
+        SPMV_REQUIRE(h_row_off[k] >= 0 && h_row_off[k] <= h_row_off[k + 1], "spmv_crs_split: bad h_row_off");
+        SPMV_REQUIRE(h_n_blocks[k] == 0 || h_row_off[k + 1] > h_row_off[k], "spmv_crs_split: plan of an empty part");
         T.base[k] = h_bounds[k];
+        T.row_off[k] = (int32_t)h_row_off[k];
         T.plan_off[k] = h_plan_off[k];
         T.n_blocks[k] = h_n_blocks[k];
         max_nb = std::max<int64_t>(max_nb, h_n_blocks[k]);
     }
     hipStream_t s = as_stream(stream);
-    double *part = (double *)ws;
+    double *slots = (double *)ws;
     const unsigned grid = (unsigned)(max_nb * SPLIT_PARTS);
     if (grid) {
-#define CSPLIT_CASE(VDT, VT, XDT, XT)                                                                         \
-    if (val_dt == VDT && vec_dt == XDT) {                                                                     \
-        const size_t lds = (size_t)block_nnz * 8;                                                             \
-        crs_split_kernel<VT, XT><<<grid, CRS_THREADS, lds, s>>>(n_rows, row_ptr_all, col_idx, (const VT *)val, \
-                                                               (const XT *)x, part, plan_all, T);             \
+#define CSPLIT_CASE(VDT, VT, XDT, XT)                                                                          \
+    if (val_dt == VDT && vec_dt == XDT) {                                                                      \
+        const size_t lds = (size_t)block_nnz * 8;                                                              \
+        crs_split_kernel<VT, XT><<<grid, CRS_THREADS, lds, s>>>(row_ptr_all, dest_all, col_idx, (const VT *)val, \
+                                                               (const XT *)x, slots, plan_all, T);             \
     } else
         CSPLIT_CASE(SPMV_F64, double, SPMV_F64, double)
         CSPLIT_CASE(SPMV_F32, float, SPMV_F64, double)
@@ -475,7 +513,7 @@ spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_pt
 #undef CSPLIT_CASE
         SPMV_CHECK_LAUNCH("spmv_crs_split");
     }
-    return launch_combine(n_rows, part, y, vec_dt, alpha, beta, s);
+    return launch_combine(n_rows, slot_ptr, slots, y, vec_dt, alpha, beta, s);
 }
 
 }  // extern "C"

@@ -40,6 +40,9 @@ struct JdsClass {
     int32_t slog;       // S = 1 << slog wavefronts per row group
 };
 
+// No XCD-aware dealing of workgroups: a class holds rows of many lengths, so
+// contiguous per-XCD chunks of a class would give the XCDs very unequal work;
+// the hardware's round-robin spreads every class evenly.
 struct JdsPlan {
     JdsClass c[JDS_MAX_CLASSES];
     int32_t ncls;
@@ -271,15 +274,15 @@ template <int FMT, int U, typename VT, typename XT>
 __global__ __launch_bounds__(JDS_THREADS) void jds_kernel(JdsArgs a, JdsPlan P)
 {
     __shared__ double part[JDS_WAVES][WAVE];
-    // No XCD remap here: the long-row classes come first and the hardware's
-    // round-robin spreads them over all XCDs.
     jds_body<FMT, U, VT, XT, XT>(a, P, blockIdx.x, part);
 }
 
 // Column-split JDS / blocked JDS: part k (the matrix restricted to the k-th
-// eighth of the columns, with its own permutation) runs on XCD k (workgroup
-// b -> part b % 8) and writes its partial result as FP64 into a[k].y.  All
-// rows accumulate in FP64, reduced-precision values included.
+// eighth of the columns and to the rows holding one of its entries, with its
+// own permutation) runs on XCD k (workgroup b -> part b % 8).  Its perm maps
+// each permuted row straight to the row's slot in a[k].y, which receives the
+// FP64 partial result.  All rows accumulate in FP64, reduced-precision values
+// included.
 struct JdsSplitArgs {
     JdsArgs a[SPLIT_PARTS];
     JdsPlan P[SPLIT_PARTS];
@@ -662,27 +665,45 @@ spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd
     return SPMV_OK;
 }
 
-spmv_status spmv_jds_split(int32_t n, const int32_t *const *h_perm, const int32_t *const *h_jd_ptr,
-                           const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag, const int32_t *const *h_jd_col,
-                           const void *const *h_jd_val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
-                           double alpha, double beta, int32_t unroll, int32_t max_iters, void *ws, size_t ws_bytes,
-                           void *stream)
+// Rows of part k: h_row_off[k+1] - h_row_off[k]; the slots hold h_row_off[8].
+static spmv_status split_rows_ok(int32_t n, const int32_t *slot_ptr, const int64_t *h_row_off, const char *who)
+{
+    if (!slot_ptr || !h_row_off) return fail(SPMV_ERR_INVALID_ARG, std::string(who) + ": null slot_ptr or h_row_off");
+    for (int k = 0; k < SPLIT_PARTS; ++k)
+        if (h_row_off[k] < 0 || h_row_off[k + 1] < h_row_off[k] || h_row_off[k + 1] - h_row_off[k] > n)
+            return fail(SPMV_ERR_INVALID_ARG, std::string(who) + ": bad h_row_off");
+    if (h_row_off[SPLIT_PARTS] > (int64_t)SPLIT_PARTS * n)
+        return fail(SPMV_ERR_INVALID_ARG, std::string(who) + ": bad h_row_off");
+    return SPMV_OK;
+}
+
+spmv_status spmv_jds_split(int32_t n, const int32_t *slot_ptr, const int64_t *h_row_off, const int32_t *const *h_perm,
+                           const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag,
+                           const int32_t *const *h_jd_col, const void *const *h_jd_val, spmv_dtype val_dt,
+                           const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, int32_t unroll,
+                           int32_t max_iters, void *ws, size_t ws_bytes, void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_jds_split: n < 0");
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_split: bad dtype");
     SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_split: bad unroll or max_iters");
     if (n == 0) return SPMV_OK;
-    SPMV_REQUIRE(h_perm && h_jd_ptr && h_jd_ptr_host && h_ndiag && h_jd_col && h_jd_val && x && y,
+    SPMV_REQUIRE(h_perm && h_jd_ptr && h_jd_ptr_host && h_ndiag && h_jd_col && h_jd_val && y,
                  "spmv_jds_split: null pointer");
-    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(n), "spmv_jds_split: workspace too small");
+    spmv_status st = split_rows_ok(n, slot_ptr, h_row_off, "spmv_jds_split");
+    if (st != SPMV_OK) return st;
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(h_row_off[SPLIT_PARTS]),
+                 "spmv_jds_split: workspace too small");
     JdsSplitArgs S{};
-    double *part = (double *)ws;
+    double *slots = (double *)ws;
     int64_t max_wg = 0;
     for (int k = 0; k < SPLIT_PARTS; ++k) {
+        const int32_t nk = (int32_t)(h_row_off[k + 1] - h_row_off[k]);
+        JdsArgs &a = S.a[k];
+        if (nk == 0) continue;                 // S.P[k].ncls == 0: no workgroup of part k does anything
+        SPMV_REQUIRE(x, "spmv_jds_split: null x");
         SPMV_REQUIRE(h_perm[k] && h_jd_ptr[k] && h_jd_ptr_host[k] && h_ndiag[k] >= 0, "spmv_jds_split: null part");
         SPMV_REQUIRE(h_ndiag[k] == 0 || (h_jd_col[k] && h_jd_val[k]), "spmv_jds_split: null part arrays");
-        JdsArgs &a = S.a[k];
-        a.n = n;
+        a.n = nk;
         a.perm = h_perm[k];
         a.jd_ptr = h_jd_ptr[k];
         a.ndiag = h_ndiag[k];
@@ -690,10 +711,10 @@ spmv_status spmv_jds_split(int32_t n, const int32_t *const *h_perm, const int32_
         a.col = h_jd_col[k];
         a.val = h_jd_val[k];
         a.x = x;
-        a.y = part + (int64_t)k * n;
+        a.y = slots;                           // perm maps part rows to their slots
         a.alpha = 1.0;
         a.beta = 0.0;
-        S.P[k] = plan_jds(n, h_jd_ptr_host[k], h_ndiag[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1);
+        S.P[k] = plan_jds(nk, h_jd_ptr_host[k], h_ndiag[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1);
         if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
     }
     hipStream_t s = as_stream(stream);
@@ -716,10 +737,11 @@ spmv_status spmv_jds_split(int32_t n, const int32_t *const *h_perm, const int32_
 #undef JSPLIT_CASE
         SPMV_CHECK_LAUNCH("spmv_jds_split");
     }
-    return launch_combine(n, part, y, vec_dt, alpha, beta, s);
+    return launch_combine(n, slot_ptr, slots, y, vec_dt, alpha, beta, s);
 }
 
-spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *const *h_perm, const int64_t *const *h_slice_ptr,
+spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *slot_ptr, const int64_t *h_row_off,
+                                   const int32_t *const *h_perm, const int64_t *const *h_slice_ptr,
                                    const int32_t *const *h_slice_nd, const int32_t *const *h_slice_nd_host,
                                    const int32_t *const *h_bl_col, const void *const *h_bl_val, spmv_dtype val_dt,
                                    const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
@@ -734,24 +756,30 @@ spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *const *h
                      rows_per_wave == 64,
                  "spmv_jds_blocked_split: rows_per_wave must be 0, 8, 16, 32 or 64");
     if (n == 0) return SPMV_OK;
-    SPMV_REQUIRE(h_perm && h_slice_ptr && h_slice_nd && h_slice_nd_host && h_bl_col && h_bl_val && x && y,
+    SPMV_REQUIRE(h_perm && h_slice_ptr && h_slice_nd && h_slice_nd_host && h_bl_col && h_bl_val && y,
                  "spmv_jds_blocked_split: null pointer");
-    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(n), "spmv_jds_blocked_split: workspace too small");
+    spmv_status st = split_rows_ok(n, slot_ptr, h_row_off, "spmv_jds_blocked_split");
+    if (st != SPMV_OK) return st;
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_workspace_size(h_row_off[SPLIT_PARTS]),
+                 "spmv_jds_blocked_split: workspace too small");
     int forced = -1;
     if (rows_per_wave) {
         forced = 0;
         while ((1 << forced) < rows_per_wave) ++forced;
     }
     JdsSplitArgs S{};
-    double *part = (double *)ws;
+    double *slots = (double *)ws;
     int64_t max_wg = 0;
     for (int k = 0; k < SPLIT_PARTS; ++k) {
+        const int32_t nk = (int32_t)(h_row_off[k + 1] - h_row_off[k]);
+        JdsArgs &a = S.a[k];
+        if (nk == 0) continue;                 // S.P[k].ncls == 0: no workgroup of part k does anything
+        SPMV_REQUIRE(x, "spmv_jds_blocked_split: null x");
         SPMV_REQUIRE(h_perm[k] && h_slice_ptr[k] && h_slice_nd[k] && h_slice_nd_host[k],
                      "spmv_jds_blocked_split: null part");
         SPMV_REQUIRE(h_slice_nd_host[k][0] == 0 || (h_bl_col[k] && h_bl_val[k]),
                      "spmv_jds_blocked_split: null part arrays");
-        JdsArgs &a = S.a[k];
-        a.n = n;
+        a.n = nk;
         a.perm = h_perm[k];
         a.C = C;
         a.slice_ptr = h_slice_ptr[k];
@@ -759,10 +787,10 @@ spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *const *h
         a.col = h_bl_col[k];
         a.val = h_bl_val[k];
         a.x = x;
-        a.y = part + (int64_t)k * n;
+        a.y = slots;                           // perm maps part rows to their slots
         a.alpha = 1.0;
         a.beta = 0.0;
-        S.P[k] = plan_blocked(n, C, h_slice_nd_host[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced);
+        S.P[k] = plan_blocked(nk, C, h_slice_nd_host[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced);
         if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
     }
     hipStream_t s = as_stream(stream);
@@ -785,7 +813,7 @@ spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *const *h
 #undef BSPLIT_CASE
         SPMV_CHECK_LAUNCH("spmv_jds_blocked_split");
     }
-    return launch_combine(n, part, y, vec_dt, alpha, beta, s);
+    return launch_combine(n, slot_ptr, slots, y, vec_dt, alpha, beta, s);
 }
 
 }  // extern "C"

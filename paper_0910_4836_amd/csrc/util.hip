@@ -164,29 +164,30 @@ static int stream_grid(int64_t n, int per_thread)
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// y_i = alpha * (sum of row i's slots, in slot order) + beta * y_i
 template <typename T>
-__global__ void combine_kernel(int32_t n, const double *__restrict__ part, T *__restrict__ y, double alpha,
-                               double beta)
+__global__ void combine_kernel(int32_t n, const int32_t *__restrict__ slot_ptr, const double *__restrict__ slots,
+                               T *__restrict__ y, double alpha, double beta)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) {
+        const int32_t s0 = slot_ptr[i], s1 = slot_ptr[i + 1];
         double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < SPLIT_PARTS; ++k) s += __builtin_nontemporal_load(part + (int64_t)k * n + i);
+        for (int32_t q = s0; q < s1; ++q) s += __builtin_nontemporal_load(slots + q);
         write_y(y, i, s, alpha, beta);
     }
 }
 
-spmv_status launch_combine(int32_t n, const double *part, void *y, spmv_dtype vec_dt, double alpha, double beta,
-                           hipStream_t s)
+spmv_status launch_combine(int32_t n, const int32_t *slot_ptr, const double *slots, void *y, spmv_dtype vec_dt,
+                           double alpha, double beta, hipStream_t s)
 {
     if (n == 0) return SPMV_OK;
     const int grid = stream_grid(n, 4);
     if (vec_dt == SPMV_F64)
-        combine_kernel<double><<<grid, 256, 0, s>>>(n, part, (double *)y, alpha, beta);
+        combine_kernel<double><<<grid, 256, 0, s>>>(n, slot_ptr, slots, (double *)y, alpha, beta);
     else
-        combine_kernel<float><<<grid, 256, 0, s>>>(n, part, (float *)y, alpha, beta);
+        combine_kernel<float><<<grid, 256, 0, s>>>(n, slot_ptr, slots, (float *)y, alpha, beta);
     SPMV_CHECK_LAUNCH("split combine");
     return SPMV_OK;
 }
@@ -229,9 +230,9 @@ spmv_status spmv_axpby(int64_t n, double alpha, const void *x, double beta, void
     return SPMV_OK;
 }
 
-size_t spmv_split_workspace_size(int32_t n_rows)
+size_t spmv_split_workspace_size(int64_t n_slots)
 {
-    return (size_t)(n_rows > 0 ? n_rows : 1) * SPLIT_PARTS * sizeof(double) + 256;
+    return (size_t)(n_slots > 0 ? n_slots : 1) * sizeof(double) + 256;
 }
 
 size_t spmv_dot_workspace_size(int64_t n)

@@ -436,7 +436,8 @@ def _ptr_array(ts):
 
 class Split:
     """A matrix cut into SPLIT_PARTS column blocks (spmv_split_columns); part k
-    is an ordinary CRS matrix and gets JDS / blocked-JDS forms on demand."""
+    is an ordinary CRS matrix over the rows that hold one of its entries, and
+    gets JDS / blocked-JDS forms on demand."""
 
     def __init__(self, A: CSR, width: int = 0, block_nnz: int = 0):
         lib = _lib.load()
@@ -444,15 +445,20 @@ class Split:
         dev = A.device
         self.n, self.n_cols = A.n_rows, A.n_cols
         nnz = A.nnz
+        cap = min(nnz, P * A.n_rows)
         ws = _ws(lib.spmv_split_columns_workspace_size(A.n_rows, nnz), dev)
-        self.row_ptr_all = torch.empty(P * (A.n_rows + 1), dtype=_I32, device=dev)
+        self.row_ptr_all = torch.empty(cap + P, dtype=_I32, device=dev)
+        self.dest_all = torch.empty(max(cap, 1), dtype=_I32, device=dev)
+        self.slot_ptr = torch.empty(A.n_rows + 1, dtype=_I32, device=dev)
         self.col = torch.empty(max(nnz, 1), dtype=_I32, device=dev)
         self.val = torch.empty(max(nnz, 1), dtype=A.val.dtype, device=dev)
         self.bounds = np.zeros(P + 1, dtype=np.int64)
+        self.row_off = np.zeros(P + 1, dtype=np.int64)
         call("spmv_split_columns", A.n_rows, A.n_cols, nnz, _p(A.row_ptr), _p(A.col_idx), _p(A.val),
-             dtype_code(A.val.dtype), width, _p(self.row_ptr_all), _p(self.col), _p(self.val),
-             _h_i64(self.bounds), _p(ws), ws.numel(), _stream())
-        self.ws = _ws(lib.spmv_split_workspace_size(A.n_rows), dev)
+             dtype_code(A.val.dtype), width, _p(self.row_ptr_all), _p(self.dest_all), _p(self.slot_ptr), _p(self.col),
+             _p(self.val), _h_i64(self.bounds), _h_i64(self.row_off), _p(ws), ws.numel(), _stream())
+        self.n_slots = int(self.row_off[P])
+        self.ws = _ws(lib.spmv_split_workspace_size(self.n_slots), dev)
         self.parts = [self.part_csr(k) for k in range(P)]
         # CRS plans of the parts, one after the other
         plans, self.plan_off, self.n_blocks = [], np.zeros(P, np.int32), np.zeros(P, np.int32)
@@ -467,10 +473,17 @@ class Split:
         self.jds = None
         self.blocked = {}
 
+    def part_rows(self, k: int) -> int:
+        return int(self.row_off[k + 1] - self.row_off[k])
+
+    def part_dest(self, k: int) -> torch.Tensor:
+        """Slot of each compressed row of part k."""
+        return self.dest_all[int(self.row_off[k]):int(self.row_off[k + 1])]
+
     def part_csr(self, k: int) -> CSR:
-        n = self.n
+        nk, r0 = self.part_rows(k), int(self.row_off[k])
         a, b = int(self.bounds[k]), int(self.bounds[k + 1])
-        return CSR(n, self.n_cols, self.row_ptr_all[k * (n + 1):(k + 1) * (n + 1)], self.col[a:b], self.val[a:b])
+        return CSR(nk, self.n_cols, self.row_ptr_all[r0 + k:r0 + k + nk + 1], self.col[a:b], self.val[a:b])
 
     def with_values(self, val: torch.Tensor) -> "Split":
         """Same structure, values (part-major order) of another dtype."""
@@ -485,8 +498,15 @@ class Split:
         return S
 
     def jds_parts(self):
+        """JDS of every part, its perm mapped to slots (rows of the part go
+        straight to their slots)."""
         if self.jds is None:
-            self.jds = [jds_from_csr(Ak) for Ak in self.parts]
+            self.jds = []
+            for k, Ak in enumerate(self.parts):
+                J = jds_from_csr(Ak)
+                if J.n > 0:
+                    J.perm = spmv_gather_values(J.perm[:J.n], self.part_dest(k))
+                self.jds.append(J)
         return self.jds
 
     def blocked_parts(self, C_: int = 64):
@@ -497,9 +517,10 @@ class Split:
 
 def spmv_crs_split(S: Split, x, y=None, alpha=1.0, beta=0.0):
     y = _out_vec(y, S.n, x, beta)
-    call("spmv_crs_split", S.n, S.n_cols, _p(S.row_ptr_all), _p(S.col), _p(S.val), _h_i64(S.bounds),
-         dtype_code(S.val.dtype), _p(S.plan_all), _h_i32(S.plan_off), _h_i32(S.n_blocks), S.block_nnz, _p(x), _p(y),
-         dtype_code(x.dtype), float(alpha), float(beta), _p(S.ws), S.ws.numel(), _stream())
+    call("spmv_crs_split", S.n, S.n_cols, _p(S.row_ptr_all), _p(S.dest_all), _p(S.slot_ptr), _p(S.col), _p(S.val),
+         _h_i64(S.bounds), _h_i64(S.row_off), dtype_code(S.val.dtype), _p(S.plan_all), _h_i32(S.plan_off),
+         _h_i32(S.n_blocks), S.block_nnz, _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), _p(S.ws),
+         S.ws.numel(), _stream())
     return y
 
 
@@ -509,10 +530,10 @@ def spmv_jds_split(S: Split, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters
     S._keep = [J.h_jd_ptr for J in Js]
     hptr = (C.c_void_p * len(Js))(*[J.h_jd_ptr.ctypes.data for J in Js])
     ndiag = np.array([J.ndiag for J in Js], dtype=np.int32)
-    call("spmv_jds_split", S.n, _ptr_array([J.perm for J in Js]), _ptr_array([J.jd_ptr for J in Js]), hptr,
-         _h_i32(ndiag), _ptr_array([J.jd_col for J in Js]), _ptr_array([J.jd_val for J in Js]),
-         dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll,
-         max_iters, _p(S.ws), S.ws.numel(), _stream())
+    call("spmv_jds_split", S.n, _p(S.slot_ptr), _h_i64(S.row_off), _ptr_array([J.perm for J in Js]),
+         _ptr_array([J.jd_ptr for J in Js]), hptr, _h_i32(ndiag), _ptr_array([J.jd_col for J in Js]),
+         _ptr_array([J.jd_val for J in Js]), dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype),
+         float(alpha), float(beta), unroll, max_iters, _p(S.ws), S.ws.numel(), _stream())
     return y
 
 
@@ -521,10 +542,11 @@ def spmv_jds_blocked_split(S: Split, x, y=None, alpha=1.0, beta=0.0, C_=64, rows
     Bs = S.blocked_parts(C_)
     y = _out_vec(y, S.n, x, beta)
     hnd = (C.c_void_p * len(Bs))(*[B.h_slice_nd.ctypes.data for B in Bs])
-    call("spmv_jds_blocked_split", S.n, C_, _ptr_array([B.perm for B in Bs]), _ptr_array([B.slice_ptr for B in Bs]),
-         _ptr_array([B.slice_nd for B in Bs]), hnd, _ptr_array([B.bl_col for B in Bs]),
-         _ptr_array([B.bl_val for B in Bs]), dtype_code(Bs[0].bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype),
-         float(alpha), float(beta), rows_per_wave, unroll, max_iters, _p(S.ws), S.ws.numel(), _stream())
+    call("spmv_jds_blocked_split", S.n, C_, _p(S.slot_ptr), _h_i64(S.row_off), _ptr_array([B.perm for B in Bs]),
+         _ptr_array([B.slice_ptr for B in Bs]), _ptr_array([B.slice_nd for B in Bs]), hnd,
+         _ptr_array([B.bl_col for B in Bs]), _ptr_array([B.bl_val for B in Bs]), dtype_code(Bs[0].bl_val.dtype), _p(x),
+         _p(y), dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave, unroll, max_iters, _p(S.ws),
+         S.ws.numel(), _stream())
     return y
 
 

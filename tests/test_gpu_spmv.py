@@ -141,7 +141,8 @@ def test_empty_matrix_and_single_row():
 @pytest.mark.parametrize("block_nnz", [256, 1024, 4096])
 def test_blocks_of_many_short_rows(block_nnz):
     """Rows of 0-3 entries (blocks of up to 2048 rows, one lane per row) mixed
-    with runs of 17-entry rows (256-row cap) and a few long rows."""
+    with runs of 17-entry rows and rows of 4-40 entries (a wavefront per row
+    above 16 entries) and a few rows longer than any block."""
     rng = np.random.default_rng(70 + block_nnz)
     nr, nc = 30000, 20000
     lens = rng.integers(0, 4, nr)
@@ -159,10 +160,11 @@ def test_blocks_of_many_short_rows(block_nnz):
     plan = to_np(A.plan)
     sizes = np.diff(plan)
     if block_nnz >= 1024:
-        assert sizes.max() > 256                  # the many-short-row path is taken
+        assert sizes.max() > 256                  # blocks of many rows are formed
     rp = to_np(A.row_ptr)
-    for b in np.nonzero(sizes > 256)[0]:          # ... only for blocks of short rows
-        assert np.diff(rp[plan[b]:plan[b + 1] + 1]).max() <= 16 and sizes[b] <= 2048
+    assert sizes.max() <= 2048
+    multi = sizes > 1
+    assert np.all(rp[plan[1:]][multi] - rp[plan[:-1]][multi] <= block_nnz)
     assert max_err(sp.spmv_crs(A, to_dev(x)), want, D) <= FP64_TOL
     X = rng.uniform(-1, 1, (nc, 9))
     Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda").t()        # column-major (n, k)
@@ -180,19 +182,40 @@ def test_blocks_of_many_short_rows(block_nnz):
 
 
 def test_split_structure_is_a_column_partition():
-    """Every part holds exactly the entries of its column range, in CRS order."""
+    """Every part holds exactly the entries of its column range, in CRS order,
+    over the rows that have one of them; slots are numbered row by row, part
+    by part."""
     r, c, v, nr, nc, _ = rand_coo(60, 3000, 5000, 0.004, empty_rows=0.1, long_rows=4, long_len=3000)
     R = oracle.csr_from_coo(nr, nc, r, c, v)
     S = sp.Split(gpu_csr(sp, r, c, v, nr, nc))
     width = -(-(-(-nc // 8)) // 64) * 64
     rows = R.row_index()
+    part = R.col // width
+    present = np.zeros((nr, 8), dtype=bool)
+    present[rows, part] = True
+    slot_ptr = np.concatenate([[0], np.cumsum(present.sum(1))])
+    assert np.array_equal(to_np(S.slot_ptr), slot_ptr)
+    assert S.n_slots == present.sum()
     for k in range(8):
         Pk = S.parts[k]
-        sel = (R.col // width) == k
-        want_ptr = np.concatenate([[0], np.cumsum(np.bincount(rows[sel], minlength=nr))])
-        assert np.array_equal(to_np(Pk.row_ptr), want_ptr)
+        sel = part == k
+        rk = np.nonzero(present[:, k])[0]
+        assert Pk.n_rows == len(rk)
+        cnt = np.bincount(rows[sel], minlength=nr)[rk]
+        assert np.array_equal(to_np(Pk.row_ptr), np.concatenate([[0], np.cumsum(cnt)]))
         assert np.array_equal(to_np(Pk.col_idx), R.col[sel])
         assert np.array_equal(to_np(Pk.val), R.val[sel])
+        want_dest = slot_ptr[rk] + present[rk, :k].sum(1)
+        assert np.array_equal(to_np(S.part_dest(k)), want_dest)
+
+
+@pytest.mark.parametrize("n_cols", [100, 64 * 8 * 3 + 5])
+def test_split_narrow_and_empty_parts(n_cols):
+    """Parts with no entries at all (few columns) and rows with no entries."""
+    r, c, v, nr, nc, rng = rand_coo(61, 2000, n_cols, 0.02, empty_rows=0.3, long_rows=3, long_len=90)
+    run_case(r, c, v, nr, nc, rng.uniform(-1, 1, nc), Cs=(64,))
+    y0 = rng.uniform(-1, 1, nr)
+    run_case(r, c, v, nr, nc, rng.uniform(-1, 1, nc), y0, alpha=0.5, beta=-2.0)
 
 
 def test_deterministic_repeat():
