@@ -495,6 +495,8 @@ class Split:
             Ak.plan, Ak.n_blocks, Ak.block_nnz = A0.plan, A0.n_blocks, A0.block_nnz
         S.jds = None
         S.blocked = {}
+        S._jds_args = None
+        S._blocked_args = {}
         return S
 
     def jds_parts(self):
@@ -524,29 +526,44 @@ def spmv_crs_split(S: Split, x, y=None, alpha=1.0, beta=0.0):
     return y
 
 
+def _jds_split_args(S: Split):
+    """ctypes arrays describing the JDS parts, built once per Split."""
+    if getattr(S, "_jds_args", None) is None:
+        Js = S.jds_parts()
+        hptr = (C.c_void_p * len(Js))(*[J.h_jd_ptr.ctypes.data for J in Js])
+        ndiag = np.array([J.ndiag for J in Js], dtype=np.int32)
+        S._jds_args = (Js, _ptr_array([J.perm for J in Js]), _ptr_array([J.jd_ptr for J in Js]), hptr, ndiag,
+                       _ptr_array([J.jd_col for J in Js]), _ptr_array([J.jd_val for J in Js]))
+    return S._jds_args
+
+
 def spmv_jds_split(S: Split, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0):
-    Js = S.jds_parts()
+    Js, perm, jp, hptr, ndiag, col, val = _jds_split_args(S)
     y = _out_vec(y, S.n, x, beta)
-    S._keep = [J.h_jd_ptr for J in Js]
-    hptr = (C.c_void_p * len(Js))(*[J.h_jd_ptr.ctypes.data for J in Js])
-    ndiag = np.array([J.ndiag for J in Js], dtype=np.int32)
-    call("spmv_jds_split", S.n, _p(S.slot_ptr), _h_i64(S.row_off), _ptr_array([J.perm for J in Js]),
-         _ptr_array([J.jd_ptr for J in Js]), hptr, _h_i32(ndiag), _ptr_array([J.jd_col for J in Js]),
-         _ptr_array([J.jd_val for J in Js]), dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype),
-         float(alpha), float(beta), unroll, max_iters, _p(S.ws), S.ws.numel(), _stream())
+    call("spmv_jds_split", S.n, _p(S.slot_ptr), _h_i64(S.row_off), perm, jp, hptr, _h_i32(ndiag), col, val,
+         dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll,
+         max_iters, _p(S.ws), S.ws.numel(), _stream())
     return y
+
+
+def _blocked_split_args(S: Split, C_: int):
+    cache = S.__dict__.setdefault("_blocked_args", {})
+    if C_ not in cache:
+        Bs = S.blocked_parts(C_)
+        hnd = (C.c_void_p * len(Bs))(*[B.h_slice_nd.ctypes.data for B in Bs])
+        cache[C_] = (Bs, _ptr_array([B.perm for B in Bs]), _ptr_array([B.slice_ptr for B in Bs]),
+                     _ptr_array([B.slice_nd for B in Bs]), hnd, _ptr_array([B.bl_col for B in Bs]),
+                     _ptr_array([B.bl_val for B in Bs]))
+    return cache[C_]
 
 
 def spmv_jds_blocked_split(S: Split, x, y=None, alpha=1.0, beta=0.0, C_=64, rows_per_wave=0, unroll=0,
                            max_iters=0):
-    Bs = S.blocked_parts(C_)
+    Bs, perm, sptr, snd, hnd, col, val = _blocked_split_args(S, C_)
     y = _out_vec(y, S.n, x, beta)
-    hnd = (C.c_void_p * len(Bs))(*[B.h_slice_nd.ctypes.data for B in Bs])
-    call("spmv_jds_blocked_split", S.n, C_, _p(S.slot_ptr), _h_i64(S.row_off), _ptr_array([B.perm for B in Bs]),
-         _ptr_array([B.slice_ptr for B in Bs]), _ptr_array([B.slice_nd for B in Bs]), hnd,
-         _ptr_array([B.bl_col for B in Bs]), _ptr_array([B.bl_val for B in Bs]), dtype_code(Bs[0].bl_val.dtype), _p(x),
-         _p(y), dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave, unroll, max_iters, _p(S.ws),
-         S.ws.numel(), _stream())
+    call("spmv_jds_blocked_split", S.n, C_, _p(S.slot_ptr), _h_i64(S.row_off), perm, sptr, snd, hnd, col, val,
+         dtype_code(Bs[0].bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave,
+         unroll, max_iters, _p(S.ws), S.ws.numel(), _stream())
     return y
 
 
