@@ -282,6 +282,22 @@ def attainable_bw(torch, sp, dev):
     return out
 
 
+def gather_rates(torch, sp, dev, n_idx=1 << 24):
+    """Random 8-byte gathers per second (spmv_gather_probe) for x vectors that
+    fit one XCD's L2, the 256 MB MALL, or only HBM."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(20091026)
+    part = torch.empty(1 << 16, dtype=torch.float64, device=dev)
+    out = {}
+    for label, nx in (("x_2MB_L2", 1 << 18), ("x_16MB_MALL", 1 << 21), ("x_512MB_HBM", 1 << 26)):
+        x = torch.ones(nx, dtype=torch.float64, device=dev)
+        idx = torch.randint(0, nx, (n_idx,), generator=g, device=dev, dtype=torch.int32)
+        ms, _ = time_loop(torch, [(label, lambda: sp.spmv_gather_probe(idx, x, part))], 20, 3)
+        out[label + "_Ggathers_s"] = round(n_idx / (ms * 1e-3) / 1e9, 1)
+        del x, idx
+    return out
+
+
 # --------------------------------------------------------------------------- suite
 
 
@@ -522,6 +538,17 @@ def main():
     else:
         out["cpu_baseline"] = None
     out["attainable_hbm"] = attainable_bw(torch, sp, dev)
+    # every stored entry gathers one x element: the products are bound by the
+    # random-gather rate of the level that holds x (16 MB here: the MALL for
+    # the unsplit forms; one XCD's L2 holds each 2 MB slice of the split forms)
+    rates = gather_rates(torch, sp, dev)
+    nnz = W["nnz"]
+    out["gather_bound"] = {
+        "gathers_per_launch": nnz, "probe": rates,
+        "kernels": {name: {"achieved_Ggathers_s": round(nnz / (ms * 1e-3) / 1e9, 1),
+                           "frac_of_mall_rate": round(nnz / (ms * 1e-3) / 1e9 / rates["x_16MB_MALL_Ggathers_s"], 3),
+                           "frac_of_l2_rate": round(nnz / (ms * 1e-3) / 1e9 / rates["x_2MB_L2_Ggathers_s"], 3)}
+                    for name, ms in dict(per, **(per_s if split else {})).items() if name.endswith("_f64")}}
     print(json.dumps(out), flush=True)
     if args.suite:
         suite_lines(torch, sp, dev, W, args.steps, args.warmup)

@@ -396,6 +396,14 @@ spmv_status spmv_stream_triad(int64_t n, const double *b, const double *c, doubl
                               void *stream);
 spmv_status spmv_stream_copy(int64_t n, const double *b, double *a, void *stream);
 spmv_status spmv_stream_read(int64_t n, const double *b, double *part, int64_t part_cap, void *stream);
+/* Random-gather probe: part[w] = sum of x[idx[i]] over the i read by
+ * workgroup w (idx streamed, one 8-byte x element gathered per index; every
+ * idx[i] must index x).  Timed with x sized to fit one XCD's L2, the MALL or
+ * only HBM, it gives the gather rate that bounds an SpMV whose x accesses
+ * are irregular (paper Section 2: the x access is the limiting factor the
+ * code balance leaves out).  part_cap >= 8 * (compute units) doubles. */
+spmv_status spmv_gather_probe(int64_t n, const int32_t *idx, const double *x, double *part, int64_t part_cap,
+                              void *stream);
 
 #ifdef __cplusplus
 }

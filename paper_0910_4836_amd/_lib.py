@@ -88,6 +88,7 @@ SIGNATURES = {
     "spmv_stream_triad": (_int, [_i64, _p, _p, _p, _f64, _p]),
     "spmv_stream_copy": (_int, [_i64, _p, _p, _p]),
     "spmv_stream_read": (_int, [_i64, _p, _p, _i64, _p]),
+    "spmv_gather_probe": (_int, [_i64, _p, _p, _p, _i64, _p]),
 }
 
 _lib = None

@@ -145,6 +145,33 @@ __global__ __launch_bounds__(256) void read_kernel(int64_t n2, const v2d *__rest
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Gather probe: part[w] = sum over the indices read by workgroup w of x[idx[i]]
+// (idx streamed, x gathered one 8-byte element per lane).  Measures how many
+// random gathers per second the memory system serves for an x of a given size.
+__global__ __launch_bounds__(256) void gather_probe_kernel(int64_t n, const int32_t *__restrict__ idx,
+                                                           const double *__restrict__ x, double *__restrict__ part)
+{
+    __shared__ double red[256 / WAVE];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    for (; i + (PROBE_UNROLL - 1) * stride < n; i += PROBE_UNROLL * stride) {
+        int32_t c[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) c[u] = __builtin_nontemporal_load(idx + i + u * stride);
+        double v[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) v[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) s += v[u];
+    }
+    for (; i < n; i += stride) s += x[idx[i]];
+    s = group_sum(s, WAVE);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 static int probe_grid()
 {
     int dev = 0, cus = 0;
@@ -329,6 +356,18 @@ spmv_status spmv_stream_read(int64_t n, const double *b, double *part, int64_t p
     SPMV_REQUIRE(part_cap >= grid, "spmv_stream_read: part needs one double per workgroup (8 per CU)");
     read_kernel<<<grid, 256, 0, as_stream(stream)>>>(n / 2, (const v2d *)b, part);
     SPMV_CHECK_LAUNCH("spmv_stream_read");
+    return SPMV_OK;
+}
+
+spmv_status spmv_gather_probe(int64_t n, const int32_t *idx, const double *x, double *part, int64_t part_cap,
+                              void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && (n == 0 || (idx && x && part)), "spmv_gather_probe: bad arguments");
+    if (n == 0) return SPMV_OK;
+    const int grid = probe_grid();
+    SPMV_REQUIRE(part_cap >= grid, "spmv_gather_probe: part needs one double per workgroup (8 per CU)");
+    gather_probe_kernel<<<grid, 256, 0, as_stream(stream)>>>(n, idx, x, part);
+    SPMV_CHECK_LAUNCH("spmv_gather_probe");
     return SPMV_OK;
 }
 

@@ -427,6 +427,10 @@ def spmv_stream_read(b, part):
     call("spmv_stream_read", b.numel(), _p(b), _p(part), part.numel(), _stream())
 
 
+def spmv_gather_probe(idx, x, part):
+    call("spmv_gather_probe", idx.numel(), _p(idx), _p(x), _p(part), part.numel(), _stream())
+
+
 # --------------------------------------------------------------------------- column-split forms
 
 

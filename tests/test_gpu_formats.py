@@ -140,3 +140,23 @@ def test_permute_and_gather():
     assert np.array_equal(to_np(sp.spmv_gather_values(to_dev(idx), t)), v[idx])
     iv = rng.integers(-2 ** 31, 2 ** 31 - 1, n).astype(np.int32)
     assert np.array_equal(to_np(sp.spmv_gather_values(to_dev(idx), to_dev(iv))), iv[idx])
+
+
+def test_bandwidth_and_gather_probes():
+    """The probes compute what they read: integer-valued data, exact sums."""
+    n = 1 << 20
+    b = torch.arange(n, dtype=torch.float64, device="cuda") % 7
+    c = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    a = torch.empty_like(b)
+    sp.spmv_stream_triad(a, b, c, 0.5)
+    assert torch.equal(a, b + 1.0)
+    sp.spmv_stream_copy(a, c)
+    assert torch.equal(a, c)
+    part = torch.zeros(1 << 16, dtype=torch.float64, device="cuda")
+    sp.spmv_stream_read(b, part)
+    assert part.sum().item() == b.sum().item()
+    x = (torch.arange(5000, dtype=torch.float64, device="cuda") % 13) - 6
+    idx = torch.from_numpy(np.random.default_rng(3).integers(0, 5000, 300001).astype(np.int32)).cuda()
+    part.zero_()
+    sp.spmv_gather_probe(idx, x, part)
+    assert part.sum().item() == x[idx.long()].sum().item()
