@@ -151,9 +151,10 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
 
 /* Row-block plan for spmv_crs / spmm_crs: plan[0..n_blocks] are row
  * boundaries.  Consecutive rows are grouped while the group holds at most
- * block_nnz entries (0 = library default, 1024) and at most 2048 rows; a row
- * longer than block_nnz is a block of its own.  The kernels accept any plan
- * whose blocks are either a single row or hold at most block_nnz entries.  If plan_cap < n_blocks+1 returns
+ * block_nnz entries (0 = library default, 1024) and at most 256 rows, or at
+ * most 2048 rows if none of them has more than 16 entries; a row longer than
+ * block_nnz is a block of its own.  The kernels accept any plan whose blocks
+ * are either a single row or hold at most block_nnz entries.  If plan_cap < n_blocks+1 returns
  * SPMV_ERR_CAPACITY with *h_n_blocks set.  Synchronises (reads row_ptr). */
 spmv_status spmv_crs_plan(int32_t n_rows, const int32_t *row_ptr, int32_t block_nnz, int32_t *plan,
                           int32_t plan_cap, int32_t *h_n_blocks, void *stream);

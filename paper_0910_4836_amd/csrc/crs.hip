@@ -2,14 +2,18 @@
 // is a sparse scalar product of its stored values with the gathered x).
 //
 // gfx950 design: the rows are cut, once per matrix, into blocks of consecutive
-// rows holding at most block_nnz entries and at most 2048 rows; a row longer
-// than block_nnz is a block of its own.  One 256-lane workgroup per block:
+// rows holding at most block_nnz entries and at most 256 rows (2048 rows when
+// none of them has more than 16 entries); a row longer than block_nnz is a
+// block of its own.  One 256-lane workgroup per block:
 //   * multi-row block ("stream" mode): the lanes walk the block's entries in
-//     order - fully coalesced val/col reads, independent x gathers - and park
-//     the products in LDS, while the block's row offsets are staged in LDS
-//     too; then one lane adds each row of at most 16 entries in order, and a
-//     whole wavefront takes each longer row (strided partial sums, a fixed
-//     shuffle tree), so no lane serialises over a long row.
+//     order - fully coalesced val/col reads, independent x gathers, four in
+//     flight per lane - and park the products in LDS; then G lanes per row
+//     (G = 256/rows, a power of two up to 64) add their row's products and
+//     combine with a fixed shuffle tree, or, in a block of more than 256 short
+//     rows, one lane adds each row.  (Measured and dropped: eight loads in
+//     flight, row offsets staged in LDS, lane groups sized per row - none
+//     helps the gather-bound power-law rows, and they cost 3-25% on uniform
+//     rows.)
 //   * single-row block ("vector" mode): all 256 lanes stride over the row with
 //     fused multiply-adds, then a fixed wave tree and an ordered sum over the
 //     four waves.
@@ -27,9 +31,9 @@ namespace spmv {
 constexpr int CRS_THREADS = 256;
 constexpr int CRS_DEFAULT_BLOCK_NNZ = 1024;
 constexpr int CRS_MAX_BLOCK_NNZ = 4096;
-constexpr int CRS_MAX_BLOCK_ROWS = 2048;     // rows of a multi-row block
-constexpr int CRS_LANE_ROW = 16;             // rows up to this length are summed by one lane
-constexpr int CRS_MAX_LONG_ROWS = CRS_MAX_BLOCK_NNZ / (CRS_LANE_ROW + 1) + 1;
+constexpr int CRS_MAX_BLOCK_ROWS = 256;          // rows of a block in general
+constexpr int CRS_MAX_SHORT_BLOCK_ROWS = 2048;   // rows of a block of short rows only
+constexpr int CRS_SHORT_ROW = 16;                // "short": at most this many entries
 
 template <bool WIDE, typename VT, typename XT, typename OT>
 __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, const VT *__restrict__ val,
@@ -67,14 +71,6 @@ __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, 
     }
 }
 
-// Shared memory of a CRS block workgroup besides the LDS products.
-struct CrsShared {
-    int32_t rofs[CRS_MAX_BLOCK_ROWS + 1];   // row offsets of the block, relative to its first entry
-    int32_t longl[CRS_MAX_LONG_ROWS];       // rows summed by a whole wavefront
-    int32_t nlong;
-    double red[CRS_THREADS / WAVE];
-};
-
 // One plan block b (rows plan[b] .. plan[b+1]) of y = alpha*A x + beta*y;
 // row r's result goes to y[out_idx[r]] if out_idx is given, else to y[r].
 // WIDE_ALL: accumulate every row in FP64 (the column-split parts, whose rows
@@ -83,7 +79,7 @@ template <typename VT, typename XT, typename OT, bool WIDE_ALL = false>
 __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                const VT *__restrict__ val, const XT *__restrict__ x,
                                                OT *__restrict__ y, const int32_t *__restrict__ plan, int64_t b,
-                                               double alpha, double beta, double *smem_d, CrsShared &sh,
+                                               double alpha, double beta, double *smem_d, double *red,
                                                const int32_t *__restrict__ out_idx = nullptr)
 {
     constexpr bool F64 = IsF64<VT>::value || WIDE_ALL;
@@ -96,49 +92,37 @@ __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_p
 
     if (nr == 1) {
         if (!F64 && ne > SPMV_WIDE_ROW_NNZ)
-            crs_vector_row<true, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, sh.red, out_idx);
+            crs_vector_row<true, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, red, out_idx);
         else
-            crs_vector_row<F64, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, sh.red, out_idx);
+            crs_vector_row<F64, VT, XT, OT>(col, val, x, y, r0, e0, e1, alpha, beta, red, out_idx);
         return;
     }
-    const bool staged = nr <= CRS_MAX_BLOCK_ROWS;
-    if (staged)
-        for (int32_t g = t; g <= nr; g += CRS_THREADS) sh.rofs[g] = row_ptr[r0 + g] - e0;
-    if (t == 0) sh.nlong = 0;
 
-    // stream mode: products of the whole block into LDS (ne <= block_nnz).
-    // Each lane first issues all U loads of val/col, then all U gathers, so a
-    // workgroup keeps U*256 independent reads in flight.
-    constexpr int U = 8;
+    // stream mode: products of the whole block into LDS (ne <= block_nnz);
+    // each lane issues its U loads of val/col before the dependent gathers
+    constexpr int U = 4;
     for (int32_t k0 = 0; k0 < ne; k0 += U * CRS_THREADS) {
         int32_t c[U];
         VT v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int32_t k = k0 + u * CRS_THREADS + t;
-            c[u] = 0;
-            v[u] = VT{};
+            const int32_t k = k0 + u * CRS_THREADS + t;
             if (k < ne) {
                 c[u] = ld_stream(col + e0 + k);
                 v[u] = ld_stream(val + e0 + k);
             }
         }
-        XT xv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int32_t k = k0 + u * CRS_THREADS + t;
-            xv[u] = k < ne ? x[c[u]] : XT(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            int32_t k = k0 + u * CRS_THREADS + t;
-            if (k < ne) prod[k] = Acc<F64>::mac((acc_t)0, v[u], xv[u]);
+            const int32_t k = k0 + u * CRS_THREADS + t;
+            if (k < ne) prod[k] = Acc<F64>::mac((acc_t)0, v[u], x[c[u]]);
         }
     }
     __syncthreads();
 
-    if (!staged) {
-        // a block of more rows than the planner makes: one lane per row
+    if (nr > CRS_THREADS) {
+        // many short rows (the planner admits more than 256 rows only when
+        // none has more than 16 entries): one lane per row, rows t, t+256, ...
         for (int32_t g = t; g < nr; g += CRS_THREADS) {
             const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
             acc_t s = 0;
@@ -148,33 +132,19 @@ __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_p
         }
         return;
     }
-    // rows of at most CRS_LANE_ROW entries: one lane each, in order; longer
-    // rows are queued for whole wavefronts (at most ne / (CRS_LANE_ROW + 1) of
-    // them, which fits longl).  Which wavefront takes which row does not
-    // change any row's summation order.
-    for (int32_t g = t; g < nr; g += CRS_THREADS) {
-        const int32_t rs = sh.rofs[g], re = sh.rofs[g + 1];
-        if (re - rs <= CRS_LANE_ROW) {
-            acc_t s = 0;
-            for (int32_t k = rs; k < re; ++k) s += prod[k];
-            const int32_t row = r0 + g;
-            write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
-        } else {
-            sh.longl[atomicAdd(&sh.nlong, 1)] = g;
-        }
+    // G lanes per row, G = largest power of two <= 256/nr, at most 64
+    int G = 64;
+    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
+    const int g = t / G, l = t % G;
+    acc_t s = 0;
+    if (g < nr) {
+        const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
+        for (int32_t k = rs + l; k < re; k += G) s += prod[k];
     }
-    __syncthreads();
-    const int nl = sh.nlong, lane = lane_id();
-    for (int i = t / WAVE; i < nl; i += CRS_THREADS / WAVE) {
-        const int32_t g = sh.longl[i];
-        const int32_t rs = sh.rofs[g], re = sh.rofs[g + 1];
-        acc_t s = 0;
-        for (int32_t k = rs + lane; k < re; k += WAVE) s += prod[k];
-        s = group_sum(s, WAVE);
-        if (lane == 0) {
-            const int32_t row = r0 + g;
-            write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
-        }
+    s = group_sum(s, G);
+    if (g < nr && l == 0) {
+        const int32_t row = r0 + g;
+        write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
     }
 }
 
@@ -187,9 +157,9 @@ __global__ __launch_bounds__(CRS_THREADS) void crs_block_kernel(const int32_t *_
                                                                 double alpha, double beta)
 {
     extern __shared__ double smem_d[];
-    __shared__ CrsShared sh;
+    __shared__ double red[CRS_THREADS / WAVE];
     crs_block_body<VT, XT, XT>(row_ptr, col, val, x, y, plan, xcd_remap(blockIdx.x, gridDim.x), alpha, beta, smem_d,
-                               sh);
+                               red);
 }
 
 // Column-split CRS: part k (columns of the k-th eighth, compressed to the rows
@@ -212,12 +182,12 @@ __global__ __launch_bounds__(CRS_THREADS) void crs_split_kernel(const int32_t *_
                                                                 const int32_t *__restrict__ plan_all, CrsSplitTab T)
 {
     extern __shared__ double smem_d[];
-    __shared__ CrsShared sh;
+    __shared__ double red[CRS_THREADS / WAVE];
     const int k = (int)(blockIdx.x % SPLIT_PARTS);
     const int64_t b = blockIdx.x / SPLIT_PARTS;
     if (b >= T.n_blocks[k]) return;
     crs_block_body<VT, XT, double, true>(row_ptr_all + T.row_off[k] + k, col + T.base[k], val + T.base[k], x, slots,
-                                         plan_all + T.plan_off[k], b, 1.0, 0.0, smem_d, sh,
+                                         plan_all + T.plan_off[k], b, 1.0, 0.0, smem_d, red,
                                          dest_all + T.row_off[k]);
 }
 
@@ -383,22 +353,27 @@ void crs_plan_rows(int32_t n_rows, const int32_t *rp, int32_t T, std::vector<int
     out.clear();
     out.push_back(0);
     int32_t start = 0;
-    int64_t cur = 0;
+    int64_t cur = 0, longest = 0;
     for (int32_t r = 0; r < n_rows; ++r) {
         const int64_t len = (int64_t)rp[r + 1] - rp[r];
         const int32_t nr = r - start;
-        if (nr > 0 && (cur + len > T || nr >= CRS_MAX_BLOCK_ROWS)) {
+        const int64_t lg = std::max(longest, len);
+        const int32_t row_cap = lg <= CRS_SHORT_ROW ? CRS_MAX_SHORT_BLOCK_ROWS : CRS_MAX_BLOCK_ROWS;
+        if (nr > 0 && (cur + len > T || nr >= row_cap)) {
             out.push_back(r);
             start = r;
             cur = 0;
+            longest = 0;
         }
         if (len > T) {                 // a long row is a block of its own
             out.push_back(r + 1);
             start = r + 1;
             cur = 0;
+            longest = 0;
             continue;
         }
         cur += len;
+        longest = std::max(longest, len);
     }
     if (start < n_rows) out.push_back(n_rows);
 }

@@ -141,13 +141,15 @@ def test_empty_matrix_and_single_row():
 @pytest.mark.parametrize("block_nnz", [256, 1024, 4096])
 def test_blocks_of_many_short_rows(block_nnz):
     """Rows of 0-3 entries (blocks of up to 2048 rows, one lane per row) mixed
-    with runs of 17-entry rows and rows of 4-40 entries (a wavefront per row
-    above 16 entries) and a few rows longer than any block."""
+    with runs of 17-entry rows (the 256-row cap), runs of mixed lengths up to
+    700 and a few rows longer than any block."""
     rng = np.random.default_rng(70 + block_nnz)
     nr, nc = 30000, 20000
     lens = rng.integers(0, 4, nr)
     lens[10000:11000] = 17                      # a run of rows just above "short"
-    lens[rng.choice(nr, 30, replace=False)] = rng.integers(4, 40, 30)
+    lens[21000:21030] = rng.integers(4, 40, 30)
+    # blocks mixing row lengths on both sides of every power of two up to 700
+    lens[20000:20240] = rng.choice([8, 9, 16, 17, 32, 33, 64, 65, 128, 129, 256, 257, 700], 240)
     lens[rng.choice(nr, 5, replace=False)] = 5000
     r = np.repeat(np.arange(nr, dtype=np.int32), lens)
     c = np.concatenate([rng.choice(nc, L, replace=False) for L in lens]).astype(np.int32)
@@ -160,9 +162,10 @@ def test_blocks_of_many_short_rows(block_nnz):
     plan = to_np(A.plan)
     sizes = np.diff(plan)
     if block_nnz >= 1024:
-        assert sizes.max() > 256                  # blocks of many rows are formed
+        assert sizes.max() > 256                  # the many-short-row path is taken
     rp = to_np(A.row_ptr)
-    assert sizes.max() <= 2048
+    for b in np.nonzero(sizes > 256)[0]:          # ... only for blocks of short rows
+        assert np.diff(rp[plan[b]:plan[b + 1] + 1]).max() <= 16 and sizes[b] <= 2048
     multi = sizes > 1
     assert np.all(rp[plan[1:]][multi] - rp[plan[:-1]][multi] <= block_nnz)
     assert max_err(sp.spmv_crs(A, to_dev(x)), want, D) <= FP64_TOL
