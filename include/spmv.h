@@ -244,8 +244,10 @@ spmv_status spmv_dot(int64_t n, const void *x, const void *y, spmv_dtype dt, dou
  * X is first copied into an interleaved row-major block inside ws so that
  * every entry gathers its k values contiguously (k <= 64); without it the
  * kernels gather straight from the column-major X.  Same arithmetic rules as
- * the single-vector forms.  spmm_crs takes the spmv_crs_plan row blocks;
- * spmm_jds takes the host copy h_jd_ptr (needed on the workspace path). */
+ * the single-vector forms.  spmm_crs takes the spmv_crs_plan row blocks and
+ * the block_nnz they were built with (0 = default; on the workspace path a
+ * multi-row block's val/col are staged in LDS, block_nnz of each); spmm_jds
+ * takes the host copy h_jd_ptr (needed on the workspace path). */
 size_t spmm_workspace_size(int32_t n_cols, int32_t k, spmv_dtype vec_dt);
 spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
                      const void *val, spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y,

@@ -1,10 +1,13 @@
 """Differentiable SpMV and the checkpointed Chebyshev recurrence on the GPU.
 
 ``SpMVOperator`` holds a square sparse pattern in JDS storage (values in JDS
-order are the differentiable parameter) together with the JDS storage of its
-transpose and the map that fills A^T's values from A's.  Backward of y = A x:
-    dx    = A^T g       (the JDS kernel on the prebuilt transpose: a gather,
-                          no atomics)
+order are the differentiable parameter) together with a prebuilt storage of
+its transpose and the map that fills A^T's values from A's.  Backward of
+y = A x:
+    dx    = A^T g       (a product with the prebuilt transpose: a gather per
+                          entry, no atomics; CRS storage by default, which
+                          keeps neighbouring rows' x windows together, or
+                          JDS with transpose="jds")
     dval  = g[row] * x[col]   (spmv_grad_vals_jds, in JDS order)
 All arithmetic runs in the library's kernels; this module only sequences calls.
 
@@ -23,13 +26,16 @@ from . import spmv as S
 
 
 class SpMVOperator:
-    def __init__(self, A: S.CSR, unroll: int = 0, max_iters: int = 0):
+    def __init__(self, A: S.CSR, unroll: int = 0, max_iters: int = 0, transpose: str = "crs"):
         if A.n_rows != A.n_cols:
             raise ValueError("the operator must be square")
+        if transpose not in ("crs", "jds"):
+            raise ValueError("transpose must be 'crs' or 'jds'")
         dev = A.device
         self.n = A.n_rows
         self.nnz = A.nnz
         self.unroll, self.max_iters = unroll, max_iters
+        self.transpose = transpose
         # JDS of A, and of A with the CRS position of every entry as payload
         self.J = S.jds_from_csr(A)
         pos = torch.arange(self.nnz, dtype=torch.int32, device=dev)
@@ -38,13 +44,20 @@ class SpMVOperator:
         jds_of_crs = S.spmv_permute_vec(self.jds_src,
                                         torch.arange(self.nnz, dtype=torch.int32, device=dev).view(torch.float32),
                                         inverse=True).view(torch.int32)        # CRS position -> JDS slot
-        # A^T in CRS (pattern + map into A's CRS values), then its JDS
+        # A^T in CRS (pattern + map into A's CRS values)
         rowT, colT, tmap = S.spmv_transpose_csr(A)
-        AT = S.CSR(A.n_cols, A.n_rows, rowT, colT, tmap.view(torch.float32))
-        JT = S.jds_from_csr(AT)
-        # A^T JDS slot -> A CRS position -> A JDS slot
-        self.tmapT = S.spmv_gather_values(JT.jd_val.view(torch.int32).contiguous(), jds_of_crs)
-        self.JT = JT.with_values(None)
+        if transpose == "crs":
+            # A^T CRS slot -> A CRS position -> A JDS slot
+            self.tmapT = S.spmv_gather_values(tmap, jds_of_crs)
+            self.AT = S.spmv_crs_plan(S.CSR(A.n_cols, A.n_rows, rowT, colT, None))
+            self.JT = None
+        else:
+            AT = S.CSR(A.n_cols, A.n_rows, rowT, colT, tmap.view(torch.float32))
+            JT = S.jds_from_csr(AT)
+            # A^T JDS slot -> A CRS position -> A JDS slot
+            self.tmapT = S.spmv_gather_values(JT.jd_val.view(torch.int32).contiguous(), jds_of_crs)
+            self.JT = JT.with_values(None)
+            self.AT = None
         self._valsT = None
         self._valsT_key = None
 
@@ -64,8 +77,10 @@ class SpMVOperator:
         return S.spmv_jds(self.J.with_values(vals), x, y, alpha, beta, self.unroll, self.max_iters)
 
     def rmatvec(self, vals, g, y=None, alpha=1.0, beta=0.0):
-        return S.spmv_jds(self.JT.with_values(self.transposed_values(vals)), g, y, alpha, beta, self.unroll,
-                          self.max_iters)
+        vT = self.transposed_values(vals)
+        if self.AT is not None:
+            return S.spmv_crs(self.AT.with_values(vT), g, y, alpha, beta)
+        return S.spmv_jds(self.JT.with_values(vT), g, y, alpha, beta, self.unroll, self.max_iters)
 
     def grad_vals(self, g, x, out=None, alpha=1.0, beta=0.0):
         return S.spmv_grad_vals_jds(self.J, g, x, out, alpha, beta)

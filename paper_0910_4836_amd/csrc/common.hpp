@@ -40,6 +40,9 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 spmv_status launch_combine(int32_t n, const int32_t *slot_ptr, const double *slots, void *y, spmv_dtype vec_dt,
                            double alpha, double beta, hipStream_t s);
 
+// Default rows-block size of the CRS plans (crs.hip).
+int32_t crs_default_block_nnz();
+
 // Column-major multi-vector kernels (crs.hip, jds.hip), the no-workspace path
 // of spmm_crs / spmm_jds (spmm.hip).
 spmv_status spmm_crs_colmajor(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,

@@ -79,48 +79,73 @@ __device__ __forceinline__ typename Acc<WIDE>::T mm_group_sum(const int32_t *__r
 
 // CRS, interleaved X.  One workgroup per plan block of nr rows: GPR groups
 // per row (GPR = largest power of two <= NG/nr), the row's entries dealt to
-// its groups with stride GPR; the GPR partials are added in group order.
+// its groups with stride GPR; the GPR partials are added in group order.  A
+// multi-row block first copies its val/col into LDS with coalesced loads
+// (the groups of a wavefront work on different rows, so reading val/col
+// straight from memory would touch one line per group per load).
 template <int K2, typename VT, typename XT>
 __global__ __launch_bounds__(MM_THREADS) void spmm_crs_il_kernel(const int32_t *__restrict__ row_ptr,
                                                                  const int32_t *__restrict__ col,
                                                                  const VT *__restrict__ val,
                                                                  const XT *__restrict__ Xr, int32_t k,
                                                                  XT *__restrict__ Y, int64_t ldy,
-                                                                 const int32_t *__restrict__ plan, double alpha,
-                                                                 double beta)
+                                                                 const int32_t *__restrict__ plan, int32_t block_nnz,
+                                                                 double alpha, double beta)
 {
     constexpr int NG = MM_THREADS / K2;
     constexpr bool F64 = IsF64<VT>::value;
     __shared__ double part[NG][K2];
+    extern __shared__ int32_t mm_stage[];               // block_nnz cols, then block_nnz values
+    int32_t *col_s = mm_stage;
+    VT *val_s = reinterpret_cast<VT *>(mm_stage + ((block_nnz + 3) & ~3));
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int32_t r0 = plan[b], r1 = plan[b + 1];
     const int32_t nr = r1 - r0;
-    const int g = (int)threadIdx.x / K2, j = (int)threadIdx.x % K2;
+    const int t = (int)threadIdx.x;
+    const int g = t / K2, j = t % K2;
     int GPR = 1;
     while (GPR * 2 * nr <= NG) GPR *= 2;
     const int sub = g % GPR;
     const int rows_per_round = NG / GPR;
     const bool wide = !F64 && nr == 1 && row_ptr[r1] - row_ptr[r0] > SPMV_WIDE_ROW_NNZ;
+    const bool staged = nr > 1;                           // then ne <= block_nnz (plan contract)
+    int32_t be0 = 0;
+    if (staged) {
+        be0 = row_ptr[r0];
+        const int32_t ne = row_ptr[r1] - be0;
+        for (int32_t i = t; i < ne; i += MM_THREADS) {
+            col_s[i] = ld_stream(col + be0 + i);
+            val_s[i] = ld_stream(val + be0 + i);
+        }
+        __syncthreads();
+    }
     for (int32_t rbase = r0; rbase < r1; rbase += rows_per_round) {
         const int32_t row = rbase + g / GPR;
         double td = 0.0;
         if (row < r1) {
             const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
-            if (F64 || wide) td = mm_group_sum<K2, true, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR);
-            else td = (double)mm_group_sum<K2, false, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR);
+            if (staged) {
+                if (F64) td = mm_group_sum<K2, true, VT, XT>(col_s, val_s, Xr, k, j, e0 - be0 + sub, e1 - be0, GPR);
+                else td = (double)mm_group_sum<K2, false, VT, XT>(col_s, val_s, Xr, k, j, e0 - be0 + sub, e1 - be0,
+                                                                  GPR);
+            } else if (F64 || wide) {
+                td = mm_group_sum<K2, true, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR);
+            } else {
+                td = (double)mm_group_sum<K2, false, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR);
+            }
         }
         if (GPR > 1) {
             part[g][j] = td;
             __syncthreads();
             if (sub == 0 && row < r1) {
                 if (F64 || wide) {
-                    double t = 0.0;
-                    for (int q = 0; q < GPR; ++q) t += part[g + q][j];
-                    td = t;
+                    double t2 = 0.0;
+                    for (int q = 0; q < GPR; ++q) t2 += part[g + q][j];
+                    td = t2;
                 } else {
-                    float t = 0.0f;
-                    for (int q = 0; q < GPR; ++q) t += (float)part[g + q][j];
-                    td = (double)t;
+                    float t2 = 0.0f;
+                    for (int q = 0; q < GPR; ++q) t2 += (float)part[g + q][j];
+                    td = (double)t2;
                 }
             }
             __syncthreads();
@@ -279,11 +304,12 @@ static spmv_status stage(int64_t n, int32_t k, const void *X, int64_t ldx, void 
 
 template <int K2, typename VT, typename XT>
 static void launch_crs_il(const int32_t *row_ptr, const int32_t *col, const void *val, const void *Xr, int32_t k,
-                          void *Y, int64_t ldy, const int32_t *plan, int32_t nb, double alpha, double beta,
-                          hipStream_t s)
+                          void *Y, int64_t ldy, const int32_t *plan, int32_t nb, int32_t block_nnz, double alpha,
+                          double beta, hipStream_t s)
 {
-    spmm_crs_il_kernel<K2, VT, XT><<<nb, MM_THREADS, 0, s>>>(row_ptr, col, (const VT *)val, (const XT *)Xr, k,
-                                                            (XT *)Y, ldy, plan, alpha, beta);
+    const size_t lds = (size_t)((block_nnz + 3) & ~3) * 4 + (size_t)block_nnz * sizeof(VT);
+    spmm_crs_il_kernel<K2, VT, XT><<<nb, MM_THREADS, lds, s>>>(row_ptr, col, (const VT *)val, (const XT *)Xr, k,
+                                                              (XT *)Y, ldy, plan, block_nnz, alpha, beta);
 }
 
 template <int K2, typename VT, typename XT>
@@ -325,8 +351,9 @@ spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
                      spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan, int32_t n_blocks,
                      int32_t block_nnz, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)block_nnz;
     SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && k >= 0, "spmm_crs: negative size");
+    if (block_nnz == 0) block_nnz = crs_default_block_nnz();
+    SPMV_REQUIRE(block_nnz >= 256 && block_nnz <= 4096, "spmm_crs: block_nnz must be in [256, 4096]");
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmm_crs: bad dtype");
     if (n_rows == 0 || k == 0) return SPMV_OK;
     SPMV_REQUIRE(plan && n_blocks >= 0, "spmm_crs: needs a plan from spmv_crs_plan");
@@ -346,8 +373,8 @@ spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
     const int K2v = k2_for(k);
 #define CRS_IL(VDT, VT, XDT, XT)                                                                              \
     if (val_dt == VDT && vec_dt == XDT) {                                                                     \
-        K2_SWITCH(K2v, (launch_crs_il<K2, VT, XT>(row_ptr, col_idx, val, ws, k, Y, ldy, plan, n_blocks, alpha, \
-                                                  beta, s)));                                                 \
+        K2_SWITCH(K2v, (launch_crs_il<K2, VT, XT>(row_ptr, col_idx, val, ws, k, Y, ldy, plan, n_blocks,        \
+                                                  block_nnz, alpha, beta, s)));                               \
         SPMV_CHECK_LAUNCH("spmm_crs");                                                                        \
         return SPMV_OK;                                                                                       \
     }

@@ -37,13 +37,14 @@ def rel_inf(a, b):
 
 
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 2e-3)])
-def test_chebyshev_loss_and_gradient(dtype, tol):
+@pytest.mark.parametrize("transpose", ["crs", "jds"])
+def test_chebyshev_loss_and_gradient(dtype, tol, transpose):
     n = 20000
     R, A = c5_like(n, 500, dtype)
     x = synth.uniform_vector(n, synth.rng_for(5, 3)).astype(dtype)
     loss_ref, dx_ref, dval_ref, ys = oracle.cheb_loss_grad(R, x.astype(np.float64), 20)
     tdt = torch.float32 if dtype == np.float32 else torch.float64
-    op = AG.SpMVOperator(A)
+    op = AG.SpMVOperator(A, transpose=transpose)
     vals = op.J.jd_val.clone().requires_grad_(True)
     xt = to_dev(x).to(tdt).requires_grad_(True)
     loss = AG.chebyshev_loss(op, vals, xt, steps=20, checkpoint=5)

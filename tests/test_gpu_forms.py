@@ -174,12 +174,13 @@ def test_graph_replay_of_single_matrix_kernels():
             assert torch.equal(o, e), rep
 
 
-def test_transposed_product_and_value_gradient():
+@pytest.mark.parametrize("transpose", ["crs", "jds"])
+def test_transposed_product_and_value_gradient(transpose):
     from paper_0910_4836_amd.autograd import SpMVOperator
     r, c, v, n, _, rng = rand_coo(90, 6000, 6000, 0.002, empty_rows=0.05, long_rows=5, long_len=1500)
     R = oracle.csr_from_coo(n, n, r, c, v)
     A = gpu_csr(sp, r, c, v, n, n)
-    op = SpMVOperator(A)
+    op = SpMVOperator(A, transpose=transpose)
     vals = op.J.jd_val
     g = rng.uniform(-1, 1, n)
     x = rng.uniform(-1, 1, n)
@@ -199,9 +200,12 @@ def test_transposed_product_and_value_gradient():
     out = to_dev(np.ones(R.nnz))
     got2 = to_np(op.grad_vals(to_dev(g), to_dev(x), out, alpha=2.0, beta=1.0))
     assert np.allclose(got2, 2.0 * dv_crs[order] + 1.0, rtol=0, atol=4e-16)
-    # values refreshed through the transpose map
-    assert np.array_equal(to_np(op.transposed_values(vals)), R.val[tmap][oracle.jds_from_csr(
-        oracle.CSR(n, n, rowT, colT, np.arange(R.nnz, dtype=np.float64))).jd_val.astype(np.int64)])
+    # values refreshed through the transpose map (A^T's CRS order, or its JDS order)
+    want_vT = R.val[tmap]
+    if transpose == "jds":
+        want_vT = want_vT[oracle.jds_from_csr(oracle.CSR(n, n, rowT, colT, np.arange(R.nnz, dtype=np.float64)))
+                          .jd_val.astype(np.int64)]
+    assert np.array_equal(to_np(op.transposed_values(vals)), want_vT)
 
 
 def test_autotuner_batched_and_cache(tmp_path):
