@@ -12,6 +12,7 @@
 // directly.
 //
 // Without a workspace the column-major kernels of crs.hip / jds.hip run.
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -20,6 +21,7 @@ namespace spmv {
 
 constexpr int MM_THREADS = 256;
 constexpr int MM_MAX_K2 = 64;
+constexpr int MM_JP_LDS = 4097;            // jd_ptr entries staged in LDS (ndiag <= 4096)
 
 // Xr[c*k + j] = X[c + j*ldx]: 64 x 64 tiles through LDS, coalesced both ways.
 template <typename T>
@@ -159,11 +161,53 @@ __global__ __launch_bounds__(MM_THREADS) void spmm_crs_il_kernel(const int32_t *
 // about 32 of the row's diagonals); a workgroup holds NG/GPR rows of a class.
 struct MmClass {
     int32_t wg_end, row_start, row_end, gpr;
+    int32_t len0;       // diagonals of the class's first (longest) row
 };
 struct MmPlan {
     MmClass c[8];
     int32_t ncls;
 };
+
+// One lane's share of a JDS row for the interleaved multi-vector kernel:
+// diagonals sub, sub + GPR, ... of row r, U per trip, stopping (for the whole
+// wavefront) where the wavefront's first and longest row r_first ends.
+template <int K2, bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ double mm_jds_sum(const int32_t *__restrict__ jp, int32_t dlim,
+                                             const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                             const XT *__restrict__ Xr, int32_t k, int j, int32_t r, bool ok,
+                                             int32_t r_first, int sub, int GPR)
+{
+    typedef typename Acc<WIDE>::T acc_t;
+    constexpr int U = 4;
+    const bool jok = j < k;
+    acc_t s = 0;
+    for (int32_t base = 0; base < dlim; base += GPR * U) {
+        if (jp[base + 1] - jp[base] <= r_first) break;
+        int32_t c[U];
+        VT v[U];
+        bool act[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t dd = base + sub + u * GPR;
+            act[u] = false;
+            if (ok && dd < dlim) {
+                const int32_t off = jp[dd];
+                if (r < jp[dd + 1] - off) {
+                    act[u] = true;
+                    c[u] = ld_stream(col + off + r);
+                    v[u] = ld_stream(val + off + r);
+                }
+            }
+        }
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = (act[u] && jok) ? Xr[(int64_t)c[u] * k + j] : XT(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (act[u]) s = Acc<WIDE>::mac(s, v[u], xv[u]);
+    }
+    return (double)s;
+}
 
 template <int K2, typename VT, typename XT>
 __global__ __launch_bounds__(MM_THREADS) void spmm_jds_il_kernel(int32_t ndiag, const int32_t *__restrict__ jp,
@@ -188,39 +232,30 @@ __global__ __launch_bounds__(MM_THREADS) void spmm_jds_il_kernel(int32_t ndiag, 
     const int64_t row64 = (int64_t)K.row_start + (wg - wg0) * (NG / GPR) + g / GPR;
     const bool ok = row64 < K.row_end;
     const int32_t r = (int32_t)(ok ? row64 : 0);
-    // the row's length: first diagonal too short to reach it
-    int32_t len = 0;
-    if (ok) {
-        int32_t lo = 0, hi = ndiag;
-        while (lo < hi) {
-            int32_t mid = (lo + hi) >> 1;
-            if (jp[mid + 1] - jp[mid] > r) lo = mid + 1;
-            else hi = mid;
-        }
-        len = lo;
+    // the wavefront's first row is its longest (rows are in JDS order): the
+    // diagonal loop ends, for the whole wavefront, where that row ends
+    const int g_first = ((int)threadIdx.x / WAVE) * (WAVE / K2);
+    const int64_t rf64 = (int64_t)K.row_start + (wg - wg0) * (NG / GPR) + g_first / GPR;
+    const int32_t r_first = (int32_t)(rf64 < K.row_end ? rf64 : K.row_end);
+    // the row's length decides the accumulator only for reduced-precision values
+    bool wide = false;
+    if (!F64 && ok && ndiag > SPMV_WIDE_ROW_NNZ) wide = jp[SPMV_WIDE_ROW_NNZ + 1] - jp[SPMV_WIDE_ROW_NNZ] > r;
+    // no row of the class has more than len0 diagonals: the part of jd_ptr
+    // this workgroup reads, jd_ptr[0 .. dlim], is staged in LDS when it fits
+    const int32_t dlim = K.len0 < ndiag ? K.len0 : ndiag;
+    extern __shared__ int32_t jp_s[];
+    const bool jp_lds = dlim + 1 <= MM_JP_LDS;
+    if (jp_lds) {
+        for (int32_t i = (int32_t)threadIdx.x; i <= dlim; i += MM_THREADS) jp_s[i] = jp[i];
+        __syncthreads();
     }
-    const bool wide = !F64 && len > SPMV_WIDE_ROW_NNZ;
     double td = 0.0;
-    if (ok) {
-        typedef double accd;
-        const bool jok = j < k;
-        if (F64 || wide) {
-            accd s = 0.0;
-            for (int32_t d = sub; d < len; d += GPR) {
-                const int64_t e = (int64_t)jp[d] + r;
-                const XT xv = jok ? Xr[(int64_t)col[e] * k + j] : XT(0);
-                s = Acc<true>::mac(s, val[e], xv);
-            }
-            td = s;
-        } else {
-            float s = 0.0f;
-            for (int32_t d = sub; d < len; d += GPR) {
-                const int64_t e = (int64_t)jp[d] + r;
-                const XT xv = jok ? Xr[(int64_t)col[e] * k + j] : XT(0);
-                s = Acc<false>::mac(s, val[e], xv);
-            }
-            td = (double)s;
-        }
+    if (jp_lds) {
+        if (F64 || wide) td = mm_jds_sum<K2, true, VT, XT>(jp_s, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR);
+        else td = mm_jds_sum<K2, false, VT, XT>(jp_s, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR);
+    } else {
+        if (F64 || wide) td = mm_jds_sum<K2, true, VT, XT>(jp, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR);
+        else td = mm_jds_sum<K2, false, VT, XT>(jp, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR);
     }
     if (GPR > 1) {
         part[g][j] = td;
@@ -285,6 +320,7 @@ static MmPlan plan_mm_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int
         K.row_start = (int32_t)row;
         K.row_end = (int32_t)end;
         K.gpr = gpr;
+        K.len0 = (int32_t)len_of(row);
         wgs += ceil_div(end - row, NG / gpr);
         K.wg_end = (int32_t)wgs;
         row = end;
@@ -319,7 +355,9 @@ static void launch_jds_il(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, con
 {
     const MmPlan P = plan_mm_jds(n, h_jd_ptr, ndiag, MM_THREADS / K2);
     if (P.ncls == 0) return;
-    spmm_jds_il_kernel<K2, VT, XT><<<(unsigned)P.c[P.ncls - 1].wg_end, MM_THREADS, 0, s>>>(
+    // room for the longest jd_ptr prefix a class stages (dlim + 1 <= min(ndiag + 1, MM_JP_LDS))
+    const size_t lds = sizeof(int32_t) * (size_t)std::min<int64_t>((int64_t)ndiag + 1, MM_JP_LDS);
+    spmm_jds_il_kernel<K2, VT, XT><<<(unsigned)P.c[P.ncls - 1].wg_end, MM_THREADS, lds, s>>>(
         ndiag, jp, perm, symperm, col, (const VT *)val, (const XT *)Xr, k, (XT *)Y, ldy, P, alpha, beta);
 }
 
