@@ -1,0 +1,212 @@
+"""Parity at the full workload sizes, in the configurations bench.py times.
+
+The oracle cannot run every product at these sizes within a test, so each
+check takes a seeded sample of rows (and of matrices for the many-matrix
+form), builds the oracle's CRS of just those rows and compares row by row
+with the same error measures as the small tests:
+  FP64:  |y_i - y_ref_i| / D_i <= 1e-12,  D_i = sum_j |a_ij| |x_j|
+  FP32 values / vectors: the accumulation bound gamma_{L+1}(2^-24) D_i
+      (+ 2^-24 D_i when y is FP32) against the oracle run on the stored
+      (rounded) values and vectors.
+Structure properties that hold at any size (permutation, sorted lengths,
+slot partition) are checked on the whole matrix.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import FP64_TOL, to_dev, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+sp = pytest.importorskip("paper_0910_4836_amd")
+
+U32 = 2.0 ** -24
+N_SAMPLE = 4000
+
+
+def gamma(k, u):
+    return k * u / (1 - k * u)
+
+
+def sample_rows(R: oracle.CSR, rows):
+    """The oracle CRS of rows `rows` of R (all columns kept)."""
+    lens = R.row_lengths()[rows]
+    starts = R.row_ptr[rows].astype(np.int64)
+    idx = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(lens.sum())
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    return oracle.CSR(len(rows), R.n_cols, rp, R.col[idx], R.val[idx])
+
+
+def coo_rows(n, r, c, v, rows):
+    """The oracle CRS of rows `rows` of the COO matrix (r, c, v): only their
+    triplets go through the oracle's COO -> CRS, so the test never sorts the
+    whole matrix on the host."""
+    keep = np.zeros(n, dtype=bool)
+    keep[rows] = True
+    sel = keep[r]
+    return sample_rows(oracle.csr_from_coo(n, n, r[sel], c[sel], np.asarray(v[sel], np.float64)), rows)
+
+
+def pick(n, seed, extra=()):
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([rng.choice(n, min(n, N_SAMPLE), replace=False), np.asarray(extra, np.int64)]))
+    return rows.astype(np.int64)
+
+
+@pytest.fixture(scope="module")
+def powerlaw():
+    r, c, v, n, _ = synth.powerlaw()
+    x = synth.uniform_vector(n, synth.rng_for(2, 1))
+    A = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v))
+    return (r, c, v, n), A, x
+
+
+def test_powerlaw_every_form_sampled(powerlaw):
+    (r, c, v, n), A, x = powerlaw
+    L = np.bincount(r, minlength=n)
+    nnz = len(r)
+    rows = pick(n, 11, extra=np.argsort(-L)[:50])            # plus the 50 longest rows
+    sub = coo_rows(n, r, c, v, rows)
+    want = oracle.spmv_crs(sub, x)
+    D = oracle.row_absdot(sub, x)
+    J = sp.jds_from_csr(A)
+    B = sp.jds_blocked_from_jds(J, 64)
+    S = sp.Split(A)
+    xd = to_dev(x)
+    forms = {"crs": lambda: sp.spmv_crs(A, xd), "jds": lambda: sp.spmv_jds(J, xd),
+             "blocked": lambda: sp.spmv_jds_blocked(B, xd), "crs_split": lambda: sp.spmv_crs_split(S, xd),
+             "jds_split": lambda: sp.spmv_jds_split(S, xd), "blocked_split": lambda: sp.spmv_jds_blocked_split(S, xd)}
+    for name, fn in forms.items():
+        got = to_np(fn())[rows]
+        e = oracle.rel_err(got, want, D).max()
+        assert e <= FP64_TOL, f"{name}: {e:.3e}"
+    # structure at full size: perm is a permutation sorting lengths down, ties by index
+    perm = to_np(J.perm)[:n].astype(np.int64)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    Lp = L[perm]
+    assert np.all(np.diff(Lp) <= 0)
+    same = np.diff(Lp) == 0
+    assert np.all(np.diff(perm)[same] > 0)
+    assert J.ndiag == L.max() and int(to_np(J.jd_ptr)[J.ndiag]) == nnz
+    assert B.padded >= nnz
+    # slots: one per (row, part) pair present
+    assert S.n_slots == int(to_np(S.slot_ptr)[-1]) and S.n_slots <= min(nnz, 8 * n)
+
+
+def test_powerlaw_fp32_values_sampled(powerlaw):
+    (r, c, v, n), A, x = powerlaw
+    rows = pick(n, 12)
+    sub = coo_rows(n, r, c, oracle.round_f32(v).astype(np.float64), rows)
+    want = oracle.spmv_crs(sub, x)
+    D = oracle.row_absdot(sub, x)
+    lim = np.where(sub.row_lengths() > 4096, gamma(sub.row_lengths() + 1, 2.0 ** -53),
+                   gamma(sub.row_lengths() + 1, U32)) * D
+    A32 = A.with_values(sp.spmv_convert_values(A.val, torch.float32))
+    A32.plan = None
+    J32 = sp.jds_from_csr(A32)
+    B32 = sp.jds_blocked_from_jds(J32, 64)
+    xd = to_dev(x)
+    for name, fn in (("crs", lambda: sp.spmv_crs(A32, xd)), ("jds", lambda: sp.spmv_jds(J32, xd)),
+                     ("blocked", lambda: sp.spmv_jds_blocked(B32, xd))):
+        got = to_np(fn())[rows]
+        assert np.all(np.abs(got - want) <= lim), name
+
+
+def test_powerlaw_multi_vector_sampled(powerlaw):
+    (r, c, v, n), A, x = powerlaw
+    rows = pick(n, 13)
+    sub = coo_rows(n, r, c, v, rows)
+    J = sp.jds_from_csr(A)
+    for k in (8, 32):
+        X = np.random.default_rng(k).uniform(-1, 1, (n, k))
+        Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda").t()
+        for name, fn in (("crs", lambda: sp.spmm_crs(A, Xd)), ("jds", lambda: sp.spmm_jds(J, Xd))):
+            Y = to_np(fn())
+            for j in (0, k // 2, k - 1):
+                want = oracle.spmv_crs(sub, X[:, j])
+                e = oracle.rel_err(Y[rows, j], want, oracle.row_absdot(sub, X[:, j])).max()
+                assert e <= FP64_TOL, (name, k, j, e)
+        del Xd
+
+
+def test_symmetric_diagonals_sampled():
+    r, c, v, n, _ = synth.sym_diagonals()
+    x = synth.uniform_vector(n, synth.rng_for(3, 1))
+    A = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v))
+    rows = pick(n, 14, extra=[0, 1, n // 2, n - 2, n - 1])
+    sub = coo_rows(n, r, c, v, rows)
+    del r, c, v
+    want = oracle.spmv_crs(sub, x)
+    D = oracle.row_absdot(sub, x)
+    J = sp.jds_from_csr(A)
+    B = sp.jds_blocked_from_jds(J, 64)
+    xd = to_dev(x)
+    for name, fn in (("crs", lambda: sp.spmv_crs(A, xd)), ("jds", lambda: sp.spmv_jds(J, xd)),
+                     ("blocked", lambda: sp.spmv_jds_blocked(B, xd))):
+        e = oracle.rel_err(to_np(fn())[rows], want, D).max()
+        assert e <= FP64_TOL, f"{name}: {e:.3e}"
+    # reduced-precision values on the same rows
+    for vdt in (torch.float32, torch.bfloat16):
+        if vdt == torch.float32:
+            vq = oracle.round_f32(sub.val).astype(np.float64)
+        else:
+            vq = oracle.bf16_bits_to_f64(oracle.round_bf16_bits(sub.val))
+        subq = oracle.CSR(sub.n_rows, n, sub.row_ptr, sub.col, vq)
+        wq = oracle.spmv_crs(subq, x)
+        lim = gamma(subq.row_lengths() + 1, U32) * oracle.row_absdot(subq, x)
+        Jq = J.with_values(sp.spmv_convert_values(J.jd_val, vdt))
+        Bq = B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
+        for name, fn in (("jds", lambda: sp.spmv_jds(Jq, xd)), ("blocked", lambda: sp.spmv_jds_blocked(Bq, xd))):
+            assert np.all(np.abs(to_np(fn())[rows] - wq) <= lim), (vdt, name)
+
+
+def test_chebyshev_operator_sampled():
+    """The banded + uniform FP32 operator: forward and transposed products."""
+    from paper_0910_4836_amd import autograd as AG
+    r, c, v, n, _ = synth.banded_uniform()
+    A = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v))
+    op = AG.SpMVOperator(A)
+    vals = op.J.jd_val
+    x = synth.uniform_vector(n, synth.rng_for(5, 1), np.float32)
+    xd = to_dev(x)
+    rows = pick(n, 15, extra=[0, n - 1])
+    sub = coo_rows(n, r, c, v, rows)
+    xx = x.astype(np.float64)
+    want = oracle.spmv_crs(sub, xx)
+    lim = (gamma(sub.row_lengths() + 1, U32) + U32) * oracle.row_absdot(sub, xx)
+    got = to_np(op.matvec(vals, xd)).astype(np.float64)[rows]
+    assert np.all(np.abs(got - want) <= lim)
+    # A^T g on sampled rows of A^T (the triplets with their roles swapped)
+    subT = coo_rows(n, c, r, v, rows)
+    wT = oracle.spmv_crs(subT, xx)
+    limT = (gamma(subT.row_lengths() + 1, U32) + U32) * oracle.row_absdot(subT, xx)
+    gotT = to_np(op.rmatvec(vals, xd)).astype(np.float64)[rows]
+    assert np.all(np.abs(gotT - wT) <= limT)
+
+
+def test_many_matrices_sampled():
+    """All 512 matrices in one persistent launch; a seeded sample of matrices
+    (the largest and smallest among them) is checked against the oracle."""
+    dev = torch.device("cuda", 0)
+    mats, xs, host = [], [], []
+    sizes = synth.many_matrix_sizes()
+    rng = np.random.default_rng(16)
+    check = set(rng.choice(len(sizes), 6, replace=False).tolist()) | {int(np.argmax(sizes)), int(np.argmin(sizes))}
+    for m, (r, c, v, n, x) in enumerate(synth.many_matrices()):
+        A = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v))
+        mats.append(sp.jds_blocked_from_jds(sp.jds_from_csr(A), 64))
+        xs.append(to_dev(x))
+        host.append((r, c, v, n, x) if m in check else None)
+        del A
+    Bt = sp.Batched(mats)
+    y = to_np(Bt(torch.cat(xs)))
+    for m in sorted(check):
+        r, c, v, n, x = host[m]
+        R = oracle.csr_from_coo(n, n, r, c, v.astype(np.float64))
+        xx = x.astype(np.float64)
+        want = oracle.spmv_crs(R, xx)
+        lim = (gamma(R.row_lengths() + 1, U32) + U32) * oracle.row_absdot(R, xx)
+        got = y[Bt.row_base[m]:Bt.row_base[m] + n].astype(np.float64)
+        assert np.all(np.abs(got - want) <= lim), m
