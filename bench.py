@@ -4,7 +4,9 @@
 Default run (the headline line): the power-law workload (n = 2,000,000 rows,
 row lengths ~ L^-1.6929 on [1, 2000], mean 15 entries, half band / half uniform
 columns, N(0,1) values, x ~ U[-1, 1]).  One step = the three FP64 products
-CRS, JDS and blocked JDS (C = 64) on that matrix, inputs resident in HBM.
+CRS, JDS and blocked JDS on that matrix, inputs resident in HBM; the JDS
+unroll / split threshold and the blocked slice height / rows per wavefront /
+unroll come from the library's autotuner, run on the device during setup.
 Prints ONE JSON line with GFLOP/s (2 flops per stored entry), the per-kernel
 times, the roofline of the dominant kernel (algorithmic bytes / its average
 launch time, against 8 TB/s) and the serial CPU oracle timed on the host as a
@@ -23,6 +25,7 @@ import json
 import os
 import platform
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -193,17 +196,25 @@ def load_powerlaw(torch, sp, dev):
     del rd, cd, vd
     timed("crs_plan_ms", lambda: sp.spmv_crs_plan(A))
     J = timed("jds_from_csr_ms", lambda: sp.jds_from_csr(A))
-    B = timed("jds_blocked_from_jds_ms", lambda: sp.jds_blocked_from_jds(J, 64))
+    xd = torch.from_numpy(x).to(dev)
+    # launch parameters from the library's autotuner, timed on this device
+    # (fresh cache, so nothing is carried over from another machine)
+    from paper_0910_4836_amd import autotune
+    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    jds_u, jds_mi = timed("autotune_jds_ms", lambda: tuner.tune_jds(J, xd))
+    bC, bR, bU = timed("autotune_blocked_ms", lambda: tuner.tune_blocked(J, xd))
+    B = timed("jds_blocked_from_jds_ms", lambda: sp.jds_blocked_from_jds(J, bC))
     A32 = A.with_values(sp.spmv_convert_values(A.val, torch.float32))
     J32 = J.with_values(sp.spmv_convert_values(J.jd_val, torch.float32))
     B32 = B.with_values(sp.spmv_convert_values(B.bl_val, torch.float32))
     S = timed("split_columns_ms", lambda: sp.Split(A))
     timed("split_jds_parts_ms", lambda: S.jds_parts())
     timed("split_blocked_parts_ms", lambda: S.blocked_parts(64))
-    xd = torch.from_numpy(x).to(dev)
     host = (r, c, v, n, x)
+    tune = {"jds_unroll": jds_u, "jds_max_iters": jds_mi, "blocked_C": bC, "blocked_rows_per_wave": bR,
+            "blocked_unroll": bU}
     return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, S=S, x=xd, n=n, nnz=A.nnz, setup=setup, gen_s=gen_s,
-                host=host)
+                host=host, tune=tune)
 
 
 def powerlaw_kernels(sp, W, torch):
@@ -211,13 +222,15 @@ def powerlaw_kernels(sp, W, torch):
     y = torch.empty(n, dtype=torch.float64, device=W["x"].device)
     x = W["x"]
     J, B = W["J"], W["B"]
+    T = W["tune"]
+    ju, jm, bR, bU = T["jds_unroll"], T["jds_max_iters"], T["blocked_rows_per_wave"], T["blocked_unroll"]
     ks = [
         ("crs_f64", lambda: sp.spmv_crs(W["A"], x, y)),
-        ("jds_f64", lambda: sp.spmv_jds(J, x, y)),
-        ("blocked_f64", lambda: sp.spmv_jds_blocked(B, x, y)),
+        ("jds_f64", lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm)),
+        ("blocked_f64", lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU)),
         ("crs_f32val", lambda: sp.spmv_crs(W["A32"], x, y)),
-        ("jds_f32val", lambda: sp.spmv_jds(W["J32"], x, y)),
-        ("blocked_f32val", lambda: sp.spmv_jds_blocked(W["B32"], x, y)),
+        ("jds_f32val", lambda: sp.spmv_jds(W["J32"], x, y, unroll=ju, max_iters=jm)),
+        ("blocked_f32val", lambda: sp.spmv_jds_blocked(W["B32"], x, y, rows_per_wave=bR, unroll=bU)),
     ]
     S = W["S"]
     S32 = W.setdefault("S32", S.with_values(sp.spmv_convert_values(S.val, torch.float32)))
@@ -251,7 +264,7 @@ def cpu_baseline(W, budget_s=20.0):
     r, c, v, n, x = W["host"]
     A = oracle.csr_from_coo(n, n, r, c, v)
     J = oracle.jds_from_csr(A)
-    Bk = oracle.blocked_from_jds(J, 64)
+    Bk = oracle.blocked_from_jds(J, W["tune"]["blocked_C"])
     step = [lambda: oracle.spmv_crs(A, x), lambda: oracle.spmv_jds(J, x), lambda: oracle.spmv_blocked(Bk, x)]
     reps = 0
     t0 = time.process_time()
@@ -526,8 +539,9 @@ def main():
         "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"power-law n={W['n']} nnz={W['nnz']} (mean 15/row, max 2000): CRS, JDS and "
-                               f"blocked JDS (C=64) products in FP64",
-                   "n": W["n"], "nnz": W["nnz"], "ndiag": W["J"].ndiag, "products_per_step": len(ks)},
+                               f"blocked JDS (C={W['tune']['blocked_C']}) products in FP64",
+                   "n": W["n"], "nnz": W["nnz"], "ndiag": W["J"].ndiag, "products_per_step": len(ks),
+                   "autotuned": W["tune"]},
         "kernels": kernels,
         "roofline": roofline_for(dom, bmin[dom], per[dom], "powerlaw"),
         "setup_ms": W["setup"],

@@ -1,5 +1,6 @@
-"""Autotuner for the blocked-JDS products: slice height C, rows per wavefront R
-and diagonals per trip U, chosen per row-length signature and cached.
+"""Autotuner for the JDS and blocked-JDS products: slice height C, rows per
+wavefront R, diagonals per trip U and diagonals per wavefront before a row is
+split (max_iters), chosen per row-length signature and cached.
 
 The signature of a matrix is (log2 of its row count, its longest row, its
 mean row length rounded to a power of two); matrices that share it share the
@@ -25,8 +26,9 @@ from . import spmv as S
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "spmv_autotune.json")
 C_CANDIDATES = (64, 128, 256)
-R_CANDIDATES = (64, 32, 16)
+R_CANDIDATES = (0, 64, 32, 16)      # 0: the library's choice per length class
 U_CANDIDATES = (2, 4, 8)
+MAX_ITERS_CANDIDATES = (0, 64, 128)  # 0: the library default
 
 
 def signature(n_rows: int, row_lengths: np.ndarray) -> str:
@@ -82,7 +84,9 @@ class Autotuner:
 
     def lookup(self, sig: str):
         ent = self.cache.get(_device_key(), {}).get(sig)
-        return None if ent is None else (ent["C"], ent["R"], ent["U"])
+        if ent is None:
+            return None
+        return (ent["U"], ent["max_iters"]) if "max_iters" in ent else (ent["C"], ent["R"], ent["U"])
 
     def _record(self, sig, best, timings):
         self.cache.setdefault(_device_key(), {})[sig] = {"C": best[0], "R": best[1], "U": best[2],
@@ -145,6 +149,25 @@ class Autotuner:
         self.log.append({"signature": sig, "timings_ms": {f"C{c}_R{r}_U{u}": round(t, 5)
                                                           for (c, r, u), t in timings.items()}})
         self._record(sig, best, timings)
+        return best
+
+
+    def tune_jds(self, J: S.JDS, x: torch.Tensor, mis=MAX_ITERS_CANDIDATES) -> Tuple[int, int]:
+        """Best (U, max_iters) for one large matrix in JDS storage."""
+        sig = "jds:" + signature(J.n, np.diff(J.h_jd_ptr))
+        hit = self.lookup(sig)
+        if hit is not None:
+            return hit
+        timings = {}
+        y = torch.empty(J.n, dtype=x.dtype, device=x.device)
+        for U in self.us:
+            for mi in mis:
+                timings[(U, mi)] = _time(lambda: S.spmv_jds(J, x, y, unroll=U, max_iters=mi))
+        best = min(timings, key=timings.get)
+        self.log.append({"signature": sig, "timings_ms": {f"U{u}_mi{m}": round(t, 5) for (u, m), t in timings.items()}})
+        self.cache.setdefault(_device_key(), {})[sig] = {"U": best[0], "max_iters": best[1],
+                                                        "ms": round(timings[best], 5)}
+        _store(self.cache_path, self.cache)
         return best
 
 

@@ -231,3 +231,18 @@ def test_autotuner_batched_and_cache(tmp_path):
     # a second tuner reads the cached choice without timing anything
     t2 = autotune.Autotuner(cache, cs=(64, 128), rs=(64, 16), us=(2, 4))
     assert t2.tune_batched(jds) == (Bt.mats_C, Bt.rows_per_wave, Bt.unroll) and not t2.log
+    # single-matrix tuning (JDS and blocked JDS): any choice computes the same y
+    r, c, v, n, _, rng = rand_coo(95, 20000, 20000, 0.001, long_rows=10, long_len=3000)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    A = gpu_csr(sp, r, c, v, n, n)
+    J = sp.jds_from_csr(A)
+    xx = rng.uniform(-1, 1, n)
+    xd = to_dev(xx)
+    want, D = oracle.spmv_crs(R, xx), oracle.row_absdot(R, xx)
+    U, mi = tuner.tune_jds(J, xd)
+    assert max_err(sp.spmv_jds(J, xd, unroll=U, max_iters=mi), want, D) <= FP64_TOL
+    C_, R_, U2 = tuner.tune_blocked(J, xd)
+    B = sp.jds_blocked_from_jds(J, C_)
+    assert max_err(sp.spmv_jds_blocked(B, xd, rows_per_wave=R_, unroll=U2), want, D) <= FP64_TOL
+    t3 = autotune.Autotuner(cache, cs=(64, 128), rs=(64, 16), us=(2, 4))
+    assert t3.tune_jds(J, xd) == (U, mi) and t3.tune_blocked(J, xd) == (C_, R_, U2) and not t3.log
