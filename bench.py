@@ -371,19 +371,26 @@ def suite_symdiag(torch, sp, dev, steps):
     A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
     del r, c, v
     J = sp.jds_from_csr(A)
-    B = sp.jds_blocked_from_jds(J, 64)
     x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(3, 1))).to(dev)
+    from paper_0910_4836_amd import autotune
+    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    ju, jm = tuner.tune_jds(J, x)
+    bC, bR, bU = tuner.tune_blocked(J, x)
+    B = sp.jds_blocked_from_jds(J, bC)
     nnz = A.nnz
     y_ref = sp.spmv_crs(A, x)
     out = {"workload": f"symmetric 12 secondary diagonals + diagonal, n={n}, nnz={nnz}", "kernels": {},
-           "max_rel_err_vs_fp64": {}}
+           "max_rel_err_vs_fp64": {},
+           "autotuned": {"jds_unroll": ju, "jds_max_iters": jm, "blocked_C": bC, "blocked_rows_per_wave": bR,
+                         "blocked_unroll": bU}}
     y = torch.empty(n, dtype=torch.float64, device=dev)
     for vdt, sv, tag in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32val"), (torch.bfloat16, 2, "bf16val")):
         Aq = A if vdt == torch.float64 else A.with_values(sp.spmv_convert_values(A.val, vdt))
         Jq = J if vdt == torch.float64 else J.with_values(sp.spmv_convert_values(J.jd_val, vdt))
         Bq = B if vdt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
-        ks = [(f"crs_{tag}", lambda Aq=Aq: sp.spmv_crs(Aq, x, y)), (f"jds_{tag}", lambda Jq=Jq: sp.spmv_jds(Jq, x, y)),
-              (f"blocked_{tag}", lambda Bq=Bq: sp.spmv_jds_blocked(Bq, x, y))]
+        ks = [(f"crs_{tag}", lambda Aq=Aq: sp.spmv_crs(Aq, x, y)),
+              (f"jds_{tag}", lambda Jq=Jq: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm)),
+              (f"blocked_{tag}", lambda Bq=Bq: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU))]
         _, per = time_loop(torch, ks, max(10, steps // 4), 3)
         bm = {ks[0][0]: bytes_crs(nnz, n, n, sv, 8), ks[1][0]: bytes_jds(nnz, n, n, J.ndiag, sv, 8),
               ks[2][0]: bytes_blocked(nnz, n, n, B.n_slices, sv, 8)}
