@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--only", default="", help="comma list of kernels for profiling runs")
     ap.add_argument("--probe", choices=["copy", "triad"], default=None,
                     help="run only the bandwidth probe on 1 GiB arrays (counter calibration)")
+    ap.add_argument("--tune-cache", default="",
+                    help="autotuner cache file (default: a fresh one, i.e. tune on this device now); "
+                         "profiling runs share one so they time the same kernels")
     return ap.parse_args()
 
 
@@ -172,7 +175,7 @@ def measured_traffic(kernel, workload):
 # --------------------------------------------------------------------------- workloads
 
 
-def load_powerlaw(torch, sp, dev):
+def load_powerlaw(torch, sp, dev, tune_cache=""):
     import synth
     t0 = time.time()
     r, c, v, n, _ = synth.powerlaw()
@@ -200,7 +203,7 @@ def load_powerlaw(torch, sp, dev):
     # launch parameters from the library's autotuner, timed on this device
     # (fresh cache, so nothing is carried over from another machine)
     from paper_0910_4836_amd import autotune
-    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    tuner = autotune.Autotuner(cache_path=tune_cache or os.path.join(tempfile.mkdtemp(), "autotune.json"))
     jds_u, jds_mi = timed("autotune_jds_ms", lambda: tuner.tune_jds(J, xd))
     bC, bR, bU = timed("autotune_blocked_ms", lambda: tuner.tune_blocked(J, xd))
     B = timed("jds_blocked_from_jds_ms", lambda: sp.jds_blocked_from_jds(J, bC))
@@ -519,7 +522,7 @@ def main():
     sp.load_library()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    W = load_powerlaw(torch, sp, dev)
+    W = load_powerlaw(torch, sp, dev, args.tune_cache)
     all_ks, bmin = powerlaw_kernels(sp, W, torch)
     # the step: the three FP64 products of the power-law workload
     ks = [k for k in all_ks if k[0].endswith("_f64") and "_split" not in k[0]]
