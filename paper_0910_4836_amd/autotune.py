@@ -31,16 +31,20 @@ U_CANDIDATES = (2, 4, 8)
 MAX_ITERS_CANDIDATES = (0, 64, 128)  # 0: the library default
 
 
-def signature(n_rows: int, row_lengths: np.ndarray) -> str:
-    if n_rows == 0 or len(row_lengths) == 0:
+def signature(n_rows: int, longest: int, nnz: int) -> str:
+    """(log2 of the row count, the longest row, the mean row length rounded
+    to a power of two)."""
+    if n_rows == 0 or nnz == 0:
         return "empty"
-    mx = int(row_lengths.max())
-    mean = float(row_lengths.mean())
-    return f"n2^{int(math.log2(max(n_rows, 1)))}/max{mx}/mean2^{int(round(math.log2(max(mean, 1.0))))}"
+    mean = nnz / n_rows
+    return f"n2^{int(math.log2(max(n_rows, 1)))}/max{longest}/mean2^{int(round(math.log2(max(mean, 1.0))))}"
 
 
 def _device_key() -> str:
-    return torch.cuda.get_device_name(torch.cuda.current_device())
+    """The GPU architecture and compute-unit count (the marketing name can be
+    empty, e.g. under a profiler)."""
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{getattr(p, 'gcnArchName', '') or p.name}/{p.multi_processor_count}CU"
 
 
 def _load(path):
@@ -133,7 +137,7 @@ class Autotuner:
 
     def tune_blocked(self, J: S.JDS, x: torch.Tensor) -> Tuple[int, int, int]:
         """Best (C, R, U) for one large matrix in blocked-JDS storage."""
-        sig = "single:" + signature(J.n, np.diff(J.h_jd_ptr))
+        sig = "single:" + signature(J.n, J.ndiag, int(J.h_jd_ptr[J.ndiag]))
         hit = self.lookup(sig)
         if hit is not None:
             return hit
@@ -154,7 +158,7 @@ class Autotuner:
 
     def tune_jds(self, J: S.JDS, x: torch.Tensor, mis=MAX_ITERS_CANDIDATES) -> Tuple[int, int]:
         """Best (U, max_iters) for one large matrix in JDS storage."""
-        sig = "jds:" + signature(J.n, np.diff(J.h_jd_ptr))
+        sig = "jds:" + signature(J.n, J.ndiag, int(J.h_jd_ptr[J.ndiag]))
         hit = self.lookup(sig)
         if hit is not None:
             return hit
