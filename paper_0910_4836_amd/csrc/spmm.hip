@@ -23,25 +23,29 @@ constexpr int MM_THREADS = 256;
 constexpr int MM_MAX_K2 = 64;
 constexpr int MM_JP_LDS = 4097;            // jd_ptr entries staged in LDS (ndiag <= 4096)
 
-// Xr[c*k + j] = X[c + j*ldx]: 64 x 64 tiles through LDS, coalesced both ways.
+// Xr[c*k + j] = X[c + j*ldx] (k <= 64): a block of STAGE_ELEMS / k rows
+// through LDS.  Reads walk each column's run of rows (coalesced), writes walk
+// the block's contiguous stretch of Xr (coalesced).
+constexpr int STAGE_ELEMS = 2048;
+
 template <typename T>
 __global__ __launch_bounds__(256) void stage_rowmajor_kernel(int64_t n, int32_t k, const T *__restrict__ X, int64_t ldx,
                                                              T *__restrict__ Xr)
 {
-    __shared__ T tile[64][65];
-    const int64_t c0 = (int64_t)blockIdx.x * 64;
-    const int j0 = blockIdx.y * 64;
-    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
-    for (int jj = ty; jj < 64; jj += 4) {
-        const int j = j0 + jj;
-        const int64_t c = c0 + tx;
-        if (j < k && c < n) tile[jj][tx] = X[c + (int64_t)j * ldx];
+    __shared__ T tile[2 * STAGE_ELEMS];                 // rows * (k + 1) <= STAGE_ELEMS + rows
+    const int rows = STAGE_ELEMS / k;                   // rows of this block (k <= 64)
+    const int64_t c0 = (int64_t)blockIdx.x * rows;
+    const int nr = n - c0 < rows ? (int)(n - c0) : rows;
+    const int tot = nr * k;
+    const int stride = k + 1;                           // padded LDS rows
+    for (int f = (int)threadIdx.x; f < rows * k; f += 256) {
+        const int r = f % rows, j = f / rows;
+        if (r < nr) tile[r * stride + j] = X[c0 + r + (int64_t)j * ldx];
     }
     __syncthreads();
-    for (int cc = ty; cc < 64; cc += 4) {
-        const int64_t c = c0 + cc;
-        const int j = j0 + tx;
-        if (j < k && c < n) Xr[c * k + j] = tile[tx][cc];
+    for (int f = (int)threadIdx.x; f < tot; f += 256) {
+        const int r = f / k, j = f % k;
+        Xr[c0 * k + f] = tile[r * stride + j];
     }
 }
 
@@ -332,8 +336,8 @@ static MmPlan plan_mm_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int
 template <typename T>
 static spmv_status stage(int64_t n, int32_t k, const void *X, int64_t ldx, void *Xr, hipStream_t s)
 {
-    dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(k, 64));
-    stage_rowmajor_kernel<T><<<grid, 256, 0, s>>>(n, k, (const T *)X, ldx, (T *)Xr);
+    const int64_t rows = STAGE_ELEMS / k;              // k <= MM_MAX_K2 = 64
+    stage_rowmajor_kernel<T><<<(unsigned)ceil_div(n, rows), 256, 0, s>>>(n, k, (const T *)X, ldx, (T *)Xr);
     SPMV_CHECK_LAUNCH("spmm staging");
     return SPMV_OK;
 }
