@@ -11,7 +11,8 @@ Prints ONE JSON line with GFLOP/s (2 flops per stored entry), the per-kernel
 times, the roofline of the dominant kernel (algorithmic bytes / its average
 launch time, against 8 TB/s) and the serial CPU oracle timed on the host as a
 reported baseline.  Beside the step (not in it) the same line reports the
-FP32-value products and the column-split forms of all three.
+FP32-value products, the column-split forms of all three and the row-split
+forms of the two JDS products.
 
 --suite adds one JSON line per other workload (Laplacian, symmetric diagonals
 in FP64/FP32/BF16, multi-vector, many matrices, Chebyshev backward).
@@ -213,10 +214,13 @@ def load_powerlaw(torch, sp, dev, tune_cache=""):
     S = timed("split_columns_ms", lambda: sp.Split(A))
     timed("split_jds_parts_ms", lambda: S.jds_parts())
     timed("split_blocked_parts_ms", lambda: S.blocked_parts(64))
+    RS = timed("split_rows_ms", lambda: sp.RowSplit(A))
+    timed("row_split_jds_parts_ms", lambda: RS.jds_parts())
+    timed("row_split_blocked_parts_ms", lambda: RS.blocked_parts(bC))
     host = (r, c, v, n, x)
     tune = {"jds_unroll": jds_u, "jds_max_iters": jds_mi, "blocked_C": bC, "blocked_rows_per_wave": bR,
             "blocked_unroll": bU}
-    return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, S=S, x=xd, n=n, nnz=A.nnz, setup=setup, gen_s=gen_s,
+    return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, S=S, RS=RS, x=xd, n=n, nnz=A.nnz, setup=setup, gen_s=gen_s,
                 host=host, tune=tune)
 
 
@@ -245,6 +249,16 @@ def powerlaw_kernels(sp, W, torch):
         ("jds_split_f32val", lambda: sp.spmv_jds_split(S32, x, y)),
         ("blocked_split_f32val", lambda: sp.spmv_jds_blocked_split(S32, x, y)),
     ]
+    RS, bC = W["RS"], T["blocked_C"]
+    RS32 = W.setdefault("RS32", RS.with_values(torch.float32))
+    ks += [
+        ("jds_rowsplit_f64", lambda: sp.spmv_jds_row_split(RS, x, y, unroll=ju, max_iters=jm)),
+        ("blocked_rowsplit_f64", lambda: sp.spmv_jds_blocked_row_split(RS, x, y, C_=bC, rows_per_wave=bR,
+                                                                         unroll=bU)),
+        ("jds_rowsplit_f32val", lambda: sp.spmv_jds_row_split(RS32, x, y, unroll=ju, max_iters=jm)),
+        ("blocked_rowsplit_f32val", lambda: sp.spmv_jds_blocked_row_split(RS32, x, y, C_=bC, rows_per_wave=bR,
+                                                                            unroll=bU)),
+    ]
     bmin = {
         "crs_f64": bytes_crs(nnz, n, n, 8, 8),
         "jds_f64": bytes_jds(nnz, n, n, J.ndiag, 8, 8),
@@ -253,10 +267,11 @@ def powerlaw_kernels(sp, W, torch):
         "jds_f32val": bytes_jds(nnz, n, n, J.ndiag, 4, 8),
         "blocked_f32val": bytes_blocked(nnz, n, n, B.n_slices, 4, 8),
     }
-    # the column-split forms move the same algorithmic bytes as the unsplit ones
+    # the column- and row-split forms move the same algorithmic bytes as the unsplit ones
     for k in list(bmin):
         base, tag = k.split("_", 1)
         bmin[f"{base}_split_{tag}"] = bmin[k]
+        bmin[f"{base}_rowsplit_{tag}"] = bmin[k]
     return ks, bmin
 
 
@@ -525,14 +540,17 @@ def main():
     W = load_powerlaw(torch, sp, dev, args.tune_cache)
     all_ks, bmin = powerlaw_kernels(sp, W, torch)
     # the step: the three FP64 products of the power-law workload
-    ks = [k for k in all_ks if k[0].endswith("_f64") and "_split" not in k[0]]
-    mixed = [k for k in all_ks if not k[0].endswith("_f64") and "_split" not in k[0]]
+    plain = [k for k in all_ks if "split" not in k[0]]
+    ks = [k for k in plain if k[0].endswith("_f64")]
+    mixed = [k for k in plain if not k[0].endswith("_f64")]
     split = [k for k in all_ks if "_split" in k[0]]
+    rsplit = [k for k in all_ks if "_rowsplit" in k[0]]
     if args.only:
         keep = set(args.only.split(","))
         ks = [k for k in all_ks if k[0] in keep]
         mixed = []
         split = []
+        rsplit = []
     ms_step, per = time_loop(torch, ks, args.steps, args.warmup)
     flops_step = 2.0 * W["nnz"] * len(ks)
     value = flops_step / (ms_step * 1e-3) / 1e9
@@ -569,6 +587,13 @@ def main():
                                           speedup_vs_unsplit=round(unsplit[name.replace("_split", "")] / per_s[name],
                                                                    3))
                                for name, _ in split}
+    if rsplit:
+        _, per_r = time_loop(torch, rsplit, max(10, args.steps // 2), 3)
+        unsplit = dict(per, **(per_m if mixed else {}))
+        out["row_split"] = {name: dict(entry(name, per_r[name]),
+                                       speedup_vs_unsplit=round(unsplit[name.replace("_rowsplit", "")] / per_r[name],
+                                                                3))
+                            for name, _ in rsplit}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)
     else:
@@ -584,7 +609,8 @@ def main():
         "kernels": {name: {"achieved_Ggathers_s": round(nnz / (ms * 1e-3) / 1e9, 1),
                            "frac_of_mall_rate": round(nnz / (ms * 1e-3) / 1e9 / rates["x_16MB_MALL_Ggathers_s"], 3),
                            "frac_of_l2_rate": round(nnz / (ms * 1e-3) / 1e9 / rates["x_2MB_L2_Ggathers_s"], 3)}
-                    for name, ms in dict(per, **(per_s if split else {})).items() if name.endswith("_f64")}}
+                    for name, ms in dict(per, **(per_s if split else {}), **(per_r if rsplit else {})).items()
+                    if name.endswith("_f64")}}
     print(json.dumps(out), flush=True)
     if args.suite:
         suite_lines(torch, sp, dev, W, args.steps, args.warmup)

@@ -346,6 +346,49 @@ spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *slot_ptr
                                    size_t ws_bytes, void *stream);
 
 /* ======================================================================== */
+/* Row-split products                                                        */
+/* ======================================================================== */
+/* The static row partition of the paper's shared-memory parallel SpMVM
+ * (Section 5: each thread owns one contiguous block of rows, its pages
+ * placed by first touch) with the MI355X's XCDs as the locality domains:
+ * part k = rows [h_bounds[k], h_bounds[k+1]), k < SPMV_SPLIT_PARTS, is
+ * stored in its own JDS or blocked-JDS form and processed on XCD k, so the
+ * x entries near its diagonal stay in that XCD's L2.  Rows are complete in
+ * their part: results go straight to y with the arithmetic of the unsplit
+ * calls (including the SPMV_WIDE_ROW_NNZ rule), no workspace, no combine.
+ *
+ * spmv_split_rows (setup, synchronises) chooses the bounds by entries:
+ * h_bounds[0] = 0, h_bounds[8] = n_rows and, for 0 < k < 8, h_bounds[k] is
+ * the first row i with row_ptr[i] >= ceil(k*nnz/8) (k*n_rows/8 when nnz == 0).
+ * h_entry_bounds[k] = row_ptr[h_bounds[k]].  row_ptr_parts[n_rows +
+ * SPMV_SPLIT_PARTS] receives part k's row pointer, rebased to 0, as
+ * h_bounds[k+1]-h_bounds[k]+1 entries at row_ptr_parts + h_bounds[k] + k, so
+ * part k is the CRS matrix (h_bounds[k+1]-h_bounds[k] rows, row_ptr_parts +
+ * h_bounds[k] + k, col_idx + h_entry_bounds[k], val + h_entry_bounds[k]).
+ * ws: spmv_split_rows_workspace_size() bytes. */
+size_t spmv_split_rows_workspace_size(void);
+spmv_status spmv_split_rows(int32_t n_rows, int64_t nnz, const int32_t *row_ptr, int32_t *row_ptr_parts,
+                            int64_t *h_bounds, int64_t *h_entry_bounds, void *ws, size_t ws_bytes, void *stream);
+/* JDS parts: part k is spmv_jds_from_csr of CRS part k (without SYMPERM);
+ * its perm holds row numbers local to the part, and permuted row r of part k
+ * writes y[h_bounds[k] + h_perm[k][r]].  Host arrays of SPMV_SPLIT_PARTS
+ * device pointers (h_perm, h_jd_ptr, h_jd_col, h_jd_val), of host pointers
+ * (h_jd_ptr_host) and of sizes (h_ndiag).  x is in the original basis. */
+spmv_status spmv_jds_row_split(int32_t n, const int64_t *h_bounds, const int32_t *const *h_perm,
+                               const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host,
+                               const int32_t *h_ndiag, const int32_t *const *h_jd_col, const void *const *h_jd_val,
+                               spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
+                               double beta, int32_t unroll, int32_t max_iters, void *stream);
+/* Blocked-JDS parts (slice height C for all parts), built from the JDS parts
+ * above. */
+spmv_status spmv_jds_blocked_row_split(int32_t n, int32_t C, const int64_t *h_bounds, const int32_t *const *h_perm,
+                                       const int64_t *const *h_slice_ptr, const int32_t *const *h_slice_nd,
+                                       const int32_t *const *h_slice_nd_host, const int32_t *const *h_bl_col,
+                                       const void *const *h_bl_val, spmv_dtype val_dt, const void *x, void *y,
+                                       spmv_dtype vec_dt, double alpha, double beta, int32_t rows_per_wave,
+                                       int32_t unroll, int32_t max_iters, void *stream);
+
+/* ======================================================================== */
 /* Many matrices in one launch                                               */
 /* ======================================================================== */
 /* Batched blocked-JDS SpMV: y_m = A_m x_m for m < n_mat, F32 values and

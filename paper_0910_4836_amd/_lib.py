@@ -78,6 +78,12 @@ SIGNATURES = {
                               _i32, _i32, _p, _sz, _p]),
     "spmv_jds_blocked_split": (_int, [_i32, _i32, _p, _i64p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, _int, _p, _p, _int,
                                       _f64, _f64, _i32, _i32, _i32, _p, _sz, _p]),
+    "spmv_split_rows_workspace_size": (_sz, []),
+    "spmv_split_rows": (_int, [_i32, _i64, _p, _p, _i64p, _i64p, _p, _sz, _p]),
+    "spmv_jds_row_split": (_int, [_i32, _i64p, _vpp, _vpp, _vpp, _i32p, _vpp, _vpp, _int, _p, _p, _int, _f64, _f64,
+                                  _i32, _i32, _p]),
+    "spmv_jds_blocked_row_split": (_int, [_i32, _i32, _i64p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, _int, _p, _p, _int,
+                                          _f64, _f64, _i32, _i32, _i32, _p]),
     "spmv_batched_plan": (_int, [_i32, _i32p, _i32p, _i64p, _i64p, _i64p, _i64p, _i32p, _i32, _p, _i64, _i64p,
                                  _p]),
     "spmv_batched": (_int, [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _p]),

@@ -559,6 +559,36 @@ __global__ void sojds_kernel(const int32_t *__restrict__ jp, int32_t ndiag, cons
     }
 }
 
+// ---- row split: part k = rows [b_k, b_{k+1}), cut so each holds about nnz/8 entries
+
+__global__ void row_bounds_kernel(const int32_t *__restrict__ rp, int32_t n_rows, int64_t nnz,
+                                  int64_t *__restrict__ bounds, int64_t *__restrict__ entry_bounds)
+{
+    const int k = (int)threadIdx.x;
+    if (k > SPLIT_PARTS) return;
+    int64_t b;
+    if (k == 0) b = 0;
+    else if (k == SPLIT_PARTS) b = n_rows;
+    else if (nnz == 0) b = (int64_t)k * n_rows / SPLIT_PARTS;
+    else b = lower_bound_dev(rp, (int64_t)n_rows + 1, (k * nnz + SPLIT_PARTS - 1) / SPLIT_PARTS);
+    if (b > n_rows) b = n_rows;     // only if row_ptr[n_rows] < nnz, which the host reports
+    bounds[k] = b;
+    entry_bounds[k] = rp[b];
+}
+
+// part k's rebased row pointer at row_ptr_parts[b_k + k .. b_{k+1} + k]
+__global__ void row_split_ptr_kernel(const int32_t *__restrict__ rp, int32_t n_rows,
+                                     const int64_t *__restrict__ bounds, int32_t *__restrict__ out)
+{
+    GRID_LOOP(j, (int64_t)n_rows + SPLIT_PARTS)
+    {
+        int k = 0;
+        while (k < SPLIT_PARTS - 1 && j > bounds[k + 1] + k) ++k;
+        const int64_t row = bounds[k] + (j - bounds[k] - k);
+        out[j] = rp[row] - rp[bounds[k]];
+    }
+}
+
 // ---- column split: part k = entries whose column lies in [k*width, (k+1)*width)
 
 __global__ void row_of_entries_kernel(const int32_t *__restrict__ rp, int32_t n, int64_t nnz, int32_t *__restrict__ rowid)
@@ -1144,6 +1174,32 @@ spmv_status spmv_split_columns(int32_t n_rows, int32_t n_cols, int64_t nnz, cons
     SPMV_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost, s));
     SPMV_HIP(hipMemcpyAsync(h_row_off, row_off, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost, s));
     SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+size_t spmv_split_rows_workspace_size(void) { return 2 * align_up(sizeof(int64_t) * (SPLIT_PARTS + 1), 256); }
+
+spmv_status spmv_split_rows(int32_t n_rows, int64_t nnz, const int32_t *row_ptr, int32_t *row_ptr_parts,
+                            int64_t *h_bounds, int64_t *h_entry_bounds, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && nnz >= 0, "spmv_split_rows: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_split_rows: nnz >= 2^31");
+    SPMV_REQUIRE(row_ptr && row_ptr_parts && h_bounds && h_entry_bounds, "spmv_split_rows: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_split_rows_workspace_size(), "spmv_split_rows: workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    int64_t *bounds = wc.take<int64_t>(SPLIT_PARTS + 1);
+    int64_t *entry_bounds = wc.take<int64_t>(SPLIT_PARTS + 1);
+    row_bounds_kernel<<<1, 64, 0, s>>>(row_ptr, n_rows, nnz, bounds, entry_bounds);
+    row_split_ptr_kernel<<<grid_for((int64_t)n_rows + SPLIT_PARTS), 256, 0, s>>>(row_ptr, n_rows, bounds,
+                                                                                 row_ptr_parts);
+    SPMV_CHECK_LAUNCH("spmv_split_rows");
+    SPMV_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipMemcpyAsync(h_entry_bounds, entry_bounds, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost,
+                            s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    if (h_entry_bounds[SPLIT_PARTS] != nnz)
+        return fail(SPMV_ERR_BAD_FORMAT, "spmv_split_rows: row_ptr[n_rows] != nnz");
     return SPMV_OK;
 }
 

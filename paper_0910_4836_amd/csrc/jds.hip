@@ -299,6 +299,20 @@ __global__ __launch_bounds__(JDS_THREADS) void jds_split_kernel(JdsSplitArgs S)
     jds_body<FMT, U, VT, XT, double, true>(S.a[k], P, wg, part);
 }
 
+// Row-split JDS / blocked JDS: part k (a contiguous block of rows with its own
+// JDS or blocked-JDS storage and local permutation) runs on XCD k; a[k].y
+// points at the part's first row of y, which receives complete results.
+template <int FMT, int U, typename VT, typename XT>
+__global__ __launch_bounds__(JDS_THREADS) void jds_rows_kernel(JdsSplitArgs S)
+{
+    __shared__ double part[JDS_WAVES][WAVE];
+    const int k = (int)(blockIdx.x % SPLIT_PARTS);
+    const int64_t wg = blockIdx.x / SPLIT_PARTS;
+    const JdsPlan &P = S.P[k];
+    if (P.ncls == 0 || wg >= P.c[P.ncls - 1].wg_end) return;
+    jds_body<FMT, U, VT, XT, XT>(S.a[k], P, wg, part);
+}
+
 // Multi-vector JDS: each lane owns one row (R = 64) and keeps k accumulators;
 // the row's entries are read once for all k columns of X.
 template <int KB, typename VT, typename XT>
@@ -505,6 +519,42 @@ static spmv_status launch_jds(const JdsArgs &a, const JdsPlan &P, int unroll, sp
 }
 
 static int unroll_ok(int32_t u) { return u == 0 || u == 2 || u == 4 || u == 8; }
+
+// Row bounds of the row-split parts: 0 = b_0 <= b_1 <= ... <= b_8 = n.
+static spmv_status row_bounds_ok(int32_t n, const int64_t *h_bounds, const char *who)
+{
+    if (!h_bounds) return fail(SPMV_ERR_INVALID_ARG, std::string(who) + ": null h_bounds");
+    if (h_bounds[0] != 0 || h_bounds[SPLIT_PARTS] != n)
+        return fail(SPMV_ERR_INVALID_ARG, std::string(who) + ": h_bounds must run from 0 to n");
+    for (int k = 0; k < SPLIT_PARTS; ++k)
+        if (h_bounds[k + 1] < h_bounds[k]) return fail(SPMV_ERR_INVALID_ARG, std::string(who) + ": h_bounds decrease");
+    return SPMV_OK;
+}
+
+template <int FMT>
+static spmv_status launch_rows(const JdsSplitArgs &S, int64_t max_wg, int32_t unroll, spmv_dtype val_dt,
+                               spmv_dtype vec_dt, hipStream_t s, const char *who)
+{
+    const unsigned grid = (unsigned)(max_wg * SPLIT_PARTS);
+    if (grid == 0) return SPMV_OK;
+    const int u = unroll ? unroll : 4;
+#define JROWS_CASE(VDT, VT, XDT, XT)                                                       \
+    if (val_dt == VDT && vec_dt == XDT) {                                                  \
+        if (u == 2) jds_rows_kernel<FMT, 2, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);       \
+        else if (u == 8) jds_rows_kernel<FMT, 8, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);  \
+        else jds_rows_kernel<FMT, 4, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);              \
+    } else
+    JROWS_CASE(SPMV_F64, double, SPMV_F64, double)
+    JROWS_CASE(SPMV_F32, float, SPMV_F64, double)
+    JROWS_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    JROWS_CASE(SPMV_F32, float, SPMV_F32, float)
+    JROWS_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    JROWS_CASE(SPMV_F64, double, SPMV_F32, float)
+    return fail(SPMV_ERR_UNSUPPORTED, std::string(who) + ": dtype combination");
+#undef JROWS_CASE
+    SPMV_CHECK_LAUNCH(who);
+    return SPMV_OK;
+}
 
 }  // namespace spmv
 
@@ -814,6 +864,100 @@ spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *slot_ptr
         SPMV_CHECK_LAUNCH("spmv_jds_blocked_split");
     }
     return launch_combine(n, slot_ptr, slots, y, vec_dt, alpha, beta, s);
+}
+
+spmv_status spmv_jds_row_split(int32_t n, const int64_t *h_bounds, const int32_t *const *h_perm,
+                               const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host,
+                               const int32_t *h_ndiag, const int32_t *const *h_jd_col, const void *const *h_jd_val,
+                               spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
+                               double beta, int32_t unroll, int32_t max_iters, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_jds_row_split: n < 0");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_row_split: bad dtype");
+    SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_row_split: bad unroll or max_iters");
+    spmv_status st = row_bounds_ok(n, h_bounds, "spmv_jds_row_split");
+    if (st != SPMV_OK) return st;
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(h_perm && h_jd_ptr && h_jd_ptr_host && h_ndiag && h_jd_col && h_jd_val && y,
+                 "spmv_jds_row_split: null pointer");
+    const size_t ysz = dtype_size(vec_dt);
+    JdsSplitArgs S{};
+    int64_t max_wg = 0;
+    for (int k = 0; k < SPLIT_PARTS; ++k) {
+        const int32_t nk = (int32_t)(h_bounds[k + 1] - h_bounds[k]);
+        if (nk == 0) continue;                 // S.P[k].ncls == 0: no workgroup of part k does anything
+        SPMV_REQUIRE(h_perm[k] && h_jd_ptr[k] && h_jd_ptr_host[k] && h_ndiag[k] >= 0,
+                     "spmv_jds_row_split: null part");
+        SPMV_REQUIRE(h_ndiag[k] == 0 || (h_jd_col[k] && h_jd_val[k] && x), "spmv_jds_row_split: null part arrays");
+        JdsArgs &a = S.a[k];
+        a.n = nk;
+        a.perm = h_perm[k];
+        a.jd_ptr = h_jd_ptr[k];
+        a.ndiag = h_ndiag[k];
+        a.C = 64;
+        a.col = h_jd_col[k];
+        a.val = h_jd_val[k];
+        a.x = x;
+        a.y = (char *)y + h_bounds[k] * ysz;
+        a.alpha = alpha;
+        a.beta = beta;
+        S.P[k] = plan_jds(nk, h_jd_ptr_host[k], h_ndiag[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1);
+        if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
+    }
+    return launch_rows<FMT_JDS>(S, max_wg, unroll, val_dt, vec_dt, as_stream(stream), "spmv_jds_row_split");
+}
+
+spmv_status spmv_jds_blocked_row_split(int32_t n, int32_t C, const int64_t *h_bounds, const int32_t *const *h_perm,
+                                       const int64_t *const *h_slice_ptr, const int32_t *const *h_slice_nd,
+                                       const int32_t *const *h_slice_nd_host, const int32_t *const *h_bl_col,
+                                       const void *const *h_bl_val, spmv_dtype val_dt, const void *x, void *y,
+                                       spmv_dtype vec_dt, double alpha, double beta, int32_t rows_per_wave,
+                                       int32_t unroll, int32_t max_iters, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_jds_blocked_row_split: n < 0");
+    SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_row_split: C must be a positive multiple of 64");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_blocked_row_split: bad dtype");
+    SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_blocked_row_split: bad unroll or max_iters");
+    SPMV_REQUIRE(rows_per_wave == 0 || rows_per_wave == 8 || rows_per_wave == 16 || rows_per_wave == 32 ||
+                     rows_per_wave == 64,
+                 "spmv_jds_blocked_row_split: rows_per_wave must be 0, 8, 16, 32 or 64");
+    spmv_status st = row_bounds_ok(n, h_bounds, "spmv_jds_blocked_row_split");
+    if (st != SPMV_OK) return st;
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(h_perm && h_slice_ptr && h_slice_nd && h_slice_nd_host && h_bl_col && h_bl_val && y,
+                 "spmv_jds_blocked_row_split: null pointer");
+    int forced = -1;
+    if (rows_per_wave) {
+        forced = 0;
+        while ((1 << forced) < rows_per_wave) ++forced;
+    }
+    const size_t ysz = dtype_size(vec_dt);
+    JdsSplitArgs S{};
+    int64_t max_wg = 0;
+    for (int k = 0; k < SPLIT_PARTS; ++k) {
+        const int32_t nk = (int32_t)(h_bounds[k + 1] - h_bounds[k]);
+        if (nk == 0) continue;                 // S.P[k].ncls == 0: no workgroup of part k does anything
+        SPMV_REQUIRE(h_perm[k] && h_slice_ptr[k] && h_slice_nd[k] && h_slice_nd_host[k],
+                     "spmv_jds_blocked_row_split: null part");
+        SPMV_REQUIRE(h_slice_nd_host[k][0] == 0 || (h_bl_col[k] && h_bl_val[k] && x),
+                     "spmv_jds_blocked_row_split: null part arrays");
+        JdsArgs &a = S.a[k];
+        a.n = nk;
+        a.perm = h_perm[k];
+        a.C = C;
+        a.slice_ptr = h_slice_ptr[k];
+        a.slice_nd = h_slice_nd[k];
+        a.col = h_bl_col[k];
+        a.val = h_bl_val[k];
+        a.x = x;
+        a.y = (char *)y + h_bounds[k] * ysz;
+        a.alpha = alpha;
+        a.beta = beta;
+        S.P[k] = plan_blocked(nk, C, h_slice_nd_host[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced);
+        if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
+    }
+    return launch_rows<FMT_BLOCKED>(S, max_wg, unroll, val_dt, vec_dt, as_stream(stream),
+                                    "spmv_jds_blocked_row_split");
 }
 
 }  // extern "C"

@@ -571,6 +571,106 @@ def spmv_jds_blocked_split(S: Split, x, y=None, alpha=1.0, beta=0.0, C_=64, rows
     return y
 
 
+# --------------------------------------------------------------------------- row-split forms
+
+
+class RowSplit:
+    """A matrix cut into SPLIT_PARTS contiguous row blocks of about nnz/8
+    entries each (spmv_split_rows); part k is an ordinary CRS matrix (views of
+    the original column and value arrays) and gets JDS / blocked-JDS forms on
+    demand, with permutations local to the part."""
+
+    def __init__(self, A: CSR):
+        lib = _lib.load()
+        P = _lib.SPLIT_PARTS
+        dev = A.device
+        self.n, self.n_cols = A.n_rows, A.n_cols
+        ws = _ws(lib.spmv_split_rows_workspace_size(), dev)
+        self.row_ptr_parts = torch.empty(A.n_rows + P, dtype=_I32, device=dev)
+        self.bounds = np.zeros(P + 1, dtype=np.int64)
+        self.entry_bounds = np.zeros(P + 1, dtype=np.int64)
+        call("spmv_split_rows", A.n_rows, A.nnz, _p(A.row_ptr), _p(self.row_ptr_parts), _h_i64(self.bounds),
+             _h_i64(self.entry_bounds), _p(ws), ws.numel(), _stream())
+        self.A = A
+        self.parts = [self.part_csr(k) for k in range(P)]
+        self.jds = None
+        self.blocked = {}
+
+    def part_rows(self, k: int) -> int:
+        return int(self.bounds[k + 1] - self.bounds[k])
+
+    def part_csr(self, k: int) -> CSR:
+        nk, r0 = self.part_rows(k), int(self.bounds[k])
+        a, b = int(self.entry_bounds[k]), int(self.entry_bounds[k + 1])
+        return CSR(nk, self.n_cols, self.row_ptr_parts[r0 + k:r0 + k + nk + 1], self.A.col_idx[a:b],
+                   self.A.val[a:b])
+
+    def jds_parts(self):
+        if self.jds is None:
+            self.jds = [jds_from_csr(Ak) for Ak in self.parts]
+        return self.jds
+
+    def blocked_parts(self, C_: int = 64):
+        if C_ not in self.blocked:
+            self.blocked[C_] = [jds_blocked_from_jds(J, C_) for J in self.jds_parts()]
+        return self.blocked[C_]
+
+    def with_values(self, dtype: torch.dtype) -> "RowSplit":
+        """Same structure with the values rounded (or widened) to ``dtype``."""
+        R = RowSplit.__new__(RowSplit)
+        R.__dict__.update(self.__dict__)
+        R.A = self.A.with_values(spmv_convert_values(self.A.val, dtype))
+        R.parts = [R.part_csr(k) for k in range(_lib.SPLIT_PARTS)]
+        R.jds = [J.with_values(spmv_convert_values(J.jd_val, dtype)) for J in self.jds_parts()]
+        R.blocked = {C_: [B.with_values(spmv_convert_values(B.bl_val, dtype)) for B in Bs]
+                     for C_, Bs in self.blocked.items()}
+        R._jds_args = None
+        R._blocked_args = {}
+        return R
+
+
+def _jds_row_split_args(R: RowSplit):
+    if getattr(R, "_jds_args", None) is None:
+        Js = R.jds_parts()
+        hptr = (C.c_void_p * len(Js))(*[J.h_jd_ptr.ctypes.data for J in Js])
+        ndiag = np.array([J.ndiag for J in Js], dtype=np.int32)
+        R._jds_args = (Js, _ptr_array([J.perm for J in Js]), _ptr_array([J.jd_ptr for J in Js]), hptr, ndiag,
+                       _ptr_array([J.jd_col for J in Js]), _ptr_array([J.jd_val for J in Js]))
+    return R._jds_args
+
+
+def spmv_jds_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0):
+    Js, perm, jp, hptr, ndiag, col, val = _jds_row_split_args(R)
+    _check_dev(x)
+    y = _out_vec(y, R.n, x, beta)
+    call("spmv_jds_row_split", R.n, _h_i64(R.bounds), perm, jp, hptr, _h_i32(ndiag), col, val,
+         dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll,
+         max_iters, _stream())
+    return y
+
+
+def _blocked_row_split_args(R: RowSplit, C_: int):
+    cache = R.__dict__.setdefault("_blocked_args", {})
+    if C_ not in cache:
+        Bs = R.blocked_parts(C_)
+        hnd = (C.c_void_p * len(Bs))(*[B.h_slice_nd.ctypes.data for B in Bs])
+        cache[C_] = (Bs, _ptr_array([B.perm for B in Bs]), _ptr_array([B.slice_ptr for B in Bs]),
+                     _ptr_array([B.slice_nd for B in Bs]), hnd, _ptr_array([B.bl_col for B in Bs]),
+                     _ptr_array([B.bl_val for B in Bs]))
+    return cache[C_]
+
+
+def spmv_jds_blocked_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, C_=64, rows_per_wave=0, unroll=0,
+                               max_iters=0):
+    Bs, perm, sptr, snd, hnd, col, val = _blocked_row_split_args(R, C_)
+    _check_dev(x)
+    y = _out_vec(y, R.n, x, beta)
+    call("spmv_jds_blocked_row_split", R.n, C_, _h_i64(R.bounds), perm, sptr, snd, hnd, col, val,
+         dtype_code(Bs[0].bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave,
+         unroll, max_iters, _stream())
+    return y
+
+
 # --------------------------------------------------------------------------- many matrices
 
 

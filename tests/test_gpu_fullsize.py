@@ -82,11 +82,14 @@ def test_powerlaw_every_form_sampled(powerlaw):
     ju, jm = tuner.tune_jds(J, xd)
     bC, bR, bU = tuner.tune_blocked(J, xd)
     Bt = sp.jds_blocked_from_jds(J, bC)
+    RS = sp.RowSplit(A)
     forms = {"crs": lambda: sp.spmv_crs(A, xd), "jds": lambda: sp.spmv_jds(J, xd),
              "blocked": lambda: sp.spmv_jds_blocked(B, xd), "crs_split": lambda: sp.spmv_crs_split(S, xd),
              "jds_split": lambda: sp.spmv_jds_split(S, xd), "blocked_split": lambda: sp.spmv_jds_blocked_split(S, xd),
              "jds_tuned": lambda: sp.spmv_jds(J, xd, unroll=ju, max_iters=jm),
-             "blocked_tuned": lambda: sp.spmv_jds_blocked(Bt, xd, rows_per_wave=bR, unroll=bU)}
+             "blocked_tuned": lambda: sp.spmv_jds_blocked(Bt, xd, rows_per_wave=bR, unroll=bU),
+             "jds_row_split": lambda: sp.spmv_jds_row_split(RS, xd, unroll=ju, max_iters=jm),
+             "blocked_row_split": lambda: sp.spmv_jds_blocked_row_split(RS, xd, C_=bC, rows_per_wave=bR, unroll=bU)}
     for name, fn in forms.items():
         got = to_np(fn())[rows]
         e = oracle.rel_err(got, want, D).max()
@@ -102,6 +105,10 @@ def test_powerlaw_every_form_sampled(powerlaw):
     assert B.padded >= nnz
     # slots: one per (row, part) pair present
     assert S.n_slots == int(to_np(S.slot_ptr)[-1]) and S.n_slots <= min(nnz, 8 * n)
+    # row parts: contiguous, each within one row of nnz/8 entries
+    eb = RS.entry_bounds
+    assert eb[0] == 0 and eb[-1] == nnz and np.all(np.diff(RS.bounds) >= 0)
+    assert np.all(np.abs(eb[1:-1] - np.arange(1, 8) * nnz / 8) <= L.max())
 
 
 def test_powerlaw_fp32_values_sampled(powerlaw):

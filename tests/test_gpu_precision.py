@@ -46,7 +46,10 @@ def kernels(A, vt):
     J = sp.jds_from_csr(A)
     B = sp.jds_blocked_from_jds(J, 64)
     S = sp.Split(A)
+    RS = sp.RowSplit(A)
     return {
+        "jds_row_split": lambda x: sp.spmv_jds_row_split(RS, x),
+        "blocked_row_split": lambda x: sp.spmv_jds_blocked_row_split(RS, x, rows_per_wave=16),
         "crs_split": lambda x: sp.spmv_crs_split(S, x),
         "jds_split": lambda x: sp.spmv_jds_split(S, x),
         "blocked_split": lambda x: sp.spmv_jds_blocked_split(S, x),

@@ -28,6 +28,10 @@ def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_
         yield "crs_split", lambda x, y, a, b: sp.spmv_crs_split(S, x, y, a, b)
         yield "jds_split", lambda x, y, a, b: sp.spmv_jds_split(S, x, y, a, b)
         yield "blocked_split", lambda x, y, a, b: sp.spmv_jds_blocked_split(S, x, y, a, b, C_=Cs[-1])
+        RS = sp.RowSplit(A)
+        yield "jds_row_split", lambda x, y, a, b: sp.spmv_jds_row_split(RS, x, y, a, b, max_iters=max_iters[-1])
+        yield "blocked_row_split", lambda x, y, a, b: sp.spmv_jds_blocked_row_split(
+            RS, x, y, a, b, C_=Cs[-1], rows_per_wave=rows_per_wave[-1], max_iters=max_iters[-1])
     J = sp.jds_from_csr(A, symperm=symperm)
     for u in unrolls:
         for mi in max_iters:
@@ -219,6 +223,73 @@ def test_split_narrow_and_empty_parts(n_cols):
     run_case(r, c, v, nr, nc, rng.uniform(-1, 1, nc), Cs=(64,))
     y0 = rng.uniform(-1, 1, nr)
     run_case(r, c, v, nr, nc, rng.uniform(-1, 1, nc), y0, alpha=0.5, beta=-2.0)
+
+
+@pytest.mark.parametrize("case", ["random", "few_rows", "one_heavy_row", "no_entries"])
+def test_row_split_structure(case):
+    """Part k is rows [b_k, b_k+1) with b_k the first row whose row pointer
+    reaches ceil(k*nnz/8) (k*n/8 without entries); its row pointer is the
+    original one rebased to 0 and its entries are the original arrays from
+    row_ptr[b_k] on."""
+    rng = np.random.default_rng(62)
+    if case == "random":
+        r, c, v, nr, nc, _ = rand_coo(62, 5000, 4000, 0.003, empty_rows=0.2, long_rows=5, long_len=2000)
+    elif case == "few_rows":                           # fewer rows than parts
+        nr, nc = 3, 50
+        r = np.repeat(np.arange(nr, dtype=np.int32), [7, 0, 20])
+        c = np.concatenate([rng.choice(nc, 7, replace=False), rng.choice(nc, 20, replace=False)]).astype(np.int32)
+        v = rng.standard_normal(len(r))
+    elif case == "one_heavy_row":                      # one row holds almost every entry
+        nr, nc = 1000, 3000
+        lens = np.ones(nr, np.int64)
+        lens[500] = 2900
+        r = np.repeat(np.arange(nr, dtype=np.int32), lens)
+        c = np.concatenate([rng.choice(nc, L, replace=False) for L in lens]).astype(np.int32)
+        v = rng.standard_normal(len(r))
+    else:
+        nr, nc = 37, 10
+        r = c = np.zeros(0, np.int32)
+        v = np.zeros(0)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    RS = sp.RowSplit(gpu_csr(sp, r, c, v, nr, nc))
+    nnz = R.nnz
+    want_b = [0] + [int(np.searchsorted(R.row_ptr, -(-k * nnz // 8), side="left")) if nnz else k * nr // 8
+                    for k in range(1, 8)] + [nr]
+    assert RS.bounds.tolist() == want_b
+    assert RS.entry_bounds.tolist() == [int(R.row_ptr[b]) for b in want_b]
+    for k in range(8):
+        a, b = want_b[k], want_b[k + 1]
+        Pk = RS.parts[k]
+        assert Pk.n_rows == b - a
+        assert np.array_equal(to_np(Pk.row_ptr), R.row_ptr[a:b + 1] - R.row_ptr[a])
+        e0, e1 = R.row_ptr[a], R.row_ptr[b]
+        assert np.array_equal(to_np(Pk.col_idx), R.col[e0:e1])
+        assert np.array_equal(to_np(Pk.val), R.val[e0:e1])
+    # products through every part, including the empty ones
+    x = rng.uniform(-1, 1, nc)
+    y0 = rng.uniform(-1, 1, nr)
+    want = oracle.spmv_crs(R, x, y0, 0.5, -1.5)
+    D = 0.5 * oracle.row_absdot(R, x) + 1.5 * np.abs(y0)
+    for C_ in (64, 128):
+        got = sp.spmv_jds_blocked_row_split(RS, to_dev(x), to_dev(y0.copy()), 0.5, -1.5, C_=C_)
+        assert max_err(got, want, D) <= FP64_TOL
+    got = sp.spmv_jds_row_split(RS, to_dev(x), to_dev(y0.copy()), 0.5, -1.5)
+    assert max_err(got, want, D) <= FP64_TOL
+
+
+def test_row_split_rejects_bad_bounds():
+    r, c, v, nr, nc, rng = rand_coo(63, 200, 200, 0.02)
+    RS = sp.RowSplit(gpu_csr(sp, r, c, v, nr, nc))
+    x = to_dev(rng.uniform(-1, 1, nc))
+    RS.jds_parts()
+    good = RS.bounds.copy()
+    for bad in ([0, 10, 5, 30, 40, 50, 60, 70, nr], [1] + good[1:].tolist(), good[:-1].tolist() + [nr - 1]):
+        RS.bounds = np.array(bad, dtype=np.int64)
+        with pytest.raises(sp.SpmvError):
+            sp.spmv_jds_row_split(RS, x)
+        with pytest.raises(sp.SpmvError):
+            sp.spmv_jds_blocked_row_split(RS, x)
+    RS.bounds = good
 
 
 def test_deterministic_repeat():
