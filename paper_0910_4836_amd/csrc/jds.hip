@@ -83,9 +83,66 @@ __device__ __forceinline__ int32_t jds_row_len(const int32_t *__restrict__ jp, i
     return lo;
 }
 
-// Partial sum of one lane over its diagonals in [dA, dB): d = base + kk + G*u.
+// JDS storage: partial sum of one lane over its diagonals in [dA, dB), d =
+// base + kk + G*u.  The U diagonal offsets of a trip are fetched first, all
+// at once (clamped to the last diagonal of the range, so every fetch is in
+// bounds), and only then the entries and the x elements: no load waits on
+// another inside a trip except the gathers on their column.  UNI (G == 1,
+// one lane per row): every lane walks the same diagonals, so base, the
+// offsets and the stop test are wave-uniform and use scalar loads.
 // `bounded` false: stop as soon as the group's first row has no diagonal
 // (used by unsplit groups, which then never search for their length).
+template <bool UNI, int U, bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ typename Acc<WIDE>::T jds_diag_sum(const JdsArgs &a, int32_t row0, int32_t r,
+                                                              bool row_ok, int kk, int G, int32_t dA,
+                                                              int32_t dB, bool bounded, int64_t xoff)
+{
+    typedef typename Acc<WIDE>::T acc_t;
+    const VT *__restrict__ val = (const VT *)a.val;
+    const XT *__restrict__ x = (const XT *)a.x + xoff;
+    const int32_t *__restrict__ col = a.col;
+    const int32_t *__restrict__ jp = a.jd_ptr;
+    if (UNI) {
+        dA = __builtin_amdgcn_readfirstlane(dA);
+        dB = __builtin_amdgcn_readfirstlane(dB);
+        row0 = __builtin_amdgcn_readfirstlane(row0);
+        kk = 0;
+        G = 1;
+    }
+    acc_t s = 0;
+    for (int32_t base = dA; base < dB; base += G * U) {
+        if (!bounded && jp[base + 1] - jp[base] <= row0) break;
+        int32_t off[U], len[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int32_t dd = base + kk + u * G;
+            dd = dd < dB ? dd : dB - 1;
+            off[u] = jp[dd];
+            len[u] = jp[dd + 1] - off[u];
+        }
+        int32_t c[U];
+        VT v[U];
+        bool act[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            act[u] = row_ok && base + kk + u * G < dB && r < len[u];
+            if (act[u]) {
+                c[u] = ld_stream(col + off[u] + r);
+                v[u] = ld_stream(val + off[u] + r);
+            }
+        }
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (act[u]) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (act[u]) s = Acc<WIDE>::mac(s, v[u], xv[u]);
+    }
+    return s;
+}
+
+// Partial sum of one lane over its diagonals in [dA, dB): d = base + kk + G*u.
 template <int FMT, int U, bool WIDE, typename VT, typename XT>
 __device__ __forceinline__ typename Acc<WIDE>::T jds_lane_sum(const JdsArgs &a, int32_t row0, int32_t r,
                                                               bool row_ok, int kk, int G, int32_t dA,
@@ -97,33 +154,8 @@ __device__ __forceinline__ typename Acc<WIDE>::T jds_lane_sum(const JdsArgs &a, 
     const int32_t *__restrict__ col = a.col;
     acc_t s = 0;
     if (FMT == FMT_JDS) {
-        const int32_t *__restrict__ jp = a.jd_ptr;
-        for (int32_t base = dA; base < dB; base += G * U) {
-            if (!bounded && jp[base + 1] - jp[base] <= row0) break;
-            int32_t c[U];
-            VT v[U];
-            bool act[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t dd = base + kk + u * G;
-                act[u] = false;
-                if (row_ok && dd < dB) {
-                    const int32_t off = jp[dd];
-                    if (r < jp[dd + 1] - off) {
-                        act[u] = true;
-                        c[u] = ld_stream(col + off + r);
-                        v[u] = ld_stream(val + off + r);
-                    }
-                }
-            }
-            XT xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (act[u]) xv[u] = x[c[u]];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (act[u]) s = Acc<WIDE>::mac(s, v[u], xv[u]);
-        }
+        if (G == 1) return jds_diag_sum<true, U, WIDE, VT, XT>(a, row0, r, row_ok, kk, G, dA, dB, bounded, xoff);
+        return jds_diag_sum<false, U, WIDE, VT, XT>(a, row0, r, row_ok, kk, G, dA, dB, bounded, xoff);
     } else {
         const int32_t sl = row0 / a.C;
         const int64_t sp = a.slice_ptr[sl];
@@ -354,43 +386,58 @@ __global__ __launch_bounds__(256) void spmm_jds_kernel(JdsArgs a)
 // beta*dval[e], computed in FP64 and rounded once.  Same wavefront layout as
 // the product (each lane walks its row's diagonals; writes of consecutive lanes
 // are consecutive), with no reduction: every entry is its own output.
-template <int U, typename T>
-__global__ __launch_bounds__(JDS_THREADS) void jds_grad_kernel(JdsArgs a, JdsPlan P)
+template <bool UNI, int U, typename T>
+__device__ __forceinline__ void jds_grad_lane(const JdsArgs &a, const WaveTask &t)
 {
-    const WaveTask t = wave_task<FMT_JDS>(a, P, false, blockIdx.x);
-    if (!t.row_ok) return;
     const int32_t *__restrict__ jp = a.jd_ptr;
     const int32_t *__restrict__ col = a.col;
     const T *__restrict__ x = (const T *)a.x;
     T *__restrict__ dval = (T *)a.dval;
     const int32_t row = a.symperm ? t.r : a.perm[t.r];
     const double gv = a.alpha * to_f64(((const T *)a.g)[row]);
-    for (int32_t base = t.dA; base < t.dB; base += t.G * U) {
-        if (!t.bounded && jp[base + 1] - jp[base] <= t.row0) break;
+    int32_t dA = t.dA, dB = t.dB, row0 = t.row0, kk = t.kk, G = t.G;
+    if (UNI) {                                 // see jds_diag_sum
+        dA = __builtin_amdgcn_readfirstlane(dA);
+        dB = __builtin_amdgcn_readfirstlane(dB);
+        row0 = __builtin_amdgcn_readfirstlane(row0);
+        kk = 0;
+        G = 1;
+    }
+    for (int32_t base = dA; base < dB; base += G * U) {
+        if (!t.bounded && jp[base + 1] - jp[base] <= row0) break;
+        int32_t off[U], len[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int32_t dd = base + kk + u * G;
+            dd = dd < dB ? dd : dB - 1;
+            off[u] = jp[dd];
+            len[u] = jp[dd + 1] - off[u];
+        }
         int32_t c[U];
-        int64_t e[U];
         bool act[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t dd = base + t.kk + u * t.G;
-            act[u] = false;
-            if (dd < t.dB) {
-                const int32_t off = jp[dd];
-                if (t.r < jp[dd + 1] - off) {
-                    act[u] = true;
-                    e[u] = (int64_t)off + t.r;
-                    c[u] = ld_stream(col + e[u]);
-                }
-            }
+            act[u] = base + kk + u * G < dB && t.r < len[u];
+            if (act[u]) c[u] = ld_stream(col + off[u] + t.r);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!act[u]) continue;
+            const int64_t e = (int64_t)off[u] + t.r;
             double v = gv * to_f64(x[c[u]]);
-            if (a.beta != 0.0) v = fma(a.beta, to_f64(dval[e[u]]), v);
-            store_from_f64(&dval[e[u]], v);
+            if (a.beta != 0.0) v = fma(a.beta, to_f64(dval[e]), v);
+            store_from_f64(&dval[e], v);
         }
     }
+}
+
+template <int U, typename T>
+__global__ __launch_bounds__(JDS_THREADS) void jds_grad_kernel(JdsArgs a, JdsPlan P)
+{
+    const WaveTask t = wave_task<FMT_JDS>(a, P, false, blockIdx.x);
+    if (!t.row_ok) return;
+    if (t.G == 1) jds_grad_lane<true, U, T>(a, t);
+    else jds_grad_lane<false, U, T>(a, t);
 }
 
 // ---------------------------------------------------------------- host planning
