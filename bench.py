@@ -205,8 +205,9 @@ def load_powerlaw(torch, sp, dev, tune_cache=""):
     # (fresh cache, so nothing is carried over from another machine)
     from paper_0910_4836_amd import autotune
     tuner = autotune.Autotuner(cache_path=tune_cache or os.path.join(tempfile.mkdtemp(), "autotune.json"))
-    jds_u, jds_mi = timed("autotune_jds_ms", lambda: tuner.tune_jds(J, xd))
-    bC, bR, bU = timed("autotune_blocked_ms", lambda: tuner.tune_blocked(J, xd))
+    crs_bn = timed("autotune_crs_ms", lambda: autotune.tune_crs(tuner, A, xd, J.ndiag))
+    jds_u, jds_mi, jds_w = timed("autotune_jds_ms", lambda: tuner.tune_jds(J, xd))
+    bC, bR, bU, bW = timed("autotune_blocked_ms", lambda: tuner.tune_blocked(J, xd))
     B = timed("jds_blocked_from_jds_ms", lambda: sp.jds_blocked_from_jds(J, bC))
     A32 = A.with_values(sp.spmv_convert_values(A.val, torch.float32))
     J32 = J.with_values(sp.spmv_convert_values(J.jd_val, torch.float32))
@@ -218,8 +219,8 @@ def load_powerlaw(torch, sp, dev, tune_cache=""):
     timed("row_split_jds_parts_ms", lambda: RS.jds_parts())
     timed("row_split_blocked_parts_ms", lambda: RS.blocked_parts(bC))
     host = (r, c, v, n, x)
-    tune = {"jds_unroll": jds_u, "jds_max_iters": jds_mi, "blocked_C": bC, "blocked_rows_per_wave": bR,
-            "blocked_unroll": bU}
+    tune = {"crs_block_nnz": crs_bn, "jds_unroll": jds_u, "jds_max_iters": jds_mi, "jds_wg_waves": jds_w,
+            "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW}
     return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, S=S, RS=RS, x=xd, n=n, nnz=A.nnz, setup=setup, gen_s=gen_s,
                 host=host, tune=tune)
 
@@ -230,14 +231,15 @@ def powerlaw_kernels(sp, W, torch):
     x = W["x"]
     J, B = W["J"], W["B"]
     T = W["tune"]
-    ju, jm, bR, bU = T["jds_unroll"], T["jds_max_iters"], T["blocked_rows_per_wave"], T["blocked_unroll"]
+    ju, jm, jw = T["jds_unroll"], T["jds_max_iters"], T["jds_wg_waves"]
+    bR, bU, bW = T["blocked_rows_per_wave"], T["blocked_unroll"], T["blocked_wg_waves"]
     ks = [
         ("crs_f64", lambda: sp.spmv_crs(W["A"], x, y)),
-        ("jds_f64", lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm)),
-        ("blocked_f64", lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU)),
+        ("jds_f64", lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
+        ("blocked_f64", lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW)),
         ("crs_f32val", lambda: sp.spmv_crs(W["A32"], x, y)),
-        ("jds_f32val", lambda: sp.spmv_jds(W["J32"], x, y, unroll=ju, max_iters=jm)),
-        ("blocked_f32val", lambda: sp.spmv_jds_blocked(W["B32"], x, y, rows_per_wave=bR, unroll=bU)),
+        ("jds_f32val", lambda: sp.spmv_jds(W["J32"], x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
+        ("blocked_f32val", lambda: sp.spmv_jds_blocked(W["B32"], x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW)),
     ]
     S = W["S"]
     S32 = W.setdefault("S32", S.with_values(sp.spmv_convert_values(S.val, torch.float32)))
@@ -252,12 +254,12 @@ def powerlaw_kernels(sp, W, torch):
     RS, bC = W["RS"], T["blocked_C"]
     RS32 = W.setdefault("RS32", RS.with_values(torch.float32))
     ks += [
-        ("jds_rowsplit_f64", lambda: sp.spmv_jds_row_split(RS, x, y, unroll=ju, max_iters=jm)),
+        ("jds_rowsplit_f64", lambda: sp.spmv_jds_row_split(RS, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
         ("blocked_rowsplit_f64", lambda: sp.spmv_jds_blocked_row_split(RS, x, y, C_=bC, rows_per_wave=bR,
-                                                                         unroll=bU)),
-        ("jds_rowsplit_f32val", lambda: sp.spmv_jds_row_split(RS32, x, y, unroll=ju, max_iters=jm)),
+                                                                         unroll=bU, wg_waves=bW)),
+        ("jds_rowsplit_f32val", lambda: sp.spmv_jds_row_split(RS32, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
         ("blocked_rowsplit_f32val", lambda: sp.spmv_jds_blocked_row_split(RS32, x, y, C_=bC, rows_per_wave=bR,
-                                                                            unroll=bU)),
+                                                                            unroll=bU, wg_waves=bW)),
     ]
     bmin = {
         "crs_f64": bytes_crs(nnz, n, n, 8, 8),
@@ -392,23 +394,24 @@ def suite_symdiag(torch, sp, dev, steps):
     x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(3, 1))).to(dev)
     from paper_0910_4836_amd import autotune
     tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
-    ju, jm = tuner.tune_jds(J, x)
-    bC, bR, bU = tuner.tune_blocked(J, x)
+    ju, jm, jw = tuner.tune_jds(J, x)
+    bC, bR, bU, bW = tuner.tune_blocked(J, x)
     B = sp.jds_blocked_from_jds(J, bC)
     nnz = A.nnz
     y_ref = sp.spmv_crs(A, x)
     out = {"workload": f"symmetric 12 secondary diagonals + diagonal, n={n}, nnz={nnz}", "kernels": {},
            "max_rel_err_vs_fp64": {},
-           "autotuned": {"jds_unroll": ju, "jds_max_iters": jm, "blocked_C": bC, "blocked_rows_per_wave": bR,
-                         "blocked_unroll": bU}}
+           "autotuned": {"jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw, "blocked_C": bC,
+                         "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW}}
     y = torch.empty(n, dtype=torch.float64, device=dev)
     for vdt, sv, tag in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32val"), (torch.bfloat16, 2, "bf16val")):
         Aq = A if vdt == torch.float64 else A.with_values(sp.spmv_convert_values(A.val, vdt))
         Jq = J if vdt == torch.float64 else J.with_values(sp.spmv_convert_values(J.jd_val, vdt))
         Bq = B if vdt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
         ks = [(f"crs_{tag}", lambda Aq=Aq: sp.spmv_crs(Aq, x, y)),
-              (f"jds_{tag}", lambda Jq=Jq: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm)),
-              (f"blocked_{tag}", lambda Bq=Bq: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU))]
+              (f"jds_{tag}", lambda Jq=Jq: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
+              (f"blocked_{tag}", lambda Bq=Bq: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU,
+                                                                    wg_waves=bW))]
         _, per = time_loop(torch, ks, max(10, steps // 4), 3)
         bm = {ks[0][0]: bytes_crs(nnz, n, n, sv, 8), ks[1][0]: bytes_jds(nnz, n, n, J.ndiag, sv, 8),
               ks[2][0]: bytes_blocked(nnz, n, n, B.n_slices, sv, 8)}
@@ -425,9 +428,13 @@ def suite_symdiag(torch, sp, dev, steps):
 def suite_spmm(torch, sp, dev, W, steps):
     n, nnz = W["n"], W["nnz"]
     out = {"workload": f"power-law n={n} nnz={nnz} times k vectors (column-major X, Y)", "kernels": {}}
+    # the multi-vector kernels use the default CRS plan (not the single-vector tuning)
+    A0 = W["A"]
+    mats = {dt: sp.spmv_crs_plan(sp.CSR(A0.n_rows, A0.n_cols, A0.row_ptr, A0.col_idx, W[key].val))
+            for dt, key in ((torch.float64, "A"), (torch.float32, "A32"))}
     for k in (8, 32):
         for dt, sv, tag in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32")):
-            A = W["A"] if dt == torch.float64 else W["A32"]
+            A = mats[dt]
             J = W["J"] if dt == torch.float64 else W["J32"]
             X = sp.colmajor(n, k, dt, dev)
             X.copy_(torch.rand(n, k, dtype=dt, device=dev) * 2 - 1)

@@ -197,25 +197,29 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
  * lane owns one permuted row and walks the jagged diagonals that reach it,
  * `unroll` diagonals at a time (2, 4 or 8; 0 = default).  Rows whose length
  * exceeds `max_iters` diagonals (0 = default) have their diagonals split over
- * up to 16 wavefronts whose partial sums are added in a fixed order.
+ * up to wg_waves wavefronts whose partial sums are added in a fixed order.
+ * wg_waves: wavefronts per workgroup, 4, 8 or 16 (0 = 16); a launch-shape
+ * choice only (small workgroups keep more gathers in flight for short,
+ * irregular rows; large ones stream uniform rows better).
  * Without SPMV_SYMPERM, x is in the original basis and y[perm[r]] receives
  * row r; with it, x and y are both in the permuted basis.
  * h_jd_ptr: host copy of jd_ptr (ndiag+1 entries). */
 spmv_status spmv_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr,
                      int32_t ndiag, const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt,
                      const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
-                     int32_t unroll, int32_t max_iters, unsigned flags, void *stream);
+                     int32_t unroll, int32_t max_iters, int32_t wg_waves, unsigned flags, void *stream);
 
 /* Blocked JDS kernel (RBJDS / SOJDS storage): same result as spmv_jds.
  * rows_per_wave R in {8, 16, 32, 64} (0 = 64): a wavefront covers R rows of a
- * slice with 64/R lanes per row striding over the diagonals.
+ * slice with 64/R lanes per row striding over the diagonals.  unroll,
+ * max_iters and wg_waves as for spmv_jds.
  * h_slice_nd: host copy of slice_nd (non-increasing, as built). */
 spmv_status spmv_jds_blocked(int32_t n, const int32_t *perm, int32_t C, int32_t n_slices,
                              const int64_t *slice_ptr, const int32_t *slice_nd,
                              const int32_t *h_slice_nd, const int32_t *bl_col, const void *bl_val,
                              spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
                              double beta, int32_t rows_per_wave, int32_t unroll, int32_t max_iters,
-                             unsigned flags, void *stream);
+                             int32_t wg_waves, unsigned flags, void *stream);
 
 /* Vector basis change: inverse == 0: out[r] = in[perm[r]] (to the permuted
  * basis); inverse != 0: out[perm[r]] = in[r].  dt F64 or F32. */
@@ -334,7 +338,7 @@ spmv_status spmv_jds_split(int32_t n, const int32_t *slot_ptr, const int64_t *h_
                            const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag,
                            const int32_t *const *h_jd_col, const void *const *h_jd_val, spmv_dtype val_dt,
                            const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, int32_t unroll,
-                           int32_t max_iters, void *ws, size_t ws_bytes, void *stream);
+                           int32_t max_iters, int32_t wg_waves, void *ws, size_t ws_bytes, void *stream);
 /* Blocked-JDS parts (slice height C for all parts), built from the JDS parts
  * above, so their perm gives slots too. */
 spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *slot_ptr, const int64_t *h_row_off,
@@ -342,8 +346,8 @@ spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *slot_ptr
                                    const int32_t *const *h_slice_nd, const int32_t *const *h_slice_nd_host,
                                    const int32_t *const *h_bl_col, const void *const *h_bl_val, spmv_dtype val_dt,
                                    const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
-                                   int32_t rows_per_wave, int32_t unroll, int32_t max_iters, void *ws,
-                                   size_t ws_bytes, void *stream);
+                                   int32_t rows_per_wave, int32_t unroll, int32_t max_iters, int32_t wg_waves,
+                                   void *ws, size_t ws_bytes, void *stream);
 
 /* ======================================================================== */
 /* Row-split products                                                        */
@@ -378,7 +382,7 @@ spmv_status spmv_jds_row_split(int32_t n, const int64_t *h_bounds, const int32_t
                                const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host,
                                const int32_t *h_ndiag, const int32_t *const *h_jd_col, const void *const *h_jd_val,
                                spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
-                               double beta, int32_t unroll, int32_t max_iters, void *stream);
+                               double beta, int32_t unroll, int32_t max_iters, int32_t wg_waves, void *stream);
 /* Blocked-JDS parts (slice height C for all parts), built from the JDS parts
  * above. */
 spmv_status spmv_jds_blocked_row_split(int32_t n, int32_t C, const int64_t *h_bounds, const int32_t *const *h_perm,
@@ -386,7 +390,7 @@ spmv_status spmv_jds_blocked_row_split(int32_t n, int32_t C, const int64_t *h_bo
                                        const int32_t *const *h_slice_nd_host, const int32_t *const *h_bl_col,
                                        const void *const *h_bl_val, spmv_dtype val_dt, const void *x, void *y,
                                        spmv_dtype vec_dt, double alpha, double beta, int32_t rows_per_wave,
-                                       int32_t unroll, int32_t max_iters, void *stream);
+                                       int32_t unroll, int32_t max_iters, int32_t wg_waves, void *stream);
 
 /* ======================================================================== */
 /* Many matrices in one launch                                               */

@@ -54,9 +54,10 @@ SIGNATURES = {
     "spmv_transpose_workspace_size": (_sz, [_i32, _i32, _i64]),
     "spmv_transpose_csr": (_int, [_i32, _i32, _i64, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "spmv_crs": (_int, [_i32, _i32, _p, _p, _p, _int, _p, _p, _int, _f64, _f64, _p, _i32, _i32, _p]),
-    "spmv_jds": (_int, [_i32, _p, _p, _i32p, _i32, _p, _p, _int, _p, _p, _int, _f64, _f64, _i32, _i32, _u32, _p]),
+    "spmv_jds": (_int, [_i32, _p, _p, _i32p, _i32, _p, _p, _int, _p, _p, _int, _f64, _f64, _i32, _i32, _i32, _u32,
+                        _p]),
     "spmv_jds_blocked": (_int, [_i32, _p, _i32, _i32, _p, _p, _i32p, _p, _p, _int, _p, _p, _int, _f64, _f64, _i32,
-                                _i32, _i32, _u32, _p]),
+                                _i32, _i32, _i32, _u32, _p]),
     "spmv_permute_vec": (_int, [_i32, _p, _p, _p, _int, _int, _p]),
     "spmv_gather_values": (_int, [_i64, _p, _p, _p, _int, _p]),
     "spmv_axpby": (_int, [_i64, _f64, _p, _f64, _p, _int, _p]),
@@ -75,15 +76,15 @@ SIGNATURES = {
     "spmv_crs_split": (_int, [_i32, _i32, _p, _p, _p, _p, _p, _i64p, _i64p, _int, _p, _i32p, _i32p, _i32, _p, _p, _int,
                               _f64, _f64, _p, _sz, _p]),
     "spmv_jds_split": (_int, [_i32, _p, _i64p, _vpp, _vpp, _vpp, _i32p, _vpp, _vpp, _int, _p, _p, _int, _f64, _f64,
-                              _i32, _i32, _p, _sz, _p]),
+                              _i32, _i32, _i32, _p, _sz, _p]),
     "spmv_jds_blocked_split": (_int, [_i32, _i32, _p, _i64p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, _int, _p, _p, _int,
-                                      _f64, _f64, _i32, _i32, _i32, _p, _sz, _p]),
+                                      _f64, _f64, _i32, _i32, _i32, _i32, _p, _sz, _p]),
     "spmv_split_rows_workspace_size": (_sz, []),
     "spmv_split_rows": (_int, [_i32, _i64, _p, _p, _i64p, _i64p, _p, _sz, _p]),
     "spmv_jds_row_split": (_int, [_i32, _i64p, _vpp, _vpp, _vpp, _i32p, _vpp, _vpp, _int, _p, _p, _int, _f64, _f64,
-                                  _i32, _i32, _p]),
+                                  _i32, _i32, _i32, _p]),
     "spmv_jds_blocked_row_split": (_int, [_i32, _i32, _i64p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, _int, _p, _p, _int,
-                                          _f64, _f64, _i32, _i32, _i32, _p]),
+                                          _f64, _f64, _i32, _i32, _i32, _i32, _p]),
     "spmv_batched_plan": (_int, [_i32, _i32p, _i32p, _i64p, _i64p, _i64p, _i64p, _i32p, _i32, _p, _i64, _i64p,
                                  _p]),
     "spmv_batched": (_int, [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _p]),

@@ -1,6 +1,8 @@
-"""Autotuner for the JDS and blocked-JDS products: slice height C, rows per
-wavefront R, diagonals per trip U and diagonals per wavefront before a row is
-split (max_iters), chosen per row-length signature and cached.
+"""Autotuner for the SpMV launch parameters: the CRS plan's entries per
+block, and for the JDS and blocked-JDS products the slice height C, rows per
+wavefront R, diagonals per trip U, diagonals per wavefront before a row is
+split (max_iters) and wavefronts per workgroup W, chosen per row-length
+signature and cached.
 
 The signature of a matrix is (log2 of its row count, its longest row, its
 mean row length rounded to a power of two); matrices that share it share the
@@ -29,6 +31,8 @@ C_CANDIDATES = (64, 128, 256)
 R_CANDIDATES = (0, 64, 32, 16)      # 0: the library's choice per length class
 U_CANDIDATES = (2, 4, 8)
 MAX_ITERS_CANDIDATES = (0, 64, 128)  # 0: the library default
+W_CANDIDATES = (16, 8, 4)            # wavefronts per workgroup
+BLOCK_NNZ_CANDIDATES = (512, 1024, 2048)
 
 
 def signature(n_rows: int, longest: int, nnz: int) -> str:
@@ -80,21 +84,23 @@ def _time(fn, reps=10, warm=2) -> float:
 class Autotuner:
     """Chooses (C, R, U) for blocked-JDS matrices; results cached per signature."""
 
-    def __init__(self, cache_path: str = DEFAULT_CACHE, cs=C_CANDIDATES, rs=R_CANDIDATES, us=U_CANDIDATES):
+    def __init__(self, cache_path: str = DEFAULT_CACHE, cs=C_CANDIDATES, rs=R_CANDIDATES, us=U_CANDIDATES,
+                 ws=W_CANDIDATES):
         self.cache_path = cache_path
-        self.cs, self.rs, self.us = tuple(cs), tuple(rs), tuple(us)
+        self.cs, self.rs, self.us, self.ws = tuple(cs), tuple(rs), tuple(us), tuple(ws)
         self.cache = _load(cache_path)
         self.log: List[dict] = []
 
-    def lookup(self, sig: str):
+    def lookup(self, sig: str, keys: Sequence[str]):
         ent = self.cache.get(_device_key(), {}).get(sig)
-        if ent is None:
+        if ent is None or any(k not in ent for k in keys):
             return None
-        return (ent["U"], ent["max_iters"]) if "max_iters" in ent else (ent["C"], ent["R"], ent["U"])
+        return tuple(ent[k] for k in keys)
 
-    def _record(self, sig, best, timings):
-        self.cache.setdefault(_device_key(), {})[sig] = {"C": best[0], "R": best[1], "U": best[2],
-                                                        "ms": round(timings[best], 5)}
+    def _record(self, sig, keys, best, timings):
+        ent = dict(zip(keys, best))
+        ent["ms"] = round(timings[best], 5)
+        self.cache.setdefault(_device_key(), {})[sig] = ent
         _store(self.cache_path, self.cache)
 
     def tune_batched(self, jds_list: Sequence[S.JDS], sample: int = 16) -> Tuple[int, int, int]:
@@ -102,7 +108,7 @@ class Autotuner:
         the blocked layout of up to `sample` of them for each C and times the
         persistent launch for each (R, U)."""
         sig = "batched:" + self._batch_signature(jds_list)
-        hit = self.lookup(sig)
+        hit = self.lookup(sig, ("C", "R", "U"))
         if hit is not None:
             return hit
         pick = list(jds_list[:: max(1, len(jds_list) // sample)])[:sample]
@@ -121,7 +127,7 @@ class Autotuner:
         best = min(timings, key=timings.get)
         self.log.append({"signature": sig, "timings_ms": {f"C{c}_R{r}_U{u}": round(t, 5)
                                                           for (c, r, u), t in timings.items()}})
-        self._record(sig, best, timings)
+        self._record(sig, ("C", "R", "U"), best, timings)
         return best
 
     @staticmethod
@@ -135,10 +141,11 @@ class Autotuner:
         mean = tot / max(rows, 1)
         return f"mats{nmat}/max{mx}/mean2^{int(round(math.log2(max(mean, 1.0))))}"
 
-    def tune_blocked(self, J: S.JDS, x: torch.Tensor) -> Tuple[int, int, int]:
-        """Best (C, R, U) for one large matrix in blocked-JDS storage."""
+    def tune_blocked(self, J: S.JDS, x: torch.Tensor) -> Tuple[int, int, int, int]:
+        """Best (C, R, U, W) for one large matrix in blocked-JDS storage."""
         sig = "single:" + signature(J.n, J.ndiag, int(J.h_jd_ptr[J.ndiag]))
-        hit = self.lookup(sig)
+        keys = ("C", "R", "U", "W")
+        hit = self.lookup(sig, keys)
         if hit is not None:
             return hit
         timings = {}
@@ -147,32 +154,57 @@ class Autotuner:
             B = S.jds_blocked_from_jds(J, C)
             for R in self.rs:
                 for U in self.us:
-                    timings[(C, R, U)] = _time(lambda: S.spmv_jds_blocked(B, x, y, rows_per_wave=R, unroll=U))
+                    for W in self.ws:
+                        timings[(C, R, U, W)] = _time(lambda: S.spmv_jds_blocked(B, x, y, rows_per_wave=R, unroll=U,
+                                                                                 wg_waves=W))
             del B
         best = min(timings, key=timings.get)
-        self.log.append({"signature": sig, "timings_ms": {f"C{c}_R{r}_U{u}": round(t, 5)
-                                                          for (c, r, u), t in timings.items()}})
-        self._record(sig, best, timings)
+        self.log.append({"signature": sig, "timings_ms": {f"C{c}_R{r}_U{u}_W{w}": round(t, 5)
+                                                          for (c, r, u, w), t in timings.items()}})
+        self._record(sig, keys, best, timings)
         return best
 
 
-    def tune_jds(self, J: S.JDS, x: torch.Tensor, mis=MAX_ITERS_CANDIDATES) -> Tuple[int, int]:
-        """Best (U, max_iters) for one large matrix in JDS storage."""
+    def tune_jds(self, J: S.JDS, x: torch.Tensor, mis=MAX_ITERS_CANDIDATES) -> Tuple[int, int, int]:
+        """Best (U, max_iters, W) for one large matrix in JDS storage."""
         sig = "jds:" + signature(J.n, J.ndiag, int(J.h_jd_ptr[J.ndiag]))
-        hit = self.lookup(sig)
+        keys = ("U", "max_iters", "W")
+        hit = self.lookup(sig, keys)
         if hit is not None:
             return hit
         timings = {}
         y = torch.empty(J.n, dtype=x.dtype, device=x.device)
         for U in self.us:
             for mi in mis:
-                timings[(U, mi)] = _time(lambda: S.spmv_jds(J, x, y, unroll=U, max_iters=mi))
+                for W in self.ws:
+                    timings[(U, mi, W)] = _time(lambda: S.spmv_jds(J, x, y, unroll=U, max_iters=mi, wg_waves=W))
         best = min(timings, key=timings.get)
-        self.log.append({"signature": sig, "timings_ms": {f"U{u}_mi{m}": round(t, 5) for (u, m), t in timings.items()}})
-        self.cache.setdefault(_device_key(), {})[sig] = {"U": best[0], "max_iters": best[1],
-                                                        "ms": round(timings[best], 5)}
-        _store(self.cache_path, self.cache)
+        self.log.append({"signature": sig, "timings_ms": {f"U{u}_mi{m}_W{w}": round(t, 5)
+                                                          for (u, m, w), t in timings.items()}})
+        self._record(sig, keys, best, timings)
         return best
+
+
+def tune_crs(tuner: "Autotuner", A: S.CSR, x: torch.Tensor, longest: int,
+             candidates=BLOCK_NNZ_CANDIDATES) -> int:
+    """Best entries-per-block of the CRS plan for one large matrix (its
+    longest row passed by the caller); A's plan is rebuilt with it."""
+    sig = "crs:" + signature(A.n_rows, longest, A.nnz)
+    ent = tuner.cache.get(_device_key(), {}).get(sig)
+    if ent is None:
+        timings = {}
+        y = torch.empty(A.n_rows, dtype=x.dtype, device=x.device)
+        for bn in candidates:
+            Ab = S.spmv_crs_plan(S.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
+            timings[bn] = _time(lambda: S.spmv_crs(Ab, x, y))
+            del Ab
+        best = min(timings, key=timings.get)
+        tuner.log.append({"signature": sig, "timings_ms": {f"block{b}": round(t, 5) for b, t in timings.items()}})
+        ent = {"block_nnz": best, "ms": round(timings[best], 5)}
+        tuner.cache.setdefault(_device_key(), {})[sig] = ent
+        _store(tuner.cache_path, tuner.cache)
+    S.spmv_crs_plan(A, ent["block_nnz"])
+    return ent["block_nnz"]
 
 
 def build_batched(jds_list: Sequence[S.JDS], tuner: Autotuner = None, n_workgroups: int = 0) -> S.Batched:

@@ -27,7 +27,7 @@
 
 namespace spmv {
 
-constexpr int JDS_WAVES = 16;                 // wavefronts per workgroup
+constexpr int JDS_WAVES = 16;                 // wavefronts per workgroup: the most, and the default
 constexpr int JDS_THREADS = JDS_WAVES * WAVE;
 constexpr int JDS_MAX_CLASSES = 8;
 constexpr int JDS_DEFAULT_MAX_ITERS = 32;
@@ -46,6 +46,7 @@ struct JdsClass {
 struct JdsPlan {
     JdsClass c[JDS_MAX_CLASSES];
     int32_t ncls;
+    int32_t waves;      // wavefronts per workgroup (4, 8 or 16)
 };
 
 struct JdsArgs {
@@ -220,7 +221,7 @@ __device__ __forceinline__ WaveTask wave_task(const JdsArgs &a, const JdsPlan &P
     t.S = 1 << K.slog;
     const int R = 1 << K.rlog;
     t.G = WAVE >> K.rlog;
-    const int64_t slot = (wg - wg0) * JDS_WAVES + t.w;
+    const int64_t slot = (wg - wg0) * P.waves + t.w;
     const int64_t grp = slot >> K.slog;
     t.p = (int)(slot & (t.S - 1));
     const int64_t row0l = (int64_t)K.row_start + grp * R;
@@ -442,14 +443,15 @@ __global__ __launch_bounds__(JDS_THREADS) void jds_grad_kernel(JdsArgs a, JdsPla
 
 // ---------------------------------------------------------------- host planning
 
-// W wavefronts per 64-row chunk, split into (R rows per wave, S waves per group).
-static void split_for(int W, int forced_rlog, int &rlog, int &slog)
+// W wavefronts per 64-row chunk, split into (R rows per wave, S waves per
+// group); a group's S waves share a workgroup of `waves` wavefronts.
+static void split_for(int W, int forced_rlog, int waves, int &rlog, int &slog)
 {
     if (forced_rlog >= 0) {
         int G = 1 << (6 - forced_rlog);
         int S = W / G;
         if (S < 1) S = 1;
-        if (S > JDS_WAVES) S = JDS_WAVES;
+        if (S > waves) S = waves;
         rlog = forced_rlog;
         slog = 0;
         while ((1 << slog) < S) ++slog;
@@ -465,13 +467,15 @@ static void split_for(int W, int forced_rlog, int &rlog, int &slog)
     case 64: rlog = 4; slog = 4; break;
     default: rlog = 3; slog = 4; break;   // 128
     }
+    while ((1 << slog) > waves) --slog;   // then each wave takes more diagonals
 }
 
 // chunk_len(i) = length of the first row of 64-row chunk i (non-increasing).
 template <typename F>
-static JdsPlan build_plan(int32_t n, int32_t max_iters, int forced_rlog, F chunk_len)
+static JdsPlan build_plan(int32_t n, int32_t max_iters, int forced_rlog, int waves, F chunk_len)
 {
     JdsPlan P{};
+    P.waves = waves;
     int64_t nchunks = ceil_div(n, 64);
     int cls = 0;
     int64_t wg_total = 0;
@@ -481,7 +485,7 @@ static JdsPlan build_plan(int32_t n, int32_t max_iters, int forced_rlog, F chunk
         int W = 1;
         while (W < 128 && (int64_t)W * max_iters < L) W <<= 1;
         int rlog, slog;
-        split_for(W, forced_rlog, rlog, slog);
+        split_for(W, forced_rlog, waves, rlog, slog);
         // extend the class while the chunks want the same split
         int64_t j = i + 1;
         if (cls == JDS_MAX_CLASSES - 1) {
@@ -503,7 +507,7 @@ static JdsPlan build_plan(int32_t n, int32_t max_iters, int forced_rlog, F chunk
         K.rlog = rlog;
         K.slog = slog;
         int64_t groups = ceil_div(K.row_end - K.row_start, (int64_t)1 << rlog);
-        wg_total += ceil_div(groups << slog, JDS_WAVES);
+        wg_total += ceil_div(groups << slog, waves);
         K.wg_end = (int32_t)wg_total;
         ++cls;
         i = j;
@@ -512,7 +516,8 @@ static JdsPlan build_plan(int32_t n, int32_t max_iters, int forced_rlog, F chunk
     return P;
 }
 
-static JdsPlan plan_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int32_t max_iters, int forced_rlog)
+static JdsPlan plan_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int32_t max_iters, int forced_rlog,
+                        int waves = JDS_WAVES)
 {
     // rows longer than d are the first (jd_ptr[d+1]-jd_ptr[d]) permuted rows
     auto chunk_len = [&](int64_t i) -> int64_t {
@@ -525,13 +530,14 @@ static JdsPlan plan_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int32
         }
         return lo;
     };
-    return build_plan(n, max_iters, forced_rlog, chunk_len);
+    return build_plan(n, max_iters, forced_rlog, waves, chunk_len);
 }
 
-static JdsPlan plan_blocked(int32_t n, int32_t C, const int32_t *h_slice_nd, int32_t max_iters, int forced_rlog)
+static JdsPlan plan_blocked(int32_t n, int32_t C, const int32_t *h_slice_nd, int32_t max_iters, int forced_rlog,
+                            int waves = JDS_WAVES)
 {
     auto chunk_len = [&](int64_t i) -> int64_t { return h_slice_nd[(i * 64) / C]; };
-    return build_plan(n, max_iters, forced_rlog, chunk_len);
+    return build_plan(n, max_iters, forced_rlog, waves, chunk_len);
 }
 
 template <int FMT, typename VT, typename XT>
@@ -541,9 +547,9 @@ static spmv_status launch_jds_t(const JdsArgs &a, const JdsPlan &P, int unroll, 
     unsigned grid = (unsigned)P.c[P.ncls - 1].wg_end;
     if (grid == 0) return SPMV_OK;
     switch (unroll) {
-    case 2: jds_kernel<FMT, 2, VT, XT><<<grid, JDS_THREADS, 0, s>>>(a, P); break;
-    case 8: jds_kernel<FMT, 8, VT, XT><<<grid, JDS_THREADS, 0, s>>>(a, P); break;
-    default: jds_kernel<FMT, 4, VT, XT><<<grid, JDS_THREADS, 0, s>>>(a, P); break;
+    case 2: jds_kernel<FMT, 2, VT, XT><<<grid, P.waves * WAVE, 0, s>>>(a, P); break;
+    case 8: jds_kernel<FMT, 8, VT, XT><<<grid, P.waves * WAVE, 0, s>>>(a, P); break;
+    default: jds_kernel<FMT, 4, VT, XT><<<grid, P.waves * WAVE, 0, s>>>(a, P); break;
     }
     SPMV_CHECK_LAUNCH(FMT == FMT_JDS ? "spmv_jds" : "spmv_jds_blocked");
     return SPMV_OK;
@@ -566,6 +572,8 @@ static spmv_status launch_jds(const JdsArgs &a, const JdsPlan &P, int unroll, sp
 }
 
 static int unroll_ok(int32_t u) { return u == 0 || u == 2 || u == 4 || u == 8; }
+static int waves_ok(int32_t w) { return w == 0 || w == 4 || w == 8 || w == 16; }
+static int waves_or_default(int32_t w) { return w ? w : JDS_WAVES; }
 
 // Row bounds of the row-split parts: 0 = b_0 <= b_1 <= ... <= b_8 = n.
 static spmv_status row_bounds_ok(int32_t n, const int64_t *h_bounds, const char *who)
@@ -579,17 +587,18 @@ static spmv_status row_bounds_ok(int32_t n, const int64_t *h_bounds, const char 
 }
 
 template <int FMT>
-static spmv_status launch_rows(const JdsSplitArgs &S, int64_t max_wg, int32_t unroll, spmv_dtype val_dt,
+static spmv_status launch_rows(const JdsSplitArgs &S, int64_t max_wg, int32_t unroll, int waves, spmv_dtype val_dt,
                                spmv_dtype vec_dt, hipStream_t s, const char *who)
 {
     const unsigned grid = (unsigned)(max_wg * SPLIT_PARTS);
+    const unsigned threads = (unsigned)(waves * WAVE);
     if (grid == 0) return SPMV_OK;
     const int u = unroll ? unroll : 4;
 #define JROWS_CASE(VDT, VT, XDT, XT)                                                       \
     if (val_dt == VDT && vec_dt == XDT) {                                                  \
-        if (u == 2) jds_rows_kernel<FMT, 2, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);       \
-        else if (u == 8) jds_rows_kernel<FMT, 8, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);  \
-        else jds_rows_kernel<FMT, 4, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);              \
+        if (u == 2) jds_rows_kernel<FMT, 2, VT, XT><<<grid, threads, 0, s>>>(S);       \
+        else if (u == 8) jds_rows_kernel<FMT, 8, VT, XT><<<grid, threads, 0, s>>>(S);  \
+        else jds_rows_kernel<FMT, 4, VT, XT><<<grid, threads, 0, s>>>(S);              \
     } else
     JROWS_CASE(SPMV_F64, double, SPMV_F64, double)
     JROWS_CASE(SPMV_F32, float, SPMV_F64, double)
@@ -612,9 +621,10 @@ extern "C" {
 spmv_status spmv_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, const int32_t *h_jd_ptr, int32_t ndiag,
                      const int32_t *jd_col, const void *jd_val, spmv_dtype val_dt, const void *x, void *y,
                      spmv_dtype vec_dt, double alpha, double beta, int32_t unroll, int32_t max_iters,
-                     unsigned flags, void *stream)
+                     int32_t wg_waves, unsigned flags, void *stream)
 {
     SPMV_REQUIRE(n >= 0 && ndiag >= 0, "spmv_jds: negative size");
+    SPMV_REQUIRE(waves_ok(wg_waves), "spmv_jds: wg_waves must be 0, 4, 8 or 16");
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds: bad dtype");
     SPMV_REQUIRE(unroll_ok(unroll), "spmv_jds: unroll must be 0, 2, 4 or 8");
     SPMV_REQUIRE(max_iters >= 0, "spmv_jds: max_iters < 0");
@@ -637,7 +647,8 @@ spmv_status spmv_jds(int32_t n, const int32_t *perm, const int32_t *jd_ptr, cons
     a.alpha = alpha;
     a.beta = beta;
     a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
-    JdsPlan P = plan_jds(n, h_jd_ptr, ndiag, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1);
+    JdsPlan P = plan_jds(n, h_jd_ptr, ndiag, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1,
+                         waves_or_default(wg_waves));
     return launch_jds<FMT_JDS>(a, P, unroll ? unroll : 4, val_dt, vec_dt, as_stream(stream));
 }
 
@@ -645,9 +656,10 @@ spmv_status spmv_jds_blocked(int32_t n, const int32_t *perm, int32_t C, int32_t 
                              const int32_t *slice_nd, const int32_t *h_slice_nd, const int32_t *bl_col,
                              const void *bl_val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
                              double alpha, double beta, int32_t rows_per_wave, int32_t unroll, int32_t max_iters,
-                             unsigned flags, void *stream)
+                             int32_t wg_waves, unsigned flags, void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_jds_blocked: n < 0");
+    SPMV_REQUIRE(waves_ok(wg_waves), "spmv_jds_blocked: wg_waves must be 0, 4, 8 or 16");
     SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked: C must be a positive multiple of 64");
     SPMV_REQUIRE(n_slices == (int32_t)ceil_div(n, C), "spmv_jds_blocked: n_slices != ceil(n / C)");
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_blocked: bad dtype");
@@ -679,7 +691,8 @@ spmv_status spmv_jds_blocked(int32_t n, const int32_t *perm, int32_t C, int32_t 
         forced = 0;
         while ((1 << forced) < rows_per_wave) ++forced;
     }
-    JdsPlan P = plan_blocked(n, C, h_slice_nd, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced);
+    JdsPlan P = plan_blocked(n, C, h_slice_nd, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced,
+                             waves_or_default(wg_waves));
     return launch_jds<FMT_BLOCKED>(a, P, unroll ? unroll : 4, val_dt, vec_dt, as_stream(stream));
 }
 
@@ -755,9 +768,9 @@ spmv_status spmv_grad_vals_jds(int32_t n, const int32_t *perm, const int32_t *jd
     const unsigned grid = (unsigned)P.c[P.ncls - 1].wg_end;
     hipStream_t s = as_stream(stream);
     if (dt == SPMV_F64)
-        jds_grad_kernel<4, double><<<grid, JDS_THREADS, 0, s>>>(a, P);
+        jds_grad_kernel<4, double><<<grid, P.waves * WAVE, 0, s>>>(a, P);
     else
-        jds_grad_kernel<4, float><<<grid, JDS_THREADS, 0, s>>>(a, P);
+        jds_grad_kernel<4, float><<<grid, P.waves * WAVE, 0, s>>>(a, P);
     SPMV_CHECK_LAUNCH("spmv_grad_vals_jds");
     return SPMV_OK;
 }
@@ -778,9 +791,11 @@ spmv_status spmv_jds_split(int32_t n, const int32_t *slot_ptr, const int64_t *h_
                            const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag,
                            const int32_t *const *h_jd_col, const void *const *h_jd_val, spmv_dtype val_dt,
                            const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, int32_t unroll,
-                           int32_t max_iters, void *ws, size_t ws_bytes, void *stream)
+                           int32_t max_iters, int32_t wg_waves, void *ws, size_t ws_bytes, void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_jds_split: n < 0");
+    SPMV_REQUIRE(waves_ok(wg_waves), "spmv_jds_split: wg_waves must be 0, 4, 8 or 16");
+    const int waves = waves_or_default(wg_waves);
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_split: bad dtype");
     SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_split: bad unroll or max_iters");
     if (n == 0) return SPMV_OK;
@@ -811,18 +826,20 @@ spmv_status spmv_jds_split(int32_t n, const int32_t *slot_ptr, const int64_t *h_
         a.y = slots;                           // perm maps part rows to their slots
         a.alpha = 1.0;
         a.beta = 0.0;
-        S.P[k] = plan_jds(nk, h_jd_ptr_host[k], h_ndiag[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1);
+        S.P[k] = plan_jds(nk, h_jd_ptr_host[k], h_ndiag[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1,
+                          waves);
         if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
     }
     hipStream_t s = as_stream(stream);
     const unsigned grid = (unsigned)(max_wg * SPLIT_PARTS);
+    const unsigned threads = (unsigned)(waves * WAVE);
     if (grid) {
         const int u = unroll ? unroll : 4;
 #define JSPLIT_CASE(VDT, VT, XDT, XT)                                                              \
     if (val_dt == VDT && vec_dt == XDT) {                                                          \
-        if (u == 2) jds_split_kernel<FMT_JDS, 2, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);          \
-        else if (u == 8) jds_split_kernel<FMT_JDS, 8, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);     \
-        else jds_split_kernel<FMT_JDS, 4, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);                 \
+        if (u == 2) jds_split_kernel<FMT_JDS, 2, VT, XT><<<grid, threads, 0, s>>>(S);          \
+        else if (u == 8) jds_split_kernel<FMT_JDS, 8, VT, XT><<<grid, threads, 0, s>>>(S);     \
+        else jds_split_kernel<FMT_JDS, 4, VT, XT><<<grid, threads, 0, s>>>(S);                 \
     } else
         JSPLIT_CASE(SPMV_F64, double, SPMV_F64, double)
         JSPLIT_CASE(SPMV_F32, float, SPMV_F64, double)
@@ -842,10 +859,12 @@ spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *slot_ptr
                                    const int32_t *const *h_slice_nd, const int32_t *const *h_slice_nd_host,
                                    const int32_t *const *h_bl_col, const void *const *h_bl_val, spmv_dtype val_dt,
                                    const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
-                                   int32_t rows_per_wave, int32_t unroll, int32_t max_iters, void *ws,
-                                   size_t ws_bytes, void *stream)
+                                   int32_t rows_per_wave, int32_t unroll, int32_t max_iters, int32_t wg_waves,
+                                   void *ws, size_t ws_bytes, void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_jds_blocked_split: n < 0");
+    SPMV_REQUIRE(waves_ok(wg_waves), "spmv_jds_blocked_split: wg_waves must be 0, 4, 8 or 16");
+    const int waves = waves_or_default(wg_waves);
     SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_split: C must be a positive multiple of 64");
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_blocked_split: bad dtype");
     SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_blocked_split: bad unroll or max_iters");
@@ -887,18 +906,20 @@ spmv_status spmv_jds_blocked_split(int32_t n, int32_t C, const int32_t *slot_ptr
         a.y = slots;                           // perm maps part rows to their slots
         a.alpha = 1.0;
         a.beta = 0.0;
-        S.P[k] = plan_blocked(nk, C, h_slice_nd_host[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced);
+        S.P[k] = plan_blocked(nk, C, h_slice_nd_host[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced,
+                              waves);
         if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
     }
     hipStream_t s = as_stream(stream);
     const unsigned grid = (unsigned)(max_wg * SPLIT_PARTS);
+    const unsigned threads = (unsigned)(waves * WAVE);
     if (grid) {
         const int u = unroll ? unroll : 4;
 #define BSPLIT_CASE(VDT, VT, XDT, XT)                                                                  \
     if (val_dt == VDT && vec_dt == XDT) {                                                              \
-        if (u == 2) jds_split_kernel<FMT_BLOCKED, 2, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);          \
-        else if (u == 8) jds_split_kernel<FMT_BLOCKED, 8, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);     \
-        else jds_split_kernel<FMT_BLOCKED, 4, VT, XT><<<grid, JDS_THREADS, 0, s>>>(S);                 \
+        if (u == 2) jds_split_kernel<FMT_BLOCKED, 2, VT, XT><<<grid, threads, 0, s>>>(S);          \
+        else if (u == 8) jds_split_kernel<FMT_BLOCKED, 8, VT, XT><<<grid, threads, 0, s>>>(S);     \
+        else jds_split_kernel<FMT_BLOCKED, 4, VT, XT><<<grid, threads, 0, s>>>(S);                 \
     } else
         BSPLIT_CASE(SPMV_F64, double, SPMV_F64, double)
         BSPLIT_CASE(SPMV_F32, float, SPMV_F64, double)
@@ -917,9 +938,11 @@ spmv_status spmv_jds_row_split(int32_t n, const int64_t *h_bounds, const int32_t
                                const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host,
                                const int32_t *h_ndiag, const int32_t *const *h_jd_col, const void *const *h_jd_val,
                                spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
-                               double beta, int32_t unroll, int32_t max_iters, void *stream)
+                               double beta, int32_t unroll, int32_t max_iters, int32_t wg_waves, void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_jds_row_split: n < 0");
+    SPMV_REQUIRE(waves_ok(wg_waves), "spmv_jds_row_split: wg_waves must be 0, 4, 8 or 16");
+    const int waves = waves_or_default(wg_waves);
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_row_split: bad dtype");
     SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_row_split: bad unroll or max_iters");
     spmv_status st = row_bounds_ok(n, h_bounds, "spmv_jds_row_split");
@@ -948,10 +971,11 @@ spmv_status spmv_jds_row_split(int32_t n, const int64_t *h_bounds, const int32_t
         a.y = (char *)y + h_bounds[k] * ysz;
         a.alpha = alpha;
         a.beta = beta;
-        S.P[k] = plan_jds(nk, h_jd_ptr_host[k], h_ndiag[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1);
+        S.P[k] = plan_jds(nk, h_jd_ptr_host[k], h_ndiag[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, -1,
+                          waves);
         if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
     }
-    return launch_rows<FMT_JDS>(S, max_wg, unroll, val_dt, vec_dt, as_stream(stream), "spmv_jds_row_split");
+    return launch_rows<FMT_JDS>(S, max_wg, unroll, waves, val_dt, vec_dt, as_stream(stream), "spmv_jds_row_split");
 }
 
 spmv_status spmv_jds_blocked_row_split(int32_t n, int32_t C, const int64_t *h_bounds, const int32_t *const *h_perm,
@@ -959,9 +983,11 @@ spmv_status spmv_jds_blocked_row_split(int32_t n, int32_t C, const int64_t *h_bo
                                        const int32_t *const *h_slice_nd_host, const int32_t *const *h_bl_col,
                                        const void *const *h_bl_val, spmv_dtype val_dt, const void *x, void *y,
                                        spmv_dtype vec_dt, double alpha, double beta, int32_t rows_per_wave,
-                                       int32_t unroll, int32_t max_iters, void *stream)
+                                       int32_t unroll, int32_t max_iters, int32_t wg_waves, void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_jds_blocked_row_split: n < 0");
+    SPMV_REQUIRE(waves_ok(wg_waves), "spmv_jds_blocked_row_split: wg_waves must be 0, 4, 8 or 16");
+    const int waves = waves_or_default(wg_waves);
     SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_row_split: C must be a positive multiple of 64");
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_blocked_row_split: bad dtype");
     SPMV_REQUIRE(unroll_ok(unroll) && max_iters >= 0, "spmv_jds_blocked_row_split: bad unroll or max_iters");
@@ -1000,10 +1026,11 @@ spmv_status spmv_jds_blocked_row_split(int32_t n, int32_t C, const int64_t *h_bo
         a.y = (char *)y + h_bounds[k] * ysz;
         a.alpha = alpha;
         a.beta = beta;
-        S.P[k] = plan_blocked(nk, C, h_slice_nd_host[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced);
+        S.P[k] = plan_blocked(nk, C, h_slice_nd_host[k], max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced,
+                              waves);
         if (S.P[k].ncls) max_wg = std::max<int64_t>(max_wg, S.P[k].c[S.P[k].ncls - 1].wg_end);
     }
-    return launch_rows<FMT_BLOCKED>(S, max_wg, unroll, val_dt, vec_dt, as_stream(stream),
+    return launch_rows<FMT_BLOCKED>(S, max_wg, unroll, waves, val_dt, vec_dt, as_stream(stream),
                                     "spmv_jds_blocked_row_split");
 }
 

@@ -301,25 +301,26 @@ def spmv_crs(A: CSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: f
 
 
 def spmv_jds(J: JDS, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
-             unroll: int = 0, max_iters: int = 0) -> torch.Tensor:
+             unroll: int = 0, max_iters: int = 0, wg_waves: int = 0) -> torch.Tensor:
     """y = alpha*A x + beta*y with the JDS kernel (spmv_jds)."""
     _check_dev(x)
     y = _out_vec(y, J.n, x, beta)
     call("spmv_jds", J.n, _p(J.perm), _p(J.jd_ptr), _h_i32(J.h_jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val),
          dtype_code(J.jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll, max_iters,
-         J.flags, _stream())
+         wg_waves, J.flags, _stream())
     return y
 
 
 def spmv_jds_blocked(B: Blocked, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
-                     beta: float = 0.0, rows_per_wave: int = 0, unroll: int = 0, max_iters: int = 0) -> torch.Tensor:
+                     beta: float = 0.0, rows_per_wave: int = 0, unroll: int = 0, max_iters: int = 0,
+                     wg_waves: int = 0) -> torch.Tensor:
     """y = alpha*A x + beta*y with the blocked-JDS kernel (spmv_jds_blocked)."""
     _check_dev(x)
     y = _out_vec(y, B.n, x, beta)
     flags = (SYMPERM if B.symperm else 0) | (SOJDS if B.sojds else 0)
     call("spmv_jds_blocked", B.n, _p(B.perm), B.C, B.n_slices, _p(B.slice_ptr), _p(B.slice_nd),
          _h_i32(B.h_slice_nd), _p(B.bl_col), _p(B.bl_val), dtype_code(B.bl_val.dtype), _p(x), _p(y),
-         dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave, unroll, max_iters, flags, _stream())
+         dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave, unroll, max_iters, wg_waves, flags, _stream())
     return y
 
 
@@ -541,12 +542,12 @@ def _jds_split_args(S: Split):
     return S._jds_args
 
 
-def spmv_jds_split(S: Split, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0):
+def spmv_jds_split(S: Split, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0, wg_waves=0):
     Js, perm, jp, hptr, ndiag, col, val = _jds_split_args(S)
     y = _out_vec(y, S.n, x, beta)
     call("spmv_jds_split", S.n, _p(S.slot_ptr), _h_i64(S.row_off), perm, jp, hptr, _h_i32(ndiag), col, val,
          dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll,
-         max_iters, _p(S.ws), S.ws.numel(), _stream())
+         max_iters, wg_waves, _p(S.ws), S.ws.numel(), _stream())
     return y
 
 
@@ -562,12 +563,12 @@ def _blocked_split_args(S: Split, C_: int):
 
 
 def spmv_jds_blocked_split(S: Split, x, y=None, alpha=1.0, beta=0.0, C_=64, rows_per_wave=0, unroll=0,
-                           max_iters=0):
+                           max_iters=0, wg_waves=0):
     Bs, perm, sptr, snd, hnd, col, val = _blocked_split_args(S, C_)
     y = _out_vec(y, S.n, x, beta)
     call("spmv_jds_blocked_split", S.n, C_, _p(S.slot_ptr), _h_i64(S.row_off), perm, sptr, snd, hnd, col, val,
          dtype_code(Bs[0].bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave,
-         unroll, max_iters, _p(S.ws), S.ws.numel(), _stream())
+         unroll, max_iters, wg_waves, _p(S.ws), S.ws.numel(), _stream())
     return y
 
 
@@ -639,13 +640,13 @@ def _jds_row_split_args(R: RowSplit):
     return R._jds_args
 
 
-def spmv_jds_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0):
+def spmv_jds_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0, wg_waves=0):
     Js, perm, jp, hptr, ndiag, col, val = _jds_row_split_args(R)
     _check_dev(x)
     y = _out_vec(y, R.n, x, beta)
     call("spmv_jds_row_split", R.n, _h_i64(R.bounds), perm, jp, hptr, _h_i32(ndiag), col, val,
          dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll,
-         max_iters, _stream())
+         max_iters, wg_waves, _stream())
     return y
 
 
@@ -661,13 +662,13 @@ def _blocked_row_split_args(R: RowSplit, C_: int):
 
 
 def spmv_jds_blocked_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, C_=64, rows_per_wave=0, unroll=0,
-                               max_iters=0):
+                               max_iters=0, wg_waves=0):
     Bs, perm, sptr, snd, hnd, col, val = _blocked_row_split_args(R, C_)
     _check_dev(x)
     y = _out_vec(y, R.n, x, beta)
     call("spmv_jds_blocked_row_split", R.n, C_, _h_i64(R.bounds), perm, sptr, snd, hnd, col, val,
          dtype_code(Bs[0].bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave,
-         unroll, max_iters, _stream())
+         unroll, max_iters, wg_waves, _stream())
     return y
 
 

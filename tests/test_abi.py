@@ -47,10 +47,10 @@ def test_host_side_validation_without_gpu():
     lib = _lib.load()
     st = lib.spmv_crs(-1, 0, None, None, None, 0, None, None, 0, 1.0, 0.0, None, 0, 0, None)
     assert st == 1 and b"negative" in lib.spmv_last_error()
-    st = lib.spmv_jds(10, None, None, None, 0, None, None, 0, None, None, 0, 1.0, 0.0, 3, 0, 0, None)
+    st = lib.spmv_jds(10, None, None, None, 0, None, None, 0, None, None, 0, 1.0, 0.0, 3, 0, 0, 0, None)
     assert st == 1 and b"unroll" in lib.spmv_last_error()
     st = lib.spmv_jds_blocked(10, None, 96, 1, None, None, None, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, 0,
-                              0, None)
+                              0, 0, None)
     assert st == 1 and b"multiple of 64" in lib.spmv_last_error()
     st = lib.spmv_crs(10, 10, None, None, None, 7, None, None, 0, 1.0, 0.0, None, 0, 0, None)
     assert st == 1 and b"dtype" in lib.spmv_last_error()
@@ -59,14 +59,18 @@ def test_host_side_validation_without_gpu():
     from paper_0910_4836_amd import spmv as spmv_mod
     for bad in ([0, 2, 1, 3, 4, 5, 6, 7, 10], [0, 1, 2, 3, 4, 5, 6, 7, 9]):
         b = np.array(bad, dtype=np.int64)
-        st = lib.spmv_jds_row_split(10, spmv_mod._h_i64(b), None, None, None, None, None, None, 0, None, None, 0, 1.0, 0.0,
-                                    0, 0, None)
+        st = lib.spmv_jds_row_split(10, spmv_mod._h_i64(b), None, None, None, None, None, None, 0, None, None, 0, 1.0,
+                                    0.0, 0, 0, 0, None)
         assert st == 1 and b"h_bounds" in lib.spmv_last_error()
         st = lib.spmv_jds_blocked_row_split(10, 64, spmv_mod._h_i64(b), None, None, None, None, None, None, 0, None, None,
-                                            0, 1.0, 0.0, 0, 0, 0, None)
+                                            0, 1.0, 0.0, 0, 0, 0, 0, None)
         assert st == 1 and b"h_bounds" in lib.spmv_last_error()
-    st = lib.spmv_jds_row_split(10, None, None, None, None, None, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, None)
+    st = lib.spmv_jds_row_split(10, None, None, None, None, None, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, 0,
+                                None)
     assert st == 1 and b"h_bounds" in lib.spmv_last_error()
+    # launch shape: 4, 8 or 16 wavefronts per workgroup
+    st = lib.spmv_jds(10, None, None, None, 0, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, 12, 0, None)
+    assert st == 1 and b"wg_waves" in lib.spmv_last_error()
 
 
 def test_product_path_does_not_use_the_oracle():

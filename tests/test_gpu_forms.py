@@ -239,10 +239,15 @@ def test_autotuner_batched_and_cache(tmp_path):
     xx = rng.uniform(-1, 1, n)
     xd = to_dev(xx)
     want, D = oracle.spmv_crs(R, xx), oracle.row_absdot(R, xx)
-    U, mi = tuner.tune_jds(J, xd)
-    assert max_err(sp.spmv_jds(J, xd, unroll=U, max_iters=mi), want, D) <= FP64_TOL
-    C_, R_, U2 = tuner.tune_blocked(J, xd)
+    U, mi, Wj = tuner.tune_jds(J, xd)
+    assert Wj in autotune.W_CANDIDATES
+    assert max_err(sp.spmv_jds(J, xd, unroll=U, max_iters=mi, wg_waves=Wj), want, D) <= FP64_TOL
+    C_, R_, U2, Wb = tuner.tune_blocked(J, xd)
     B = sp.jds_blocked_from_jds(J, C_)
-    assert max_err(sp.spmv_jds_blocked(B, xd, rows_per_wave=R_, unroll=U2), want, D) <= FP64_TOL
+    assert max_err(sp.spmv_jds_blocked(B, xd, rows_per_wave=R_, unroll=U2, wg_waves=Wb), want, D) <= FP64_TOL
+    bn = autotune.tune_crs(tuner, A, xd, J.ndiag)
+    assert bn in autotune.BLOCK_NNZ_CANDIDATES and A.block_nnz == bn
+    assert max_err(sp.spmv_crs(A, xd), want, D) <= FP64_TOL
     t3 = autotune.Autotuner(cache, cs=(64, 128), rs=(64, 16), us=(2, 4))
-    assert t3.tune_jds(J, xd) == (U, mi) and t3.tune_blocked(J, xd) == (C_, R_, U2) and not t3.log
+    assert t3.tune_jds(J, xd) == (U, mi, Wj) and t3.tune_blocked(J, xd) == (C_, R_, U2, Wb) and not t3.log
+    assert autotune.tune_crs(t3, A, xd, J.ndiag) == bn and not t3.log

@@ -79,17 +79,18 @@ def test_powerlaw_every_form_sampled(powerlaw):
     import tempfile
     from paper_0910_4836_amd import autotune
     tuner = autotune.Autotuner(cache_path=tempfile.mktemp(suffix=".json"))
-    ju, jm = tuner.tune_jds(J, xd)
-    bC, bR, bU = tuner.tune_blocked(J, xd)
+    ju, jm, jw = tuner.tune_jds(J, xd)
+    bC, bR, bU, bW = tuner.tune_blocked(J, xd)
     Bt = sp.jds_blocked_from_jds(J, bC)
     RS = sp.RowSplit(A)
     forms = {"crs": lambda: sp.spmv_crs(A, xd), "jds": lambda: sp.spmv_jds(J, xd),
              "blocked": lambda: sp.spmv_jds_blocked(B, xd), "crs_split": lambda: sp.spmv_crs_split(S, xd),
              "jds_split": lambda: sp.spmv_jds_split(S, xd), "blocked_split": lambda: sp.spmv_jds_blocked_split(S, xd),
-             "jds_tuned": lambda: sp.spmv_jds(J, xd, unroll=ju, max_iters=jm),
-             "blocked_tuned": lambda: sp.spmv_jds_blocked(Bt, xd, rows_per_wave=bR, unroll=bU),
-             "jds_row_split": lambda: sp.spmv_jds_row_split(RS, xd, unroll=ju, max_iters=jm),
-             "blocked_row_split": lambda: sp.spmv_jds_blocked_row_split(RS, xd, C_=bC, rows_per_wave=bR, unroll=bU)}
+             "jds_tuned": lambda: sp.spmv_jds(J, xd, unroll=ju, max_iters=jm, wg_waves=jw),
+             "blocked_tuned": lambda: sp.spmv_jds_blocked(Bt, xd, rows_per_wave=bR, unroll=bU, wg_waves=bW),
+             "jds_row_split": lambda: sp.spmv_jds_row_split(RS, xd, unroll=ju, max_iters=jm, wg_waves=jw),
+             "blocked_row_split": lambda: sp.spmv_jds_blocked_row_split(RS, xd, C_=bC, rows_per_wave=bR, unroll=bU,
+                                                                        wg_waves=bW)}
     for name, fn in forms.items():
         got = to_np(fn())[rows]
         e = oracle.rel_err(got, want, D).max()

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 sp = pytest.importorskip("paper_0910_4836_amd")
 
 
-def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_iters=(0,), split=True):
+def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_iters=(0,), split=True, waves=(0,)):
     """Yields (name, fn(x, y, alpha, beta)) for every kernel variant on matrix A."""
     yield "crs", lambda x, y, a, b: sp.spmv_crs(A, x, y, a, b)
     yield "crs_wave", lambda x, y, a, b: sp.spmv_crs(A, x, y, a, b, use_plan=False)
@@ -25,23 +25,29 @@ def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_
         yield f"crs_b{bn}", (lambda Ab=Ab: lambda x, y, a, b: sp.spmv_crs(Ab, x, y, a, b))()
     if split and not symperm:
         S = sp.Split(A)
+        w = waves[-1]
         yield "crs_split", lambda x, y, a, b: sp.spmv_crs_split(S, x, y, a, b)
-        yield "jds_split", lambda x, y, a, b: sp.spmv_jds_split(S, x, y, a, b)
-        yield "blocked_split", lambda x, y, a, b: sp.spmv_jds_blocked_split(S, x, y, a, b, C_=Cs[-1])
+        yield "jds_split", lambda x, y, a, b: sp.spmv_jds_split(S, x, y, a, b, wg_waves=w)
+        yield "blocked_split", lambda x, y, a, b: sp.spmv_jds_blocked_split(S, x, y, a, b, C_=Cs[-1], wg_waves=w)
         RS = sp.RowSplit(A)
-        yield "jds_row_split", lambda x, y, a, b: sp.spmv_jds_row_split(RS, x, y, a, b, max_iters=max_iters[-1])
+        yield "jds_row_split", lambda x, y, a, b: sp.spmv_jds_row_split(RS, x, y, a, b, max_iters=max_iters[-1],
+                                                                        wg_waves=w)
         yield "blocked_row_split", lambda x, y, a, b: sp.spmv_jds_blocked_row_split(
-            RS, x, y, a, b, C_=Cs[-1], rows_per_wave=rows_per_wave[-1], max_iters=max_iters[-1])
+            RS, x, y, a, b, C_=Cs[-1], rows_per_wave=rows_per_wave[-1], max_iters=max_iters[-1], wg_waves=w)
     J = sp.jds_from_csr(A, symperm=symperm)
     for u in unrolls:
         for mi in max_iters:
-            yield f"jds_u{u}_mi{mi}", (lambda J=J, u=u, mi=mi: lambda x, y, a, b: sp.spmv_jds(J, x, y, a, b, u, mi))()
+            for w in waves:
+                yield f"jds_u{u}_mi{mi}_w{w}", (lambda J=J, u=u, mi=mi, w=w:
+                                                lambda x, y, a, b: sp.spmv_jds(J, x, y, a, b, u, mi, w))()
     for C in Cs:
         B = sp.jds_blocked_from_jds(J, C)
         for R in rows_per_wave:
             for mi in max_iters:
-                yield f"blk_C{C}_R{R}_mi{mi}", (lambda B=B, R=R, mi=mi:
-                                                lambda x, y, a, b: sp.spmv_jds_blocked(B, x, y, a, b, R, 0, mi))()
+                for w in waves:
+                    yield f"blk_C{C}_R{R}_mi{mi}_w{w}", (lambda B=B, R=R, mi=mi, w=w:
+                                                         lambda x, y, a, b: sp.spmv_jds_blocked(B, x, y, a, b, R, 0,
+                                                                                                mi, w))()
 
 
 def run_case(r, c, v, nr, nc, x, y0=None, alpha=1.0, beta=0.0, exact=False, **kw):
@@ -86,7 +92,8 @@ def test_random_ragged_with_empty_and_long_rows(seed):
     r, c, v, nr, nc, rng = rand_coo(10 + seed, 9000 + 37 * seed, 7000, 0.0015, empty_rows=0.25, long_rows=40,
                                     long_len=3000)
     x = rng.uniform(-1, 1, nc)
-    run_case(r, c, v, nr, nc, x, unrolls=(2, 8), Cs=(64, 128), rows_per_wave=(0, 16, 64), max_iters=(0, 4))
+    run_case(r, c, v, nr, nc, x, unrolls=(2, 8), Cs=(64, 128), rows_per_wave=(0, 16, 64), max_iters=(0, 4),
+             waves=(0, 4, 8))
 
 
 def test_alpha_beta_accumulate():
@@ -104,7 +111,7 @@ def test_integer_bit_exact(seed):
     x = synth.integer_vector(nc, rng)
     y0 = synth.integer_vector(nr, rng)
     run_case(r, c, v, nr, nc, x, exact=True, unrolls=(2, 4, 8), Cs=(64, 256), rows_per_wave=(0, 8, 32),
-             max_iters=(0, 2))
+             max_iters=(0, 2), waves=(0, 4))
     run_case(r, c, v, nr, nc, x, y0, alpha=1.0, beta=1.0, exact=True)     # the paper's accumulate form
 
 
