@@ -26,7 +26,7 @@ from . import spmv as S
 
 
 class SpMVOperator:
-    def __init__(self, A: S.CSR, unroll: int = 0, max_iters: int = 0, transpose: str = "crs"):
+    def __init__(self, A: S.CSR, unroll: int = 0, max_iters: int = 0, transpose: str = "crs", wg_waves: int = 0):
         if A.n_rows != A.n_cols:
             raise ValueError("the operator must be square")
         if transpose not in ("crs", "jds"):
@@ -34,7 +34,7 @@ class SpMVOperator:
         dev = A.device
         self.n = A.n_rows
         self.nnz = A.nnz
-        self.unroll, self.max_iters = unroll, max_iters
+        self.unroll, self.max_iters, self.wg_waves = unroll, max_iters, wg_waves
         self.transpose = transpose
         # JDS of A, and of A with the CRS position of every entry as payload
         self.J = S.jds_from_csr(A)
@@ -74,13 +74,13 @@ class SpMVOperator:
 
     # y = alpha*A x + beta*y
     def matvec(self, vals, x, y=None, alpha=1.0, beta=0.0):
-        return S.spmv_jds(self.J.with_values(vals), x, y, alpha, beta, self.unroll, self.max_iters)
+        return S.spmv_jds(self.J.with_values(vals), x, y, alpha, beta, self.unroll, self.max_iters, self.wg_waves)
 
     def rmatvec(self, vals, g, y=None, alpha=1.0, beta=0.0):
         vT = self.transposed_values(vals)
         if self.AT is not None:
             return S.spmv_crs(self.AT.with_values(vT), g, y, alpha, beta)
-        return S.spmv_jds(self.JT.with_values(vT), g, y, alpha, beta, self.unroll, self.max_iters)
+        return S.spmv_jds(self.JT.with_values(vT), g, y, alpha, beta, self.unroll, self.max_iters, self.wg_waves)
 
     def grad_vals(self, g, x, out=None, alpha=1.0, beta=0.0):
         return S.spmv_grad_vals_jds(self.J, g, x, out, alpha, beta)

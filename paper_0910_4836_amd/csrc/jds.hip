@@ -13,8 +13,9 @@
 // so the host splits the rows into classes by length: a class has R rows per
 // wavefront (64/R lanes share a row and stride over its diagonals) and S
 // wavefronts per row group (each takes a contiguous range of diagonals; the S
-// partial sums meet in LDS and are added in a fixed order).  Every y element is
-// written by one lane; no atomics.
+// partial sums meet in LDS and are added in a fixed order).  A workgroup holds
+// 4, 8 or 16 wavefronts (launch parameter).  Every y element is written by one
+// lane; no atomics.
 //
 // The same kernel runs on both storages:
 //   JDS:     entry (d, r) at jd_ptr[d] + r, diagonal d reaches rows r < len_d
