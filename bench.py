@@ -146,7 +146,9 @@ KERNEL_SOURCES = {"crs": ("common.hpp", "crs.hip"), "jds": ("common.hpp", "jds.h
 
 def kernel_sources(kernel):
     """Sources a product's kernels are compiled from (the split forms add the
-    combine kernel in util.hip)."""
+    combine kernel in util.hip; the probes live in util.hip)."""
+    if kernel.startswith("gather_"):
+        return ("common.hpp", "util.hip")
     fam = kernel.split("_")[0]
     files = KERNEL_SOURCES[fam]
     return files + ("util.hip",) if "_split" in kernel else files
@@ -340,6 +342,10 @@ def gather_rates(torch, sp, dev, n_idx=1 << 24):
         idx = torch.randint(0, nx, (n_idx,), generator=g, device=dev, dtype=torch.int32)
         ms, _ = time_loop(torch, [(label, lambda: sp.spmv_gather_probe(idx, x, part))], 20, 3)
         out[label + "_Ggathers_s"] = round(n_idx / (ms * 1e-3) / 1e9, 1)
+        # the line fills behind those gathers (rocprofv3 FETCH_SIZE of the probe), as a rate
+        fill = measured_traffic("gather_" + label, "probe")
+        if fill:
+            out[label + "_fill_GBs"] = round(fill / (ms * 1e-3) / 1e9, 1)
         del x, idx
     return out
 
@@ -611,11 +617,21 @@ def main():
     # the unsplit forms; one XCD's L2 holds each 2 MB slice of the split forms)
     rates = gather_rates(torch, sp, dev)
     nnz = W["nnz"]
+
+    def gather_entry(name, ms):
+        e = {"achieved_Ggathers_s": round(nnz / (ms * 1e-3) / 1e9, 1),
+             "frac_of_mall_rate": round(nnz / (ms * 1e-3) / 1e9 / rates["x_16MB_MALL_Ggathers_s"], 3),
+             "frac_of_l2_rate": round(nnz / (ms * 1e-3) / 1e9 / rates["x_2MB_L2_Ggathers_s"], 3)}
+        # HBM-side (L2 fill) traffic per second against what the MALL gather probe draws
+        t = measured_traffic(name, "powerlaw")
+        probe_fill = rates.get("x_16MB_MALL_fill_GBs")
+        if t and probe_fill:
+            e["fill_GBs"] = round(t / (ms * 1e-3) / 1e9, 1)
+            e["frac_of_mall_probe_fill"] = round(e["fill_GBs"] / probe_fill, 3)
+        return e
     out["gather_bound"] = {
         "gathers_per_launch": nnz, "probe": rates,
-        "kernels": {name: {"achieved_Ggathers_s": round(nnz / (ms * 1e-3) / 1e9, 1),
-                           "frac_of_mall_rate": round(nnz / (ms * 1e-3) / 1e9 / rates["x_16MB_MALL_Ggathers_s"], 3),
-                           "frac_of_l2_rate": round(nnz / (ms * 1e-3) / 1e9 / rates["x_2MB_L2_Ggathers_s"], 3)}
+        "kernels": {name: gather_entry(name, ms)
                     for name, ms in dict(per, **(per_s if split else {}), **(per_r if rsplit else {})).items()
                     if name.endswith("_f64")}}
     print(json.dumps(out), flush=True)
