@@ -197,10 +197,12 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
  * lane owns one permuted row and walks the jagged diagonals that reach it,
  * `unroll` diagonals at a time (2, 4 or 8; 0 = default).  Rows whose length
  * exceeds `max_iters` diagonals (0 = default) have their diagonals split over
- * up to wg_waves wavefronts whose partial sums are added in a fixed order.
- * wg_waves: wavefronts per workgroup, 4, 8 or 16 (0 = 16); a launch-shape
- * choice only (small workgroups keep more gathers in flight for short,
- * irregular rows; large ones stream uniform rows better).
+ * up to W wavefronts whose partial sums are added in a fixed order, W =
+ * wg_waves, the wavefronts per workgroup: 4, 8 or 16 (0 = 16).  unroll,
+ * max_iters and wg_waves shape the launch only (small workgroups keep more
+ * gathers in flight for short, irregular rows; large ones stream uniform
+ * rows better); the result is the same up to the summation order of long
+ * rows.
  * Without SPMV_SYMPERM, x is in the original basis and y[perm[r]] receives
  * row r; with it, x and y are both in the permuted basis.
  * h_jd_ptr: host copy of jd_ptr (ndiag+1 entries). */
@@ -333,7 +335,8 @@ spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_pt
  * h_perm[k][r] = dest_all[h_row_off[k] + perm_k[r]] is the slot of permuted
  * row r.  Host arrays of SPMV_SPLIT_PARTS device pointers (h_perm, h_jd_ptr,
  * h_jd_col, h_jd_val), of host pointers (h_jd_ptr_host) and of sizes
- * (h_ndiag). */
+ * (h_ndiag).  unroll, max_iters and wg_waves as for spmv_jds (one value for
+ * every part). */
 spmv_status spmv_jds_split(int32_t n, const int32_t *slot_ptr, const int64_t *h_row_off, const int32_t *const *h_perm,
                            const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host, const int32_t *h_ndiag,
                            const int32_t *const *h_jd_col, const void *const *h_jd_val, spmv_dtype val_dt,
@@ -377,7 +380,8 @@ spmv_status spmv_split_rows(int32_t n_rows, int64_t nnz, const int32_t *row_ptr,
  * its perm holds row numbers local to the part, and permuted row r of part k
  * writes y[h_bounds[k] + h_perm[k][r]].  Host arrays of SPMV_SPLIT_PARTS
  * device pointers (h_perm, h_jd_ptr, h_jd_col, h_jd_val), of host pointers
- * (h_jd_ptr_host) and of sizes (h_ndiag).  x is in the original basis. */
+ * (h_jd_ptr_host) and of sizes (h_ndiag).  x is in the original basis.
+ * unroll, max_iters and wg_waves as for spmv_jds (one value for every part). */
 spmv_status spmv_jds_row_split(int32_t n, const int64_t *h_bounds, const int32_t *const *h_perm,
                                const int32_t *const *h_jd_ptr, const int32_t *const *h_jd_ptr_host,
                                const int32_t *h_ndiag, const int32_t *const *h_jd_col, const void *const *h_jd_val,
