@@ -207,6 +207,34 @@ def tune_crs(tuner: "Autotuner", A: S.CSR, x: torch.Tensor, longest: int,
     return ent["block_nnz"]
 
 
+def tune_spmm_crs(tuner: "Autotuner", A: S.CSR, k: int, dtype: torch.dtype, longest: int,
+                  candidates=(256, 512, 1024)) -> S.CSR:
+    """The CRS plan (entries per block) for k-vector products with A: returns a
+    copy of A's structure carrying the best plan for spmm_crs (A's own plan,
+    used by the single-vector product, is left alone)."""
+    sig = f"spmm_crs:k{k}:{str(dtype).replace('torch.', '')}:" + signature(A.n_rows, longest, A.nnz)
+    ent = tuner.cache.get(_device_key(), {}).get(sig)
+    plans = {}
+    if ent is None:
+        X = S.colmajor(A.n_cols, k, dtype, A.device)
+        X.copy_(torch.rand(A.n_cols, k, dtype=dtype, device=A.device))
+        Y = S.colmajor(A.n_rows, k, dtype, A.device)
+        ws = S.spmm_workspace(A.n_cols, k, dtype, A.device)
+        timings = {}
+        for bn in candidates:
+            Ab = S.spmv_crs_plan(S.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
+            plans[bn] = Ab
+            timings[bn] = _time(lambda: S.spmm_crs(Ab, X, Y, ws=ws), reps=5, warm=1)
+        best = min(timings, key=timings.get)
+        tuner.log.append({"signature": sig, "timings_ms": {f"block{b}": round(t, 5) for b, t in timings.items()}})
+        ent = {"block_nnz": best, "ms": round(timings[best], 5)}
+        tuner.cache.setdefault(_device_key(), {})[sig] = ent
+        _store(tuner.cache_path, tuner.cache)
+        del X, Y, ws
+    bn = ent["block_nnz"]
+    return plans.get(bn) or S.spmv_crs_plan(S.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
+
+
 def build_batched(jds_list: Sequence[S.JDS], tuner: Autotuner = None, n_workgroups: int = 0) -> S.Batched:
     """Blocked layouts and the persistent plan for many matrices, with the
     slice height / rows per wavefront / unroll the autotuner picks."""

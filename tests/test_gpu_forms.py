@@ -251,3 +251,14 @@ def test_autotuner_batched_and_cache(tmp_path):
     t3 = autotune.Autotuner(cache, cs=(64, 128), rs=(64, 16), us=(2, 4))
     assert t3.tune_jds(J, xd) == (U, mi, Wj) and t3.tune_blocked(J, xd) == (C_, R_, U2, Wb) and not t3.log
     assert autotune.tune_crs(t3, A, xd, J.ndiag) == bn and not t3.log
+    # multi-vector CRS plan: its own copy of the structure, A's plan untouched
+    Am = autotune.tune_spmm_crs(tuner, A, 8, torch.float64, J.ndiag)
+    assert Am.block_nnz in (256, 512, 1024) and A.block_nnz == bn and Am.plan is not A.plan
+    X = rng.uniform(-1, 1, (n, 8))
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda").t()
+    Y = to_np(sp.spmm_crs(Am, Xd))
+    want_X = oracle.spmm_crs(R, X)
+    for j in range(8):
+        assert oracle.rel_err(Y[:, j], want_X[:, j], oracle.row_absdot(R, X[:, j])).max() <= FP64_TOL
+    t4 = autotune.Autotuner(cache)
+    assert autotune.tune_spmm_crs(t4, A, 8, torch.float64, J.ndiag).block_nnz == Am.block_nnz and not t4.log

@@ -131,6 +131,11 @@ def test_symperm_mode():
     B = sp.jds_blocked_from_jds(J, 128)
     yb = sp.spmv_jds_blocked(B, xp)
     assert max_err(yb, want[perm], D[perm]) <= FP64_TOL
+    for w in (4, 8):
+        yw = sp.spmv_jds(J, xp, max_iters=4, wg_waves=w)
+        assert max_err(yw, want[perm], D[perm]) <= FP64_TOL
+        yw = sp.spmv_jds_blocked(B, xp, rows_per_wave=16, max_iters=4, wg_waves=w)
+        assert max_err(yw, want[perm], D[perm]) <= FP64_TOL
 
 
 def test_empty_matrix_and_single_row():
