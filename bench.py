@@ -400,6 +400,7 @@ def suite_symdiag(torch, sp, dev, steps):
     x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(3, 1))).to(dev)
     from paper_0910_4836_amd import autotune
     tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    crs_bn = autotune.tune_crs(tuner, A, x, J.ndiag)
     ju, jm, jw = tuner.tune_jds(J, x)
     bC, bR, bU, bW = tuner.tune_blocked(J, x)
     B = sp.jds_blocked_from_jds(J, bC)
@@ -407,7 +408,8 @@ def suite_symdiag(torch, sp, dev, steps):
     y_ref = sp.spmv_crs(A, x)
     out = {"workload": f"symmetric 12 secondary diagonals + diagonal, n={n}, nnz={nnz}", "kernels": {},
            "max_rel_err_vs_fp64": {},
-           "autotuned": {"jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw, "blocked_C": bC,
+           "autotuned": {"crs_block_nnz": crs_bn, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw,
+                         "blocked_C": bC,
                          "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW}}
     y = torch.empty(n, dtype=torch.float64, device=dev)
     for vdt, sv, tag in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32val"), (torch.bfloat16, 2, "bf16val")):
