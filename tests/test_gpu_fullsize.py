@@ -83,9 +83,12 @@ def test_powerlaw_every_form_sampled(powerlaw):
     bC, bR, bU, bW = tuner.tune_blocked(J, xd)
     Bt = sp.jds_blocked_from_jds(J, bC)
     RS = sp.RowSplit(A)
+    At = sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val)
+    autotune.tune_crs(tuner, At, xd, J.ndiag)
     forms = {"crs": lambda: sp.spmv_crs(A, xd), "jds": lambda: sp.spmv_jds(J, xd),
              "blocked": lambda: sp.spmv_jds_blocked(B, xd), "crs_split": lambda: sp.spmv_crs_split(S, xd),
              "jds_split": lambda: sp.spmv_jds_split(S, xd), "blocked_split": lambda: sp.spmv_jds_blocked_split(S, xd),
+             "crs_tuned": lambda: sp.spmv_crs(At, xd),
              "jds_tuned": lambda: sp.spmv_jds(J, xd, unroll=ju, max_iters=jm, wg_waves=jw),
              "blocked_tuned": lambda: sp.spmv_jds_blocked(Bt, xd, rows_per_wave=bR, unroll=bU, wg_waves=bW),
              "jds_row_split": lambda: sp.spmv_jds_row_split(RS, xd, unroll=ju, max_iters=jm, wg_waves=jw),
@@ -136,10 +139,13 @@ def test_powerlaw_multi_vector_sampled(powerlaw):
     rows = pick(n, 13)
     sub = coo_rows(n, r, c, v, rows)
     J = sp.jds_from_csr(A)
+    # the plan bench.py times for the multi-vector CRS product (256-entry blocks)
+    A256 = sp.spmv_crs_plan(sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), 256)
     for k in (8, 32):
         X = np.random.default_rng(k).uniform(-1, 1, (n, k))
         Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda").t()
-        for name, fn in (("crs", lambda: sp.spmm_crs(A, Xd)), ("jds", lambda: sp.spmm_jds(J, Xd))):
+        for name, fn in (("crs", lambda: sp.spmm_crs(A, Xd)), ("crs_b256", lambda: sp.spmm_crs(A256, Xd)),
+                         ("jds", lambda: sp.spmm_jds(J, Xd))):
             Y = to_np(fn())
             for j in (0, k // 2, k - 1):
                 want = oracle.spmv_crs(sub, X[:, j])
@@ -160,10 +166,21 @@ def test_symmetric_diagonals_sampled():
     J = sp.jds_from_csr(A)
     B = sp.jds_blocked_from_jds(J, 64)
     xd = to_dev(x)
+    # plus the launch configurations the autotuner picks for this matrix
+    import tempfile
+    from paper_0910_4836_amd import autotune
+    tuner = autotune.Autotuner(cache_path=tempfile.mktemp(suffix=".json"))
+    ju, jm, jw = tuner.tune_jds(J, xd)
+    bC, bR, bU, bW = tuner.tune_blocked(J, xd)
+    Bt = sp.jds_blocked_from_jds(J, bC)
     for name, fn in (("crs", lambda: sp.spmv_crs(A, xd)), ("jds", lambda: sp.spmv_jds(J, xd)),
-                     ("blocked", lambda: sp.spmv_jds_blocked(B, xd))):
+                     ("blocked", lambda: sp.spmv_jds_blocked(B, xd)),
+                     ("jds_tuned", lambda: sp.spmv_jds(J, xd, unroll=ju, max_iters=jm, wg_waves=jw)),
+                     ("blocked_tuned", lambda: sp.spmv_jds_blocked(Bt, xd, rows_per_wave=bR, unroll=bU,
+                                                                   wg_waves=bW))):
         e = oracle.rel_err(to_np(fn())[rows], want, D).max()
         assert e <= FP64_TOL, f"{name}: {e:.3e}"
+    del Bt
     # reduced-precision values on the same rows
     for vdt in (torch.float32, torch.bfloat16):
         if vdt == torch.float32:
