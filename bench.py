@@ -539,9 +539,33 @@ def suite_chebyshev(torch, sp, dev, steps):
             "spmv_equivalents_per_gradient": "20 forward + 15 recomputed + 20 transposed products + 20 value gradients"}
 
 
+def suite_orderings(torch, sp, dev, W, steps):
+    """Blocked JDS of the power-law matrix in the slice order (RBJDS) and with
+    the SOJDS re-assignment, same tuned launch parameters."""
+    n, nnz = W["n"], W["nnz"]
+    T = W["tune"]
+    bC, bR, bU, bW = T["blocked_C"], T["blocked_rows_per_wave"], T["blocked_unroll"], T["blocked_wg_waves"]
+    t0 = time.perf_counter()
+    Bs = sp.jds_blocked_from_jds(W["J"], bC, sojds=True)
+    torch.cuda.synchronize()
+    build_ms = round((time.perf_counter() - t0) * 1e3, 1)
+    x = W["x"]
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    ks = [("rbjds_f64", lambda: sp.spmv_jds_blocked(W["B"], x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW)),
+          ("sojds_f64", lambda: sp.spmv_jds_blocked(Bs, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW))]
+    _, per = time_loop(torch, ks, max(10, steps // 4), 3)
+    out = {"workload": f"power-law n={n} nnz={nnz}: blocked JDS (C={bC}) in slice order vs SOJDS order, FP64",
+           "kernels": {name: _kernel_entry(name, 2.0 * nnz, bytes_blocked(nnz, n, n, Bs.n_slices, 8, 8), per[name])
+                       for name, _ in ks},
+           "sojds_build_ms": build_ms}
+    del Bs
+    return out
+
+
 def suite_lines(torch, sp, dev, W, steps, warmup):
     lines = []
     for name, fn in (("laplacian", lambda: suite_laplacian(torch, sp, dev, steps)),
+                     ("orderings", lambda: suite_orderings(torch, sp, dev, W, steps)),
                      ("multi-vector", lambda: suite_spmm(torch, sp, dev, W, steps)),
                      ("symmetric-diagonals", lambda: suite_symdiag(torch, sp, dev, steps)),
                      ("chebyshev", lambda: suite_chebyshev(torch, sp, dev, steps)),

@@ -522,6 +522,39 @@ __global__ void blocked_fill_kernel(const int32_t *__restrict__ jp, int32_t ndia
 // (first row keeps CRS order; later rows take, slot by slot, the unused entry
 // whose column is nearest to the previous row's column in that slot plus one,
 // the smaller column on a tie).  `taken` holds one bit per entry of a row.
+// A row whose columns strictly increase (CRS order of a matrix built by
+// spmv_csr_from_coo) finds that entry in O(log L) loads: a binary search for
+// the target column, then the nearest clear bit of `taken` on either side;
+// any other row compares all of its unused entries.
+
+// first clear bit at index >= from, or -1 if none below len
+__device__ __forceinline__ int32_t next_clear(const uint32_t *taken, int32_t from, int32_t len)
+{
+    if (from >= len) return -1;
+    int32_t w = from >> 5;
+    uint32_t m = ~taken[w] & (0xffffffffu << (from & 31));
+    const int32_t last = (len - 1) >> 5;
+    while (m == 0) {
+        if (++w > last) return -1;
+        m = ~taken[w];
+    }
+    const int32_t e = (w << 5) + __ffs(m) - 1;
+    return e < len ? e : -1;
+}
+
+// last clear bit at index < below, or -1 if none
+__device__ __forceinline__ int32_t prev_clear(const uint32_t *taken, int32_t below)
+{
+    if (below <= 0) return -1;
+    int32_t w = (below - 1) >> 5;
+    uint32_t m = ~taken[w] & (0xffffffffu >> (31 - ((below - 1) & 31)));
+    while (m == 0) {
+        if (--w < 0) return -1;
+        m = ~taken[w];
+    }
+    return (w << 5) + 31 - __clz(m);
+}
+
 template <typename T>
 __global__ void sojds_kernel(const int32_t *__restrict__ jp, int32_t ndiag, const int32_t *__restrict__ jd_col,
                              const T *__restrict__ jd_val, int32_t n, int32_t C, const int64_t *__restrict__ slice_ptr,
@@ -537,18 +570,34 @@ __global__ void sojds_kernel(const int32_t *__restrict__ jp, int32_t ndiag, cons
             if (r >= n) break;
             const int32_t len = jds_len_of(jp, ndiag, r);
             for (int32_t q = 0; q < (len + 31) / 32; ++q) taken[q] = 0;
+            auto col_of = [&](int32_t e) -> int64_t { return jd_col[jp[e] + r]; };
+            bool sorted = true;
+            for (int32_t e = 1; e < len && sorted; ++e) sorted = col_of(e) > col_of(e - 1);
             for (int32_t d = 0; d < len; ++d) {
                 const int64_t want = (int64_t)bl_col[sp + (int64_t)d * C + rl - 1] + 1;
                 int32_t pick = -1;
-                int64_t best = 0, bestc = 0;
-                for (int32_t e = 0; e < len; ++e) {
-                    if (taken[e >> 5] & (1u << (e & 31))) continue;
-                    const int64_t c = jd_col[jp[e] + r];
-                    const int64_t dist = c > want ? c - want : want - c;
-                    if (pick < 0 || dist < best || (dist == best && c < bestc)) {
-                        pick = e;
-                        best = dist;
-                        bestc = c;
+                if (sorted) {
+                    int32_t lo = 0, hi = len;                  // first entry with column >= want
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        if (col_of(mid) < want) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    const int32_t right = next_clear(taken, lo, len), left = prev_clear(taken, lo);
+                    if (left < 0) pick = right;
+                    else if (right < 0) pick = left;
+                    else pick = (col_of(right) - want < want - col_of(left)) ? right : left;   // tie: smaller column
+                } else {
+                    int64_t best = 0, bestc = 0;
+                    for (int32_t e = 0; e < len; ++e) {
+                        if (taken[e >> 5] & (1u << (e & 31))) continue;
+                        const int64_t c = col_of(e);
+                        const int64_t dist = c > want ? c - want : want - c;
+                        if (pick < 0 || dist < best || (dist == best && c < bestc)) {
+                            pick = e;
+                            best = dist;
+                            bestc = c;
+                        }
                     }
                 }
                 taken[pick >> 5] |= 1u << (pick & 31);

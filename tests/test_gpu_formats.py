@@ -100,6 +100,28 @@ def test_blocked_from_jds_bit_exact(C, sojds):
     assert np.array_equal(to_np(B.bl_val), Rb.bl_val)
 
 
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_sojds_long_and_unsorted_rows_bit_exact(shuffle):
+    """SOJDS on rows of up to 2,500 entries (the logarithmic search of sorted
+    rows) and, with `shuffle`, on a CRS whose rows are not in column order
+    (the direct search): bit-exact against the oracle's greedy rule."""
+    r, c, v, nr, nc, rng = rand_coo(8, 1500, 4000, 0.004, empty_rows=0.1, long_rows=40, long_len=2500)
+    Rc = oracle.csr_from_coo(nr, nc, r, c, v)
+    if shuffle:
+        col, val = Rc.col.copy(), Rc.val.copy()
+        for i in rng.choice(nr, nr // 3, replace=False):
+            a, b = Rc.row_ptr[i], Rc.row_ptr[i + 1]
+            p = rng.permutation(b - a)
+            col[a:b], val[a:b] = col[a:b][p], val[a:b][p]
+        Rc = oracle.CSR(nr, nc, Rc.row_ptr, col, val)
+    A = sp.CSR(nr, nc, to_dev(Rc.row_ptr), to_dev(Rc.col), to_dev(Rc.val))
+    for C in (64, 256):
+        Rb = oracle.blocked_from_jds(oracle.jds_from_csr(Rc), C, sojds=True)
+        B = sp.jds_blocked_from_jds(sp.jds_from_csr(A), C, sojds=True)
+        assert np.array_equal(to_np(B.bl_col), Rb.bl_col), C
+        assert np.array_equal(to_np(B.bl_val), Rb.bl_val), C
+
+
 def test_transpose_bit_exact():
     r, c, v, nr, nc, _ = rand_coo(7, 2000, 1500, 0.004, empty_rows=0.1)
     Rc = oracle.csr_from_coo(nr, nc, r, c, v)
