@@ -581,8 +581,8 @@ def suite_lines(torch, sp, dev, W, steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU row partition is "
-              "a design in DESIGN.md, not a measured path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); a row partition over several GPUs is "
+              "a design, not a built or measured path", file=sys.stderr)
         sys.exit(2)
     if args.probe:
         run_probe(args.probe)
