@@ -109,9 +109,13 @@ class Timer:
     def avg_ms(self, name):
         return float(np.mean([a.elapsed_time(b) for a, b in self.pairs[name]]))
 
+    def median_ms(self, name):
+        return float(np.median([a.elapsed_time(b) for a, b in self.pairs[name]]))
 
-def time_loop(torch, kernels, steps, warmup):
-    """kernels: list of (name, fn).  Returns (ms_per_step, {name: avg ms}).
+
+def time_loop(torch, kernels, steps, warmup, medians=None):
+    """kernels: list of (name, fn).  Returns (ms_per_step, {name: avg ms});
+    `medians`, if given, receives {name: median ms}.
 
     Python's cyclic garbage collector is paused over the timed steps: one of
     its passes can hold the launching thread for tens of milliseconds, which
@@ -137,7 +141,39 @@ def time_loop(torch, kernels, steps, warmup):
     finally:
         gc.enable()
     total = start.elapsed_time(end)
+    if medians is not None:
+        medians.update({name: timer.median_ms(name) for name, _ in kernels})
     return total / steps, {name: timer.avg_ms(name) for name, _ in kernels}
+
+
+def cold_times(torch, sp, dev, kernels, reps=20):
+    """Each product timed alone right after a streaming copy of 512 MiB into
+    another 512 MiB buffer (twice the 256 MB MALL, far beyond the L2s), so it
+    starts with none of its arrays in cache; median over `reps` launches."""
+    n = 1 << 26
+    a = torch.empty(n, dtype=torch.float64, device=dev)
+    b = torch.zeros(n, dtype=torch.float64, device=dev)
+    out = {}
+    gc.collect()
+    gc.disable()
+    try:
+        for name, fn in kernels:
+            fn()
+            pairs = []
+            for _ in range(reps):
+                sp.spmv_stream_copy(a, b)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                pairs.append((e0, e1))
+            torch.cuda.synchronize()
+            out[name] = float(np.median([e0.elapsed_time(e1) for e0, e1 in pairs]))
+    finally:
+        gc.enable()
+    del a, b
+    return out
 
 
 KERNEL_SOURCES = {"crs": ("common.hpp", "crs.hip"), "jds": ("common.hpp", "jds.hip"),
@@ -562,10 +598,57 @@ def suite_orderings(torch, sp, dev, W, steps):
     return out
 
 
+def _lines_per_wave(cols, chunk, line_elems):
+    """Distinct x lines (of line_elems elements) per 64-lane gather, for entries
+    grouped into wavefront gathers by `chunk`; padding (col < 0) left out."""
+    ok = cols >= 0
+    cols, chunk = cols[ok].astype(np.int64), chunk[ok].astype(np.int64)
+    lines = cols // line_elems
+    m = int(lines.max(initial=0)) + 1
+    _, per_chunk = np.unique(np.unique(chunk * m + lines) // m, return_counts=True)
+    return {"mean": round(float(per_chunk.mean()), 2), "median": float(np.median(per_chunk)),
+            "frac_ge_32": round(float((per_chunk >= 32).mean()), 3)}
+
+
+def suite_gather_model(torch, sp, W):
+    """Host model of the x accesses (the GPU analogue of the paper's stride
+    analysis, Section 4.2): how many distinct 128-byte lines of x one 64-lane
+    gather instruction touches in each format's access order, from the
+    library's own arrays.  CRS: 64 consecutive entries of the stream; JDS: 64
+    consecutive permuted rows of one diagonal; blocked: 64 rows of one slice
+    diagonal."""
+    n, nnz = W["n"], W["nnz"]
+    le = 128 // 8
+    A, J, B = W["A"], W["J"], W["B"]
+    col = A.col_idx.cpu().numpy()
+    out = {"workload": f"power-law n={n} nnz={nnz}: distinct 128-byte x lines per 64-lane gather (FP64 x)",
+           "lines_per_wave": {"crs": _lines_per_wave(col, np.arange(len(col)) // 64, le)}}
+    jc = J.jd_col.cpu().numpy()
+    idx = np.arange(len(jc), dtype=np.int64)
+    d = np.searchsorted(J.h_jd_ptr, idx, side="right") - 1
+    r = idx - J.h_jd_ptr[d]
+    out["lines_per_wave"]["jds"] = _lines_per_wave(jc, d * (n // 64 + 1) + r // 64, le)
+    del jc, idx, d, r
+    bc = B.bl_col.cpu().numpy()
+    out["lines_per_wave"][f"blocked_C{B.C}"] = _lines_per_wave(bc, np.arange(len(bc)) // 64, le)
+    del bc
+    # every line a miss: bytes of x fetched per stored entry, against the measured HBM-side bytes
+    out["x_bytes_per_entry_if_every_line_misses"] = {k: round(v["mean"] * 128 / 64, 1)
+                                                     for k, v in out["lines_per_wave"].items()}
+    meas = {}
+    for name in ("crs_f64", "jds_f64", "blocked_f64"):
+        t = measured_traffic(name, "powerlaw")
+        if t:
+            meas[name] = round(t / nnz, 1)
+    out["measured_hbm_bytes_per_entry"] = meas
+    return out
+
+
 def suite_lines(torch, sp, dev, W, steps, warmup):
     lines = []
     for name, fn in (("laplacian", lambda: suite_laplacian(torch, sp, dev, steps)),
                      ("orderings", lambda: suite_orderings(torch, sp, dev, W, steps)),
+                     ("gather-model", lambda: suite_gather_model(torch, sp, W)),
                      ("multi-vector", lambda: suite_spmm(torch, sp, dev, W, steps)),
                      ("symmetric-diagonals", lambda: suite_symdiag(torch, sp, dev, steps)),
                      ("chebyshev", lambda: suite_chebyshev(torch, sp, dev, steps)),
@@ -606,7 +689,8 @@ def main():
         mixed = []
         split = []
         rsplit = []
-    ms_step, per = time_loop(torch, ks, args.steps, args.warmup)
+    med = {}
+    ms_step, per = time_loop(torch, ks, args.steps, args.warmup, med)
     flops_step = 2.0 * W["nnz"] * len(ks)
     value = flops_step / (ms_step * 1e-3) / 1e9
     dom = max(per, key=per.get)
@@ -615,7 +699,7 @@ def main():
         return {"avg_ms": round(ms, 5), "gflops": round(2.0 * W["nnz"] / (ms * 1e-3) / 1e9, 1),
                 "algorithmic_GBs": round(bmin[name] / (ms * 1e-3) / 1e9, 1),
                 "frac_of_8TBs": round(bmin[name] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    kernels = {name: entry(name, per[name]) for name, _ in ks}
+    kernels = {name: dict(entry(name, per[name]), median_ms=round(med[name], 5)) for name, _ in ks}
     out = {
         "metric": "SpMV GFLOP/s + % of HBM code-balance roofline, CRS vs JDS, FP64 vs mixed",
         "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -653,6 +737,10 @@ def main():
         out["cpu_baseline"] = cpu_baseline(W)
     else:
         out["cpu_baseline"] = None
+    # the step's products from cold caches (MALL and L2 flushed before each launch)
+    cold = cold_times(torch, sp, dev, ks)
+    out["cold"] = {name: {"median_ms": round(ms, 5), "gflops": round(2.0 * W["nnz"] / (ms * 1e-3) / 1e9, 1),
+                          "slowdown_vs_warm_median": round(ms / med[name], 3)} for name, ms in cold.items()}
     out["attainable_hbm"] = attainable_bw(torch, sp, dev)
     # every stored entry gathers one x element: the products are bound by the
     # random-gather rate of the level that holds x (16 MB here: the MALL for
