@@ -397,6 +397,44 @@ spmv_status spmv_jds_blocked_row_split(int32_t n, int32_t C, const int64_t *h_bo
                                        int32_t unroll, int32_t max_iters, int32_t wg_waves, void *stream);
 
 /* ======================================================================== */
+/* DIA + CRS hybrid                                                          */
+/* ======================================================================== */
+/* The paper (Section 4.2) notes that the outer secondary diagonals of its
+ * Hamiltonian hold most of the entries and could be stored densely.  Here a
+ * diagonal (offset o = col - row) is stored densely when that costs no more
+ * bytes than its entries in CRS: count_o * (s_v + 4) >= span_o * s_v, with
+ * span_o the rows the diagonal crosses; at most max_diags of them (0 =
+ * SPMV_DIA_MAX), the fullest first (ties: smaller offset).  Stored diagonals
+ * are in ascending offset order; diagonal k holds dia_val[k*n_rows + i] =
+ * a(i, i + offsets[k]) for every row i (0 where the matrix has no entry or
+ * the column falls outside the matrix).  The other entries form the
+ * remainder CRS (rem_row_ptr[n_rows+1], rem_col, rem_val: each row's
+ * entries in CRS order).
+ * spmv_dia_from_csr (setup, synchronises): with dia_val == NULL it only
+ * returns *h_ndia, h_offsets[0..*h_ndia) and *h_rem_nnz; otherwise it also
+ * fills dia_val (*h_ndia * n_rows values of dt), rem_row_ptr, rem_col and
+ * rem_val (*h_rem_nnz entries).  ws: spmv_dia_workspace_size(n_rows, n_cols). */
+#define SPMV_DIA_MAX 64
+size_t spmv_dia_workspace_size(int32_t n_rows, int32_t n_cols);
+spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t max_diags,
+                              int32_t *h_offsets, int32_t *h_ndia, int64_t *h_rem_nnz, void *dia_val,
+                              int32_t *rem_row_ptr, int32_t *rem_col, void *rem_val, void *ws, size_t ws_bytes,
+                              void *stream);
+/* y = alpha * A x + beta * y over the hybrid: each lane owns one row, reads
+ * its value of every stored diagonal (consecutive rows: consecutive values
+ * and consecutive x) and then its remainder entries.  A row sums its
+ * diagonals in offset order, then its remainder entries, in FP64 for every
+ * value type (at most SPMV_DIA_MAX + remainder terms; the FP64 sum meets the
+ * bound of the reduced-precision rule); y is rounded to vec_dt once.  Zeros
+ * stored inside a diagonal are multiplied like entries (an Inf or NaN in x
+ * reaches those rows).  rem_row_ptr may be NULL when the remainder is empty.
+ * h_offsets: host copy of the ndia offsets. */
+spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets, const void *dia_val,
+                     spmv_dtype val_dt, const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val,
+                     const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream);
+
+/* ======================================================================== */
 /* Many matrices in one launch                                               */
 /* ======================================================================== */
 /* Batched blocked-JDS SpMV: y_m = A_m x_m for m < n_mat, F32 values and

@@ -16,6 +16,7 @@ SYMPERM, SOJDS = 1, 2
 WIDE_ROW_NNZ = 4096
 BATCHED_PLAN_WORDS = 12
 SPLIT_PARTS = 8
+DIA_MAX = 64           # SPMV_DIA_MAX
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "bad matrix format", 3: "output capacity too small",
           4: "unsupported", 5: "HIP runtime error"}
@@ -85,6 +86,10 @@ SIGNATURES = {
                                   _i32, _i32, _i32, _p]),
     "spmv_jds_blocked_row_split": (_int, [_i32, _i32, _i64p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, _int, _p, _p, _int,
                                           _f64, _f64, _i32, _i32, _i32, _i32, _p]),
+    "spmv_dia_workspace_size": (_sz, [_i32, _i32]),
+    "spmv_dia_from_csr": (_int, [_i32, _i32, _i64, _p, _p, _p, _int, _i32, _i32p, _i32p, _i64p, _p, _p, _p, _p, _p,
+                                 _sz, _p]),
+    "spmv_dia": (_int, [_i32, _i32, _i32, _i32p, _p, _int, _p, _p, _p, _p, _p, _int, _f64, _f64, _p]),
     "spmv_batched_plan": (_int, [_i32, _i32p, _i32p, _i64p, _i64p, _i64p, _i64p, _i32p, _i32, _p, _i64, _i64p,
                                  _p]),
     "spmv_batched": (_int, [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _p]),

@@ -6,6 +6,7 @@
 // All orderings are produced by a stable least-significant-digit radix sort
 // written here (8-bit digits, wave ballots for the in-tile ranks), so every
 // permutation is unique and reproducible; counts use integer atomics only.
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -604,6 +605,77 @@ __global__ void sojds_kernel(const int32_t *__restrict__ jp, int32_t ndiag, cons
                 bl_col[sp + (int64_t)d * C + rl] = jd_col[jp[pick] + r];
                 bl_val[sp + (int64_t)d * C + rl] = jd_val[jp[pick] + r];
             }
+        }
+    }
+}
+
+// ---- DIA + CRS hybrid: diagonals (offset col - row) stored densely, the rest in CRS
+
+__global__ void diag_hist_kernel(const int32_t *__restrict__ rp, int32_t n_rows, const int32_t *__restrict__ col,
+                                 int32_t *__restrict__ hist)
+{
+    GRID_LOOP(i, (int64_t)n_rows)
+    {
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) atomicAdd(hist + ((int64_t)col[e] - i + n_rows - 1), 1);
+    }
+}
+
+struct DiaOffsets {
+    int32_t n;
+    int32_t off[SPMV_DIA_MAX];
+};
+
+__global__ void dia_index_kernel(int64_t m, int32_t *__restrict__ oidx)
+{
+    GRID_LOOP(t, m) oidx[t] = -1;
+}
+
+__global__ void dia_index_set_kernel(int32_t n_rows, DiaOffsets D, int32_t *__restrict__ oidx)
+{
+    const int k = (int)threadIdx.x;
+    if (k < D.n) oidx[(int64_t)D.off[k] + n_rows - 1] = k;
+}
+
+template <typename T>
+__global__ void dia_zero_kernel(int64_t m, T *__restrict__ out)
+{
+    GRID_LOOP(t, m) out[t] = T{};
+}
+
+// entries on a stored diagonal go to dia[k * n_rows + row]; the others are
+// counted per row for the remainder CRS
+template <typename T>
+__global__ void dia_scatter_kernel(const int32_t *__restrict__ rp, int32_t n_rows, const int32_t *__restrict__ col,
+                                   const T *__restrict__ val, const int32_t *__restrict__ oidx, T *__restrict__ dia,
+                                   int32_t *__restrict__ rem_cnt)
+{
+    GRID_LOOP(i, (int64_t)n_rows)
+    {
+        int32_t cnt = 0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int32_t k = oidx[(int64_t)col[e] - i + n_rows - 1];
+            if (k >= 0) dia[(int64_t)k * n_rows + i] = val[e];
+            else ++cnt;
+        }
+        rem_cnt[i] = cnt;
+    }
+}
+
+// remainder entries of each row, in CRS order
+template <typename T>
+__global__ void dia_rem_kernel(const int32_t *__restrict__ rp, int32_t n_rows, const int32_t *__restrict__ col,
+                               const T *__restrict__ val, const int32_t *__restrict__ oidx,
+                               const int32_t *__restrict__ rem_rp, int32_t *__restrict__ rem_col,
+                               T *__restrict__ rem_val)
+{
+    GRID_LOOP(i, (int64_t)n_rows)
+    {
+        int32_t p = rem_rp[i];
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (oidx[(int64_t)col[e] - i + n_rows - 1] >= 0) continue;
+            rem_col[p] = col[e];
+            rem_val[p] = val[e];
+            ++p;
         }
     }
 }
@@ -1222,6 +1294,104 @@ spmv_status spmv_split_columns(int32_t n_rows, int32_t n_cols, int64_t nnz, cons
     }
     SPMV_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost, s));
     SPMV_HIP(hipMemcpyAsync(h_row_off, row_off, sizeof(int64_t) * (SPLIT_PARTS + 1), hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+size_t spmv_dia_workspace_size(int32_t n_rows, int32_t n_cols)
+{
+    const int64_t m = (int64_t)(n_rows > 0 ? n_rows : 1) + (n_cols > 0 ? n_cols : 1) - 1;
+    const size_t nn = (size_t)(n_rows > 0 ? n_rows : 1);
+    return align_up(sizeof(int32_t) * (size_t)m, 256) + align_up(sizeof(int32_t) * nn, 256) +
+           align_up(sizeof(int32_t) * scan_ws_elems((int64_t)nn), 256) + 1024;
+}
+
+spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t max_diags,
+                              int32_t *h_offsets, int32_t *h_ndia, int64_t *h_rem_nnz, void *dia_val,
+                              int32_t *rem_row_ptr, int32_t *rem_col, void *rem_val, void *ws, size_t ws_bytes,
+                              void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && nnz >= 0, "spmv_dia_from_csr: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_dia_from_csr: nnz >= 2^31");
+    SPMV_REQUIRE(valid_dtype(dt), "spmv_dia_from_csr: bad dtype");
+    if (max_diags == 0) max_diags = SPMV_DIA_MAX;
+    SPMV_REQUIRE(max_diags > 0 && max_diags <= SPMV_DIA_MAX, "spmv_dia_from_csr: max_diags must be 0..SPMV_DIA_MAX");
+    SPMV_REQUIRE(h_offsets && h_ndia && h_rem_nnz, "spmv_dia_from_csr: null host output");
+    SPMV_REQUIRE(n_rows == 0 || row_ptr, "spmv_dia_from_csr: null row_ptr");
+    SPMV_REQUIRE(nnz == 0 || (col_idx && val), "spmv_dia_from_csr: null col_idx or val");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_dia_workspace_size(n_rows, n_cols), "spmv_dia_from_csr: workspace too small");
+    hipStream_t s = as_stream(stream);
+    const int64_t m = (int64_t)(n_rows > 0 ? n_rows : 1) + (n_cols > 0 ? n_cols : 1) - 1;
+    const size_t nn = (size_t)(n_rows > 0 ? n_rows : 1);
+    WsCarver wc(ws, ws_bytes);
+    int32_t *hist = wc.take<int32_t>((size_t)m);           // later: offset -> stored diagonal index
+    int32_t *cnt = wc.take<int32_t>(nn);
+    int32_t *scan_ws = wc.take<int32_t>(scan_ws_elems((int64_t)nn));
+    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_dia_from_csr: workspace too small");
+
+    // entries per offset
+    std::vector<int32_t> h_hist((size_t)m, 0);
+    if (nnz > 0 && n_rows > 0) {
+        SPMV_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * (size_t)m, s));
+        diag_hist_kernel<<<grid_for(n_rows), 256, 0, s>>>(row_ptr, n_rows, col_idx, hist);
+        SPMV_CHECK_LAUNCH("dia histogram");
+        SPMV_HIP(hipMemcpyAsync(h_hist.data(), hist, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, s));
+        SPMV_HIP(hipStreamSynchronize(s));
+    }
+    // a diagonal is stored densely when its dense span costs no more bytes
+    // than its entries do in CRS (value + 4-byte index); the fullest first
+    const int64_t sv = (int64_t)dtype_size(dt);
+    std::vector<std::pair<int32_t, int64_t>> cand;            // (count, offset)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t c = h_hist[(size_t)t];
+        if (c == 0) continue;
+        const int64_t o = t - (n_rows - 1);
+        const int64_t span = std::min<int64_t>(n_rows, (int64_t)n_cols - o) - std::max<int64_t>(0, -o);
+        if (c * (sv + 4) >= span * sv) cand.push_back({(int32_t)c, o});
+    }
+    std::sort(cand.begin(), cand.end(), [](const std::pair<int32_t, int64_t> &a, const std::pair<int32_t, int64_t> &b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+    });
+    if ((int64_t)cand.size() > max_diags) cand.resize((size_t)max_diags);
+    DiaOffsets D{};
+    D.n = (int32_t)cand.size();
+    int64_t on_dia = 0;
+    for (int k = 0; k < D.n; ++k) {
+        D.off[k] = (int32_t)cand[(size_t)k].second;
+        on_dia += cand[(size_t)k].first;
+    }
+    std::sort(D.off, D.off + D.n);
+    *h_ndia = D.n;
+    for (int k = 0; k < D.n; ++k) h_offsets[k] = D.off[k];
+    *h_rem_nnz = nnz - on_dia;
+    if (!dia_val) return SPMV_OK;                            // sizes only
+
+    SPMV_REQUIRE(rem_row_ptr && (*h_rem_nnz == 0 || (rem_col && rem_val)), "spmv_dia_from_csr: null output");
+    if (n_rows > 0) {
+        dia_index_kernel<<<grid_for(m), 256, 0, s>>>(m, hist);
+        dia_index_set_kernel<<<1, SPMV_DIA_MAX, 0, s>>>(n_rows, D, hist);
+        SPMV_CHECK_LAUNCH("dia index");
+    }
+    const int64_t ndv = (int64_t)D.n * n_rows;
+#define DIA_CASE(DT, T)                                                                                          \
+    if (dt == DT) {                                                                                              \
+        if (ndv > 0) dia_zero_kernel<T><<<grid_for(ndv), 256, 0, s>>>(ndv, (T *)dia_val);                       \
+        if (n_rows > 0)                                                                                          \
+            dia_scatter_kernel<T><<<grid_for(n_rows), 256, 0, s>>>(row_ptr, n_rows, col_idx, (const T *)val,     \
+                                                                   hist, (T *)dia_val, cnt);                    \
+        SPMV_CHECK_LAUNCH("dia scatter");                                                                        \
+        spmv_status st = exclusive_scan<int32_t, int32_t>(cnt, n_rows, rem_row_ptr, scan_ws, s);                \
+        if (st != SPMV_OK) return st;                                                                            \
+        if (*h_rem_nnz > 0)                                                                                      \
+            dia_rem_kernel<T><<<grid_for(n_rows), 256, 0, s>>>(row_ptr, n_rows, col_idx, (const T *)val, hist,  \
+                                                               rem_row_ptr, rem_col, (T *)rem_val);             \
+        SPMV_CHECK_LAUNCH("dia remainder");                                                                      \
+    }
+    DIA_CASE(SPMV_F64, uint64_t)
+    DIA_CASE(SPMV_F32, uint32_t)
+    DIA_CASE(SPMV_BF16, uint16_t)
+#undef DIA_CASE
     SPMV_HIP(hipStreamSynchronize(s));
     return SPMV_OK;
 }

@@ -1,0 +1,121 @@
+// DIA + CRS hybrid product (the dense storage of heavily filled diagonals that
+// the paper's Section 4.2 suggests for its Hamiltonian, with the other
+// entries in CRS).
+//
+// gfx950 design.  One lane per row, consecutive lanes on consecutive rows:
+// for every stored diagonal the wavefront reads 64 consecutive values and 64
+// consecutive x entries (no index array, no gather), then each lane adds its
+// row's remainder entries.  The offsets travel in the kernel arguments
+// (scalar registers); the diagonal loop is unrolled so that several value
+// and x loads are in flight per lane.  Workgroups are remapped so that each
+// XCD walks a contiguous range of rows and keeps its x windows in its L2.
+// Every row is summed in FP64 in a fixed order and y is written once.
+#include "common.hpp"
+
+namespace spmv {
+
+constexpr int DIA_THREADS = 256;
+
+struct DiaArgs {
+    int32_t n_rows, n_cols, ndia;
+    int32_t off[SPMV_DIA_MAX];
+    const void *dia;
+    const int32_t *rem_rp;
+    const int32_t *rem_col;
+    const void *rem_val;
+    const void *x;
+    void *y;
+    double alpha, beta;
+};
+
+template <typename VT, typename XT>
+__global__ __launch_bounds__(DIA_THREADS) void dia_kernel(DiaArgs a)
+{
+    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * DIA_THREADS + threadIdx.x;
+    if (i >= a.n_rows) return;
+    const VT *__restrict__ dia = (const VT *)a.dia + i;
+    const XT *__restrict__ x = (const XT *)a.x;
+    constexpr int U = 8;
+    double s = 0.0;
+    int k = 0;
+    for (; k + U <= a.ndia; k += U) {
+        VT v[U];
+        XT xv[U];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = i + a.off[k + u];
+            in[u] = j >= 0 && j < a.n_cols;
+            if (in[u]) {
+                v[u] = ld_stream(dia + (int64_t)(k + u) * a.n_rows);
+                xv[u] = x[j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (in[u]) s = fma(to_f64(v[u]), to_f64(xv[u]), s);
+    }
+    for (; k < a.ndia; ++k) {
+        const int64_t j = i + a.off[k];
+        if (j >= 0 && j < a.n_cols) s = fma(to_f64(ld_stream(dia + (int64_t)k * a.n_rows)), to_f64(x[j]), s);
+    }
+    if (a.rem_rp) {
+        const VT *__restrict__ rv = (const VT *)a.rem_val;
+        for (int32_t e = a.rem_rp[i]; e < a.rem_rp[i + 1]; ++e) s = fma(to_f64(rv[e]), to_f64(x[a.rem_col[e]]), s);
+    }
+    write_y((XT *)a.y, i, s, a.alpha, a.beta);
+}
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" {
+
+spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets, const void *dia_val,
+                     spmv_dtype val_dt, const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val,
+                     const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0, "spmv_dia: negative size");
+    SPMV_REQUIRE(ndia >= 0 && ndia <= SPMV_DIA_MAX, "spmv_dia: ndia must be 0..SPMV_DIA_MAX");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_dia: bad dtype");
+    if (n_rows == 0) return SPMV_OK;
+    SPMV_REQUIRE(y, "spmv_dia: null y");
+    SPMV_REQUIRE(ndia == 0 || (h_offsets && dia_val && x), "spmv_dia: null offsets, values or x");
+    SPMV_REQUIRE(!rem_row_ptr || x, "spmv_dia: null x");
+    DiaArgs a{};
+    a.n_rows = n_rows;
+    a.n_cols = n_cols;
+    a.ndia = ndia;
+    for (int k = 0; k < ndia; ++k) {
+        SPMV_REQUIRE(h_offsets[k] > -n_rows && h_offsets[k] < n_cols, "spmv_dia: offset outside the matrix");
+        SPMV_REQUIRE(k == 0 || h_offsets[k] > h_offsets[k - 1], "spmv_dia: offsets must increase");
+        a.off[k] = h_offsets[k];
+    }
+    a.dia = dia_val;
+    a.rem_rp = rem_row_ptr;
+    a.rem_col = rem_col;
+    a.rem_val = rem_val;
+    a.x = x;
+    a.y = y;
+    a.alpha = alpha;
+    a.beta = beta;
+    hipStream_t s = as_stream(stream);
+    const unsigned grid = (unsigned)ceil_div(n_rows, DIA_THREADS);
+#define DIA_CASE(VDT, VT, XDT, XT)                                          \
+    if (val_dt == VDT && vec_dt == XDT) {                                   \
+        dia_kernel<VT, XT><<<grid, DIA_THREADS, 0, s>>>(a);                 \
+        SPMV_CHECK_LAUNCH("spmv_dia");                                      \
+        return SPMV_OK;                                                     \
+    }
+    DIA_CASE(SPMV_F64, double, SPMV_F64, double)
+    DIA_CASE(SPMV_F32, float, SPMV_F64, double)
+    DIA_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    DIA_CASE(SPMV_F32, float, SPMV_F32, float)
+    DIA_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    DIA_CASE(SPMV_F64, double, SPMV_F32, float)
+#undef DIA_CASE
+    return fail(SPMV_ERR_UNSUPPORTED, "spmv_dia: dtype combination");
+}
+
+}  // extern "C"

@@ -672,6 +672,57 @@ def spmv_jds_blocked_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, C_=6
     return y
 
 
+# --------------------------------------------------------------------------- DIA + CRS hybrid
+
+
+@dataclass
+class DIA:
+    """Densely stored diagonals (offset col - row) plus a remainder CRS."""
+    n_rows: int
+    n_cols: int
+    offsets: np.ndarray          # int32, ascending, host
+    dia_val: torch.Tensor        # ndia * n_rows values, diagonal after diagonal
+    rem: CSR                     # the entries on no stored diagonal
+
+    @property
+    def ndia(self) -> int:
+        return len(self.offsets)
+
+
+def dia_from_csr(A: CSR, max_diags: int = 0) -> DIA:
+    """CRS -> DIA + CRS hybrid on the GPU (spmv_dia_from_csr)."""
+    lib = _lib.load()
+    dev = A.device
+    ws = _ws(lib.spmv_dia_workspace_size(A.n_rows, A.n_cols), dev)
+    offs = np.zeros(_lib.DIA_MAX, dtype=np.int32)
+    nd = C.c_int32(0)
+    rem_nnz = C.c_int64(0)
+    args = lambda dv, rp, rc, rv: (A.n_rows, A.n_cols, A.nnz, _p(A.row_ptr), _p(A.col_idx), _p(A.val),
+                                   dtype_code(A.val.dtype), max_diags, _h_i32(offs), C.byref(nd), C.byref(rem_nnz),
+                                   dv, rp, rc, rv, _p(ws), ws.numel(), _stream())
+    call("spmv_dia_from_csr", *args(None, None, None, None))
+    k, m = nd.value, rem_nnz.value
+    dia_val = torch.empty(max(k * A.n_rows, 1), dtype=A.val.dtype, device=dev)
+    rem_rp = torch.empty(A.n_rows + 1, dtype=_I32, device=dev)
+    rem_col = torch.empty(max(m, 1), dtype=_I32, device=dev)
+    rem_val = torch.empty(max(m, 1), dtype=A.val.dtype, device=dev)
+    call("spmv_dia_from_csr", *args(_p(dia_val), _p(rem_rp), _p(rem_col), _p(rem_val)))
+    return DIA(A.n_rows, A.n_cols, offs[:k].copy(), dia_val[:k * A.n_rows],
+               CSR(A.n_rows, A.n_cols, rem_rp, rem_col[:m], rem_val[:m]))
+
+
+def spmv_dia(D: DIA, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
+             beta: float = 0.0) -> torch.Tensor:
+    """y = alpha*A x + beta*y over the DIA + CRS hybrid (spmv_dia)."""
+    _check_dev(x)
+    y = _out_vec(y, D.n_rows, x, beta)
+    has_rem = D.rem.nnz > 0
+    call("spmv_dia", D.n_rows, D.n_cols, D.ndia, _h_i32(D.offsets), _p(D.dia_val), dtype_code(D.dia_val.dtype),
+         _p(D.rem.row_ptr) if has_rem else None, _p(D.rem.col_idx) if has_rem else None,
+         _p(D.rem.val) if has_rem else None, _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), _stream())
+    return y
+
+
 # --------------------------------------------------------------------------- many matrices
 
 

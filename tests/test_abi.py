@@ -68,6 +68,15 @@ def test_host_side_validation_without_gpu():
     st = lib.spmv_jds_row_split(10, None, None, None, None, None, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, 0,
                                 None)
     assert st == 1 and b"h_bounds" in lib.spmv_last_error()
+    # DIA offsets: at most SPMV_DIA_MAX, increasing, inside the matrix
+    offs = np.array([0, 5, 3], dtype=np.int32)
+    st = lib.spmv_dia(10, 10, 3, spmv_mod._h_i32(offs), 1, 0, None, None, None, 1, 1, 0, 1.0, 0.0, None)
+    assert st == 1 and b"increase" in lib.spmv_last_error()
+    offs = np.array([-10], dtype=np.int32)
+    st = lib.spmv_dia(10, 10, 1, spmv_mod._h_i32(offs), 1, 0, None, None, None, 1, 1, 0, 1.0, 0.0, None)
+    assert st == 1 and b"outside" in lib.spmv_last_error()
+    st = lib.spmv_dia(10, 10, 65, None, None, 0, None, None, None, None, None, 0, 1.0, 0.0, None)
+    assert st == 1 and b"ndia" in lib.spmv_last_error()
     # launch shape: 4, 8 or 16 wavefronts per workgroup
     st = lib.spmv_jds(10, None, None, None, 0, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, 12, 0, None)
     assert st == 1 and b"wg_waves" in lib.spmv_last_error()

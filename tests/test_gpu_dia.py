@@ -1,0 +1,158 @@
+"""DIA + CRS hybrid against the FP64 oracle and against the selection rule.
+
+Structure: the stored diagonals are those whose dense span costs no more
+bytes than their CRS entries (count * (s_v + 4) >= span * s_v), the fullest
+first up to max_diags, kept in ascending offset order; everything else is
+the remainder CRS, in CRS order.  The rule is recomputed here with numpy.
+Products: FP64 within 1e-12 of sum_j |a_ij||x_j|; integer inputs bit-exact;
+FP32 / BF16 values are summed in FP64, so |y - A_q x| <= gamma_{L+1}(2^-53) D
+(+ 2^-24 D when y is FP32).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import FP64_TOL, gpu_csr, max_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_0910_4836_amd")
+
+U32, U64 = 2.0 ** -24, 2.0 ** -53
+
+
+def gamma(k, u):
+    return k * u / (1 - k * u)
+
+
+def planted(seed, nr, nc, full=(-7, 0, 3, 500), partial=((-40, 0.8), (11, 0.5)), scatter=0.002):
+    """Whole diagonals `full`, diagonals filled with a given probability, and
+    uniformly scattered entries."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for o in full:
+        i = np.arange(max(0, -o), min(nr, nc - o))
+        rows.append(i)
+        cols.append(i + o)
+    for o, p in partial:
+        i = np.arange(max(0, -o), min(nr, nc - o))
+        i = i[rng.random(len(i)) < p]
+        rows.append(i)
+        cols.append(i + o)
+    m = int(scatter * nr * nc)
+    rows.append(rng.integers(0, nr, m))
+    cols.append(rng.integers(0, nc, m))
+    r = np.concatenate(rows).astype(np.int32)
+    c = np.concatenate(cols).astype(np.int32)
+    key = np.unique(r.astype(np.int64) * nc + c)                   # distinct (row, col)
+    r, c = (key // nc).astype(np.int32), (key % nc).astype(np.int32)
+    return r, c, rng.standard_normal(len(r)), nr, nc, rng
+
+
+def rule_offsets(R: oracle.CSR, sv, max_diags):
+    rows = R.row_index()
+    off = R.col.astype(np.int64) - rows
+    o, cnt = np.unique(off, return_counts=True)
+    span = np.minimum(R.n_rows, R.n_cols - o) - np.maximum(0, -o)
+    keep = cnt * (sv + 4) >= span * sv
+    o, cnt = o[keep], cnt[keep]
+    order = np.lexsort((o, -cnt))[:max_diags]
+    return np.sort(o[order])
+
+
+@pytest.mark.parametrize("max_diags", [0, 2])
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_dia_structure(max_diags, dt):
+    r, c, v, nr, nc, _ = planted(1, 3000, 3200)
+    v = v.astype(np.float32).astype(np.float64) if dt == torch.float32 else v
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    D = sp.dia_from_csr(gpu_csr(sp, r, c, v, nr, nc, dt), max_diags)
+    want = rule_offsets(R, 8 if dt == torch.float64 else 4, max_diags or 64)
+    assert D.offsets.tolist() == want.tolist()
+    if max_diags == 0:
+        assert set(want.tolist()) >= {-7, 0, 3, 500, -40}           # 0.8 filled: stored in both widths
+    rows = R.row_index()
+    off = R.col.astype(np.int64) - rows
+    on = np.isin(off, want)
+    dense = np.zeros((len(want), nr))
+    k = np.searchsorted(want, off[on])
+    dense[k, rows[on]] = R.val[on]
+    assert np.array_equal(to_np(D.dia_val).astype(np.float64).reshape(len(want), nr), dense)
+    rem = D.rem
+    cnt = np.bincount(rows[~on], minlength=nr)
+    assert np.array_equal(to_np(rem.row_ptr), np.concatenate([[0], np.cumsum(cnt)]))
+    assert np.array_equal(to_np(rem.col_idx), R.col[~on])
+    assert np.array_equal(to_np(rem.val).astype(np.float64), R.val[~on])
+
+
+def _cases():
+    yield "planted", planted(2, 4000, 4000)[:5]
+    yield "rectangular", planted(3, 2500, 3100, full=(-100, 0, 700), partial=((5, 0.9),))[:5]
+    yield "wide_offsets", planted(4, 3000, 2000, full=(-2999, -1500, 1999), partial=())[:5]
+    r, c, v, n, _ = synth.sym_diagonals(n=30000, ndiag=12)
+    yield "symmetric_diagonals", (r, c, v, n, n)
+    rr, cc, vv, nr, nc = synth.random_pattern(2000, 2000, 0.004, np.random.default_rng(5), empty_rows=0.2,
+                                              long_rows=3, long_len=900)
+    yield "no_heavy_diagonal", (rr, cc, vv, nr, nc)
+
+
+@pytest.mark.parametrize("case", ["planted", "rectangular", "wide_offsets", "symmetric_diagonals",
+                                  "no_heavy_diagonal"])
+def test_dia_fp64_parity(case):
+    r, c, v, nr, nc = dict(_cases())[case]
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    D = sp.dia_from_csr(A)
+    if case == "symmetric_diagonals":
+        assert D.ndia == 25 and D.rem.nnz == 0
+    if case == "no_heavy_diagonal":                             # at most a few corner diagonals of span 1-2
+        assert D.rem.nnz >= 0.99 * R.nnz
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, nc)
+    y0 = rng.uniform(-1, 1, nr)
+    for alpha, beta in ((1.0, 0.0), (-0.75, 2.0)):
+        want = oracle.spmv_crs(R, x, y0 if beta else None, alpha, beta)
+        Dm = abs(alpha) * oracle.row_absdot(R, x) + (abs(beta) * np.abs(y0) if beta else 0)
+        got = sp.spmv_dia(D, to_dev(x), to_dev(y0.copy()) if beta else None, alpha, beta)
+        assert max_err(got, want, Dm) <= FP64_TOL, (alpha, beta)
+    # FP32 vectors: one final rounding
+    x32 = x.astype(np.float32)
+    want = oracle.spmv_crs(R, x32.astype(np.float64))
+    Dm = oracle.row_absdot(R, x32.astype(np.float64))
+    got = to_np(sp.spmv_dia(D, to_dev(x32))).astype(np.float64)
+    assert np.all(np.abs(got - want) <= (U32 + gamma(R.row_lengths() + 1, U64)) * Dm)
+
+
+def test_dia_integer_exact_and_empty():
+    r, c, _, nr, nc, rng = planted(8, 3000, 3000)
+    v = rng.integers(-8, 9, len(r)).astype(np.float64)
+    x = synth.integer_vector(nc, rng)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    want = oracle.spmv_crs(R, x)
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        A = gpu_csr(sp, r, c, v, nr, nc)
+        D = sp.dia_from_csr(A.with_values(sp.spmv_convert_values(A.val, dt)))
+        assert np.array_equal(to_np(sp.spmv_dia(D, to_dev(x))), want), dt
+    # no entries at all: y = beta*y
+    A = sp.csr_from_coo(5, 4, to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0)))
+    D = sp.dia_from_csr(A)
+    assert D.ndia == 0 and D.rem.nnz == 0
+    assert to_np(sp.spmv_dia(D, to_dev(np.ones(4)), to_dev(np.full(5, 2.0)), 1.0, 0.5)).tolist() == [1.0] * 5
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16])
+def test_dia_reduced_precision_values(dt):
+    r, c, v, n, _ = synth.sym_diagonals(n=20000, ndiag=12)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    vq = oracle.round_f32(R.val).astype(np.float64) if dt == torch.float32 else \
+        oracle.bf16_bits_to_f64(oracle.round_bf16_bits(R.val))
+    Rq = oracle.CSR(n, n, R.row_ptr, R.col, vq)
+    x = np.random.default_rng(9).uniform(-1, 1, n)
+    want = oracle.spmv_crs(Rq, x)
+    Dm = oracle.row_absdot(Rq, x)
+    A = gpu_csr(sp, r, c, v, n, n)
+    Aq = A.with_values(sp.spmv_convert_values(A.val, dt))
+    D = sp.dia_from_csr(Aq)
+    got = to_np(sp.spmv_dia(D, to_dev(x)))
+    assert np.all(np.abs(got - want) <= gamma(Rq.row_lengths() + 1, U64) * Dm)
