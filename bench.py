@@ -315,6 +315,14 @@ def powerlaw_kernels(sp, W, torch):
     return ks, bmin
 
 
+def bytes_dia(D, s_v, s_x):
+    """Stored diagonals read over their spans (zeros inside a span included),
+    the remainder as CRS, x and y once."""
+    span = sum(max(0, min(D.n_rows, D.n_cols - int(o)) - max(0, -int(o))) for o in D.offsets)
+    rem = D.rem.nnz * (s_v + 4) + (4 * (D.n_rows + 1) if D.rem.nnz else 0)
+    return span * s_v + rem + s_x * (D.n_cols + D.n_rows)
+
+
 def cpu_baseline(W, budget_s=20.0):
     """The serial oracle (plain C, one core) on the same step, repeated for about
     budget_s seconds of CPU time; returns GFLOP/s."""
@@ -440,6 +448,10 @@ def suite_symdiag(torch, sp, dev, steps):
     ju, jm, jw = tuner.tune_jds(J, x)
     bC, bR, bU, bW = tuner.tune_blocked(J, x)
     B = sp.jds_blocked_from_jds(J, bC)
+    t0 = time.perf_counter()
+    Dd = sp.dia_from_csr(A)
+    torch.cuda.synchronize()
+    dia_ms = round((time.perf_counter() - t0) * 1e3, 1)
     nnz = A.nnz
     y_ref = sp.spmv_crs(A, x)
     out = {"workload": f"symmetric 12 secondary diagonals + diagonal, n={n}, nnz={nnz}", "kernels": {},
@@ -452,18 +464,22 @@ def suite_symdiag(torch, sp, dev, steps):
         Aq = A if vdt == torch.float64 else A.with_values(sp.spmv_convert_values(A.val, vdt))
         Jq = J if vdt == torch.float64 else J.with_values(sp.spmv_convert_values(J.jd_val, vdt))
         Bq = B if vdt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
+        Dq = Dd if vdt == torch.float64 else sp.DIA(Dd.n_rows, Dd.n_cols, Dd.offsets,
+                                                    sp.spmv_convert_values(Dd.dia_val, vdt), Dd.rem)
         ks = [(f"crs_{tag}", lambda Aq=Aq: sp.spmv_crs(Aq, x, y)),
               (f"jds_{tag}", lambda Jq=Jq: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
               (f"blocked_{tag}", lambda Bq=Bq: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU,
-                                                                    wg_waves=bW))]
+                                                                    wg_waves=bW)),
+              (f"dia_{tag}", lambda Dq=Dq: sp.spmv_dia(Dq, x, y))]
         _, per = time_loop(torch, ks, max(10, steps // 4), 3)
         bm = {ks[0][0]: bytes_crs(nnz, n, n, sv, 8), ks[1][0]: bytes_jds(nnz, n, n, J.ndiag, sv, 8),
-              ks[2][0]: bytes_blocked(nnz, n, n, B.n_slices, sv, 8)}
+              ks[2][0]: bytes_blocked(nnz, n, n, B.n_slices, sv, 8), ks[3][0]: bytes_dia(Dd, sv, 8)}
         for name, fn in ks:
             out["kernels"][name] = _kernel_entry(name, 2.0 * nnz, bm[name], per[name])
             fn()
             out["max_rel_err_vs_fp64"][name] = _rel_err_gpu(torch, sp, A, x, y, y_ref)
-        del Aq, Jq, Bq
+        del Aq, Jq, Bq, Dq
+    out["dia"] = {"diagonals": Dd.ndia, "remainder_nnz": Dd.rem.nnz, "setup_ms": dia_ms}
     # SOJDS (paper Section 2): the same slices with every row's entries
     # re-assigned to diagonal slots for near-unit x strides across rows
     t0 = time.perf_counter()

@@ -181,6 +181,12 @@ def test_symmetric_diagonals_sampled():
         e = oracle.rel_err(to_np(fn())[rows], want, D).max()
         assert e <= FP64_TOL, f"{name}: {e:.3e}"
     del Bt
+    # the DIA + CRS hybrid: every entry of this matrix lies on one of its 25 diagonals
+    Dd = sp.dia_from_csr(A)
+    assert Dd.ndia == 25 and Dd.rem.nnz == 0
+    e = oracle.rel_err(to_np(sp.spmv_dia(Dd, xd))[rows], want, D).max()
+    assert e <= FP64_TOL, f"dia: {e:.3e}"
+    del Dd
     # reduced-precision values on the same rows
     for vdt in (torch.float32, torch.bfloat16):
         if vdt == torch.float32:
