@@ -46,8 +46,9 @@ def parse():
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="", help="comma list of kernels for profiling runs")
-    ap.add_argument("--probe", choices=["copy", "triad"], default=None,
-                    help="run only the bandwidth probe on 1 GiB arrays (counter calibration)")
+    ap.add_argument("--probe", choices=["copy", "triad", "strides"], default=None,
+                    help="copy / triad: only the bandwidth probe on 1 GiB arrays (counter calibration); "
+                         "strides: the access-pattern microbenchmarks of the inner loop")
     ap.add_argument("--tune-cache", default="",
                     help="autotuner cache file (default: a fresh one, i.e. tune on this device now); "
                          "profiling runs share one so they time the same kernels")
@@ -58,6 +59,9 @@ def run_probe(kind):
     import torch
     import paper_0910_4836_amd as sp
     dev = torch.device("cuda", 0)
+    if kind == "strides":
+        print(json.dumps(run_strides(torch, sp, dev)))
+        return
     n = 1 << 27
     a = torch.empty(n, dtype=torch.float64, device=dev)
     b = torch.ones(n, dtype=torch.float64, device=dev)
@@ -70,6 +74,135 @@ def run_probe(kind):
     torch.cuda.synchronize()
     print(json.dumps({"probe": kind, "elements": n, "launches": 10,
                       "bytes_per_launch": (16 if kind == "copy" else 24) * n}))
+
+
+STRIDE_SWEEP = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512, 530, 1024, 2048, 4096, 8192)
+WRAP_SWEEP = (128, 512, 2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144)
+GAUSS_MEANS = (1, 2, 4, 8, 16, 32, 64, 128)
+GAUSS_SDS = (0, 1, 2, 4, 8, 16, 32, 64, 128, 256)
+
+
+def run_strides(torch, sp, dev, reps=5):
+    """The basic operations of the inner loop (Section 4.1, Table 1) on this
+    GPU: s += B(j) (ADD) or s += A(i)*B(j) (SCP) over i < n with j = i (PD),
+    k*i (CS), ind(i) = k*i (IS), ind(i) with geometric strides of mean k (IR,
+    the keep-with-probability-1/k rule) or Gaussian strides of given mean
+    and standard deviation (the stride plane, backward jumps included).
+
+    B is 2^31 doubles (16 GiB: every int32 index fits) and every launch is
+    timed cold, right after a 512 MiB streaming copy, so nothing starts in
+    the L2s or the 256 MB MALL, as the paper sizes its arrays beyond every
+    cache.  Rates are updates per second; "cu_cycles" is the chip's CU-cycles
+    per update (256 CUs at 2.4 GHz), the analogue of the paper's cycles per
+    update.  A and B hold ones, so every launch must sum to exactly n."""
+    import synth
+    NB = 1 << 31
+    NMAX = 1 << 25
+    b = torch.ones(NB, dtype=torch.float64, device=dev)
+    a = torch.ones(NMAX, dtype=torch.float64, device=dev)
+    part = torch.zeros(1 << 16, dtype=torch.float64, device=dev)
+    fa = torch.empty(1 << 26, dtype=torch.float64, device=dev)
+    fb = torch.zeros(1 << 26, dtype=torch.float64, device=dev)
+    cycles = 256 * 2.4e9
+    rng = synth.rng_for(6, 1)
+
+    def cold(fn, n):
+        fn()
+        pairs = []
+        for r in range(reps):
+            if r == reps - 1:
+                part.zero_()
+            sp.spmv_stream_copy(fa, fb)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            pairs.append((e0, e1))
+        torch.cuda.synchronize()
+        got = part.sum().item()
+        if got != n:
+            raise RuntimeError(f"stride probe summed {got}, expected {n}")
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in pairs]))
+
+    def lines(j):
+        """Distinct 128-byte lines of B per update, counted over the 64
+        consecutive updates that one wavefront load instruction issues
+        (first 2^20 updates)."""
+        j = np.asarray(j[: (min(len(j), 1 << 20) // 64) * 64], dtype=np.int64).reshape(-1, 64) // 16
+        j = np.sort(j, axis=1)
+        return float((1 + (np.diff(j, axis=1) != 0).sum(axis=1)).mean() / 64)
+
+    def entry(name, n, ms, lpu, **kw):
+        rate = n / (ms * 1e-3)
+        e = {"case": name, "n": n, "us": round(ms * 1e3, 2), "Gupdates_s": round(rate / 1e9, 2),
+             "cu_cycles": round(cycles / rate, 1), "lines_per_update": round(lpu, 4)}
+        e.update(kw)
+        print(json.dumps(e), file=sys.stderr, flush=True)
+        return e
+
+    def indirect(kind, k, n, sd=0.0):
+        ind = synth.index_stream(kind, n, k, rng, sd)
+        ind = ind[ind < NB]
+        return torch.from_numpy(ind.astype(np.int32)).to(dev), len(ind), int(ind.max()), lines(ind)
+
+    out = {"probe": "strides", "B_elements": NB, "reps": reps, "timing": "cold, median", "ops": [],
+           "sweep": [], "wrap": [], "gauss": []}
+    # launch and event overhead: one update
+    out["launch_us"] = round(cold(lambda: sp.spmv_stride_probe(1, b, part), 1) * 1e3, 2)
+    # Table 1's eight operations at the strides of the paper's Fig. 2
+    for k in (1, 8, 530):
+        n = min(NMAX, (NB - 1) // k + 1)
+        for scp in (False, True):
+            op = "SCP" if scp else "ADD"
+            aa = a if scp else None
+            lk = lines(np.arange(1 << 20) * k)
+            ms = cold(lambda: sp.spmv_stride_probe(n, b, part, a=aa, k=k), n)
+            out["ops"].append(entry(("PD" if k == 1 else "CS") + op, n, ms, lk, k=k))
+            ind = (torch.arange(n, device=dev, dtype=torch.int64) * k).to(torch.int32)
+            ms = cold(lambda: sp.spmv_stride_probe(n, b, part, a=aa, ind=ind, ind_max=k * (n - 1)), n)
+            out["ops"].append(entry("IS" + op, n, ms, lk, k=k))
+            ir, m, mx, li = indirect("IR", k, min(NMAX, int((NB - 1) / (k * 1.1)) + 1))
+            ms = cold(lambda: sp.spmv_stride_probe(m, b, part, a=aa, ind=ir, ind_max=mx), m)
+            out["ops"].append(entry("IR" + op, m, ms, li, k=k))
+            del ind, ir
+    # SCP against the stride: constant (CS, IS) and random (IR)
+    for k in STRIDE_SWEEP:
+        n = min(NMAX, (NB - 1) // k + 1)
+        lk = lines(np.arange(1 << 20) * k)
+        ms = cold(lambda: sp.spmv_stride_probe(n, b, part, a=a, k=k), n)
+        out["sweep"].append(entry("CSSCP", n, ms, lk, k=k))
+        ind = (torch.arange(n, device=dev, dtype=torch.int64) * k).to(torch.int32)
+        ms = cold(lambda: sp.spmv_stride_probe(n, b, part, a=a, ind=ind, ind_max=k * (n - 1)), n)
+        out["sweep"].append(entry("ISSCP", n, ms, lk, k=k))
+        ir, m, mx, li = indirect("IR", k, min(NMAX, int((NB - 1) / (k * 1.1)) + 1))
+        ms = cold(lambda: sp.spmv_stride_probe(m, b, part, a=a, ind=ir, ind_max=mx), m)
+        out["sweep"].append(entry("IRSCP", m, ms, li, k=k))
+        del ind, ir
+    # ISSCP at strides up to 2 MiB with 2^24 updates each: the stream wraps
+    # around B, each pass shifted by one 128-byte line, so no line is read
+    # twice and every pass walks all 16 GiB again (the address translation
+    # footprint of the stride, not of a short launch)
+    for k in WRAP_SWEEP:
+        n = 1 << 24
+        t = torch.arange(n, device=dev, dtype=torch.int64) * k
+        span = NB - 16 * (int(t[-1].item()) // NB + 2)
+        ind = (t % span + 16 * (t // span)).to(torch.int32)
+        mx = int(ind.max().item())
+        del t
+        ms = cold(lambda: sp.spmv_stride_probe(n, b, part, a=a, ind=ind, ind_max=mx), n)
+        out["wrap"].append(entry("ISSCP_wrap", n, ms, 1.0, k=k))
+        del ind
+    # IRSCP with Gaussian strides: mean and standard deviation set independently
+    for mean in GAUSS_MEANS:
+        for sd in GAUSS_SDS:
+            n = min(NMAX // 2, int((NB - 1) / (mean * 1.2)))
+            g, m, mx, lg = indirect("GAUSS", mean, n, float(sd))
+            ms = cold(lambda: sp.spmv_stride_probe(m, b, part, a=a, ind=g, ind_max=mx), m)
+            out["gauss"].append(entry("IRSCP_gauss", m, ms, lg, mean=mean, sd=sd))
+            del g
+    del a, b, fa, fb, part
+    return out
 
 
 # --------------------------------------------------------------------------- byte models

@@ -496,6 +496,15 @@ spmv_status spmv_stream_read(int64_t n, const double *b, double *part, int64_t p
  * code balance leaves out).  part_cap >= 8 * (compute units) doubles. */
 spmv_status spmv_gather_probe(int64_t n, const int32_t *idx, const double *x, double *part, int64_t part_cap,
                               void *stream);
+/* The basic sparse vector operations of the paper's Section 4.1 (Table 1):
+ * for i < n, s += b[j(i)] (scp == 0: PDADD / CSADD / ISADD / IRADD) or
+ * s += a[i] * b[j(i)] (scp != 0: the ..SCP forms), with j(i) = k*i when ind
+ * is NULL (k = 1 dense, k > 1 constant stride) and j(i) = ind[i] otherwise
+ * (indirect: constant or random strides); part[w] receives workgroup w's
+ * sum.  Every j(i) must index b (b holds at least k*(n-1)+1 doubles when ind
+ * is NULL) and a holds n doubles; part_cap >= 8 * (compute units). */
+spmv_status spmv_stride_probe(int64_t n, int32_t scp, const double *a, const double *b, const int32_t *ind, int64_t k,
+                              double *part, int64_t part_cap, void *stream);
 
 #ifdef __cplusplus
 }

@@ -12,4 +12,4 @@ from .spmv import (  # noqa: F401
     spmv_convert_values, spmv_crs, spmv_crs_plan, spmv_crs_split, spmv_csr_validate, spmv_dia, spmv_dot,
     spmv_gather_probe, spmv_gather_values, spmv_grad_vals_jds, spmv_jds, spmv_jds_blocked,
     spmv_jds_blocked_row_split, spmv_jds_blocked_split, spmv_jds_row_split, spmv_jds_split, spmv_permute_vec,
-    spmv_stream_copy, spmv_stream_read, spmv_stream_triad, spmv_transpose_csr, version)
+    spmv_stream_copy, spmv_stream_read, spmv_stream_triad, spmv_stride_probe, spmv_transpose_csr, version)

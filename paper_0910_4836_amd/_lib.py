@@ -86,6 +86,7 @@ SIGNATURES = {
                                   _i32, _i32, _i32, _p]),
     "spmv_jds_blocked_row_split": (_int, [_i32, _i32, _i64p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, _int, _p, _p, _int,
                                           _f64, _f64, _i32, _i32, _i32, _i32, _p]),
+    "spmv_stride_probe": (_int, [_i64, _i32, _p, _p, _p, _i64, _p, _i64, _p]),
     "spmv_dia_workspace_size": (_sz, [_i32, _i32]),
     "spmv_dia_from_csr": (_int, [_i32, _i32, _i64, _p, _p, _p, _int, _i32, _i32p, _i32p, _i64p, _p, _p, _p, _p, _p,
                                  _sz, _p]),

@@ -428,6 +428,21 @@ def spmv_stream_read(b, part):
     call("spmv_stream_read", b.numel(), _p(b), _p(part), part.numel(), _stream())
 
 
+def spmv_stride_probe(n, b, part, a=None, ind=None, k=1, ind_max=None):
+    """s += b[j(i)] or s += a[i]*b[j(i)] for i < n, j(i) = k*i or ind[i]
+    (spmv_stride_probe); with `ind`, `ind_max` is its largest entry (known to
+    the caller that built it)."""
+    if ind is not None and ind_max is None:
+        raise ValueError("ind needs ind_max")
+    need = ind_max + 1 if ind is not None else k * (n - 1) + 1
+    if n > 0 and b.numel() < need:
+        raise ValueError("b is too short for the index stream")
+    if a is not None and a.numel() < n:
+        raise ValueError("a is shorter than n")
+    call("spmv_stride_probe", n, 1 if a is not None else 0, _p(a), _p(b), _p(ind), k, _p(part), part.numel(),
+         _stream())
+
+
 def spmv_gather_probe(idx, x, part):
     call("spmv_gather_probe", idx.numel(), _p(idx), _p(x), _p(part), part.numel(), _stream())
 

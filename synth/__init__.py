@@ -297,3 +297,30 @@ def random_pattern(n_rows: int, n_cols: int, density: float, rng, *,
 
 def integer_vector(n: int, rng, lo: int = -8, hi: int = 8) -> np.ndarray:
     return rng.integers(lo, hi + 1, size=n).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# index streams for the access-pattern microbenchmarks (Section 4.1, Table 1)
+
+
+def index_stream(kind: str, n: int, k: float, rng, sd: float = 0.0) -> np.ndarray:
+    """n int64 indices into the input vector.
+
+    * ``"IS"``: constant stride, ind(i) = k*i (k integer).
+    * ``"IR"``: random strides of mean k: every element of the vector is kept
+      with probability p = 1/k, so the gaps between kept elements are
+      geometric on {1, 2, ...} with mean k and variance k(k-1); the first
+      kept element is the first success, at gap-1.
+    * ``"GAUSS"``: strides round(N(k, sd^2)), started far enough from 0
+      (six standard deviations of the walk) that backward jumps stay
+      inside the vector; the rare walk that leaves [0, ...) is clipped.
+    """
+    if kind == "IS":
+        return np.arange(n, dtype=np.int64) * int(k)
+    if kind == "IR":
+        return np.cumsum(rng.geometric(1.0 / k, size=n).astype(np.int64)) - 1
+    if kind == "GAUSS":
+        steps = np.rint(rng.normal(k, sd, size=n)).astype(np.int64)
+        start = int(math.ceil(6.0 * sd * math.sqrt(n)))
+        return np.maximum(start + np.cumsum(steps), 0)
+    raise ValueError(kind)

@@ -80,6 +80,9 @@ def test_host_side_validation_without_gpu():
     # launch shape: 4, 8 or 16 wavefronts per workgroup
     st = lib.spmv_jds(10, None, None, None, 0, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, 12, 0, None)
     assert st == 1 and b"wg_waves" in lib.spmv_last_error()
+    # access-pattern probe: a stride of at least 1
+    st = lib.spmv_stride_probe(100, 0, None, None, None, 0, None, 0, None)
+    assert st == 1 and b"k < 1" in lib.spmv_last_error()
 
 
 def test_product_path_does_not_use_the_oracle():

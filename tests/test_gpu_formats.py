@@ -182,3 +182,43 @@ def test_bandwidth_and_gather_probes():
     part.zero_()
     sp.spmv_gather_probe(idx, x, part)
     assert part.sum().item() == x[idx.long()].sum().item()
+
+
+@pytest.mark.parametrize("n", [1, 255, 2048 * 8 + 77, 600_001])
+def test_stride_probe(n):
+    """The access-pattern probe sums what its index stream names: small
+    integers, so every order of the sum is exact."""
+    rng = np.random.default_rng(n)
+    av = rng.integers(-4, 5, n).astype(np.float64)
+    bv = rng.integers(-4, 5, 64 * n + 1).astype(np.float64)
+    a, b = to_dev(av), to_dev(bv)
+    part = torch.zeros(1 << 16, dtype=torch.float64, device="cuda")
+    for k in (1, 3, 64):
+        j = np.arange(n) * k
+        for scp in (False, True):
+            part.zero_()
+            sp.spmv_stride_probe(n, b, part, a=a if scp else None, k=k)
+            want = (av * bv[j]).sum() if scp else bv[j].sum()
+            assert part.sum().item() == want, (k, scp)
+    streams = {"IS": synth.index_stream("IS", n, 5, rng), "IR": synth.index_stream("IR", n, 7, rng),
+               "GAUSS": synth.index_stream("GAUSS", n, 3, rng, 40.0)}
+    for kind, ind in streams.items():
+        ind = np.minimum(ind, len(bv) - 1)
+        it = to_dev(ind.astype(np.int32))
+        for scp in (False, True):
+            part.zero_()
+            sp.spmv_stride_probe(n, b, part, a=a if scp else None, ind=it, ind_max=int(ind.max()))
+            want = (av * bv[ind]).sum() if scp else bv[ind].sum()
+            assert part.sum().item() == want, (kind, scp)
+
+
+def test_stride_probe_rejects():
+    b = torch.ones(100, dtype=torch.float64, device="cuda")
+    part = torch.zeros(1 << 16, dtype=torch.float64, device="cuda")
+    sp.spmv_stride_probe(0, b, part)                                  # empty: nothing to do
+    with pytest.raises(ValueError):
+        sp.spmv_stride_probe(51, b, part, k=2)                        # index 100 is past b
+    with pytest.raises(sp.SpmvError):
+        sp.spmv_stride_probe(100, b, part, k=0)
+    with pytest.raises(sp.SpmvError):
+        sp.spmv_stride_probe(100, b, part[:0])                        # no room for the partial sums
