@@ -793,11 +793,72 @@ def suite_gather_model(torch, sp, W):
     return out
 
 
+STRIDE_EDGES = (8, 64, 512, 4096, 32768, 262144, 2097152, 16777216)
+
+
+def _stride_dist(cols, sx=8):
+    """Jumps in x between consecutive accesses of one serial traversal of the
+    stored entries (padding, col < 0, left out), in bytes: the fraction of
+    backward jumps, of forward jumps below 64 bytes, and the cumulative
+    fractions below each edge for forward and backward jumps (each a share
+    of all jumps)."""
+    c = cols[cols >= 0].astype(np.int64)
+    d = np.diff(c) * sx
+    m = max(len(d), 1)
+    fwd, bwd = d[d >= 0], -d[d < 0]
+    return {"jumps": int(len(d)), "backward_frac": round(len(bwd) / m, 4),
+            "forward_below_64B_frac": round(float((fwd < 64).sum()) / m, 4),
+            "forward_cdf": {str(e): round(float((fwd < e).sum()) / m, 4) for e in STRIDE_EDGES},
+            "backward_cdf": {str(e): round(float((bwd < e).sum()) / m, 4) for e in STRIDE_EDGES}}
+
+
+def _row_order_cols(A, perm):
+    """Columns in the order a row-by-row traversal of the permuted rows reads
+    them (RBJDS with one-row blocks)."""
+    rp = A.row_ptr.cpu().numpy().astype(np.int64)
+    col = A.col_idx.cpu().numpy()
+    lens = rp[perm + 1] - rp[perm]
+    starts = np.repeat(rp[perm], lens)
+    offs = np.arange(int(lens.sum()), dtype=np.int64) - np.repeat(np.cumsum(lens) - lens, lens)
+    return col[starts + offs]
+
+
+def suite_stride_dist(torch, sp, dev, W):
+    """The paper's stride distributions (Fig. 6a, Section 4.2) on the library's
+    own arrays: CRS, RBJDS with one-row blocks, blocked JDS (RBJDS) with 64-
+    and 1024-row slices, SOJDS with 1024-row slices, and JDS, for the
+    power-law matrix and a symmetric-diagonals matrix (the paper's matrix has
+    that shape).  A serial traversal is what the paper's CPU kernels do; a
+    wavefront reads 64 of these entries at once (the gather model)."""
+    import synth
+    out = {"unit": "fractions of all jumps; x is FP64, edges in bytes", "matrices": {}}
+
+    def schemes(A, J):
+        perm = J.perm.cpu().numpy().astype(np.int64)
+        res = {"crs": _stride_dist(A.col_idx.cpu().numpy()),
+               "rbjds_1": _stride_dist(_row_order_cols(A, perm))}
+        for C_, so in ((64, False), (1024, False), (1024, True)):
+            B = sp.jds_blocked_from_jds(J, C_, sojds=so)
+            res[("sojds_" if so else "rbjds_") + str(C_)] = _stride_dist(B.bl_col.cpu().numpy())
+            del B
+        res["jds"] = _stride_dist(J.jd_col.cpu().numpy())
+        return res
+
+    out["matrices"][f"power-law n={W['n']} nnz={W['nnz']}"] = schemes(W["A"], W["J"])
+    r, c, v, n, _ = synth.sym_diagonals(n=1_000_000, ndiag=12)
+    A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
+    J = sp.jds_from_csr(A)
+    out["matrices"][f"symmetric diagonals n={n} nnz={len(r)}"] = schemes(A, J)
+    del A, J
+    return out
+
+
 def suite_lines(torch, sp, dev, W, steps, warmup):
     lines = []
     for name, fn in (("laplacian", lambda: suite_laplacian(torch, sp, dev, steps)),
                      ("orderings", lambda: suite_orderings(torch, sp, dev, W, steps)),
                      ("gather-model", lambda: suite_gather_model(torch, sp, W)),
+                     ("stride-distribution", lambda: suite_stride_dist(torch, sp, dev, W)),
                      ("multi-vector", lambda: suite_spmm(torch, sp, dev, W, steps)),
                      ("symmetric-diagonals", lambda: suite_symdiag(torch, sp, dev, steps)),
                      ("chebyshev", lambda: suite_chebyshev(torch, sp, dev, steps)),
