@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads")
+    ap.add_argument("--suite-lines", default="", help="comma list: run only these suite lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="", help="comma list of kernels for profiling runs")
     ap.add_argument("--probe", choices=["copy", "triad", "strides"], default=None,
@@ -878,16 +879,79 @@ def suite_stride_dist(torch, sp, dev, W):
     return out
 
 
-def suite_lines(torch, sp, dev, W, steps, warmup):
+def suite_shard(torch, sp, dev, W, steps, G=8, g=3):
+    """One GPU's share of the row-partitioned product over G GPUs, at its real
+    shape: rows [g*n/G, (g+1)*n/G) of the power-law matrix, split into the
+    local block (the columns this GPU owns, read from its own slice of x) and
+    the remote block (every other column, read from the all-gathered x):
+    y = A_loc x_loc, then y += A_rem x (beta = 1), in CRS and in JDS.  The x
+    exchange itself is not run (one GPU); its link time is the estimate of a
+    16 MB all-gather over 7 xGMI links."""
+    r, c, v, n, _ = W["host"]
+    r0, r1 = g * n // G, (g + 1) * n // G
+    m = r1 - r0
+    a, b = np.searchsorted(r, [r0, r1])
+    rr = (r[a:b] - r0).astype(np.int32)
+    cc, vv = c[a:b], v[a:b]
+    loc = (cc >= r0) & (cc < r1)
+
+    def to(arr):
+        return torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
+    AL = sp.csr_from_coo(m, m, to(rr[loc]), to((cc[loc] - r0).astype(np.int32)), to(vv[loc]))
+    AR = sp.csr_from_coo(m, n, to(rr[~loc]), to(cc[~loc]), to(vv[~loc]))
+    sp.spmv_crs_plan(AL)
+    sp.spmv_crs_plan(AR)
+    JL, JR = sp.jds_from_csr(AL), sp.jds_from_csr(AR)
+    T = W["tune"]
+    ju, jm, jw = T["jds_unroll"], T["jds_max_iters"], T["jds_wg_waves"]
+    x = W["x"]
+    xl = x[r0:r1]
+    y = torch.empty(m, dtype=torch.float64, device=dev)
+    pairs = {
+        "crs": [("crs_local", lambda: sp.spmv_crs(AL, xl, y)),
+                ("crs_remote", lambda: sp.spmv_crs(AR, x, y, beta=1.0))],
+        "jds": [("jds_local", lambda: sp.spmv_jds(JL, xl, y, unroll=ju, max_iters=jm, wg_waves=jw)),
+                ("jds_remote", lambda: sp.spmv_jds(JR, x, y, beta=1.0, unroll=ju, max_iters=jm, wg_waves=jw))]}
+    # the shard's y against the same rows of the whole-matrix product
+    A = W["A"]
+    y_full = sp.spmv_crs(A, x)[r0:r1]
+    D = sp.spmv_crs(A.with_values(A.val.abs()), x.abs())[r0:r1]
+    nnz_shard = int(b - a)
+    out = {"workload": f"power-law n={n}: rows {r0}..{r1} (GPU {g} of {G}), local block {int(loc.sum())} entries, "
+                       f"remote block {int((~loc).sum())} entries, FP64",
+           "nnz_shard": nnz_shard, "kernels": {}, "shard_product": {}}
+    for fam, ks in pairs.items():
+        for _, fn in ks:
+            fn()
+        err = float(((y - y_full).abs() / D.clamp_min(1e-300)).max())
+        if err > 1e-12:
+            raise RuntimeError(f"shard {fam} product differs from the whole-matrix rows: {err}")
+        _, per = time_loop(torch, ks, max(20, steps), 5)
+        ms = graph_step_ms(torch, sp, ks, max(20, steps), 5)
+        for name, _ in ks:
+            out["kernels"][name] = {"avg_us": round(per[name] * 1e3, 2)}
+        out["shard_product"][fam] = {"us": round(ms * 1e3, 2),
+                                     "gflops": round(2.0 * nnz_shard / (ms * 1e-3) / 1e9, 1),
+                                     "max_rel_err_vs_whole": err}
+    out["x_allgather_estimate_us"] = round((n - m) * 8 / (7 * 153e9) * 1e6, 1)
+    del AL, AR, JL, JR
+    return out
+
+
+def suite_lines(torch, sp, dev, W, steps, warmup, only=""):
     lines = []
+    keep = set(x for x in only.split(",") if x)
     for name, fn in (("laplacian", lambda: suite_laplacian(torch, sp, dev, steps)),
                      ("orderings", lambda: suite_orderings(torch, sp, dev, W, steps)),
                      ("gather-model", lambda: suite_gather_model(torch, sp, W)),
                      ("stride-distribution", lambda: suite_stride_dist(torch, sp, dev, W)),
+                     ("one-shard-of-8", lambda: suite_shard(torch, sp, dev, W, steps)),
                      ("multi-vector", lambda: suite_spmm(torch, sp, dev, W, steps)),
                      ("symmetric-diagonals", lambda: suite_symdiag(torch, sp, dev, steps)),
                      ("chebyshev", lambda: suite_chebyshev(torch, sp, dev, steps)),
                      ("many-matrices", lambda: suite_batched(torch, sp, dev, steps))):
+        if keep and name not in keep:
+            continue
         print(f"# suite: {name}", file=sys.stderr, flush=True)
         rec = fn()
         print(json.dumps(rec), flush=True)
@@ -1007,7 +1071,7 @@ def main():
                     if name.endswith("_f64")}}
     print(json.dumps(out), flush=True)
     if args.suite:
-        suite_lines(torch, sp, dev, W, args.steps, args.warmup)
+        suite_lines(torch, sp, dev, W, args.steps, args.warmup, args.suite_lines)
 
 
 if __name__ == "__main__":

@@ -312,3 +312,32 @@ def test_deterministic_repeat():
         a = to_np(fn(x, None, 1.0, 0.0))
         b = to_np(fn(x, None, 1.0, 0.0))
         assert np.array_equal(a, b), name
+
+
+@pytest.mark.parametrize("g", [0, 2, 3])
+def test_row_shard_local_then_remote(g):
+    """One GPU's share of a row-partitioned product over 4 GPUs: rows of shard
+    g, local block (own columns, own slice of x) then remote block (other
+    columns, whole x) accumulated with beta = 1, in CRS and JDS, equals those
+    rows of the oracle's product."""
+    G = 4
+    r, c, v, nr, nc, rng = rand_coo(50 + g, 6000, 6000, 0.003, empty_rows=0.1, long_rows=6, long_len=2000)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    x = rng.uniform(-1, 1, nc)
+    r0, r1 = g * nr // G, (g + 1) * nr // G
+    want = oracle.spmv_crs(R, x)[r0:r1]
+    D = oracle.row_absdot(R, x)[r0:r1]
+    sel = (r >= r0) & (r < r1)
+    rr, cc, vv = (r[sel] - r0).astype(np.int32), c[sel], v[sel]
+    loc = (cc >= r0) & (cc < r1)
+    m = r1 - r0
+    AL = gpu_csr(sp, rr[loc], (cc[loc] - r0).astype(np.int32), vv[loc], m, m)
+    AR = gpu_csr(sp, rr[~loc], cc[~loc], vv[~loc], m, nc)
+    xd = to_dev(x)
+    y = sp.spmv_crs(AL, xd[r0:r1])
+    sp.spmv_crs(AR, xd, y, beta=1.0)
+    assert max_err(y, want, D) <= FP64_TOL
+    JL, JR = sp.jds_from_csr(AL), sp.jds_from_csr(AR)
+    y = sp.spmv_jds(JL, xd[r0:r1])
+    sp.spmv_jds(JR, xd, y, beta=1.0)
+    assert max_err(y, want, D) <= FP64_TOL
