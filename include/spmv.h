@@ -20,9 +20,11 @@
  *    through h_ outputs; they cannot be captured in a HIP graph.  Compute calls
  *    (spmv_*, spmm_*, grad, axpby, batched run) are asynchronous, do not
  *    allocate and do not synchronise, so they can be captured.
- *  - Compute calls validate their arguments on the host only (null pointers,
- *    negative sizes, unsupported dtype combinations); the matrix contents are
- *    trusted.  spmv_csr_validate() checks CRS contents on the device.
+ *  - Compute calls, and setup calls that start from a CRS or JDS matrix,
+ *    validate their arguments on the host only (null pointers, negative
+ *    sizes, unsupported dtype combinations); the matrix contents are trusted.
+ *    spmv_csr_from_coo checks its indices; spmv_csr_validate() checks CRS
+ *    contents on the device.
  *  - Every call returns a spmv_status; on failure spmv_last_error() returns a
  *    message for the calling thread.  No C++ exception crosses this boundary.
  *  - Results are deterministic: no floating-point atomics; every output
