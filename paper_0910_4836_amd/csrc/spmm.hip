@@ -5,11 +5,11 @@
 // library first copies X into an interleaved (row-major) block Xr, one
 // transposing pass at streaming speed, and then every entry gathers its k
 // values as one contiguous run of k*8 bytes.  Each row is handled by a group
-// of K2 lanes (K2 = k rounded up to a power of two, at most 64), lane j owning
-// column j: val/col are read once per entry for all k columns and the loads of
-// a group are contiguous.  Long rows get several groups whose partial sums
-// meet in LDS and are added in a fixed order.  Y is written column-major
-// directly.
+// of LPR lanes (K2 = k rounded up to a power of two, at most 64; LPR = K2 up
+// to 8, then 8 or 16), lane j owning columns j, j + LPR, ...: val/col are read
+// once per entry for all k columns and each gather load of a group is
+// contiguous.  Long rows get several groups whose partial sums meet in LDS and
+// are added in a fixed order.  Y is written column-major directly.
 //
 // Without a workspace the column-major kernels of crs.hip / jds.hip run.
 #include <algorithm>
@@ -24,6 +24,15 @@ namespace spmv {
 // for k <= 8 keep more rounds in flight (10-14% faster than 256); the JDS
 // kernel's classes favour larger groups (512: 3-5% faster than 256).
 constexpr int mm_crs_threads(int K2) { return K2 <= 8 ? 128 : 256; }
+// Lanes per row group (LPR) for k > 8: each lane owns k / LPR columns, so a
+// wavefront keeps 64 / LPR rows' gathers in flight.  Measured on the
+// power-law matrix at k = 32: CRS is fastest with 16 lanes for FP64 vectors
+// (8 lanes: 11% slower, 32: 1% slower) and 8 for FP32 (1.30x faster than
+// 32); JDS with 8 for both.
+template <int K2, typename XT>
+constexpr int mm_crs_lpr() { return K2 <= 8 ? K2 : (sizeof(XT) == 8 ? 16 : 8); }
+template <int K2, typename XT>
+constexpr int mm_jds_lpr() { return K2 <= 8 ? K2 : 8; }
 constexpr int MM_JDS_THREADS = 512;
 constexpr int MM_MAX_K2 = 64;
 constexpr int MM_JP_LDS = 4097;            // jd_ptr entries staged in LDS (ndiag <= 4096)
@@ -54,16 +63,17 @@ __global__ __launch_bounds__(256) void stage_rowmajor_kernel(int64_t n, int32_t 
     }
 }
 
-// One group of K2 lanes per (row, part): lane j accumulates column j.
-template <int K2, bool WIDE, typename VT, typename XT>
-__device__ __forceinline__ typename Acc<WIDE>::T mm_group_sum(const int32_t *__restrict__ col,
-                                                              const VT *__restrict__ val,
-                                                              const XT *__restrict__ Xr, int32_t k, int j,
-                                                              int64_t e_begin, int64_t e_end, int64_t e_step)
+// One group of LPR lanes per (row, part): lane j accumulates columns j,
+// j + LPR, ..., j + (CPL-1)*LPR over entries e_begin, e_begin + e_step, ...
+template <int LPR, int CPL, bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ void mm_group_sum(const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                             const XT *__restrict__ Xr, int32_t k, int j, int64_t e_begin,
+                                             int64_t e_end, int64_t e_step, double (&out)[CPL])
 {
     typedef typename Acc<WIDE>::T acc_t;
-    acc_t s = 0;
-    const bool jok = j < k;
+    acc_t s[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) s[t] = 0;
     constexpr int U = 4;
     int64_t e = e_begin;
     for (; e + (U - 1) * e_step < e_end; e += U * e_step) {
@@ -74,18 +84,28 @@ __device__ __forceinline__ typename Acc<WIDE>::T mm_group_sum(const int32_t *__r
             c[u] = col[e + u * e_step];
             v[u] = val[e + u * e_step];
         }
-        XT xv[U];
+        XT xv[U][CPL];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = jok ? Xr[(int64_t)c[u] * k + j] : XT(0);
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int u = 0; u < U; ++u) s = Acc<WIDE>::mac(s, v[u], xv[u]);
+            for (int t = 0; t < CPL; ++t)
+                xv[u][t] = t * LPR + j < k ? Xr[(int64_t)c[u] * k + t * LPR + j] : XT(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) s[t] = Acc<WIDE>::mac(s[t], v[u], xv[u][t]);
     }
     for (; e < e_end; e += e_step) {
         const int32_t c = col[e];
-        const XT xv = jok ? Xr[(int64_t)c * k + j] : XT(0);
-        s = Acc<WIDE>::mac(s, val[e], xv);
+        const VT v = val[e];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const XT xv = t * LPR + j < k ? Xr[(int64_t)c * k + t * LPR + j] : XT(0);
+            s[t] = Acc<WIDE>::mac(s[t], v, xv);
+        }
     }
-    return s;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) out[t] = (double)s[t];
 }
 
 // CRS, interleaved X.  One workgroup per plan block of nr rows: GPR groups
@@ -103,7 +123,9 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
                                                                  const int32_t *__restrict__ plan, int32_t block_nnz,
                                                                  double alpha, double beta)
 {
-    constexpr int NG = NT / K2;
+    constexpr int LPR = mm_crs_lpr<K2, XT>();           // lanes per row group
+    constexpr int CPL = K2 / LPR;                       // columns per lane
+    constexpr int NG = NT / LPR;
     constexpr bool F64 = IsF64<VT>::value;
     __shared__ double part[NG][K2];
     extern __shared__ int32_t mm_stage[];               // block_nnz cols, then block_nnz values
@@ -113,7 +135,7 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
     const int32_t r0 = plan[b], r1 = plan[b + 1];
     const int32_t nr = r1 - r0;
     const int t = (int)threadIdx.x;
-    const int g = t / K2, j = t % K2;
+    const int g = t / LPR, j = t % LPR;
     int GPR = 1;
     while (GPR * 2 * nr <= NG) GPR *= 2;
     const int sub = g % GPR;
@@ -132,42 +154,52 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
     }
     for (int32_t rbase = r0; rbase < r1; rbase += rows_per_round) {
         const int32_t row = rbase + g / GPR;
-        double td = 0.0;
+        double td[CPL];
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) td[q] = 0.0;
         if (row < r1) {
             const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
             if (staged) {
-                if (F64) td = mm_group_sum<K2, true, VT, XT>(col_s, val_s, Xr, k, j, e0 - be0 + sub, e1 - be0, GPR);
-                else td = (double)mm_group_sum<K2, false, VT, XT>(col_s, val_s, Xr, k, j, e0 - be0 + sub, e1 - be0,
-                                                                  GPR);
+                if (F64) mm_group_sum<LPR, CPL, true, VT, XT>(col_s, val_s, Xr, k, j, e0 - be0 + sub, e1 - be0, GPR, td);
+                else mm_group_sum<LPR, CPL, false, VT, XT>(col_s, val_s, Xr, k, j, e0 - be0 + sub, e1 - be0, GPR, td);
             } else if (F64 || wide) {
-                td = mm_group_sum<K2, true, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR);
+                mm_group_sum<LPR, CPL, true, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR, td);
             } else {
-                td = (double)mm_group_sum<K2, false, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR);
+                mm_group_sum<LPR, CPL, false, VT, XT>(col, val, Xr, k, j, e0 + sub, e1, GPR, td);
             }
         }
         if (GPR > 1) {
-            part[g][j] = td;
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) part[g][q * LPR + j] = td[q];
             __syncthreads();
             if (sub == 0 && row < r1) {
-                if (F64 || wide) {
-                    double t2 = 0.0;
-                    for (int q = 0; q < GPR; ++q) t2 += part[g + q][j];
-                    td = t2;
-                } else {
-                    float t2 = 0.0f;
-                    for (int q = 0; q < GPR; ++q) t2 += (float)part[g + q][j];
-                    td = (double)t2;
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    if (F64 || wide) {
+                        double t2 = 0.0;
+                        for (int p = 0; p < GPR; ++p) t2 += part[g + p][q * LPR + j];
+                        td[q] = t2;
+                    } else {
+                        float t2 = 0.0f;
+                        for (int p = 0; p < GPR; ++p) t2 += (float)part[g + p][q * LPR + j];
+                        td[q] = (double)t2;
+                    }
                 }
             }
             __syncthreads();
         }
-        if (sub == 0 && row < r1 && j < k) write_y(Y + (int64_t)j * ldy, row, td, alpha, beta);
+        if (sub == 0 && row < r1) {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q)
+                if (q * LPR + j < k) write_y(Y + (int64_t)(q * LPR + j) * ldy, row, td[q], alpha, beta);
+        }
     }
 }
 
 // JDS, interleaved X.  The host splits the permuted rows (longest first) into
-// classes with GPR groups per row (enough that each group handles at most
-// about 32 of the row's diagonals); a workgroup holds NG/GPR rows of a class.
+// classes with GPR wavefronts per row set (enough that each handles at most
+// about 32 of a row's diagonals, GPR <= wavefronts per workgroup); a
+// workgroup holds NG/GPR rows of a class.
 struct MmClass {
     int32_t wg_end, row_start, row_end, gpr;
     int32_t len0;       // diagonals of the class's first (longest) row
@@ -178,18 +210,21 @@ struct MmPlan {
 };
 
 // One lane's share of a JDS row for the interleaved multi-vector kernel:
-// diagonals sub, sub + GPR, ... of row r, U per trip, stopping (for the whole
-// wavefront) where the wavefront's first and longest row r_first ends.
-template <int K2, bool WIDE, typename VT, typename XT>
-__device__ __forceinline__ double mm_jds_sum(const int32_t *__restrict__ jp, int32_t dlim,
-                                             const int32_t *__restrict__ col, const VT *__restrict__ val,
-                                             const XT *__restrict__ Xr, int32_t k, int j, int32_t r, bool ok,
-                                             int32_t r_first, int sub, int GPR)
+// columns j, j + LPR, ..., j + (CPL-1)*LPR over diagonals sub, sub + GPR, ...
+// of row r, U per trip, stopping (for the whole wavefront) where the
+// wavefront's first and longest row r_first ends.  Column t*LPR + j of the
+// row's LPR lanes is one contiguous run of LPR elements per load.
+template <int LPR, int CPL, bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ void mm_jds_sum(const int32_t *__restrict__ jp, int32_t dlim,
+                                           const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                           const XT *__restrict__ Xr, int32_t k, int j, int32_t r, bool ok,
+                                           int32_t r_first, int sub, int GPR, double (&out)[CPL])
 {
     typedef typename Acc<WIDE>::T acc_t;
     constexpr int U = 4;
-    const bool jok = j < k;
-    acc_t s = 0;
+    acc_t s[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) s[t] = 0;
     for (int32_t base = 0; base < dlim; base += GPR * U) {
         if (jp[base + 1] - jp[base] <= r_first) break;
         int32_t c[U];
@@ -208,14 +243,21 @@ __device__ __forceinline__ double mm_jds_sum(const int32_t *__restrict__ jp, int
                 }
             }
         }
-        XT xv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = (act[u] && jok) ? Xr[(int64_t)c[u] * k + j] : XT(0);
+        XT xv[U][CPL];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (act[u]) s = Acc<WIDE>::mac(s, v[u], xv[u]);
+#pragma unroll
+            for (int t = 0; t < CPL; ++t)
+                xv[u][t] = (act[u] && t * LPR + j < k) ? Xr[(int64_t)c[u] * k + t * LPR + j] : XT(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (act[u]) {
+#pragma unroll
+                for (int t = 0; t < CPL; ++t) s[t] = Acc<WIDE>::mac(s[t], v[u], xv[u][t]);
+            }
     }
-    return (double)s;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) out[t] = (double)s[t];
 }
 
 template <int K2, int NT, typename VT, typename XT>
@@ -227,7 +269,12 @@ __global__ __launch_bounds__(NT) void spmm_jds_il_kernel(int32_t ndiag, const in
                                                                  XT *__restrict__ Y, int64_t ldy, MmPlan P,
                                                                  double alpha, double beta)
 {
-    constexpr int NG = NT / K2;
+    // a row is handled by a group of LPR <= 8 lanes, lane j owning columns
+    // j, j + LPR, ..., so a wavefront holds at least 8 rows for any k
+    constexpr int LPR = mm_jds_lpr<K2, XT>();
+    constexpr int CPL = K2 / LPR;
+    constexpr int NG = NT / LPR;
+    constexpr int GPW = WAVE / LPR;            // rows per wavefront
     constexpr bool F64 = IsF64<VT>::value;
     __shared__ double part[NG][K2];
     const int64_t wg = blockIdx.x;
@@ -235,17 +282,20 @@ __global__ __launch_bounds__(NT) void spmm_jds_il_kernel(int32_t ndiag, const in
     while (ci < P.ncls - 1 && wg >= P.c[ci].wg_end) ++ci;
     const MmClass K = P.c[ci];
     const int64_t wg0 = ci ? P.c[ci - 1].wg_end : 0;
+    // a wavefront always holds GPW consecutive rows, so every val/col load
+    // of one diagonal covers GPW consecutive entries; a row set's diagonals
+    // are shared by GPR wavefronts (sub = 0..GPR-1, every GPR-th diagonal)
     const int GPR = K.gpr;
-    const int g = (int)threadIdx.x / K2, j = (int)threadIdx.x % K2;
-    const int sub = g % GPR;
-    const int64_t row64 = (int64_t)K.row_start + (wg - wg0) * (NG / GPR) + g / GPR;
+    const int g = (int)threadIdx.x / LPR, j = (int)threadIdx.x % LPR;
+    const int w = (int)threadIdx.x / WAVE, gl = g % GPW;
+    const int sub = w % GPR, rs = w / GPR;
+    const int64_t rs0 = (int64_t)K.row_start + (wg - wg0) * (NG / GPR) + (int64_t)rs * GPW;
+    const int64_t row64 = rs0 + gl;
     const bool ok = row64 < K.row_end;
     const int32_t r = (int32_t)(ok ? row64 : 0);
     // the wavefront's first row is its longest (rows are in JDS order): the
     // diagonal loop ends, for the whole wavefront, where that row ends
-    const int g_first = ((int)threadIdx.x / WAVE) * (WAVE / K2);
-    const int64_t rf64 = (int64_t)K.row_start + (wg - wg0) * (NG / GPR) + g_first / GPR;
-    const int32_t r_first = (int32_t)(rf64 < K.row_end ? rf64 : K.row_end);
+    const int32_t r_first = (int32_t)(rs0 < K.row_end ? rs0 : K.row_end);
     // the row's length decides the accumulator only for reduced-precision values
     bool wide = false;
     if (!F64 && ok && ndiag > SPMV_WIDE_ROW_NNZ) wide = jp[SPMV_WIDE_ROW_NNZ + 1] - jp[SPMV_WIDE_ROW_NNZ] > r;
@@ -258,30 +308,41 @@ __global__ __launch_bounds__(NT) void spmm_jds_il_kernel(int32_t ndiag, const in
         for (int32_t i = (int32_t)threadIdx.x; i <= dlim; i += NT) jp_s[i] = jp[i];
         __syncthreads();
     }
-    double td = 0.0;
+    double td[CPL];
     if (jp_lds) {
-        if (F64 || wide) td = mm_jds_sum<K2, true, VT, XT>(jp_s, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR);
-        else td = mm_jds_sum<K2, false, VT, XT>(jp_s, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR);
+        if (F64 || wide) mm_jds_sum<LPR, CPL, true, VT, XT>(jp_s, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR, td);
+        else mm_jds_sum<LPR, CPL, false, VT, XT>(jp_s, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR, td);
     } else {
-        if (F64 || wide) td = mm_jds_sum<K2, true, VT, XT>(jp, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR);
-        else td = mm_jds_sum<K2, false, VT, XT>(jp, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR);
+        if (F64 || wide) mm_jds_sum<LPR, CPL, true, VT, XT>(jp, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR, td);
+        else mm_jds_sum<LPR, CPL, false, VT, XT>(jp, dlim, col, val, Xr, k, j, r, ok, r_first, sub, GPR, td);
     }
     if (GPR > 1) {
-        part[g][j] = td;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) part[g][t * LPR + j] = td[t];
         __syncthreads();
         if (sub == 0 && ok) {
-            if (F64 || wide) {
-                double t = 0.0;
-                for (int q = 0; q < GPR; ++q) t += part[g + q][j];
-                td = t;
-            } else {
-                float t = 0.0f;
-                for (int q = 0; q < GPR; ++q) t += (float)part[g + q][j];
-                td = (double)t;
+            // the row's GPR partial sums sit in wavefronts rs*GPR .. rs*GPR+GPR-1, same lane group
+            const int g0 = rs * GPR * GPW + gl;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                if (F64 || wide) {
+                    double a = 0.0;
+                    for (int q = 0; q < GPR; ++q) a += part[g0 + q * GPW][t * LPR + j];
+                    td[t] = a;
+                } else {
+                    float a = 0.0f;
+                    for (int q = 0; q < GPR; ++q) a += (float)part[g0 + q * GPW][t * LPR + j];
+                    td[t] = (double)a;
+                }
             }
         }
     }
-    if (sub == 0 && ok && j < k) write_y(Y + (int64_t)j * ldy, symperm ? r : perm[r], td, alpha, beta);
+    if (sub == 0 && ok) {
+        const int32_t yi = symperm ? r : perm[r];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t)
+            if (t * LPR + j < k) write_y(Y + (int64_t)(t * LPR + j) * ldy, yi, td[t], alpha, beta);
+    }
 }
 
 static int k2_for(int32_t k)
@@ -291,7 +352,10 @@ static int k2_for(int32_t k)
     return K2;
 }
 
-static MmPlan plan_mm_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int NG)
+// NG row groups per workgroup, NW wavefronts per workgroup: a class's rows
+// get GPR = 1, 2, ..., NW wavefronts each (a power of two), NG / GPR rows per
+// workgroup.
+static MmPlan plan_mm_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int NG, int NW)
 {
     constexpr int64_t LT = 32;   // target diagonals per group
     MmPlan P{};
@@ -306,7 +370,7 @@ static MmPlan plan_mm_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int
     };
     auto gpr_of = [&](int64_t L) {
         int gpr = 1;
-        while (gpr < NG && gpr * LT < L) gpr *= 2;
+        while (gpr < NW && gpr * LT < L) gpr *= 2;
         return gpr;
     };
     int64_t row = 0, wgs = 0;
@@ -364,7 +428,7 @@ static void launch_jds_il(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, con
                           int64_t ldy, double alpha, double beta, hipStream_t s)
 {
     constexpr int NT = MM_JDS_THREADS;
-    const MmPlan P = plan_mm_jds(n, h_jd_ptr, ndiag, NT / K2);
+    const MmPlan P = plan_mm_jds(n, h_jd_ptr, ndiag, NT / mm_jds_lpr<K2, XT>(), NT / WAVE);
     if (P.ncls == 0) return;
     // room for the longest jd_ptr prefix a class stages (dlim + 1 <= min(ndiag + 1, MM_JP_LDS))
     const size_t lds = sizeof(int32_t) * (size_t)std::min<int64_t>((int64_t)ndiag + 1, MM_JP_LDS);
