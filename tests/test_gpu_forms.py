@@ -24,7 +24,7 @@ def colmajor_from(X_np, dtype):
     return t.t()
 
 
-@pytest.mark.parametrize("k", [1, 3, 8, 11, 32])
+@pytest.mark.parametrize("k", [1, 3, 8, 11, 32, 40, 64])
 def test_spmm_fp64(k):
     r, c, v, nr, nc, rng = rand_coo(60 + k, 6000, 5000, 0.002, empty_rows=0.1, long_rows=6, long_len=2000)
     R = oracle.csr_from_coo(nr, nc, r, c, v)
