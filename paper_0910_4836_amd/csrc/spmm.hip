@@ -74,7 +74,9 @@ __device__ __forceinline__ void mm_group_sum(const int32_t *__restrict__ col, co
     acc_t s[CPL];
 #pragma unroll
     for (int t = 0; t < CPL; ++t) s[t] = 0;
-    constexpr int U = 4;
+    // entries per trip: eight gathers in flight per lane (U * CPL = 8);
+    // measured at k = 8 (U = 8: 4-11% faster than 4) and k = 32 FP32 (U = 2)
+    constexpr int U = CPL >= 8 ? 1 : 8 / CPL;
     int64_t e = e_begin;
     for (; e + (U - 1) * e_step < e_end; e += U * e_step) {
         int32_t c[U];
@@ -221,7 +223,7 @@ __device__ __forceinline__ void mm_jds_sum(const int32_t *__restrict__ jp, int32
                                            int32_t r_first, int sub, int GPR, double (&out)[CPL])
 {
     typedef typename Acc<WIDE>::T acc_t;
-    constexpr int U = 4;
+    constexpr int U = 2;   // diagonals per trip (2 measured 1-2% faster than 4, 8 slower)
     acc_t s[CPL];
 #pragma unroll
     for (int t = 0; t < CPL; ++t) s[t] = 0;
