@@ -730,6 +730,10 @@ def suite_chebyshev(torch, sp, dev, steps):
     op = AG.SpMVOperator(A)
     vals = op.J.jd_val.clone()
     x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(5, 1), np.float32)).to(dev)
+    # the operator's JDS launch parameters from the library's autotuner, on this device
+    from paper_0910_4836_amd import autotune
+    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    op.unroll, op.max_iters, op.wg_waves = tuner.tune_jds(op.J, x)
     g = torch.ones(n, dtype=torch.float32, device=dev)
     y = torch.empty(n, dtype=torch.float32, device=dev)
     dv = torch.empty(nnz, dtype=torch.float32, device=dev)
@@ -746,6 +750,7 @@ def suite_chebyshev(torch, sp, dev, steps):
         AG.chebyshev_loss(op, vv, xx, 20, 5).backward()
     ms_fb, _ = time_loop(torch, [("cheb", fwd_bwd)], 5, 1)
     return {"workload": f"banded+uniform n={n} nnz={nnz} FP32, 20-step Chebyshev, checkpoint every 5", "kernels": kern,
+            "autotuned_jds": {"unroll": op.unroll, "max_iters": op.max_iters, "wg_waves": op.wg_waves},
             "loss_and_gradient_ms": round(ms_fb, 3),
             "spmv_equivalents_per_gradient": "20 forward + 15 recomputed + 20 transposed products + 20 value gradients"}
 
