@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads")
     ap.add_argument("--suite-lines", default="", help="comma list: run only these suite lines")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the step from the eager loop instead of HIP graph replays (profiler runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="", help="comma list of kernels for profiling runs")
     ap.add_argument("--probe", choices=["copy", "triad", "strides"], default=None,
@@ -998,7 +1000,7 @@ def main():
     # the step itself runs as one HIP graph of its products (no launch gaps
     # between them); the per-kernel times above come from the eager loop,
     # with events between the products
-    ms_step = graph_step_ms(torch, sp, ks, args.steps, args.warmup)
+    ms_step = ms_eager if args.no_graph else graph_step_ms(torch, sp, ks, args.steps, args.warmup)
     flops_step = 2.0 * W["nnz"] * len(ks)
     value = flops_step / (ms_step * 1e-3) / 1e9
     dom = max(per, key=per.get)
@@ -1012,8 +1014,9 @@ def main():
         "metric": "SpMV GFLOP/s + % of HBM code-balance roofline, CRS vs JDS, FP64 vs mixed",
         "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 5), "ms_per_step_eager": round(ms_eager, 5),
-        "step_timing": "K replays of one HIP graph holding the step's products; per-kernel times from an eager "
-                       "loop with HIP events between the products", "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "step_timing": ("eager loop with HIP events between the products" if args.no_graph else
+                        "K replays of one HIP graph holding the step's products; per-kernel times from an eager "
+                        "loop with HIP events between the products"), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"power-law n={W['n']} nnz={W['nnz']} (mean 15/row, max 2000): CRS, JDS and "
                                f"blocked JDS (C={W['tune']['blocked_C']}) products in FP64",
