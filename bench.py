@@ -689,18 +689,24 @@ def suite_spmm(torch, sp, dev, W, steps):
 
 def suite_batched(torch, sp, dev, steps, count=512):
     import synth
-    mats, xs = [], []
+    from paper_0910_4836_amd import autotune
+    jds, xs = [], []
     nnz = 0
     rows = 0
     for r, c, v, n, x in synth.many_matrices(count=count):
         A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev),
                             torch.from_numpy(v).to(dev))
-        mats.append(sp.jds_blocked_from_jds(sp.jds_from_csr(A), 64))
+        jds.append(sp.jds_from_csr(A))
         xs.append(torch.from_numpy(x).to(dev))
         nnz += A.nnz
         rows += n
         del A
-    Bt = sp.Batched(mats)
+    # slice height, rows per wavefront and unroll from the library's autotuner, on this device
+    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    bC, bR, bU = tuner.tune_batched(jds)
+    mats = [sp.jds_blocked_from_jds(J, bC) for J in jds]
+    del jds
+    Bt = sp.Batched(mats, rows_per_wave=bR or 64, unroll=bU)
     x = torch.cat(xs)
     y = torch.empty(Bt.total_rows, dtype=torch.float32, device=dev)
     g = sp.Graph()
@@ -719,7 +725,7 @@ def suite_batched(torch, sp, dev, steps, count=512):
     return {"workload": f"{count} matrices, n log-uniform [1e3, 2e5], 5-40 entries/row, FP32; sum n={rows}, "
                         f"sum nnz={nnz}", "persistent_graph": e,
             "persistent_eager_us": round(ms_eager * 1e3, 1), "one_launch_per_matrix_us": round(ms_loop * 1e3, 1),
-            "tiles": Bt.n_tiles, "rows_per_wave": Bt.rows_per_wave}
+            "tiles": Bt.n_tiles, "rows_per_wave": Bt.rows_per_wave, "autotuned": {"C": bC, "R": bR, "U": bU}}
 
 
 def suite_chebyshev(torch, sp, dev, steps):
