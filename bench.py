@@ -613,6 +613,10 @@ def suite_symdiag(torch, sp, dev, steps):
     Dd = sp.dia_from_csr(A)
     torch.cuda.synchronize()
     dia_ms = round((time.perf_counter() - t0) * 1e3, 1)
+    t0 = time.perf_counter()
+    Ds = sp.dia_from_csr(A, symmetric=True)
+    torch.cuda.synchronize()
+    dia_sym_ms = round((time.perf_counter() - t0) * 1e3, 1)
     nnz = A.nnz
     y_ref = sp.spmv_crs(A, x)
     out = {"workload": f"symmetric 12 secondary diagonals + diagonal, n={n}, nnz={nnz}", "kernels": {},
@@ -627,20 +631,29 @@ def suite_symdiag(torch, sp, dev, steps):
         Bq = B if vdt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
         Dq = Dd if vdt == torch.float64 else sp.DIA(Dd.n_rows, Dd.n_cols, Dd.offsets,
                                                     sp.spmv_convert_values(Dd.dia_val, vdt), Dd.rem)
+        Dsq = Ds if vdt == torch.float64 else sp.DIA(Ds.n_rows, Ds.n_cols, Ds.offsets,
+                                                     sp.spmv_convert_values(Ds.dia_val, vdt), Ds.rem, True)
         ks = [(f"crs_{tag}", lambda Aq=Aq: sp.spmv_crs(Aq, x, y)),
               (f"jds_{tag}", lambda Jq=Jq: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
               (f"blocked_{tag}", lambda Bq=Bq: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU,
                                                                     wg_waves=bW)),
-              (f"dia_{tag}", lambda Dq=Dq: sp.spmv_dia(Dq, x, y))]
+              (f"dia_{tag}", lambda Dq=Dq: sp.spmv_dia(Dq, x, y)),
+              (f"dia_sym_{tag}", lambda Dsq=Dsq: sp.spmv_dia(Dsq, x, y))]
         _, per = time_loop(torch, ks, max(10, steps // 4), 3)
         bm = {ks[0][0]: bytes_crs(nnz, n, n, sv, 8), ks[1][0]: bytes_jds(nnz, n, n, J.ndiag, sv, 8),
-              ks[2][0]: bytes_blocked(nnz, n, n, B.n_slices, sv, 8), ks[3][0]: bytes_dia(Dd, sv, 8)}
+              ks[2][0]: bytes_blocked(nnz, n, n, B.n_slices, sv, 8), ks[3][0]: bytes_dia(Dd, sv, 8),
+              ks[4][0]: bytes_dia(Ds, sv, 8)}
         for name, fn in ks:
             out["kernels"][name] = _kernel_entry(name, 2.0 * nnz, bm[name], per[name])
             fn()
             out["max_rel_err_vs_fp64"][name] = _rel_err_gpu(torch, sp, A, x, y, y_ref)
-        del Aq, Jq, Bq, Dq
-    out["dia"] = {"diagonals": Dd.ndia, "remainder_nnz": Dd.rem.nnz, "setup_ms": dia_ms}
+        del Aq, Jq, Bq, Dq, Dsq
+    out["dia"] = {"diagonals": Dd.ndia, "remainder_nnz": Dd.rem.nnz, "setup_ms": dia_ms,
+                  "stored_fp64_bytes": Dd.dia_val.numel() * 8}
+    # symmetric storage: the upper diagonals only, each read twice (its own
+    # rows and, shifted, its mirror's); the algorithmic bytes count it once
+    out["dia_sym"] = {"diagonals": Ds.ndia, "remainder_nnz": Ds.rem.nnz, "setup_ms": dia_sym_ms,
+                      "stored_fp64_bytes": Ds.dia_val.numel() * 8}
     # SOJDS (paper Section 2): the same slices with every row's entries
     # re-assigned to diagonal slots for near-unit x strides across rows
     t0 = time.perf_counter()

@@ -435,6 +435,32 @@ spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const
 spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets, const void *dia_val,
                      spmv_dtype val_dt, const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val,
                      const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream);
+/* Symmetric storage of the stored diagonals (the paper, Section 4.2, notes
+ * that its Hamiltonian is symmetric and that storing one triangle would
+ * halve the matrix).  For a square n x n matrix whose entries on the chosen
+ * diagonals are symmetric (a(i, i+o) == a(i+o, i)): only offsets o >= 0 are
+ * stored, diagonal k holding dia_val[k*n + i] = a(i, i + o_k); a diagonal is
+ * chosen when (count_o + count_-o) * (s_v + 4) >= span_o * s_v, at most
+ * max_diags, fullest first.  The entries below the main diagonal on a chosen
+ * diagonal's mirror are not read: they are taken to equal their mirrors.
+ * The remainder CRS holds every entry on neither a chosen diagonal nor its
+ * mirror (both triangles, CRS order).  Same calling pattern, workspace and
+ * outputs as spmv_dia_from_csr.  The stored diagonal bytes are half those of
+ * spmv_dia_from_csr on a matrix of symmetric pairs of diagonals. */
+spmv_status spmv_dia_sym_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                  const void *val, spmv_dtype dt, int32_t max_diags, int32_t *h_offsets,
+                                  int32_t *h_ndia, int64_t *h_rem_nnz, void *dia_val, int32_t *rem_row_ptr,
+                                  int32_t *rem_col, void *rem_val, void *ws, size_t ws_bytes, void *stream);
+/* y = alpha * A x + beta * y over the symmetric hybrid: row i adds
+ * dia[k][i] * x[i + o_k] for every stored diagonal (offset order), then
+ * dia[k][i - o_k] * x[i - o_k] for every o_k > 0 with i >= o_k (offset
+ * order), then its remainder entries; FP64 sums, one rounding of y.  Every
+ * term is a gather-free contiguous read (the mirror is the same diagonal
+ * shifted by o_k rows), so no row writes another row's y: deterministic,
+ * no atomics.  Offsets must be >= 0, increasing, < n. */
+spmv_status spmv_dia_sym(int32_t n, int32_t ndia, const int32_t *h_offsets, const void *dia_val, spmv_dtype val_dt,
+                         const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val, const void *x,
+                         void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream);
 
 /* ======================================================================== */
 /* Many matrices in one launch                                               */

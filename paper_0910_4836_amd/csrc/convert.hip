@@ -630,10 +630,14 @@ __global__ void dia_index_kernel(int64_t m, int32_t *__restrict__ oidx)
     GRID_LOOP(t, m) oidx[t] = -1;
 }
 
-__global__ void dia_index_set_kernel(int32_t n_rows, DiaOffsets D, int32_t *__restrict__ oidx)
+// stored diagonal k: oidx = k; with `sym`, its mirror -off (off > 0) gets
+// SPMV_DIA_MAX + k: covered by the stored diagonal, kept out of the remainder
+__global__ void dia_index_set_kernel(int32_t n_rows, DiaOffsets D, int sym, int32_t *__restrict__ oidx)
 {
     const int k = (int)threadIdx.x;
-    if (k < D.n) oidx[(int64_t)D.off[k] + n_rows - 1] = k;
+    if (k >= D.n) return;
+    oidx[(int64_t)D.off[k] + n_rows - 1] = k;
+    if (sym && D.off[k] > 0) oidx[(int64_t)n_rows - 1 - D.off[k]] = SPMV_DIA_MAX + k;
 }
 
 template <typename T>
@@ -654,8 +658,8 @@ __global__ void dia_scatter_kernel(const int32_t *__restrict__ rp, int32_t n_row
         int32_t cnt = 0;
         for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
             const int32_t k = oidx[(int64_t)col[e] - i + n_rows - 1];
-            if (k >= 0) dia[(int64_t)k * n_rows + i] = val[e];
-            else ++cnt;
+            if (k < 0) ++cnt;
+            else if (k < SPMV_DIA_MAX) dia[(int64_t)k * n_rows + i] = val[e];
         }
         rem_cnt[i] = cnt;
     }
@@ -1306,21 +1310,24 @@ size_t spmv_dia_workspace_size(int32_t n_rows, int32_t n_cols)
            align_up(sizeof(int32_t) * scan_ws_elems((int64_t)nn), 256) + 1024;
 }
 
-spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
-                              const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t max_diags,
-                              int32_t *h_offsets, int32_t *h_ndia, int64_t *h_rem_nnz, void *dia_val,
-                              int32_t *rem_row_ptr, int32_t *rem_col, void *rem_val, void *ws, size_t ws_bytes,
-                              void *stream)
+}  // extern "C"
+
+namespace spmv {
+static spmv_status dia_from_csr_impl(bool sym, int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                                     const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t max_diags,
+                                     int32_t *h_offsets, int32_t *h_ndia, int64_t *h_rem_nnz, void *dia_val,
+                                     int32_t *rem_row_ptr, int32_t *rem_col, void *rem_val, void *ws, size_t ws_bytes,
+                                     void *stream)
 {
-    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && nnz >= 0, "spmv_dia_from_csr: negative size");
-    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_dia_from_csr: nnz >= 2^31");
-    SPMV_REQUIRE(valid_dtype(dt), "spmv_dia_from_csr: bad dtype");
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0 && nnz >= 0, "spmv_dia[_sym]_from_csr: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_dia[_sym]_from_csr: nnz >= 2^31");
+    SPMV_REQUIRE(valid_dtype(dt), "spmv_dia[_sym]_from_csr: bad dtype");
     if (max_diags == 0) max_diags = SPMV_DIA_MAX;
-    SPMV_REQUIRE(max_diags > 0 && max_diags <= SPMV_DIA_MAX, "spmv_dia_from_csr: max_diags must be 0..SPMV_DIA_MAX");
-    SPMV_REQUIRE(h_offsets && h_ndia && h_rem_nnz, "spmv_dia_from_csr: null host output");
-    SPMV_REQUIRE(n_rows == 0 || row_ptr, "spmv_dia_from_csr: null row_ptr");
-    SPMV_REQUIRE(nnz == 0 || (col_idx && val), "spmv_dia_from_csr: null col_idx or val");
-    SPMV_REQUIRE(ws && ws_bytes >= spmv_dia_workspace_size(n_rows, n_cols), "spmv_dia_from_csr: workspace too small");
+    SPMV_REQUIRE(max_diags > 0 && max_diags <= SPMV_DIA_MAX, "spmv_dia[_sym]_from_csr: max_diags must be 0..SPMV_DIA_MAX");
+    SPMV_REQUIRE(h_offsets && h_ndia && h_rem_nnz, "spmv_dia[_sym]_from_csr: null host output");
+    SPMV_REQUIRE(n_rows == 0 || row_ptr, "spmv_dia[_sym]_from_csr: null row_ptr");
+    SPMV_REQUIRE(nnz == 0 || (col_idx && val), "spmv_dia[_sym]_from_csr: null col_idx or val");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_dia_workspace_size(n_rows, n_cols), "spmv_dia[_sym]_from_csr: workspace too small");
     hipStream_t s = as_stream(stream);
     const int64_t m = (int64_t)(n_rows > 0 ? n_rows : 1) + (n_cols > 0 ? n_cols : 1) - 1;
     const size_t nn = (size_t)(n_rows > 0 ? n_rows : 1);
@@ -1328,7 +1335,7 @@ spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const
     int32_t *hist = wc.take<int32_t>((size_t)m);           // later: offset -> stored diagonal index
     int32_t *cnt = wc.take<int32_t>(nn);
     int32_t *scan_ws = wc.take<int32_t>(scan_ws_elems((int64_t)nn));
-    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_dia_from_csr: workspace too small");
+    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_dia[_sym]_from_csr: workspace too small");
 
     // entries per offset
     std::vector<int32_t> h_hist((size_t)m, 0);
@@ -1340,13 +1347,17 @@ spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const
         SPMV_HIP(hipStreamSynchronize(s));
     }
     // a diagonal is stored densely when its dense span costs no more bytes
-    // than its entries do in CRS (value + 4-byte index); the fullest first
+    // than its entries do in CRS (value + 4-byte index); the fullest first.
+    // Symmetric: only offsets >= 0 are stored, each also serving its mirror,
+    // so its entries are those of offset o and -o
     const int64_t sv = (int64_t)dtype_size(dt);
     std::vector<std::pair<int32_t, int64_t>> cand;            // (count, offset)
     for (int64_t t = 0; t < m; ++t) {
-        const int64_t c = h_hist[(size_t)t];
-        if (c == 0) continue;
         const int64_t o = t - (n_rows - 1);
+        if (sym && o < 0) continue;
+        int64_t c = h_hist[(size_t)t];
+        if (sym && o > 0) c += h_hist[(size_t)(n_rows - 1 - o)];
+        if (c == 0) continue;
         const int64_t span = std::min<int64_t>(n_rows, (int64_t)n_cols - o) - std::max<int64_t>(0, -o);
         if (c * (sv + 4) >= span * sv) cand.push_back({(int32_t)c, o});
     }
@@ -1367,10 +1378,10 @@ spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const
     *h_rem_nnz = nnz - on_dia;
     if (!dia_val) return SPMV_OK;                            // sizes only
 
-    SPMV_REQUIRE(rem_row_ptr && (*h_rem_nnz == 0 || (rem_col && rem_val)), "spmv_dia_from_csr: null output");
+    SPMV_REQUIRE(rem_row_ptr && (*h_rem_nnz == 0 || (rem_col && rem_val)), "spmv_dia[_sym]_from_csr: null output");
     if (n_rows > 0) {
         dia_index_kernel<<<grid_for(m), 256, 0, s>>>(m, hist);
-        dia_index_set_kernel<<<1, SPMV_DIA_MAX, 0, s>>>(n_rows, D, hist);
+        dia_index_set_kernel<<<1, SPMV_DIA_MAX, 0, s>>>(n_rows, D, sym ? 1 : 0, hist);
         SPMV_CHECK_LAUNCH("dia index");
     }
     const int64_t ndv = (int64_t)D.n * n_rows;
@@ -1394,6 +1405,29 @@ spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const
 #undef DIA_CASE
     SPMV_HIP(hipStreamSynchronize(s));
     return SPMV_OK;
+}
+
+}  // namespace spmv
+
+extern "C" {
+
+spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t max_diags,
+                              int32_t *h_offsets, int32_t *h_ndia, int64_t *h_rem_nnz, void *dia_val,
+                              int32_t *rem_row_ptr, int32_t *rem_col, void *rem_val, void *ws, size_t ws_bytes,
+                              void *stream)
+{
+    return dia_from_csr_impl(false, n_rows, n_cols, nnz, row_ptr, col_idx, val, dt, max_diags, h_offsets, h_ndia,
+                             h_rem_nnz, dia_val, rem_row_ptr, rem_col, rem_val, ws, ws_bytes, stream);
+}
+
+spmv_status spmv_dia_sym_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                  const void *val, spmv_dtype dt, int32_t max_diags, int32_t *h_offsets,
+                                  int32_t *h_ndia, int64_t *h_rem_nnz, void *dia_val, int32_t *rem_row_ptr,
+                                  int32_t *rem_col, void *rem_val, void *ws, size_t ws_bytes, void *stream)
+{
+    return dia_from_csr_impl(true, n, n, nnz, row_ptr, col_idx, val, dt, max_diags, h_offsets, h_ndia, h_rem_nnz,
+                             dia_val, rem_row_ptr, rem_col, rem_val, ws, ws_bytes, stream);
 }
 
 size_t spmv_split_rows_workspace_size(void) { return 2 * align_up(sizeof(int64_t) * (SPLIT_PARTS + 1), 256); }

@@ -10,6 +10,12 @@
 // and x loads are in flight per lane.  Workgroups are remapped so that each
 // XCD walks a contiguous range of rows and keeps its x windows in its L2.
 // Every row is summed in FP64 in a fixed order and y is written once.
+//
+// Symmetric storage (the paper notes its Hamiltonian is symmetric): only the
+// diagonals with offset >= 0 are stored and each also stands for its mirror,
+// whose entry a(i, i - o) = dia[k][i - o] is the same diagonal read o rows
+// earlier: another contiguous stream, so every lane still writes only its own
+// row of y.
 #include "common.hpp"
 
 namespace spmv {
@@ -28,7 +34,10 @@ struct DiaArgs {
     double alpha, beta;
 };
 
-template <typename VT, typename XT>
+// SYM: the stored offsets are >= 0 and diagonal k (offset o > 0) also holds
+// the mirrored entries a(i, i - o) = a(i - o, i) = dia[k][i - o]; the row adds
+// its upper terms in offset order, then its mirrored terms in offset order.
+template <typename VT, typename XT, bool SYM>
 __global__ __launch_bounds__(DIA_THREADS) void dia_kernel(DiaArgs a)
 {
     const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * DIA_THREADS + threadIdx.x;
@@ -59,6 +68,31 @@ __global__ __launch_bounds__(DIA_THREADS) void dia_kernel(DiaArgs a)
         const int64_t j = i + a.off[k];
         if (j >= 0 && j < a.n_cols) s = fma(to_f64(ld_stream(dia + (int64_t)k * a.n_rows)), to_f64(x[j]), s);
     }
+    if (SYM) {
+        k = 0;
+        for (; k + U <= a.ndia; k += U) {
+            VT v[U];
+            XT xv[U];
+            bool in[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = i - a.off[k + u];
+                in[u] = a.off[k + u] > 0 && j >= 0;
+                if (in[u]) {
+                    v[u] = ld_stream((const VT *)a.dia + (int64_t)(k + u) * a.n_rows + j);
+                    xv[u] = x[j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (in[u]) s = fma(to_f64(v[u]), to_f64(xv[u]), s);
+        }
+        for (; k < a.ndia; ++k) {
+            const int64_t j = i - a.off[k];
+            if (a.off[k] > 0 && j >= 0)
+                s = fma(to_f64(ld_stream((const VT *)a.dia + (int64_t)k * a.n_rows + j)), to_f64(x[j]), s);
+        }
+    }
     if (a.rem_rp) {
         const VT *__restrict__ rv = (const VT *)a.rem_val;
         for (int32_t e = a.rem_rp[i]; e < a.rem_rp[i + 1]; ++e) s = fma(to_f64(rv[e]), to_f64(x[a.rem_col[e]]), s);
@@ -66,15 +100,11 @@ __global__ __launch_bounds__(DIA_THREADS) void dia_kernel(DiaArgs a)
     write_y((XT *)a.y, i, s, a.alpha, a.beta);
 }
 
-}  // namespace spmv
-
-using namespace spmv;
-
-extern "C" {
-
-spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets, const void *dia_val,
-                     spmv_dtype val_dt, const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val,
-                     const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream)
+template <bool SYM>
+static spmv_status dia_product(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets,
+                               const void *dia_val, spmv_dtype val_dt, const int32_t *rem_row_ptr,
+                               const int32_t *rem_col, const void *rem_val, const void *x, void *y, spmv_dtype vec_dt,
+                               double alpha, double beta, void *stream)
 {
     SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0, "spmv_dia: negative size");
     SPMV_REQUIRE(ndia >= 0 && ndia <= SPMV_DIA_MAX, "spmv_dia: ndia must be 0..SPMV_DIA_MAX");
@@ -89,6 +119,7 @@ spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t
     a.ndia = ndia;
     for (int k = 0; k < ndia; ++k) {
         SPMV_REQUIRE(h_offsets[k] > -n_rows && h_offsets[k] < n_cols, "spmv_dia: offset outside the matrix");
+        SPMV_REQUIRE(!SYM || h_offsets[k] >= 0, "spmv_dia_sym: offsets must be >= 0 (upper diagonals)");
         SPMV_REQUIRE(k == 0 || h_offsets[k] > h_offsets[k - 1], "spmv_dia: offsets must increase");
         a.off[k] = h_offsets[k];
     }
@@ -104,7 +135,7 @@ spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t
     const unsigned grid = (unsigned)ceil_div(n_rows, DIA_THREADS);
 #define DIA_CASE(VDT, VT, XDT, XT)                                          \
     if (val_dt == VDT && vec_dt == XDT) {                                   \
-        dia_kernel<VT, XT><<<grid, DIA_THREADS, 0, s>>>(a);                 \
+        dia_kernel<VT, XT, SYM><<<grid, DIA_THREADS, 0, s>>>(a);            \
         SPMV_CHECK_LAUNCH("spmv_dia");                                      \
         return SPMV_OK;                                                     \
     }
@@ -116,6 +147,28 @@ spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t
     DIA_CASE(SPMV_F64, double, SPMV_F32, float)
 #undef DIA_CASE
     return fail(SPMV_ERR_UNSUPPORTED, "spmv_dia: dtype combination");
+}
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" {
+
+spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets, const void *dia_val,
+                     spmv_dtype val_dt, const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val,
+                     const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream)
+{
+    return dia_product<false>(n_rows, n_cols, ndia, h_offsets, dia_val, val_dt, rem_row_ptr, rem_col, rem_val, x, y,
+                              vec_dt, alpha, beta, stream);
+}
+
+spmv_status spmv_dia_sym(int32_t n, int32_t ndia, const int32_t *h_offsets, const void *dia_val, spmv_dtype val_dt,
+                         const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val, const void *x,
+                         void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream)
+{
+    return dia_product<true>(n, n, ndia, h_offsets, dia_val, val_dt, rem_row_ptr, rem_col, rem_val, x, y, vec_dt,
+                             alpha, beta, stream);
 }
 
 }  // extern "C"

@@ -698,32 +698,39 @@ class DIA:
     offsets: np.ndarray          # int32, ascending, host
     dia_val: torch.Tensor        # ndia * n_rows values, diagonal after diagonal
     rem: CSR                     # the entries on no stored diagonal
+    symmetric: bool = False      # offsets >= 0, each diagonal also serves its mirror
 
     @property
     def ndia(self) -> int:
         return len(self.offsets)
 
 
-def dia_from_csr(A: CSR, max_diags: int = 0) -> DIA:
-    """CRS -> DIA + CRS hybrid on the GPU (spmv_dia_from_csr)."""
+def dia_from_csr(A: CSR, max_diags: int = 0, symmetric: bool = False) -> DIA:
+    """CRS -> DIA + CRS hybrid on the GPU (spmv_dia_from_csr; with
+    symmetric=True, spmv_dia_sym_from_csr: upper diagonals only, each also
+    standing for its mirror, for a square matrix symmetric on them)."""
     lib = _lib.load()
     dev = A.device
+    if symmetric and A.n_rows != A.n_cols:
+        raise ValueError("symmetric storage needs a square matrix")
     ws = _ws(lib.spmv_dia_workspace_size(A.n_rows, A.n_cols), dev)
     offs = np.zeros(_lib.DIA_MAX, dtype=np.int32)
     nd = C.c_int32(0)
     rem_nnz = C.c_int64(0)
-    args = lambda dv, rp, rc, rv: (A.n_rows, A.n_cols, A.nnz, _p(A.row_ptr), _p(A.col_idx), _p(A.val),
+    shape = (A.n_rows,) if symmetric else (A.n_rows, A.n_cols)
+    fn = "spmv_dia_sym_from_csr" if symmetric else "spmv_dia_from_csr"
+    args = lambda dv, rp, rc, rv: (*shape, A.nnz, _p(A.row_ptr), _p(A.col_idx), _p(A.val),
                                    dtype_code(A.val.dtype), max_diags, _h_i32(offs), C.byref(nd), C.byref(rem_nnz),
                                    dv, rp, rc, rv, _p(ws), ws.numel(), _stream())
-    call("spmv_dia_from_csr", *args(None, None, None, None))
+    call(fn, *args(None, None, None, None))
     k, m = nd.value, rem_nnz.value
     dia_val = torch.empty(max(k * A.n_rows, 1), dtype=A.val.dtype, device=dev)
     rem_rp = torch.empty(A.n_rows + 1, dtype=_I32, device=dev)
     rem_col = torch.empty(max(m, 1), dtype=_I32, device=dev)
     rem_val = torch.empty(max(m, 1), dtype=A.val.dtype, device=dev)
-    call("spmv_dia_from_csr", *args(_p(dia_val), _p(rem_rp), _p(rem_col), _p(rem_val)))
+    call(fn, *args(_p(dia_val), _p(rem_rp), _p(rem_col), _p(rem_val)))
     return DIA(A.n_rows, A.n_cols, offs[:k].copy(), dia_val[:k * A.n_rows],
-               CSR(A.n_rows, A.n_cols, rem_rp, rem_col[:m], rem_val[:m]))
+               CSR(A.n_rows, A.n_cols, rem_rp, rem_col[:m], rem_val[:m]), symmetric)
 
 
 def spmv_dia(D: DIA, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
@@ -732,9 +739,11 @@ def spmv_dia(D: DIA, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: f
     _check_dev(x)
     y = _out_vec(y, D.n_rows, x, beta)
     has_rem = D.rem.nnz > 0
-    call("spmv_dia", D.n_rows, D.n_cols, D.ndia, _h_i32(D.offsets), _p(D.dia_val), dtype_code(D.dia_val.dtype),
-         _p(D.rem.row_ptr) if has_rem else None, _p(D.rem.col_idx) if has_rem else None,
-         _p(D.rem.val) if has_rem else None, _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), _stream())
+    shape = (D.n_rows,) if D.symmetric else (D.n_rows, D.n_cols)
+    call("spmv_dia_sym" if D.symmetric else "spmv_dia", *shape, D.ndia, _h_i32(D.offsets), _p(D.dia_val),
+         dtype_code(D.dia_val.dtype), _p(D.rem.row_ptr) if has_rem else None,
+         _p(D.rem.col_idx) if has_rem else None, _p(D.rem.val) if has_rem else None, _p(x), _p(y),
+         dtype_code(x.dtype), float(alpha), float(beta), _stream())
     return y
 
 

@@ -80,6 +80,10 @@ def test_host_side_validation_without_gpu():
     # launch shape: 4, 8 or 16 wavefronts per workgroup
     st = lib.spmv_jds(10, None, None, None, 0, None, None, 0, None, None, 0, 1.0, 0.0, 0, 0, 12, 0, None)
     assert st == 1 and b"wg_waves" in lib.spmv_last_error()
+    # symmetric DIA: upper diagonals only
+    offs = np.array([-3], dtype=np.int32)
+    st = lib.spmv_dia_sym(10, 1, spmv_mod._h_i32(offs), 1, 0, None, None, None, 1, 1, 0, 1.0, 0.0, None)
+    assert st == 1 and b">= 0" in lib.spmv_last_error()
     # access-pattern probe: a stride of at least 1
     st = lib.spmv_stride_probe(100, 0, None, None, None, 0, None, 0, None)
     assert st == 1 and b"k < 1" in lib.spmv_last_error()

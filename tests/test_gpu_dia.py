@@ -156,3 +156,112 @@ def test_dia_reduced_precision_values(dt):
     D = sp.dia_from_csr(Aq)
     got = to_np(sp.spmv_dia(D, to_dev(x)))
     assert np.all(np.abs(got - want) <= gamma(Rq.row_lengths() + 1, U64) * Dm)
+
+
+# ---- symmetric storage: upper diagonals, each also serving its mirror
+
+
+def symmetric_planted(seed, n, full=(0, 3, 500), partial=((40, 0.8), (7, 0.3)), scatter=0.001):
+    """Upper-triangle entries (whole diagonals `full`, diagonals filled with a
+    given probability, scattered entries) mirrored with equal values."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for o in full:
+        i = np.arange(0, n - o)
+        rows.append(i)
+        cols.append(i + o)
+    for o, p in partial:
+        i = np.arange(0, n - o)
+        i = i[rng.random(len(i)) < p]
+        rows.append(i)
+        cols.append(i + o)
+    m = int(scatter * n * n)
+    a, b = rng.integers(0, n, m), rng.integers(0, n, m)
+    rows.append(np.minimum(a, b))
+    cols.append(np.maximum(a, b))
+    key = np.unique(np.concatenate(rows).astype(np.int64) * n + np.concatenate(cols))
+    r, c = key // n, key % n
+    v = rng.standard_normal(len(r))
+    off = r != c
+    R = np.concatenate([r, c[off]])
+    Cc = np.concatenate([c, r[off]])
+    V = np.concatenate([v, v[off]])
+    order = np.argsort(R * n + Cc, kind="stable")
+    return R[order].astype(np.int32), Cc[order].astype(np.int32), V[order], n, rng
+
+
+def sym_rule_offsets(R: oracle.CSR, sv, max_diags):
+    off = R.col.astype(np.int64) - R.row_index()
+    o, cnt = np.unique(off, return_counts=True)
+    count = dict(zip(o.tolist(), cnt.tolist()))
+    keep = []
+    for d in sorted(k for k in count if k >= 0):
+        c = count[d] + (count.get(-d, 0) if d > 0 else 0)
+        if c * (sv + 4) >= (R.n_rows - d) * sv:
+            keep.append((c, d))
+    keep.sort(key=lambda t: (-t[0], t[1]))
+    return np.sort(np.array([d for _, d in keep[:max_diags]], dtype=np.int64))
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_dia_sym_structure(dt):
+    r, c, v, n, _ = symmetric_planted(11, 3000)
+    v = v.astype(np.float32).astype(np.float64) if dt == torch.float32 else v
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    D = sp.dia_from_csr(gpu_csr(sp, r, c, v, n, n, dt), symmetric=True)
+    want = sym_rule_offsets(R, 8 if dt == torch.float64 else 4, 64)
+    assert D.symmetric and D.offsets.tolist() == want.tolist()
+    assert set(want.tolist()) >= {0, 3, 40, 500}
+    rows = R.row_index()
+    off = R.col.astype(np.int64) - rows
+    up = np.isin(off, want)
+    dense = np.zeros((len(want), n))
+    dense[np.searchsorted(want, off[up]), rows[up]] = R.val[up]
+    assert np.array_equal(to_np(D.dia_val).astype(np.float64).reshape(len(want), n), dense)
+    covered = np.isin(np.abs(off), want)
+    cnt = np.bincount(rows[~covered], minlength=n)
+    assert np.array_equal(to_np(D.rem.row_ptr), np.concatenate([[0], np.cumsum(cnt)]))
+    assert np.array_equal(to_np(D.rem.col_idx), R.col[~covered])
+    assert np.array_equal(to_np(D.rem.val).astype(np.float64), R.val[~covered])
+
+
+@pytest.mark.parametrize("case", ["planted", "symmetric_diagonals"])
+def test_dia_sym_fp64_parity(case):
+    if case == "planted":
+        r, c, v, n, _ = symmetric_planted(12, 4000)
+    else:
+        r, c, v, n, _ = synth.sym_diagonals(n=30000, ndiag=12)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    D = sp.dia_from_csr(gpu_csr(sp, r, c, v, n, n), symmetric=True)
+    full = sp.dia_from_csr(gpu_csr(sp, r, c, v, n, n))
+    if case == "symmetric_diagonals":
+        assert D.ndia == 13 and D.rem.nnz == 0 and full.ndia == 25
+        assert D.dia_val.numel() * 25 == full.dia_val.numel() * 13          # half the stored diagonals
+    rng = np.random.default_rng(13)
+    x = rng.uniform(-1, 1, n)
+    y0 = rng.uniform(-1, 1, n)
+    for alpha, beta in ((1.0, 0.0), (-0.75, 2.0)):
+        want = oracle.spmv_crs(R, x, y0 if beta else None, alpha, beta)
+        Dm = abs(alpha) * oracle.row_absdot(R, x) + (abs(beta) * np.abs(y0) if beta else 0)
+        got = sp.spmv_dia(D, to_dev(x), to_dev(y0.copy()) if beta else None, alpha, beta)
+        assert max_err(got, want, Dm) <= FP64_TOL, (alpha, beta)
+    x32 = x.astype(np.float32)
+    want = oracle.spmv_crs(R, x32.astype(np.float64))
+    Dm = oracle.row_absdot(R, x32.astype(np.float64))
+    got = to_np(sp.spmv_dia(D, to_dev(x32))).astype(np.float64)
+    assert np.all(np.abs(got - want) <= (U32 + gamma(R.row_lengths() + 1, U64)) * Dm)
+
+
+def test_dia_sym_integer_exact_and_reduced_values():
+    r, c, _, n, rng = symmetric_planted(14, 3000)
+    key = np.minimum(r, c).astype(np.int64) * n + np.maximum(r, c)          # equal values on mirrored pairs
+    v = (np.random.default_rng(15).integers(-8, 9, key.max() + 1)[key]).astype(np.float64)
+    x = synth.integer_vector(n, rng)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    want = oracle.spmv_crs(R, x)
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        A = gpu_csr(sp, r, c, v, n, n)
+        D = sp.dia_from_csr(A.with_values(sp.spmv_convert_values(A.val, dt)), symmetric=True)
+        assert np.array_equal(to_np(sp.spmv_dia(D, to_dev(x))), want), dt
+    with pytest.raises(ValueError):
+        sp.dia_from_csr(gpu_csr(sp, r[r < 2000], c[r < 2000], v[r < 2000], 2000, n), symmetric=True)
