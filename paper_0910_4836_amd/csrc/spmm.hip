@@ -23,7 +23,10 @@ namespace spmv {
 // are handled in rounds that each wait on their gathers, and 128-lane groups
 // for k <= 8 keep more rounds in flight (10-14% faster than 256); the JDS
 // kernel's classes favour larger groups (512: 3-5% faster than 256).
-constexpr int mm_crs_threads(int K2) { return K2 <= 8 ? 128 : 256; }
+// CRS workgroup size: 128 lanes for k <= 8 and for FP32 above (1.10x faster
+// than 256 at k = 32), 256 for FP64 above 8 (128: 5% slower).
+template <int K2, typename XT>
+constexpr int mm_crs_threads() { return (K2 <= 8 || sizeof(XT) == 4) ? 128 : 256; }
 // Lanes per row group (LPR) for k > 8: each lane owns k / LPR columns, so a
 // wavefront keeps 64 / LPR rows' gathers in flight.  Measured on the
 // power-law matrix at k = 32: CRS is fastest with 16 lanes for FP64 vectors
@@ -419,7 +422,7 @@ static void launch_crs_il(const int32_t *row_ptr, const int32_t *col, const void
                           double beta, hipStream_t s)
 {
     const size_t lds = (size_t)((block_nnz + 3) & ~3) * 4 + (size_t)block_nnz * sizeof(VT);
-    constexpr int NT = mm_crs_threads(K2);
+    constexpr int NT = mm_crs_threads<K2, XT>();
     spmm_crs_il_kernel<K2, NT, VT, XT><<<nb, NT, lds, s>>>(row_ptr, col, (const VT *)val, (const XT *)Xr, k,
                                                           (XT *)Y, ldy, plan, block_nnz, alpha, beta);
 }
