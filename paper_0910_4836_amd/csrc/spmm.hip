@@ -23,10 +23,11 @@ namespace spmv {
 // are handled in rounds that each wait on their gathers, and 128-lane groups
 // for k <= 8 keep more rounds in flight (10-14% faster than 256); the JDS
 // kernel's classes favour larger groups (512: 3-5% faster than 256).
-// CRS workgroup size: 128 lanes for k <= 8 and for FP32 above (1.10x faster
-// than 256 at k = 32), 256 for FP64 above 8 (128: 5% slower).
+// CRS workgroup size: one wavefront for FP32 vectors (against 128 lanes:
+// 1.14x faster at k = 8, 1.01x at k = 32; 256 lanes at k = 32: 1.13x slower),
+// 128 lanes for FP64 up to k = 8 (64: 4% slower), 256 above (128: 5% slower).
 template <int K2, typename XT>
-constexpr int mm_crs_threads() { return (K2 <= 8 || sizeof(XT) == 4) ? 128 : 256; }
+constexpr int mm_crs_threads() { return sizeof(XT) == 4 ? 64 : (K2 <= 8 ? 128 : 256); }
 // Lanes per row group (LPR) for k > 8: each lane owns k / LPR columns, so a
 // wavefront keeps 64 / LPR rows' gathers in flight.  Measured on the
 // power-law matrix at k = 32: CRS is fastest with 16 lanes for FP64 vectors
