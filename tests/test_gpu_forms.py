@@ -174,6 +174,48 @@ def test_graph_replay_of_single_matrix_kernels():
             assert torch.equal(o, e), rep
 
 
+def test_graph_replay_of_split_dia_and_multivector_calls():
+    """The other compute calls are capturable too: column and row split,
+    DIA (full and symmetric) and the interleaved multi-vector products
+    (staging kernel + product) replay bit-identically to their eager runs,
+    with eager work between the replays."""
+    r, c, v, n, _, rng = rand_coo(81, 12000, 12000, 0.001, long_rows=6, long_len=2500)
+    off = r != c                                                      # a symmetric matrix for DIA
+    rs, cs, vs = np.concatenate([r, c[off]]), np.concatenate([c, r[off]]), np.concatenate([v, v[off]])
+    A = gpu_csr(sp, rs, cs, vs, n, n)
+    sp.spmv_crs_plan(A)
+    J = sp.jds_from_csr(A)
+    S, RS = sp.Split(A), sp.RowSplit(A)
+    D, Ds = sp.dia_from_csr(A), sp.dia_from_csr(A, symmetric=True)
+    x = to_dev(rng.uniform(-1, 1, n))
+    X = colmajor_from(rng.uniform(-1, 1, (n, 8)), torch.float64)
+    ws = sp.spmm_workspace(n, 8, torch.float64, "cuda")
+    calls = [lambda y: sp.spmv_crs_split(S, x, y), lambda y: sp.spmv_jds_split(S, x, y),
+             lambda y: sp.spmv_jds_row_split(RS, x, y), lambda y: sp.spmv_dia(D, x, y),
+             lambda y: sp.spmv_dia(Ds, x, y), lambda Y: sp.spmm_crs(A, X, Y, ws=ws),
+             lambda Y: sp.spmm_jds(J, X, Y, ws=ws)]
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(5)] + \
+           [sp.colmajor(n, 8, torch.float64, "cuda") for _ in range(2)]
+    eager = []
+    for fn, o in zip(calls, outs):
+        fn(o)
+        eager.append(o.clone())
+    g = sp.Graph()
+    with g.capture():
+        for fn, o in zip(calls, outs):
+            fn(o)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (o, e) in enumerate(zip(outs, eager)):
+            assert torch.equal(o, e), (rep, i)
+        sp.spmv_crs(A, x)                                             # eager work between replays
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("transpose", ["crs", "jds"])
 def test_transposed_product_and_value_gradient(transpose):
     from paper_0910_4836_amd.autograd import SpMVOperator
