@@ -114,6 +114,137 @@ __device__ __forceinline__ void mm_group_sum(const int32_t *__restrict__ col, co
     for (int t = 0; t < CPL; ++t) out[t] = (double)s[t];
 }
 
+// Entry-balanced multi-row block (staged in LDS): group g takes the g-th of
+// NG equal shares [cs, ce) of the block's entries, walks them in order and
+// sums row by row, so no group waits on a longer row than its neighbours.
+// A row that starts and ends inside the share is written directly; a row
+// crossing a share boundary leaves its pieces in LDS (tail: the piece in the
+// share where it starts; lead: its pieces in later shares) and the group
+// where it starts adds them in share order.  Empty rows (beta*y) are written
+// by the group whose share holds their position; those after the last entry
+// by the last group.
+template <int LPR, int CPL, int NG, int K2, bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ void mm_crs_balanced(const int32_t *__restrict__ row_ptr, int32_t r0, int32_t r1,
+                                                int32_t be0, const int32_t *col_s, const VT *val_s,
+                                                const XT *__restrict__ Xr, int32_t k, XT *__restrict__ Y,
+                                                int64_t ldy, double alpha, double beta, int g, int j,
+                                                double (*lead)[K2], double (*tail)[K2], int32_t *lead_row,
+                                                int32_t *tail_row)
+{
+    typedef typename Acc<WIDE>::T acc_t;
+    constexpr int U = CPL >= 8 ? 1 : 8 / CPL;
+    const int32_t E = row_ptr[r1] - be0;
+    const int32_t cs = (int32_t)((int64_t)g * E / NG), ce = (int32_t)((int64_t)(g + 1) * E / NG);
+    auto put = [&](int32_t row, const acc_t *v) {
+#pragma unroll
+        for (int t = 0; t < CPL; ++t)
+            if (t * LPR + j < k) write_y(Y + (int64_t)(t * LPR + j) * ldy, row, (double)v[t], alpha, beta);
+    };
+    acc_t zero[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) zero[t] = 0;
+    if (j == 0) lead_row[g] = tail_row[g] = -1;
+    __syncthreads();
+    // first row with row_ptr >= be0 + cs
+    int32_t lo = r0, hi = r1 + 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (row_ptr[mid] < be0 + cs) lo = mid + 1;
+        else hi = mid;
+    }
+    if (cs == ce) {
+        if (g == NG - 1)
+            for (int32_t r = lo; r < r1; ++r) put(r, zero);
+    } else {
+        int32_t cr;
+        bool here;
+        if (lo > r1 || row_ptr[lo] > be0 + cs) {
+            cr = lo - 1;                                   // the row holding entry cs started before it
+            here = false;
+        } else {
+            cr = lo;
+            here = true;
+            while (cr < r1 && row_ptr[cr + 1] - be0 == cs) put(cr++, zero);    // empty rows at cs
+        }
+        int32_t bnd = row_ptr[cr + 1] - be0;
+        acc_t s[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) s[t] = 0;
+        for (int32_t e = cs; e < ce; e += U) {
+            int32_t c[U];
+            VT v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t q = e + u < ce ? e + u : ce - 1;
+                c[u] = col_s[q];
+                v[u] = val_s[q];
+            }
+            XT xv[U][CPL];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int t = 0; t < CPL; ++t)
+                    xv[u][t] = t * LPR + j < k ? Xr[(int64_t)c[u] * k + t * LPR + j] : XT(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (e + u >= ce) break;
+                while (e + u == bnd) {                      // row cr ended before this entry
+                    if (here) {
+                        put(cr, s);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < CPL; ++t) lead[g][t * LPR + j] = (double)s[t];
+                        if (j == 0) lead_row[g] = cr;
+                    }
+#pragma unroll
+                    for (int t = 0; t < CPL; ++t) s[t] = 0;
+                    ++cr;
+                    here = true;
+                    while (cr < r1 && row_ptr[cr + 1] - be0 == e + u) put(cr++, zero);   // empty rows
+                    bnd = row_ptr[cr + 1] - be0;
+                }
+#pragma unroll
+                for (int t = 0; t < CPL; ++t) s[t] = Acc<WIDE>::mac(s[t], v[u], xv[u][t]);
+            }
+        }
+        if (bnd == ce) {                                    // row cr ends with the share
+            if (here) {
+                put(cr, s);
+            } else {
+#pragma unroll
+                for (int t = 0; t < CPL; ++t) lead[g][t * LPR + j] = (double)s[t];
+                if (j == 0) lead_row[g] = cr;
+            }
+            ++cr;
+            if (g == NG - 1)
+                while (cr < r1) put(cr++, zero);
+        } else if (here) {                                  // continues into the next shares
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) tail[g][t * LPR + j] = (double)s[t];
+            if (j == 0) tail_row[g] = cr;
+        } else {                                            // the whole share is inside one row
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) lead[g][t * LPR + j] = (double)s[t];
+            if (j == 0) lead_row[g] = cr;
+        }
+    }
+    __syncthreads();
+    const int32_t R = tail_row[g];
+    if (R >= 0) {
+        acc_t a[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) a[t] = (acc_t)tail[g][t * LPR + j];
+        for (int q = g + 1; q < NG; ++q) {
+            const bool empty = (int64_t)q * E / NG == (int64_t)(q + 1) * E / NG;
+            if (empty) continue;
+            if (lead_row[q] != R) break;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) a[t] += (acc_t)lead[q][t * LPR + j];
+        }
+        put(R, a);
+    }
+}
+
 // CRS, interleaved X.  One workgroup per plan block of nr rows: GPR groups
 // per row (GPR = largest power of two <= NG/nr), the row's entries dealt to
 // its groups with stride GPR; the GPR partials are added in group order.  A
@@ -134,6 +265,8 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
     constexpr int NG = NT / LPR;
     constexpr bool F64 = IsF64<VT>::value;
     __shared__ double part[NG][K2];
+    __shared__ double tailp[sizeof(XT) == 8 ? NG : 1][K2];
+    __shared__ int32_t lead_row[NG], tail_row[NG];
     extern __shared__ int32_t mm_stage[];               // block_nnz cols, then block_nnz values
     int32_t *col_s = mm_stage;
     VT *val_s = reinterpret_cast<VT *>(mm_stage + ((block_nnz + 3) & ~3));
@@ -157,6 +290,14 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
             val_s[i] = ld_stream(val + be0 + i);
         }
         __syncthreads();
+        // FP64 vectors: entry-balanced shares (3-9% faster than rows in
+        // rounds on the power-law matrix); FP32 vectors keep the rounds
+        // (the shares were 1.3x slower at k = 32 with one-wavefront groups)
+        if constexpr (sizeof(XT) == 8) {
+            mm_crs_balanced<LPR, CPL, NG, K2, F64, VT, XT>(row_ptr, r0, r1, be0, col_s, val_s, Xr, k, Y, ldy, alpha,
+                                                           beta, g, j, part, tailp, lead_row, tail_row);
+            return;
+        }
     }
     for (int32_t rbase = r0; rbase < r1; rbase += rows_per_round) {
         const int32_t row = rbase + g / GPR;
