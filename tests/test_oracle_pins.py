@@ -281,6 +281,81 @@ def test_sojds_keeps_rows_and_is_close():
     assert np.array_equal(B.bl_col[ks], J.jd_col[J.jd_ptr[:-1]])
 
 
+def test_sojds_hand_worked_block():
+    """The SOJDS slot rule on a block worked out by hand (paper Section 2,
+    SOJDS: entries of each row re-sorted so the x access across the rows of a
+    block is as close to stride one as possible; reading: the block's first
+    row keeps CRS order, each next row fills slot d with its unused entry
+    nearest to (previous row's column in slot d) + 1, the smaller column on a
+    tie).  Six rows, C = 4, every row already in JDS order (lengths 3, 3, 3,
+    2, 2, 2 keep their original order):
+
+      row 0 {2, 5, 9}   first row of slice 0: CRS order        -> 2, 5, 9
+      row 1 {0, 4, 10}  slot 0: want 2+1 = 3, |0-3|=3 |4-3|=1   -> 4
+                        slot 1: want 5+1 = 6, |0-6|=6 |10-6|=4  -> 10
+                        slot 2: only 0 left                     -> 0
+      row 2 {1, 5, 11}  slot 0: want 4+1 = 5 (row 1's slot, not its CRS
+                        order), |5-5|=0                          -> 5
+                        slot 1: want 10+1 = 11                   -> 11
+                        slot 2: only 1 left                      -> 1
+      row 3 {4, 8}      slot 0: want 5+1 = 6, |4-6| = |8-6| = 2: tie,
+                        smaller column                           -> 4
+                        slot 1: want 11+1 = 12, only 8 left      -> 8
+                        slot 2: beyond the row: padding          -> -1
+      row 4 {3, 7}      first row of slice 1: CRS order          -> 3, 7
+      row 5 {1, 4}      slot 0: want 3+1 = 4, |4-4| = 0          -> 4
+                        slot 1: only 1 left                      -> 1
+      rows 6, 7         do not exist: padding
+
+    A rule without the "+1" (row 1 slot 0: |0-2| = |4-2|, tie -> 0), one that
+    looks at the previous row's CRS order (row 2 slot 0: want 0+1 -> 1), or
+    one that breaks ties upwards (row 3 slot 0 -> 8) fails this layout."""
+    rows = [[2, 5, 9], [0, 4, 10], [1, 5, 11], [4, 8], [3, 7], [1, 4]]
+    r = np.array([i for i, cs in enumerate(rows) for _ in cs], np.int32)
+    c = np.array([cc for cs in rows for cc in cs], np.int32)
+    v = 100.0 * r + c                              # each value names its entry
+    A = oracle.csr_from_coo(6, 12, r, c, v)
+    J = oracle.jds_from_csr(A)
+    assert J.perm.tolist() == [0, 1, 2, 3, 4, 5]
+    B = oracle.blocked_from_jds(J, 4, sojds=True)
+    assert B.slice_ptr.tolist() == [0, 12, 20]
+    assert B.slice_nd.tolist() == [3, 2]
+    want_col = [2, 4, 5, 4,
+                5, 10, 11, 8,
+                9, 0, 1, -1,
+                3, 4, -1, -1,
+                7, 1, -1, -1]
+    assert B.bl_col.tolist() == want_col
+    rows_of_slot = [0, 1, 2, 3] * 3 + [4, 5, 6, 7] * 2
+    want_val = [100.0 * rr + cc if cc >= 0 else 0.0 for rr, cc in zip(rows_of_slot, want_col)]
+    assert B.bl_val.tolist() == want_val
+
+
+def test_row_absdot_matches_python_floats():
+    """D_i = sum_j |a_ij| |x_j| (the denominator of every tolerance) against a
+    Python-float loop over a dense copy in ascending j: bit for bit on random
+    patterns, exact on small integers, and never below |y_i|."""
+    for seed in range(8):
+        A, rng = rand_csr(700 + seed, n_rows=int(12 + 6 * seed), n_cols=int(64 - 4 * seed))
+        x = rng.uniform(-1, 1, A.n_cols)
+        M = dense_of(A)
+        want = np.zeros(A.n_rows)
+        for i in range(A.n_rows):
+            s = 0.0
+            for j in range(A.n_cols):
+                if M[i, j] != 0.0:
+                    s = s + abs(float(M[i, j])) * abs(float(x[j]))
+            want[i] = s
+        D = oracle.row_absdot(A, x)
+        assert np.array_equal(D, want)
+        assert np.all(np.abs(oracle.spmv_crs(A, x)) <= D * (1 + 1e-15))
+    A, rng = rand_csr(720, n_rows=50, n_cols=60, integer=True)
+    x = rng.integers(-8, 9, A.n_cols).astype(np.float64)
+    M = dense_of(A).astype(np.int64)
+    want = (np.abs(M) @ np.abs(x.astype(np.int64))).astype(np.float64)
+    assert np.array_equal(oracle.row_absdot(A, x), want)
+
+
 def test_jds_empty_rows_and_all_empty():
     A = oracle.csr_from_coo(5, 5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
     J = oracle.jds_from_csr(A)
