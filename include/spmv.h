@@ -54,7 +54,13 @@ typedef enum {
 typedef enum {
     SPMV_F64 = 0,  /* IEEE double                                       */
     SPMV_F32 = 1,  /* IEEE float                                        */
-    SPMV_BF16 = 2  /* bfloat16 bit patterns (uint16_t), values only     */
+    SPMV_BF16 = 2, /* bfloat16 bit patterns (uint16_t), values only     */
+    SPMV_I32 = 3   /* int32 payload: accepted only by the calls that move */
+                   /* values without arithmetic (spmv_jds_from_csr,       */
+                   /* spmv_jds_to_csr, spmv_jds_blocked_from_jds,         */
+                   /* spmv_permute_vec, spmv_gather_values), which copy   */
+                   /* every element bit for bit; e.g. entry positions     */
+                   /* carried through a conversion.  Rejected elsewhere.  */
 } spmv_dtype;
 
 /* flags */

@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspmv.so")
 
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, I32 = 0, 1, 2, 3     # I32: payload of the value-moving calls only
 SYMPERM, SOJDS = 1, 2
 WIDE_ROW_NNZ = 4096
 BATCHED_PLAN_WORDS = 12

@@ -19,6 +19,8 @@ is recomputed before it is swept (activation checkpointing).
 """
 from __future__ import annotations
 
+import weakref
+
 import numpy as np
 import torch
 
@@ -36,14 +38,13 @@ class SpMVOperator:
         self.nnz = A.nnz
         self.unroll, self.max_iters, self.wg_waves = unroll, max_iters, wg_waves
         self.transpose = transpose
-        # JDS of A, and of A with the CRS position of every entry as payload
+        # JDS of A, and of A with the CRS position of every entry as an int32
+        # payload (the conversion moves values bit for bit)
         self.J = S.jds_from_csr(A)
         pos = torch.arange(self.nnz, dtype=torch.int32, device=dev)
-        Jpos = S.jds_from_csr(A.with_values(pos.view(torch.float32)))
-        self.jds_src = Jpos.jd_val.view(torch.int32).contiguous()                # JDS slot -> CRS position
-        jds_of_crs = S.spmv_permute_vec(self.jds_src,
-                                        torch.arange(self.nnz, dtype=torch.int32, device=dev).view(torch.float32),
-                                        inverse=True).view(torch.int32)        # CRS position -> JDS slot
+        Jpos = S.jds_from_csr(A.with_values(pos))
+        self.jds_src = Jpos.jd_val                                              # JDS slot -> CRS position
+        jds_of_crs = S.spmv_permute_vec(self.jds_src, pos, inverse=True)      # CRS position -> JDS slot
         # A^T in CRS (pattern + map into A's CRS values)
         rowT, colT, tmap = S.spmv_transpose_csr(A)
         if transpose == "crs":
@@ -52,13 +53,14 @@ class SpMVOperator:
             self.AT = S.spmv_crs_plan(S.CSR(A.n_cols, A.n_rows, rowT, colT, None))
             self.JT = None
         else:
-            AT = S.CSR(A.n_cols, A.n_rows, rowT, colT, tmap.view(torch.float32))
+            AT = S.CSR(A.n_cols, A.n_rows, rowT, colT, tmap)
             JT = S.jds_from_csr(AT)
             # A^T JDS slot -> A CRS position -> A JDS slot
-            self.tmapT = S.spmv_gather_values(JT.jd_val.view(torch.int32).contiguous(), jds_of_crs)
+            self.tmapT = S.spmv_gather_values(JT.jd_val, jds_of_crs)
             self.JT = JT.with_values(None)
             self.AT = None
         self._valsT = None
+        self._valsT_of = None        # weak reference to the vals tensor _valsT was built from
         self._valsT_key = None
 
     def vals_from_crs(self, crs_val: torch.Tensor) -> torch.Tensor:
@@ -66,9 +68,15 @@ class SpMVOperator:
         return S.spmv_gather_values(self.jds_src, crs_val)
 
     def transposed_values(self, vals: torch.Tensor) -> torch.Tensor:
-        key = (vals.data_ptr(), vals._version, vals.dtype)
-        if self._valsT is None or self._valsT_key != key:
+        """A^T's values (one gather), reused while `vals` is the same tensor
+        object with the same version counter, storage and dtype.  A new
+        tensor is never taken for the old one, even when the allocator puts
+        it at the address of a freed one."""
+        key = (vals._version, vals.data_ptr(), vals.dtype)
+        same = self._valsT_of is not None and self._valsT_of() is vals and self._valsT_key == key
+        if self._valsT is None or not same:
             self._valsT = S.spmv_gather_values(self.tmapT, vals)
+            self._valsT_of = weakref.ref(vals)
             self._valsT_key = key
         return self._valsT
 

@@ -56,10 +56,12 @@ spmv_status spmm_jds_colmajor(int32_t n, const int32_t *perm, const int32_t *jd_
 
 inline size_t dtype_size(spmv_dtype dt)
 {
-    return dt == SPMV_F64 ? 8 : dt == SPMV_F32 ? 4 : 2;
+    return dt == SPMV_F64 ? 8 : (dt == SPMV_F32 || dt == SPMV_I32) ? 4 : 2;
 }
 
 inline bool valid_dtype(spmv_dtype dt) { return dt == SPMV_F64 || dt == SPMV_F32 || dt == SPMV_BF16; }
+// Element types of the calls that only move values (bit-for-bit copies).
+inline bool valid_payload_dtype(spmv_dtype dt) { return valid_dtype(dt) || dt == SPMV_I32; }
 inline bool valid_vec_dtype(spmv_dtype dt) { return dt == SPMV_F64 || dt == SPMV_F32; }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

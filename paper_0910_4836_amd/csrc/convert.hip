@@ -1028,7 +1028,7 @@ spmv_status spmv_jds_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, co
 {
     SPMV_REQUIRE(n >= 0 && nnz >= 0, "spmv_jds_from_csr: negative size");
     if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_jds_from_csr: nnz >= 2^31");
-    SPMV_REQUIRE(valid_dtype(dt), "spmv_jds_from_csr: bad dtype");
+    SPMV_REQUIRE(valid_payload_dtype(dt), "spmv_jds_from_csr: bad dtype");
     SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_jds_from_csr: unknown flag");
     SPMV_REQUIRE(h_ndiag && row_ptr && (jd_ptr || jd_ptr_cap == 0), "spmv_jds_from_csr: null pointer");
     SPMV_REQUIRE(n == 0 || (perm && iperm), "spmv_jds_from_csr: null perm");
@@ -1081,7 +1081,7 @@ spmv_status spmv_jds_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, co
         if (dt == SPMV_F64)
             jds_scatter_kernel<uint64_t><<<grid_for(nnz), 256, 0, s>>>(row_ptr, col_idx, (const uint64_t *)val, n, nnz,
                                                                      iperm, jd_ptr, sym, jd_col, (uint64_t *)jd_val);
-        else if (dt == SPMV_F32)
+        else if (dt == SPMV_F32 || dt == SPMV_I32)
             jds_scatter_kernel<uint32_t><<<grid_for(nnz), 256, 0, s>>>(row_ptr, col_idx, (const uint32_t *)val, n, nnz,
                                                                     iperm, jd_ptr, sym, jd_col, (uint32_t *)jd_val);
         else
@@ -1107,7 +1107,7 @@ spmv_status spmv_jds_to_csr(int32_t n, const int32_t *perm, const int32_t *jd_pt
                             void *val, void *ws, size_t ws_bytes, void *stream)
 {
     SPMV_REQUIRE(n >= 0 && ndiag >= 0, "spmv_jds_to_csr: negative size");
-    SPMV_REQUIRE(valid_dtype(dt), "spmv_jds_to_csr: bad dtype");
+    SPMV_REQUIRE(valid_payload_dtype(dt), "spmv_jds_to_csr: bad dtype");
     SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_jds_to_csr: unknown flag");
     SPMV_REQUIRE(row_ptr && jd_ptr, "spmv_jds_to_csr: null pointer");
     SPMV_REQUIRE(ws && ws_bytes >= spmv_jds_to_csr_workspace_size(n), "spmv_jds_to_csr: workspace too small");
@@ -1134,7 +1134,7 @@ spmv_status spmv_jds_to_csr(int32_t n, const int32_t *perm, const int32_t *jd_pt
         jds_to_csr_kernel<uint64_t><<<grid_for(nnz), 256, 0, s>>>(jd_ptr, ndiag, nnz, perm, jd_col,
                                                                 (const uint64_t *)jd_val, sym, row_ptr, col_idx,
                                                                 (uint64_t *)val);
-    else if (dt == SPMV_F32)
+    else if (dt == SPMV_F32 || dt == SPMV_I32)
         jds_to_csr_kernel<uint32_t><<<grid_for(nnz), 256, 0, s>>>(jd_ptr, ndiag, nnz, perm, jd_col, (const uint32_t *)jd_val,
                                                                sym, row_ptr, col_idx, (uint32_t *)val);
     else
@@ -1161,7 +1161,7 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
 {
     SPMV_REQUIRE(n >= 0 && ndiag >= 0, "spmv_jds_blocked_from_jds: negative size");
     SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_from_jds: C must be a positive multiple of 64");
-    SPMV_REQUIRE(valid_dtype(dt), "spmv_jds_blocked_from_jds: bad dtype");
+    SPMV_REQUIRE(valid_payload_dtype(dt), "spmv_jds_blocked_from_jds: bad dtype");
     SPMV_REQUIRE((flags & ~SPMV_SOJDS) == 0, "spmv_jds_blocked_from_jds: unknown flag");
     SPMV_REQUIRE(jd_ptr && slice_ptr && h_padded, "spmv_jds_blocked_from_jds: null pointer");
     SPMV_REQUIRE(ws && ws_bytes >= spmv_jds_blocked_workspace_size(n, ndiag, C, flags),
@@ -1207,6 +1207,7 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
     }
     BLK_CASE(SPMV_F64, uint64_t)
     BLK_CASE(SPMV_F32, uint32_t)
+    BLK_CASE(SPMV_I32, uint32_t)
     BLK_CASE(SPMV_BF16, uint16_t)
 #undef BLK_CASE
     SPMV_HIP(hipStreamSynchronize(s));
@@ -1513,7 +1514,7 @@ spmv_status spmv_permute_vec(int32_t n, const int32_t *perm, const void *in, voi
                              void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_permute_vec: n < 0");
-    SPMV_REQUIRE(valid_vec_dtype(dt), "spmv_permute_vec: dtype must be F64 or F32");
+    SPMV_REQUIRE(valid_vec_dtype(dt) || dt == SPMV_I32, "spmv_permute_vec: dtype must be F64, F32 or I32");
     if (n == 0) return SPMV_OK;
     SPMV_REQUIRE(perm && in && out && in != out, "spmv_permute_vec: null or aliased pointer");
     hipStream_t s = as_stream(stream);
@@ -1528,13 +1529,13 @@ spmv_status spmv_permute_vec(int32_t n, const int32_t *perm, const void *in, voi
 spmv_status spmv_gather_values(int64_t n, const int32_t *map, const void *in, void *out, spmv_dtype dt, void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_gather_values: n < 0");
-    SPMV_REQUIRE(valid_dtype(dt), "spmv_gather_values: bad dtype");
+    SPMV_REQUIRE(valid_payload_dtype(dt), "spmv_gather_values: bad dtype");
     if (n == 0) return SPMV_OK;
     SPMV_REQUIRE(map && in && out && in != out, "spmv_gather_values: null or aliased pointer");
     hipStream_t s = as_stream(stream);
     if (dt == SPMV_F64)
         gather_kernel<uint64_t><<<grid_for(n), 256, 0, s>>>(n, map, (const uint64_t *)in, (uint64_t *)out);
-    else if (dt == SPMV_F32)
+    else if (dt == SPMV_F32 || dt == SPMV_I32)
         gather_kernel<uint32_t><<<grid_for(n), 256, 0, s>>>(n, map, (const uint32_t *)in, (uint32_t *)out);
     else
         gather_kernel<uint16_t><<<grid_for(n), 256, 0, s>>>(n, map, (const uint16_t *)in, (uint16_t *)out);

@@ -348,18 +348,12 @@ __global__ __launch_bounds__(JDS_THREADS) void jds_rows_kernel(JdsSplitArgs S)
 }
 
 // Multi-vector JDS: each lane owns one row (R = 64) and keeps k accumulators;
-// the row's entries are read once for all k columns of X.
-template <int KB, typename VT, typename XT>
-__global__ __launch_bounds__(256) void spmm_jds_kernel(JdsArgs a)
+// the row's entries are read once for all k columns of X.  Rows longer than
+// SPMV_WIDE_ROW_NNZ entries with reduced-precision values accumulate in FP64.
+template <int KB, bool WIDE, typename VT, typename XT>
+__device__ __forceinline__ void spmm_jds_row(const JdsArgs &a, int32_t r, int32_t row0, int col0, int kb)
 {
-    constexpr bool F64 = IsF64<VT>::value;
-    typedef typename Acc<F64>::T acc_t;
-    const int64_t r64 = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int col0 = blockIdx.y * KB;
-    const int kb = a.k - col0 < KB ? a.k - col0 : KB;
-    if (r64 >= a.n) return;
-    const int32_t r = (int32_t)r64;
-    const int32_t row0 = (int32_t)(r64 & ~(int64_t)(WAVE - 1));
+    typedef typename Acc<WIDE>::T acc_t;
     const int32_t *__restrict__ jp = a.jd_ptr;
     const VT *__restrict__ val = (const VT *)a.val;
     const XT *__restrict__ X = (const XT *)a.x + (int64_t)col0 * a.ldx;
@@ -374,7 +368,7 @@ __global__ __launch_bounds__(256) void spmm_jds_kernel(JdsArgs a)
             const VT v = ld_stream(val + off + r);
 #pragma unroll
             for (int j = 0; j < KB; ++j)
-                if (j < kb) acc[j] = Acc<F64>::mac(acc[j], v, X[c + (int64_t)j * a.ldx]);
+                if (j < kb) acc[j] = Acc<WIDE>::mac(acc[j], v, X[c + (int64_t)j * a.ldx]);
         }
     }
     const int32_t yi = a.symperm ? r : a.perm[r];
@@ -382,6 +376,23 @@ __global__ __launch_bounds__(256) void spmm_jds_kernel(JdsArgs a)
 #pragma unroll
     for (int j = 0; j < KB; ++j)
         if (j < kb) write_y(Y + (int64_t)j * a.ldy, yi, (double)acc[j], a.alpha, a.beta);
+}
+
+template <int KB, typename VT, typename XT>
+__global__ __launch_bounds__(256) void spmm_jds_kernel(JdsArgs a)
+{
+    constexpr bool F64 = IsF64<VT>::value;
+    const int64_t r64 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int col0 = blockIdx.y * KB;
+    const int kb = a.k - col0 < KB ? a.k - col0 : KB;
+    if (r64 >= a.n) return;
+    const int32_t r = (int32_t)r64;
+    const int32_t row0 = (int32_t)(r64 & ~(int64_t)(WAVE - 1));
+    // row r has more than SPMV_WIDE_ROW_NNZ entries iff diagonal 4096 reaches it
+    const bool wide = !F64 && a.ndiag > SPMV_WIDE_ROW_NNZ &&
+                      a.jd_ptr[SPMV_WIDE_ROW_NNZ + 1] - a.jd_ptr[SPMV_WIDE_ROW_NNZ] > r;
+    if (F64 || wide) spmm_jds_row<KB, true, VT, XT>(a, r, row0, col0, kb);
+    else spmm_jds_row<KB, false, VT, XT>(a, r, row0, col0, kb);
 }
 
 // Value gradient in JDS storage order: dval[e] = alpha*g[row]*x[col[e]] +

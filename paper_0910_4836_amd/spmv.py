@@ -21,9 +21,12 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BF16, F32, F64, SOJDS, SYMPERM, SpmvError, call
+from ._lib import BF16, F32, F64, I32, SOJDS, SYMPERM, SpmvError, call
 
-_DTYPE_CODE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+# int32 is a payload type: the value-moving calls (conversions, permute,
+# gather) copy it bit for bit; the arithmetic calls reject it.
+_DTYPE_CODE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.int32: I32}
+_VEC_DTYPES = (torch.float64, torch.float32)
 _I32 = torch.int32
 
 
@@ -277,11 +280,25 @@ def spmv_transpose_csr(A: CSR):
 # --------------------------------------------------------------------------- compute
 
 
-def _out_vec(y, n, like, beta):
+def _out_vec(y, n, x, beta, n_cols):
+    """Checks x and y against the product's shape and returns y (a new vector
+    if None).  The kernels read n_cols elements of x and write n elements of
+    y in x's dtype with no device-side bounds checks, so a short or mistyped
+    vector is refused here, before any launch."""
+    if x.dtype not in _VEC_DTYPES:
+        raise TypeError(f"x must be float64 or float32, got {x.dtype}")
+    if x.numel() < n_cols:
+        raise ValueError(f"x has {x.numel()} elements, the matrix has {n_cols} columns")
+    if y is not None:
+        if y.dtype != x.dtype:
+            raise ValueError(f"y is {y.dtype} but x is {x.dtype}; both vectors take one dtype")
+        if y.numel() < n:
+            raise ValueError(f"y has {y.numel()} elements, the matrix has {n} rows")
+    _check_dev(x)
     if y is None:
         if beta != 0.0:
             raise ValueError("beta != 0 needs y")
-        return torch.empty(n, dtype=like.dtype, device=like.device)
+        return torch.empty(n, dtype=x.dtype, device=x.device)
     _check_dev(y)
     return y
 
@@ -289,10 +306,9 @@ def _out_vec(y, n, like, beta):
 def spmv_crs(A: CSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
              use_plan: bool = True) -> torch.Tensor:
     """y = alpha*A x + beta*y with the CRS kernels (spmv_crs)."""
-    _check_dev(x)
+    y = _out_vec(y, A.n_rows, x, beta, A.n_cols)
     if use_plan and A.plan is None:
         spmv_crs_plan(A)
-    y = _out_vec(y, A.n_rows, x, beta)
     plan = A.plan if use_plan else None
     call("spmv_crs", A.n_rows, A.n_cols, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(x),
          _p(y), dtype_code(x.dtype), float(alpha), float(beta), _p(plan), A.n_blocks if use_plan else 0,
@@ -303,8 +319,7 @@ def spmv_crs(A: CSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: f
 def spmv_jds(J: JDS, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
              unroll: int = 0, max_iters: int = 0, wg_waves: int = 0) -> torch.Tensor:
     """y = alpha*A x + beta*y with the JDS kernel (spmv_jds)."""
-    _check_dev(x)
-    y = _out_vec(y, J.n, x, beta)
+    y = _out_vec(y, J.n, x, beta, J.n_cols)
     call("spmv_jds", J.n, _p(J.perm), _p(J.jd_ptr), _h_i32(J.h_jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val),
          dtype_code(J.jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll, max_iters,
          wg_waves, J.flags, _stream())
@@ -315,8 +330,7 @@ def spmv_jds_blocked(B: Blocked, x: torch.Tensor, y: Optional[torch.Tensor] = No
                      beta: float = 0.0, rows_per_wave: int = 0, unroll: int = 0, max_iters: int = 0,
                      wg_waves: int = 0) -> torch.Tensor:
     """y = alpha*A x + beta*y with the blocked-JDS kernel (spmv_jds_blocked)."""
-    _check_dev(x)
-    y = _out_vec(y, B.n, x, beta)
+    y = _out_vec(y, B.n, x, beta, B.n_cols)
     flags = (SYMPERM if B.symperm else 0) | (SOJDS if B.sojds else 0)
     call("spmv_jds_blocked", B.n, _p(B.perm), B.C, B.n_slices, _p(B.slice_ptr), _p(B.slice_nd),
          _h_i32(B.h_slice_nd), _p(B.bl_col), _p(B.bl_val), dtype_code(B.bl_val.dtype), _p(x), _p(y),
@@ -335,6 +349,24 @@ def _ld(X: torch.Tensor, n: int) -> int:
     return X.stride(1) if X.shape[1] > 1 else n
 
 
+def _check_blocks(X: torch.Tensor, Y: Optional[torch.Tensor], n_rows: int, n_cols: int) -> None:
+    """X must be (n_cols, k) and Y (n_rows, k), column-major, one vector dtype:
+    the kernels trust these shapes, so a mismatch is refused before launch."""
+    if X.dtype not in _VEC_DTYPES:
+        raise TypeError(f"X must be float64 or float32, got {X.dtype}")
+    if X.dim() != 2 or X.shape[0] != n_cols:
+        raise ValueError(f"X must be ({n_cols}, k), got {tuple(X.shape)}")
+    if Y is not None:
+        if Y.dtype != X.dtype:
+            raise ValueError(f"Y is {Y.dtype} but X is {X.dtype}; both blocks take one dtype")
+        if Y.dim() != 2 or tuple(Y.shape) != (n_rows, X.shape[1]):
+            raise ValueError(f"Y must be ({n_rows}, {X.shape[1]}), got {tuple(Y.shape)}")
+    _ld(X, n_cols)
+    if Y is not None:
+        _ld(Y, n_rows)
+    _check_dev(X, Y)
+
+
 def spmm_workspace(n_cols: int, k: int, dtype, device) -> torch.Tensor:
     """Workspace for the interleaved multi-vector path (a row-major copy of X)."""
     return _ws(_lib.load().spmm_workspace_size(n_cols, k, dtype_code(dtype)), device)
@@ -343,6 +375,7 @@ def spmm_workspace(n_cols: int, k: int, dtype, device) -> torch.Tensor:
 def spmm_crs(A: CSR, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
              ws: Optional[torch.Tensor] = None, interleave: bool = True) -> torch.Tensor:
     """Y = alpha*A X + beta*Y for a column-major block X (spmm_crs)."""
+    _check_blocks(X, Y, A.n_rows, A.n_cols)
     if A.plan is None:
         spmv_crs_plan(A)
     k = X.shape[1]
@@ -360,6 +393,7 @@ def spmm_crs(A: CSR, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: f
 def spmm_jds(J: JDS, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
              ws: Optional[torch.Tensor] = None, interleave: bool = True) -> torch.Tensor:
     """Y = alpha*A X + beta*Y for a column-major block X (spmm_jds)."""
+    _check_blocks(X, Y, J.n, J.n_cols)
     k = X.shape[1]
     if Y is None:
         Y = colmajor(J.n, k, X.dtype, X.device)
@@ -379,14 +413,10 @@ def spmv_permute_vec(perm: torch.Tensor, v: torch.Tensor, inverse: bool = False)
 
 
 def spmv_gather_values(map_: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
-    """out[i] = v[map_[i]]; 4-byte and 8-byte payloads move bit for bit."""
-    dt = v.dtype
-    src = v
-    if dt == torch.int32:
-        src, dt = v.view(torch.float32), torch.float32
-    out = torch.empty(map_.numel(), dtype=dt, device=v.device)
-    call("spmv_gather_values", map_.numel(), _p(map_), _p(src), _p(out), dtype_code(dt), _stream())
-    return out.view(v.dtype) if v.dtype == torch.int32 else out
+    """out[i] = v[map_[i]]; every element moves bit for bit (int32 included)."""
+    out = torch.empty(map_.numel(), dtype=v.dtype, device=v.device)
+    call("spmv_gather_values", map_.numel(), _p(map_), _p(v), _p(out), dtype_code(v.dtype), _stream())
+    return out
 
 
 def spmv_axpby(alpha: float, x: torch.Tensor, beta: float, y: torch.Tensor) -> torch.Tensor:
@@ -538,7 +568,7 @@ class Split:
 
 
 def spmv_crs_split(S: Split, x, y=None, alpha=1.0, beta=0.0):
-    y = _out_vec(y, S.n, x, beta)
+    y = _out_vec(y, S.n, x, beta, S.n_cols)
     call("spmv_crs_split", S.n, S.n_cols, _p(S.row_ptr_all), _p(S.dest_all), _p(S.slot_ptr), _p(S.col), _p(S.val),
          _h_i64(S.bounds), _h_i64(S.row_off), dtype_code(S.val.dtype), _p(S.plan_all), _h_i32(S.plan_off),
          _h_i32(S.n_blocks), S.block_nnz, _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), _p(S.ws),
@@ -558,8 +588,8 @@ def _jds_split_args(S: Split):
 
 
 def spmv_jds_split(S: Split, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0, wg_waves=0):
+    y = _out_vec(y, S.n, x, beta, S.n_cols)
     Js, perm, jp, hptr, ndiag, col, val = _jds_split_args(S)
-    y = _out_vec(y, S.n, x, beta)
     call("spmv_jds_split", S.n, _p(S.slot_ptr), _h_i64(S.row_off), perm, jp, hptr, _h_i32(ndiag), col, val,
          dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll,
          max_iters, wg_waves, _p(S.ws), S.ws.numel(), _stream())
@@ -579,8 +609,8 @@ def _blocked_split_args(S: Split, C_: int):
 
 def spmv_jds_blocked_split(S: Split, x, y=None, alpha=1.0, beta=0.0, C_=64, rows_per_wave=0, unroll=0,
                            max_iters=0, wg_waves=0):
+    y = _out_vec(y, S.n, x, beta, S.n_cols)
     Bs, perm, sptr, snd, hnd, col, val = _blocked_split_args(S, C_)
-    y = _out_vec(y, S.n, x, beta)
     call("spmv_jds_blocked_split", S.n, C_, _p(S.slot_ptr), _h_i64(S.row_off), perm, sptr, snd, hnd, col, val,
          dtype_code(Bs[0].bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave,
          unroll, max_iters, wg_waves, _p(S.ws), S.ws.numel(), _stream())
@@ -656,9 +686,8 @@ def _jds_row_split_args(R: RowSplit):
 
 
 def spmv_jds_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, unroll=0, max_iters=0, wg_waves=0):
+    y = _out_vec(y, R.n, x, beta, R.n_cols)
     Js, perm, jp, hptr, ndiag, col, val = _jds_row_split_args(R)
-    _check_dev(x)
-    y = _out_vec(y, R.n, x, beta)
     call("spmv_jds_row_split", R.n, _h_i64(R.bounds), perm, jp, hptr, _h_i32(ndiag), col, val,
          dtype_code(Js[0].jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll,
          max_iters, wg_waves, _stream())
@@ -678,9 +707,8 @@ def _blocked_row_split_args(R: RowSplit, C_: int):
 
 def spmv_jds_blocked_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, C_=64, rows_per_wave=0, unroll=0,
                                max_iters=0, wg_waves=0):
+    y = _out_vec(y, R.n, x, beta, R.n_cols)
     Bs, perm, sptr, snd, hnd, col, val = _blocked_row_split_args(R, C_)
-    _check_dev(x)
-    y = _out_vec(y, R.n, x, beta)
     call("spmv_jds_blocked_row_split", R.n, C_, _h_i64(R.bounds), perm, sptr, snd, hnd, col, val,
          dtype_code(Bs[0].bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), rows_per_wave,
          unroll, max_iters, wg_waves, _stream())
@@ -736,8 +764,7 @@ def dia_from_csr(A: CSR, max_diags: int = 0, symmetric: bool = False) -> DIA:
 def spmv_dia(D: DIA, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
              beta: float = 0.0) -> torch.Tensor:
     """y = alpha*A x + beta*y over the DIA + CRS hybrid (spmv_dia)."""
-    _check_dev(x)
-    y = _out_vec(y, D.n_rows, x, beta)
+    y = _out_vec(y, D.n_rows, x, beta, D.n_cols)
     has_rem = D.rem.nnz > 0
     shape = (D.n_rows,) if D.symmetric else (D.n_rows, D.n_cols)
     call("spmv_dia_sym" if D.symmetric else "spmv_dia", *shape, D.ndia, _h_i32(D.offsets), _p(D.dia_val),

@@ -87,3 +87,62 @@ def test_spmv_function_gradcheck_fp64():
     gAx = float(torch.dot(g, y))
     assert abs(float(torch.dot(x.grad, x)) - gAx) <= 1e-12 * n
     assert abs(float(torch.dot(vals.grad, vals)) - gAx) <= 1e-12 * n
+
+
+@pytest.mark.parametrize("transpose", ["crs", "jds"])
+def test_transposed_values_follow_a_new_vals_tensor(transpose):
+    """A^T's values are cached per vals tensor.  A new tensor of the same size
+    (freed and reallocated in between, so the allocator may well hand out
+    the old address, version 0 again) must not reuse the old transpose:
+    dx = A^T g is checked against the oracle for both."""
+    r, c, v, n, _ = synth.random_pattern(3000, 3000, 0.004, np.random.default_rng(11))[:5]
+    A = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v))
+    op = AG.SpMVOperator(A, transpose=transpose)
+    g = synth.uniform_vector(n, np.random.default_rng(12))
+    order = to_np(op.jds_src).astype(np.int64)          # JDS slot -> CRS position
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    assert R.nnz == A.nnz
+    for seed in (1, 2, 3):
+        crs_vals = np.random.default_rng(seed).standard_normal(R.nnz)
+        Rv = oracle.CSR(n, n, R.row_ptr, R.col, crs_vals)
+        vals = op.vals_from_crs(to_dev(crs_vals))
+        assert np.array_equal(to_np(vals), crs_vals[order])
+        dx = to_np(op.rmatvec(vals, to_dev(g)))
+        want = oracle.spmv_crs_transposed(Rv, g)
+        D = oracle.spmv_crs_transposed(oracle.CSR(n, n, R.row_ptr, R.col, np.abs(crs_vals)), np.abs(g))
+        assert oracle.rel_err(dx, want, D).max() <= 1e-12, seed
+        # an in-place change of the same tensor is seen too
+        vals.mul_(2.0)
+        dx2 = to_np(op.rmatvec(vals, to_dev(g)))
+        assert oracle.rel_err(dx2, 2.0 * want, 2.0 * D).max() <= 1e-12, seed
+        del vals
+        torch.cuda.synchronize()
+
+
+def test_int32_payload_through_the_conversions():
+    """int32 values ride through CRS -> JDS -> blocked JDS, the permutation
+    and the gather bit for bit (the position maps of the operator above)."""
+    r, c, v, n, _ = synth.random_pattern(500, 400, 0.02, np.random.default_rng(13))[:5]
+    R = oracle.csr_from_coo(n, 400, r, c, v)
+    A = sp.csr_from_coo(n, 400, to_dev(r), to_dev(c), to_dev(v))
+    pos = torch.arange(A.nnz, dtype=torch.int32, device="cuda")
+    pos[::7] = -pos[::7] - 1                         # negative payloads too
+    Jp = sp.jds_from_csr(A.with_values(pos))
+    Jo = oracle.jds_from_csr(R)
+    want = np.arange(R.nnz, dtype=np.int64)
+    want[::7] = -want[::7] - 1
+    # the JDS scatter is a permutation of entries: compare against the oracle's
+    # JDS of the same positions
+    Jw = oracle.jds_from_csr(oracle.CSR(n, 400, R.row_ptr, R.col, want.astype(np.float64)))
+    assert Jp.jd_val.dtype == torch.int32
+    assert np.array_equal(to_np(Jp.jd_val).astype(np.int64), Jw.jd_val.astype(np.int64))
+    assert np.array_equal(to_np(Jp.perm), Jo.perm)
+    B = sp.jds_blocked_from_jds(Jp, 64)
+    Bw = oracle.blocked_from_jds(Jw, 64)
+    assert np.array_equal(to_np(B.bl_val).astype(np.int64), Bw.bl_val.astype(np.int64))
+    back = sp.jds_to_csr(Jp)
+    assert np.array_equal(to_np(back.val).astype(np.int64), want)
+    g = sp.spmv_gather_values(torch.tensor([2, 0, 1], dtype=torch.int32, device="cuda"), pos[:3])
+    assert to_np(g).tolist() == [int(want[2]), int(want[0]), int(want[1])]
+    p = sp.spmv_permute_vec(Jp.perm, pos[:n].clone())
+    assert np.array_equal(to_np(p).astype(np.int64), want[:n][Jo.perm])

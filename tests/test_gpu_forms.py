@@ -87,6 +87,72 @@ def test_spmm_integer_exact_and_fp32_bound():
             assert np.all(np.abs(got[:, j] - want[:, j]) <= (gamma(L + 1, U32) + U32) * D)
 
 
+_PAIRS = [(torch.float64, torch.float64), (torch.float32, torch.float32), (torch.float32, torch.float64),
+          (torch.bfloat16, torch.float32), (torch.bfloat16, torch.float64), (torch.float64, torch.float32)]
+
+
+@pytest.fixture(scope="module")
+def mixed_spmm_matrix():
+    """Rows of 1-80 entries (rows cross the entry shares of the 256- and
+    1024-entry plan blocks), 10% empty rows, four single-row blocks of 2,000
+    entries and two rows of 4,500 (FP64 accumulation for reduced values)."""
+    rng = np.random.default_rng(77)
+    n_rows, n_cols = 6000, 7000
+    lens = rng.integers(1, 81, n_rows)
+    lens[rng.random(n_rows) < 0.1] = 0
+    lens[[5, 2100, 2101, 4999]] = 2000
+    lens[[17, 3000]] = 4500
+    r = np.repeat(np.arange(n_rows), lens).astype(np.int32)
+    c = np.concatenate([rng.choice(n_cols, L, replace=False) for L in lens if L]).astype(np.int32)
+    v = rng.standard_normal(len(r))
+    return r, c, v, n_rows, n_cols, rng
+
+
+@pytest.mark.parametrize("vdt,xdt", _PAIRS, ids=[f"{str(a)[6:]}-{str(b)[6:]}" for a, b in _PAIRS])
+def test_spmm_every_dtype_pair(mixed_spmm_matrix, vdt, xdt):
+    """Every value/vector pair that spmm_crs and spmm_jds export, on the
+    interleaved and column-major paths, with the default and a 256-entry CRS
+    plan: against the oracle on the rounded values and vectors, under the
+    single-vector bound (x rounded to FP32, L+1 roundings for reduced values
+    in rows of <= 4096 entries; FP64 products and sums otherwise; one more
+    rounding for FP32 output)."""
+    r, c, v, nr, nc, rng = mixed_spmm_matrix
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    if vdt == torch.float64:
+        vq = R.val
+    elif vdt == torch.float32:
+        vq = oracle.round_f32(R.val).astype(np.float64)
+    else:
+        vq = oracle.bf16_bits_to_f64(oracle.round_bf16_bits(R.val))
+    Rq = oracle.CSR(nr, nc, R.row_ptr, R.col, vq)
+    L = R.row_lengths()
+    A64 = gpu_csr(sp, r, c, v, nr, nc)
+    A = A64 if vdt == torch.float64 else A64.with_values(sp.spmv_convert_values(A64.val, vdt))
+    assert np.array_equal(to_np(A.val.to(torch.float64)), vq)
+    J = sp.jds_from_csr(A)
+    for k in (3, 8, 32, 64):
+        X = rng.uniform(-1, 1, (nc, k))
+        if xdt == torch.float32:
+            X = X.astype(np.float32).astype(np.float64)
+        want = oracle.spmm_crs(Rq, X)
+        Xd = colmajor_from(X, xdt)
+        wide = (L > 4096) | (vdt == torch.float64)
+        u = np.where(wide, gamma(L + 1, U64), gamma(L + 1, U32)) + (U32 if xdt == torch.float32 else 0.0)
+        runs = []
+        for bn in (0, 256):
+            A.plan = None
+            sp.spmv_crs_plan(A, bn)
+            runs += [(f"crs_il_b{bn}", to_np(sp.spmm_crs(A, Xd))),
+                     (f"crs_cm_b{bn}", to_np(sp.spmm_crs(A, Xd, interleave=False)))]
+        runs += [("jds_il", to_np(sp.spmm_jds(J, Xd))), ("jds_cm", to_np(sp.spmm_jds(J, Xd, interleave=False)))]
+        for name, got in runs:
+            for j in range(k):
+                D = oracle.row_absdot(Rq, X[:, j])
+                err = np.abs(got[:, j].astype(np.float64) - want[:, j])
+                assert np.all(err <= u * D), (name, k, j, float(np.max(err / np.maximum(u * D, 1e-300))))
+                assert np.all(got[L == 0, j] == 0), (name, k, j)
+
+
 def small_batch(count, integer=False, seed=0):
     mats = []
     rng = np.random.default_rng(seed)
