@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--probe", choices=["copy", "triad", "strides"], default=None,
                     help="copy / triad: only the bandwidth probe on 1 GiB arrays (counter calibration); "
                          "strides: the access-pattern microbenchmarks of the inner loop")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="leave out the mixed-precision block on the symmetric-diagonals matrix")
+    ap.add_argument("--workload", choices=["powerlaw", "symdiag"], default="powerlaw",
+                    help="symdiag: time only the symmetric-diagonals products named by --only (profiling runs)")
     ap.add_argument("--tune-cache", default="",
                     help="autotuner cache file (default: a fresh one, i.e. tune on this device now); "
                          "profiling runs share one so they time the same kernels")
@@ -484,32 +488,60 @@ def bytes_dia(D, s_v, s_x):
     return span * s_v + rem + s_x * (D.n_cols + D.n_rows)
 
 
-def cpu_baseline(W, budget_s=20.0):
+def host_cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (platform's name otherwise)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(W, budget_s=20.0, W3=None):
     """The serial oracle (plain C, one core) on the same step, repeated for about
-    budget_s seconds of CPU time; returns GFLOP/s."""
+    budget_s seconds of CPU time; returns GFLOP/s.  The calling thread (the
+    one that runs the oracle through ctypes) is pinned to one core for the
+    duration, as the paper pins its threads; the GPU work is done by then.
+    With W3 (the symmetric-diagonals workload), the sampled rows of its
+    mixed-precision products are also checked against the oracle."""
     import oracle
     r, c, v, n, x = W["host"]
     A = oracle.csr_from_coo(n, n, r, c, v)
     J = oracle.jds_from_csr(A)
     Bk = oracle.blocked_from_jds(J, W["tune"]["blocked_C"])
     step = [lambda: oracle.spmv_crs(A, x), lambda: oracle.spmv_jds(J, x), lambda: oracle.spmv_blocked(Bk, x)]
-    reps = 0
-    t0 = time.process_time()
-    w0 = time.perf_counter()
-    while True:
-        for f in step:
-            f()
-        reps += 1
-        if time.process_time() - t0 >= budget_s:
-            break
-    cpu_s = time.process_time() - t0
-    wall = time.perf_counter() - w0
+    old_aff = None
+    core = None
+    if hasattr(os, "sched_getaffinity"):
+        old_aff = os.sched_getaffinity(0)
+        core = min(old_aff)
+        os.sched_setaffinity(0, {core})
+    try:
+        reps = 0
+        t0 = time.process_time()
+        w0 = time.perf_counter()
+        while True:
+            for f in step:
+                f()
+            reps += 1
+            if time.process_time() - t0 >= budget_s:
+                break
+        cpu_s = time.process_time() - t0
+        wall = time.perf_counter() - w0
+    finally:
+        if old_aff is not None:
+            os.sched_setaffinity(0, old_aff)
     flops = len(step) * 2.0 * A.nnz * reps
-    return {"value": round(flops / wall / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full steps (CRS, JDS, blocked JDS products in FP64) of the n=2,000,000 "
-                      f"power-law matrix, "
-                      f"{cpu_s:.1f} s CPU, serial FP64 C oracle (-O2, no FMA), one thread",
-            "host_cpu": platform.processor() or platform.machine(), "host_logical_cpus": os.cpu_count()}
+    out = {"value": round(flops / wall / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+           "sample": f"{reps} full steps (CRS, JDS, blocked JDS products in FP64) of the n=2,000,000 "
+                     f"power-law matrix, "
+                     f"{cpu_s:.1f} s CPU, serial FP64 C oracle (-O2, no FMA), one thread",
+           "pinned_core": core, "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
+    if W3 is not None and "samples" in W3:
+        out["symdiag_sampled_rows_max_rel_err_vs_oracle"] = c3_oracle_check(W3)
+    return out
 
 
 def roofline_for(name, bytes_per_launch, ms, workload):
@@ -528,7 +560,8 @@ def attainable_bw(torch, sp, dev):
     out = {}
     for name, fn, nbytes in (("triad", lambda: sp.spmv_stream_triad(a, b, c, 0.5), 24 * n),
                              ("copy", lambda: sp.spmv_stream_copy(a, b), 16 * n),
-                             ("read", lambda: sp.spmv_stream_read(b, part), 8 * n)):
+                             ("read", lambda: sp.spmv_stream_read(b, part), 8 * n),
+                             ("torch_copy", lambda: a.copy_(b), 16 * n)):
         ms, _ = time_loop(torch, [(name, fn)], 20, 3)
         out[name + "_GBs"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
     del a, b, c
@@ -596,64 +629,129 @@ def suite_laplacian(torch, sp, dev, steps):
             "crs_in_hip_graph_us_per_product": round(ms_g * 1e3 / 100, 2)}
 
 
-def suite_symdiag(torch, sp, dev, steps):
+def load_symdiag(torch, sp, dev, tune_cache=""):
+    """The symmetric-diagonals workload (n = 6,000,000: the diagonal and 12
+    mirrored secondary diagonals, N(0,1) values) in every storage the
+    library has, with launch parameters from the autotuner on this device.
+    The host triplets are kept for the oracle check of the CPU leg."""
     import synth
+    from paper_0910_4836_amd import autotune
     r, c, v, n, _ = synth.sym_diagonals()
     A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
-    del r, c, v
     J = sp.jds_from_csr(A)
     x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(3, 1))).to(dev)
-    from paper_0910_4836_amd import autotune
-    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    tuner = autotune.Autotuner(cache_path=tune_cache or os.path.join(tempfile.mkdtemp(), "autotune.json"))
     crs_bn = autotune.tune_crs(tuner, A, x, J.ndiag)
     ju, jm, jw = tuner.tune_jds(J, x)
     bC, bR, bU, bW = tuner.tune_blocked(J, x)
     B = sp.jds_blocked_from_jds(J, bC)
+    setup = {}
     t0 = time.perf_counter()
     Dd = sp.dia_from_csr(A)
     torch.cuda.synchronize()
-    dia_ms = round((time.perf_counter() - t0) * 1e3, 1)
+    setup["dia_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
     t0 = time.perf_counter()
     Ds = sp.dia_from_csr(A, symmetric=True)
     torch.cuda.synchronize()
-    dia_sym_ms = round((time.perf_counter() - t0) * 1e3, 1)
-    nnz = A.nnz
-    y_ref = sp.spmv_crs(A, x)
-    out = {"workload": f"symmetric 12 secondary diagonals + diagonal, n={n}, nnz={nnz}", "kernels": {},
-           "max_rel_err_vs_fp64": {},
-           "autotuned": {"crs_block_nnz": crs_bn, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw,
-                         "blocked_C": bC,
-                         "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW}}
+    setup["dia_sym_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    tune = {"crs_block_nnz": crs_bn, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw, "blocked_C": bC,
+            "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW}
+    return dict(A=A, J=J, B=B, D=Dd, Ds=Ds, x=x, n=n, nnz=A.nnz, tune=tune, setup=setup, host=(r, c, v, n))
+
+
+def symdiag_kernels(torch, sp, W3, vdt, y):
+    """(name, fn, algorithmic bytes) of the five products with values in vdt
+    and FP64 vectors."""
+    A, J, B, Dd, Ds, x, n, nnz = (W3[k] for k in ("A", "J", "B", "D", "Ds", "x", "n", "nnz"))
+    T = W3["tune"]
+    ju, jm, jw = T["jds_unroll"], T["jds_max_iters"], T["jds_wg_waves"]
+    bR, bU, bW = T["blocked_rows_per_wave"], T["blocked_unroll"], T["blocked_wg_waves"]
+    sv, tag = {torch.float64: (8, "f64"), torch.float32: (4, "f32val"), torch.bfloat16: (2, "bf16val")}[vdt]
+    conv = (lambda t: t) if vdt == torch.float64 else (lambda t: sp.spmv_convert_values(t, vdt))
+    Aq = A.with_values(conv(A.val))
+    Jq = J.with_values(conv(J.jd_val))
+    Bq = B.with_values(conv(B.bl_val))
+    Dq = sp.DIA(Dd.n_rows, Dd.n_cols, Dd.offsets, conv(Dd.dia_val), Dd.rem)
+    Dsq = sp.DIA(Ds.n_rows, Ds.n_cols, Ds.offsets, conv(Ds.dia_val), Ds.rem, True)
+    return [(f"crs_{tag}", lambda: sp.spmv_crs(Aq, x, y), bytes_crs(nnz, n, n, sv, 8)),
+            (f"jds_{tag}", lambda: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm, wg_waves=jw),
+             bytes_jds(nnz, n, n, J.ndiag, sv, 8)),
+            (f"blocked_{tag}", lambda: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW),
+             bytes_blocked(nnz, n, n, B.n_slices, sv, 8)),
+            (f"dia_{tag}", lambda: sp.spmv_dia(Dq, x, y), bytes_dia(Dd, sv, 8)),
+            (f"dia_sym_{tag}", lambda: sp.spmv_dia(Dsq, x, y), bytes_dia(Ds, sv, 8))]
+
+
+def mixed_precision_c3(torch, sp, dev, W3, steps, n_sample=4000):
+    """FP64 against reduced-precision value storage (FP32, BF16; FP64
+    vectors) on the symmetric-diagonals matrix, in CRS, JDS, blocked JDS,
+    DIA and symmetric DIA: time, GFLOP/s, algorithmic bytes, fraction of
+    8 TB/s, speed-up over the same format in FP64, and the error against the
+    FP64 product (the library's FP64 CRS, all rows, scaled by
+    D_i = sum_j |a_ij||x_j|).  Each product's output on a seeded sample of
+    rows is kept for the oracle check of the CPU leg."""
+    n, nnz, x = W3["n"], W3["nnz"], W3["x"]
     y = torch.empty(n, dtype=torch.float64, device=dev)
-    for vdt, sv, tag in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32val"), (torch.bfloat16, 2, "bf16val")):
-        Aq = A if vdt == torch.float64 else A.with_values(sp.spmv_convert_values(A.val, vdt))
-        Jq = J if vdt == torch.float64 else J.with_values(sp.spmv_convert_values(J.jd_val, vdt))
-        Bq = B if vdt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
-        Dq = Dd if vdt == torch.float64 else sp.DIA(Dd.n_rows, Dd.n_cols, Dd.offsets,
-                                                    sp.spmv_convert_values(Dd.dia_val, vdt), Dd.rem)
-        Dsq = Ds if vdt == torch.float64 else sp.DIA(Ds.n_rows, Ds.n_cols, Ds.offsets,
-                                                     sp.spmv_convert_values(Ds.dia_val, vdt), Ds.rem, True)
-        ks = [(f"crs_{tag}", lambda Aq=Aq: sp.spmv_crs(Aq, x, y)),
-              (f"jds_{tag}", lambda Jq=Jq: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
-              (f"blocked_{tag}", lambda Bq=Bq: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU,
-                                                                    wg_waves=bW)),
-              (f"dia_{tag}", lambda Dq=Dq: sp.spmv_dia(Dq, x, y)),
-              (f"dia_sym_{tag}", lambda Dsq=Dsq: sp.spmv_dia(Dsq, x, y))]
-        _, per = time_loop(torch, ks, max(10, steps // 4), 3)
-        bm = {ks[0][0]: bytes_crs(nnz, n, n, sv, 8), ks[1][0]: bytes_jds(nnz, n, n, J.ndiag, sv, 8),
-              ks[2][0]: bytes_blocked(nnz, n, n, B.n_slices, sv, 8), ks[3][0]: bytes_dia(Dd, sv, 8),
-              ks[4][0]: bytes_dia(Ds, sv, 8)}
-        for name, fn in ks:
-            out["kernels"][name] = _kernel_entry(name, 2.0 * nnz, bm[name], per[name])
+    y_ref = sp.spmv_crs(W3["A"], x)
+    Aabs = W3["A"].with_values(W3["A"].val.abs())
+    D = sp.spmv_crs(Aabs, x.abs())
+    nz = D > 0
+    rows = np.sort(np.random.default_rng(20091029).choice(n, n_sample, replace=False))
+    rows_d = torch.from_numpy(rows).to(dev)
+    out = {"workload": f"symmetric diagonals n={n} nnz={nnz} (diagonal + 12 mirrored secondary diagonals), "
+                       f"values in FP64 / FP32 / BF16, x and y FP64", "autotuned": W3["tune"],
+           "dia_diagonals": W3["D"].ndia, "dia_sym_diagonals": W3["Ds"].ndia, "setup_ms": W3["setup"],
+           "kernels": {}}
+    samples = {}
+    fp64_ms = {}
+    for vdt in (torch.float64, torch.float32, torch.bfloat16):
+        ks = symdiag_kernels(torch, sp, W3, vdt, y)
+        _, per = time_loop(torch, [(k, f) for k, f, _ in ks], max(10, steps // 4), 3)
+        for name, fn, bmin in ks:
+            ms = per[name]
+            fam = name.rsplit("_", 1)[0]
+            if vdt == torch.float64:
+                fp64_ms[fam] = ms
+            gbs = bmin / (ms * 1e-3) / 1e9
             fn()
-            out["max_rel_err_vs_fp64"][name] = _rel_err_gpu(torch, sp, A, x, y, y_ref)
-        del Aq, Jq, Bq, Dq, Dsq
-    out["dia"] = {"diagonals": Dd.ndia, "remainder_nnz": Dd.rem.nnz, "setup_ms": dia_ms,
-                  "stored_fp64_bytes": Dd.dia_val.numel() * 8}
-    # symmetric storage: the upper diagonals only, each read twice (its own
-    # rows and, shifted, its mirror's); the algorithmic bytes count it once
-    out["dia_sym"] = {"diagonals": Ds.ndia, "remainder_nnz": Ds.rem.nnz, "setup_ms": dia_sym_ms,
-                      "stored_fp64_bytes": Ds.dia_val.numel() * 8}
+            err = float(((y - y_ref).abs()[nz] / D[nz]).max())
+            samples[name] = y[rows_d].cpu().numpy()
+            out["kernels"][name] = {"avg_ms": round(ms, 5), "gflops": round(2.0 * nnz / (ms * 1e-3) / 1e9, 1),
+                                    "algorithmic_bytes": int(bmin), "algorithmic_GBs": round(gbs, 1),
+                                    "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+                                    "speedup_vs_fp64": round(fp64_ms[fam] / ms, 3),
+                                    "max_rel_err_vs_fp64_product": err}
+        del ks
+    W3["samples"] = (rows, samples)
+    return out
+
+
+def c3_oracle_check(W3):
+    """The sampled rows of every product of the mixed-precision block against
+    the serial FP64 oracle (unrounded values): max_i |y_i - y_oracle_i| / D_i."""
+    import oracle
+    r, c, v, n = W3["host"]
+    rows, samples = W3["samples"]
+    keep = np.zeros(n, dtype=bool)
+    keep[rows] = True
+    sel = keep[r]
+    R = oracle.csr_from_coo(n, n, r[sel], c[sel], v[sel])
+    x = W3["x"].cpu().numpy()
+    want = oracle.spmv_crs(R, x)[rows]
+    D = oracle.row_absdot(R, x)[rows]
+    return {name: float(oracle.rel_err(got, want, D).max()) for name, got in samples.items()}
+
+
+def suite_symdiag(torch, sp, dev, steps):
+    """The symmetric-diagonals products (as in the default line) plus the
+    SOJDS ordering of the blocked storage."""
+    W3 = load_symdiag(torch, sp, dev)
+    out = mixed_precision_c3(torch, sp, dev, W3, steps)
+    n, nnz, x, J = W3["n"], W3["nnz"], W3["x"], W3["J"]
+    T = W3["tune"]
+    bC, bR, bU, bW = T["blocked_C"], T["blocked_rows_per_wave"], T["blocked_unroll"], T["blocked_wg_waves"]
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    y_ref = sp.spmv_crs(W3["A"], x)
     # SOJDS (paper Section 2): the same slices with every row's entries
     # re-assigned to diagonal slots for near-unit x strides across rows
     t0 = time.perf_counter()
@@ -666,10 +764,9 @@ def suite_symdiag(torch, sp, dev, steps):
                                                         bytes_blocked(nnz, n, n, Bs.n_slices, 8, 8),
                                                         per["blocked_sojds_f64"])
     ks[0][1]()
-    out["max_rel_err_vs_fp64"]["blocked_sojds_f64"] = _rel_err_gpu(torch, sp, A, x, y, y_ref)
+    out["kernels"]["blocked_sojds_f64"]["max_rel_err_vs_fp64_product"] = _rel_err_gpu(torch, sp, W3["A"], x, y, y_ref)
     del Bs
-    f64 = out["kernels"]["crs_f64"]["avg_us"]
-    out["speedup_vs_fp64_crs"] = {k: round(f64 / e["avg_us"], 2) for k, e in out["kernels"].items()}
+    W3.pop("samples", None)
     return out
 
 
@@ -986,6 +1083,22 @@ def suite_lines(torch, sp, dev, W, steps, warmup, only=""):
     return lines
 
 
+def run_symdiag_only(torch, sp, dev, args):
+    """Profiling runs of the symmetric-diagonals products: the kernels named
+    by --only (all fifteen if none), eager loop, one JSON line."""
+    W3 = load_symdiag(torch, sp, dev, args.tune_cache)
+    y = torch.empty(W3["n"], dtype=torch.float64, device=dev)
+    keep = set(args.only.split(",")) if args.only else None
+    out = {"workload": "symdiag", "kernels": {}}
+    for vdt in (torch.float64, torch.float32, torch.bfloat16):
+        ks = [(k, f) for k, f, _ in symdiag_kernels(torch, sp, W3, vdt, y) if keep is None or k in keep]
+        if not ks:
+            continue
+        _, per = time_loop(torch, ks, args.steps, args.warmup)
+        out["kernels"].update({k: round(ms, 5) for k, ms in per.items()})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1000,7 +1113,11 @@ def main():
     sp.load_library()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "symdiag":
+        run_symdiag_only(torch, sp, dev, args)
+        return
     W = load_powerlaw(torch, sp, dev, args.tune_cache)
+    print("# power-law workload built", file=sys.stderr, flush=True)
     all_ks, bmin = powerlaw_kernels(sp, W, torch)
     # the step: the three FP64 products of the power-law workload
     plain = [k for k in all_ks if "split" not in k[0]]
@@ -1065,10 +1182,20 @@ def main():
                                        speedup_vs_unsplit=round(unsplit[name.replace("_rowsplit", "")] / per_r[name],
                                                                 3))
                             for name, _ in rsplit}
+    W3 = None
+    if not args.only and not args.no_c3:
+        print("# mixed-precision block: symmetric-diagonals matrix", file=sys.stderr, flush=True)
+        W3 = load_symdiag(torch, sp, dev, args.tune_cache)
+        out["mixed_precision_c3"] = mixed_precision_c3(torch, sp, dev, W3, args.steps)
+        for k in ("A", "J", "B", "D", "Ds"):
+            W3.pop(k)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(W)
+        print("# CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(W, W3=W3)
     else:
         out["cpu_baseline"] = None
+    del W3
     # the step's products from cold caches (MALL and L2 flushed before each launch)
     cold = cold_times(torch, sp, dev, ks)
     out["cold"] = {name: {"median_ms": round(ms, 5), "gflops": round(2.0 * W["nnz"] / (ms * 1e-3) / 1e9, 1),

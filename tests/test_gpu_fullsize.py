@@ -250,3 +250,106 @@ def test_many_matrices_sampled():
         lim = (gamma(R.row_lengths() + 1, U32) + U32) * oracle.row_absdot(R, xx)
         got = y[Bt.row_base[m]:Bt.row_base[m] + n].astype(np.float64)
         assert np.all(np.abs(got - want) <= lim), m
+
+
+@pytest.mark.timeout(900)
+def test_chebyshev_loss_and_gradient_full_size():
+    """The full differentiable workload: n = 4,000,000, 80 M entries (16
+    banded + 4 uniform per row, scaled to norm_inf = 1), 20-step Chebyshev
+    recurrence, loss = ||y_20||^2, backward with a checkpoint every 5 steps,
+    the operator's JDS launch taken from the autotuner as the benchmark does.
+      FP32 on the GPU against the FP64 oracle (same FP32-rounded values):
+          loss, y_20, dx, dvals within 2e-3 norm-wise (the FP32 recurrence
+          bound of the small tests).
+      FP64 on the GPU (same values): loss, dx, dvals within 1e-10 of the
+          oracle, and a directional derivative <dx, u> + <dvals, w> for
+          seeded directions supported on a 2,000-row slice (u on x's slice,
+          w on those rows' entries) against central differences of the GPU
+          FP64 loss: exact for u (the loss is quadratic in x), Richardson-
+          extrapolated from eps = 1e-3 and 5e-4 for w (error O(eps^4));
+          both within 1e-6 of sum |u_i dx_i| (resp. |w_e dval_e|)."""
+    from paper_0910_4836_amd import autograd as AG
+    from paper_0910_4836_amd import autotune
+    import tempfile
+    import os
+
+    def say(msg):
+        print(f"[c5 full] {msg}", flush=True)
+
+    r, c, v, n, _ = synth.banded_uniform()
+    assert n == 4_000_000 and len(r) == 80_000_000
+    x32 = synth.uniform_vector(n, synth.rng_for(5, 1), np.float32)
+    x64 = x32.astype(np.float64)
+    say("generated")
+    R = oracle.csr_from_coo(n, n, r, c, v.astype(np.float64))
+    loss_ref, dx_ref, dval_ref, ys = oracle.cheb_loss_grad(R, x64, 20)
+    y20_ref = ys[20].copy()
+    del ys
+    say(f"oracle loss {loss_ref:.6e}")
+
+    def rel_inf(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    # FP32 operator, autotuned JDS launch
+    A32 = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v))
+    op = AG.SpMVOperator(A32)
+    xd32 = to_dev(x32)
+    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    op.unroll, op.max_iters, op.wg_waves = tuner.tune_jds(op.J, xd32)
+    order = to_np(op.jds_src).astype(np.int64)          # JDS slot -> CRS position
+    vals = op.J.jd_val.clone().requires_grad_(True)
+    xt = xd32.clone().requires_grad_(True)
+    loss = AG.chebyshev_loss(op, vals, xt, steps=20, checkpoint=5)
+    loss.backward()
+    say(f"fp32 loss {loss.item():.6e}")
+    assert abs(loss.item() - loss_ref) <= 2e-3 * abs(loss_ref)
+    assert rel_inf(to_np(xt.grad).astype(np.float64), dx_ref) <= 2e-3
+    assert rel_inf(to_np(vals.grad).astype(np.float64), dval_ref[order]) <= 2e-3
+    y20 = AG.cheb_states(op, vals.detach(), xd32, 20)[20]
+    assert rel_inf(to_np(y20).astype(np.float64), y20_ref) <= 2e-3
+    del A32, op, vals, xt, y20
+    torch.cuda.empty_cache()
+
+    # FP64 operator over the same values
+    A64 = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v.astype(np.float64)))
+    op64 = AG.SpMVOperator(A64)
+    op64.unroll, op64.max_iters, op64.wg_waves = tuner.tune_jds(op64.J, to_dev(x64))
+    assert np.array_equal(to_np(op64.jds_src).astype(np.int64), order)
+    v64 = op64.J.jd_val.clone()
+    xd64 = to_dev(x64)
+    vals = v64.clone().requires_grad_(True)
+    xt = xd64.clone().requires_grad_(True)
+    loss = AG.chebyshev_loss(op64, vals, xt, steps=20, checkpoint=5)
+    loss.backward()
+    dx64 = to_np(xt.grad)
+    dv64 = to_np(vals.grad)
+    say(f"fp64 loss {loss.item():.15e}")
+    assert abs(loss.item() - loss_ref) <= 1e-10 * abs(loss_ref)
+    assert rel_inf(dx64, dx_ref) <= 1e-10
+    assert rel_inf(dv64, dval_ref[order]) <= 1e-10
+    del vals, xt
+
+    # directions on a 2,000-row slice
+    rng = np.random.default_rng(20091031)
+    r0 = int(rng.integers(0, n - 2000))
+    u = np.zeros(n)
+    u[r0:r0 + 2000] = rng.uniform(-1, 1, 2000)
+    w_crs = np.zeros(R.nnz)
+    a, b = int(R.row_ptr[r0]), int(R.row_ptr[r0 + 2000])
+    w_crs[a:b] = rng.standard_normal(b - a) * np.abs(R.val[a:b])   # relative changes of the slice's values
+    w = w_crs[order]
+    ud, wd = to_dev(u), to_dev(w)
+
+    def loss64(tx, tv):
+        with torch.no_grad():
+            return AG.chebyshev_loss(op64, v64 + tv * wd, xd64 + tx * ud, steps=20, checkpoint=20).item()
+
+    fd_x = (loss64(1e-3, 0.0) - loss64(-1e-3, 0.0)) / 2e-3
+
+    def fd_v(e):
+        return (loss64(0.0, e) - loss64(0.0, -e)) / (2 * e)
+    fd_w = (4 * fd_v(5e-4) - fd_v(1e-3)) / 3
+    dd_x, dd_w = float(np.dot(dx64, u)), float(np.dot(dv64, w))
+    say(f"directional: x {dd_x:.9e} vs FD {fd_x:.9e}; vals {dd_w:.9e} vs FD {fd_w:.9e}")
+    assert abs(dd_x - fd_x) <= 1e-6 * float(np.abs(dx64 * u).sum())
+    assert abs(dd_w - fd_w) <= 1e-6 * float(np.abs(dv64 * w).sum())
