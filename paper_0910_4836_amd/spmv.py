@@ -364,7 +364,9 @@ def _check_blocks(X: torch.Tensor, Y: Optional[torch.Tensor], n_rows: int, n_col
     _ld(X, n_cols)
     if Y is not None:
         _ld(Y, n_rows)
-    _check_dev(X, Y)
+    for t in (X, Y):
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on the GPU")
 
 
 def spmm_workspace(n_cols: int, k: int, dtype, device) -> torch.Tensor:
