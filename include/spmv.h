@@ -251,6 +251,22 @@ size_t spmv_dot_workspace_size(int64_t n);
 spmv_status spmv_dot(int64_t n, const void *x, const void *y, spmv_dtype dt, double *out, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* spmv_dot without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the block partials go to a fixed array inside the
+ * library (SPMV_DOT_NOALLOC_PARTS doubles, 256 KiB, one per GPU, held until
+ * the process ends).  Same kernels and summation tree as spmv_dot, so the
+ * result is bit-identical to it.  n > SPMV_DOT_NOALLOC_MAX_N returns
+ * SPMV_ERR_CAPACITY before any device work.  The call allocates nothing and
+ * does not synchronise.  Every call on one GPU shares that GPU's array:
+ * calls whose executions overlap on one GPU (different streams, or graphs
+ * replayed concurrently) race on it and give undefined results; calls
+ * ordered on one stream are safe. */
+#define SPMV_DOT_NOALLOC_PARTS 32768
+#define SPMV_DOT_NOALLOC_MAX_N 134217728 /* SPMV_DOT_NOALLOC_PARTS * 4096 elements */
+spmv_status spmv_dot_noalloc(int64_t n, const void *x, const void *y, spmv_dtype dt, double *out,
+                             void *stream);
+
 /* Multi-vector forms: Y[:, c] = alpha*A X[:, c] + beta*Y[:, c] for c < k,
  * X and Y column-major with leading dimensions ldx >= n_cols and ldy >= n
  * (the paper's kernels, each stored entry used for k right-hand sides).

@@ -64,6 +64,7 @@ SIGNATURES = {
     "spmv_axpby": (_int, [_i64, _f64, _p, _f64, _p, _int, _p]),
     "spmv_dot_workspace_size": (_sz, [_i64]),
     "spmv_dot": (_int, [_i64, _p, _p, _int, _p, _p, _sz, _p]),
+    "spmv_dot_noalloc": (_int, [_i64, _p, _p, _int, _p, _p]),
     "spmm_workspace_size": (_sz, [_i32, _i32, _int]),
     "spmm_crs": (_int, [_i32, _i32, _p, _p, _p, _int, _i32, _p, _i64, _p, _i64, _int, _f64, _f64, _p, _i32, _i32,
                         _p, _sz, _p]),

@@ -1,5 +1,6 @@
 // Status strings, error plumbing, small vector kernels, HIP graph helpers and
 // bandwidth probes.
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -288,6 +289,74 @@ spmv_status spmv_dot(int64_t n, const void *x, const void *y, spmv_dtype dt, dou
     }
     dot_final_kernel<<<1, DOT_THREADS, 0, s>>>(parts, part, out);
     SPMV_CHECK_LAUNCH("spmv_dot final");
+    return SPMV_OK;
+}
+
+}  // extern "C"
+
+namespace spmv {
+
+// Scratch of spmv_dot_noalloc: the block partials of the dot product, one
+// array per GPU for the life of the process.  Host code never passes the
+// name `scratch` to a kernel (on the host it is only a stand-in for the
+// symbol); it looks up the device address once per device and uses that.
+static __device__ __align__(256) double scratch[SPMV_DOT_NOALLOC_PARTS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of the current device's scratch array, looked up on the
+// first call on that device (with that device current).
+static spmv_status scratch_for_current_device(double **out)
+{
+    int dev = 0;
+    SPMV_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(SPMV_ERR_UNSUPPORTED, "spmv_dot_noalloc: device index >= 64");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SPMV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SPMV_ERR_HIP, "spmv_dot_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SPMV_OK;
+}
+
+}  // namespace spmv
+
+extern "C" {
+
+spmv_status spmv_dot_noalloc(int64_t n, const void *x, const void *y, spmv_dtype dt, double *out, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_dot_noalloc: n < 0");
+    if (n > SPMV_DOT_NOALLOC_MAX_N)
+        return fail(SPMV_ERR_CAPACITY, "spmv_dot_noalloc: n > SPMV_DOT_NOALLOC_MAX_N (134,217,728); use spmv_dot "
+                                       "with a workspace");
+    SPMV_REQUIRE(valid_vec_dtype(dt), "spmv_dot_noalloc: dtype must be F64 or F32");
+    SPMV_REQUIRE(out, "spmv_dot_noalloc: null output");
+    SPMV_REQUIRE(n == 0 || (x && y), "spmv_dot_noalloc: null input");
+    static_assert((int64_t)SPMV_DOT_NOALLOC_PARTS * DOT_CHUNK == SPMV_DOT_NOALLOC_MAX_N,
+                  "the scratch array holds one partial per chunk of the largest input");
+    double *part = nullptr;
+    spmv_status st = scratch_for_current_device(&part);
+    if (st != SPMV_OK) return st;
+    // every partial the final kernel reads is written by this call's first
+    // kernel, so nothing left by an earlier call is read
+    const int64_t parts = n > 0 ? ceil_div(n, DOT_CHUNK) : 0;
+    hipStream_t s = as_stream(stream);
+    if (parts > 0) {
+        if (dt == SPMV_F64)
+            dot_partial_kernel<double><<<(unsigned)parts, DOT_THREADS, 0, s>>>(n, (const double *)x, (const double *)y, part);
+        else
+            dot_partial_kernel<float><<<(unsigned)parts, DOT_THREADS, 0, s>>>(n, (const float *)x, (const float *)y, part);
+        SPMV_CHECK_LAUNCH("spmv_dot_noalloc partial");
+    }
+    dot_final_kernel<<<1, DOT_THREADS, 0, s>>>(parts, part, out);
+    SPMV_CHECK_LAUNCH("spmv_dot_noalloc final");
     return SPMV_OK;
 }
 

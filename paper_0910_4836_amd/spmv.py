@@ -436,6 +436,19 @@ def spmv_dot(x: torch.Tensor, y: torch.Tensor, out: Optional[torch.Tensor] = Non
     return out
 
 
+def spmv_dot_noalloc(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """sum_i x_i y_i into the 1-element FP64 device tensor `out`, with the
+    library's own scratch array instead of a workspace (no allocation here or
+    in the library; bit-identical to spmv_dot)."""
+    _check_dev(x, y, out)
+    if x.dtype not in _VEC_DTYPES or y.dtype != x.dtype or y.numel() != x.numel():
+        raise ValueError("x and y must be float64 or float32 vectors of one dtype and length")
+    if out.dtype != torch.float64 or out.numel() < 1:
+        raise ValueError("out must be a float64 device tensor")
+    call("spmv_dot_noalloc", x.numel(), _p(x), _p(y), dtype_code(x.dtype), _p(out), _stream())
+    return out
+
+
 def spmv_grad_vals_jds(J: JDS, g: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None,
                        alpha: float = 1.0, beta: float = 0.0) -> torch.Tensor:
     """dval[e] = alpha*g[row_e]*x[col_e] + beta*dval[e] over the JDS entries."""
