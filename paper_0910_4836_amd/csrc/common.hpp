@@ -40,6 +40,10 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 spmv_status launch_combine(int32_t n, const int32_t *slot_ptr, const double *slots, void *y, spmv_dtype vec_dt,
                            double alpha, double beta, hipStream_t s);
 
+// Compute units of the current device (queried once per device, util.hip);
+// 256 if the query fails.
+int device_cus();
+
 // Default rows-block size of the CRS plans (crs.hip).
 int32_t crs_default_block_nnz();
 

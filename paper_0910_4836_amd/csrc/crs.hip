@@ -34,6 +34,14 @@ constexpr int CRS_MAX_BLOCK_NNZ = 4096;
 constexpr int CRS_MAX_BLOCK_ROWS = 256;          // rows of a block in general
 constexpr int CRS_MAX_SHORT_BLOCK_ROWS = 2048;   // rows of a block of short rows only
 constexpr int CRS_SHORT_ROW = 16;                // "short": at most this many entries
+constexpr int CRS_STREAM_U = 4;                  // stream mode: entries per lane per trip
+constexpr int CRS_LDS_ROUND = CRS_STREAM_U * CRS_THREADS;   // products per trip
+
+// LDS bytes of a block kernel: block_nnz products rounded up to whole trips.
+inline size_t crs_lds_bytes(int32_t block_nnz, size_t acc_bytes)
+{
+    return (size_t)ceil_div(block_nnz, CRS_LDS_ROUND) * CRS_LDS_ROUND * acc_bytes;
+}
 
 template <bool WIDE, typename VT, typename XT, typename OT>
 __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, const VT *__restrict__ val,
@@ -71,6 +79,43 @@ __device__ __forceinline__ void crs_vector_row(const int32_t *__restrict__ col, 
     }
 }
 
+// Row sums of a multi-row block whose products sit in LDS (prod[k] = product
+// of entry e0 + k): G lanes per row (G = largest power of two <= 256/nr, at
+// most 64) with a fixed shuffle tree, or, in a block of more than 256 short
+// rows, one lane per row adding its products in order.
+// rs, re: the bounds of row r0 + t / G (G as below), loaded by the caller
+// (for blocks of at most 256 rows) before the products, off the critical path.
+template <typename acc_t, typename OT>
+__device__ __forceinline__ void crs_row_sums(const int32_t *__restrict__ row_ptr, const acc_t *prod, int32_t r0,
+                                             int32_t nr, int32_t e0, OT *__restrict__ y, double alpha, double beta,
+                                             const int32_t *__restrict__ out_idx, int32_t rs, int32_t re)
+{
+    const int t = (int)threadIdx.x;
+    if (nr > CRS_THREADS) {
+        // many short rows (the planner admits more than 256 rows only when
+        // none has more than 16 entries): one lane per row, rows t, t+256, ...
+        for (int32_t g = t; g < nr; g += CRS_THREADS) {
+            const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
+            acc_t s = 0;
+            for (int32_t k = rs; k < re; ++k) s += prod[k];
+            const int32_t row = r0 + g;
+            write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
+        }
+        return;
+    }
+    int G = 64;
+    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
+    const int g = t / G, l = t % G;
+    acc_t s = 0;
+    if (g < nr)
+        for (int32_t k = rs - e0 + l; k < re - e0; k += G) s += prod[k];
+    s = group_sum(s, G);
+    if (g < nr && l == 0) {
+        const int32_t row = r0 + g;
+        write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
+    }
+}
+
 // One plan block b (rows plan[b] .. plan[b+1]) of y = alpha*A x + beta*y;
 // row r's result goes to y[out_idx[r]] if out_idx is given, else to y[r].
 // WIDE_ALL: accumulate every row in FP64 (the column-split parts, whose rows
@@ -98,54 +143,45 @@ __device__ __forceinline__ void crs_block_body(const int32_t *__restrict__ row_p
         return;
     }
 
+    // the row bounds the row sums need, loaded now so that their latency
+    // overlaps that of the entries and gathers
+    int32_t rs = 0, re = 0;
+    if (nr <= CRS_THREADS) {
+        int G = 64;
+        while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
+        const int g = t / G;
+        if (g < nr) {
+            rs = row_ptr[r0 + g];
+            re = row_ptr[r0 + g + 1];
+        }
+    }
+
     // stream mode: products of the whole block into LDS (ne <= block_nnz);
-    // each lane issues its U loads of val/col before the dependent gathers
-    constexpr int U = 4;
-    for (int32_t k0 = 0; k0 < ne; k0 += U * CRS_THREADS) {
-        int32_t c[U];
-        VT v[U];
+    // each lane issues its U loads of val/col, then its U gathers, all before
+    // it waits on any of them.  Lanes past the block's end load its last
+    // entry again and store into LDS slots past ne, which hold
+    // CRS_LDS_ROUND-rounded room and are never read: no branch around a
+    // load, so the compiler cannot sink a gather behind a wait for another.
+    constexpr int U = CRS_STREAM_U;
+    if (ne > 0) {
+        for (int32_t k0 = 0; k0 < ne; k0 += U * CRS_THREADS) {
+            int32_t c[U];
+            VT v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t k = k0 + u * CRS_THREADS + t;
-            if (k < ne) {
+            for (int u = 0; u < U; ++u) {
+                const int32_t k = min(k0 + u * CRS_THREADS + t, ne - 1);
                 c[u] = ld_stream(col + e0 + k);
                 v[u] = ld_stream(val + e0 + k);
             }
-        }
+            XT xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t k = k0 + u * CRS_THREADS + t;
-            if (k < ne) prod[k] = Acc<F64>::mac((acc_t)0, v[u], x[c[u]]);
+            for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) prod[k0 + u * CRS_THREADS + t] = Acc<F64>::mac((acc_t)0, v[u], xv[u]);
         }
     }
     __syncthreads();
-
-    if (nr > CRS_THREADS) {
-        // many short rows (the planner admits more than 256 rows only when
-        // none has more than 16 entries): one lane per row, rows t, t+256, ...
-        for (int32_t g = t; g < nr; g += CRS_THREADS) {
-            const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
-            acc_t s = 0;
-            for (int32_t k = rs; k < re; ++k) s += prod[k];
-            const int32_t row = r0 + g;
-            write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
-        }
-        return;
-    }
-    // G lanes per row, G = largest power of two <= 256/nr, at most 64
-    int G = 64;
-    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
-    const int g = t / G, l = t % G;
-    acc_t s = 0;
-    if (g < nr) {
-        const int32_t rs = row_ptr[r0 + g] - e0, re = row_ptr[r0 + g + 1] - e0;
-        for (int32_t k = rs + l; k < re; k += G) s += prod[k];
-    }
-    s = group_sum(s, G);
-    if (g < nr && l == 0) {
-        const int32_t row = r0 + g;
-        write_y(y, out_idx ? out_idx[row] : row, (double)s, alpha, beta);
-    }
+    crs_row_sums<acc_t>(row_ptr, prod, r0, nr, e0, y, alpha, beta, out_idx, rs, re);
 }
 
 template <typename VT, typename XT>
@@ -333,7 +369,7 @@ static spmv_status launch_crs(int32_t n_rows, const int32_t *row_ptr, const int3
 {
     if (plan) {
         if (n_blocks == 0) return SPMV_OK;
-        size_t lds = (size_t)block_nnz * (IsF64<VT>::value ? 8 : 4);
+        const size_t lds = crs_lds_bytes(block_nnz, IsF64<VT>::value ? 8 : 4);
         crs_block_kernel<VT, XT><<<n_blocks, CRS_THREADS, lds, s>>>(row_ptr, col, (const VT *)val, (const XT *)x,
                                                                    (XT *)y, plan, alpha, beta);
     } else {
@@ -474,7 +510,7 @@ spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_pt
     if (grid) {
 #define CSPLIT_CASE(VDT, VT, XDT, XT)                                                                          \
     if (val_dt == VDT && vec_dt == XDT) {                                                                      \
-        const size_t lds = (size_t)block_nnz * 8;                                                              \
+        const size_t lds = crs_lds_bytes(block_nnz, 8);                                                        \
         crs_split_kernel<VT, XT><<<grid, CRS_THREADS, lds, s>>>(row_ptr_all, dest_all, col_idx, (const VT *)val, \
                                                                (const XT *)x, slots, plan_all, T);             \
     } else

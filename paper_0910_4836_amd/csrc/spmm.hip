@@ -40,6 +40,13 @@ constexpr int mm_jds_lpr() { return K2 <= 8 ? K2 : 8; }
 constexpr int MM_JDS_THREADS = 512;
 constexpr int MM_MAX_K2 = 64;
 constexpr int MM_JP_LDS = 4097;            // jd_ptr entries staged in LDS (ndiag <= 4096)
+// Rows of a multi-row CRS block whose offsets can be staged in LDS: twice
+// the block's entries (a block of non-empty rows has at most block_nnz), at
+// most 2048 (the planner's largest block of short rows).
+__host__ __device__ constexpr int32_t mm_rp_lds(int32_t block_nnz)
+{
+    return 2 * block_nnz < 2048 ? 2 * block_nnz : 2048;
+}
 
 // Xr[c*k + j] = X[c + j*ldx] (k <= 64): a block of STAGE_ELEMS / k rows
 // through LDS.  Reads walk each column's run of rows (coalesced), writes walk
@@ -124,8 +131,8 @@ __device__ __forceinline__ void mm_group_sum(const int32_t *__restrict__ col, co
 // by the group whose share holds their position; those after the last entry
 // by the last group.
 template <int LPR, int CPL, int NG, int K2, bool WIDE, typename VT, typename XT>
-__device__ __forceinline__ void mm_crs_balanced(const int32_t *__restrict__ row_ptr, int32_t r0, int32_t r1,
-                                                int32_t be0, const int32_t *col_s, const VT *val_s,
+__device__ __forceinline__ void mm_crs_balanced(const int32_t *rp, int32_t r0, int32_t r1,
+                                                const int32_t *col_s, const VT *val_s,
                                                 const XT *__restrict__ Xr, int32_t k, XT *__restrict__ Y,
                                                 int64_t ldy, double alpha, double beta, int g, int j,
                                                 double (*lead)[K2], double (*tail)[K2], int32_t *lead_row,
@@ -133,7 +140,7 @@ __device__ __forceinline__ void mm_crs_balanced(const int32_t *__restrict__ row_
 {
     typedef typename Acc<WIDE>::T acc_t;
     constexpr int U = CPL >= 8 ? 1 : 8 / CPL;
-    const int32_t E = row_ptr[r1] - be0;
+    const int32_t E = rp[r1 - r0];
     const int32_t cs = (int32_t)((int64_t)g * E / NG), ce = (int32_t)((int64_t)(g + 1) * E / NG);
     auto put = [&](int32_t row, const acc_t *v) {
 #pragma unroll
@@ -145,11 +152,11 @@ __device__ __forceinline__ void mm_crs_balanced(const int32_t *__restrict__ row_
     for (int t = 0; t < CPL; ++t) zero[t] = 0;
     if (j == 0) lead_row[g] = tail_row[g] = -1;
     __syncthreads();
-    // first row with row_ptr >= be0 + cs
+    // first row starting at or after entry cs
     int32_t lo = r0, hi = r1 + 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
-        if (row_ptr[mid] < be0 + cs) lo = mid + 1;
+        if (rp[mid - r0] < cs) lo = mid + 1;
         else hi = mid;
     }
     if (cs == ce) {
@@ -158,15 +165,15 @@ __device__ __forceinline__ void mm_crs_balanced(const int32_t *__restrict__ row_
     } else {
         int32_t cr;
         bool here;
-        if (lo > r1 || row_ptr[lo] > be0 + cs) {
+        if (lo > r1 || rp[lo - r0] > cs) {
             cr = lo - 1;                                   // the row holding entry cs started before it
             here = false;
         } else {
             cr = lo;
             here = true;
-            while (cr < r1 && row_ptr[cr + 1] - be0 == cs) put(cr++, zero);    // empty rows at cs
+            while (cr < r1 && rp[cr + 1 - r0] == cs) put(cr++, zero);    // empty rows at cs
         }
-        int32_t bnd = row_ptr[cr + 1] - be0;
+        int32_t bnd = rp[cr + 1 - r0];
         acc_t s[CPL];
 #pragma unroll
         for (int t = 0; t < CPL; ++t) s[t] = 0;
@@ -200,8 +207,8 @@ __device__ __forceinline__ void mm_crs_balanced(const int32_t *__restrict__ row_
                     for (int t = 0; t < CPL; ++t) s[t] = 0;
                     ++cr;
                     here = true;
-                    while (cr < r1 && row_ptr[cr + 1] - be0 == e + u) put(cr++, zero);   // empty rows
-                    bnd = row_ptr[cr + 1] - be0;
+                    while (cr < r1 && rp[cr + 1 - r0] == e + u) put(cr++, zero);   // empty rows
+                    bnd = rp[cr + 1 - r0];
                 }
 #pragma unroll
                 for (int t = 0; t < CPL; ++t) s[t] = Acc<WIDE>::mac(s[t], v[u], xv[u][t]);
@@ -267,9 +274,11 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
     __shared__ double part[NG][K2];
     __shared__ double tailp[sizeof(XT) == 8 ? NG : 1][K2];
     __shared__ int32_t lead_row[NG], tail_row[NG];
-    extern __shared__ int32_t mm_stage[];               // block_nnz cols, then block_nnz values
+    // block_nnz cols, block_nnz values, then the block's row offsets
+    extern __shared__ int32_t mm_stage[];
     int32_t *col_s = mm_stage;
     VT *val_s = reinterpret_cast<VT *>(mm_stage + ((block_nnz + 3) & ~3));
+    int32_t *rp_s = reinterpret_cast<int32_t *>(val_s + ((block_nnz + 1) & ~1));
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int32_t r0 = plan[b], r1 = plan[b + 1];
     const int32_t nr = r1 - r0;
@@ -281,6 +290,12 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
     const int rows_per_round = NG / GPR;
     const bool wide = !F64 && nr == 1 && row_ptr[r1] - row_ptr[r0] > SPMV_WIDE_ROW_NNZ;
     const bool staged = nr > 1;                           // then ne <= block_nnz (plan contract)
+    // with FP64 vectors the row offsets go to LDS too when the block has at
+    // most mm_rp_lds(block_nnz) rows (the share search and the row ends are
+    // then LDS reads, not dependent memory round trips: 1.15x at k = 8 and 32);
+    // FP32 vectors keep them in memory (their one-wavefront workgroups need
+    // the LDS for occupancy)
+    const bool rp_lds = sizeof(XT) == 8 && staged && nr <= mm_rp_lds(block_nnz);
     int32_t be0 = 0;
     if (staged) {
         be0 = row_ptr[r0];
@@ -289,14 +304,18 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
             col_s[i] = ld_stream(col + be0 + i);
             val_s[i] = ld_stream(val + be0 + i);
         }
+        if (rp_lds)
+            for (int32_t i = t; i <= nr; i += NT) rp_s[i] = row_ptr[r0 + i] - be0;
         __syncthreads();
         // FP64 vectors: entry-balanced shares (3-9% faster than rows in
         // rounds on the power-law matrix); FP32 vectors keep the rounds
         // (the shares were 1.3x slower at k = 32 with one-wavefront groups)
         if constexpr (sizeof(XT) == 8) {
-            mm_crs_balanced<LPR, CPL, NG, K2, F64, VT, XT>(row_ptr, r0, r1, be0, col_s, val_s, Xr, k, Y, ldy, alpha,
-                                                           beta, g, j, part, tailp, lead_row, tail_row);
-            return;
+            if (rp_lds) {
+                mm_crs_balanced<LPR, CPL, NG, K2, F64, VT, XT>(rp_s, r0, r1, col_s, val_s, Xr, k, Y, ldy, alpha,
+                                                               beta, g, j, part, tailp, lead_row, tail_row);
+                return;
+            }
         }
     }
     for (int32_t rbase = r0; rbase < r1; rbase += rows_per_round) {
@@ -305,7 +324,8 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
 #pragma unroll
         for (int q = 0; q < CPL; ++q) td[q] = 0.0;
         if (row < r1) {
-            const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+            const int32_t e0 = rp_lds ? rp_s[row - r0] + be0 : row_ptr[row];
+            const int32_t e1 = rp_lds ? rp_s[row + 1 - r0] + be0 : row_ptr[row + 1];
             if (staged) {
                 if (F64) mm_group_sum<LPR, CPL, true, VT, XT>(col_s, val_s, Xr, k, j, e0 - be0 + sub, e1 - be0, GPR, td);
                 else mm_group_sum<LPR, CPL, false, VT, XT>(col_s, val_s, Xr, k, j, e0 - be0 + sub, e1 - be0, GPR, td);
@@ -563,7 +583,8 @@ static void launch_crs_il(const int32_t *row_ptr, const int32_t *col, const void
                           void *Y, int64_t ldy, const int32_t *plan, int32_t nb, int32_t block_nnz, double alpha,
                           double beta, hipStream_t s)
 {
-    const size_t lds = (size_t)((block_nnz + 3) & ~3) * 4 + (size_t)block_nnz * sizeof(VT);
+    const size_t lds = (size_t)((block_nnz + 3) & ~3) * 4 + (size_t)((block_nnz + 1) & ~1) * sizeof(VT) +
+                       (sizeof(XT) == 8 ? sizeof(int32_t) * ((size_t)mm_rp_lds(block_nnz) + 1) : 0);
     constexpr int NT = mm_crs_threads<K2, XT>();
     spmm_crs_il_kernel<K2, NT, VT, XT><<<nb, NT, lds, s>>>(row_ptr, col, (const VT *)val, (const XT *)Xr, k,
                                                           (XT *)Y, ldy, plan, block_nnz, alpha, beta);

@@ -23,6 +23,22 @@ spmv_status hip_fail(hipError_t e, const char *what)
     return SPMV_ERR_HIP;
 }
 
+int device_cus()
+{
+    static std::mutex mu;
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
 // ---------------------------------------------------------------- kernels
 
 template <typename T>
