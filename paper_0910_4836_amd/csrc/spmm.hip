@@ -48,29 +48,50 @@ __host__ __device__ constexpr int32_t mm_rp_lds(int32_t block_nnz)
     return 2 * block_nnz < 2048 ? 2 * block_nnz : 2048;
 }
 
-// Xr[c*k + j] = X[c + j*ldx] (k <= 64): a block of STAGE_ELEMS / k rows
+// Xr[c*k + j] = X[c + j*ldx] (2 <= k <= 64): a block of STAGE_ELEMS / k rows
 // through LDS.  Reads walk each column's run of rows (coalesced), writes walk
-// the block's contiguous stretch of Xr (coalesced).
+// the block's contiguous stretch of Xr (coalesced).  Each lane issues all
+// of its STAGE_PER_LANE reads before its LDS stores, and all of its LDS reads
+// before its global stores, so a lane keeps 8 loads in flight.  (k = 1
+// needs no staging: X itself is the row-major block.)
 constexpr int STAGE_ELEMS = 2048;
+constexpr int STAGE_THREADS = 256;
+constexpr int STAGE_PER_LANE = STAGE_ELEMS / STAGE_THREADS;
 
 template <typename T>
-__global__ __launch_bounds__(256) void stage_rowmajor_kernel(int64_t n, int32_t k, const T *__restrict__ X, int64_t ldx,
-                                                             T *__restrict__ Xr)
+__global__ __launch_bounds__(STAGE_THREADS) void stage_rowmajor_kernel(int64_t n, int32_t k, const T *__restrict__ X,
+                                                                       int64_t ldx, T *__restrict__ Xr)
 {
-    __shared__ T tile[2 * STAGE_ELEMS];                 // rows * (k + 1) <= STAGE_ELEMS + rows
-    const int rows = STAGE_ELEMS / k;                   // rows of this block (k <= 64)
+    __shared__ T tile[STAGE_ELEMS + STAGE_ELEMS / 2];   // rows * (k + 1) for k >= 2
+    const int rows = STAGE_ELEMS / k;                   // rows of this block
     const int64_t c0 = (int64_t)blockIdx.x * rows;
     const int nr = n - c0 < rows ? (int)(n - c0) : rows;
     const int tot = nr * k;
     const int stride = k + 1;                           // padded LDS rows
-    for (int f = (int)threadIdx.x; f < rows * k; f += 256) {
+    const int t = (int)threadIdx.x;
+    T v[STAGE_PER_LANE];
+#pragma unroll
+    for (int e = 0; e < STAGE_PER_LANE; ++e) {
+        const int f = t + e * STAGE_THREADS;            // f < rows * k <= STAGE_ELEMS
+        const int r = min(f % rows, nr - 1), j = min(f / rows, k - 1);
+        v[e] = X[c0 + r + (int64_t)j * ldx];
+    }
+#pragma unroll
+    for (int e = 0; e < STAGE_PER_LANE; ++e) {
+        const int f = t + e * STAGE_THREADS;
         const int r = f % rows, j = f / rows;
-        if (r < nr) tile[r * stride + j] = X[c0 + r + (int64_t)j * ldx];
+        if (r < nr && j < k) tile[r * stride + j] = v[e];
     }
     __syncthreads();
-    for (int f = (int)threadIdx.x; f < tot; f += 256) {
-        const int r = f / k, j = f % k;
-        Xr[c0 * k + f] = tile[r * stride + j];
+#pragma unroll
+    for (int e = 0; e < STAGE_PER_LANE; ++e) {
+        const int f = min(t + e * STAGE_THREADS, tot - 1);
+        v[e] = tile[(f / k) * stride + f % k];
+    }
+#pragma unroll
+    for (int e = 0; e < STAGE_PER_LANE; ++e) {
+        const int f = t + e * STAGE_THREADS;
+        if (f < tot) Xr[c0 * k + f] = v[e];
     }
 }
 
@@ -569,11 +590,19 @@ static MmPlan plan_mm_jds(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int
     return P;
 }
 
+// The row-major block the interleaved kernels read: X itself for k = 1,
+// otherwise Xr in the workspace, filled here.
 template <typename T>
-static spmv_status stage(int64_t n, int32_t k, const void *X, int64_t ldx, void *Xr, hipStream_t s)
+static spmv_status stage(int64_t n, int32_t k, const void *X, int64_t ldx, void *ws, const void **Xr, hipStream_t s)
 {
-    const int64_t rows = STAGE_ELEMS / k;              // k <= MM_MAX_K2 = 64
-    stage_rowmajor_kernel<T><<<(unsigned)ceil_div(n, rows), 256, 0, s>>>(n, k, (const T *)X, ldx, (T *)Xr);
+    if (k == 1) {
+        *Xr = X;
+        return SPMV_OK;
+    }
+    *Xr = ws;
+    if (n == 0) return SPMV_OK;
+    const int64_t rows = STAGE_ELEMS / k;              // 2 <= k <= MM_MAX_K2 = 64
+    stage_rowmajor_kernel<T><<<(unsigned)ceil_div(n, rows), STAGE_THREADS, 0, s>>>(n, k, (const T *)X, ldx, (T *)ws);
     SPMV_CHECK_LAUNCH("spmm staging");
     return SPMV_OK;
 }
@@ -646,15 +675,14 @@ spmv_status spmm_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
                                  beta, plan, n_blocks, s);
     SPMV_REQUIRE(ws_bytes >= spmm_workspace_size(n_cols, k, vec_dt), "spmm_crs: workspace too small");
     if (n_blocks == 0) return SPMV_OK;
-    if (n_cols > 0) {
-        spmv_status st = vec_dt == SPMV_F64 ? stage<double>(n_cols, k, X, ldx, ws, s)
-                                            : stage<float>(n_cols, k, X, ldx, ws, s);
-        if (st != SPMV_OK) return st;
-    }
+    const void *Xr = nullptr;
+    spmv_status st = vec_dt == SPMV_F64 ? stage<double>(n_cols, k, X, ldx, ws, &Xr, s)
+                                        : stage<float>(n_cols, k, X, ldx, ws, &Xr, s);
+    if (st != SPMV_OK) return st;
     const int K2v = k2_for(k);
 #define CRS_IL(VDT, VT, XDT, XT)                                                                              \
     if (val_dt == VDT && vec_dt == XDT) {                                                                     \
-        K2_SWITCH(K2v, (launch_crs_il<K2, VT, XT>(row_ptr, col_idx, val, ws, k, Y, ldy, plan, n_blocks,        \
+        K2_SWITCH(K2v, (launch_crs_il<K2, VT, XT>(row_ptr, col_idx, val, Xr, k, Y, ldy, plan, n_blocks,        \
                                                   block_nnz, alpha, beta, s)));                               \
         SPMV_CHECK_LAUNCH("spmm_crs");                                                                        \
         return SPMV_OK;                                                                                       \
@@ -689,13 +717,15 @@ spmv_status spmm_jds(int32_t n, int32_t n_cols, const int32_t *perm, const int32
                                  beta, flags, s);
     SPMV_REQUIRE(h_jd_ptr, "spmm_jds: the interleaved path needs h_jd_ptr");
     SPMV_REQUIRE(ws_bytes >= spmm_workspace_size(n_cols, k, vec_dt), "spmm_jds: workspace too small");
-    spmv_status st = vec_dt == SPMV_F64 ? stage<double>(n_cols, k, X, ldx, ws, s) : stage<float>(n_cols, k, X, ldx, ws, s);
+    const void *Xr = nullptr;
+    spmv_status st = vec_dt == SPMV_F64 ? stage<double>(n_cols, k, X, ldx, ws, &Xr, s)
+                                        : stage<float>(n_cols, k, X, ldx, ws, &Xr, s);
     if (st != SPMV_OK) return st;
     const int K2v = k2_for(k);
     const int sym = (flags & SPMV_SYMPERM) ? 1 : 0;
 #define JDS_IL(VDT, VT, XDT, XT)                                                                                 \
     if (val_dt == VDT && vec_dt == XDT) {                                                                        \
-        K2_SWITCH(K2v, (launch_jds_il<K2, VT, XT>(n, h_jd_ptr, ndiag, jd_ptr, perm, sym, jd_col, jd_val, ws, k, Y, \
+        K2_SWITCH(K2v, (launch_jds_il<K2, VT, XT>(n, h_jd_ptr, ndiag, jd_ptr, perm, sym, jd_col, jd_val, Xr, k, Y, \
                                                   ldy, alpha, beta, s)));                                        \
         SPMV_CHECK_LAUNCH("spmm_jds");                                                                           \
         return SPMV_OK;                                                                                          \
