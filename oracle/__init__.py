@@ -51,6 +51,8 @@ _SIGS = {
     "orc_spmv_nujds": (None, [_i32, _i32p, _i32p, _i32, _i32p, _f64p, _f64p, _f64p, _f64, _f64, _int, _i32]),
     "orc_spmv_nbjds": (None, [_i32, _i32p, _i32p, _i32, _i32p, _f64p, _f64p, _f64p, _f64, _f64, _int, _i32]),
     "orc_jds_blocked_from_jds": (_i64, [_i32, _i32p, _i32, _i32p, _f64p, _i32, _int, _i64p, _i32p, _i32p, _f64p]),
+    "orc_jds_blocked_windowed": (_i64, [_i32, _i32p, _i32p, _f64p, _i32, _i32, _i32p, _i64p, _i32p, C.c_void_p,
+                                        C.c_void_p]),
     "orc_spmv_jds_blocked": (None, [_i32, _i32p, _i32, _i32, _i64p, _i32p, _i32p, _f64p, _f64p, _f64p, _f64, _f64, _int]),
     "orc_round_bf16": (None, [_f64p, _u16p, _i64]),
     "orc_csr_transpose": (None, [_i32, _i32, _i32p, _i32p, _i32p, _i32p, _i64p]),
@@ -250,6 +252,26 @@ def blocked_from_jds(J: JDS, C: int, sojds=False) -> Blocked:
                                          bl_col, bl_val)
     assert got == total
     return Blocked(n, J.perm, C, slice_ptr, slice_nd[:ns], bl_col[:total], bl_val[:total], J.symperm)
+
+
+def blocked_windowed(A: CSR, C_: int, sigma: int) -> Blocked:
+    """RBJDS storage over rows sorted by decreasing length inside windows of
+    sigma consecutive rows (sigma a multiple of C_)."""
+    n = A.n_rows
+    ns = (n + C_ - 1) // C_
+    perm = np.zeros(max(n, 1), np.int32)
+    slice_ptr = np.zeros(ns + 1, np.int64)
+    slice_nd = np.zeros(max(ns, 1), np.int32)
+    total = lib().orc_jds_blocked_windowed(n, A.row_ptr, A.col, A.val, C_, sigma, perm, slice_ptr, slice_nd,
+                                           None, None)          # sizes only
+    if total < 0:
+        raise ValueError("sigma must be a positive multiple of C")
+    bl_col = np.zeros(max(total, 1), np.int32)
+    bl_val = np.zeros(max(total, 1), np.float64)
+    got = lib().orc_jds_blocked_windowed(n, A.row_ptr, A.col, A.val, C_, sigma, perm, slice_ptr, slice_nd,
+                                         bl_col.ctypes.data, bl_val.ctypes.data)
+    assert got == total
+    return Blocked(n, perm[:n], C_, slice_ptr, slice_nd[:ns], bl_col[:total], bl_val[:total], False)
 
 
 def spmv_blocked(B: Blocked, x, y=None, alpha=1.0, beta=0.0):

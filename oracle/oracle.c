@@ -337,6 +337,63 @@ i64 orc_jds_blocked_from_jds(i32 n, const i32 *jd_ptr, i32 ndiag, const i32 *jd_
     return total;
 }
 
+/* RBJDS storage over a windowed row order (paper Section 2 notes that a more
+ * elaborate initial ordering of the elements can pay off).  Reading: the rows
+ * are cut into windows of sigma consecutive original rows (sigma a multiple
+ * of C; the last window may be shorter), each window is sorted by decreasing
+ * row length with ties in ascending original index, and the windows follow
+ * one another; sigma >= n is the plain JDS order.  Blocks of C consecutive
+ * permuted rows then never span two windows, are stored diagonal by diagonal
+ * and padded to their first (longest) row exactly as in the RBJDS builder
+ * above (col = -1, value 0 in padded slots), entries of a row in CRS order.
+ *   perm[r] = original row of permuted row r
+ * slice_ptr / slice_nd / bl_col / bl_val as above.  Returns the padded total,
+ * or -1 if sigma is not a positive multiple of C. */
+i64 orc_jds_blocked_windowed(i32 n, const i32 *row_ptr, const i32 *col, const double *val, i32 C, i32 sigma,
+                             i32 *perm, i64 *slice_ptr, i32 *slice_nd, i32 *bl_col, double *bl_val)
+{
+    if (C <= 0 || sigma <= 0 || sigma % C != 0) return -1;
+    len_key *keys = (len_key *)malloc(sizeof(len_key) * (size_t)(n > 0 ? n : 1));
+    for (i32 w0 = 0; w0 < n; w0 += sigma) {
+        i32 w1 = w0 + sigma < n ? w0 + sigma : n;
+        for (i32 i = w0; i < w1; ++i) {
+            keys[i].len = row_ptr[i + 1] - row_ptr[i];
+            keys[i].row = i;
+        }
+        qsort(keys + w0, (size_t)(w1 - w0), sizeof(len_key), len_cmp);
+    }
+    for (i32 r = 0; r < n; ++r) perm[r] = keys[r].row;
+    i32 n_slices = (n + C - 1) / C;
+    i64 total = 0;
+    for (i32 s = 0; s < n_slices; ++s) {
+        slice_ptr[s] = total;
+        slice_nd[s] = keys[s * C].len;          /* the block's first row is its longest */
+        total += (i64)slice_nd[s] * C;
+    }
+    slice_ptr[n_slices] = total;
+    if (bl_col) {
+        for (i32 s = 0; s < n_slices; ++s) {
+            for (i32 rl = 0; rl < C; ++rl) {
+                i32 r = s * C + rl;
+                i32 len = r < n ? keys[r].len : 0;
+                for (i32 d = 0; d < slice_nd[s]; ++d) {
+                    i64 dst = slice_ptr[s] + (i64)d * C + rl;
+                    if (d < len) {
+                        i32 src = row_ptr[perm[r]] + d;
+                        bl_col[dst] = col[src];
+                        bl_val[dst] = val[src];
+                    } else {
+                        bl_col[dst] = -1;
+                        bl_val[dst] = 0.0;
+                    }
+                }
+            }
+        }
+    }
+    free(keys);
+    return total;
+}
+
 /* RBJDS kernel: block by block, diagonal by diagonal inside the block, so the
  * block's part of the result vector stays in cache (paper Section 2). */
 void orc_spmv_jds_blocked(i32 n, const i32 *perm, i32 C, i32 n_slices, const i64 *slice_ptr,

@@ -281,6 +281,46 @@ def test_sojds_keeps_rows_and_is_close():
     assert np.array_equal(B.bl_col[ks], J.jd_col[J.jd_ptr[:-1]])
 
 
+def test_windowed_blocked_layout_brute_force():
+    """Windowed RBJDS (rows sorted by decreasing length inside windows of sigma
+    rows): every window's order and every slot rebuilt in Python from the
+    definition; sigma >= n is the plain RBJDS of the JDS (pinned above); the
+    blocked product stays bit-identical to CRS (each row summed in CRS
+    order)."""
+    A, rng = rand_csr(900, n_rows=300, n_cols=200, density=0.05, long_rows=4, long_len=90, empty=0.15)
+    lens = A.row_lengths()
+    x = rng.uniform(-1, 1, A.n_cols)
+    for C, sigma in ((64, 64), (64, 128), (128, 128), (64, 320)):
+        B = oracle.blocked_windowed(A, C, sigma)
+        want_perm = []
+        for w0 in range(0, A.n_rows, sigma):
+            rows = range(w0, min(w0 + sigma, A.n_rows))
+            want_perm += sorted(rows, key=lambda i: (-lens[i], i))
+        assert B.perm.tolist() == want_perm
+        for sl in range(B.n_slices):
+            assert B.slice_nd[sl] == lens[want_perm[sl * C]]
+            assert B.slice_ptr[sl + 1] - B.slice_ptr[sl] == B.slice_nd[sl] * C
+            for rl in range(C):
+                r = sl * C + rl
+                row = want_perm[r] if r < A.n_rows else None
+                for d in range(B.slice_nd[sl]):
+                    k = B.slice_ptr[sl] + d * C + rl
+                    if row is not None and d < lens[row]:
+                        e = A.row_ptr[row] + d
+                        assert B.bl_col[k] == A.col[e] and B.bl_val[k] == A.val[e]
+                    else:
+                        assert B.bl_col[k] == -1 and B.bl_val[k] == 0.0
+        assert np.array_equal(oracle.spmv_blocked(B, x), oracle.spmv_crs(A, x))
+    # one window of all rows is the paper's RBJDS
+    for C in (64, 128):
+        Bw = oracle.blocked_windowed(A, C, ((A.n_rows + C - 1) // C) * C)
+        Bj = oracle.blocked_from_jds(oracle.jds_from_csr(A), C)
+        assert np.array_equal(Bw.perm, Bj.perm) and np.array_equal(Bw.slice_ptr, Bj.slice_ptr)
+        assert np.array_equal(Bw.bl_col, Bj.bl_col) and np.array_equal(Bw.bl_val, Bj.bl_val)
+    with pytest.raises(ValueError):
+        oracle.blocked_windowed(A, 64, 96)
+
+
 def test_sojds_hand_worked_block():
     """The SOJDS slot rule on a block worked out by hand (paper Section 2,
     SOJDS: entries of each row re-sorted so the x access across the rows of a
