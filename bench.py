@@ -342,7 +342,7 @@ def cold_times(torch, sp, dev, kernels, reps=20):
 
 
 KERNEL_SOURCES = {"crs": ("common.hpp", "crs.hip"), "jds": ("common.hpp", "jds.hip"),
-                  "blocked": ("common.hpp", "jds.hip")}
+                  "blocked": ("common.hpp", "jds.hip"), "dia": ("common.hpp", "dia.hip")}
 
 
 def kernel_sources(kernel):
@@ -421,11 +421,15 @@ def load_powerlaw(torch, sp, dev, tune_cache=""):
     RS = timed("split_rows_ms", lambda: sp.RowSplit(A))
     timed("row_split_jds_parts_ms", lambda: RS.jds_parts())
     timed("row_split_blocked_parts_ms", lambda: RS.blocked_parts(bC))
+    wS, wC, wU, wW = timed("autotune_windowed_ms", lambda: tuner.tune_windowed(A, xd, J.ndiag))
+    BW = timed("jds_blocked_windowed_from_csr_ms", lambda: sp.jds_blocked_windowed_from_csr(A, wC, wS))
+    timed("windowed_tile_plan_ms", lambda: sp.spmv_jds_blocked_tiles(BW, 32, 0, wW))
     host = (r, c, v, n, x)
     tune = {"crs_block_nnz": crs_bn, "jds_unroll": jds_u, "jds_max_iters": jds_mi, "jds_wg_waves": jds_w,
-            "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW}
-    return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, S=S, RS=RS, x=xd, n=n, nnz=A.nnz, setup=setup, gen_s=gen_s,
-                host=host, tune=tune)
+            "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW,
+            "windowed_sigma": wS, "windowed_C": wC, "windowed_unroll": wU, "windowed_wg_waves": wW}
+    return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, S=S, RS=RS, BW=BW, x=xd, n=n, nnz=A.nnz, setup=setup,
+                gen_s=gen_s, host=host, tune=tune)
 
 
 def powerlaw_kernels(sp, W, torch):
@@ -464,7 +468,12 @@ def powerlaw_kernels(sp, W, torch):
         ("blocked_rowsplit_f32val", lambda: sp.spmv_jds_blocked_row_split(RS32, x, y, C_=bC, rows_per_wave=bR,
                                                                             unroll=bU, wg_waves=bW)),
     ]
+    BW = W["BW"]
+    wU, wW = T["windowed_unroll"], T["windowed_wg_waves"]
+    ks += [("blocked_windowed_f64", lambda: sp.spmv_jds_blocked_tiled(BW, x, y, unroll=wU, max_iters=32,
+                                                                       wg_waves=wW))]
     bmin = {
+        "blocked_windowed_f64": bytes_blocked(nnz, n, n, BW.n_slices, 8, 8),
         "crs_f64": bytes_crs(nnz, n, n, 8, 8),
         "jds_f64": bytes_jds(nnz, n, n, J.ndiag, 8, 8),
         "blocked_f64": bytes_blocked(nnz, n, n, B.n_slices, 8, 8),
@@ -473,7 +482,7 @@ def powerlaw_kernels(sp, W, torch):
         "blocked_f32val": bytes_blocked(nnz, n, n, B.n_slices, 4, 8),
     }
     # the column- and row-split forms move the same algorithmic bytes as the unsplit ones
-    for k in list(bmin):
+    for k in [k for k in bmin if "windowed" not in k]:
         base, tag = k.split("_", 1)
         bmin[f"{base}_split_{tag}"] = bmin[k]
         bmin[f"{base}_rowsplit_{tag}"] = bmin[k]
@@ -1120,7 +1129,8 @@ def main():
     print("# power-law workload built", file=sys.stderr, flush=True)
     all_ks, bmin = powerlaw_kernels(sp, W, torch)
     # the step: the three FP64 products of the power-law workload
-    plain = [k for k in all_ks if "split" not in k[0]]
+    plain = [k for k in all_ks if "split" not in k[0] and "windowed" not in k[0]]
+    windowed = [k for k in all_ks if "windowed" in k[0]]
     ks = [k for k in plain if k[0].endswith("_f64")]
     mixed = [k for k in plain if not k[0].endswith("_f64")]
     split = [k for k in all_ks if "_split" in k[0]]
@@ -1131,6 +1141,7 @@ def main():
         mixed = []
         split = []
         rsplit = []
+        windowed = []
     med = {}
     ms_eager, per = time_loop(torch, ks, args.steps, args.warmup, med)
     # the step itself runs as one HIP graph of its products (no launch gaps
@@ -1182,6 +1193,14 @@ def main():
                                        speedup_vs_unsplit=round(unsplit[name.replace("_rowsplit", "")] / per_r[name],
                                                                 3))
                             for name, _ in rsplit}
+    if windowed:
+        _, per_w = time_loop(torch, windowed, max(10, args.steps // 2), 3)
+        out["windowed"] = {name: dict(entry(name, per_w[name]),
+                                      speedup_vs_blocked=round(per["blocked_f64"] / per_w[name], 3))
+                           for name, _ in windowed}
+        out["windowed"]["note"] = ("blocked JDS with rows sorted by length inside windows of "
+                                   f"{W['tune']['windowed_sigma']} rows (slices C={W['tune']['windowed_C']}), "
+                                   "launched from a tile plan that gives each XCD an eighth of the slices in order")
     W3 = None
     if not args.only and not args.no_c3:
         print("# mixed-precision block: symmetric-diagonals matrix", file=sys.stderr, flush=True)
@@ -1221,7 +1240,8 @@ def main():
     out["gather_bound"] = {
         "gathers_per_launch": nnz, "probe": rates,
         "kernels": {name: gather_entry(name, ms)
-                    for name, ms in dict(per, **(per_s if split else {}), **(per_r if rsplit else {})).items()
+                    for name, ms in dict(per, **(per_s if split else {}), **(per_r if rsplit else {}),
+                                         **(per_w if windowed else {})).items()
                     if name.endswith("_f64")}}
     print(json.dumps(out), flush=True)
     if args.suite:

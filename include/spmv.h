@@ -157,6 +157,50 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
                                       int32_t *bl_col, void *bl_val, int64_t bl_cap, int64_t *h_padded,
                                       int32_t *h_slice_nd, void *ws, size_t ws_bytes, void *stream);
 
+/* CRS -> blocked JDS over a windowed row order (the RBJDS storage of
+ * spmv_jds_blocked_from_jds; paper Section 2 leaves room for a more elaborate
+ * initial ordering of the elements).  The rows are cut into windows of sigma
+ * consecutive original rows (sigma a positive multiple of C); inside each
+ * window they are sorted by decreasing length (ties in ascending original
+ * index), and the windows follow one another, so perm is window-local and
+ * sigma >= n gives the plain JDS order.  Slices of C permuted rows never span
+ * two windows; each is stored diagonal by diagonal and padded to its first
+ * (longest) row (col = -1, value 0), entries of a row in CRS order.  Rows that
+ * are neighbours in the original order stay neighbours in time when the
+ * slices are processed in order, which keeps the x window of a banded part
+ * of the matrix in cache.
+ *   perm[n], slice_ptr[n_slices+1] (int64), slice_nd[n_slices],
+ *   n_slices = ceil(n / C); bl_col/bl_val hold the padded total.
+ * *h_padded = padded total; if bl_cap < padded returns SPMV_ERR_CAPACITY with
+ * *h_padded set and the arrays unwritten.  h_slice_nd (optional) receives a
+ * host copy of slice_nd.  dt: F64, F32, BF16 or I32 (moved bit for bit).
+ * ws: spmv_jds_blocked_windowed_workspace_size(n).  Synchronises. */
+size_t spmv_jds_blocked_windowed_workspace_size(int32_t n);
+spmv_status spmv_jds_blocked_windowed_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                                               const int32_t *col_idx, const void *val, spmv_dtype dt,
+                                               int32_t C, int32_t sigma, int32_t *perm, int64_t *slice_ptr,
+                                               int32_t *slice_nd, int32_t *bl_col, void *bl_val,
+                                               int64_t bl_cap, int64_t *h_padded, int32_t *h_slice_nd,
+                                               void *ws, size_t ws_bytes, void *stream);
+
+/* Tile plan for spmv_jds_blocked_tiled, built on the host from the slice
+ * depths of any blocked-JDS storage (slice depths need not decrease, as in
+ * the windowed order).  Every run of slices wanting the same split (R rows
+ * per wavefront, S wavefronts per row group; chosen from the slice depth as
+ * in spmv_jds_blocked, or R = rows_per_wave when that is non-zero) is covered
+ * by workgroups of (wg_waves / S) * R rows, one record of two int32 each
+ * (first row; R, S and row count packed).  The records are cut into 8
+ * contiguous ranges of about equal work: range k runs on XCD k.
+ *   tiles: 2 * n_tiles int32 (device), written when tiles_cap >= 2 * n_tiles,
+ *          otherwise SPMV_ERR_CAPACITY with *h_n_tiles set (two-call pattern)
+ *   h_plan[10]: the 9 range bounds and the wavefronts per workgroup, passed
+ *          unchanged to spmv_jds_blocked_tiled.
+ * Synchronises. */
+spmv_status spmv_jds_blocked_tiles(int32_t n, int32_t C, int32_t n_slices, const int32_t *h_slice_nd,
+                                   int32_t max_iters, int32_t rows_per_wave, int32_t wg_waves,
+                                   int32_t *tiles, int64_t tiles_cap, int64_t *h_n_tiles, int64_t *h_plan,
+                                   void *stream);
+
 /* Row-block plan for spmv_crs / spmm_crs: plan[0..n_blocks] are row
  * boundaries.  Consecutive rows are grouped while the group holds at most
  * block_nnz entries (0 = library default, 1024) and at most 256 rows, or at
@@ -230,6 +274,19 @@ spmv_status spmv_jds_blocked(int32_t n, const int32_t *perm, int32_t C, int32_t 
                              spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
                              double beta, int32_t rows_per_wave, int32_t unroll, int32_t max_iters,
                              int32_t wg_waves, unsigned flags, void *stream);
+
+/* The blocked-JDS product y = alpha*A x + beta*y (as spmv_jds_blocked, same
+ * arithmetic per row) launched from a tile plan (spmv_jds_blocked_tiles):
+ * every workgroup takes one record, and the workgroups on XCD k walk range k
+ * of the records in order.  For the windowed order this keeps each XCD on
+ * neighbouring rows of the original matrix.  h_plan is the plan's h_plan[10].
+ * Asynchronous; allocates nothing. */
+spmv_status spmv_jds_blocked_tiled(int32_t n, const int32_t *perm, int32_t C, int32_t n_slices,
+                                   const int64_t *slice_ptr, const int32_t *slice_nd, const int32_t *bl_col,
+                                   const void *bl_val, spmv_dtype val_dt, const void *x, void *y,
+                                   spmv_dtype vec_dt, double alpha, double beta, const int32_t *tiles,
+                                   int64_t n_tiles, const int64_t *h_plan, int32_t unroll, unsigned flags,
+                                   void *stream);
 
 /* Vector basis change: inverse == 0: out[r] = in[perm[r]] (to the permuted
  * basis); inverse != 0: out[perm[r]] = in[r].  dt F64 or F32. */

@@ -33,6 +33,7 @@ U_CANDIDATES = (2, 4, 8)
 MAX_ITERS_CANDIDATES = (0, 64, 128)  # 0: the library default
 W_CANDIDATES = (16, 8, 4)            # wavefronts per workgroup
 BLOCK_NNZ_CANDIDATES = (512, 1024, 2048)
+SIGMA_CANDIDATES = (16384, 65536, 262144)   # windowed order: rows per window
 
 
 def signature(n_rows: int, longest: int, nnz: int) -> str:
@@ -164,6 +165,31 @@ class Autotuner:
         self._record(sig, keys, best, timings)
         return best
 
+
+    def tune_windowed(self, A: S.CSR, x: torch.Tensor, longest: int, sigmas=SIGMA_CANDIDATES,
+                      Cs=(64, 128), Us=(4, 8), Ws=(8, 16)) -> Tuple[int, int, int, int]:
+        """Best (sigma, C, U, W) for one large matrix in windowed blocked-JDS
+        storage launched from its tile plan (max_iters 32)."""
+        sig = "windowed:" + signature(A.n_rows, longest, A.nnz)
+        keys = ("sigma", "C", "U", "W")
+        hit = self.lookup(sig, keys)
+        if hit is not None:
+            return hit
+        timings = {}
+        y = torch.empty(A.n_rows, dtype=x.dtype, device=x.device)
+        for sg in sigmas:
+            for C in Cs:
+                B = S.jds_blocked_windowed_from_csr(A, C, sg)
+                for U in Us:
+                    for W in Ws:
+                        timings[(sg, C, U, W)] = _time(lambda: S.spmv_jds_blocked_tiled(B, x, y, unroll=U,
+                                                                                        max_iters=32, wg_waves=W))
+                del B
+        best = min(timings, key=timings.get)
+        self.log.append({"signature": sig, "timings_ms": {f"s{a}_C{c}_U{u}_W{w}": round(t, 5)
+                                                          for (a, c, u, w), t in timings.items()}})
+        self._record(sig, keys, best, timings)
+        return best
 
     def tune_jds(self, J: S.JDS, x: torch.Tensor, mis=MAX_ITERS_CANDIDATES) -> Tuple[int, int, int]:
         """Best (U, max_iters, W) for one large matrix in JDS storage."""

@@ -519,6 +519,65 @@ __global__ void blocked_fill_kernel(const int32_t *__restrict__ jp, int32_t ndia
     }
 }
 
+// Windowed RBJDS (rows sorted by length inside windows of sigma rows):
+// window of the row each permuted position holds, the sort key of the
+// second, stable pass.
+__global__ void window_key_kernel(const int32_t *__restrict__ perm, int32_t n, int32_t sigma,
+                                  uint32_t *__restrict__ key)
+{
+    GRID_LOOP(r, (int64_t)n) key[r] = (uint32_t)(perm[r] / sigma);
+}
+
+// slice s's depth = length of its first row (the longest: slices never span
+// two windows and rows are sorted inside a window)
+__global__ void window_slice_nd_kernel(const int32_t *__restrict__ rp, const int32_t *__restrict__ perm,
+                                       int32_t C, int32_t n_slices, int32_t *__restrict__ nd,
+                                       int64_t *__restrict__ sz)
+{
+    GRID_LOOP(s, (int64_t)n_slices)
+    {
+        const int32_t row = perm[s * (int64_t)C];
+        const int32_t l = rp[row + 1] - rp[row];
+        nd[s] = l;
+        sz[s] = (int64_t)l * C;
+    }
+}
+
+// slot k of the padded storage: entry d of permuted row r, taken from CRS in
+// its row order, or padding (col = -1, value 0)
+template <typename T>
+__global__ void window_fill_kernel(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                   const T *__restrict__ val, const int32_t *__restrict__ perm, int32_t n, int32_t C,
+                                   const int64_t *__restrict__ slice_ptr, int32_t n_slices, int64_t total,
+                                   int32_t *__restrict__ bl_col, T *__restrict__ bl_val)
+{
+    GRID_LOOP(k, total)
+    {
+        int32_t lo = 0, hi = n_slices - 1;
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) >> 1;
+            if (slice_ptr[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t local = k - slice_ptr[lo];
+        const int32_t d = (int32_t)(local / C);
+        const int32_t rl = (int32_t)(local - (int64_t)d * C);
+        const int64_t r = (int64_t)lo * C + rl;
+        int32_t e = -1;
+        if (r < n) {
+            const int32_t row = perm[r];
+            if (d < rp[row + 1] - rp[row]) e = rp[row] + d;
+        }
+        if (e >= 0) {
+            bl_col[k] = col[e];
+            bl_val[k] = val[e];
+        } else {
+            bl_col[k] = -1;
+            bl_val[k] = T{};
+        }
+    }
+}
+
 // SOJDS: one thread per slice re-assigns each row's entries to diagonal slots
 // (first row keeps CRS order; later rows take, slot by slot, the unused entry
 // whose column is nearest to the previous row's column in that slot plus one,
@@ -1145,6 +1204,18 @@ spmv_status spmv_jds_to_csr(int32_t n, const int32_t *perm, const int32_t *jd_pt
     return SPMV_OK;
 }
 
+size_t spmv_jds_blocked_windowed_workspace_size(int32_t n)
+{
+    size_t m = (size_t)(n > 0 ? n : 1);
+    size_t b = 256;                                              // longest row
+    b += align_up(sizeof(int32_t) * m, 256);                     // lengths
+    b += align_up(sizeof(uint32_t) * m, 256);                    // sort keys
+    b += radix_ws_bytes((int64_t)m);
+    b += align_up(sizeof(int64_t) * m, 256);                     // slice sizes (at most n slices)
+    b += align_up(sizeof(int64_t) * scan_ws_elems((int64_t)m), 256);
+    return b + 1024;
+}
+
 size_t spmv_jds_blocked_workspace_size(int32_t n, int32_t ndiag, int32_t C, unsigned flags)
 {
     if (C <= 0) return 0;
@@ -1210,6 +1281,79 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
     BLK_CASE(SPMV_I32, uint32_t)
     BLK_CASE(SPMV_BF16, uint16_t)
 #undef BLK_CASE
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+spmv_status spmv_jds_blocked_windowed_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                               const void *val, spmv_dtype dt, int32_t C, int32_t sigma,
+                                               int32_t *perm, int64_t *slice_ptr, int32_t *slice_nd,
+                                               int32_t *bl_col, void *bl_val, int64_t bl_cap, int64_t *h_padded,
+                                               int32_t *h_slice_nd, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && nnz >= 0, "spmv_jds_blocked_windowed_from_csr: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_jds_blocked_windowed_from_csr: nnz >= 2^31");
+    SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_windowed_from_csr: C must be a positive multiple of 64");
+    SPMV_REQUIRE(sigma > 0 && sigma % C == 0, "spmv_jds_blocked_windowed_from_csr: sigma must be a positive multiple of C");
+    SPMV_REQUIRE(valid_payload_dtype(dt), "spmv_jds_blocked_windowed_from_csr: bad dtype");
+    SPMV_REQUIRE(row_ptr && slice_ptr && h_padded, "spmv_jds_blocked_windowed_from_csr: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_jds_blocked_windowed_workspace_size(n),
+                 "spmv_jds_blocked_windowed_from_csr: workspace too small");
+    hipStream_t s = as_stream(stream);
+    const int32_t ns = (int32_t)ceil_div(n, C);
+    if (ns == 0) {
+        SPMV_HIP(hipMemsetAsync(slice_ptr, 0, sizeof(int64_t), s));
+        SPMV_HIP(hipStreamSynchronize(s));
+        *h_padded = 0;
+        return SPMV_OK;
+    }
+    SPMV_REQUIRE(perm && slice_nd, "spmv_jds_blocked_windowed_from_csr: null perm or slice_nd");
+    const size_t m = (size_t)n;
+    WsCarver wc(ws, ws_bytes);
+    int32_t *maxlen = wc.take<int32_t>(1);
+    int32_t *len = wc.take<int32_t>(m);
+    uint32_t *keys = wc.take<uint32_t>(m);
+    const size_t rws_bytes = radix_ws_bytes((int64_t)m);
+    void *rws = wc.take<char>(rws_bytes);
+    int64_t *sz = wc.take<int64_t>(m);
+    int64_t *sws = wc.take<int64_t>(scan_ws_elems((int64_t)m));
+    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_jds_blocked_windowed_from_csr: workspace too small");
+    int32_t ndiag = 0;
+    SPMV_HIP(hipMemsetAsync(maxlen, 0, sizeof(int32_t), s));
+    row_len_kernel<<<grid_for(n), 256, 0, s>>>(row_ptr, n, len, maxlen);
+    SPMV_CHECK_LAUNCH("windowed lengths");
+    if (read_flag(maxlen, &ndiag, s) != SPMV_OK) return SPMV_ERR_HIP;
+    // rows by decreasing length (stable), then by window (stable): window-major,
+    // longest first inside a window, ties in original order
+    desc_key_kernel<<<grid_for(n), 256, 0, s>>>(len, n, ndiag, keys);
+    iota_kernel<<<grid_for(n), 256, 0, s>>>(perm, n);
+    SPMV_CHECK_LAUNCH("windowed keys");
+    spmv_status st = radix_sort_pairs(keys, perm, n, bits_for(ndiag), rws, rws_bytes, s);
+    if (st != SPMV_OK) return st;
+    window_key_kernel<<<grid_for(n), 256, 0, s>>>(perm, n, sigma, keys);
+    SPMV_CHECK_LAUNCH("windowed window keys");
+    st = radix_sort_pairs(keys, perm, n, bits_for((int64_t)(n - 1) / sigma), rws, rws_bytes, s);
+    if (st != SPMV_OK) return st;
+    window_slice_nd_kernel<<<grid_for(ns), 256, 0, s>>>(row_ptr, perm, C, ns, slice_nd, sz);
+    SPMV_CHECK_LAUNCH("windowed slice sizes");
+    st = exclusive_scan<int64_t, int64_t>(sz, ns, slice_ptr, sws, s);
+    if (st != SPMV_OK) return st;
+    int64_t total = 0;
+    SPMV_HIP(hipMemcpyAsync(&total, slice_ptr + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (h_slice_nd) SPMV_HIP(hipMemcpyAsync(h_slice_nd, slice_nd, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    *h_padded = total;
+    if (bl_cap < total) return fail(SPMV_ERR_CAPACITY, "spmv_jds_blocked_windowed_from_csr: capacity < padded size");
+    if (total == 0) return SPMV_OK;
+    SPMV_REQUIRE(col_idx && val && bl_col && bl_val, "spmv_jds_blocked_windowed_from_csr: null arrays");
+#define WFILL_CASE(T)                                                                                              \
+    window_fill_kernel<T><<<grid_for(total), 256, 0, s>>>(row_ptr, col_idx, (const T *)val, perm, n, C, slice_ptr, \
+                                                          ns, total, bl_col, (T *)bl_val)
+    if (dt == SPMV_F64) WFILL_CASE(uint64_t);
+    else if (dt == SPMV_F32 || dt == SPMV_I32) WFILL_CASE(uint32_t);
+    else WFILL_CASE(uint16_t);
+#undef WFILL_CASE
+    SPMV_CHECK_LAUNCH("windowed fill");
     SPMV_HIP(hipStreamSynchronize(s));
     return SPMV_OK;
 }

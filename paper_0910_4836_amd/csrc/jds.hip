@@ -264,11 +264,9 @@ __device__ __forceinline__ WaveTask wave_task(const JdsArgs &a, const JdsPlan &P
 // WIDE_ALL: accumulate every row in FP64 (the column-split parts, whose rows
 // are pieces of rows whose full length the workgroup does not see).
 template <int FMT, int U, typename VT, typename XT, typename OT, bool WIDE_ALL = false>
-__device__ __forceinline__ void jds_body(const JdsArgs &a, const JdsPlan &P, int64_t wg,
-                                         double (*part)[WAVE])
+__device__ __forceinline__ void jds_body_task(const JdsArgs &a, const WaveTask &t, double (*part)[WAVE])
 {
     constexpr bool F64 = IsF64<VT>::value || WIDE_ALL;
-    const WaveTask t = wave_task<FMT>(a, P, !F64, wg);
     const bool valid = t.valid, row_ok = t.row_ok, wide = t.wide, bounded = t.bounded;
     const int32_t row0 = t.row0, r = t.r, dA = t.dA, dB = t.dB;
     const int w = t.w, rl = t.rl, kk = t.kk, G = t.G, S = t.S, p = t.p;
@@ -302,6 +300,73 @@ __device__ __forceinline__ void jds_body(const JdsArgs &a, const JdsPlan &P, int
         const int32_t yi = a.symperm ? r : a.perm[r];
         write_y((OT *)a.y, yi, td, a.alpha, a.beta);
     }
+}
+
+template <int FMT, int U, typename VT, typename XT, typename OT, bool WIDE_ALL = false>
+__device__ __forceinline__ void jds_body(const JdsArgs &a, const JdsPlan &P, int64_t wg,
+                                         double (*part)[WAVE])
+{
+    constexpr bool F64 = IsF64<VT>::value || WIDE_ALL;
+    jds_body_task<FMT, U, VT, XT, OT, WIDE_ALL>(a, wave_task<FMT>(a, P, !F64, wg), part);
+}
+
+// Tile plans (blocked storage in any row order, e.g. sorted inside windows
+// of rows): workgroup record (row0, code) covers permuted rows [row0, row0 +
+// nrows) with R = 2^rlog rows per wave group and S = 2^slog waves per group,
+// code = rlog | slog << 4 | nrows << 8.  The records are cut into 8
+// contiguous ranges of about equal work, range k for the workgroups on XCD k
+// (workgroup b runs on XCD b % 8), so each XCD walks its rows in order.
+struct TileBounds {
+    int64_t b[9];
+};
+
+__device__ __forceinline__ WaveTask tile_task(const JdsArgs &a, int32_t row0, int32_t nrows, int rlog, int slog,
+                                              bool reduced_values)
+{
+    WaveTask t;
+    t.w = (int)threadIdx.x / WAVE;
+    const int lane = lane_id();
+    t.rlog = rlog;
+    t.S = 1 << slog;
+    const int R = 1 << rlog;
+    t.G = WAVE >> rlog;
+    const int64_t row_end = min((int64_t)row0 + nrows, (int64_t)a.n);
+    const int64_t grp = t.w >> slog;
+    t.p = t.w & (t.S - 1);
+    const int64_t row0l = (int64_t)row0 + grp * R;
+    t.valid = row0l < row_end;
+    t.row0 = t.valid ? (int32_t)row0l : row0;
+    t.rl = lane & (R - 1);
+    t.kk = lane >> rlog;
+    t.r = t.row0 + t.rl;
+    t.row_ok = t.valid && t.r < row_end;
+    const int32_t Lmax = t.valid ? a.slice_nd[t.row0 / a.C] : 0;
+    t.wide = reduced_values && Lmax > SPMV_WIDE_ROW_NNZ;
+    t.dA = 0;
+    t.dB = Lmax;
+    if (t.S > 1) {
+        const int64_t SG = (int64_t)t.S * t.G;
+        const int32_t per = (int32_t)(((int64_t)Lmax + SG - 1) / SG * t.G);
+        t.dA = t.p * per;
+        t.dB = t.dA + per < Lmax ? t.dA + per : Lmax;
+        if (t.dA > t.dB) t.dA = t.dB;
+    }
+    t.bounded = true;
+    return t;
+}
+
+template <int U, typename VT, typename XT>
+__global__ __launch_bounds__(JDS_THREADS) void jds_tiles_kernel(JdsArgs a, const int32_t *__restrict__ tiles,
+                                                                TileBounds xb)
+{
+    __shared__ double part[JDS_WAVES][WAVE];
+    constexpr bool F64 = IsF64<VT>::value;
+    const int x = (int)(blockIdx.x % 8);
+    const int64_t idx = xb.b[x] + blockIdx.x / 8;
+    if (idx >= xb.b[x + 1]) return;
+    const int32_t row0 = tiles[2 * idx], code = tiles[2 * idx + 1];
+    jds_body_task<FMT_BLOCKED, U, VT, XT, XT>(a, tile_task(a, row0, code >> 8, code & 15, (code >> 4) & 15, !F64),
+                                              part);
 }
 
 template <int FMT, int U, typename VT, typename XT>
@@ -552,6 +617,55 @@ static JdsPlan plan_blocked(int32_t n, int32_t C, const int32_t *h_slice_nd, int
     return build_plan(n, max_iters, forced_rlog, waves, chunk_len);
 }
 
+// Tile plan of blocked storage whose slice depths need not decrease: each run
+// of slices that wants the same (R, S) is covered by workgroups of
+// (waves / S) * R rows; the record list is cut into 8 ranges of about equal
+// cost (padded slots covered plus a fixed cost per wavefront).
+static void plan_tiles(int32_t n, int32_t C, const int32_t *h_slice_nd, int32_t max_iters, int forced_rlog, int waves,
+                       std::vector<int32_t> &rec, int64_t bounds[9])
+{
+    rec.clear();
+    std::vector<double> cost;
+    const int32_t ns = (int32_t)ceil_div(n, C);
+    auto split_of = [&](int32_t sl, int &rlog, int &slog) {
+        const int64_t L = h_slice_nd[sl];
+        int W = 1;
+        while (W < 128 && (int64_t)W * max_iters < L) W <<= 1;
+        split_for(W, forced_rlog, waves, rlog, slog);
+    };
+    int32_t sl = 0;
+    while (sl < ns) {
+        int rlog, slog;
+        split_of(sl, rlog, slog);
+        int32_t e = sl + 1;
+        for (; e < ns; ++e) {
+            int r2, s2;
+            split_of(e, r2, s2);
+            if (r2 != rlog || s2 != slog) break;
+        }
+        const int64_t a0 = (int64_t)sl * C, a1 = std::min<int64_t>((int64_t)e * C, n);
+        const int64_t rpw = (int64_t)(waves >> slog) << rlog;
+        for (int64_t r = a0; r < a1; r += rpw) {
+            const int64_t nr = std::min<int64_t>(rpw, a1 - r);
+            rec.push_back((int32_t)r);
+            rec.push_back(rlog | (slog << 4) | (int32_t)(nr << 8));
+            cost.push_back((double)nr * h_slice_nd[r / C] + 64.0 * waves);
+        }
+        sl = e;
+    }
+    const int64_t nt = (int64_t)cost.size();
+    double total = 0;
+    for (double c : cost) total += c;
+    bounds[0] = 0;
+    double acc = 0;
+    int64_t i = 0;
+    for (int k = 1; k < 8; ++k) {
+        while (i < nt && acc + cost[i] / 2 < total * k / 8) acc += cost[i++];
+        bounds[k] = i;
+    }
+    bounds[8] = nt;
+}
+
 template <int FMT, typename VT, typename XT>
 static spmv_status launch_jds_t(const JdsArgs &a, const JdsPlan &P, int unroll, hipStream_t s)
 {
@@ -706,6 +820,102 @@ spmv_status spmv_jds_blocked(int32_t n, const int32_t *perm, int32_t C, int32_t 
     JdsPlan P = plan_blocked(n, C, h_slice_nd, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced,
                              waves_or_default(wg_waves));
     return launch_jds<FMT_BLOCKED>(a, P, unroll ? unroll : 4, val_dt, vec_dt, as_stream(stream));
+}
+
+spmv_status spmv_jds_blocked_tiles(int32_t n, int32_t C, int32_t n_slices, const int32_t *h_slice_nd,
+                                   int32_t max_iters, int32_t rows_per_wave, int32_t wg_waves, int32_t *tiles,
+                                   int64_t tiles_cap, int64_t *h_n_tiles, int64_t *h_plan, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_jds_blocked_tiles: n < 0");
+    SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_tiles: C must be a positive multiple of 64");
+    SPMV_REQUIRE(n_slices == (int32_t)ceil_div(n, C), "spmv_jds_blocked_tiles: n_slices != ceil(n / C)");
+    SPMV_REQUIRE(waves_ok(wg_waves), "spmv_jds_blocked_tiles: wg_waves must be 0, 4, 8 or 16");
+    SPMV_REQUIRE(max_iters >= 0, "spmv_jds_blocked_tiles: max_iters < 0");
+    SPMV_REQUIRE(rows_per_wave == 0 || rows_per_wave == 8 || rows_per_wave == 16 || rows_per_wave == 32 ||
+                     rows_per_wave == 64,
+                 "spmv_jds_blocked_tiles: rows_per_wave must be 0, 8, 16, 32 or 64");
+    SPMV_REQUIRE(h_n_tiles && h_plan && (n_slices == 0 || h_slice_nd), "spmv_jds_blocked_tiles: null pointer");
+    int forced = -1;
+    if (rows_per_wave) {
+        forced = 0;
+        while ((1 << forced) < rows_per_wave) ++forced;
+    }
+    const int waves = waves_or_default(wg_waves);
+    std::vector<int32_t> rec;
+    int64_t bounds[9];
+    plan_tiles(n, C, h_slice_nd, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced, waves, rec, bounds);
+    const int64_t nt = (int64_t)rec.size() / 2;
+    *h_n_tiles = nt;
+    for (int k = 0; k < 9; ++k) h_plan[k] = bounds[k];
+    h_plan[9] = waves;
+    if (!tiles || tiles_cap < 2 * nt) return fail(SPMV_ERR_CAPACITY, "spmv_jds_blocked_tiles: tiles capacity < 2 * n_tiles");
+    if (nt == 0) return SPMV_OK;
+    hipStream_t s = as_stream(stream);
+    SPMV_HIP(hipMemcpyAsync(tiles, rec.data(), sizeof(int32_t) * rec.size(), hipMemcpyHostToDevice, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+spmv_status spmv_jds_blocked_tiled(int32_t n, const int32_t *perm, int32_t C, int32_t n_slices,
+                                   const int64_t *slice_ptr, const int32_t *slice_nd, const int32_t *bl_col,
+                                   const void *bl_val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
+                                   double alpha, double beta, const int32_t *tiles, int64_t n_tiles,
+                                   const int64_t *h_plan, int32_t unroll, unsigned flags, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && n_tiles >= 0, "spmv_jds_blocked_tiled: negative size");
+    SPMV_REQUIRE(C > 0 && C % 64 == 0, "spmv_jds_blocked_tiled: C must be a positive multiple of 64");
+    SPMV_REQUIRE(n_slices == (int32_t)ceil_div(n, C), "spmv_jds_blocked_tiled: n_slices != ceil(n / C)");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_blocked_tiled: bad dtype");
+    SPMV_REQUIRE(unroll_ok(unroll), "spmv_jds_blocked_tiled: unroll must be 0, 2, 4 or 8");
+    SPMV_REQUIRE((flags & ~(SPMV_SYMPERM | SPMV_SOJDS)) == 0, "spmv_jds_blocked_tiled: unknown flag");
+    SPMV_REQUIRE(h_plan, "spmv_jds_blocked_tiled: null h_plan");
+    TileBounds xb;
+    for (int k = 0; k < 9; ++k) xb.b[k] = h_plan[k];
+    SPMV_REQUIRE(xb.b[0] == 0 && xb.b[8] == n_tiles, "spmv_jds_blocked_tiled: plan bounds do not cover n_tiles");
+    int64_t widest = 0;
+    for (int k = 0; k < 8; ++k) {
+        SPMV_REQUIRE(xb.b[k + 1] >= xb.b[k], "spmv_jds_blocked_tiled: plan bounds decrease");
+        widest = std::max<int64_t>(widest, xb.b[k + 1] - xb.b[k]);
+    }
+    const int64_t waves = h_plan[9];
+    SPMV_REQUIRE(waves_ok((int32_t)waves) && waves != 0, "spmv_jds_blocked_tiled: bad wavefront count in h_plan");
+    if (n == 0 || n_tiles == 0) return SPMV_OK;
+    // bl_col, bl_val and x are read only where a slice has diagonals (they may
+    // be null for storage without entries)
+    SPMV_REQUIRE(y && slice_ptr && slice_nd && tiles, "spmv_jds_blocked_tiled: null pointer");
+    SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmv_jds_blocked_tiled: null perm");
+    JdsArgs a{};
+    a.n = n;
+    a.perm = perm;
+    a.C = C;
+    a.slice_ptr = slice_ptr;
+    a.slice_nd = slice_nd;
+    a.col = bl_col;
+    a.val = bl_val;
+    a.x = x;
+    a.y = y;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
+    hipStream_t s = as_stream(stream);
+    const unsigned grid = (unsigned)(8 * widest), threads = (unsigned)(waves * WAVE);
+    const int u = unroll ? unroll : 4;
+#define JTILE_CASE(VDT, VT, XDT, XT)                                                                         \
+    if (val_dt == VDT && vec_dt == XDT) {                                                                    \
+        if (u == 2) jds_tiles_kernel<2, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);                   \
+        else if (u == 8) jds_tiles_kernel<8, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);              \
+        else jds_tiles_kernel<4, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);                          \
+    } else
+    JTILE_CASE(SPMV_F64, double, SPMV_F64, double)
+    JTILE_CASE(SPMV_F32, float, SPMV_F64, double)
+    JTILE_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    JTILE_CASE(SPMV_F32, float, SPMV_F32, float)
+    JTILE_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    JTILE_CASE(SPMV_F64, double, SPMV_F32, float)
+    return fail(SPMV_ERR_UNSUPPORTED, "spmv_jds_blocked_tiled: dtype combination");
+#undef JTILE_CASE
+    SPMV_CHECK_LAUNCH("spmv_jds_blocked_tiled");
+    return SPMV_OK;
 }
 
 }  // extern "C"

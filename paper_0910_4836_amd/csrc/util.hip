@@ -210,28 +210,34 @@ static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // y_i = alpha * (sum of row i's slots, in slot order) + beta * y_i
 template <typename T>
-__global__ void combine_kernel(int32_t n, const int32_t *__restrict__ slot_ptr, const double *__restrict__ slots,
-                               T *__restrict__ y, double alpha, double beta)
+__global__ __launch_bounds__(256) void combine_kernel(int32_t n, const int32_t *__restrict__ slot_ptr,
+                                                     const double *__restrict__ slots, T *__restrict__ y,
+                                                     double alpha, double beta)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        const int32_t s0 = slot_ptr[i], s1 = slot_ptr[i + 1];
-        double s = 0.0;
-        for (int32_t q = s0; q < s1; ++q) s += __builtin_nontemporal_load(slots + q);
-        write_y(y, i, s, alpha, beta);
-    }
+    // one row per lane; a row has at most SPLIT_PARTS slots, all loaded at
+    // once (lanes past their row's last slot load it again and drop the
+    // value), then added in slot order
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t s0 = slot_ptr[i], s1 = slot_ptr[i + 1];
+    double v[SPLIT_PARTS];
+#pragma unroll
+    for (int q = 0; q < SPLIT_PARTS; ++q) v[q] = s1 > s0 ? __builtin_nontemporal_load(slots + min(s0 + q, s1 - 1)) : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < SPLIT_PARTS; ++q) s = s0 + q < s1 ? s + v[q] : s;
+    write_y(y, i, s, alpha, beta);
 }
 
 spmv_status launch_combine(int32_t n, const int32_t *slot_ptr, const double *slots, void *y, spmv_dtype vec_dt,
                            double alpha, double beta, hipStream_t s)
 {
     if (n == 0) return SPMV_OK;
-    const int grid = stream_grid(n, 4);
+    const int64_t grid = ceil_div(n, 256);
     if (vec_dt == SPMV_F64)
-        combine_kernel<double><<<grid, 256, 0, s>>>(n, slot_ptr, slots, (double *)y, alpha, beta);
+        combine_kernel<double><<<(unsigned)grid, 256, 0, s>>>(n, slot_ptr, slots, (double *)y, alpha, beta);
     else
-        combine_kernel<float><<<grid, 256, 0, s>>>(n, slot_ptr, slots, (float *)y, alpha, beta);
+        combine_kernel<float><<<(unsigned)grid, 256, 0, s>>>(n, slot_ptr, slots, (float *)y, alpha, beta);
     SPMV_CHECK_LAUNCH("split combine");
     return SPMV_OK;
 }

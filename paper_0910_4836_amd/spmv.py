@@ -145,6 +145,8 @@ class Blocked:
     padded: int
     symperm: bool = False
     sojds: bool = False
+    sigma: int = 0                   # > 0: rows sorted by length inside windows of sigma rows
+    tile_plans: dict = field(default_factory=dict, repr=False)   # (max_iters, rows_per_wave, wg_waves) -> plan
 
     @property
     def n_slices(self) -> int:
@@ -152,7 +154,7 @@ class Blocked:
 
     def with_values(self, val: torch.Tensor) -> "Blocked":
         return Blocked(self.n, self.n_cols, self.C, self.perm, self.slice_ptr, self.slice_nd, self.h_slice_nd,
-                       self.bl_col, val, self.padded, self.symperm, self.sojds)
+                       self.bl_col, val, self.padded, self.symperm, self.sojds, self.sigma, self.tile_plans)
 
 
 # --------------------------------------------------------------------------- setup
@@ -254,6 +256,70 @@ def jds_blocked_from_jds(J: JDS, C_: int = 64, sojds: bool = False) -> Blocked:
         call("spmv_jds_blocked_from_jds", *args(tot, _p(bl_col), _p(bl_val)))
     return Blocked(J.n, J.n_cols, C_, J.perm, slice_ptr, slice_nd[:ns], h_slice_nd[:ns].copy(), bl_col[:tot],
                    bl_val[:tot], tot, J.symperm, sojds)
+
+
+def jds_blocked_windowed_from_csr(A: CSR, C_: int = 64, sigma: int = 65536) -> Blocked:
+    """CRS -> blocked JDS with rows sorted by length inside windows of sigma
+    rows (spmv_jds_blocked_windowed_from_csr); sigma is rounded up to a
+    multiple of C_."""
+    lib = _lib.load()
+    dev = A.device
+    sigma = -(-int(sigma) // C_) * C_
+    n = A.n_rows
+    ns = -(-n // C_)
+    ws = _ws(lib.spmv_jds_blocked_windowed_workspace_size(n), dev)
+    perm = torch.empty(max(n, 1), dtype=_I32, device=dev)
+    slice_ptr = torch.empty(ns + 1, dtype=torch.int64, device=dev)
+    slice_nd = torch.empty(max(ns, 1), dtype=_I32, device=dev)
+    h_slice_nd = np.zeros(max(ns, 1), dtype=np.int32)
+    padded = C.c_int64(0)
+    args = lambda cap, bc, bv: (n, A.nnz, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), C_,
+                                sigma, _p(perm), _p(slice_ptr), _p(slice_nd), bc, bv, cap, C.byref(padded),
+                                _h_i32(h_slice_nd), _p(ws), ws.numel(), _stream())
+    st = lib.spmv_jds_blocked_windowed_from_csr(*args(0, None, None))
+    if st not in (0, 3):
+        call("spmv_jds_blocked_windowed_from_csr", *args(0, None, None))
+    tot = padded.value
+    bl_col = torch.empty(max(tot, 1), dtype=_I32, device=dev)
+    bl_val = torch.empty(max(tot, 1), dtype=A.val.dtype, device=dev)
+    if tot > 0:
+        call("spmv_jds_blocked_windowed_from_csr", *args(tot, _p(bl_col), _p(bl_val)))
+    return Blocked(n, A.n_cols, C_, perm[:n], slice_ptr, slice_nd[:ns], h_slice_nd[:ns].copy(), bl_col[:tot],
+                   bl_val[:tot], tot, False, False, sigma)
+
+
+def spmv_jds_blocked_tiles(B: Blocked, max_iters: int = 0, rows_per_wave: int = 0, wg_waves: int = 0):
+    """The tile plan of B for spmv_jds_blocked_tiled (spmv_jds_blocked_tiles),
+    built once per launch shape and kept on B: (tiles, n_tiles, h_plan)."""
+    key = (max_iters, rows_per_wave, wg_waves)
+    if key not in B.tile_plans:
+        lib = _lib.load()
+        nt = C.c_int64(0)
+        h_plan = np.zeros(10, dtype=np.int64)
+        args = lambda t, cap: (B.n, B.C, B.n_slices, _h_i32(B.h_slice_nd), max_iters, rows_per_wave, wg_waves, t,
+                               cap, C.byref(nt), _h_i64(h_plan), _stream())
+        st = lib.spmv_jds_blocked_tiles(*args(None, 0))
+        if st not in (0, 3):
+            call("spmv_jds_blocked_tiles", *args(None, 0))
+        tiles = torch.empty(max(2 * nt.value, 1), dtype=_I32, device=B.bl_col.device)
+        call("spmv_jds_blocked_tiles", *args(_p(tiles), tiles.numel()))
+        B.tile_plans[key] = (tiles, nt.value, h_plan)
+    return B.tile_plans[key]
+
+
+def spmv_jds_blocked_tiled(B: Blocked, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                           beta: float = 0.0, unroll: int = 0, max_iters: int = 0, rows_per_wave: int = 0,
+                           wg_waves: int = 0) -> torch.Tensor:
+    """y = alpha*A x + beta*y with the blocked-JDS kernel launched from B's
+    tile plan (spmv_jds_blocked_tiled): each XCD walks its eighth of the
+    slices in order."""
+    y = _out_vec(y, B.n, x, beta, B.n_cols)
+    tiles, nt, h_plan = spmv_jds_blocked_tiles(B, max_iters, rows_per_wave, wg_waves)
+    flags = (SYMPERM if B.symperm else 0) | (SOJDS if B.sojds else 0)
+    call("spmv_jds_blocked_tiled", B.n, _p(B.perm), B.C, B.n_slices, _p(B.slice_ptr), _p(B.slice_nd), _p(B.bl_col),
+         _p(B.bl_val), dtype_code(B.bl_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta),
+         _p(tiles), nt, _h_i64(h_plan), unroll, flags, _stream())
+    return y
 
 
 def spmv_convert_values(t: torch.Tensor, dtype: torch.dtype) -> torch.Tensor:

@@ -122,6 +122,49 @@ def test_sojds_long_and_unsorted_rows_bit_exact(shuffle):
         assert np.array_equal(to_np(B.bl_val), Rb.bl_val), C
 
 
+@pytest.mark.parametrize("C,sigma", [(64, 64), (64, 256), (128, 384), (64, 1 << 20)])
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32, torch.int32])
+def test_windowed_blocked_bit_exact(C, sigma, dt):
+    """The windowed RBJDS builder against the oracle's: perm, slice pointers
+    and depths, and every padded slot, bit for bit (empty rows, rows of
+    5,000 entries, a ragged last slice)."""
+    r, c, v, nr, nc, rng = rand_coo(95, 5003, 6000, 0.002, empty_rows=0.2, long_rows=3, long_len=5000)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    Bo = oracle.blocked_windowed(R, C, sigma)
+    A = sp.csr_from_coo(nr, nc, to_dev(r), to_dev(c), to_dev(v))
+    if dt == torch.int32:
+        # int32 payload: each entry's CRS position, laid out by the oracle
+        A = A.with_values(torch.arange(A.nnz, dtype=torch.int32, device="cuda"))
+        Bp = oracle.blocked_windowed(oracle.CSR(nr, nc, R.row_ptr, R.col, np.arange(R.nnz, dtype=np.float64)), C,
+                                     sigma)
+        want_val = Bp.bl_val.astype(np.int64)
+    elif dt == torch.float32:
+        A = A.with_values(sp.spmv_convert_values(A.val, torch.float32))
+        want_val = oracle.round_f32(Bo.bl_val)
+    else:
+        want_val = Bo.bl_val
+    B = sp.jds_blocked_windowed_from_csr(A, C, sigma)
+    assert np.array_equal(to_np(B.perm), Bo.perm)
+    assert np.array_equal(to_np(B.slice_ptr), Bo.slice_ptr)
+    assert np.array_equal(B.h_slice_nd, Bo.slice_nd) and np.array_equal(to_np(B.slice_nd), Bo.slice_nd)
+    assert np.array_equal(to_np(B.bl_col), Bo.bl_col)
+    got = to_np(B.bl_val)
+    assert np.array_equal(got.astype(np.int64) if dt == torch.int32 else got, want_val)
+
+
+def test_windowed_blocked_rejects_and_empty():
+    A = sp.csr_from_coo(10, 10, to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0)))
+    B = sp.jds_blocked_windowed_from_csr(A, 64, 64)
+    assert B.padded == 0 and B.h_slice_nd.tolist() == [0]
+    y = sp.spmv_jds_blocked_tiled(B, to_dev(np.ones(10)), to_dev(np.full(10, 3.0)), 1.0, 0.5)
+    assert to_np(y).tolist() == [1.5] * 10
+    from paper_0910_4836_amd import _lib
+    lib = _lib.load()
+    st = lib.spmv_jds_blocked_windowed_from_csr(10, 0, None, None, None, 0, 64, 96, None, None, None, None, None, 0,
+                                                None, None, None, 0, None)
+    assert st == 1 and b"multiple of C" in lib.spmv_last_error()
+
+
 def test_transpose_bit_exact():
     r, c, v, nr, nc, _ = rand_coo(7, 2000, 1500, 0.004, empty_rows=0.1)
     Rc = oracle.csr_from_coo(nr, nc, r, c, v)

@@ -85,6 +85,8 @@ def test_powerlaw_every_form_sampled(powerlaw):
     RS = sp.RowSplit(A)
     At = sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val)
     autotune.tune_crs(tuner, At, xd, J.ndiag)
+    wS, wC, wU, wW = tuner.tune_windowed(A, xd, J.ndiag)
+    BW = sp.jds_blocked_windowed_from_csr(A, wC, wS)
     forms = {"crs": lambda: sp.spmv_crs(A, xd), "jds": lambda: sp.spmv_jds(J, xd),
              "blocked": lambda: sp.spmv_jds_blocked(B, xd), "crs_split": lambda: sp.spmv_crs_split(S, xd),
              "jds_split": lambda: sp.spmv_jds_split(S, xd), "blocked_split": lambda: sp.spmv_jds_blocked_split(S, xd),
@@ -93,7 +95,8 @@ def test_powerlaw_every_form_sampled(powerlaw):
              "blocked_tuned": lambda: sp.spmv_jds_blocked(Bt, xd, rows_per_wave=bR, unroll=bU, wg_waves=bW),
              "jds_row_split": lambda: sp.spmv_jds_row_split(RS, xd, unroll=ju, max_iters=jm, wg_waves=jw),
              "blocked_row_split": lambda: sp.spmv_jds_blocked_row_split(RS, xd, C_=bC, rows_per_wave=bR, unroll=bU,
-                                                                        wg_waves=bW)}
+                                                                        wg_waves=bW),
+             "blocked_windowed": lambda: sp.spmv_jds_blocked_tiled(BW, xd, unroll=wU, max_iters=32, wg_waves=wW)}
     for name, fn in forms.items():
         got = to_np(fn())[rows]
         e = oracle.rel_err(got, want, D).max()
@@ -107,6 +110,14 @@ def test_powerlaw_every_form_sampled(powerlaw):
     assert np.all(np.diff(perm)[same] > 0)
     assert J.ndiag == L.max() and int(to_np(J.jd_ptr)[J.ndiag]) == nnz
     assert B.padded >= nnz
+    # windowed order: each window of sigma rows is a permutation of itself,
+    # sorted by length down, ties by index
+    pw = to_np(BW.perm)[:n].astype(np.int64)
+    assert np.array_equal(pw // wS, np.arange(n) // wS)
+    Lw = L[pw]
+    inside = (np.arange(1, n) % wS) != 0
+    assert np.all(np.diff(Lw)[inside] <= 0)
+    assert np.all(np.diff(pw)[inside & (np.diff(Lw) == 0)] > 0)
     # slots: one per (row, part) pair present
     assert S.n_slots == int(to_np(S.slot_ptr)[-1]) and S.n_slots <= min(nnz, 8 * n)
     # row parts: contiguous, each within one row of nnz/8 entries

@@ -48,6 +48,20 @@ def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_
                     yield f"blk_C{C}_R{R}_mi{mi}_w{w}", (lambda B=B, R=R, mi=mi, w=w:
                                                          lambda x, y, a, b: sp.spmv_jds_blocked(B, x, y, a, b, R, 0,
                                                                                                 mi, w))()
+        # the tile-plan launch, on the plain order and on windowed orders
+        # (windows of one slice, four slices, and one window of all rows)
+        yield f"blk_tiled_C{C}", (lambda B=B: lambda x, y, a, b: sp.spmv_jds_blocked_tiled(
+            B, x, y, a, b, max_iters=max_iters[-1], wg_waves=waves[-1]))()
+        if symperm:
+            continue
+        for sg in (C, 4 * C, A.n_rows + C):
+            Bw = sp.jds_blocked_windowed_from_csr(A, C, sg)
+            for R in rows_per_wave:
+                for w in waves:
+                    yield f"win_C{C}_s{sg}_R{R}_w{w}", (lambda Bw=Bw, R=R, w=w: lambda x, y, a, b:
+                                                       sp.spmv_jds_blocked_tiled(Bw, x, y, a, b,
+                                                                                 max_iters=max_iters[-1],
+                                                                                 rows_per_wave=R, wg_waves=w))()
 
 
 def run_case(r, c, v, nr, nc, x, y0=None, alpha=1.0, beta=0.0, exact=False, **kw):
