@@ -113,9 +113,9 @@ def test_powerlaw_every_form_sampled(powerlaw):
     # windowed order: each window of sigma rows is a permutation of itself,
     # sorted by length down, ties by index
     pw = to_np(BW.perm)[:n].astype(np.int64)
-    assert np.array_equal(pw // wS, np.arange(n) // wS)
+    assert np.array_equal(pw // BW.sigma, np.arange(n) // BW.sigma)
     Lw = L[pw]
-    inside = (np.arange(1, n) % wS) != 0
+    inside = (np.arange(1, n) % BW.sigma) != 0
     assert np.all(np.diff(Lw)[inside] <= 0)
     assert np.all(np.diff(pw)[inside & (np.diff(Lw) == 0)] > 0)
     # slots: one per (row, part) pair present
