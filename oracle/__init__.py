@@ -56,6 +56,8 @@ _SIGS = {
     "orc_spmv_jds_blocked": (None, [_i32, _i32p, _i32, _i32, _i64p, _i32p, _i32p, _f64p, _f64p, _f64p, _f64, _f64, _int]),
     "orc_round_bf16": (None, [_f64p, _u16p, _i64]),
     "orc_csr_transpose": (None, [_i32, _i32, _i32p, _i32p, _i32p, _i32p, _i64p]),
+    "orc_csr_upper": (_i64, [_i32, _i32p, _i32p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "orc_spmv_crs_sym": (None, [_i32, _i32p, _i32p, _f64p, _f64p, _f64p, _f64, _f64]),
     "orc_grad_vals_csr": (None, [_i32, _i32p, _i32p, _f64p, _f64p, _f64p, _f64, _f64]),
     "orc_spmv_crs_transposed": (None, [_i32, _i32, _i32p, _i32p, _f64p, _f64p, _f64p]),
     "orc_cheb_forward": (None, [_i32, _i32p, _i32p, _f64p, _f64p, _i32, _f64p]),
@@ -154,6 +156,26 @@ def transpose(A: CSR):
     tmap = np.zeros(max(A.nnz, 1), np.int64)
     lib().orc_csr_transpose(A.n_rows, A.n_cols, A.row_ptr, A.col, rowT, colT, tmap)
     return rowT, colT[:A.nnz], tmap[:A.nnz]
+
+
+def csr_upper(A: CSR) -> CSR:
+    """Upper triangle (col >= row) of a square matrix, each row in CRS order."""
+    assert A.n_rows == A.n_cols
+    n = A.n_rows
+    m = int(lib().orc_csr_upper(n, A.row_ptr, A.col, A.val, None, None, None))
+    rp = np.zeros(n + 1, np.int32)
+    col = np.zeros(max(m, 1), np.int32)
+    val = np.zeros(max(m, 1), np.float64)
+    lib().orc_csr_upper(n, A.row_ptr, A.col, A.val, rp.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p),
+                        val.ctypes.data_as(C.c_void_p))
+    return CSR(n, n, rp, col[:m], val[:m])
+
+
+def spmv_crs_sym(U: CSR, x, y=None, alpha=1.0, beta=0.0):
+    """y = alpha * (U + U^T - diag(U)) x + beta * y from the upper triangle U."""
+    out = np.zeros(U.n_rows, np.float64) if y is None else _c(y, np.float64).copy()
+    lib().orc_spmv_crs_sym(U.n_rows, U.row_ptr, U.col, U.val, _c(x, np.float64), out, alpha, beta)
+    return out
 
 
 def grad_vals(A: CSR, g, x, alpha=1.0, beta=0.0, out=None):

@@ -452,6 +452,58 @@ void orc_round_bf16(const double *in, uint16_t *out, i64 n)
 }
 
 /* ------------------------------------------------------------------------ */
+/* One-triangle storage of a symmetric matrix.  Section 4.2 observes that the
+ * Hamiltonian is symmetric (Hermitian), which would let an SpMV move less
+ * data; the paper does not pursue it.  Reading: A is stored as its upper
+ * triangle U (entries with col >= row, each row in CRS order) and
+ * A = U + U^T - diag(U).  Entries below the diagonal are dropped unread.
+ * Returns nnz(U); with out_row_ptr == NULL nothing is written. */
+i64 orc_csr_upper(i32 n, const i32 *row_ptr, const i32 *col, const double *val,
+                  i32 *out_row_ptr, i32 *out_col, double *out_val)
+{
+    i64 p = 0;
+    if (out_row_ptr) out_row_ptr[0] = 0;
+    for (i32 i = 0; i < n; ++i) {
+        for (i32 j = row_ptr[i]; j < row_ptr[i + 1]; ++j) {
+            if (col[j] < i) continue;
+            if (out_row_ptr) {
+                out_col[p] = col[j];
+                out_val[p] = val[j];
+            }
+            ++p;
+        }
+        if (out_row_ptr) out_row_ptr[i + 1] = (i32)p;
+    }
+    return p;
+}
+
+/* y = alpha * (U + U^T - diag(U)) x + beta * y from the upper triangle U.
+ * Row i's sum is taken in ascending column order, as orc_spmv_crs takes it
+ * on the full matrix with sorted rows: first the mirrored entries a(k, i),
+ * k < i, in ascending k, then row i of U left to right.  beta == 0 never
+ * reads y. */
+void orc_spmv_crs_sym(i32 n, const i32 *row_ptr, const i32 *col, const double *val,
+                      const double *x, double *y, double alpha, double beta)
+{
+    double *lo = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    /* lo[j] = sum over k < j of a(k, j) * x[k]; rows k are visited in
+     * ascending order, so each lo[j] adds its terms in ascending k */
+    for (i32 k = 0; k < n; ++k)
+        for (i32 e = row_ptr[k]; e < row_ptr[k + 1]; ++e)
+            if (col[e] > k) lo[col[e]] = lo[col[e]] + val[e] * x[k];
+    for (i32 i = 0; i < n; ++i) {
+        double s = lo[i];
+        for (i32 e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            s = s + val[e] * x[col[e]];
+        if (beta == 0.0)
+            y[i] = alpha * s;
+        else
+            y[i] = alpha * s + beta * y[i];
+    }
+    free(lo);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Transpose of a CRS pattern: row c of A^T lists the entries of column c of A
  * in ascending original row order; tmap[t] is the position in A of entry t of
  * A^T, so A^T's values are val[tmap]. */

@@ -295,6 +295,22 @@ def random_pattern(n_rows: int, n_cols: int, density: float, rng, *,
     return _finish(rows, cols, vals, n_cols) + (n_rows, n_cols)
 
 
+def random_symmetric(n: int, density: float, rng, *, integer: bool = False,
+                     empty_rows: float = 0.0, long_rows: int = 0, long_len: int = 0):
+    """Random symmetric pattern: a random_pattern whose entries on or above the
+    diagonal are kept and mirrored below it (the mirror holds the same value).
+    Rows are in ascending column order."""
+    r, c, v, _, _ = random_pattern(n, n, density, rng, integer=integer, empty_rows=empty_rows,
+                                   long_rows=long_rows, long_len=long_len)
+    up = c >= r
+    r, c, v = r[up].astype(np.int64), c[up].astype(np.int64), v[up]
+    off = c > r
+    rows = np.concatenate([r, c[off]])
+    cols = np.concatenate([c, r[off]])
+    vals = np.concatenate([v, v[off]])
+    return _finish(rows, cols, vals, n) + (n, n)
+
+
 def integer_vector(n: int, rng, lo: int = -8, hi: int = 8) -> np.ndarray:
     return rng.integers(lo, hi + 1, size=n).astype(np.float64)
 

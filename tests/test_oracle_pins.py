@@ -551,3 +551,88 @@ def test_chebyshev_directional_derivative():
     assert e1 <= 1e-6 * max(abs(an), abs(loss))
     # central differences converge at second order towards the adjoint value
     assert e2 <= 0.35 * e1 or e2 <= 1e-9 * abs(loss)
+
+
+# --------------------------------------------------------------- one-triangle storage
+
+
+def rand_sym(seed, n=48, density=0.12, integer=False, empty=0.1, long_rows=0, long_len=0):
+    rng = np.random.default_rng(1000 + seed)
+    r, c, v, n_, _ = synth.random_symmetric(n, density, rng, integer=integer, empty_rows=empty,
+                                            long_rows=long_rows, long_len=long_len)
+    return oracle.csr_from_coo(n_, n_, r, c, v), rng
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_csr_upper_brute_force(seed):
+    """Upper triangle against a dense copy: the entries with col >= row, in
+    ascending column order per row, and A = U + U^T - diag(U)."""
+    A, _ = rand_sym(seed, n=20 + 7 * seed)
+    M = dense_of(A)
+    assert np.array_equal(M, M.T)
+    U = oracle.csr_upper(A)
+    want_rp = [0]
+    want_c, want_v = [], []
+    for i in range(A.n_rows):
+        for j in range(A.n_cols):
+            if j >= i and M[i, j] != 0.0:
+                want_c.append(j)
+                want_v.append(M[i, j])
+        want_rp.append(len(want_c))
+    assert np.array_equal(U.row_ptr, np.array(want_rp, np.int32))
+    assert np.array_equal(U.col, np.array(want_c, np.int32))
+    assert np.array_equal(U.val, np.array(want_v))
+    MU = dense_of(U)
+    assert np.array_equal(MU + MU.T - np.diag(np.diag(MU)), M)
+
+
+def test_csr_upper_drops_lower_entries_unread():
+    """Entries below the diagonal never reach U: changing them leaves U as is."""
+    A, _ = rand_sym(7, n=30)
+    rows = A.row_index()
+    B = oracle.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, np.where(A.col < rows, 99.0, A.val))
+    U, V = oracle.csr_upper(A), oracle.csr_upper(B)
+    assert np.array_equal(U.val, V.val) and np.array_equal(U.col, V.col)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_spmv_crs_sym_bit_identical_to_full_crs(seed):
+    """Row i of the triangle product sums in ascending column order, as the
+    full CRS product does on the symmetric matrix with sorted rows: the two
+    are bit-identical for any values."""
+    A, rng = rand_sym(seed, n=30 + 11 * seed, long_rows=2, long_len=25)
+    U = oracle.csr_upper(A)
+    x = rng.uniform(-1, 1, A.n_rows)
+    y0 = rng.uniform(-1, 1, A.n_rows)
+    for alpha, beta in ((1.0, 0.0), (-0.75, 0.5), (2.0, 1.0)):
+        got = oracle.spmv_crs_sym(U, x, y0, alpha, beta)
+        want = oracle.spmv_crs(A, x, y0, alpha, beta)
+        assert np.array_equal(got, want)
+
+
+def test_spmv_crs_sym_dense_and_integer():
+    """Against dense Python floats (1e-14 of the row scale) and exactly on
+    integer values, where every partial sum is exact."""
+    A, rng = rand_sym(11, n=60, density=0.2)
+    U = oracle.csr_upper(A)
+    x = rng.uniform(-1, 1, A.n_rows)
+    M = dense_of(A)
+    want = np.array([sum(float(M[i, j]) * float(x[j]) for j in range(A.n_cols)) for i in range(A.n_rows)])
+    scale = np.abs(M) @ np.abs(x)
+    assert np.all(np.abs(oracle.spmv_crs_sym(U, x) - want) <= 1e-14 * np.maximum(scale, 1e-300))
+    Ai, rng = rand_sym(12, n=60, density=0.2, integer=True)
+    Ui = oracle.csr_upper(Ai)
+    xi = synth.integer_vector(Ai.n_rows, rng)
+    Mi = dense_of(Ai)
+    assert np.array_equal(oracle.spmv_crs_sym(Ui, xi), Mi @ xi)
+
+
+def test_spmv_crs_sym_beta_zero_ignores_y_and_empty():
+    A, rng = rand_sym(13, n=25, empty=0.4)
+    U = oracle.csr_upper(A)
+    x = rng.uniform(-1, 1, A.n_rows)
+    got = oracle.spmv_crs_sym(U, x, np.full(A.n_rows, np.nan), 1.0, 0.0)
+    assert np.all(np.isfinite(got))
+    E = oracle.CSR(5, 5, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert oracle.csr_upper(E).nnz == 0
+    assert np.array_equal(oracle.spmv_crs_sym(oracle.csr_upper(E), np.ones(5), np.ones(5), 1.0, 2.0), np.full(5, 2.0))
