@@ -663,14 +663,20 @@ def load_symdiag(torch, sp, dev, tune_cache=""):
     Ds = sp.dia_from_csr(A, symmetric=True)
     torch.cuda.synchronize()
     setup["dia_sym_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    t0 = time.perf_counter()
+    S = sp.csr_upper_from_csr(A)
+    torch.cuda.synchronize()
+    setup["crs_sym_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    sym_bn = autotune.tune_crs_sym(tuner, S, x, J.ndiag // 2 + 1)
     tune = {"crs_block_nnz": crs_bn, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw, "blocked_C": bC,
-            "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW}
-    return dict(A=A, J=J, B=B, D=Dd, Ds=Ds, x=x, n=n, nnz=A.nnz, tune=tune, setup=setup, host=(r, c, v, n))
+            "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW, "crs_sym_block_nnz": sym_bn}
+    return dict(A=A, J=J, B=B, D=Dd, Ds=Ds, S=S, x=x, n=n, nnz=A.nnz, tune=tune, setup=setup, host=(r, c, v, n))
 
 
 def symdiag_kernels(torch, sp, W3, vdt, y):
-    """(name, fn, algorithmic bytes) of the five products with values in vdt
-    and FP64 vectors."""
+    """(name, fn, algorithmic bytes) of the six products with values in vdt
+    and FP64 vectors (the one-triangle CRS counted over its stored entries,
+    x and y once, like CRS)."""
     A, J, B, Dd, Ds, x, n, nnz = (W3[k] for k in ("A", "J", "B", "D", "Ds", "x", "n", "nnz"))
     T = W3["tune"]
     ju, jm, jw = T["jds_unroll"], T["jds_max_iters"], T["jds_wg_waves"]
@@ -682,19 +688,21 @@ def symdiag_kernels(torch, sp, W3, vdt, y):
     Bq = B.with_values(conv(B.bl_val))
     Dq = sp.DIA(Dd.n_rows, Dd.n_cols, Dd.offsets, conv(Dd.dia_val), Dd.rem)
     Dsq = sp.DIA(Ds.n_rows, Ds.n_cols, Ds.offsets, conv(Ds.dia_val), Ds.rem, True)
+    Sq = W3["S"].with_values(conv(W3["S"].upper.val))
     return [(f"crs_{tag}", lambda: sp.spmv_crs(Aq, x, y), bytes_crs(nnz, n, n, sv, 8)),
             (f"jds_{tag}", lambda: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm, wg_waves=jw),
              bytes_jds(nnz, n, n, J.ndiag, sv, 8)),
             (f"blocked_{tag}", lambda: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW),
              bytes_blocked(nnz, n, n, B.n_slices, sv, 8)),
             (f"dia_{tag}", lambda: sp.spmv_dia(Dq, x, y), bytes_dia(Dd, sv, 8)),
-            (f"dia_sym_{tag}", lambda: sp.spmv_dia(Dsq, x, y), bytes_dia(Ds, sv, 8))]
+            (f"dia_sym_{tag}", lambda: sp.spmv_dia(Dsq, x, y), bytes_dia(Ds, sv, 8)),
+            (f"crs_sym_{tag}", lambda: sp.spmv_crs_sym(Sq, x, y), bytes_crs(Sq.nnz, n, n, sv, 8))]
 
 
 def mixed_precision_c3(torch, sp, dev, W3, steps, n_sample=4000):
     """FP64 against reduced-precision value storage (FP32, BF16; FP64
     vectors) on the symmetric-diagonals matrix, in CRS, JDS, blocked JDS,
-    DIA and symmetric DIA: time, GFLOP/s, algorithmic bytes, fraction of
+    DIA, symmetric DIA and one-triangle CRS: time, GFLOP/s, algorithmic bytes, fraction of
     8 TB/s, speed-up over the same format in FP64, and the error against the
     FP64 product (the library's FP64 CRS, all rows, scaled by
     D_i = sum_j |a_ij||x_j|).  Each product's output on a seeded sample of
@@ -709,7 +717,8 @@ def mixed_precision_c3(torch, sp, dev, W3, steps, n_sample=4000):
     rows_d = torch.from_numpy(rows).to(dev)
     out = {"workload": f"symmetric diagonals n={n} nnz={nnz} (diagonal + 12 mirrored secondary diagonals), "
                        f"values in FP64 / FP32 / BF16, x and y FP64", "autotuned": W3["tune"],
-           "dia_diagonals": W3["D"].ndia, "dia_sym_diagonals": W3["Ds"].ndia, "setup_ms": W3["setup"],
+           "dia_diagonals": W3["D"].ndia, "dia_sym_diagonals": W3["Ds"].ndia, "crs_sym_stored": W3["S"].nnz,
+           "setup_ms": W3["setup"],
            "kernels": {}}
     samples = {}
     fp64_ms = {}

@@ -27,9 +27,10 @@
  *    contents on the device.
  *  - Every call returns a spmv_status; on failure spmv_last_error() returns a
  *    message for the calling thread.  No C++ exception crosses this boundary.
- *  - Results are deterministic: no floating-point atomics; every output
- *    element is produced by one fixed sequence of operations for a given
- *    argument set.
+ *  - Results are deterministic: every output element is produced by one
+ *    fixed sequence of operations for a given argument set.  The one
+ *    exception is spmv_crs_sym (one-triangle storage), whose mirrored terms
+ *    are added with floating-point atomics.
  *  - Vectors x and y of one call must not overlap (except where stated).
  */
 #ifndef SPMV_H
@@ -58,7 +59,8 @@ typedef enum {
     SPMV_I32 = 3   /* int32 payload: accepted only by the calls that move */
                    /* values without arithmetic (spmv_jds_from_csr,       */
                    /* spmv_jds_to_csr, spmv_jds_blocked_from_jds,         */
-                   /* spmv_permute_vec, spmv_gather_values), which copy   */
+                   /* spmv_csr_upper_from_csr, spmv_permute_vec,          */
+                   /* spmv_gather_values), which copy                     */
                    /* every element bit for bit; e.g. entry positions     */
                    /* carried through a conversion.  Rejected elsewhere.  */
 } spmv_dtype;
@@ -540,6 +542,41 @@ spmv_status spmv_dia_sym_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr
 spmv_status spmv_dia_sym(int32_t n, int32_t ndia, const int32_t *h_offsets, const void *dia_val, spmv_dtype val_dt,
                          const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val, const void *x,
                          void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream);
+
+/* ======================================================================== */
+/* One-triangle CRS of a symmetric matrix                                    */
+/* ======================================================================== */
+/* The paper (Section 4.2) notes that its Hamiltonian is symmetric, so an
+ * SpMV could move less data by storing one triangle; it does not try this.
+ * Here a symmetric n x n matrix is stored as its upper triangle U (entries
+ * with col >= row, each row in CRS order): A = U + U^T - diag(U), about half
+ * the entries of the full CRS.
+ * spmv_csr_upper_from_csr (setup, synchronises): from a full CRS matrix
+ * (row_ptr[n+1], col_idx/val: nnz entries of dt, any payload dtype including
+ * SPMV_I32, copied bit for bit) keeps the entries with col >= row.  Entries
+ * below the diagonal are dropped without being read, so the matrix is taken
+ * to be symmetric, not checked.  With up_row_ptr == NULL it only returns
+ * *h_nnz_upper; otherwise it also fills up_row_ptr[n+1], up_col and up_val
+ * (*h_nnz_upper entries).  ws: spmv_csr_upper_workspace_size(n) bytes. */
+size_t spmv_csr_upper_workspace_size(int32_t n);
+spmv_status spmv_csr_upper_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                    const void *val, spmv_dtype dt, int64_t *h_nnz_upper, int32_t *up_row_ptr,
+                                    int32_t *up_col, void *up_val, void *ws, size_t ws_bytes, void *stream);
+/* y = alpha * (U + U^T - diag U) x + beta * y from the upper triangle:
+ * row_ptr/col_idx/val hold U (every col >= its row; val F64, F32 or BF16);
+ * x and y are FP64 (vec_dt must be SPMV_F64, else SPMV_ERR_UNSUPPORTED).
+ * plan/n_blocks/block_nnz: spmv_crs_plan run on U's row_ptr with this
+ * block_nnz (0 = default); a plan made with another block_nnz is an error the
+ * library cannot see.  Two launches on `stream`: y = beta*y (beta == 0 writes
+ * zeros without reading y), then one pass over U in which each entry
+ * (i, j, a) is read once and serves row i (a*x_j, summed in FP64 per row and
+ * added to y_i once) and, for j > i, row j (alpha*a*x_i added to y_j).  The
+ * adds into y use device-scope FP64 atomics: every y_i is a sum of its terms
+ * in an order that varies between runs (not bit-reproducible; the error
+ * bound of an FP64 sum of row-length + 1 terms holds for every order). */
+spmv_status spmv_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                         spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                         const int32_t *plan, int32_t n_blocks, int32_t block_nnz, void *stream);
 
 /* ======================================================================== */
 /* Many matrices in one launch                                               */

@@ -1458,6 +1458,36 @@ size_t spmv_dia_workspace_size(int32_t n_rows, int32_t n_cols)
 }  // extern "C"
 
 namespace spmv {
+// ---- upper triangle of a symmetric matrix: entries with col >= row
+
+__global__ void upper_count_kernel(const int32_t *__restrict__ rp, int32_t n, const int32_t *__restrict__ col,
+                                   int32_t *__restrict__ cnt)
+{
+    GRID_LOOP(i, (int64_t)n)
+    {
+        int32_t c = 0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) c += col[e] >= i;
+        cnt[i] = c;
+    }
+}
+
+template <typename T>
+__global__ void upper_fill_kernel(const int32_t *__restrict__ rp, int32_t n, const int32_t *__restrict__ col,
+                                  const T *__restrict__ val, const int32_t *__restrict__ up_rp,
+                                  int32_t *__restrict__ up_col, T *__restrict__ up_val)
+{
+    GRID_LOOP(i, (int64_t)n)
+    {
+        int32_t p = up_rp[i];
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (col[e] < i) continue;
+            up_col[p] = col[e];
+            up_val[p] = val[e];
+            ++p;
+        }
+    }
+}
+
 static spmv_status dia_from_csr_impl(bool sym, int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                                      const int32_t *col_idx, const void *val, spmv_dtype dt, int32_t max_diags,
                                      int32_t *h_offsets, int32_t *h_ndia, int64_t *h_rem_nnz, void *dia_val,
@@ -1573,6 +1603,65 @@ spmv_status spmv_dia_sym_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr
 {
     return dia_from_csr_impl(true, n, n, nnz, row_ptr, col_idx, val, dt, max_diags, h_offsets, h_ndia, h_rem_nnz,
                              dia_val, rem_row_ptr, rem_col, rem_val, ws, ws_bytes, stream);
+}
+
+size_t spmv_csr_upper_workspace_size(int32_t n)
+{
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    return align_up(sizeof(int32_t) * nn, 256) + align_up(sizeof(int32_t) * (nn + 1), 256) +
+           align_up(sizeof(int32_t) * scan_ws_elems((int64_t)nn), 256) + 512;
+}
+
+spmv_status spmv_csr_upper_from_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                    const void *val, spmv_dtype dt, int64_t *h_nnz_upper, int32_t *up_row_ptr,
+                                    int32_t *up_col, void *up_val, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && nnz >= 0, "spmv_csr_upper_from_csr: negative size");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPMV_ERR_UNSUPPORTED, "spmv_csr_upper_from_csr: nnz >= 2^31");
+    SPMV_REQUIRE(valid_payload_dtype(dt), "spmv_csr_upper_from_csr: bad dtype");
+    SPMV_REQUIRE(h_nnz_upper, "spmv_csr_upper_from_csr: null h_nnz_upper");
+    SPMV_REQUIRE(n == 0 || row_ptr, "spmv_csr_upper_from_csr: null row_ptr");
+    SPMV_REQUIRE(nnz == 0 || (col_idx && val), "spmv_csr_upper_from_csr: null col_idx or val");
+    SPMV_REQUIRE(ws && ws_bytes >= spmv_csr_upper_workspace_size(n), "spmv_csr_upper_from_csr: workspace too small");
+    hipStream_t s = as_stream(stream);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    WsCarver wc(ws, ws_bytes);
+    int32_t *cnt = wc.take<int32_t>(nn);
+    int32_t *rp = wc.take<int32_t>(nn + 1);
+    int32_t *sws = wc.take<int32_t>(scan_ws_elems((int64_t)nn));
+    if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_csr_upper_from_csr: workspace too small");
+    int32_t total = 0;
+    if (n > 0) {
+        upper_count_kernel<<<grid_for(n), 256, 0, s>>>(row_ptr, n, col_idx, cnt);
+        SPMV_CHECK_LAUNCH("upper count");
+        spmv_status st = exclusive_scan<int32_t, int32_t>(cnt, n, rp, sws, s);
+        if (st != SPMV_OK) return st;
+        SPMV_HIP(hipMemcpyAsync(&total, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SPMV_HIP(hipStreamSynchronize(s));
+    }
+    *h_nnz_upper = total;
+    if (!up_row_ptr) return SPMV_OK;                          // size only
+    SPMV_REQUIRE(total == 0 || (up_col && up_val), "spmv_csr_upper_from_csr: null output");
+    if (n == 0) {
+        SPMV_HIP(hipMemsetAsync(up_row_ptr, 0, sizeof(int32_t), s));
+        SPMV_HIP(hipStreamSynchronize(s));
+        return SPMV_OK;
+    }
+    SPMV_HIP(hipMemcpyAsync(up_row_ptr, rp, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+    if (total > 0) {
+#define UP_CASE(DT, T)                                                                                          \
+        if (dt == DT)                                                                                           \
+            upper_fill_kernel<T><<<grid_for(n), 256, 0, s>>>(row_ptr, n, col_idx, (const T *)val, rp, up_col,   \
+                                                             (T *)up_val);
+        UP_CASE(SPMV_F64, uint64_t)
+        UP_CASE(SPMV_F32, uint32_t)
+        UP_CASE(SPMV_BF16, uint16_t)
+        UP_CASE(SPMV_I32, uint32_t)
+#undef UP_CASE
+        SPMV_CHECK_LAUNCH("upper fill");
+    }
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
 }
 
 size_t spmv_split_rows_workspace_size(void) { return 2 * align_up(sizeof(int64_t) * (SPLIT_PARTS + 1), 256); }

@@ -349,6 +349,147 @@ __global__ __launch_bounds__(CRS_THREADS) void spmm_crs_kernel(const int32_t *__
     }
 }
 
+// ---------------------------------------------------------------- one triangle
+// y = alpha * (U + U^T - diag U) x + beta * y from the upper triangle U of a
+// symmetric matrix.  y is first scaled by beta (sym_scale_kernel); then every
+// plan block of U streams its entries once: entry (i, j, a) gives the product
+// a*x[j] for row i's own sum (LDS, as in the CRS block kernel) and, for j > i,
+// adds alpha*a*x[i] to y[j] with a device-scope FP64 atomic add; each row's
+// own sum goes to y[i] with one more atomic add.  The order of the adds into
+// a y entry is not fixed, so y is not bit-reproducible from run to run.
+__global__ __launch_bounds__(256) void sym_scale_kernel(double *__restrict__ y, int64_t n, double beta)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = beta == 0.0 ? 0.0 : beta * y[i];
+}
+
+// LDS of the triangle kernel: FP64 products rounded up to whole trips, then
+// one int16 row number per entry.
+inline size_t crs_sym_lds_bytes(int32_t block_nnz)
+{
+    return (size_t)ceil_div(block_nnz, CRS_LDS_ROUND) * CRS_LDS_ROUND * 8 + (size_t)block_nnz * 2;
+}
+
+template <typename VT>
+__global__ __launch_bounds__(CRS_THREADS) void crs_sym_kernel(const int32_t *__restrict__ row_ptr,
+                                                              const int32_t *__restrict__ col,
+                                                              const VT *__restrict__ val,
+                                                              const double *__restrict__ x, double *__restrict__ y,
+                                                              const int32_t *__restrict__ plan, int32_t block_nnz,
+                                                              double alpha)
+{
+    extern __shared__ double smem_d[];
+    __shared__ double red[CRS_THREADS / WAVE];
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t r0 = plan[b], r1 = plan[b + 1];
+    const int32_t e0 = row_ptr[r0], e1 = row_ptr[r1];
+    const int32_t nr = r1 - r0, ne = e1 - e0;
+    const int t = (int)threadIdx.x;
+
+    if (nr == 1) {
+        // one (long) row: lanes stride over its entries
+        const double xi = x[r0];
+        double s = 0.0;
+        for (int32_t e = e0 + t; e < e1; e += CRS_THREADS) {
+            const int32_t c = ld_stream(col + e);
+            const double a = to_f64(ld_stream(val + e));
+            s = fma(a, x[c], s);
+            if (c > r0) unsafeAtomicAdd(y + c, alpha * (a * xi));
+        }
+        s = group_sum(s, WAVE);
+        if (lane_id() == 0) red[t / WAVE] = s;
+        __syncthreads();
+        if (t == 0) {
+            double tot = red[0];
+            for (int w = 1; w < CRS_THREADS / WAVE; ++w) tot += red[w];
+            unsafeAtomicAdd(y + r0, alpha * tot);
+        }
+        return;
+    }
+
+    int G = 64;
+    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
+    const int g = t / G, l = t % G;
+    int32_t rs = 0, re = 0;
+    if (nr <= CRS_THREADS && g < nr) {
+        rs = row_ptr[r0 + g];
+        re = row_ptr[r0 + g + 1];
+    }
+
+    // the row of every entry of the block, into LDS
+    const int32_t rounded = (block_nnz + CRS_LDS_ROUND - 1) / CRS_LDS_ROUND * CRS_LDS_ROUND;
+    double *prod = smem_d;
+    int16_t *rid = reinterpret_cast<int16_t *>(smem_d + rounded);
+    if (nr <= CRS_THREADS) {
+        if (g < nr)
+            for (int32_t k = rs - e0 + l; k < re - e0; k += G) rid[k] = (int16_t)g;
+    } else {
+        for (int32_t q = t; q < nr; q += CRS_THREADS)
+            for (int32_t k = row_ptr[r0 + q] - e0; k < row_ptr[r0 + q + 1] - e0; ++k) rid[k] = (int16_t)q;
+    }
+    __syncthreads();
+
+    // stream the entries: own-row products into LDS, mirrored terms to y
+    constexpr int U = CRS_STREAM_U;
+    if (ne > 0) {
+        for (int32_t k0 = 0; k0 < ne; k0 += U * CRS_THREADS) {
+            int32_t c[U], i[U];
+            VT v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t k = min(k0 + u * CRS_THREADS + t, ne - 1);
+                c[u] = ld_stream(col + e0 + k);
+                v[u] = ld_stream(val + e0 + k);
+                i[u] = r0 + rid[k];
+            }
+            double xj[U], xi[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xj[u] = x[c[u]];
+                xi[u] = x[i[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t k = k0 + u * CRS_THREADS + t;
+                const double a = to_f64(v[u]);
+                prod[k] = a * xj[u];
+                if (k < ne && c[u] > i[u]) unsafeAtomicAdd(y + c[u], alpha * (a * xi[u]));
+            }
+        }
+    }
+    __syncthreads();
+
+    // each row's own sum, in entry order per lane, then a fixed shuffle tree
+    if (nr > CRS_THREADS) {
+        for (int32_t q = t; q < nr; q += CRS_THREADS) {
+            double acc = 0.0;
+            for (int32_t k = row_ptr[r0 + q] - e0; k < row_ptr[r0 + q + 1] - e0; ++k) acc += prod[k];
+            unsafeAtomicAdd(y + r0 + q, alpha * acc);
+        }
+        return;
+    }
+    double acc = 0.0;
+    if (g < nr)
+        for (int32_t k = rs - e0 + l; k < re - e0; k += G) acc += prod[k];
+    acc = group_sum(acc, G);
+    if (g < nr && l == 0) unsafeAtomicAdd(y + r0 + g, alpha * acc);
+}
+
+template <typename VT>
+static spmv_status launch_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col, const void *val,
+                                  const double *x, double *y, double alpha, double beta, const int32_t *plan,
+                                  int32_t n_blocks, int32_t block_nnz, hipStream_t s)
+{
+    const int64_t sgrid = std::min<int64_t>(ceil_div(n, 256), 8192);
+    sym_scale_kernel<<<(unsigned)sgrid, 256, 0, s>>>(y, n, beta);
+    SPMV_CHECK_LAUNCH("spmv_crs_sym scale");
+    if (n_blocks == 0) return SPMV_OK;
+    crs_sym_kernel<VT><<<n_blocks, CRS_THREADS, crs_sym_lds_bytes(block_nnz), s>>>(
+        row_ptr, col, (const VT *)val, x, y, plan, block_nnz, alpha);
+    SPMV_CHECK_LAUNCH("spmv_crs_sym");
+    return SPMV_OK;
+}
+
 template <typename VT, typename XT>
 static spmv_status launch_spmm_crs(const int32_t *row_ptr, const int32_t *col, const void *val, int32_t k,
                                    const void *X, int64_t ldx, void *Y, int64_t ldy, double alpha, double beta,
@@ -471,6 +612,33 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
     CRS_CASE(SPMV_F64, double, SPMV_F32, float)
 #undef CRS_CASE
     return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs: dtype combination");
+}
+
+spmv_status spmv_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                         spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                         const int32_t *plan, int32_t n_blocks, int32_t block_nnz, void *stream)
+{
+    SPMV_REQUIRE(n >= 0, "spmv_crs_sym: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt), "spmv_crs_sym: bad value dtype");
+    if (vec_dt != SPMV_F64) return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs_sym: x and y must be FP64");
+    if (n == 0) return SPMV_OK;
+    SPMV_REQUIRE(row_ptr && x && y && plan, "spmv_crs_sym: null pointer");
+    SPMV_REQUIRE(n_blocks >= 0, "spmv_crs_sym: n_blocks < 0");
+    if (block_nnz == 0) block_nnz = CRS_DEFAULT_BLOCK_NNZ;
+    SPMV_REQUIRE(block_nnz >= CRS_THREADS && block_nnz <= CRS_MAX_BLOCK_NNZ,
+                 "spmv_crs_sym: block_nnz must be in [256, 4096]");
+    hipStream_t s = as_stream(stream);
+    const double *xd = (const double *)x;
+    double *yd = (double *)y;
+    switch (val_dt) {
+    case SPMV_F64: return launch_crs_sym<double>(n, row_ptr, col_idx, val, xd, yd, alpha, beta, plan, n_blocks,
+                                                 block_nnz, s);
+    case SPMV_F32: return launch_crs_sym<float>(n, row_ptr, col_idx, val, xd, yd, alpha, beta, plan, n_blocks,
+                                                block_nnz, s);
+    case SPMV_BF16: return launch_crs_sym<bf16>(n, row_ptr, col_idx, val, xd, yd, alpha, beta, plan, n_blocks,
+                                                block_nnz, s);
+    default: return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs_sym: value dtype");
+    }
 }
 
 spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr_all, const int32_t *dest_all,

@@ -800,6 +800,66 @@ def spmv_jds_blocked_row_split(R: RowSplit, x, y=None, alpha=1.0, beta=0.0, C_=6
 
 
 @dataclass
+class SymCSR:
+    """A symmetric n x n matrix stored as its upper triangle U (entries with
+    col >= row, CRS order): A = U + U^T - diag(U)."""
+    upper: CSR
+
+    @property
+    def n(self) -> int:
+        return self.upper.n_rows
+
+    @property
+    def nnz(self) -> int:
+        """Stored entries (those of U)."""
+        return self.upper.nnz
+
+    @property
+    def device(self):
+        return self.upper.device
+
+    def with_values(self, val: torch.Tensor) -> "SymCSR":
+        return SymCSR(self.upper.with_values(val))
+
+
+def csr_upper_from_csr(A: CSR) -> SymCSR:
+    """Full CRS of a symmetric matrix -> its upper triangle on the GPU
+    (spmv_csr_upper_from_csr; entries below the diagonal are not read)."""
+    if A.n_rows != A.n_cols:
+        raise ValueError("one-triangle storage needs a square matrix")
+    lib = _lib.load()
+    dev = A.device
+    n = A.n_rows
+    ws = _ws(lib.spmv_csr_upper_workspace_size(n), dev)
+    m = C.c_int64(0)
+    args = lambda rp, uc, uv: (n, A.nnz, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype),
+                               C.byref(m), rp, uc, uv, _p(ws), ws.numel(), _stream())
+    call("spmv_csr_upper_from_csr", *args(None, None, None))
+    k = m.value
+    rp = torch.empty(n + 1, dtype=_I32, device=dev)
+    col = torch.empty(max(k, 1), dtype=_I32, device=dev)
+    val = torch.empty(max(k, 1), dtype=A.val.dtype, device=dev)
+    call("spmv_csr_upper_from_csr", *args(_p(rp), _p(col), _p(val)))
+    return SymCSR(CSR(n, n, rp, col[:k], val[:k]))
+
+
+def spmv_crs_sym(S: SymCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                 beta: float = 0.0) -> torch.Tensor:
+    """y = alpha*A x + beta*y from the upper triangle (spmv_crs_sym; FP64 x
+    and y; the mirrored terms are added with atomics, so y may differ in the
+    last bits between runs)."""
+    U = S.upper
+    if x.dtype != torch.float64:
+        raise TypeError("spmv_crs_sym: x must be float64")
+    y = _out_vec(y, U.n_rows, x, beta, U.n_cols)
+    if U.plan is None:
+        spmv_crs_plan(U)
+    call("spmv_crs_sym", U.n_rows, _p(U.row_ptr), _p(U.col_idx), _p(U.val), dtype_code(U.val.dtype), _p(x), _p(y),
+         dtype_code(x.dtype), float(alpha), float(beta), _p(U.plan), U.n_blocks, U.block_nnz, _stream())
+    return y
+
+
+@dataclass
 class DIA:
     """Densely stored diagonals (offset col - row) plus a remainder CRS."""
     n_rows: int

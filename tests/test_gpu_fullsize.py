@@ -198,6 +198,12 @@ def test_symmetric_diagonals_sampled():
     e = oracle.rel_err(to_np(sp.spmv_dia(Dd, xd))[rows], want, D).max()
     assert e <= FP64_TOL, f"dia: {e:.3e}"
     del Dd
+    # one-triangle CRS: the diagonal and one of each mirrored pair
+    S = sp.csr_upper_from_csr(A)
+    assert S.nnz == (A.nnz + n) // 2
+    e = oracle.rel_err(to_np(sp.spmv_crs_sym(S, xd))[rows], want, D).max()
+    assert e <= FP64_TOL, f"crs_sym: {e:.3e}"
+    del S
     # reduced-precision values on the same rows
     for vdt in (torch.float32, torch.bfloat16):
         if vdt == torch.float32:
