@@ -364,8 +364,9 @@ def kernel_source_sha(files):
 
 
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when they are missing or were taken on different kernel sources."""
+    """L2-fill bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on the
+    copy probe) from the committed rocprofv3 counter runs, or None when they
+    are missing or were taken on different kernel sources."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -557,6 +558,8 @@ def roofline_for(name, bytes_per_launch, ms, workload):
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
+            "traffic_kind": "L2-fill bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe calibrated): "
+                            "what the L2s exchange with the MALL and HBM, not HBM bytes alone",
             "algorithmic_bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(ms, 5)}
 
 
