@@ -209,24 +209,44 @@ static int stream_grid(int64_t n, int per_thread)
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // y_i = alpha * (sum of row i's slots, in slot order) + beta * y_i
+// Each wavefront takes 64 consecutive rows, whose slots are one contiguous
+// run of at most SPLIT_PARTS * 64: it loads the run into LDS with coalesced
+// loads (eight per lane, all in flight), then each lane adds its row's slots
+// in order, starting from 0.
 template <typename T>
 __global__ __launch_bounds__(256) void combine_kernel(int32_t n, const int32_t *__restrict__ slot_ptr,
                                                      const double *__restrict__ slots, T *__restrict__ y,
                                                      double alpha, double beta)
 {
-    // one row per lane; a row has at most SPLIT_PARTS slots, all loaded at
-    // once (lanes past their row's last slot load it again and drop the
-    // value), then added in slot order
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t s0 = slot_ptr[i], s1 = slot_ptr[i + 1];
-    double v[SPLIT_PARTS];
+    constexpr int WAVES = 256 / WAVE;
+    __shared__ double buf[WAVES][SPLIT_PARTS * WAVE];
+    const int w = (int)threadIdx.x / WAVE, l = lane_id();
+    const int64_t r0 = ((int64_t)blockIdx.x * WAVES + w) * WAVE;
+    const int64_t i = r0 + l;
+    int32_t s0 = 0, s1 = 0, base = 0, cnt = 0;
+    if (r0 < n) {
+        if (i < n) {
+            s0 = slot_ptr[i];
+            s1 = slot_ptr[i + 1];
+        }
+        base = slot_ptr[r0];
+        cnt = slot_ptr[min(r0 + WAVE, (int64_t)n)] - base;       // <= SPLIT_PARTS * 64
+    }
+    if (cnt > 0) {
+        double v[SPLIT_PARTS];
 #pragma unroll
-    for (int q = 0; q < SPLIT_PARTS; ++q) v[q] = s1 > s0 ? __builtin_nontemporal_load(slots + min(s0 + q, s1 - 1)) : 0.0;
-    double s = 0.0;
+        for (int q = 0; q < SPLIT_PARTS; ++q)
+            v[q] = __builtin_nontemporal_load(slots + base + min(l + q * WAVE, cnt - 1));
 #pragma unroll
-    for (int q = 0; q < SPLIT_PARTS; ++q) s = s0 + q < s1 ? s + v[q] : s;
-    write_y(y, i, s, alpha, beta);
+        for (int q = 0; q < SPLIT_PARTS; ++q)
+            if (l + q * WAVE < cnt) buf[w][l + q * WAVE] = v[q];
+    }
+    __syncthreads();
+    if (i < n) {
+        double s = 0.0;
+        for (int32_t k = s0 - base; k < s1 - base; ++k) s += buf[w][k];
+        write_y(y, i, s, alpha, beta);
+    }
 }
 
 spmv_status launch_combine(int32_t n, const int32_t *slot_ptr, const double *slots, void *y, spmv_dtype vec_dt,
