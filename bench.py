@@ -223,8 +223,8 @@ def bytes_jds(nnz, n, n_cols, ndiag, sv, sx, k=1):
     return nnz * (sv + 4) + 4 * (ndiag + 1) + 4 * n + k * sx * (n_cols + n)
 
 
-def bytes_blocked(nnz, n, n_cols, n_slices, sv, sx):
-    return nnz * (sv + 4) + 12 * n_slices + 4 * n + sx * (n_cols + n)
+def bytes_blocked(nnz, n, n_cols, n_slices, sv, sx, k=1):
+    return nnz * (sv + 4) + 12 * n_slices + 4 * n + k * sx * (n_cols + n)
 
 
 # --------------------------------------------------------------------------- timing
@@ -798,6 +798,10 @@ def suite_spmm(torch, sp, dev, W, steps):
     from paper_0910_4836_amd import autotune
     tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
     out["autotuned_block_nnz"] = {}
+    # blocked JDS over the windowed row order (C = 64), two window sizes: a
+    # window's X rows at k = 32 (FP64: 2 or 8 MB) against one XCD's 4 MB L2
+    wins = {sig: sp.jds_blocked_windowed_from_csr(W["A"], 64, sig) for sig in (8192, 32768)}
+    out["windowed_sigma_ms"] = {}
     for k in (8, 32):
         for dt, sv, tag in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32")):
             A = autotune.tune_spmm_crs(tuner, W["A"] if dt == torch.float64 else W["A32"], k, dt, W["J"].ndiag)
@@ -807,14 +811,26 @@ def suite_spmm(torch, sp, dev, W, steps):
             X.copy_(torch.rand(n, k, dtype=dt, device=dev) * 2 - 1)
             Y = sp.colmajor(n, k, dt, dev)
             ws = sp.spmm_workspace(n, k, dt, dev)
+            wq = {sig: (B if dt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, dt)))
+                  for sig, B in wins.items()}
+            _, pw = time_loop(torch, [(str(sig), (lambda B: lambda: sp.spmm_jds_blocked(B, X, Y, ws=ws))(B))
+                                      for sig, B in wq.items()], max(5, steps // 20), 2)
+            sig = int(min(pw, key=pw.get))
+            out["windowed_sigma_ms"][f"{tag}_k{k}"] = {s_: round(ms, 4) for s_, ms in pw.items()}
+            Bw = wq[sig]
             ks = [(f"spmm_crs_{tag}_k{k}", lambda: sp.spmm_crs(A, X, Y, ws=ws)),
-                  (f"spmm_jds_{tag}_k{k}", lambda: sp.spmm_jds(J, X, Y, ws=ws))]
+                  (f"spmm_jds_{tag}_k{k}", lambda: sp.spmm_jds(J, X, Y, ws=ws)),
+                  (f"spmm_windowed_{tag}_k{k}", lambda: sp.spmm_jds_blocked(Bw, X, Y, ws=ws))]
             _, per = time_loop(torch, ks, max(5, steps // 20), 2)
             out["kernels"][ks[0][0]] = _kernel_entry(ks[0][0], 2.0 * nnz * k, bytes_crs(nnz, n, n, sv, sv, k),
                                                      per[ks[0][0]])
             out["kernels"][ks[1][0]] = _kernel_entry(ks[1][0], 2.0 * nnz * k,
                                                      bytes_jds(nnz, n, n, J.ndiag, sv, sv, k), per[ks[1][0]])
-            del X, Y, ws
+            out["kernels"][ks[2][0]] = _kernel_entry(ks[2][0], 2.0 * nnz * k,
+                                                     bytes_blocked(nnz, n, n, Bw.n_slices, sv, sv, k), per[ks[2][0]])
+            out["kernels"][ks[2][0]]["sigma"] = sig
+            del X, Y, ws, wq
+    del wins
     return out
 
 

@@ -347,6 +347,41 @@ spmv_status spmm_jds(int32_t n, int32_t n_cols, const int32_t *perm, const int32
                      spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
                      spmv_dtype vec_dt, double alpha, double beta, unsigned flags, void *ws,
                      size_t ws_bytes, void *stream);
+/* Multi-vector product over blocked-JDS storage (paper Section 2, RBJDS),
+ * either order: spmv_jds_blocked_from_jds (global length sort) or
+ * spmv_jds_blocked_windowed_from_csr (sorted inside windows of sigma rows,
+ * which keeps the rows an XCD works on neighbours in the original order, so
+ * the X rows that banded entries gather stay in that XCD's L2).  X is staged
+ * row-major into ws as for spmm_crs (ws required, 1 <= k <= 64), then a
+ * group of min(K2, 8) lanes (K2 = k rounded up to a power of two) walks a
+ * row's diagonals (deep slices: several groups per row, and several
+ * wavefronts per row set, each on a contiguous range of diagonals, their
+ * partial sums added in a fixed order); a record of the plan is one
+ * 512-lane workgroup; the records are dealt to the XCDs in contiguous
+ * ranges.  Same arithmetic rules as the other multi-vector forms
+ * (rows of more than SPMV_WIDE_ROW_NNZ entries accumulate in FP64).
+ * spmm_jds_blocked_plan (setup, synchronises) builds the plan on the host
+ * from h_slice_nd for this k: 9 int32 range bounds, then 3 int32 per record
+ * (first row, end row, and the lane groups per row and wavefronts per row
+ * set chosen from the slice depth: groups double up to max_groups (1, 2, 4
+ * or 8; 0 = 1), then wavefronts up to 8, until each lane has about 32
+ * diagonals).  xcd_ranges != 0: range x holds about an eighth of the stored
+ * work, in row order, and runs on XCD x (keeps a windowed order's rows
+ * together); 0: the bounds are -1 and the hardware deals the records to the
+ * XCDs in turn (balances a global length order).  *h_plan_words = the plan's
+ * length, *h_grid = the workgroups to launch.  The plan is written to `plan` when plan_cap >= *h_plan_words,
+ * otherwise SPMV_ERR_CAPACITY with both outputs set (two-call pattern).  It
+ * depends on n, C, the slice depths and k rounded up to a power of two.
+ * perm, C, n_slices, slice_ptr, slice_nd, bl_col, bl_val: the blocked
+ * storage; Y[perm[r], c] receives permuted row r. */
+spmv_status spmm_jds_blocked_plan(int32_t n, int32_t C, int32_t n_slices, const int32_t *h_slice_nd, int32_t k,
+                                  int32_t max_groups, int32_t xcd_ranges, int32_t *plan, int32_t plan_cap,
+                                  int32_t *h_plan_words, int32_t *h_grid, void *stream);
+spmv_status spmm_jds_blocked(int32_t n, int32_t n_cols, const int32_t *perm, int32_t C, int32_t n_slices,
+                             const int64_t *slice_ptr, const int32_t *slice_nd, const int32_t *bl_col,
+                             const void *bl_val, spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y,
+                             int64_t ldy, spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan,
+                             int32_t grid, void *ws, size_t ws_bytes, void *stream);
 
 /* Value gradient of y = A x in JDS storage order:
  * dval[jd_ptr[d]+r] = alpha * g[row(r)] * x[jd_col[jd_ptr[d]+r]] + beta * dval[...]

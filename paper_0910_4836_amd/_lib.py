@@ -76,6 +76,9 @@ SIGNATURES = {
                         _p, _sz, _p]),
     "spmm_jds": (_int, [_i32, _i32, _p, _p, _i32p, _i32, _p, _p, _int, _i32, _p, _i64, _p, _i64, _int, _f64, _f64,
                         _u32, _p, _sz, _p]),
+    "spmm_jds_blocked_plan": (_int, [_i32, _i32, _i32, _i32p, _i32, _i32, _i32, _p, _i32, _i32p, _i32p, _p]),
+    "spmm_jds_blocked": (_int, [_i32, _i32, _p, _i32, _i32, _p, _p, _p, _p, _int, _i32, _p, _i64, _p, _i64, _int,
+                                _f64, _f64, _p, _i32, _p, _sz, _p]),
     "spmv_grad_vals_jds": (_int, [_i32, _p, _p, _i32p, _i32, _i64, _p, _p, _p, _p, _int, _f64, _f64, _u32, _p]),
     "spmv_split_columns_workspace_size": (_sz, [_i32, _i64]),
     "spmv_split_columns": (_int, [_i32, _i32, _i64, _p, _p, _p, _int, _i32, _p, _p, _p, _p, _p, _i64p, _i64p, _p, _sz,

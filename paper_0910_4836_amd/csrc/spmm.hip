@@ -533,6 +533,221 @@ __global__ __launch_bounds__(NT) void spmm_jds_il_kernel(int32_t ndiag, const in
     }
 }
 
+// Blocked JDS (RBJDS slices, in the global or the windowed row order),
+// interleaved X.  A workgroup of MM_BLK_THREADS lanes is one plan record
+// (first row, S, D).  A row is served by D groups of LPR lanes (lane j of a
+// group owns columns j, j + LPR, ...; the D groups take every D-th diagonal),
+// so a wavefront holds RW = 64 / (LPR * D) consecutive rows (RW divides the
+// slice height: a wavefront's rows share a slice); the workgroup's (8/S) row
+// sets each get S wavefronts, which cut the slice's diagonals into S
+// contiguous ranges.  Partial sums meet by a fixed shuffle tree over the D
+// groups, then in LDS in range order.  Rows of a slice are sorted by
+// decreasing length, so a wavefront stops, as a whole, where its first row's
+// entries end (padding has col = -1).  Deep slices get larger D and S, so no
+// lane walks more than about MM_BLK_DIAGS diagonals.
+constexpr int MM_BLK_THREADS = 512;
+constexpr int MM_BLK_WAVES = MM_BLK_THREADS / WAVE;
+constexpr int MM_BLK_DIAGS = 32;           // target diagonals per lane
+constexpr int MM_BLK_MAX_D = 8;
+constexpr int MM_BLK_XCDS = 8;             // MI355X: workgroup b runs on XCD b % 8
+
+template <int K2, typename VT, typename XT>
+__global__ __launch_bounds__(MM_BLK_THREADS) void spmm_blk_il_kernel(
+    int32_t n, const int32_t *__restrict__ perm, int32_t C, const int64_t *__restrict__ slice_ptr,
+    const int32_t *__restrict__ slice_nd, const int32_t *__restrict__ col, const VT *__restrict__ val,
+    const XT *__restrict__ Xr, int32_t k, XT *__restrict__ Y, int64_t ldy, const int32_t *__restrict__ recs,
+    double alpha, double beta)
+{
+    constexpr int LPR = mm_jds_lpr<K2, XT>();
+    constexpr int CPL = K2 / LPR;
+    constexpr bool F64 = IsF64<VT>::value;
+    constexpr int U = 2;
+    __shared__ double part[MM_BLK_WAVES][CPL][WAVE];
+    // ranged plan (recs[0] >= 0): workgroup b runs on XCD b % 8 and takes
+    // the (b / 8)-th record of that XCD's range (ranges of equal stored work,
+    // in row order); otherwise workgroup b takes record b (the hardware deals
+    // consecutive workgroups to the XCDs in turn)
+    int64_t ri = blockIdx.x;
+    if (recs[0] >= 0) {
+        const int xcd = (int)(blockIdx.x % MM_BLK_XCDS);
+        const int32_t lo = recs[xcd], hi = recs[xcd + 1];
+        ri = (int64_t)lo + blockIdx.x / MM_BLK_XCDS;
+        if (ri >= hi) return;                      // the whole workgroup: no barrier is reached
+    }
+    const int32_t *rec = recs + (MM_BLK_XCDS + 1) + 3 * ri;
+    const int32_t first = rec[0], last = rec[1], sd = rec[2];
+    const int S = sd & 0xff, D = sd >> 8;
+    const int RW = WAVE / (LPR * D);
+    const int w = (int)threadIdx.x / WAVE, lane = lane_id();
+    const int g = w / S, p = w % S;
+    const int j = lane % LPR, dl = (lane / LPR) % D, gl = lane / (LPR * D);
+    const int64_t row0l = (int64_t)first + (int64_t)g * RW;
+    const bool valid = row0l < last;
+    const int32_t row0 = valid ? (int32_t)row0l : 0;
+    const int32_t r = row0 + gl;
+    const bool ok = valid && r < last;
+    const int32_t sl = row0 / C;
+    const int64_t sp = slice_ptr[sl];
+    const int32_t nd = valid ? slice_nd[sl] : 0;
+    const int32_t rs = r - sl * C;
+    // rows of more than SPMV_WIDE_ROW_NNZ entries accumulate in FP64 (their
+    // length found by a binary search of the padding, only in such slices)
+    bool wide = false;
+    if (!F64 && ok && nd > SPMV_WIDE_ROW_NNZ) {
+        int32_t lo = 0, hi = nd;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (col[sp + (int64_t)mid * C + rs] >= 0) lo = mid + 1;
+            else hi = mid;
+        }
+        wide = lo > SPMV_WIDE_ROW_NNZ;
+    }
+    const int32_t dA = (int32_t)((int64_t)p * nd / S), dB = (int32_t)((int64_t)(p + 1) * nd / S);
+    double td[CPL];
+    auto walk = [&](auto acc_tag) {
+        typedef decltype(acc_tag) acc_t;
+        constexpr bool WD = sizeof(acc_t) == 8;
+        acc_t sacc[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) sacc[t] = 0;
+        for (int32_t d0 = dA; d0 < dB; d0 += U * D) {
+            int32_t c[U];
+            VT v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                // in bounds for every lane of a wavefront that runs the loop:
+                // d < nd and 0 <= rs < C address its slice's storage
+                const int32_t du = d0 + u * D + dl;
+                const int32_t d = min(du, dB - 1);
+                const int64_t e = sp + (int64_t)d * C + rs;
+                c[u] = ld_stream(col + e);
+                v[u] = ld_stream(val + e);
+                c[u] = (ok && du < dB) ? c[u] : -1;
+            }
+            // the first row of the wavefront is its longest: once it has no
+            // entry at d0 (lane 0's first load), no row of the wavefront has
+            // one at any later diagonal
+            if (__builtin_amdgcn_readfirstlane(c[0]) < 0) break;
+            XT xv[U][CPL];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int t = 0; t < CPL; ++t)
+                    xv[u][t] = (c[u] >= 0 && t * LPR + j < k) ? Xr[(int64_t)c[u] * k + t * LPR + j] : XT(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (c[u] >= 0) {
+#pragma unroll
+                    for (int t = 0; t < CPL; ++t) sacc[t] = Acc<WD>::mac(sacc[t], v[u], xv[u][t]);
+                }
+        }
+        // the D groups of a row: fixed xor tree over the group index
+        for (int off = LPR; off < LPR * D; off <<= 1)
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) sacc[t] += __shfl_xor(sacc[t], off, WAVE);
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) td[t] = (double)sacc[t];
+    };
+    if (F64 || wide) walk(0.0);
+    else walk(0.0f);
+    if (S > 1) {
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) part[w][t][lane] = td[t];
+        __syncthreads();
+        if (p == 0 && ok && dl == 0) {
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                if (F64 || wide) {
+                    double a = 0.0;
+                    for (int q = 0; q < S; ++q) a += part[w + q][t][lane];
+                    td[t] = a;
+                } else {
+                    float a = 0.0f;
+                    for (int q = 0; q < S; ++q) a += (float)part[w + q][t][lane];
+                    td[t] = (double)a;
+                }
+            }
+        }
+    }
+    if (p == 0 && ok && dl == 0) {
+        const int32_t yi = perm[r];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t)
+            if (t * LPR + j < k) write_y(Y + (int64_t)(t * LPR + j) * ldy, yi, td[t], alpha, beta);
+    }
+}
+
+// Records (first row, end row, S | D << 8).  Each slice's depth sets its
+// (D, S): D doubles up to min(MM_BLK_MAX_D, 64 / LPR), then S up to 8, until
+// D * S * MM_BLK_DIAGS reaches the depth.  A run of consecutive slices with
+// the same (D, S) is cut into records of (8/S) * 64 / (LPR * D) rows from the
+// run's first row (a slice start), so every wavefront's rows start at a
+// multiple of its row count and stay inside one slice; the run's last record
+// ends with the run.
+static void plan_mm_blk(int32_t n, int32_t C, int32_t n_slices, const int32_t *h_slice_nd, int LPR, int max_groups,
+                        std::vector<int32_t> &out)
+{
+    const int dmax = std::min(max_groups, WAVE / LPR);
+    auto ds_of = [&](int32_t nd) {
+        int D = 1, S = 1;
+        while ((int64_t)D * S * MM_BLK_DIAGS < nd) {
+            if (D < dmax) D *= 2;
+            else if (S < MM_BLK_WAVES) S *= 2;
+            else break;
+        }
+        return S | (D << 8);
+    };
+    out.clear();
+    for (int32_t s0 = 0; s0 < n_slices;) {
+        const int sd = ds_of(h_slice_nd[s0]);
+        int32_t s1 = s0 + 1;
+        while (s1 < n_slices && ds_of(h_slice_nd[s1]) == sd) ++s1;
+        const int S = sd & 0xff, D = sd >> 8;
+        const int64_t rows = (int64_t)(MM_BLK_WAVES / S) * (WAVE / (LPR * D));
+        const int64_t end = std::min<int64_t>(n, (int64_t)s1 * C);
+        for (int64_t row = (int64_t)s0 * C; row < end; row += rows) {
+            out.push_back((int32_t)row);
+            out.push_back((int32_t)std::min<int64_t>(end, row + rows));
+            out.push_back(sd);
+        }
+        s0 = s1;
+    }
+}
+
+// Plan words: MM_BLK_XCDS + 1 range bounds, then the records.  Ranged: the
+// bounds are record indices, range x (run on XCD x) holding about an eighth
+// of the stored work (rows times their slice's depth), and the grid is
+// MM_BLK_XCDS times the longest range.  Not ranged: the bounds are -1 and
+// the grid is the record count.
+static int64_t plan_mm_blk_words(int32_t n, int32_t C, int32_t n_slices, const int32_t *h_slice_nd, int LPR,
+                                 int max_groups, bool ranged, std::vector<int32_t> &words)
+{
+    std::vector<int32_t> recs;
+    plan_mm_blk(n, C, n_slices, h_slice_nd, LPR, max_groups, recs);
+    const int64_t nr = (int64_t)recs.size() / 3;
+    if (!ranged) {
+        words.assign(MM_BLK_XCDS + 1, -1);
+        words.insert(words.end(), recs.begin(), recs.end());
+        return nr;
+    }
+    std::vector<int64_t> pre((size_t)nr + 1, 0);
+    for (int64_t i = 0; i < nr; ++i) {
+        const int64_t rows = recs[3 * i + 1] - recs[3 * i];
+        pre[i + 1] = pre[i] + rows * std::max<int64_t>(1, h_slice_nd[recs[3 * i] / C]);
+    }
+    words.assign(MM_BLK_XCDS + 1, 0);
+    int64_t longest = 0;
+    for (int x = 1; x <= MM_BLK_XCDS; ++x) {
+        const int64_t target = (pre[nr] * x + MM_BLK_XCDS - 1) / MM_BLK_XCDS;
+        words[x] = x == MM_BLK_XCDS ? (int32_t)nr
+                                    : (int32_t)(std::lower_bound(pre.begin(), pre.end(), target) - pre.begin());
+        words[x] = std::max(words[x], words[x - 1]);
+        longest = std::max<int64_t>(longest, words[x] - words[x - 1]);
+    }
+    words.insert(words.end(), recs.begin(), recs.end());
+    return longest * MM_BLK_XCDS;
+}
+
 static int k2_for(int32_t k)
 {
     int K2 = 1;
@@ -631,6 +846,16 @@ static void launch_jds_il(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, con
     const size_t lds = sizeof(int32_t) * (size_t)std::min<int64_t>((int64_t)ndiag + 1, MM_JP_LDS);
     spmm_jds_il_kernel<K2, NT, VT, XT><<<(unsigned)P.c[P.ncls - 1].wg_end, NT, lds, s>>>(
         ndiag, jp, perm, symperm, col, (const VT *)val, (const XT *)Xr, k, (XT *)Y, ldy, P, alpha, beta);
+}
+
+template <int K2, typename VT, typename XT>
+static void launch_blk_il(int32_t n, const int32_t *perm, int32_t C, const int64_t *slice_ptr,
+                          const int32_t *slice_nd, const int32_t *col, const void *val, const void *Xr, int32_t k,
+                          void *Y, int64_t ldy, const int32_t *recs, int32_t grid, double alpha, double beta,
+                          hipStream_t s)
+{
+    spmm_blk_il_kernel<K2, VT, XT><<<(unsigned)grid, MM_BLK_THREADS, 0, s>>>(
+        n, perm, C, slice_ptr, slice_nd, col, (const VT *)val, (const XT *)Xr, k, (XT *)Y, ldy, recs, alpha, beta);
 }
 
 #define K2_SWITCH(K2VAR, CALL)          \
@@ -738,6 +963,71 @@ spmv_status spmm_jds(int32_t n, int32_t n_cols, const int32_t *perm, const int32
     JDS_IL(SPMV_F64, double, SPMV_F32, float)
 #undef JDS_IL
     return fail(SPMV_ERR_UNSUPPORTED, "spmm_jds: dtype combination");
+}
+
+spmv_status spmm_jds_blocked_plan(int32_t n, int32_t C, int32_t n_slices, const int32_t *h_slice_nd, int32_t k,
+                                  int32_t max_groups, int32_t xcd_ranges, int32_t *plan, int32_t plan_cap,
+                                  int32_t *h_plan_words, int32_t *h_grid, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && k >= 1 && k <= MM_MAX_K2, "spmm_jds_blocked_plan: n < 0 or k outside [1, 64]");
+    if (max_groups == 0) max_groups = 1;
+    SPMV_REQUIRE(max_groups == 1 || max_groups == 2 || max_groups == 4 || max_groups == 8,
+                 "spmm_jds_blocked_plan: max_groups must be 1, 2, 4 or 8");
+    SPMV_REQUIRE(C >= WAVE && C % WAVE == 0, "spmm_jds_blocked_plan: C must be a positive multiple of 64");
+    SPMV_REQUIRE(n_slices == (int32_t)ceil_div(n, C), "spmm_jds_blocked_plan: n_slices != ceil(n / C)");
+    SPMV_REQUIRE(h_plan_words && h_grid && (n == 0 || h_slice_nd), "spmm_jds_blocked_plan: null pointer");
+    const int K2v = k2_for(k);
+    const int LPR = K2v <= 8 ? K2v : 8;             // mm_jds_lpr
+    std::vector<int32_t> words;
+    const int64_t grid = plan_mm_blk_words(n, C, n_slices, h_slice_nd, LPR, max_groups, xcd_ranges != 0, words);
+    SPMV_REQUIRE(grid <= INT32_MAX, "spmm_jds_blocked_plan: too many records");
+    *h_plan_words = (int32_t)words.size();
+    *h_grid = (int32_t)grid;
+    if (!plan || plan_cap < (int32_t)words.size())
+        return fail(SPMV_ERR_CAPACITY, "spmm_jds_blocked_plan: plan capacity < *h_plan_words");
+    hipStream_t s = as_stream(stream);
+    SPMV_HIP(hipMemcpyAsync(plan, words.data(), sizeof(int32_t) * words.size(), hipMemcpyHostToDevice, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+spmv_status spmm_jds_blocked(int32_t n, int32_t n_cols, const int32_t *perm, int32_t C, int32_t n_slices,
+                             const int64_t *slice_ptr, const int32_t *slice_nd, const int32_t *bl_col,
+                             const void *bl_val, spmv_dtype val_dt, int32_t k, const void *X, int64_t ldx, void *Y,
+                             int64_t ldy, spmv_dtype vec_dt, double alpha, double beta, const int32_t *plan,
+                             int32_t grid, void *ws, size_t ws_bytes, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && n_cols >= 0 && k >= 0 && grid >= 0, "spmm_jds_blocked: negative size");
+    SPMV_REQUIRE(k <= MM_MAX_K2, "spmm_jds_blocked: k > 64");
+    SPMV_REQUIRE(C >= WAVE && C % WAVE == 0, "spmm_jds_blocked: C must be a positive multiple of 64");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmm_jds_blocked: bad dtype");
+    if (n == 0 || k == 0) return SPMV_OK;
+    SPMV_REQUIRE(ldx >= n_cols && ldy >= n, "spmm_jds_blocked: leading dimension too small");
+    SPMV_REQUIRE(n_slices == (int32_t)ceil_div(n, C), "spmm_jds_blocked: n_slices != ceil(n / C)");
+    SPMV_REQUIRE(perm && slice_ptr && slice_nd && Y && plan && X, "spmm_jds_blocked: null pointer");
+    SPMV_REQUIRE(ws && ws_bytes >= spmm_workspace_size(n_cols, k, vec_dt), "spmm_jds_blocked: workspace too small");
+    hipStream_t s = as_stream(stream);
+    const void *Xr = nullptr;
+    spmv_status st = vec_dt == SPMV_F64 ? stage<double>(n_cols, k, X, ldx, ws, &Xr, s)
+                                        : stage<float>(n_cols, k, X, ldx, ws, &Xr, s);
+    if (st != SPMV_OK) return st;
+    if (grid == 0) return SPMV_OK;
+    const int K2v = k2_for(k);
+#define BLK_IL(VDT, VT, XDT, XT)                                                                                 \
+    if (val_dt == VDT && vec_dt == XDT) {                                                                        \
+        K2_SWITCH(K2v, (launch_blk_il<K2, VT, XT>(n, perm, C, slice_ptr, slice_nd, bl_col, bl_val, Xr, k, Y, ldy,  \
+                                                  plan, grid, alpha, beta, s)));                                 \
+        SPMV_CHECK_LAUNCH("spmm_jds_blocked");                                                                   \
+        return SPMV_OK;                                                                                          \
+    }
+    BLK_IL(SPMV_F64, double, SPMV_F64, double)
+    BLK_IL(SPMV_F32, float, SPMV_F32, float)
+    BLK_IL(SPMV_F32, float, SPMV_F64, double)
+    BLK_IL(SPMV_BF16, bf16, SPMV_F32, float)
+    BLK_IL(SPMV_BF16, bf16, SPMV_F64, double)
+    BLK_IL(SPMV_F64, double, SPMV_F32, float)
+#undef BLK_IL
+    return fail(SPMV_ERR_UNSUPPORTED, "spmm_jds_blocked: dtype combination");
 }
 
 }  // extern "C"

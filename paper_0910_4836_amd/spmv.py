@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import ctypes as C
 from dataclasses import dataclass, field
-from typing import Optional
+from typing import Optional, Tuple
 
 import numpy as np
 import torch
@@ -471,6 +471,57 @@ def spmm_jds(J: JDS, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: f
          _p(J.jd_val), dtype_code(J.jd_val.dtype), k, _p(X), _ld(X, J.n_cols), _p(Y), _ld(Y, J.n), dtype_code(X.dtype),
          float(alpha), float(beta), J.flags, _p(ws) if interleave else None,
          ws.numel() if (interleave and ws is not None) else 0, _stream())
+    return Y
+
+
+def spmm_jds_blocked_plan(B: Blocked, k: int, max_groups: int = 0,
+                          xcd_ranges: Optional[bool] = None) -> Tuple[torch.Tensor, int]:
+    """Plan of spmm_jds_blocked for k vectors and its grid size (cached on B
+    per k rounded up to a power of two and the two launch choices).
+    Defaults, measured on the power-law matrix at k = 8 and 32: the windowed
+    order takes up to 4 lane groups per row and XCD ranges of equal work
+    (its rows stay together); the global order one group per row, records
+    dealt to the XCDs in turn (its deep slices spread over all of them)."""
+    K2 = 1
+    while K2 < k and K2 < 64:
+        K2 *= 2
+    if xcd_ranges is None:
+        xcd_ranges = B.sigma > 0
+    if max_groups == 0:
+        max_groups = 4 if B.sigma > 0 else 1
+    key = ("spmm", K2, max_groups, bool(xcd_ranges))
+    if key not in B.tile_plans:
+        words, grid = C.c_int32(0), C.c_int32(0)
+        args = lambda pl, cap: (B.n, B.C, B.n_slices, _h_i32(B.h_slice_nd), K2, max_groups, int(bool(xcd_ranges)),
+                                pl, cap, C.byref(words), C.byref(grid), _stream())
+        st = _lib.load().spmm_jds_blocked_plan(*args(None, 0))
+        if st not in (0, 3):
+            call("spmm_jds_blocked_plan", *args(None, 0))
+        plan = torch.empty(max(words.value, 1), dtype=_I32, device=B.perm.device)
+        call("spmm_jds_blocked_plan", *args(_p(plan), plan.numel()))
+        B.tile_plans[key] = (plan, grid.value)
+    return B.tile_plans[key]
+
+
+def spmm_jds_blocked(B: Blocked, X: torch.Tensor, Y: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                     beta: float = 0.0, ws: Optional[torch.Tensor] = None, max_groups: int = 0,
+                     xcd_ranges: Optional[bool] = None) -> torch.Tensor:
+    """Y = alpha*A X + beta*Y over blocked-JDS storage, global or windowed
+    order (spmm_jds_blocked; X staged row-major in ws, 1 <= k <= 64)."""
+    if B.symperm:
+        raise ValueError("spmm_jds_blocked: symmetric-permutation storage is not supported")
+    _check_blocks(X, Y, B.n, B.n_cols)
+    k = X.shape[1]
+    if not 1 <= k <= 64:
+        raise ValueError("spmm_jds_blocked: k must be in [1, 64]")
+    if Y is None:
+        Y = colmajor(B.n, k, X.dtype, X.device)
+    if ws is None:
+        ws = spmm_workspace(B.n_cols, k, X.dtype, X.device)
+    plan, grid = spmm_jds_blocked_plan(B, k, max_groups, xcd_ranges)
+    call("spmm_jds_blocked", B.n, B.n_cols, _p(B.perm), B.C, B.n_slices, _p(B.slice_ptr), _p(B.slice_nd),
+         _p(B.bl_col), _p(B.bl_val), dtype_code(B.bl_val.dtype), k, _p(X), _ld(X, B.n_cols), _p(Y), _ld(Y, B.n),
+         dtype_code(X.dtype), float(alpha), float(beta), _p(plan), grid, _p(ws), ws.numel(), _stream())
     return Y
 
 

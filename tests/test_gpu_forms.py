@@ -370,3 +370,96 @@ def test_autotuner_batched_and_cache(tmp_path):
         assert oracle.rel_err(Y[:, j], want_X[:, j], oracle.row_absdot(R, X[:, j])).max() <= FP64_TOL
     t4 = autotune.Autotuner(cache)
     assert autotune.tune_spmm_crs(t4, A, 8, torch.float64, J.ndiag).block_nnz == Am.block_nnz and not t4.log
+
+
+# ---- multi-vector products over blocked-JDS storage (global and windowed row order)
+
+
+def _blocked_storages(A):
+    """Blocked JDS at C = 64 and 256 (global length order) and windowed at
+    C = 64 with windows of 512 and 4096 rows (square matrices only)."""
+    J = sp.jds_from_csr(A)
+    out = [("blocked_c64", sp.jds_blocked_from_jds(J, 64)), ("blocked_c256", sp.jds_blocked_from_jds(J, 256))]
+    if A.n_rows == A.n_cols:
+        out += [("windowed_s512", sp.jds_blocked_windowed_from_csr(A, 64, 512)),
+                ("windowed_s4096", sp.jds_blocked_windowed_from_csr(A, 64, 4096))]
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 11, 32, 40, 64])
+def test_spmm_jds_blocked_fp64(k):
+    r, c, v, n, _, rng = rand_coo(160 + k, 6000, 6000, 0.002, empty_rows=0.1, long_rows=6, long_len=2000)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    X = rng.uniform(-1, 1, (n, k))
+    Y0 = rng.uniform(-1, 1, (n, k))
+    want = oracle.spmm_crs(R, X, alpha=1.5, beta=-0.5, Y=Y0)
+    A = gpu_csr(sp, r, c, v, n, n)
+    Xd = colmajor_from(X, torch.float64)
+    # both launch choices: lane groups per row (1 or up to 8) and records
+    # dealt to XCD ranges of equal work or in turn
+    for name, B in _blocked_storages(A):
+        for mg, xr in ((0, None), (1, True), (8, False), (8, True)):
+            got = to_np(sp.spmm_jds_blocked(B, Xd, colmajor_from(Y0, torch.float64), 1.5, -0.5, max_groups=mg,
+                                            xcd_ranges=xr))
+            for j in range(k):
+                D = 1.5 * oracle.row_absdot(R, X[:, j]) + 0.5 * np.abs(Y0[:, j])
+                e = oracle.rel_err(got[:, j], want[:, j], D).max()
+                assert e <= FP64_TOL, (name, mg, xr, j, e)
+
+
+def test_spmm_jds_blocked_rectangular_and_integer_exact():
+    # rectangular, integer values, a row of 4,500 entries (FP64 accumulation
+    # for reduced-precision values), every k from the single to the widest
+    r, c, v, nr, nc, rng = rand_coo(171, 3000, 7000, 0.003, integer=True, empty_rows=0.2)
+    rr = np.concatenate([r, np.full(4500, 11, np.int32)])
+    cc = np.concatenate([c, rng.choice(nc, 4500, replace=False).astype(np.int32)])
+    vv = np.concatenate([v, rng.integers(-8, 9, 4500).astype(np.float64)])
+    R = oracle.csr_from_coo(nr, nc, rr, cc, vv)
+    A = gpu_csr(sp, rr, cc, vv, nr, nc)
+    for name, B in _blocked_storages(A):
+        for vdt, xdt in ((torch.float64, torch.float64), (torch.float32, torch.float32),
+                         (torch.bfloat16, torch.float64)):
+            Bq = B if vdt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
+            for k in (1, 5, 16, 64):
+                X = rng.integers(-8, 9, (nc, k)).astype(np.float64)
+                got = to_np(sp.spmm_jds_blocked(Bq, colmajor_from(X, xdt)))
+                assert np.array_equal(got.astype(np.float64), oracle.spmm_crs(R, X)), (name, str(vdt), k)
+
+
+@pytest.mark.parametrize("vdt,xdt", _PAIRS, ids=[f"{str(a)[6:]}-{str(b)[6:]}" for a, b in _PAIRS])
+def test_spmm_jds_blocked_every_dtype_pair(mixed_spmm_matrix, vdt, xdt):
+    """The single-vector bound on rounded inputs (see test_spmm_every_dtype_pair),
+    for the blocked storages in both row orders (square part of the matrix)."""
+    r0, c0, v0, nr, nc0, rng = mixed_spmm_matrix
+    keep = c0 < nr
+    # the rectangular matrix (rows of 4,500 entries: FP64 accumulation for
+    # reduced values; global order only) and its square part (both orders)
+    for r, c, v, nc in ((r0, c0, v0, nc0), (r0[keep], c0[keep], v0[keep], nr)):
+        _check_blocked_pair(r, c, v, nr, nc, rng, vdt, xdt)
+
+
+def _check_blocked_pair(r, c, v, nr, nc, rng, vdt, xdt):
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    if vdt == torch.float64:
+        vq = R.val
+    elif vdt == torch.float32:
+        vq = oracle.round_f32(R.val).astype(np.float64)
+    else:
+        vq = oracle.bf16_bits_to_f64(oracle.round_bf16_bits(R.val))
+    Rq = oracle.CSR(nr, nc, R.row_ptr, R.col, vq)
+    L = R.row_lengths()
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    for name, B in _blocked_storages(A):
+        Bq = B if vdt == torch.float64 else B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
+        for k in (3, 8, 32, 64):
+            X = rng.uniform(-1, 1, (nc, k))
+            if xdt == torch.float32:
+                X = X.astype(np.float32).astype(np.float64)
+            want = oracle.spmm_crs(Rq, X)
+            wide = (L > 4096) | (vdt == torch.float64)
+            u = np.where(wide, gamma(L + 1, U64), gamma(L + 1, U32)) + (U32 if xdt == torch.float32 else 0.0)
+            got = to_np(sp.spmm_jds_blocked(Bq, colmajor_from(X, xdt)))
+            for j in range(k):
+                D = oracle.row_absdot(Rq, X[:, j])
+                err = np.abs(got[:, j].astype(np.float64) - want[:, j])
+                assert np.all(err <= u * D), (name, k, j, float(np.max(err / np.maximum(u * D, 1e-300))))
