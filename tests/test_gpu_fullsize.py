@@ -152,11 +152,17 @@ def test_powerlaw_multi_vector_sampled(powerlaw):
     J = sp.jds_from_csr(A)
     # the plan bench.py times for the multi-vector CRS product (256-entry blocks)
     A256 = sp.spmv_crs_plan(sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), 256)
+    # and the blocked-JDS multi-vector product in both row orders (the window
+    # sizes the suite line times; the global order with its launch default)
+    B = sp.jds_blocked_from_jds(J, 64)
+    wins = {sig: sp.jds_blocked_windowed_from_csr(A, 64, sig) for sig in (8192, 32768)}
     for k in (8, 32):
         X = np.random.default_rng(k).uniform(-1, 1, (n, k))
         Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda").t()
         for name, fn in (("crs", lambda: sp.spmm_crs(A, Xd)), ("crs_b256", lambda: sp.spmm_crs(A256, Xd)),
-                         ("jds", lambda: sp.spmm_jds(J, Xd))):
+                         ("jds", lambda: sp.spmm_jds(J, Xd)), ("blocked", lambda: sp.spmm_jds_blocked(B, Xd)),
+                         ("windowed_8192", lambda: sp.spmm_jds_blocked(wins[8192], Xd)),
+                         ("windowed_32768", lambda: sp.spmm_jds_blocked(wins[32768], Xd))):
             Y = to_np(fn())
             for j in (0, k // 2, k - 1):
                 want = oracle.spmv_crs(sub, X[:, j])
