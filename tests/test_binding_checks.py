@@ -33,6 +33,12 @@ def dia():
     return S.DIA(N_ROWS, N_COLS, np.zeros(1, np.int32), torch.zeros(N_ROWS, dtype=torch.float64), csr())
 
 
+def blocked():
+    return S.Blocked(N_ROWS, N_COLS, 64, torch.arange(N_ROWS, dtype=torch.int32), torch.zeros(2, dtype=torch.int64),
+                     torch.zeros(1, dtype=torch.int32), np.zeros(1, np.int32), torch.zeros(1, dtype=torch.int32),
+                     torch.zeros(1, dtype=torch.float64), 0)
+
+
 def single_vector_calls():
     A, J, D = csr(), jds(), dia()
     return {
@@ -40,6 +46,20 @@ def single_vector_calls():
         "spmv_jds": lambda x, y: S.spmv_jds(J, x, y),
         "spmv_dia": lambda x, y: S.spmv_dia(D, x, y),
     }
+
+
+def test_one_triangle_checks_before_launch():
+    """The one-triangle product takes FP64 vectors only and square storage."""
+    U = S.SymCSR(S.CSR(N_ROWS, N_ROWS, torch.zeros(N_ROWS + 1, dtype=torch.int32), torch.zeros(0, dtype=torch.int32),
+                       torch.zeros(0, dtype=torch.float64)))
+    with pytest.raises(TypeError, match="float64"):
+        S.spmv_crs_sym(U, torch.zeros(N_ROWS, dtype=torch.float32))
+    with pytest.raises(ValueError, match="y has 5 elements"):
+        S.spmv_crs_sym(U, torch.zeros(N_ROWS, dtype=torch.float64), torch.zeros(N_ROWS - 1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="must live on the GPU"):
+        S.spmv_crs_sym(U, torch.zeros(N_ROWS, dtype=torch.float64))
+    with pytest.raises(ValueError, match="square"):
+        S.csr_upper_from_csr(csr())
 
 
 @pytest.mark.parametrize("name", ["spmv_crs", "spmv_jds", "spmv_dia"])
@@ -61,10 +81,11 @@ def test_vector_mismatches_raise_before_launch(name):
         fn(x, torch.zeros(N_ROWS, dtype=torch.float64))
 
 
-@pytest.mark.parametrize("name", ["spmm_crs", "spmm_jds"])
+@pytest.mark.parametrize("name", ["spmm_crs", "spmm_jds", "spmm_jds_blocked"])
 def test_block_mismatches_raise_before_launch(name):
-    A, J = csr(), jds()
-    fn = {"spmm_crs": lambda X, Y: S.spmm_crs(A, X, Y), "spmm_jds": lambda X, Y: S.spmm_jds(J, X, Y)}[name]
+    A, J, B = csr(), jds(), blocked()
+    fn = {"spmm_crs": lambda X, Y: S.spmm_crs(A, X, Y), "spmm_jds": lambda X, Y: S.spmm_jds(J, X, Y),
+          "spmm_jds_blocked": lambda X, Y: S.spmm_jds_blocked(B, X, Y)}[name]
     k = 3
     X = torch.zeros(k, N_COLS, dtype=torch.float64).t()           # column-major (n_cols, k)
     with pytest.raises(ValueError, match="Y is torch.float32 but X is torch.float64"):
@@ -88,3 +109,10 @@ def test_int32_is_a_payload_dtype_only():
     assert S.dtype_code(torch.int32) == 3
     with pytest.raises(TypeError):
         S.dtype_code(torch.int64)
+
+
+def test_blocked_multi_vector_refuses_symmetric_permutation():
+    B = blocked()
+    B.symperm = True
+    with pytest.raises(ValueError, match="symmetric-permutation"):
+        S.spmm_jds_blocked(B, torch.zeros(3, N_COLS, dtype=torch.float64).t())
