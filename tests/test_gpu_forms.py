@@ -463,3 +463,31 @@ def _check_blocked_pair(r, c, v, nr, nc, rng, vdt, xdt):
                 D = oracle.row_absdot(Rq, X[:, j])
                 err = np.abs(got[:, j].astype(np.float64) - want[:, j])
                 assert np.all(err <= u * D), (name, k, j, float(np.max(err / np.maximum(u * D, 1e-300))))
+
+
+def test_spmm_jds_blocked_edge_cases():
+    """A matrix smaller than one slice, a matrix of empty rows (beta*Y only,
+    NaN in Y ignored at beta = 0), and n = 0 / k = 0 calls that launch nothing."""
+    rng = np.random.default_rng(181)
+    # 40 rows: one partial slice of the 64-row height
+    r, c, v, n, _, _ = rand_coo(182, 40, 40, 0.2, empty_rows=0.2)
+    R = oracle.csr_from_coo(n, n, r, c, v)
+    A = gpu_csr(sp, r, c, v, n, n)
+    for name, B in _blocked_storages(A):
+        for k in (1, 6, 33):
+            X = rng.uniform(-1, 1, (n, k))
+            got = to_np(sp.spmm_jds_blocked(B, colmajor_from(X, torch.float64)))
+            want = oracle.spmm_crs(R, X)
+            for j in range(k):
+                assert oracle.rel_err(got[:, j], want[:, j], oracle.row_absdot(R, X[:, j])).max() <= FP64_TOL, name
+    # every row empty
+    n = 300
+    E = sp.CSR(n, n, torch.zeros(n + 1, dtype=torch.int32, device="cuda"),
+               torch.zeros(0, dtype=torch.int32, device="cuda"), torch.zeros(0, dtype=torch.float64, device="cuda"))
+    for name, B in _blocked_storages(E):
+        X = colmajor_from(rng.uniform(-1, 1, (n, 4)), torch.float64)
+        Y0 = rng.uniform(-1, 1, (n, 4))
+        got = to_np(sp.spmm_jds_blocked(B, X, colmajor_from(Y0, torch.float64), 1.0, 0.5))
+        assert np.array_equal(got, 0.5 * Y0), name
+        Yn = colmajor_from(np.full((n, 4), np.nan), torch.float64)
+        assert np.array_equal(to_np(sp.spmm_jds_blocked(B, X, Yn, 1.0, 0.0)), np.zeros((n, 4))), name
