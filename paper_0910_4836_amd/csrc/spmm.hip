@@ -561,7 +561,7 @@ __global__ __launch_bounds__(MM_BLK_THREADS) void spmm_blk_il_kernel(
     constexpr int LPR = mm_jds_lpr<K2, XT>();
     constexpr int CPL = K2 / LPR;
     constexpr bool F64 = IsF64<VT>::value;
-    constexpr int U = 2;
+    constexpr int U = CPL == 1 ? 4 : 2;     // diagonals per trip: 4 measured 5-14% faster at k <= 8, 2 at k = 32
     __shared__ double part[MM_BLK_WAVES][CPL][WAVE];
     // ranged plan (recs[0] >= 0): workgroup b runs on XCD b % 8 and takes
     // the (b / 8)-th record of that XCD's range (ranges of equal stored work,
