@@ -615,14 +615,92 @@ __device__ __forceinline__ int32_t prev_clear(const uint32_t *taken, int32_t bel
     return (w << 5) + 31 - __clz(m);
 }
 
+// The same greedy rule with one wavefront per slice, for slices whose first
+// row has at most SOJDS_LDS_CAP entries: the current row's columns (placed
+// entries overwritten by a marker) and the previous row's slot columns live
+// in LDS; for each slot the 64 lanes scan the row's unused entries (lane l:
+// entries l, l+64, ...) for the one nearest to (previous row's column in that
+// slot) + 1, smaller column on a tie, and a fixed shuffle tree picks the
+// wavefront's best.  Columns of a row are distinct, so the pick is unique and
+// matches the serial search whatever the entries' order.
+constexpr int SOJDS_LDS_CAP = 4096;
+constexpr int32_t SOJDS_TAKEN = INT32_MAX;    // no column reaches it (columns < n_cols <= INT32_MAX)
+
+template <typename T>
+__global__ __launch_bounds__(WAVE) void sojds_wave_kernel(const int32_t *__restrict__ jp, int32_t ndiag,
+                                                          const int32_t *__restrict__ jd_col,
+                                                          const T *__restrict__ jd_val, int32_t n, int32_t C,
+                                                          const int64_t *__restrict__ slice_ptr,
+                                                          int32_t *__restrict__ bl_col, T *__restrict__ bl_val)
+{
+    __shared__ int32_t cur[SOJDS_LDS_CAP];        // the row's columns; SOJDS_TAKEN once placed
+    __shared__ int32_t prv[SOJDS_LDS_CAP];        // the previous row's column in each slot
+    __shared__ int32_t pick[SOJDS_LDS_CAP];       // entry placed in each slot
+    const int l = (int)threadIdx.x;
+    const int64_t s = blockIdx.x;
+    const int64_t r0 = s * (int64_t)C;
+    const int32_t len0 = jds_len_of(jp, ndiag, r0);
+    if (len0 > SOJDS_LDS_CAP || len0 == 0) return;       // whole wavefront: serial kernel's slice, or nothing to do
+    const int64_t sp = slice_ptr[s];
+    for (int32_t d = l; d < len0; d += WAVE) prv[d] = bl_col[sp + (int64_t)d * C];   // first row, CRS order
+    __syncthreads();
+    for (int32_t rl = 1; rl < C; ++rl) {
+        const int64_t r = r0 + rl;
+        if (r >= n) break;
+        const int32_t len = jds_len_of(jp, ndiag, r);     // <= the previous row's length
+        if (len == 0) break;                              // rows of the slice are sorted by length
+        for (int32_t e = l; e < len; e += WAVE) cur[e] = jd_col[jp[e] + r];
+        __syncthreads();
+        for (int32_t d = 0; d < len; ++d) {
+            // key = distance << 32 | column: the smallest key is the nearest
+            // entry, the smaller column on a tie
+            const uint32_t want = (uint32_t)prv[d] + 1u;
+            uint64_t best = UINT64_MAX;
+            int32_t be = -1;
+            for (int32_t e = l; e < len; e += WAVE) {
+                const int32_t c = cur[e];
+                if (c == SOJDS_TAKEN) continue;
+                const uint32_t uc = (uint32_t)c;
+                const uint64_t key = ((uint64_t)(uc > want ? uc - want : want - uc) << 32) | uc;
+                if (key < best) {
+                    best = key;
+                    be = e;
+                }
+            }
+#pragma unroll
+            for (int off = WAVE / 2; off > 0; off >>= 1) {
+                const uint64_t ok = __shfl_xor(best, off, WAVE);
+                const int32_t oe = __shfl_xor(be, off, WAVE);
+                if (ok < best) {
+                    best = ok;
+                    be = oe;
+                }
+            }
+            if (l == 0) {
+                cur[be] = SOJDS_TAKEN;
+                pick[d] = be;
+                prv[d] = (int32_t)(uint32_t)best;        // the next row's target in this slot
+            }
+            __syncthreads();
+        }
+        for (int32_t d = l; d < len; d += WAVE) {
+            const int32_t e = pick[d];
+            bl_col[sp + (int64_t)d * C + rl] = prv[d];
+            bl_val[sp + (int64_t)d * C + rl] = jd_val[jp[e] + r];
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ void sojds_kernel(const int32_t *__restrict__ jp, int32_t ndiag, const int32_t *__restrict__ jd_col,
                              const T *__restrict__ jd_val, int32_t n, int32_t C, const int64_t *__restrict__ slice_ptr,
                              int32_t n_slices, int32_t words, uint32_t *__restrict__ taken_all,
-                             int32_t *__restrict__ bl_col, T *__restrict__ bl_val)
+                             int32_t *__restrict__ bl_col, T *__restrict__ bl_val, int32_t min_len)
 {
     GRID_LOOP(s, (int64_t)n_slices)
     {
+        if (jds_len_of(jp, ndiag, s * (int64_t)C) <= min_len) continue;   // sojds_wave_kernel's slice
         uint32_t *taken = taken_all + s * (int64_t)words;
         const int64_t sp = slice_ptr[s];
         for (int32_t rl = 1; rl < C; ++rl) {
@@ -1271,9 +1349,15 @@ spmv_status spmv_jds_blocked_from_jds(int32_t n, const int32_t *jd_ptr, int32_t 
                                                                slice_ptr, ns, total, bl_col, (T *)bl_val);          \
         SPMV_CHECK_LAUNCH("blocked fill");                                                                          \
         if (flags & SPMV_SOJDS) {                                                                                   \
-            sojds_kernel<T><<<grid_for(ns), 64, 0, s>>>(jd_ptr, ndiag, jd_col, (const T *)jd_val, n, C, slice_ptr,  \
-                                                        ns, words, taken, bl_col, (T *)bl_val);                     \
-            SPMV_CHECK_LAUNCH("sojds");                                                                             \
+            sojds_wave_kernel<T><<<(unsigned)ns, WAVE, 0, s>>>(jd_ptr, ndiag, jd_col, (const T *)jd_val, n, C,       \
+                                                               slice_ptr, bl_col, (T *)bl_val);                     \
+            SPMV_CHECK_LAUNCH("sojds (wavefront per slice)");                                                       \
+            if (ndiag > SOJDS_LDS_CAP) {                                                                            \
+                sojds_kernel<T><<<grid_for(ns), 64, 0, s>>>(jd_ptr, ndiag, jd_col, (const T *)jd_val, n, C,         \
+                                                            slice_ptr, ns, words, taken, bl_col, (T *)bl_val,       \
+                                                            SOJDS_LDS_CAP);                                         \
+                SPMV_CHECK_LAUNCH("sojds (long rows)");                                                             \
+            }                                                                                                       \
         }                                                                                                           \
     }
     BLK_CASE(SPMV_F64, uint64_t)

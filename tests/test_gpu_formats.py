@@ -122,6 +122,19 @@ def test_sojds_long_and_unsorted_rows_bit_exact(shuffle):
         assert np.array_equal(to_np(B.bl_val), Rb.bl_val), C
 
 
+def test_sojds_rows_past_the_lds_capacity_bit_exact():
+    """Slices whose first row has more than 4,096 entries take the serial
+    builder, the others the wavefront builder: both bit-exact against the
+    oracle's greedy rule, in one storage."""
+    r, c, v, nr, nc, rng = rand_coo(9, 1200, 6000, 0.003, empty_rows=0.1, long_rows=5, long_len=5000)
+    Rc = oracle.csr_from_coo(nr, nc, r, c, v)
+    A = sp.CSR(nr, nc, to_dev(Rc.row_ptr), to_dev(Rc.col), to_dev(Rc.val))
+    Rb = oracle.blocked_from_jds(oracle.jds_from_csr(Rc), 64, sojds=True)
+    B = sp.jds_blocked_from_jds(sp.jds_from_csr(A), 64, sojds=True)
+    assert np.array_equal(to_np(B.bl_col), Rb.bl_col)
+    assert np.array_equal(to_np(B.bl_val), Rb.bl_val)
+
+
 @pytest.mark.parametrize("C,sigma", [(64, 64), (64, 256), (128, 384), (64, 1 << 20)])
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32, torch.int32])
 def test_windowed_blocked_bit_exact(C, sigma, dt):
