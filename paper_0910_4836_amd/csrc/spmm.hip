@@ -47,6 +47,14 @@ __host__ __device__ constexpr int32_t mm_rp_lds(int32_t block_nnz)
 {
     return 2 * block_nnz < 2048 ? 2 * block_nnz : 2048;
 }
+// Y tile of a multi-row CRS block with FP64 vectors and K2 >= 16: rows x K2
+// doubles when they fit in this many (8 KB).  Measured on the power-law
+// matrix: k = 32 1.07x faster (Y written 0.84 instead of 1.0 GB); at k = 8
+// the tile halves the Y writes but its LDS costs a third of the occupancy of
+// the 128-lane workgroups, 1.14x slower, so small k writes directly.
+constexpr int MM_YTILE_ELEMS = 1024;
+template <int K2>
+constexpr size_t mm_ytile_bytes() { return K2 >= 16 ? sizeof(double) * MM_YTILE_ELEMS + 16 : 0; }
 
 // Xr[c*k + j] = X[c + j*ldx] (2 <= k <= 64): a block of STAGE_ELEMS / k rows
 // through LDS.  Reads walk each column's run of rows (coalesced), writes walk
@@ -157,16 +165,22 @@ __device__ __forceinline__ void mm_crs_balanced(const int32_t *rp, int32_t r0, i
                                                 const XT *__restrict__ Xr, int32_t k, XT *__restrict__ Y,
                                                 int64_t ldy, double alpha, double beta, int g, int j,
                                                 double (*lead)[K2], double (*tail)[K2], int32_t *lead_row,
-                                                int32_t *tail_row)
+                                                int32_t *tail_row, double *ytile)
 {
     typedef typename Acc<WIDE>::T acc_t;
     constexpr int U = CPL >= 8 ? 1 : 8 / CPL;
     const int32_t E = rp[r1 - r0];
     const int32_t cs = (int32_t)((int64_t)g * E / NG), ce = (int32_t)((int64_t)(g + 1) * E / NG);
+    // with a tile (blocks of few rows), finished rows wait in LDS and the
+    // block writes them at the end, column by column, in runs of consecutive
+    // rows: whole lines of a column leave together instead of 8-byte pieces
     auto put = [&](int32_t row, const acc_t *v) {
 #pragma unroll
         for (int t = 0; t < CPL; ++t)
-            if (t * LPR + j < k) write_y(Y + (int64_t)(t * LPR + j) * ldy, row, (double)v[t], alpha, beta);
+            if (t * LPR + j < k) {
+                if (ytile) ytile[(int64_t)(t * LPR + j) * (r1 - r0) + (row - r0)] = (double)v[t];
+                else write_y(Y + (int64_t)(t * LPR + j) * ldy, row, (double)v[t], alpha, beta);
+            }
     };
     acc_t zero[CPL];
 #pragma unroll
@@ -271,6 +285,15 @@ __device__ __forceinline__ void mm_crs_balanced(const int32_t *rp, int32_t r0, i
         }
         put(R, a);
     }
+    if (ytile) {
+        __syncthreads();
+        const int32_t nr = r1 - r0;
+        const int lane = g * LPR + j;
+        for (int64_t q = lane; q < (int64_t)nr * k; q += NG * LPR) {
+            const int32_t c = (int32_t)(q / nr), rr = (int32_t)(q % nr);
+            write_y(Y + (int64_t)c * ldy, r0 + rr, ytile[q], alpha, beta);
+        }
+    }
 }
 
 // CRS, interleaved X.  One workgroup per plan block of nr rows: GPR groups
@@ -333,8 +356,11 @@ __global__ __launch_bounds__(NT) void spmm_crs_il_kernel(const int32_t *__restri
         // (the shares were 1.3x slower at k = 32 with one-wavefront groups)
         if constexpr (sizeof(XT) == 8) {
             if (rp_lds) {
+                // after the row offsets, rounded up to 16 bytes
+                const uintptr_t tile_at = ((uintptr_t)(rp_s + mm_rp_lds(block_nnz) + 1) + 15) & ~(uintptr_t)15;
+                double *ytile = K2 >= 16 && nr * K2 <= MM_YTILE_ELEMS ? reinterpret_cast<double *>(tile_at) : nullptr;
                 mm_crs_balanced<LPR, CPL, NG, K2, F64, VT, XT>(rp_s, r0, r1, col_s, val_s, Xr, k, Y, ldy, alpha,
-                                                               beta, g, j, part, tailp, lead_row, tail_row);
+                                                               beta, g, j, part, tailp, lead_row, tail_row, ytile);
                 return;
             }
         }
@@ -828,7 +854,8 @@ static void launch_crs_il(const int32_t *row_ptr, const int32_t *col, const void
                           double beta, hipStream_t s)
 {
     const size_t lds = (size_t)((block_nnz + 3) & ~3) * 4 + (size_t)((block_nnz + 1) & ~1) * sizeof(VT) +
-                       (sizeof(XT) == 8 ? sizeof(int32_t) * ((size_t)mm_rp_lds(block_nnz) + 1) : 0);
+                       (sizeof(XT) == 8 ? sizeof(int32_t) * ((size_t)mm_rp_lds(block_nnz) + 1) + mm_ytile_bytes<K2>()
+                                        : 0);
     constexpr int NT = mm_crs_threads<K2, XT>();
     spmm_crs_il_kernel<K2, NT, VT, XT><<<nb, NT, lds, s>>>(row_ptr, col, (const VT *)val, (const XT *)Xr, k,
                                                           (XT *)Y, ldy, plan, block_nnz, alpha, beta);
