@@ -492,9 +492,14 @@ def powerlaw_kernels(sp, W, torch):
 
 def bytes_dia(D, s_v, s_x):
     """Stored diagonals read over their spans (zeros inside a span included),
-    the remainder as CRS, x and y once."""
+    the remainder as CRS (or its padded row-order slices, 12 bytes of slice
+    header each), x and y once."""
     span = sum(max(0, min(D.n_rows, D.n_cols - int(o)) - max(0, -int(o))) for o in D.offsets)
-    rem = D.rem.nnz * (s_v + 4) + (4 * (D.n_rows + 1) if D.rem.nnz else 0)
+    if D.rem_slices is not None and D.rem.nnz:
+        R = D.rem_slices
+        rem = len(R.bl_col) * (s_v + 4) + 12 * len(R.slice_nd)
+    else:
+        rem = D.rem.nnz * (s_v + 4) + (4 * (D.n_rows + 1) if D.rem.nnz else 0)
     return span * s_v + rem + s_x * (D.n_cols + D.n_rows)
 
 
@@ -788,6 +793,53 @@ def suite_symdiag(torch, sp, dev, steps):
     out["kernels"]["blocked_sojds_f64"]["max_rel_err_vs_fp64_product"] = _rel_err_gpu(torch, sp, W3["A"], x, y, y_ref)
     del Bs
     W3.pop("samples", None)
+    return out
+
+
+def suite_hamiltonian(torch, sp, dev, steps):
+    """A symmetric matrix shaped like the paper's Hamiltonian (the diagonal,
+    six mirrored pairs of 70%-filled outer diagonals, 2-3 scattered entries
+    per row and triangle inside a band of 500): CRS, JDS, blocked JDS and the
+    DIA hybrid with its remainder in CRS, in row-order slices, and over one
+    triangle of the diagonals."""
+    import synth
+    from paper_0910_4836_amd import autotune
+    r, c, v, n, _ = synth.heavy_diagonals_band()
+    nnz = len(r)
+    x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(6, 1))).to(dev)
+    A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
+    del r, c, v
+    J = sp.jds_from_csr(A)
+    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    autotune.tune_crs(tuner, A, x, J.ndiag)
+    ju, jm, jw = tuner.tune_jds(J, x)
+    bC, bR, bU, bW = tuner.tune_blocked(J, x)
+    B = sp.jds_blocked_from_jds(J, bC)
+    D = sp.dia_from_csr(A)
+    Ds = sp.dia_from_csr(A, sliced=True)
+    Dy = sp.dia_from_csr(A, symmetric=True, sliced=True)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    ks = [("crs", lambda: sp.spmv_crs(A, x, y)),
+          ("jds", lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
+          ("blocked", lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW)),
+          ("dia_crs_remainder", lambda: sp.spmv_dia(D, x, y)),
+          ("dia_sliced_remainder", lambda: sp.spmv_dia(Ds, x, y)),
+          ("dia_sym_sliced_remainder", lambda: sp.spmv_dia(Dy, x, y))]
+    _, per = time_loop(torch, ks, max(20, steps // 4), 5)
+    bmin = {"crs": bytes_crs(nnz, n, n, 8, 8), "jds": bytes_jds(nnz, n, n, J.ndiag, 8, 8),
+            "blocked": bytes_blocked(nnz, n, n, B.n_slices, 8, 8), "dia_crs_remainder": bytes_dia(D, 8, 8),
+            "dia_sliced_remainder": bytes_dia(Ds, 8, 8), "dia_sym_sliced_remainder": bytes_dia(Dy, 8, 8)}
+    out = {"workload": f"Hamiltonian-shaped symmetric matrix n={n} nnz={nnz} (diagonal, 6 mirrored pairs of "
+                       "70%-filled outer diagonals, band of 500), FP64",
+           "dia": {"stored_diagonals": int(D.ndia), "remainder_nnz": int(D.rem.nnz),
+                   "remainder_padded_slots": int(Ds.rem_slices.bl_col.numel()),
+                   "sym_stored_diagonals": int(Dy.ndia), "sym_remainder_nnz": int(Dy.rem.nnz)},
+           "kernels": {}}
+    y_ref = sp.spmv_crs(A, x)
+    for k, fn in ks:
+        out["kernels"][k] = _kernel_entry(k, 2.0 * nnz, bmin[k], per[k])
+        fn()
+        out["kernels"][k]["max_rel_err_vs_fp64_crs"] = _rel_err_gpu(torch, sp, A, x, y, y_ref)
     return out
 
 
@@ -1108,6 +1160,7 @@ def suite_lines(torch, sp, dev, W, steps, warmup, only=""):
                      ("one-shard-of-8", lambda: suite_shard(torch, sp, dev, W, steps)),
                      ("multi-vector", lambda: suite_spmm(torch, sp, dev, W, steps)),
                      ("symmetric-diagonals", lambda: suite_symdiag(torch, sp, dev, steps)),
+                     ("hamiltonian-shaped", lambda: suite_hamiltonian(torch, sp, dev, steps)),
                      ("chebyshev", lambda: suite_chebyshev(torch, sp, dev, steps)),
                      ("many-matrices", lambda: suite_batched(torch, sp, dev, steps))):
         if keep and name not in keep:

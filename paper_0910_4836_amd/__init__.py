@@ -7,7 +7,7 @@ multiplications on current multicore environments", Section 2.
 """
 from ._lib import SpmvError, load as load_library  # noqa: F401
 from .spmv import (  # noqa: F401
-    CSR, DIA, JDS, SymCSR, Batched, Blocked, Graph, RowSplit, Split, colmajor, csr_from_coo, dia_from_csr, dtype_code,
+    CSR, DIA, JDS, SymCSR, Slices, Batched, csr_to_slices, Blocked, Graph, RowSplit, Split, colmajor, csr_from_coo, dia_from_csr, dtype_code,
     jds_blocked_from_jds, jds_from_csr, jds_to_csr, spmm_crs, spmm_jds, spmm_jds_blocked, spmm_workspace, spmv_axpby,
     spmv_convert_values, spmv_crs, spmv_crs_plan, spmv_crs_split, spmv_csr_validate, spmv_dia, spmv_dot,
     spmv_dot_noalloc, jds_blocked_windowed_from_csr, spmv_jds_blocked_tiles, spmv_jds_blocked_tiled,

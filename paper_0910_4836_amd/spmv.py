@@ -911,24 +911,70 @@ def spmv_crs_sym(S: SymCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, a
 
 
 @dataclass
+class Slices:
+    """A CRS matrix in row-order slices of 64 rows (spmv_csr_to_slices)."""
+    n_rows: int
+    slice_ptr: torch.Tensor      # int64, n_slices + 1
+    slice_nd: torch.Tensor       # int32, the slice's longest row
+    bl_col: torch.Tensor         # padded slots, col = -1 in padding
+    bl_val: torch.Tensor
+
+    def with_values(self, val: torch.Tensor) -> "Slices":
+        return Slices(self.n_rows, self.slice_ptr, self.slice_nd, self.bl_col, val)
+
+
+def csr_to_slices(A: CSR) -> Slices:
+    """CRS -> row-order slices of 64 rows on the GPU (spmv_csr_to_slices)."""
+    lib = _lib.load()
+    dev = A.device
+    n = A.n_rows
+    ns = (n + 63) // 64
+    ws = _ws(lib.spmv_csr_slices_workspace_size(n), dev)
+    sp_ = torch.empty(ns + 1, dtype=torch.int64, device=dev)
+    nd = torch.empty(max(ns, 1), dtype=_I32, device=dev)
+    padded = C.c_int64(0)
+    call("spmv_csr_to_slices", n, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(sp_), _p(nd),
+         None, None, 0, C.byref(padded), _p(ws), ws.numel(), _stream())
+    m = padded.value
+    col = torch.empty(max(m, 1), dtype=_I32, device=dev)
+    val = torch.empty(max(m, 1), dtype=A.val.dtype, device=dev)
+    call("spmv_csr_to_slices", n, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(sp_), _p(nd),
+         _p(col), _p(val), max(m, 1), C.byref(padded), _p(ws), ws.numel(), _stream())
+    return Slices(n, sp_, nd[:ns], col[:m], val[:m])
+
+
+@dataclass
 class DIA:
-    """Densely stored diagonals (offset col - row) plus a remainder CRS."""
+    """Densely stored diagonals (offset col - row) plus a remainder, in CRS or
+    (rem_slices) in row-order slices of 64 rows."""
     n_rows: int
     n_cols: int
     offsets: np.ndarray          # int32, ascending, host
     dia_val: torch.Tensor        # ndia * n_rows values, diagonal after diagonal
     rem: CSR                     # the entries on no stored diagonal
     symmetric: bool = False      # offsets >= 0, each diagonal also serves its mirror
+    rem_slices: Optional[Slices] = None
 
     @property
     def ndia(self) -> int:
         return len(self.offsets)
 
+    def with_values(self, dia_val: torch.Tensor, rem_val: Optional[torch.Tensor] = None) -> "DIA":
+        """Same structure, other values (rem_val: the remainder CRS's values;
+        the sliced copy, if any, is rebuilt from them)."""
+        rem = self.rem if rem_val is None else self.rem.with_values(rem_val)
+        D = DIA(self.n_rows, self.n_cols, self.offsets, dia_val, rem, self.symmetric)
+        if self.rem_slices is not None:
+            D.rem_slices = csr_to_slices(rem) if rem.nnz else self.rem_slices
+        return D
 
-def dia_from_csr(A: CSR, max_diags: int = 0, symmetric: bool = False) -> DIA:
+
+def dia_from_csr(A: CSR, max_diags: int = 0, symmetric: bool = False, sliced: bool = False) -> DIA:
     """CRS -> DIA + CRS hybrid on the GPU (spmv_dia_from_csr; with
     symmetric=True, spmv_dia_sym_from_csr: upper diagonals only, each also
-    standing for its mirror, for a square matrix symmetric on them)."""
+    standing for its mirror, for a square matrix symmetric on them).  With
+    sliced=True the remainder is also laid out in row-order slices
+    (spmv_csr_to_slices) and spmv_dia uses them."""
     lib = _lib.load()
     dev = A.device
     if symmetric and A.n_rows != A.n_cols:
@@ -949,8 +995,11 @@ def dia_from_csr(A: CSR, max_diags: int = 0, symmetric: bool = False) -> DIA:
     rem_col = torch.empty(max(m, 1), dtype=_I32, device=dev)
     rem_val = torch.empty(max(m, 1), dtype=A.val.dtype, device=dev)
     call(fn, *args(_p(dia_val), _p(rem_rp), _p(rem_col), _p(rem_val)))
-    return DIA(A.n_rows, A.n_cols, offs[:k].copy(), dia_val[:k * A.n_rows],
-               CSR(A.n_rows, A.n_cols, rem_rp, rem_col[:m], rem_val[:m]), symmetric)
+    D = DIA(A.n_rows, A.n_cols, offs[:k].copy(), dia_val[:k * A.n_rows],
+            CSR(A.n_rows, A.n_cols, rem_rp, rem_col[:m], rem_val[:m]), symmetric)
+    if sliced:
+        D.rem_slices = csr_to_slices(D.rem)
+    return D
 
 
 def spmv_dia(D: DIA, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
@@ -958,6 +1007,13 @@ def spmv_dia(D: DIA, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: f
     """y = alpha*A x + beta*y over the DIA + CRS hybrid (spmv_dia)."""
     y = _out_vec(y, D.n_rows, x, beta, D.n_cols)
     has_rem = D.rem.nnz > 0
+    if D.rem_slices is not None:
+        R = D.rem_slices
+        call("spmv_dia_sliced", D.n_rows, D.n_cols, D.ndia, _h_i32(D.offsets), _p(D.dia_val),
+             dtype_code(D.dia_val.dtype), _p(R.slice_ptr) if has_rem else None, _p(R.slice_nd) if has_rem else None,
+             _p(R.bl_col) if has_rem else None, _p(R.bl_val) if has_rem else None, _p(x), _p(y), dtype_code(x.dtype),
+             float(alpha), float(beta), int(D.symmetric), _stream())
+        return y
     shape = (D.n_rows,) if D.symmetric else (D.n_rows, D.n_cols)
     call("spmv_dia_sym" if D.symmetric else "spmv_dia", *shape, D.ndia, _h_i32(D.offsets), _p(D.dia_val),
          dtype_code(D.dia_val.dtype), _p(D.rem.row_ptr) if has_rem else None,

@@ -198,6 +198,53 @@ def sym_diagonals(n: int = 6_000_000, ndiag: int = 12, seed_config: int = 3):
     return (rows.astype(np.int32), cand[valid].astype(np.int32), vals[valid], n, n)
 
 
+def heavy_diagonals_band(n: int = 6_000_000, npairs: int = 6, fill: float = 0.7, band: int = 500,
+                         band_per_row: float = 2.3, seed_config: int = 6):
+    """Symmetric pattern shaped like the paper's Hamiltonian: the diagonal,
+    ``npairs`` mirrored pairs of outer secondary diagonals (offsets drawn
+    without replacement from [2*band, n/4], each position filled with
+    probability ``fill``) and entries scattered over the band |i - j| <= band
+    (2 or 3 upper entries per row, mean ``band_per_row``, distinct, mirrored).
+    N(0,1) values, mirrored pairs equal.  With the defaults 12.7 entries per
+    row, 56% of them on the outer diagonals, 36% in the band.
+
+    Draw order: offsets, the outer diagonals' fill masks and values in
+    ascending offset order, the band offsets (redrawn on collision), the band
+    values, the diagonal."""
+    rng = rng_for(seed_config)
+    offs = np.sort(rng.choice(np.arange(2 * band, n // 4 + 1), size=npairs, replace=False)).astype(np.int64)
+    up_r, up_c, up_v = [], [], []
+    for d in offs:
+        i = np.arange(n - d, dtype=np.int64)
+        keep = rng.random(len(i)) < fill
+        up_r.append(i[keep])
+        up_c.append(i[keep] + d)
+        up_v.append(rng.standard_normal(int(keep.sum())))
+    p3 = band_per_row - 2.0
+    lengths = 2 + (rng.random(n) < p3).astype(np.int64)
+    rows = _row_ids(lengths)
+    kinds = np.zeros(len(rows), np.int8)
+
+    def draw(rr, kk):
+        return rr + rng.integers(1, band + 1, size=len(rr), dtype=np.int64)
+
+    cols = draw(rows, kinds)
+    cols = _dedupe(rng, rows, cols, kinds, n + band + 1, draw)
+    inside = cols < n
+    up_r.append(rows[inside])
+    up_c.append(cols[inside])
+    up_v.append(rng.standard_normal(int(inside.sum())))
+    diag = rng.standard_normal(n)
+    r = np.concatenate(up_r)
+    c = np.concatenate(up_c)
+    v = np.concatenate(up_v)
+    i = np.arange(n, dtype=np.int64)
+    rows_all = np.concatenate([r, c, i])
+    cols_all = np.concatenate([c, r, i])
+    vals_all = np.concatenate([v, v, diag])
+    return _finish(rows_all, cols_all, vals_all, n) + (n, n)
+
+
 def sym_diagonals_offsets(n: int = 6_000_000, ndiag: int = 12, seed_config: int = 3):
     return sym_offsets(n, ndiag, rng_for(seed_config))
 

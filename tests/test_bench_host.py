@@ -27,9 +27,15 @@ def test_dia_bytes_count_spans():
         nnz, n_rows = 3, 6
 
     class D:
-        n_rows, n_cols, offsets, rem = 6, 6, np.array([-2, 0, 5]), R()
+        n_rows, n_cols, offsets, rem, rem_slices = 6, 6, np.array([-2, 0, 5]), R(), None
     # spans 4 + 6 + 1 stored values, the remainder as CRS, x and y
     assert bench.bytes_dia(D, 8, 8) == 11 * 8 + 3 * 12 + 4 * 7 + 8 * 12
+
+    class T:                                        # one slice of depth 2: 128 padded slots
+        bl_col, slice_nd = np.zeros(128), np.zeros(1)
+
+    D.rem_slices = T()
+    assert bench.bytes_dia(D, 8, 8) == 11 * 8 + 128 * 12 + 12 + 8 * 12
 
 
 def test_roofline_record():

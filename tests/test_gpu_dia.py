@@ -265,3 +265,95 @@ def test_dia_sym_integer_exact_and_reduced_values():
         assert np.array_equal(to_np(sp.spmv_dia(D, to_dev(x))), want), dt
     with pytest.raises(ValueError):
         sp.dia_from_csr(gpu_csr(sp, r[r < 2000], c[r < 2000], v[r < 2000], 2000, n), symmetric=True)
+
+
+# ---- remainder in row-order slices of 64 rows
+
+
+def slices_numpy(R: oracle.CSR):
+    """The row-order slice layout re-derived with numpy: slice s holds rows
+    [64s, 64s+64), depth = its longest row, entry d of row r at
+    slice_ptr[s] + 64 d + r % 64, padding col -1 / value 0."""
+    n = R.n_rows
+    L = R.row_lengths()
+    ns = (n + 63) // 64
+    nd = np.array([L[64 * s:64 * s + 64].max(initial=0) for s in range(ns)], dtype=np.int64)
+    sp_ = np.concatenate([[0], np.cumsum(nd * 64)])
+    col = np.full(int(sp_[-1]), -1, np.int64)
+    val = np.zeros(int(sp_[-1]))
+    rows = R.row_index()
+    d = np.arange(R.nnz) - R.row_ptr[rows]
+    slot = sp_[rows // 64] + 64 * d + rows % 64
+    col[slot] = R.col
+    val[slot] = R.val
+    return sp_, nd, col, val
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 4099])
+def test_csr_to_slices_layout(n):
+    r, c, v, nr, nc = synth.random_pattern(n, 3000, 0.004, np.random.default_rng(200 + n), empty_rows=0.2,
+                                           long_rows=min(2, n), long_len=700)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    S = sp.csr_to_slices(gpu_csr(sp, r, c, v, nr, nc))
+    sp_, nd, col, val = slices_numpy(R)
+    assert np.array_equal(to_np(S.slice_ptr), sp_)
+    assert np.array_equal(to_np(S.slice_nd), nd)
+    assert np.array_equal(to_np(S.bl_col), col)
+    assert np.array_equal(to_np(S.bl_val).view(np.uint64), val.view(np.uint64))
+
+
+def _sliced_cases():
+    r, c, v, nr, nc, _ = planted(21, 3000, 3200)
+    yield "planted", (r, c, v, nr, nc), False
+    r, c, v, n, _ = symmetric_planted(22, 3000)
+    yield "symmetric_planted", (r, c, v, n, n), True
+    r, c, v, n, _ = synth.heavy_diagonals_band(n=40000)
+    yield "heavy_diagonals_band", (r, c, v, n, n), False
+    yield "heavy_diagonals_band_sym", (r, c, v, n, n), True
+
+
+@pytest.mark.parametrize("case", ["planted", "symmetric_planted", "heavy_diagonals_band", "heavy_diagonals_band_sym"])
+def test_dia_sliced_bit_identical_and_parity(case):
+    """The sliced remainder sums the same terms in the same order as the CRS
+    remainder: bit-identical for every value type, and within the FP64 bound
+    of the oracle."""
+    (r, c, v, nr, nc), sym = dict((k, (a, b)) for k, a, b in _sliced_cases())[case]
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    rng = np.random.default_rng(23)
+    x = rng.uniform(-1, 1, nc)
+    y0 = rng.uniform(-1, 1, nr)
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        Aq = A if dt == torch.float64 else A.with_values(sp.spmv_convert_values(A.val, dt))
+        D = sp.dia_from_csr(Aq, symmetric=sym)
+        Ds = sp.dia_from_csr(Aq, symmetric=sym, sliced=True)
+        assert D.rem.nnz > 0 or case == "planted"
+        for alpha, beta in ((1.0, 0.0), (-0.75, 2.0)):
+            a = to_np(sp.spmv_dia(D, to_dev(x), to_dev(y0.copy()), alpha, beta))
+            b = to_np(sp.spmv_dia(Ds, to_dev(x), to_dev(y0.copy()), alpha, beta))
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), (case, str(dt), alpha)
+    Ds = sp.dia_from_csr(A, symmetric=sym, sliced=True)
+    want = oracle.spmv_crs(R, x)
+    assert max_err(sp.spmv_dia(Ds, to_dev(x)), want, oracle.row_absdot(R, x)) <= FP64_TOL
+
+
+def test_dia_sliced_integer_exact_and_empty_remainder():
+    r, c, _, nr, nc, rng = planted(8, 3000, 3000)
+    v = rng.integers(-8, 9, len(r)).astype(np.float64)
+    x = synth.integer_vector(nc, rng)
+    want = oracle.spmv_crs(oracle.csr_from_coo(nr, nc, r, c, v), x)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        D = sp.dia_from_csr(A.with_values(sp.spmv_convert_values(A.val, dt)), sliced=True)
+        assert np.array_equal(to_np(sp.spmv_dia(D, to_dev(x))), want), dt
+    # whole diagonals only: an empty remainder in slices of depth 0
+    r, c, v, nr, nc, _ = planted(9, 1000, 1000, partial=(), scatter=0.0)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    D = sp.dia_from_csr(gpu_csr(sp, r, c, v, nr, nc), sliced=True)
+    assert D.rem.nnz == 0 and int(to_np(D.rem_slices.slice_ptr)[-1]) == 0
+    x = np.random.default_rng(10).uniform(-1, 1, nc)
+    assert max_err(sp.spmv_dia(D, to_dev(x)), oracle.spmv_crs(R, x), oracle.row_absdot(R, x)) <= FP64_TOL
+    # nothing stored at all
+    A = sp.csr_from_coo(5, 4, to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0)))
+    D = sp.dia_from_csr(A, sliced=True)
+    assert to_np(sp.spmv_dia(D, to_dev(np.ones(4)), to_dev(np.full(5, 2.0)), 1.0, 0.5)).tolist() == [1.0] * 5
