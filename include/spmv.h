@@ -578,36 +578,46 @@ spmv_status spmv_dia_sym(int32_t n, int32_t ndia, const int32_t *h_offsets, cons
                          const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val, const void *x,
                          void *y, spmv_dtype vec_dt, double alpha, double beta, void *stream);
 
-/* Remainder in row-order slices.  The paper (Section 2) stores RBJDS blocks
- * of consecutive (length-sorted) rows together, diagonal by diagonal; the
- * same layout without the sort keeps every row in its place, which is what
- * a kernel with one lane per row (the DIA hybrid) wants for its remainder:
- * the d-th entries of 64 consecutive rows are 64 consecutive slots.
- * spmv_csr_to_slices (setup, synchronises): slices of SPMV_SLICE_ROWS rows in
- * row order, slice s holding slice_nd[s] = its longest row's length and
- * occupying slots [slice_ptr[s], slice_ptr[s] + slice_nd[s] * 64); entry d
- * of row r sits at slice_ptr[r / 64] + d * 64 + r % 64 (CRS order inside a
- * row), padding has col = -1 and value 0.  slice_ptr[n_slices+1] (int64),
- * slice_nd[n_slices], n_slices = ceil(n_rows / 64).  With bl_col == NULL only
- * slice_ptr, slice_nd and *h_padded are written; bl_cap < *h_padded gives
- * SPMV_ERR_CAPACITY.  Any payload dtype (moved bit for bit).
+/* Remainder in window-sorted slices.  The paper (Section 2) stores RBJDS
+ * blocks of length-sorted rows together, diagonal by diagonal.  The DIA
+ * hybrid's remainder takes that layout with the sort confined to windows of
+ * SPMV_REM_WINDOW rows (the rows one workgroup of the DIA kernel owns), so a
+ * wavefront's loads of the d-th remainder entries are contiguous and the
+ * padding stays small, while the permutation never leaves the workgroup.
+ * spmv_csr_to_slices (setup, synchronises): window w holds rows
+ * [256 w, 256 w + 256); its rows in decreasing length order (ties: lower row
+ * first) fill sorted positions 256 w + t, and slot_row[256 w + t] (uint8) is
+ * the window-local index of the row at position t.  Slices are
+ * SPMV_REM_SLICE = 16 consecutive positions: slice s holds slice_nd[s] = the
+ * length of its first (longest) row and occupies slots
+ * [slice_ptr[s], slice_ptr[s] + 16 * slice_nd[s]); entry d (CRS order) of the
+ * row at position p sits at slice_ptr[p / 16] + 16 d + p % 16; padding has
+ * col = -1 and value 0 (also in the positions past n_rows of the last
+ * slice).  slice_ptr[n_slices + 1] (int64), slice_nd[n_slices],
+ * slot_row[n_rows], n_slices = ceil(n_rows / 16).  With bl_col == NULL only
+ * slice_ptr, slice_nd, slot_row and *h_padded are written; bl_cap <
+ * *h_padded gives SPMV_ERR_CAPACITY.  Any payload dtype (moved bit for bit).
  * ws: spmv_csr_slices_workspace_size(n_rows). */
-#define SPMV_SLICE_ROWS 64
+#define SPMV_REM_WINDOW 256
+#define SPMV_REM_SLICE 16
 size_t spmv_csr_slices_workspace_size(int32_t n_rows);
 spmv_status spmv_csr_to_slices(int32_t n_rows, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
-                               spmv_dtype dt, int64_t *slice_ptr, int32_t *slice_nd, int32_t *bl_col, void *bl_val,
-                               int64_t bl_cap, int64_t *h_padded, void *ws, size_t ws_bytes, void *stream);
+                               spmv_dtype dt, int64_t *slice_ptr, int32_t *slice_nd, uint8_t *slot_row,
+                               int32_t *bl_col, void *bl_val, int64_t bl_cap, int64_t *h_padded, void *ws,
+                               size_t ws_bytes, void *stream);
 /* The DIA hybrid (symmetric = 0: spmv_dia; 1: spmv_dia_sym storage) with its
- * remainder in row-order slices (spmv_csr_to_slices of the remainder CRS):
- * each lane reads its row's remainder entries as slots of its slice, so a
- * wavefront's loads of the d-th remainder entries are contiguous.  The sums
- * are the same FP64 sums in the same order as spmv_dia / spmv_dia_sym, so
- * the result is bit-identical to them.  rem_slice_ptr may be NULL when the
- * remainder is empty. */
+ * remainder in window-sorted slices (spmv_csr_to_slices of the remainder
+ * CRS).  Each lane first sums its row's stored diagonals, the workgroup puts
+ * the partial sums in LDS, and the lane at sorted position p continues the
+ * sum of row slot_row[p] with that row's remainder entries, so every row is
+ * still one FP64 sum in the order of spmv_dia / spmv_dia_sym (its diagonals,
+ * then its remainder in CRS order): the result is bit-identical to them.
+ * rem_slice_ptr may be NULL when the remainder is empty. */
 spmv_status spmv_dia_sliced(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets,
                             const void *dia_val, spmv_dtype val_dt, const int64_t *rem_slice_ptr,
-                            const int32_t *rem_slice_nd, const int32_t *rem_col, const void *rem_val, const void *x,
-                            void *y, spmv_dtype vec_dt, double alpha, double beta, int symmetric, void *stream);
+                            const int32_t *rem_slice_nd, const uint8_t *rem_slot_row, const int32_t *rem_col,
+                            const void *rem_val, const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                            int symmetric, void *stream);
 
 /* ======================================================================== */
 /* One-triangle CRS of a symmetric matrix                                    */

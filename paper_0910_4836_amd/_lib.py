@@ -105,9 +105,9 @@ SIGNATURES = {
                                      _sz, _p]),
     "spmv_dia_sym": (_int, [_i32, _i32, _i32p, _p, _int, _p, _p, _p, _p, _p, _int, _f64, _f64, _p]),
     "spmv_csr_slices_workspace_size": (_sz, [_i32]),
-    "spmv_csr_to_slices": (_int, [_i32, _p, _p, _p, _int, _p, _p, _p, _p, _i64, _i64p, _p, _sz, _p]),
-    "spmv_dia_sliced": (_int, [_i32, _i32, _i32, _i32p, _p, _int, _p, _p, _p, _p, _p, _p, _int, _f64, _f64, _int,
-                               _p]),
+    "spmv_csr_to_slices": (_int, [_i32, _p, _p, _p, _int, _p, _p, _p, _p, _p, _i64, _i64p, _p, _sz, _p]),
+    "spmv_dia_sliced": (_int, [_i32, _i32, _i32, _i32p, _p, _int, _p, _p, _p, _p, _p, _p, _p, _int, _f64, _f64,
+                                  _int, _p]),
     "spmv_csr_upper_workspace_size": (_sz, [_i32]),
     "spmv_csr_upper_from_csr": (_int, [_i32, _i64, _p, _p, _p, _int, _i64p, _p, _p, _p, _p, _sz, _p]),
     "spmv_crs_sym": (_int, [_i32, _p, _p, _p, _int, _p, _p, _int, _f64, _f64, _p, _i32, _i32, _p]),

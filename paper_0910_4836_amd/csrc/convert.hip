@@ -544,16 +544,40 @@ __global__ void window_slice_nd_kernel(const int32_t *__restrict__ rp, const int
 }
 
 // slices of C rows in row order: depth = the slice's longest row
-__global__ void slice_max_nd_kernel(const int32_t *__restrict__ rp, int32_t n, int32_t C, int32_t n_slices,
-                                    int32_t *__restrict__ nd, int64_t *__restrict__ sz)
+// One workgroup per window of SPMV_REM_WINDOW rows: each row's rank in the
+// window's decreasing-length order (ties: lower row first) by counting over
+// the window's lengths in LDS; the sorted position's window-local row (uint8)
+// and global row (for the fill), and the depth of every slice of
+// SPMV_REM_SLICE positions (its first row's length).
+__global__ __launch_bounds__(SPMV_REM_WINDOW) void rem_order_kernel(const int32_t *__restrict__ rp, int32_t n,
+                                                                     uint8_t *__restrict__ slot_row,
+                                                                     int32_t *__restrict__ perm,
+                                                                     int32_t *__restrict__ nd, int64_t *__restrict__ sz)
 {
-    GRID_LOOP(s, (int64_t)n_slices)
-    {
-        const int64_t r0 = s * (int64_t)C, r1 = r0 + C < n ? r0 + C : n;
-        int32_t l = 0;
-        for (int64_t r = r0; r < r1; ++r) l = max(l, rp[r + 1] - rp[r]);
-        nd[s] = l;
-        sz[s] = (int64_t)l * C;
+    __shared__ int32_t len[SPMV_REM_WINDOW];
+    __shared__ int32_t at[SPMV_REM_WINDOW];
+    const int64_t base = (int64_t)blockIdx.x * SPMV_REM_WINDOW;
+    const int t = threadIdx.x;
+    const int cnt = n - base < SPMV_REM_WINDOW ? (int)(n - base) : SPMV_REM_WINDOW;
+    len[t] = t < cnt ? rp[base + t + 1] - rp[base + t] : -1;
+    __syncthreads();
+    if (t < cnt) {
+        const int32_t l = len[t];
+        int rank = 0;
+        for (int j = 0; j < cnt; ++j) {
+            const int32_t lj = len[j];
+            rank += (lj > l) | ((lj == l) & (j < t));
+        }
+        at[rank] = t;
+        slot_row[base + rank] = (uint8_t)t;
+        perm[base + rank] = (int32_t)(base + t);
+    }
+    __syncthreads();
+    if (t < cnt && t % SPMV_REM_SLICE == 0) {
+        const int64_t sl = (base + t) / SPMV_REM_SLICE;
+        const int32_t d = len[at[t]];
+        nd[sl] = d;
+        sz[sl] = (int64_t)d * SPMV_REM_SLICE;
     }
 }
 
@@ -579,7 +603,7 @@ __global__ void window_fill_kernel(const int32_t *__restrict__ rp, const int32_t
         const int64_t r = (int64_t)lo * C + rl;
         int32_t e = -1;
         if (r < n) {
-            const int32_t row = perm ? perm[r] : (int32_t)r;     // no perm: rows in their own order
+            const int32_t row = perm[r];
             if (d < rp[row + 1] - rp[row]) e = rp[row] + d;
         }
         if (e >= 0) {
@@ -1458,34 +1482,38 @@ spmv_status spmv_jds_blocked_windowed_from_csr(int32_t n, int64_t nnz, const int
 
 size_t spmv_csr_slices_workspace_size(int32_t n_rows)
 {
-    const int64_t ns = ceil_div(n_rows > 0 ? n_rows : 1, SPMV_SLICE_ROWS);
-    return align_up(sizeof(int64_t) * (size_t)ns, 256) + align_up(sizeof(int64_t) * scan_ws_elems(ns), 256) + 512;
+    const int64_t n = n_rows > 0 ? n_rows : 1;
+    const int64_t ns = ceil_div(n, SPMV_REM_SLICE);
+    return align_up(sizeof(int32_t) * (size_t)n, 256) + align_up(sizeof(int64_t) * (size_t)ns, 256) +
+           align_up(sizeof(int64_t) * scan_ws_elems(ns), 256) + 512;
 }
 
 spmv_status spmv_csr_to_slices(int32_t n_rows, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
-                               spmv_dtype dt, int64_t *slice_ptr, int32_t *slice_nd, int32_t *bl_col, void *bl_val,
-                               int64_t bl_cap, int64_t *h_padded, void *ws, size_t ws_bytes, void *stream)
+                               spmv_dtype dt, int64_t *slice_ptr, int32_t *slice_nd, uint8_t *slot_row,
+                               int32_t *bl_col, void *bl_val, int64_t bl_cap, int64_t *h_padded, void *ws,
+                               size_t ws_bytes, void *stream)
 {
     SPMV_REQUIRE(n_rows >= 0, "spmv_csr_to_slices: n_rows < 0");
     SPMV_REQUIRE(valid_payload_dtype(dt), "spmv_csr_to_slices: bad dtype");
     SPMV_REQUIRE(slice_ptr && h_padded, "spmv_csr_to_slices: null pointer");
     SPMV_REQUIRE(ws && ws_bytes >= spmv_csr_slices_workspace_size(n_rows), "spmv_csr_to_slices: workspace too small");
     hipStream_t s = as_stream(stream);
-    const int32_t C = SPMV_SLICE_ROWS;
-    const int32_t ns = (int32_t)ceil_div(n_rows, C);
+    const int32_t ns = (int32_t)ceil_div(n_rows, SPMV_REM_SLICE);
     if (ns == 0) {
         SPMV_HIP(hipMemsetAsync(slice_ptr, 0, sizeof(int64_t), s));
         SPMV_HIP(hipStreamSynchronize(s));
         *h_padded = 0;
         return SPMV_OK;
     }
-    SPMV_REQUIRE(row_ptr && slice_nd, "spmv_csr_to_slices: null row_ptr or slice_nd");
+    SPMV_REQUIRE(row_ptr && slice_nd && slot_row, "spmv_csr_to_slices: null row_ptr, slice_nd or slot_row");
     WsCarver wc(ws, ws_bytes);
+    int32_t *perm = wc.take<int32_t>((size_t)n_rows);
     int64_t *sz = wc.take<int64_t>((size_t)ns);
     int64_t *sws = wc.take<int64_t>(scan_ws_elems(ns));
     if (!wc.ok()) return fail(SPMV_ERR_INVALID_ARG, "spmv_csr_to_slices: workspace too small");
-    slice_max_nd_kernel<<<grid_for(ns), 256, 0, s>>>(row_ptr, n_rows, C, ns, slice_nd, sz);
-    SPMV_CHECK_LAUNCH("slice depths");
+    rem_order_kernel<<<(unsigned)ceil_div(n_rows, SPMV_REM_WINDOW), SPMV_REM_WINDOW, 0, s>>>(row_ptr, n_rows,
+                                                                                          slot_row, perm, slice_nd, sz);
+    SPMV_CHECK_LAUNCH("slice order");
     spmv_status st = exclusive_scan<int64_t, int64_t>(sz, ns, slice_ptr, sws, s);
     if (st != SPMV_OK) return st;
     int64_t total = 0;
@@ -1496,9 +1524,9 @@ spmv_status spmv_csr_to_slices(int32_t n_rows, const int32_t *row_ptr, const int
     if (bl_cap < total) return fail(SPMV_ERR_CAPACITY, "spmv_csr_to_slices: capacity < padded size");
     if (total == 0) return SPMV_OK;
     SPMV_REQUIRE(col_idx && val && bl_val, "spmv_csr_to_slices: null arrays");
-#define SFILL_CASE(T)                                                                                               \
-    window_fill_kernel<T><<<grid_for(total), 256, 0, s>>>(row_ptr, col_idx, (const T *)val, nullptr, n_rows, C,     \
-                                                          slice_ptr, ns, total, bl_col, (T *)bl_val)
+#define SFILL_CASE(T)                                                                                                \
+    window_fill_kernel<T><<<grid_for(total), 256, 0, s>>>(row_ptr, col_idx, (const T *)val, perm, n_rows,            \
+                                                          SPMV_REM_SLICE, slice_ptr, ns, total, bl_col, (T *)bl_val)
     if (dt == SPMV_F64) SFILL_CASE(uint64_t);
     else if (dt == SPMV_F32 || dt == SPMV_I32) SFILL_CASE(uint32_t);
     else SFILL_CASE(uint16_t);

@@ -16,6 +16,13 @@
 // whose entry a(i, i - o) = dia[k][i - o] is the same diagonal read o rows
 // earlier: another contiguous stream, so every lane still writes only its own
 // row of y.
+//
+// Remainder in window-sorted slices: the rows of a workgroup's window are
+// ordered by remainder length and cut into slices of 16, the RBJDS layout
+// with the sort kept inside the workgroup.  The diagonal sums meet the
+// remainder sums in LDS, so the row order, the sums and y's coalesced writes
+// stay those of the CRS-remainder kernel while the remainder loads become
+// contiguous and the padding small.
 #include "common.hpp"
 
 namespace spmv {
@@ -27,8 +34,9 @@ struct DiaArgs {
     int32_t off[SPMV_DIA_MAX];
     const void *dia;
     const int32_t *rem_rp;      // CRS remainder, or
-    const int64_t *rem_sp;      // row-order slices of 64 rows (slice pointers and depths)
+    const int64_t *rem_sp;      // window-sorted slices (slice pointers, depths, window-local rows)
     const int32_t *rem_nd;
+    const uint8_t *rem_slot_row;
     const int32_t *rem_col;
     const void *rem_val;
     const void *x;
@@ -39,11 +47,9 @@ struct DiaArgs {
 // SYM: the stored offsets are >= 0 and diagonal k (offset o > 0) also holds
 // the mirrored entries a(i, i - o) = a(i - o, i) = dia[k][i - o]; the row adds
 // its upper terms in offset order, then its mirrored terms in offset order.
-template <typename VT, typename XT, bool SYM, bool SLICED>
-__global__ __launch_bounds__(DIA_THREADS) void dia_kernel(DiaArgs a)
+template <typename VT, typename XT, bool SYM>
+__device__ __forceinline__ double dia_row_sum(const DiaArgs &a, int64_t i)
 {
-    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * DIA_THREADS + threadIdx.x;
-    if (i >= a.n_rows) return;
     const VT *__restrict__ dia = (const VT *)a.dia + i;
     const XT *__restrict__ x = (const XT *)a.x;
     constexpr int U = 8;
@@ -95,42 +101,75 @@ __global__ __launch_bounds__(DIA_THREADS) void dia_kernel(DiaArgs a)
                 s = fma(to_f64(ld_stream((const VT *)a.dia + (int64_t)k * a.n_rows + j)), to_f64(x[j]), s);
         }
     }
-    if (!SLICED && a.rem_rp) {
+    return s;
+}
+
+// Remainder in CRS: the lane adds its own row's entries.
+template <typename VT, typename XT, bool SYM>
+__global__ __launch_bounds__(DIA_THREADS) void dia_kernel(DiaArgs a)
+{
+    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * DIA_THREADS + threadIdx.x;
+    if (i >= a.n_rows) return;
+    double s = dia_row_sum<VT, XT, SYM>(a, i);
+    if (a.rem_rp) {
         const VT *__restrict__ rv = (const VT *)a.rem_val;
+        const XT *__restrict__ x = (const XT *)a.x;
         for (int32_t e = a.rem_rp[i]; e < a.rem_rp[i + 1]; ++e) s = fma(to_f64(rv[e]), to_f64(x[a.rem_col[e]]), s);
     }
-    if (SLICED && a.rem_sp) {
-        // slot d*64 + (i % 64) of the row's slice: the wavefront's 64
-        // consecutive rows read 64 consecutive slots per entry index; entries
-        // in the row's CRS order, padding (col < 0) skipped
-        const int64_t sl = i / SPMV_SLICE_ROWS;
-        const int32_t ln = (int32_t)(i % SPMV_SLICE_ROWS);
-        const int64_t sp = a.rem_sp[sl] + ln;
-        const int32_t nd = a.rem_nd[sl];
-        const VT *__restrict__ rv = (const VT *)a.rem_val;
-        constexpr int UR = 4;
-        int32_t d = 0;
-        for (; d + UR <= nd; d += UR) {
-            int32_t c[UR];
-            VT v[UR];
-#pragma unroll
-            for (int u = 0; u < UR; ++u) {
-                c[u] = ld_stream(a.rem_col + sp + (int64_t)(d + u) * SPMV_SLICE_ROWS);
-                v[u] = ld_stream(rv + sp + (int64_t)(d + u) * SPMV_SLICE_ROWS);
-            }
-            XT xv[UR];
-#pragma unroll
-            for (int u = 0; u < UR; ++u) xv[u] = x[c[u] >= 0 ? c[u] : 0];
-#pragma unroll
-            for (int u = 0; u < UR; ++u)
-                if (c[u] >= 0) s = fma(to_f64(v[u]), to_f64(xv[u]), s);
-        }
-        for (; d < nd; ++d) {
-            const int32_t c = ld_stream(a.rem_col + sp + (int64_t)d * SPMV_SLICE_ROWS);
-            if (c >= 0) s = fma(to_f64(ld_stream(rv + sp + (int64_t)d * SPMV_SLICE_ROWS)), to_f64(x[c]), s);
-        }
-    }
     write_y((XT *)a.y, i, s, a.alpha, a.beta);
+}
+
+// Remainder in window-sorted slices: the workgroup owns one window of
+// SPMV_REM_WINDOW rows.  Lane t sums row base + t's diagonals into LDS; after
+// a barrier the lane at sorted position base + t continues the sum of the
+// window's row slot_row[base + t] with its remainder (the d-th entries of 16
+// consecutive positions are 16 consecutive slots) and puts it back; after a
+// second barrier lane t writes y for row base + t.  Each LDS slot is touched
+// by one lane between the barriers (slot_row is a permutation of the window).
+template <typename VT, typename XT, bool SYM>
+__global__ __launch_bounds__(DIA_THREADS) void dia_sliced_kernel(DiaArgs a)
+{
+    static_assert(DIA_THREADS == SPMV_REM_WINDOW, "one workgroup per remainder window");
+    __shared__ double part[DIA_THREADS];
+    const int64_t base = xcd_remap(blockIdx.x, gridDim.x) * DIA_THREADS;
+    const int64_t i = base + threadIdx.x;
+    const bool row = i < a.n_rows;
+    part[threadIdx.x] = row ? dia_row_sum<VT, XT, SYM>(a, i) : 0.0;
+    if (a.rem_sp) {
+        __syncthreads();
+        if (row) {
+            const int lr = a.rem_slot_row[i];
+            const int64_t sp = a.rem_sp[i / SPMV_REM_SLICE] + i % SPMV_REM_SLICE;
+            const int32_t nd = a.rem_nd[i / SPMV_REM_SLICE];
+            const VT *__restrict__ rv = (const VT *)a.rem_val;
+            const XT *__restrict__ x = (const XT *)a.x;
+            double s = part[lr];
+            constexpr int UR = 4;
+            int32_t d = 0;
+            for (; d + UR <= nd; d += UR) {
+                int32_t c[UR];
+                VT v[UR];
+#pragma unroll
+                for (int u = 0; u < UR; ++u) {
+                    c[u] = ld_stream(a.rem_col + sp + (int64_t)(d + u) * SPMV_REM_SLICE);
+                    v[u] = ld_stream(rv + sp + (int64_t)(d + u) * SPMV_REM_SLICE);
+                }
+                XT xv[UR];
+#pragma unroll
+                for (int u = 0; u < UR; ++u) xv[u] = x[c[u] >= 0 ? c[u] : 0];
+#pragma unroll
+                for (int u = 0; u < UR; ++u)
+                    if (c[u] >= 0) s = fma(to_f64(v[u]), to_f64(xv[u]), s);
+            }
+            for (; d < nd; ++d) {
+                const int32_t c = ld_stream(a.rem_col + sp + (int64_t)d * SPMV_REM_SLICE);
+                if (c >= 0) s = fma(to_f64(ld_stream(rv + sp + (int64_t)d * SPMV_REM_SLICE)), to_f64(x[c]), s);
+            }
+            part[lr] = s;
+        }
+        __syncthreads();
+    }
+    if (row) write_y((XT *)a.y, i, part[threadIdx.x], a.alpha, a.beta);
 }
 
 template <bool SYM, bool SLICED = false>
@@ -138,7 +177,7 @@ static spmv_status dia_product(int32_t n_rows, int32_t n_cols, int32_t ndia, con
                                const void *dia_val, spmv_dtype val_dt, const int32_t *rem_row_ptr,
                                const int32_t *rem_col, const void *rem_val, const void *x, void *y, spmv_dtype vec_dt,
                                double alpha, double beta, void *stream, const int64_t *rem_sp = nullptr,
-                               const int32_t *rem_nd = nullptr)
+                               const int32_t *rem_nd = nullptr, const uint8_t *rem_slot_row = nullptr)
 {
     SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0, "spmv_dia: negative size");
     SPMV_REQUIRE(ndia >= 0 && ndia <= SPMV_DIA_MAX, "spmv_dia: ndia must be 0..SPMV_DIA_MAX");
@@ -147,7 +186,8 @@ static spmv_status dia_product(int32_t n_rows, int32_t n_cols, int32_t ndia, con
     SPMV_REQUIRE(y, "spmv_dia: null y");
     SPMV_REQUIRE(ndia == 0 || (h_offsets && dia_val && x), "spmv_dia: null offsets, values or x");
     SPMV_REQUIRE(!rem_row_ptr || x, "spmv_dia: null x");
-    SPMV_REQUIRE(!rem_sp || (x && rem_nd && rem_col && rem_val), "spmv_dia_sliced: null remainder slices or x");
+    SPMV_REQUIRE(!rem_sp || (x && rem_nd && rem_slot_row && rem_col && rem_val),
+                 "spmv_dia_sliced: null remainder slices or x");
     DiaArgs a{};
     a.n_rows = n_rows;
     a.n_cols = n_cols;
@@ -162,6 +202,7 @@ static spmv_status dia_product(int32_t n_rows, int32_t n_cols, int32_t ndia, con
     a.rem_rp = rem_row_ptr;
     a.rem_sp = rem_sp;
     a.rem_nd = rem_nd;
+    a.rem_slot_row = rem_slot_row;
     a.rem_col = rem_col;
     a.rem_val = rem_val;
     a.x = x;
@@ -172,7 +213,8 @@ static spmv_status dia_product(int32_t n_rows, int32_t n_cols, int32_t ndia, con
     const unsigned grid = (unsigned)ceil_div(n_rows, DIA_THREADS);
 #define DIA_CASE(VDT, VT, XDT, XT)                                          \
     if (val_dt == VDT && vec_dt == XDT) {                                   \
-        dia_kernel<VT, XT, SYM, SLICED><<<grid, DIA_THREADS, 0, s>>>(a);    \
+        if (SLICED) dia_sliced_kernel<VT, XT, SYM><<<grid, DIA_THREADS, 0, s>>>(a); \
+        else dia_kernel<VT, XT, SYM><<<grid, DIA_THREADS, 0, s>>>(a);       \
         SPMV_CHECK_LAUNCH("spmv_dia");                                      \
         return SPMV_OK;                                                     \
     }
@@ -210,16 +252,17 @@ spmv_status spmv_dia_sym(int32_t n, int32_t ndia, const int32_t *h_offsets, cons
 
 spmv_status spmv_dia_sliced(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets,
                             const void *dia_val, spmv_dtype val_dt, const int64_t *rem_slice_ptr,
-                            const int32_t *rem_slice_nd, const int32_t *rem_col, const void *rem_val, const void *x,
-                            void *y, spmv_dtype vec_dt, double alpha, double beta, int symmetric, void *stream)
+                            const int32_t *rem_slice_nd, const uint8_t *rem_slot_row, const int32_t *rem_col,
+                            const void *rem_val, const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                            int symmetric, void *stream)
 {
     if (symmetric) {
         SPMV_REQUIRE(n_rows == n_cols, "spmv_dia_sliced: symmetric storage needs a square matrix");
         return dia_product<true, true>(n_rows, n_cols, ndia, h_offsets, dia_val, val_dt, nullptr, rem_col, rem_val, x,
-                                       y, vec_dt, alpha, beta, stream, rem_slice_ptr, rem_slice_nd);
+                                       y, vec_dt, alpha, beta, stream, rem_slice_ptr, rem_slice_nd, rem_slot_row);
     }
     return dia_product<false, true>(n_rows, n_cols, ndia, h_offsets, dia_val, val_dt, nullptr, rem_col, rem_val, x, y,
-                                    vec_dt, alpha, beta, stream, rem_slice_ptr, rem_slice_nd);
+                                    vec_dt, alpha, beta, stream, rem_slice_ptr, rem_slice_nd, rem_slot_row);
 }
 
 }  // extern "C"

@@ -910,43 +910,49 @@ def spmv_crs_sym(S: SymCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, a
     return y
 
 
+REM_WINDOW, REM_SLICE = 256, 16
+
+
 @dataclass
 class Slices:
-    """A CRS matrix in row-order slices of 64 rows (spmv_csr_to_slices)."""
+    """A CRS matrix in window-sorted slices (spmv_csr_to_slices): rows sorted
+    by decreasing length inside windows of 256, slices of 16 positions."""
     n_rows: int
     slice_ptr: torch.Tensor      # int64, n_slices + 1
-    slice_nd: torch.Tensor       # int32, the slice's longest row
+    slice_nd: torch.Tensor       # int32, the slice's first (longest) row's length
+    slot_row: torch.Tensor       # uint8, window-local row at each sorted position
     bl_col: torch.Tensor         # padded slots, col = -1 in padding
     bl_val: torch.Tensor
 
     def with_values(self, val: torch.Tensor) -> "Slices":
-        return Slices(self.n_rows, self.slice_ptr, self.slice_nd, self.bl_col, val)
+        return Slices(self.n_rows, self.slice_ptr, self.slice_nd, self.slot_row, self.bl_col, val)
 
 
 def csr_to_slices(A: CSR) -> Slices:
-    """CRS -> row-order slices of 64 rows on the GPU (spmv_csr_to_slices)."""
+    """CRS -> window-sorted slices on the GPU (spmv_csr_to_slices)."""
     lib = _lib.load()
     dev = A.device
     n = A.n_rows
-    ns = (n + 63) // 64
+    ns = (n + REM_SLICE - 1) // REM_SLICE
     ws = _ws(lib.spmv_csr_slices_workspace_size(n), dev)
     sp_ = torch.empty(ns + 1, dtype=torch.int64, device=dev)
     nd = torch.empty(max(ns, 1), dtype=_I32, device=dev)
+    rows = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
     padded = C.c_int64(0)
-    call("spmv_csr_to_slices", n, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(sp_), _p(nd),
-         None, None, 0, C.byref(padded), _p(ws), ws.numel(), _stream())
+    args = lambda col, val, cap: (n, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(sp_),
+                                  _p(nd), _p(rows), col, val, cap, C.byref(padded), _p(ws), ws.numel(), _stream())
+    call("spmv_csr_to_slices", *args(None, None, 0))
     m = padded.value
     col = torch.empty(max(m, 1), dtype=_I32, device=dev)
     val = torch.empty(max(m, 1), dtype=A.val.dtype, device=dev)
-    call("spmv_csr_to_slices", n, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(sp_), _p(nd),
-         _p(col), _p(val), max(m, 1), C.byref(padded), _p(ws), ws.numel(), _stream())
-    return Slices(n, sp_, nd[:ns], col[:m], val[:m])
+    call("spmv_csr_to_slices", *args(_p(col), _p(val), max(m, 1)))
+    return Slices(n, sp_, nd[:ns], rows[:n], col[:m], val[:m])
 
 
 @dataclass
 class DIA:
     """Densely stored diagonals (offset col - row) plus a remainder, in CRS or
-    (rem_slices) in row-order slices of 64 rows."""
+    (rem_slices) in window-sorted slices."""
     n_rows: int
     n_cols: int
     offsets: np.ndarray          # int32, ascending, host
@@ -973,7 +979,7 @@ def dia_from_csr(A: CSR, max_diags: int = 0, symmetric: bool = False, sliced: bo
     """CRS -> DIA + CRS hybrid on the GPU (spmv_dia_from_csr; with
     symmetric=True, spmv_dia_sym_from_csr: upper diagonals only, each also
     standing for its mirror, for a square matrix symmetric on them).  With
-    sliced=True the remainder is also laid out in row-order slices
+    sliced=True the remainder is also laid out in window-sorted slices
     (spmv_csr_to_slices) and spmv_dia uses them."""
     lib = _lib.load()
     dev = A.device
@@ -1010,9 +1016,9 @@ def spmv_dia(D: DIA, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: f
     if D.rem_slices is not None:
         R = D.rem_slices
         call("spmv_dia_sliced", D.n_rows, D.n_cols, D.ndia, _h_i32(D.offsets), _p(D.dia_val),
-             dtype_code(D.dia_val.dtype), _p(R.slice_ptr) if has_rem else None, _p(R.slice_nd) if has_rem else None,
-             _p(R.bl_col) if has_rem else None, _p(R.bl_val) if has_rem else None, _p(x), _p(y), dtype_code(x.dtype),
-             float(alpha), float(beta), int(D.symmetric), _stream())
+             dtype_code(D.dia_val.dtype), *((_p(R.slice_ptr), _p(R.slice_nd), _p(R.slot_row), _p(R.bl_col),
+                                             _p(R.bl_val)) if has_rem else (None,) * 5),
+             _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), int(D.symmetric), _stream())
         return y
     shape = (D.n_rows,) if D.symmetric else (D.n_rows, D.n_cols)
     call("spmv_dia_sym" if D.symmetric else "spmv_dia", *shape, D.ndia, _h_i32(D.offsets), _p(D.dia_val),

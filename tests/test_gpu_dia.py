@@ -267,37 +267,48 @@ def test_dia_sym_integer_exact_and_reduced_values():
         sp.dia_from_csr(gpu_csr(sp, r[r < 2000], c[r < 2000], v[r < 2000], 2000, n), symmetric=True)
 
 
-# ---- remainder in row-order slices of 64 rows
+# ---- remainder in window-sorted slices (windows of 256 rows, slices of 16)
 
 
 def slices_numpy(R: oracle.CSR):
-    """The row-order slice layout re-derived with numpy: slice s holds rows
-    [64s, 64s+64), depth = its longest row, entry d of row r at
-    slice_ptr[s] + 64 d + r % 64, padding col -1 / value 0."""
+    """The window-sorted slice layout re-derived with numpy: inside each
+    window of 256 rows the rows by decreasing length (stable), position p's
+    window-local row in slot_row[p]; slice s = positions [16s, 16s+16), depth
+    = its first row's length, entry d of position p at slice_ptr[p // 16] +
+    16 d + p % 16, padding col -1 / value 0."""
     n = R.n_rows
     L = R.row_lengths()
-    ns = (n + 63) // 64
-    nd = np.array([L[64 * s:64 * s + 64].max(initial=0) for s in range(ns)], dtype=np.int64)
-    sp_ = np.concatenate([[0], np.cumsum(nd * 64)])
+    slot_row = np.concatenate([np.argsort(-L[w:w + 256], kind="stable") for w in range(0, n, 256)]) \
+        if n else np.zeros(0, np.int64)
+    perm = (np.arange(n) // 256) * 256 + slot_row                 # global row at each position
+    Lp = L[perm]
+    ns = (n + 15) // 16
+    nd = Lp[::16].astype(np.int64)
+    sp_ = np.concatenate([[0], np.cumsum(nd * 16)])
     col = np.full(int(sp_[-1]), -1, np.int64)
     val = np.zeros(int(sp_[-1]))
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)                                      # position of each row
     rows = R.row_index()
     d = np.arange(R.nnz) - R.row_ptr[rows]
-    slot = sp_[rows // 64] + 64 * d + rows % 64
+    p = pos[rows]
+    slot = sp_[p // 16] + 16 * d + p % 16
     col[slot] = R.col
     val[slot] = R.val
-    return sp_, nd, col, val
+    assert len(nd) == ns
+    return sp_, nd, slot_row, col, val
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 1000, 4099])
+@pytest.mark.parametrize("n", [1, 15, 255, 256, 1000, 4099])
 def test_csr_to_slices_layout(n):
     r, c, v, nr, nc = synth.random_pattern(n, 3000, 0.004, np.random.default_rng(200 + n), empty_rows=0.2,
                                            long_rows=min(2, n), long_len=700)
     R = oracle.csr_from_coo(nr, nc, r, c, v)
     S = sp.csr_to_slices(gpu_csr(sp, r, c, v, nr, nc))
-    sp_, nd, col, val = slices_numpy(R)
+    sp_, nd, slot_row, col, val = slices_numpy(R)
     assert np.array_equal(to_np(S.slice_ptr), sp_)
     assert np.array_equal(to_np(S.slice_nd), nd)
+    assert np.array_equal(to_np(S.slot_row), slot_row)
     assert np.array_equal(to_np(S.bl_col), col)
     assert np.array_equal(to_np(S.bl_val).view(np.uint64), val.view(np.uint64))
 
