@@ -54,8 +54,8 @@ def parse():
                          "strides: the access-pattern microbenchmarks of the inner loop")
     ap.add_argument("--no-c3", action="store_true",
                     help="leave out the mixed-precision block on the symmetric-diagonals matrix")
-    ap.add_argument("--workload", choices=["powerlaw", "symdiag"], default="powerlaw",
-                    help="symdiag: time only the symmetric-diagonals products named by --only (profiling runs)")
+    ap.add_argument("--workload", choices=["powerlaw", "symdiag", "hamiltonian"], default="powerlaw",
+                    help="symdiag / hamiltonian: time only that matrix's products named by --only (profiling runs)")
     ap.add_argument("--tune-cache", default="",
                     help="autotuner cache file (default: a fresh one, i.e. tune on this device now); "
                          "profiling runs share one so they time the same kernels")
@@ -711,9 +711,10 @@ def mixed_precision_c3(torch, sp, dev, W3, steps, n_sample=4000):
     """FP64 against reduced-precision value storage (FP32, BF16; FP64
     vectors) on the symmetric-diagonals matrix, in CRS, JDS, blocked JDS,
     DIA, symmetric DIA and one-triangle CRS: time, GFLOP/s, algorithmic bytes, fraction of
-    8 TB/s, speed-up over the same format in FP64, and the error against the
+    8 TB/s, speed-up over the same format in FP64, the error against the
     FP64 product (the library's FP64 CRS, all rows, scaled by
-    D_i = sum_j |a_ij||x_j|).  Each product's output on a seeded sample of
+    D_i = sum_j |a_ij||x_j|) and the committed counter runs' L2-fill bytes
+    per launch (null when the kernel sources changed since).  Each product's output on a seeded sample of
     rows is kept for the oracle check of the CPU leg."""
     n, nnz, x = W3["n"], W3["nnz"], W3["x"]
     y = torch.empty(n, dtype=torch.float64, device=dev)
@@ -746,7 +747,8 @@ def mixed_precision_c3(torch, sp, dev, W3, steps, n_sample=4000):
                                     "algorithmic_bytes": int(bmin), "algorithmic_GBs": round(gbs, 1),
                                     "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
                                     "speedup_vs_fp64": round(fp64_ms[fam] / ms, 3),
-                                    "max_rel_err_vs_fp64_product": err}
+                                    "max_rel_err_vs_fp64_product": err,
+                                    "l2_fill_bytes": measured_traffic(name, "symdiag")}
         del ks
     W3["samples"] = (rows, samples)
     return out
@@ -796,12 +798,12 @@ def suite_symdiag(torch, sp, dev, steps):
     return out
 
 
-def suite_hamiltonian(torch, sp, dev, steps):
+def load_hamiltonian(torch, sp, dev, tune_cache=""):
     """A symmetric matrix shaped like the paper's Hamiltonian (the diagonal,
     six mirrored pairs of 70%-filled outer diagonals, 2-3 scattered entries
-    per row and triangle inside a band of 500): CRS, JDS, blocked JDS and the
-    DIA hybrid with its remainder in CRS, in row-order slices, and over one
-    triangle of the diagonals."""
+    per row and triangle inside a band of 500) in CRS, JDS, blocked JDS and
+    the DIA hybrid with its remainder in CRS, in window-sorted slices, and
+    over one triangle of the diagonals; launch shapes autotuned."""
     import synth
     from paper_0910_4836_amd import autotune
     r, c, v, n, _ = synth.heavy_diagonals_band()
@@ -810,36 +812,52 @@ def suite_hamiltonian(torch, sp, dev, steps):
     A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
     del r, c, v
     J = sp.jds_from_csr(A)
-    tuner = autotune.Autotuner(cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    tuner = autotune.Autotuner(cache_path=tune_cache or os.path.join(tempfile.mkdtemp(), "autotune.json"))
     autotune.tune_crs(tuner, A, x, J.ndiag)
     ju, jm, jw = tuner.tune_jds(J, x)
     bC, bR, bU, bW = tuner.tune_blocked(J, x)
     B = sp.jds_blocked_from_jds(J, bC)
-    D = sp.dia_from_csr(A)
-    Ds = sp.dia_from_csr(A, sliced=True)
-    Dy = sp.dia_from_csr(A, symmetric=True, sliced=True)
+    return {"n": n, "nnz": nnz, "x": x, "A": A, "J": J, "B": B, "D": sp.dia_from_csr(A),
+            "Ds": sp.dia_from_csr(A, sliced=True), "Dy": sp.dia_from_csr(A, symmetric=True, sliced=True),
+            "tune": {"jds": (ju, jm, jw), "blocked": (bR, bU, bW)}}
+
+
+def hamiltonian_kernels(sp, H, y):
+    """(name, launch, algorithmic bytes) of the Hamiltonian-shaped products."""
+    A, J, B, D, Ds, Dy, x = H["A"], H["J"], H["B"], H["D"], H["Ds"], H["Dy"], H["x"]
+    n, nnz = H["n"], H["nnz"]
+    ju, jm, jw = H["tune"]["jds"]
+    bR, bU, bW = H["tune"]["blocked"]
+    return [("crs", lambda: sp.spmv_crs(A, x, y), bytes_crs(nnz, n, n, 8, 8)),
+            ("jds", lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm, wg_waves=jw),
+             bytes_jds(nnz, n, n, J.ndiag, 8, 8)),
+            ("blocked", lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW),
+             bytes_blocked(nnz, n, n, B.n_slices, 8, 8)),
+            ("dia_crs_remainder", lambda: sp.spmv_dia(D, x, y), bytes_dia(D, 8, 8)),
+            ("dia_sliced_remainder", lambda: sp.spmv_dia(Ds, x, y), bytes_dia(Ds, 8, 8)),
+            ("dia_sym_sliced_remainder", lambda: sp.spmv_dia(Dy, x, y), bytes_dia(Dy, 8, 8))]
+
+
+def suite_hamiltonian(torch, sp, dev, steps):
+    """The Hamiltonian-shaped products: time, rate, and agreement with the
+    library's FP64 CRS product."""
+    H = load_hamiltonian(torch, sp, dev)
+    n, nnz, A, D, Ds, Dy = H["n"], H["nnz"], H["A"], H["D"], H["Ds"], H["Dy"]
     y = torch.empty(n, dtype=torch.float64, device=dev)
-    ks = [("crs", lambda: sp.spmv_crs(A, x, y)),
-          ("jds", lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
-          ("blocked", lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW)),
-          ("dia_crs_remainder", lambda: sp.spmv_dia(D, x, y)),
-          ("dia_sliced_remainder", lambda: sp.spmv_dia(Ds, x, y)),
-          ("dia_sym_sliced_remainder", lambda: sp.spmv_dia(Dy, x, y))]
-    _, per = time_loop(torch, ks, max(20, steps // 4), 5)
-    bmin = {"crs": bytes_crs(nnz, n, n, 8, 8), "jds": bytes_jds(nnz, n, n, J.ndiag, 8, 8),
-            "blocked": bytes_blocked(nnz, n, n, B.n_slices, 8, 8), "dia_crs_remainder": bytes_dia(D, 8, 8),
-            "dia_sliced_remainder": bytes_dia(Ds, 8, 8), "dia_sym_sliced_remainder": bytes_dia(Dy, 8, 8)}
+    ks = hamiltonian_kernels(sp, H, y)
+    _, per = time_loop(torch, [(k, f) for k, f, _ in ks], max(20, steps // 4), 5)
     out = {"workload": f"Hamiltonian-shaped symmetric matrix n={n} nnz={nnz} (diagonal, 6 mirrored pairs of "
                        "70%-filled outer diagonals, band of 500), FP64",
            "dia": {"stored_diagonals": int(D.ndia), "remainder_nnz": int(D.rem.nnz),
                    "remainder_padded_slots": int(Ds.rem_slices.bl_col.numel()),
                    "sym_stored_diagonals": int(Dy.ndia), "sym_remainder_nnz": int(Dy.rem.nnz)},
            "kernels": {}}
-    y_ref = sp.spmv_crs(A, x)
-    for k, fn in ks:
-        out["kernels"][k] = _kernel_entry(k, 2.0 * nnz, bmin[k], per[k])
+    y_ref = sp.spmv_crs(A, H["x"])
+    for k, fn, bmin in ks:
+        out["kernels"][k] = _kernel_entry(k, 2.0 * nnz, bmin, per[k])
         fn()
-        out["kernels"][k]["max_rel_err_vs_fp64_crs"] = _rel_err_gpu(torch, sp, A, x, y, y_ref)
+        out["kernels"][k]["max_rel_err_vs_fp64_crs"] = _rel_err_gpu(torch, sp, A, H["x"], y, y_ref)
+        out["kernels"][k]["l2_fill_bytes"] = measured_traffic(k, "hamiltonian")
     return out
 
 
@@ -1179,14 +1197,29 @@ def run_symdiag_only(torch, sp, dev, args):
     W3 = load_symdiag(torch, sp, dev, args.tune_cache)
     y = torch.empty(W3["n"], dtype=torch.float64, device=dev)
     keep = set(args.only.split(",")) if args.only else None
-    out = {"workload": "symdiag", "kernels": {}}
+    out = {"workload": "symdiag", "autotuned": W3["tune"], "kernels": {}, "algorithmic_bytes": {}}
     for vdt in (torch.float64, torch.float32, torch.bfloat16):
-        ks = [(k, f) for k, f, _ in symdiag_kernels(torch, sp, W3, vdt, y) if keep is None or k in keep]
-        if not ks:
+        kb = [(k, f, b) for k, f, b in symdiag_kernels(torch, sp, W3, vdt, y) if keep is None or k in keep]
+        if not kb:
             continue
-        _, per = time_loop(torch, ks, args.steps, args.warmup)
+        _, per = time_loop(torch, [(k, f) for k, f, _ in kb], args.steps, args.warmup)
         out["kernels"].update({k: round(ms, 5) for k, ms in per.items()})
+        out["algorithmic_bytes"].update({k: int(b) for k, _, b in kb})
     print(json.dumps(out), flush=True)
+
+
+def run_hamiltonian_only(torch, sp, dev, args):
+    """Profiling runs of the Hamiltonian-shaped products: the kernels named by
+    --only (all six if none), eager loop, one JSON line."""
+    H = load_hamiltonian(torch, sp, dev, args.tune_cache)
+    y = torch.empty(H["n"], dtype=torch.float64, device=dev)
+    keep = set(args.only.split(",")) if args.only else None
+    kb = [(k, f, b) for k, f, b in hamiltonian_kernels(sp, H, y) if keep is None or k in keep]
+    _, per = time_loop(torch, [(k, f) for k, f, _ in kb], args.steps, args.warmup)
+    print(json.dumps({"workload": "hamiltonian", "n": H["n"], "nnz": H["nnz"],
+                      "autotuned": {"jds": H["tune"]["jds"], "blocked": H["tune"]["blocked"], "blocked_C": H["B"].C},
+                      "kernels": {k: round(ms, 5) for k, ms in per.items()},
+                      "algorithmic_bytes": {k: int(b) for k, _, b in kb}}), flush=True)
 
 
 def main():
@@ -1205,6 +1238,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "symdiag":
         run_symdiag_only(torch, sp, dev, args)
+        return
+    if args.workload == "hamiltonian":
+        run_hamiltonian_only(torch, sp, dev, args)
         return
     W = load_powerlaw(torch, sp, dev, args.tune_cache)
     print("# power-law workload built", file=sys.stderr, flush=True)
