@@ -52,17 +52,19 @@ __device__ __forceinline__ double dia_row_sum(const DiaArgs &a, int64_t i)
 {
     const VT *__restrict__ dia = (const VT *)a.dia + i;
     const XT *__restrict__ x = (const XT *)a.x;
+    // U diagonals per trip, the last trip masked (diagonals past ndia are
+    // not loaded), so that every trip has all its loads in flight at once
     constexpr int U = 8;
     double s = 0.0;
-    int k = 0;
-    for (; k + U <= a.ndia; k += U) {
+    for (int k = 0; k < a.ndia; k += U) {
         VT v[U];
         XT xv[U];
         bool in[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t j = i + a.off[k + u];
-            in[u] = j >= 0 && j < a.n_cols;
+            const bool live = k + u < a.ndia;
+            const int64_t j = i + a.off[live ? k + u : 0];
+            in[u] = live && j >= 0 && j < a.n_cols;
             if (in[u]) {
                 v[u] = ld_stream(dia + (int64_t)(k + u) * a.n_rows);
                 xv[u] = x[j];
@@ -72,20 +74,17 @@ __device__ __forceinline__ double dia_row_sum(const DiaArgs &a, int64_t i)
         for (int u = 0; u < U; ++u)
             if (in[u]) s = fma(to_f64(v[u]), to_f64(xv[u]), s);
     }
-    for (; k < a.ndia; ++k) {
-        const int64_t j = i + a.off[k];
-        if (j >= 0 && j < a.n_cols) s = fma(to_f64(ld_stream(dia + (int64_t)k * a.n_rows)), to_f64(x[j]), s);
-    }
     if (SYM) {
-        k = 0;
-        for (; k + U <= a.ndia; k += U) {
+        for (int k = 0; k < a.ndia; k += U) {
             VT v[U];
             XT xv[U];
             bool in[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t j = i - a.off[k + u];
-                in[u] = a.off[k + u] > 0 && j >= 0;
+                const bool live = k + u < a.ndia;
+                const int32_t o = a.off[live ? k + u : 0];
+                const int64_t j = i - o;
+                in[u] = live && o > 0 && j >= 0;
                 if (in[u]) {
                     v[u] = ld_stream((const VT *)a.dia + (int64_t)(k + u) * a.n_rows + j);
                     xv[u] = x[j];
@@ -94,11 +93,6 @@ __device__ __forceinline__ double dia_row_sum(const DiaArgs &a, int64_t i)
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (in[u]) s = fma(to_f64(v[u]), to_f64(xv[u]), s);
-        }
-        for (; k < a.ndia; ++k) {
-            const int64_t j = i - a.off[k];
-            if (a.off[k] > 0 && j >= 0)
-                s = fma(to_f64(ld_stream((const VT *)a.dia + (int64_t)k * a.n_rows + j)), to_f64(x[j]), s);
         }
     }
     return s;
@@ -144,26 +138,26 @@ __global__ __launch_bounds__(DIA_THREADS) void dia_sliced_kernel(DiaArgs a)
             const VT *__restrict__ rv = (const VT *)a.rem_val;
             const XT *__restrict__ x = (const XT *)a.x;
             double s = part[lr];
+            // UR entries per trip, the last trip masked like the diagonals'
             constexpr int UR = 4;
-            int32_t d = 0;
-            for (; d + UR <= nd; d += UR) {
+            for (int32_t d = 0; d < nd; d += UR) {
                 int32_t c[UR];
                 VT v[UR];
-#pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    c[u] = ld_stream(a.rem_col + sp + (int64_t)(d + u) * SPMV_REM_SLICE);
-                    v[u] = ld_stream(rv + sp + (int64_t)(d + u) * SPMV_REM_SLICE);
-                }
                 XT xv[UR];
 #pragma unroll
-                for (int u = 0; u < UR; ++u) xv[u] = x[c[u] >= 0 ? c[u] : 0];
+                for (int u = 0; u < UR; ++u) {
+                    c[u] = -1;
+                    if (d + u < nd) {
+                        c[u] = ld_stream(a.rem_col + sp + (int64_t)(d + u) * SPMV_REM_SLICE);
+                        v[u] = ld_stream(rv + sp + (int64_t)(d + u) * SPMV_REM_SLICE);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UR; ++u)
+                    if (c[u] >= 0) xv[u] = x[c[u]];
 #pragma unroll
                 for (int u = 0; u < UR; ++u)
                     if (c[u] >= 0) s = fma(to_f64(v[u]), to_f64(xv[u]), s);
-            }
-            for (; d < nd; ++d) {
-                const int32_t c = ld_stream(a.rem_col + sp + (int64_t)d * SPMV_REM_SLICE);
-                if (c >= 0) s = fma(to_f64(ld_stream(rv + sp + (int64_t)d * SPMV_REM_SLICE)), to_f64(x[c]), s);
             }
             part[lr] = s;
         }
