@@ -84,6 +84,17 @@ def test_host_side_validation_without_gpu():
     offs = np.array([-3], dtype=np.int32)
     st = lib.spmv_dia_sym(10, 1, spmv_mod._h_i32(offs), 1, 0, None, None, None, 1, 1, 0, 1.0, 0.0, None)
     assert st == 1 and b">= 0" in lib.spmv_last_error()
+    # DIA with the remainder in window-sorted slices: square for symmetric
+    # storage; a remainder needs its slot rows
+    st = lib.spmv_dia_sliced(10, 12, 0, None, None, 0, None, None, None, None, None, 1, 1, 0, 1.0, 0.0, 1, None)
+    assert st == 1 and b"square" in lib.spmv_last_error()
+    st = lib.spmv_dia_sliced(10, 10, 0, None, None, 0, 1, 1, None, 1, 1, 1, 1, 0, 1.0, 0.0, 0, None)
+    assert st == 1 and b"null remainder slices" in lib.spmv_last_error()
+    st = lib.spmv_csr_to_slices(10, 1, 1, 1, 0, 1, 1, 1, None, None, 0, spmv_mod.C.byref(spmv_mod.C.c_int64(0)), 1,
+                                16, None)
+    assert st == 1 and b"workspace" in lib.spmv_last_error()
+    st = lib.spmv_csr_to_slices(-1, None, None, None, 0, None, None, None, None, None, 0, None, None, 0, None)
+    assert st == 1 and b"n_rows < 0" in lib.spmv_last_error()
     # access-pattern probe: a stride of at least 1
     st = lib.spmv_stride_probe(100, 0, None, None, None, 0, None, 0, None)
     assert st == 1 and b"k < 1" in lib.spmv_last_error()
