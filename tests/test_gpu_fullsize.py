@@ -225,6 +225,35 @@ def test_symmetric_diagonals_sampled():
             assert np.all(np.abs(to_np(fn())[rows] - wq) <= lim), (vdt, name)
 
 
+def test_hamiltonian_shaped_dia_sampled():
+    """The Hamiltonian-shaped matrix (n = 6 M): the DIA hybrid with its
+    remainder in CRS, in window-sorted slices and over one triangle of the
+    diagonals, and CRS, on sampled rows against the oracle; the window-sorted
+    forms bit-identical to the CRS-remainder forms on every row."""
+    r, c, v, n, _ = synth.heavy_diagonals_band()
+    x = synth.uniform_vector(n, synth.rng_for(6, 1))
+    A = sp.csr_from_coo(n, n, to_dev(r), to_dev(c), to_dev(v))
+    rows = pick(n, 16, extra=[0, 1, 255, 256, n // 2, n - 257, n - 1])
+    sub = coo_rows(n, r, c, v, rows)
+    del r, c, v
+    want = oracle.spmv_crs(sub, x)
+    D = oracle.row_absdot(sub, x)
+    xd = to_dev(x)
+    e = oracle.rel_err(to_np(sp.spmv_crs(A, xd))[rows], want, D).max()
+    assert e <= FP64_TOL, f"crs: {e:.3e}"
+    for sym in (False, True):
+        Dc = sp.dia_from_csr(A, symmetric=sym)
+        Ds = sp.dia_from_csr(A, symmetric=sym, sliced=True)
+        assert Dc.ndia == (7 if sym else 13) and Dc.rem.nnz > 0
+        # window-sorted padding stays small on this matrix
+        assert Ds.rem_slices.bl_col.numel() <= 1.1 * Ds.rem.nnz
+        yc, ys = sp.spmv_dia(Dc, xd), sp.spmv_dia(Ds, xd)
+        assert torch.equal(yc, ys), f"sym={sym}: sliced remainder differs from the CRS remainder"
+        e = oracle.rel_err(to_np(ys)[rows], want, D).max()
+        assert e <= FP64_TOL, f"dia sym={sym}: {e:.3e}"
+        del Dc, Ds, yc, ys
+
+
 def test_chebyshev_operator_sampled():
     """The banded + uniform FP32 operator: forward and transposed products."""
     from paper_0910_4836_amd import autograd as AG
