@@ -969,9 +969,9 @@ class DIA:
         """Same structure, other values (rem_val: the remainder CRS's values;
         the sliced copy, if any, is rebuilt from them)."""
         rem = self.rem if rem_val is None else self.rem.with_values(rem_val)
-        D = DIA(self.n_rows, self.n_cols, self.offsets, dia_val, rem, self.symmetric)
-        if self.rem_slices is not None:
-            D.rem_slices = csr_to_slices(rem) if rem.nnz else self.rem_slices
+        D = DIA(self.n_rows, self.n_cols, self.offsets, dia_val, rem, self.symmetric, self.rem_slices)
+        if self.rem_slices is not None and rem_val is not None and rem.nnz:
+            D.rem_slices = csr_to_slices(rem)
         return D
 
 

@@ -368,3 +368,27 @@ def test_dia_sliced_integer_exact_and_empty_remainder():
     A = sp.csr_from_coo(5, 4, to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0)))
     D = sp.dia_from_csr(A, sliced=True)
     assert to_np(sp.spmv_dia(D, to_dev(np.ones(4)), to_dev(np.full(5, 2.0)), 1.0, 0.5)).tolist() == [1.0] * 5
+
+
+def test_dia_with_values_rebuilds_the_sliced_remainder():
+    """DIA.with_values: new diagonal and remainder values reach the sliced
+    remainder (its product equals the CRS-remainder form given the same
+    values, bit for bit); new diagonal values alone keep the remainder
+    slices."""
+    r, c, v, nr, nc, _ = planted(24, 2000, 2100)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    x = to_dev(np.random.default_rng(25).uniform(-1, 1, nc))
+    D = sp.dia_from_csr(A, sliced=True)
+    Dc = sp.dia_from_csr(A)
+    conv = lambda t: sp.spmv_convert_values(t, torch.float32)
+    Dq = D.with_values(conv(D.dia_val), conv(D.rem.val))
+    Dcq = Dc.with_values(conv(Dc.dia_val), conv(Dc.rem.val))
+    assert Dq.rem_slices.bl_val.dtype == torch.float32
+    assert torch.equal(sp.spmv_dia(Dq, x), sp.spmv_dia(Dcq, x))
+    D2 = D.with_values(D.dia_val * 2)
+    assert D2.rem_slices is D.rem_slices
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    xn = to_np(x)
+    on = np.isin(R.col.astype(np.int64) - R.row_index(), D.offsets)      # entries on a stored diagonal
+    R2 = oracle.CSR(nr, nc, R.row_ptr, R.col, np.where(on, 2 * R.val, R.val))
+    assert max_err(sp.spmv_dia(D2, x), oracle.spmv_crs(R2, xn), oracle.row_absdot(R2, xn)) <= FP64_TOL
