@@ -492,7 +492,7 @@ def powerlaw_kernels(sp, W, torch):
 
 def bytes_dia(D, s_v, s_x):
     """Stored diagonals read over their spans (zeros inside a span included),
-    the remainder as CRS (or its padded row-order slices, 12 bytes of slice
+    the remainder as CRS (or its padded window-sorted slices, 12 bytes of slice
     header each), x and y once."""
     span = sum(max(0, min(D.n_rows, D.n_cols - int(o)) - max(0, -int(o))) for o in D.offsets)
     if D.rem_slices is not None and D.rem.nnz:
