@@ -493,11 +493,11 @@ def powerlaw_kernels(sp, W, torch):
 def bytes_dia(D, s_v, s_x):
     """Stored diagonals read over their spans (zeros inside a span included),
     the remainder as CRS (or its padded window-sorted slices, 12 bytes of slice
-    header each), x and y once."""
+    header each and one byte of slot row per row), x and y once."""
     span = sum(max(0, min(D.n_rows, D.n_cols - int(o)) - max(0, -int(o))) for o in D.offsets)
     if D.rem_slices is not None and D.rem.nnz:
         R = D.rem_slices
-        rem = len(R.bl_col) * (s_v + 4) + 12 * len(R.slice_nd)
+        rem = len(R.bl_col) * (s_v + 4) + 12 * len(R.slice_nd) + len(R.slot_row)
     else:
         rem = D.rem.nnz * (s_v + 4) + (4 * (D.n_rows + 1) if D.rem.nnz else 0)
     return span * s_v + rem + s_x * (D.n_cols + D.n_rows)

@@ -32,10 +32,10 @@ def test_dia_bytes_count_spans():
     assert bench.bytes_dia(D, 8, 8) == 11 * 8 + 3 * 12 + 4 * 7 + 8 * 12
 
     class T:                                        # one slice of depth 2: 128 padded slots
-        bl_col, slice_nd = np.zeros(128), np.zeros(1)
+        bl_col, slice_nd, slot_row = np.zeros(128), np.zeros(1), np.zeros(6)
 
     D.rem_slices = T()
-    assert bench.bytes_dia(D, 8, 8) == 11 * 8 + 128 * 12 + 12 + 8 * 12
+    assert bench.bytes_dia(D, 8, 8) == 11 * 8 + 128 * 12 + 12 + 6 + 8 * 12
 
 
 def test_roofline_record():
