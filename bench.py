@@ -54,6 +54,8 @@ def parse():
                          "strides: the access-pattern microbenchmarks of the inner loop")
     ap.add_argument("--no-c3", action="store_true",
                     help="leave out the mixed-precision block on the symmetric-diagonals matrix")
+    ap.add_argument("--no-hamiltonian", action="store_true",
+                    help="leave out the DIA-hybrid block on the Hamiltonian-shaped matrix")
     ap.add_argument("--workload", choices=["powerlaw", "symdiag", "hamiltonian"], default="powerlaw",
                     help="symdiag / hamiltonian: time only that matrix's products named by --only (profiling runs)")
     ap.add_argument("--tune-cache", default="",
@@ -1325,6 +1327,10 @@ def main():
         out["mixed_precision_c3"] = mixed_precision_c3(torch, sp, dev, W3, args.steps)
         for k in ("A", "J", "B", "D", "Ds"):
             W3.pop(k)
+        torch.cuda.empty_cache()
+    if not args.only and not args.no_hamiltonian:
+        print("# DIA hybrid block: Hamiltonian-shaped matrix", file=sys.stderr, flush=True)
+        out["dia_hybrid_hamiltonian"] = suite_hamiltonian(torch, sp, dev, args.steps)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         print("# CPU oracle baseline", file=sys.stderr, flush=True)
