@@ -516,13 +516,14 @@ def host_cpu_model():
     return platform.processor() or platform.machine()
 
 
-def cpu_baseline(W, budget_s=20.0, W3=None):
+def cpu_baseline(W, budget_s=20.0, W3=None, HH=None):
     """The serial oracle (plain C, one core) on the same step, repeated for about
     budget_s seconds of CPU time; returns GFLOP/s.  The calling thread (the
     one that runs the oracle through ctypes) is pinned to one core for the
     duration, as the paper pins its threads; the GPU work is done by then.
-    With W3 (the symmetric-diagonals workload), the sampled rows of its
-    mixed-precision products are also checked against the oracle."""
+    With W3 (the symmetric-diagonals workload) and HH (what the
+    Hamiltonian-shaped block kept), the sampled rows of their products are
+    also checked against the oracle, after the timing."""
     import oracle
     r, c, v, n, x = W["host"]
     A = oracle.csr_from_coo(n, n, r, c, v)
@@ -558,6 +559,9 @@ def cpu_baseline(W, budget_s=20.0, W3=None):
            "pinned_core": core, "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
     if W3 is not None and "samples" in W3:
         out["symdiag_sampled_rows_max_rel_err_vs_oracle"] = c3_oracle_check(W3)
+    if HH:
+        out["hamiltonian_sampled_rows_max_rel_err_vs_oracle"] = sampled_oracle_check(HH["host"], HH["x"], HH["rows"],
+                                                                                     HH["samples"])
     return out
 
 
@@ -756,20 +760,27 @@ def mixed_precision_c3(torch, sp, dev, W3, steps, n_sample=4000):
     return out
 
 
-def c3_oracle_check(W3):
-    """The sampled rows of every product of the mixed-precision block against
-    the serial FP64 oracle (unrounded values): max_i |y_i - y_oracle_i| / D_i."""
+def sampled_oracle_check(host, x, rows, samples):
+    """Sampled rows of products against the serial FP64 oracle (unrounded
+    values): max_i |y_i - y_oracle_i| / D_i over the rows, per product.  Only
+    the triplets of those rows go through the oracle's COO -> CRS."""
     import oracle
-    r, c, v, n = W3["host"]
-    rows, samples = W3["samples"]
+    r, c, v, n = host
     keep = np.zeros(n, dtype=bool)
     keep[rows] = True
     sel = keep[r]
     R = oracle.csr_from_coo(n, n, r[sel], c[sel], v[sel])
-    x = W3["x"].cpu().numpy()
+    x = x.cpu().numpy()
     want = oracle.spmv_crs(R, x)[rows]
     D = oracle.row_absdot(R, x)[rows]
     return {name: float(oracle.rel_err(got, want, D).max()) for name, got in samples.items()}
+
+
+def c3_oracle_check(W3):
+    """The sampled rows of every product of the mixed-precision block against
+    the serial FP64 oracle."""
+    rows, samples = W3["samples"]
+    return sampled_oracle_check(W3["host"], W3["x"], rows, samples)
 
 
 def suite_symdiag(torch, sp, dev, steps):
@@ -812,7 +823,6 @@ def load_hamiltonian(torch, sp, dev, tune_cache=""):
     nnz = len(r)
     x = torch.from_numpy(synth.uniform_vector(n, synth.rng_for(6, 1))).to(dev)
     A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
-    del r, c, v
     J = sp.jds_from_csr(A)
     tuner = autotune.Autotuner(cache_path=tune_cache or os.path.join(tempfile.mkdtemp(), "autotune.json"))
     autotune.tune_crs(tuner, A, x, J.ndiag)
@@ -821,7 +831,7 @@ def load_hamiltonian(torch, sp, dev, tune_cache=""):
     B = sp.jds_blocked_from_jds(J, bC)
     return {"n": n, "nnz": nnz, "x": x, "A": A, "J": J, "B": B, "D": sp.dia_from_csr(A),
             "Ds": sp.dia_from_csr(A, sliced=True), "Dy": sp.dia_from_csr(A, symmetric=True, sliced=True),
-            "tune": {"jds": (ju, jm, jw), "blocked": (bR, bU, bW)}}
+            "tune": {"jds": (ju, jm, jw), "blocked": (bR, bU, bW)}, "host": (r, c, v, n)}
 
 
 def hamiltonian_kernels(sp, H, y):
@@ -840,9 +850,11 @@ def hamiltonian_kernels(sp, H, y):
             ("dia_sym_sliced_remainder", lambda: sp.spmv_dia(Dy, x, y), bytes_dia(Dy, 8, 8))]
 
 
-def suite_hamiltonian(torch, sp, dev, steps):
+def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000):
     """The Hamiltonian-shaped products: time, rate, and agreement with the
-    library's FP64 CRS product."""
+    library's FP64 CRS product.  With `keep` (a dict), each product's output
+    on a seeded sample of rows and the host triplets are left there for the
+    oracle check of the CPU leg."""
     H = load_hamiltonian(torch, sp, dev)
     n, nnz, A, D, Ds, Dy = H["n"], H["nnz"], H["A"], H["D"], H["Ds"], H["Dy"]
     y = torch.empty(n, dtype=torch.float64, device=dev)
@@ -855,11 +867,17 @@ def suite_hamiltonian(torch, sp, dev, steps):
                    "sym_stored_diagonals": int(Dy.ndia), "sym_remainder_nnz": int(Dy.rem.nnz)},
            "kernels": {}}
     y_ref = sp.spmv_crs(A, H["x"])
+    rows = np.sort(np.random.default_rng(20091030).choice(n, n_sample, replace=False))
+    rows_d = torch.from_numpy(rows).to(dev)
+    samples = {}
     for k, fn, bmin in ks:
         out["kernels"][k] = _kernel_entry(k, 2.0 * nnz, bmin, per[k])
         fn()
+        samples[k] = y[rows_d].cpu().numpy()
         out["kernels"][k]["max_rel_err_vs_fp64_crs"] = _rel_err_gpu(torch, sp, A, H["x"], y, y_ref)
         out["kernels"][k]["l2_fill_bytes"] = measured_traffic(k, "hamiltonian")
+    if keep is not None:
+        keep.update(host=H["host"], x=H["x"], rows=rows, samples=samples)
     return out
 
 
@@ -1328,16 +1346,17 @@ def main():
         for k in ("A", "J", "B", "D", "Ds"):
             W3.pop(k)
         torch.cuda.empty_cache()
+    HH = {}
     if not args.only and not args.no_hamiltonian:
         print("# DIA hybrid block: Hamiltonian-shaped matrix", file=sys.stderr, flush=True)
-        out["dia_hybrid_hamiltonian"] = suite_hamiltonian(torch, sp, dev, args.steps)
+        out["dia_hybrid_hamiltonian"] = suite_hamiltonian(torch, sp, dev, args.steps, keep=HH)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         print("# CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(W, W3=W3)
+        out["cpu_baseline"] = cpu_baseline(W, W3=W3, HH=HH)
     else:
         out["cpu_baseline"] = None
-    del W3
+    del W3, HH
     # the step's products from cold caches (MALL and L2 flushed before each launch)
     cold = cold_times(torch, sp, dev, ks)
     out["cold"] = {name: {"median_ms": round(ms, 5), "gflops": round(2.0 * W["nnz"] / (ms * 1e-3) / 1e9, 1),
