@@ -1103,8 +1103,9 @@ def suite_stride_dist(torch, sp, dev, W):
     """The paper's stride distributions (Fig. 6a, Section 4.2) on the library's
     own arrays: CRS, RBJDS with one-row blocks, blocked JDS (RBJDS) with 64-
     and 1024-row slices, SOJDS with 1024-row slices, and JDS, for the
-    power-law matrix and a symmetric-diagonals matrix (the paper's matrix has
-    that shape).  A serial traversal is what the paper's CPU kernels do; a
+    power-law matrix, a symmetric-diagonals matrix and a Hamiltonian-shaped
+    one (partly filled outer diagonals and a band, the paper's matrix's
+    structure).  A serial traversal is what the paper's CPU kernels do; a
     wavefront reads 64 of these entries at once (the gather model)."""
     import synth
     out = {"unit": "fractions of all jumps; x is FP64, edges in bytes", "matrices": {}}
@@ -1125,6 +1126,11 @@ def suite_stride_dist(torch, sp, dev, W):
     A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
     J = sp.jds_from_csr(A)
     out["matrices"][f"symmetric diagonals n={n} nnz={len(r)}"] = schemes(A, J)
+    del A, J
+    r, c, v, n, _ = synth.heavy_diagonals_band(n=1_000_000)
+    A = sp.csr_from_coo(n, n, torch.from_numpy(r).to(dev), torch.from_numpy(c).to(dev), torch.from_numpy(v).to(dev))
+    J = sp.jds_from_csr(A)
+    out["matrices"][f"Hamiltonian-shaped n={n} nnz={len(r)}"] = schemes(A, J)
     del A, J
     return out
 
