@@ -850,11 +850,13 @@ def hamiltonian_kernels(sp, H, y):
             ("dia_sym_sliced_remainder", lambda: sp.spmv_dia(Dy, x, y), bytes_dia(Dy, 8, 8))]
 
 
-def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000):
+def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000, sweep=False):
     """The Hamiltonian-shaped products: time, rate, and agreement with the
     library's FP64 CRS product.  With `keep` (a dict), each product's output
     on a seeded sample of rows and the host triplets are left there for the
-    oracle check of the CPU leg."""
+    oracle check of the CPU leg.  With `sweep`, blocked JDS in slice order
+    (RBJDS) and in SOJDS order over slice heights 64..4096 (the paper's
+    block-size dependence, Fig. 5), same launch parameters."""
     H = load_hamiltonian(torch, sp, dev)
     n, nnz, A, D, Ds, Dy = H["n"], H["nnz"], H["A"], H["D"], H["Ds"], H["Dy"]
     y = torch.empty(n, dtype=torch.float64, device=dev)
@@ -878,6 +880,20 @@ def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000):
         out["kernels"][k]["l2_fill_bytes"] = measured_traffic(k, "hamiltonian")
     if keep is not None:
         keep.update(host=H["host"], x=H["x"], rows=rows, samples=samples)
+    if sweep:
+        bR, bU, bW = H["tune"]["blocked"]
+        J, x = H["J"], H["x"]
+        del H["B"], H["D"], H["Ds"], H["Dy"]
+        torch.cuda.empty_cache()
+        out["block_size_sweep_us"] = {}
+        for C_ in (64, 128, 256, 512, 1024, 4096):
+            for so in (False, True):
+                Bc = sp.jds_blocked_from_jds(J, C_, sojds=so)
+                name = f"{'sojds' if so else 'rbjds'}_{C_}"
+                _, pc = time_loop(torch, [(name, lambda: sp.spmv_jds_blocked(Bc, x, y, rows_per_wave=bR, unroll=bU,
+                                                                             wg_waves=bW))], 20, 3)
+                out["block_size_sweep_us"][name] = round(pc[name] * 1e3, 1)
+                del Bc
     return out
 
 
@@ -1204,7 +1220,7 @@ def suite_lines(torch, sp, dev, W, steps, warmup, only=""):
                      ("one-shard-of-8", lambda: suite_shard(torch, sp, dev, W, steps)),
                      ("multi-vector", lambda: suite_spmm(torch, sp, dev, W, steps)),
                      ("symmetric-diagonals", lambda: suite_symdiag(torch, sp, dev, steps)),
-                     ("hamiltonian-shaped", lambda: suite_hamiltonian(torch, sp, dev, steps)),
+                     ("hamiltonian-shaped", lambda: suite_hamiltonian(torch, sp, dev, steps, sweep=True)),
                      ("chebyshev", lambda: suite_chebyshev(torch, sp, dev, steps)),
                      ("many-matrices", lambda: suite_batched(torch, sp, dev, steps))):
         if keep and name not in keep:
