@@ -856,7 +856,7 @@ def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000, sweep=Fal
     on a seeded sample of rows and the host triplets are left there for the
     oracle check of the CPU leg.  With `sweep`, blocked JDS in slice order
     (RBJDS) and in SOJDS order over slice heights 64..4096 (the paper's
-    block-size dependence, Fig. 5), same launch parameters."""
+    block-size dependence, Fig. 7), same launch parameters."""
     H = load_hamiltonian(torch, sp, dev)
     n, nnz, A, D, Ds, Dy = H["n"], H["nnz"], H["A"], H["D"], H["Ds"], H["Dy"]
     y = torch.empty(n, dtype=torch.float64, device=dev)
