@@ -392,3 +392,26 @@ def test_dia_with_values_rebuilds_the_sliced_remainder():
     on = np.isin(R.col.astype(np.int64) - R.row_index(), D.offsets)      # entries on a stored diagonal
     R2 = oracle.CSR(nr, nc, R.row_ptr, R.col, np.where(on, 2 * R.val, R.val))
     assert max_err(sp.spmv_dia(D2, x), oracle.spmv_crs(R2, xn), oracle.row_absdot(R2, xn)) <= FP64_TOL
+
+
+def test_dia_sliced_fp32_vectors_and_no_stored_diagonal():
+    """FP32 x and y (values FP64, FP32, BF16) through the sliced remainder,
+    bit-identical to the CRS remainder; and a matrix with no heavy diagonal
+    (every entry in the remainder, ndia = 0), against the oracle."""
+    r, c, v, nr, nc, _ = planted(26, 2500, 2600)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    rng = np.random.default_rng(27)
+    x = to_dev(rng.uniform(-1, 1, nc).astype(np.float32))
+    y0 = to_dev(rng.uniform(-1, 1, nr).astype(np.float32))
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        Aq = A.with_values(sp.spmv_convert_values(A.val, dt))
+        D, Ds = sp.dia_from_csr(Aq), sp.dia_from_csr(Aq, sliced=True)
+        a = sp.spmv_dia(D, x, y0.clone(), 0.5, -1.25)
+        b = sp.spmv_dia(Ds, x, y0.clone(), 0.5, -1.25)
+        assert a.dtype == torch.float32 and torch.equal(a, b), str(dt)
+    r, c, v, nr, nc = synth.random_pattern(3000, 2000, 0.003, np.random.default_rng(28), empty_rows=0.1)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    Ds = sp.dia_from_csr(gpu_csr(sp, r, c, v, nr, nc), sliced=True)
+    assert Ds.ndia == 0 and Ds.rem.nnz == R.nnz
+    xn = np.random.default_rng(29).uniform(-1, 1, nc)
+    assert max_err(sp.spmv_dia(Ds, to_dev(xn)), oracle.spmv_crs(R, xn), oracle.row_absdot(R, xn)) <= FP64_TOL
