@@ -612,7 +612,11 @@ spmv_status spmv_csr_to_slices(int32_t n_rows, const int32_t *row_ptr, const int
  * sum of row slot_row[p] with that row's remainder entries, so every row is
  * still one FP64 sum in the order of spmv_dia / spmv_dia_sym (its diagonals,
  * then its remainder in CRS order): the result is bit-identical to them.
- * rem_slice_ptr may be NULL when the remainder is empty. */
+ * rem_slice_ptr may be NULL when the remainder is empty; otherwise
+ * rem_slice_nd, rem_slot_row, rem_col, rem_val and x must be given
+ * (SPMV_ERR_INVALID_ARG).  Offsets, dtypes and sizes follow spmv_dia
+ * (symmetric = 1: spmv_dia_sym, and n_rows must equal n_cols).
+ * Asynchronous; allocates nothing. */
 spmv_status spmv_dia_sliced(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets,
                             const void *dia_val, spmv_dtype val_dt, const int64_t *rem_slice_ptr,
                             const int32_t *rem_slice_nd, const uint8_t *rem_slot_row, const int32_t *rem_col,
