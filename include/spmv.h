@@ -547,6 +547,9 @@ spmv_status spmv_dia_from_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const
  * bound of the reduced-precision rule); y is rounded to vec_dt once.  Zeros
  * stored inside a diagonal are multiplied like entries (an Inf or NaN in x
  * reaches those rows).  rem_row_ptr may be NULL when the remainder is empty.
+ * One lane walks a row's whole remainder, so the hybrid is meant for short
+ * remainder rows: a row with many remainder entries holds up its wavefront
+ * (and, in window-sorted slices, pads its slice to its length).
  * h_offsets: host copy of the ndia offsets. */
 spmv_status spmv_dia(int32_t n_rows, int32_t n_cols, int32_t ndia, const int32_t *h_offsets, const void *dia_val,
                      spmv_dtype val_dt, const int32_t *rem_row_ptr, const int32_t *rem_col, const void *rem_val,
