@@ -415,6 +415,9 @@ def load_powerlaw(torch, sp, dev, tune_cache=""):
     jds_u, jds_mi, jds_w = timed("autotune_jds_ms", lambda: tuner.tune_jds(J, xd))
     bC, bR, bU, bW = timed("autotune_blocked_ms", lambda: tuner.tune_blocked(J, xd))
     B = timed("jds_blocked_from_jds_ms", lambda: sp.jds_blocked_from_jds(J, bC))
+    # class plan or XCD-local tile plan, whichever the autotuner times faster
+    jds_tiled = timed("autotune_jds_launch_ms", lambda: tuner.tune_jds_launch(J, xd, jds_u, jds_mi, jds_w))
+    blk_tiled = timed("autotune_blocked_launch_ms", lambda: tuner.tune_blocked_launch(B, xd, bR, bU, bW))
     A32 = A.with_values(sp.spmv_convert_values(A.val, torch.float32))
     J32 = J.with_values(sp.spmv_convert_values(J.jd_val, torch.float32))
     B32 = B.with_values(sp.spmv_convert_values(B.bl_val, torch.float32))
@@ -429,10 +432,28 @@ def load_powerlaw(torch, sp, dev, tune_cache=""):
     timed("windowed_tile_plan_ms", lambda: sp.spmv_jds_blocked_tiles(BW, 32, 0, wW))
     host = (r, c, v, n, x)
     tune = {"crs_block_nnz": crs_bn, "jds_unroll": jds_u, "jds_max_iters": jds_mi, "jds_wg_waves": jds_w,
-            "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW,
-            "windowed_sigma": wS, "windowed_C": wC, "windowed_unroll": wU, "windowed_wg_waves": wW}
+            "jds_tiled": jds_tiled, "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU,
+            "blocked_wg_waves": bW, "blocked_tiled": blk_tiled, "windowed_sigma": wS, "windowed_C": wC,
+            "windowed_unroll": wU, "windowed_wg_waves": wW}
     return dict(A=A, J=J, B=B, A32=A32, J32=J32, B32=B32, S=S, RS=RS, BW=BW, x=xd, n=n, nnz=A.nnz, setup=setup,
                 gen_s=gen_s, host=host, tune=tune)
+
+
+def jds_launch(sp, T, x, y):
+    """The JDS product with the tuned launch shape and plan (class plan, or
+    the XCD-local tile plan when the autotuner timed it faster)."""
+    ju, jm, jw = T["jds_unroll"], T["jds_max_iters"], T["jds_wg_waves"]
+    if T.get("jds_tiled"):
+        return lambda J: lambda: sp.spmv_jds_tiled(J, x, y, unroll=ju, max_iters=jm, wg_waves=jw)
+    return lambda J: lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm, wg_waves=jw)
+
+
+def blocked_launch(sp, T, x, y):
+    """The blocked-JDS product with the tuned launch shape and plan."""
+    bR, bU, bW = T["blocked_rows_per_wave"], T["blocked_unroll"], T["blocked_wg_waves"]
+    if T.get("blocked_tiled"):
+        return lambda B: lambda: sp.spmv_jds_blocked_tiled(B, x, y, unroll=bU, rows_per_wave=bR, wg_waves=bW)
+    return lambda B: lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW)
 
 
 def powerlaw_kernels(sp, W, torch):
@@ -443,13 +464,14 @@ def powerlaw_kernels(sp, W, torch):
     T = W["tune"]
     ju, jm, jw = T["jds_unroll"], T["jds_max_iters"], T["jds_wg_waves"]
     bR, bU, bW = T["blocked_rows_per_wave"], T["blocked_unroll"], T["blocked_wg_waves"]
+    jl, bl = jds_launch(sp, T, x, y), blocked_launch(sp, T, x, y)
     ks = [
         ("crs_f64", lambda: sp.spmv_crs(W["A"], x, y)),
-        ("jds_f64", lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
-        ("blocked_f64", lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW)),
+        ("jds_f64", jl(J)),
+        ("blocked_f64", bl(B)),
         ("crs_f32val", lambda: sp.spmv_crs(W["A32"], x, y)),
-        ("jds_f32val", lambda: sp.spmv_jds(W["J32"], x, y, unroll=ju, max_iters=jm, wg_waves=jw)),
-        ("blocked_f32val", lambda: sp.spmv_jds_blocked(W["B32"], x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW)),
+        ("jds_f32val", jl(W["J32"])),
+        ("blocked_f32val", bl(W["B32"])),
     ]
     S = W["S"]
     S32 = W.setdefault("S32", S.with_values(sp.spmv_convert_values(S.val, torch.float32)))
@@ -668,6 +690,8 @@ def load_symdiag(torch, sp, dev, tune_cache=""):
     ju, jm, jw = tuner.tune_jds(J, x)
     bC, bR, bU, bW = tuner.tune_blocked(J, x)
     B = sp.jds_blocked_from_jds(J, bC)
+    jds_tiled = tuner.tune_jds_launch(J, x, ju, jm, jw)
+    blk_tiled = tuner.tune_blocked_launch(B, x, bR, bU, bW)
     setup = {}
     t0 = time.perf_counter()
     Dd = sp.dia_from_csr(A)
@@ -682,8 +706,9 @@ def load_symdiag(torch, sp, dev, tune_cache=""):
     torch.cuda.synchronize()
     setup["crs_sym_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
     sym_bn = autotune.tune_crs_sym(tuner, S, x, J.ndiag // 2 + 1)
-    tune = {"crs_block_nnz": crs_bn, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw, "blocked_C": bC,
-            "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW, "crs_sym_block_nnz": sym_bn}
+    tune = {"crs_block_nnz": crs_bn, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw,
+            "jds_tiled": jds_tiled, "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU,
+            "blocked_wg_waves": bW, "blocked_tiled": blk_tiled, "crs_sym_block_nnz": sym_bn}
     return dict(A=A, J=J, B=B, D=Dd, Ds=Ds, S=S, x=x, n=n, nnz=A.nnz, tune=tune, setup=setup, host=(r, c, v, n))
 
 
@@ -704,10 +729,8 @@ def symdiag_kernels(torch, sp, W3, vdt, y):
     Dsq = sp.DIA(Ds.n_rows, Ds.n_cols, Ds.offsets, conv(Ds.dia_val), Ds.rem, True)
     Sq = W3["S"].with_values(conv(W3["S"].upper.val))
     return [(f"crs_{tag}", lambda: sp.spmv_crs(Aq, x, y), bytes_crs(nnz, n, n, sv, 8)),
-            (f"jds_{tag}", lambda: sp.spmv_jds(Jq, x, y, unroll=ju, max_iters=jm, wg_waves=jw),
-             bytes_jds(nnz, n, n, J.ndiag, sv, 8)),
-            (f"blocked_{tag}", lambda: sp.spmv_jds_blocked(Bq, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW),
-             bytes_blocked(nnz, n, n, B.n_slices, sv, 8)),
+            (f"jds_{tag}", jds_launch(sp, T, x, y)(Jq), bytes_jds(nnz, n, n, J.ndiag, sv, 8)),
+            (f"blocked_{tag}", blocked_launch(sp, T, x, y)(Bq), bytes_blocked(nnz, n, n, B.n_slices, sv, 8)),
             (f"dia_{tag}", lambda: sp.spmv_dia(Dq, x, y), bytes_dia(Dd, sv, 8)),
             (f"dia_sym_{tag}", lambda: sp.spmv_dia(Dsq, x, y), bytes_dia(Ds, sv, 8)),
             (f"crs_sym_{tag}", lambda: sp.spmv_crs_sym(Sq, x, y), bytes_crs(Sq.nnz, n, n, sv, 8))]
@@ -829,22 +852,21 @@ def load_hamiltonian(torch, sp, dev, tune_cache=""):
     ju, jm, jw = tuner.tune_jds(J, x)
     bC, bR, bU, bW = tuner.tune_blocked(J, x)
     B = sp.jds_blocked_from_jds(J, bC)
+    T = {"jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw, "jds_tiled": tuner.tune_jds_launch(J, x, ju, jm, jw),
+         "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW,
+         "blocked_tiled": tuner.tune_blocked_launch(B, x, bR, bU, bW)}
     return {"n": n, "nnz": nnz, "x": x, "A": A, "J": J, "B": B, "D": sp.dia_from_csr(A),
             "Ds": sp.dia_from_csr(A, sliced=True), "Dy": sp.dia_from_csr(A, symmetric=True, sliced=True),
-            "tune": {"jds": (ju, jm, jw), "blocked": (bR, bU, bW)}, "host": (r, c, v, n)}
+            "tune": T, "host": (r, c, v, n)}
 
 
 def hamiltonian_kernels(sp, H, y):
     """(name, launch, algorithmic bytes) of the Hamiltonian-shaped products."""
     A, J, B, D, Ds, Dy, x = H["A"], H["J"], H["B"], H["D"], H["Ds"], H["Dy"], H["x"]
     n, nnz = H["n"], H["nnz"]
-    ju, jm, jw = H["tune"]["jds"]
-    bR, bU, bW = H["tune"]["blocked"]
     return [("crs", lambda: sp.spmv_crs(A, x, y), bytes_crs(nnz, n, n, 8, 8)),
-            ("jds", lambda: sp.spmv_jds(J, x, y, unroll=ju, max_iters=jm, wg_waves=jw),
-             bytes_jds(nnz, n, n, J.ndiag, 8, 8)),
-            ("blocked", lambda: sp.spmv_jds_blocked(B, x, y, rows_per_wave=bR, unroll=bU, wg_waves=bW),
-             bytes_blocked(nnz, n, n, B.n_slices, 8, 8)),
+            ("jds", jds_launch(sp, H["tune"], x, y)(J), bytes_jds(nnz, n, n, J.ndiag, 8, 8)),
+            ("blocked", blocked_launch(sp, H["tune"], x, y)(B), bytes_blocked(nnz, n, n, B.n_slices, 8, 8)),
             ("dia_crs_remainder", lambda: sp.spmv_dia(D, x, y), bytes_dia(D, 8, 8)),
             ("dia_sliced_remainder", lambda: sp.spmv_dia(Ds, x, y), bytes_dia(Ds, 8, 8)),
             ("dia_sym_sliced_remainder", lambda: sp.spmv_dia(Dy, x, y), bytes_dia(Dy, 8, 8))]
@@ -863,7 +885,7 @@ def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000, sweep=Fal
     ks = hamiltonian_kernels(sp, H, y)
     _, per = time_loop(torch, [(k, f) for k, f, _ in ks], max(20, steps // 4), 5)
     out = {"workload": f"Hamiltonian-shaped symmetric matrix n={n} nnz={nnz} (diagonal, 6 mirrored pairs of "
-                       "70%-filled outer diagonals, band of 500), FP64",
+                       "70%-filled outer diagonals, band of 500), FP64", "autotuned": H["tune"],
            "dia": {"stored_diagonals": int(D.ndia), "remainder_nnz": int(D.rem.nnz),
                    "remainder_padded_slots": int(Ds.rem_slices.bl_col.numel()),
                    "sym_stored_diagonals": int(Dy.ndia), "sym_remainder_nnz": int(Dy.rem.nnz)},
@@ -881,7 +903,8 @@ def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000, sweep=Fal
     if keep is not None:
         keep.update(host=H["host"], x=H["x"], rows=rows, samples=samples)
     if sweep:
-        bR, bU, bW = H["tune"]["blocked"]
+        T = H["tune"]
+        bR, bU, bW = T["blocked_rows_per_wave"], T["blocked_unroll"], T["blocked_wg_waves"]
         J, x = H["J"], H["x"]
         del H["B"], H["D"], H["Ds"], H["Dy"]
         torch.cuda.empty_cache()
@@ -1259,7 +1282,7 @@ def run_hamiltonian_only(torch, sp, dev, args):
     kb = [(k, f, b) for k, f, b in hamiltonian_kernels(sp, H, y) if keep is None or k in keep]
     _, per = time_loop(torch, [(k, f) for k, f, _ in kb], args.steps, args.warmup)
     print(json.dumps({"workload": "hamiltonian", "n": H["n"], "nnz": H["nnz"],
-                      "autotuned": {"jds": H["tune"]["jds"], "blocked": H["tune"]["blocked"], "blocked_C": H["B"].C},
+                      "autotuned": H["tune"],
                       "kernels": {k: round(ms, 5) for k, ms in per.items()},
                       "algorithmic_bytes": {k: int(b) for k, _, b in kb}}), flush=True)
 

@@ -191,8 +191,13 @@ spmv_status spmv_jds_blocked_windowed_from_csr(int32_t n, int64_t nnz, const int
  * per wavefront, S wavefronts per row group; chosen from the slice depth as
  * in spmv_jds_blocked, or R = rows_per_wave when that is non-zero) is covered
  * by workgroups of (wg_waves / S) * R rows, one record of two int32 each
- * (first row; R, S and row count packed).  The records are cut into 8
- * contiguous ranges of about equal work: range k runs on XCD k.
+ * (first row; R, S and row count packed).  When the depths never increase
+ * (the globally sorted order) the records are dealt as in spmv_jds_tiles,
+ * with slices for rows: each run of equal-depth slices of at least 4,096
+ * rows in 8 contiguous pieces, one per XCD, the rest for equal cost.
+ * Otherwise (e.g. the windowed order, whose windows already keep
+ * neighbouring rows together) they are cut into 8 contiguous ranges of about
+ * equal work: range k runs on XCD k.
  *   tiles: 2 * n_tiles int32 (device), written when tiles_cap >= 2 * n_tiles,
  *          otherwise SPMV_ERR_CAPACITY with *h_n_tiles set (two-call pattern)
  *   h_plan[10]: the 9 range bounds and the wavefronts per workgroup, passed
@@ -289,6 +294,33 @@ spmv_status spmv_jds_blocked_tiled(int32_t n, const int32_t *perm, int32_t C, in
                                    spmv_dtype vec_dt, double alpha, double beta, const int32_t *tiles,
                                    int64_t n_tiles, const int64_t *h_plan, int32_t unroll, unsigned flags,
                                    void *stream);
+/* XCD-local tile plan of JDS storage for spmv_jds_tiled, built on the host
+ * from h_jd_ptr (setup; synchronises when it copies the records).  The
+ * length sort (stable) keeps the rows of one length in original order, and a
+ * length class draws its rows from the whole matrix; dealt round robin, the
+ * rows of one region of the matrix land on every XCD, each fetching that
+ * region's band of x into its own L2.  Here each run of at least 4,096 rows
+ * of one length is cut into 8 contiguous pieces, piece k for XCD k (one
+ * eighth of those rows each, neighbours in the original order); every other
+ * row group (rows longer than max_iters diagonals, in 64-row chunks wanting
+ * the same split, and short runs) is dealt to the XCD with the least cost so
+ * far, largest first.  R and S per group as in spmv_jds (R = rows_per_wave
+ * when non-zero); records of (wg_waves / S) * R rows, two int32 each (first
+ * row; R, S and row count packed); XCD k's range holds its dealt records in
+ * row order, then its pieces.
+ *   tiles: 2 * n_tiles int32 (device), written when tiles_cap >= 2 * n_tiles,
+ *          otherwise SPMV_ERR_CAPACITY with *h_n_tiles set (two-call pattern)
+ *   h_plan[10]: the 9 range bounds and the wavefronts per workgroup. */
+spmv_status spmv_jds_tiles(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int32_t max_iters, int32_t rows_per_wave,
+                           int32_t wg_waves, int32_t *tiles, int64_t tiles_cap, int64_t *h_n_tiles, int64_t *h_plan,
+                           void *stream);
+/* The JDS product (as spmv_jds, same arithmetic per row for the same R and
+ * S) launched from a tile plan (spmv_jds_tiles): the workgroups on XCD k walk
+ * range k of the records in order.  Asynchronous; allocates nothing. */
+spmv_status spmv_jds_tiled(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag, const int32_t *jd_col,
+                           const void *jd_val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
+                           double alpha, double beta, const int32_t *tiles, int64_t n_tiles, const int64_t *h_plan,
+                           int32_t unroll, unsigned flags, void *stream);
 
 /* Vector basis change: inverse == 0: out[r] = in[perm[r]] (to the permuted
  * basis); inverse != 0: out[perm[r]] = in[r].  dt F64 or F32. */

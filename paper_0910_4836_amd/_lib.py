@@ -57,6 +57,9 @@ SIGNATURES = {
     "spmv_jds_blocked_tiles": (_int, [_i32, _i32, _i32, _i32p, _i32, _i32, _i32, _p, _i64, _i64p, _i64p, _p]),
     "spmv_jds_blocked_tiled": (_int, [_i32, _p, _i32, _i32, _p, _p, _p, _p, _int, _p, _p, _int, _f64, _f64, _p,
                                       _i64, _i64p, _i32, _u32, _p]),
+    "spmv_jds_tiles": (_int, [_i32, _i32p, _i32, _i32, _i32, _i32, _p, _i64, _i64p, _i64p, _p]),
+    "spmv_jds_tiled": (_int, [_i32, _p, _p, _i32, _p, _p, _int, _p, _p, _int, _f64, _f64, _p, _i64, _i64p, _i32,
+                              _u32, _p]),
     "spmv_convert_values": (_int, [_i64, _p, _int, _p, _int, _p]),
     "spmv_transpose_workspace_size": (_sz, [_i32, _i32, _i64]),
     "spmv_transpose_csr": (_int, [_i32, _i32, _i64, _p, _p, _p, _p, _p, _p, _sz, _p]),

@@ -210,6 +210,40 @@ class Autotuner:
         self._record(sig, keys, best, timings)
         return best
 
+    def _tune_launch(self, sig: str, plain, tiled, reps: int = 20) -> bool:
+        hit = self.lookup(sig, ("tiled",))
+        if hit is not None:
+            return bool(hit[0])
+        # alternate the two launches so that clock and cache drift hit both alike
+        t = {False: 0.0, True: 0.0}
+        for _ in range(3):
+            t[False] += _time(plain, reps=reps)
+            t[True] += _time(tiled, reps=reps)
+        timings = {(False,): t[False] / 3, (True,): t[True] / 3}
+        best = min(timings, key=timings.get)
+        self.log.append({"signature": sig, "timings_ms": {"plain": round(timings[(False,)], 5),
+                                                          "tiled": round(timings[(True,)], 5)}})
+        self._record(sig, ("tiled",), best, timings)
+        return bool(best[0])
+
+    def tune_jds_launch(self, J: S.JDS, x: torch.Tensor, U: int, mi: int, W: int) -> bool:
+        """Whether the XCD-local tile plan (spmv_jds_tiled) beats the class
+        plan (spmv_jds) for J at this launch shape."""
+        sig = f"jds_launch:U{U}_mi{mi}_W{W}:" + signature(J.n, J.ndiag, int(J.h_jd_ptr[J.ndiag]))
+        y = torch.empty(J.n, dtype=x.dtype, device=x.device)
+        return self._tune_launch(sig, lambda: S.spmv_jds(J, x, y, unroll=U, max_iters=mi, wg_waves=W),
+                                 lambda: S.spmv_jds_tiled(J, x, y, unroll=U, max_iters=mi, wg_waves=W))
+
+    def tune_blocked_launch(self, B: S.Blocked, x: torch.Tensor, R: int, U: int, W: int) -> bool:
+        """Whether the tile plan (spmv_jds_blocked_tiled; XCD-local on the
+        globally sorted order) beats the class plan (spmv_jds_blocked) for B
+        at this launch shape."""
+        sig = f"blocked_launch:C{B.C}_R{R}_U{U}_W{W}:" + signature(B.n, int(B.h_slice_nd[0]) if len(B.h_slice_nd)
+                                                                    else 0, B.padded)
+        y = torch.empty(B.n, dtype=x.dtype, device=x.device)
+        return self._tune_launch(sig, lambda: S.spmv_jds_blocked(B, x, y, rows_per_wave=R, unroll=U, wg_waves=W),
+                                 lambda: S.spmv_jds_blocked_tiled(B, x, y, unroll=U, rows_per_wave=R, wg_waves=W))
+
 
 def tune_crs(tuner: "Autotuner", A: S.CSR, x: torch.Tensor, longest: int,
              candidates=BLOCK_NNZ_CANDIDATES) -> int:

@@ -310,16 +310,19 @@ __device__ __forceinline__ void jds_body(const JdsArgs &a, const JdsPlan &P, int
     jds_body_task<FMT, U, VT, XT, OT, WIDE_ALL>(a, wave_task<FMT>(a, P, !F64, wg), part);
 }
 
-// Tile plans (blocked storage in any row order, e.g. sorted inside windows
-// of rows): workgroup record (row0, code) covers permuted rows [row0, row0 +
-// nrows) with R = 2^rlog rows per wave group and S = 2^slog waves per group,
-// code = rlog | slog << 4 | nrows << 8.  The records are cut into 8
-// contiguous ranges of about equal work, range k for the workgroups on XCD k
-// (workgroup b runs on XCD b % 8), so each XCD walks its rows in order.
+// Tile plans (JDS storage, or blocked storage in any row order): workgroup
+// record (row0, code) covers permuted rows [row0, row0 + nrows) with R =
+// 2^rlog rows per wave group and S = 2^slog waves per group, code = rlog |
+// slog << 4 | nrows << 8 (a blocked record stays inside one slice).  The
+// records form 8 ranges, range k for the workgroups on XCD k (workgroup b
+// runs on XCD b % 8): contiguous ranges of equal work for a windowed order,
+// XCD-local pieces of the long equal-length runs plus records dealt for
+// equal cost for a globally sorted order.
 struct TileBounds {
     int64_t b[9];
 };
 
+template <int FMT>
 __device__ __forceinline__ WaveTask tile_task(const JdsArgs &a, int32_t row0, int32_t nrows, int rlog, int slog,
                                               bool reduced_values)
 {
@@ -340,10 +343,22 @@ __device__ __forceinline__ WaveTask tile_task(const JdsArgs &a, int32_t row0, in
     t.kk = lane >> rlog;
     t.r = t.row0 + t.rl;
     t.row_ok = t.valid && t.r < row_end;
-    const int32_t Lmax = t.valid ? a.slice_nd[t.row0 / a.C] : 0;
-    t.wide = reduced_values && Lmax > SPMV_WIDE_ROW_NNZ;
+    // length of the group's first (longest) row, as in wave_task
+    int32_t Lmax = 0;
+    t.wide = false;
+    if (t.valid) {
+        if (FMT == FMT_JDS) {
+            if (t.S > 1) Lmax = jds_row_len(a.jd_ptr, a.ndiag, t.row0);
+            if (reduced_values)
+                t.wide = a.ndiag > SPMV_WIDE_ROW_NNZ &&
+                         a.jd_ptr[SPMV_WIDE_ROW_NNZ + 1] - a.jd_ptr[SPMV_WIDE_ROW_NNZ] > t.row0;
+        } else {
+            Lmax = a.slice_nd[t.row0 / a.C];
+            t.wide = reduced_values && Lmax > SPMV_WIDE_ROW_NNZ;
+        }
+    }
     t.dA = 0;
-    t.dB = Lmax;
+    t.dB = (FMT == FMT_JDS) ? a.ndiag : Lmax;
     if (t.S > 1) {
         const int64_t SG = (int64_t)t.S * t.G;
         const int32_t per = (int32_t)(((int64_t)Lmax + SG - 1) / SG * t.G);
@@ -351,11 +366,11 @@ __device__ __forceinline__ WaveTask tile_task(const JdsArgs &a, int32_t row0, in
         t.dB = t.dA + per < Lmax ? t.dA + per : Lmax;
         if (t.dA > t.dB) t.dA = t.dB;
     }
-    t.bounded = true;
+    t.bounded = (FMT == FMT_BLOCKED) || t.S > 1;
     return t;
 }
 
-template <int U, typename VT, typename XT>
+template <int FMT, int U, typename VT, typename XT>
 __global__ __launch_bounds__(JDS_THREADS) void jds_tiles_kernel(JdsArgs a, const int32_t *__restrict__ tiles,
                                                                 TileBounds xb)
 {
@@ -365,8 +380,8 @@ __global__ __launch_bounds__(JDS_THREADS) void jds_tiles_kernel(JdsArgs a, const
     const int64_t idx = xb.b[x] + blockIdx.x / 8;
     if (idx >= xb.b[x + 1]) return;
     const int32_t row0 = tiles[2 * idx], code = tiles[2 * idx + 1];
-    jds_body_task<FMT_BLOCKED, U, VT, XT, XT>(a, tile_task(a, row0, code >> 8, code & 15, (code >> 4) & 15, !F64),
-                                              part);
+    jds_body_task<FMT, U, VT, XT, XT>(a, tile_task<FMT>(a, row0, code >> 8, code & 15, (code >> 4) & 15, !F64),
+                                      part);
 }
 
 template <int FMT, int U, typename VT, typename XT>
@@ -681,6 +696,130 @@ static spmv_status launch_jds_t(const JdsArgs &a, const JdsPlan &P, int unroll, 
     return SPMV_OK;
 }
 
+// XCD-local tile plan of a globally length-sorted storage (JDS rows, or
+// the slices of a blocked JDS whose depths never increase).  A length class
+// holds rows from all over the matrix, so dealing workgroups round robin (or
+// in contiguous ranges of the sorted order) spreads the rows of one region
+// of the original matrix over all XCDs, each fetching the same x lines of
+// that region's band.  Here every long run of equal length (in original row
+// order, since the sort is stable) is cut into 8 contiguous pieces, piece k
+// to XCD k, so each XCD's short rows come from one eighth of the original
+// rows; the remaining records (long rows, short runs) are dealt to the XCDs
+// for equal cost, longest first.  Each XCD walks its dealt records (in
+// sorted order), then its pieces.
+//   unit_len(u): length of unit u (a row, or a slice's depth); units are
+//     non-increasing in length; unit u spans rows [u*U, min((u+1)*U, n)).
+//   U: rows per unit (1 for JDS rows, C for slices); chunk: rows per split
+//     decision (64 for JDS, C for slices: a record never crosses a slice).
+// Runs of at least this many rows of one length are cut into 8 XCD pieces
+// (measured on the power-law matrix: 4,096 against 16,384).
+constexpr int64_t TILE_LOCAL_MIN_RUN = 4096;
+
+template <typename F>
+static void plan_tiles_local(int32_t n, int32_t U, int64_t n_units, F unit_len, int32_t max_iters, int forced_rlog,
+                             int waves, int64_t min_run_rows, std::vector<int32_t> &rec, int64_t bounds[9])
+{
+    struct Rec {
+        int32_t row0, code;
+        double cost;
+    };
+    auto split_of = [&](int64_t L, int &rlog, int &slog) {
+        int W = 1;
+        while (W < 128 && (int64_t)W * max_iters < L) W <<= 1;
+        split_for(W, forced_rlog, waves, rlog, slog);
+    };
+    auto records = [&](int64_t a0, int64_t a1, int rlog, int slog, int64_t L, std::vector<Rec> &out) {
+        const int64_t rpw = (int64_t)(waves >> slog) << rlog;
+        for (int64_t r = a0; r < a1; r += rpw) {
+            const int64_t nr = std::min<int64_t>(rpw, a1 - r);
+            out.push_back({(int32_t)r, rlog | (slog << 4) | (int32_t)(nr << 8), (double)nr * L + 64.0 * waves});
+        }
+    };
+    auto row_end = [&](int64_t u) { return std::min<int64_t>(u * U, n); };
+    // first unit of length <= max_iters: one lane per row from there on
+    int64_t q = 0, hi = n_units;
+    while (q < hi) {
+        const int64_t mid = (q + hi) >> 1;
+        if (unit_len(mid) > max_iters) q = mid + 1;
+        else hi = mid;
+    }
+    std::vector<Rec> others, pieces[8];
+    // long units: runs of 64-row (JDS) or one-slice (blocked) steps wanting the same split
+    const int64_t step = U == 1 ? 64 : 1;
+    for (int64_t i = 0; i < q;) {
+        int rlog, slog;
+        split_of(unit_len(i), rlog, slog);
+        int64_t j = std::min(i + step, q);
+        for (; j < q; j = std::min(j + step, q)) {
+            int r2, s2;
+            split_of(unit_len(j), r2, s2);
+            if (r2 != rlog || s2 != slog) break;
+        }
+        if (U == 1) {
+            records(i, j, rlog, slog, unit_len(i), others);
+        } else {
+            for (int64_t u = i; u < j; ++u) records(u * U, row_end(u + 1), rlog, slog, unit_len(u), others);
+        }
+        i = j;
+    }
+    // short units: runs of equal length
+    for (int64_t i = q; i < n_units;) {
+        const int64_t L = unit_len(i);
+        int64_t lo = i + 1, h2 = n_units;
+        while (lo < h2) {
+            const int64_t mid = (lo + h2) >> 1;
+            if (unit_len(mid) == L) lo = mid + 1;
+            else h2 = mid;
+        }
+        const int64_t j = lo;
+        int rlog, slog;
+        split_of(L, rlog, slog);
+        if (row_end(j) - i * U >= min_run_rows) {
+            for (int k = 0; k < 8; ++k) {
+                const int64_t u0 = i + (j - i) * k / 8, u1 = i + (j - i) * (k + 1) / 8;
+                if (U == 1) records(u0, u1, rlog, slog, L, pieces[k]);
+                else
+                    for (int64_t u = u0; u < u1; ++u) records(u * U, row_end(u + 1), rlog, slog, L, pieces[k]);
+            }
+        } else if (U == 1) {
+            records(i, j, rlog, slog, L, others);
+        } else {
+            for (int64_t u = i; u < j; ++u) records(u * U, row_end(u + 1), rlog, slog, L, others);
+        }
+        i = j;
+    }
+    double load[8];
+    for (int k = 0; k < 8; ++k) {
+        load[k] = 0;
+        for (const Rec &r : pieces[k]) load[k] += r.cost;
+    }
+    std::vector<int64_t> order(others.size());
+    for (size_t t = 0; t < order.size(); ++t) order[t] = (int64_t)t;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return others[a].cost > others[b].cost; });
+    std::vector<int64_t> dealt[8];
+    for (int64_t t : order) {
+        int k = 0;
+        for (int m = 1; m < 8; ++m)
+            if (load[m] < load[k]) k = m;
+        dealt[k].push_back(t);
+        load[k] += others[t].cost;
+    }
+    rec.clear();
+    bounds[0] = 0;
+    for (int k = 0; k < 8; ++k) {
+        std::sort(dealt[k].begin(), dealt[k].end());
+        for (int64_t t : dealt[k]) {
+            rec.push_back(others[t].row0);
+            rec.push_back(others[t].code);
+        }
+        for (const Rec &r : pieces[k]) {
+            rec.push_back(r.row0);
+            rec.push_back(r.code);
+        }
+        bounds[k + 1] = (int64_t)rec.size() / 2;
+    }
+}
+
 template <int FMT>
 static spmv_status launch_jds(const JdsArgs &a, const JdsPlan &P, int unroll, spmv_dtype vdt, spmv_dtype xdt,
                               hipStream_t s)
@@ -741,6 +880,48 @@ static spmv_status launch_rows(const JdsSplitArgs &S, int64_t max_wg, int32_t un
 }  // namespace spmv
 
 using namespace spmv;
+
+// Checks a tile plan's 8 range bounds (h_plan[0..8]) and wavefront count
+// (h_plan[9]); returns the widest range through *widest.
+static spmv_status check_tile_plan(const int64_t *h_plan, int64_t n_tiles, TileBounds &xb, int64_t *widest,
+                                   const char *who)
+{
+    if (!h_plan) return fail(SPMV_ERR_INVALID_ARG, who);
+    for (int k = 0; k < 9; ++k) xb.b[k] = h_plan[k];
+    if (xb.b[0] != 0 || xb.b[8] != n_tiles) return fail(SPMV_ERR_INVALID_ARG, who);
+    *widest = 0;
+    for (int k = 0; k < 8; ++k) {
+        if (xb.b[k + 1] < xb.b[k]) return fail(SPMV_ERR_INVALID_ARG, who);
+        *widest = std::max<int64_t>(*widest, xb.b[k + 1] - xb.b[k]);
+    }
+    if (!waves_ok((int32_t)h_plan[9]) || h_plan[9] == 0) return fail(SPMV_ERR_INVALID_ARG, who);
+    return SPMV_OK;
+}
+
+template <int FMT>
+static spmv_status launch_tiles(const JdsArgs &a, const int32_t *tiles, const TileBounds &xb, int64_t widest,
+                                int64_t waves, int32_t unroll, spmv_dtype val_dt, spmv_dtype vec_dt, hipStream_t s,
+                                const char *who)
+{
+    const unsigned grid = (unsigned)(8 * widest), threads = (unsigned)(waves * WAVE);
+    const int u = unroll ? unroll : 4;
+#define JTILE_CASE(VDT, VT, XDT, XT)                                                                         \
+    if (val_dt == VDT && vec_dt == XDT) {                                                                    \
+        if (u == 2) jds_tiles_kernel<FMT, 2, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);              \
+        else if (u == 8) jds_tiles_kernel<FMT, 8, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);         \
+        else jds_tiles_kernel<FMT, 4, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);                     \
+    } else
+    JTILE_CASE(SPMV_F64, double, SPMV_F64, double)
+    JTILE_CASE(SPMV_F32, float, SPMV_F64, double)
+    JTILE_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    JTILE_CASE(SPMV_F32, float, SPMV_F32, float)
+    JTILE_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    JTILE_CASE(SPMV_F64, double, SPMV_F32, float)
+    return fail(SPMV_ERR_UNSUPPORTED, who);
+#undef JTILE_CASE
+    SPMV_CHECK_LAUNCH(who);
+    return SPMV_OK;
+}
 
 extern "C" {
 
@@ -841,14 +1022,65 @@ spmv_status spmv_jds_blocked_tiles(int32_t n, int32_t C, int32_t n_slices, const
         while ((1 << forced) < rows_per_wave) ++forced;
     }
     const int waves = waves_or_default(wg_waves);
+    const int32_t mi = max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS;
     std::vector<int32_t> rec;
     int64_t bounds[9];
-    plan_tiles(n, C, h_slice_nd, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced, waves, rec, bounds);
+    bool sorted = true;                       // the globally sorted order: depths never increase
+    for (int32_t sl = 1; sl < n_slices && sorted; ++sl) sorted = h_slice_nd[sl] <= h_slice_nd[sl - 1];
+    if (sorted)
+        plan_tiles_local(n, C, n_slices, [&](int64_t u) -> int64_t { return h_slice_nd[u]; }, mi, forced, waves,
+                         TILE_LOCAL_MIN_RUN, rec, bounds);
+    else
+        plan_tiles(n, C, h_slice_nd, mi, forced, waves, rec, bounds);
     const int64_t nt = (int64_t)rec.size() / 2;
     *h_n_tiles = nt;
     for (int k = 0; k < 9; ++k) h_plan[k] = bounds[k];
     h_plan[9] = waves;
     if (!tiles || tiles_cap < 2 * nt) return fail(SPMV_ERR_CAPACITY, "spmv_jds_blocked_tiles: tiles capacity < 2 * n_tiles");
+    if (nt == 0) return SPMV_OK;
+    hipStream_t s = as_stream(stream);
+    SPMV_HIP(hipMemcpyAsync(tiles, rec.data(), sizeof(int32_t) * rec.size(), hipMemcpyHostToDevice, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+spmv_status spmv_jds_tiles(int32_t n, const int32_t *h_jd_ptr, int32_t ndiag, int32_t max_iters, int32_t rows_per_wave,
+                           int32_t wg_waves, int32_t *tiles, int64_t tiles_cap, int64_t *h_n_tiles, int64_t *h_plan,
+                           void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && ndiag >= 0, "spmv_jds_tiles: negative size");
+    SPMV_REQUIRE(waves_ok(wg_waves), "spmv_jds_tiles: wg_waves must be 0, 4, 8 or 16");
+    SPMV_REQUIRE(max_iters >= 0, "spmv_jds_tiles: max_iters < 0");
+    SPMV_REQUIRE(rows_per_wave == 0 || rows_per_wave == 8 || rows_per_wave == 16 || rows_per_wave == 32 ||
+                     rows_per_wave == 64,
+                 "spmv_jds_tiles: rows_per_wave must be 0, 8, 16, 32 or 64");
+    SPMV_REQUIRE(h_n_tiles && h_plan && (ndiag == 0 || h_jd_ptr), "spmv_jds_tiles: null pointer");
+    SPMV_REQUIRE(ndiag == 0 || (h_jd_ptr[0] == 0 && h_jd_ptr[1] <= n), "spmv_jds_tiles: h_jd_ptr inconsistent with n");
+    int forced = -1;
+    if (rows_per_wave) {
+        forced = 0;
+        while ((1 << forced) < rows_per_wave) ++forced;
+    }
+    const int waves = waves_or_default(wg_waves);
+    // length of permuted row r: the diagonals longer than r
+    auto row_len = [&](int64_t r) -> int64_t {
+        int32_t lo = 0, hi = ndiag;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (h_jd_ptr[mid + 1] - h_jd_ptr[mid] > r) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    std::vector<int32_t> rec;
+    int64_t bounds[9];
+    plan_tiles_local(n, 1, n, row_len, max_iters ? max_iters : JDS_DEFAULT_MAX_ITERS, forced, waves,
+                     TILE_LOCAL_MIN_RUN, rec, bounds);
+    const int64_t nt = (int64_t)rec.size() / 2;
+    *h_n_tiles = nt;
+    for (int k = 0; k < 9; ++k) h_plan[k] = bounds[k];
+    h_plan[9] = waves;
+    if (!tiles || tiles_cap < 2 * nt) return fail(SPMV_ERR_CAPACITY, "spmv_jds_tiles: tiles capacity < 2 * n_tiles");
     if (nt == 0) return SPMV_OK;
     hipStream_t s = as_stream(stream);
     SPMV_HIP(hipMemcpyAsync(tiles, rec.data(), sizeof(int32_t) * rec.size(), hipMemcpyHostToDevice, s));
@@ -868,17 +1100,11 @@ spmv_status spmv_jds_blocked_tiled(int32_t n, const int32_t *perm, int32_t C, in
     SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_blocked_tiled: bad dtype");
     SPMV_REQUIRE(unroll_ok(unroll), "spmv_jds_blocked_tiled: unroll must be 0, 2, 4 or 8");
     SPMV_REQUIRE((flags & ~(SPMV_SYMPERM | SPMV_SOJDS)) == 0, "spmv_jds_blocked_tiled: unknown flag");
-    SPMV_REQUIRE(h_plan, "spmv_jds_blocked_tiled: null h_plan");
     TileBounds xb;
-    for (int k = 0; k < 9; ++k) xb.b[k] = h_plan[k];
-    SPMV_REQUIRE(xb.b[0] == 0 && xb.b[8] == n_tiles, "spmv_jds_blocked_tiled: plan bounds do not cover n_tiles");
     int64_t widest = 0;
-    for (int k = 0; k < 8; ++k) {
-        SPMV_REQUIRE(xb.b[k + 1] >= xb.b[k], "spmv_jds_blocked_tiled: plan bounds decrease");
-        widest = std::max<int64_t>(widest, xb.b[k + 1] - xb.b[k]);
-    }
-    const int64_t waves = h_plan[9];
-    SPMV_REQUIRE(waves_ok((int32_t)waves) && waves != 0, "spmv_jds_blocked_tiled: bad wavefront count in h_plan");
+    spmv_status st = check_tile_plan(h_plan, n_tiles, xb, &widest,
+                                     "spmv_jds_blocked_tiled: h_plan bounds or wavefront count invalid");
+    if (st != SPMV_OK) return st;
     if (n == 0 || n_tiles == 0) return SPMV_OK;
     // bl_col, bl_val and x are read only where a slice has diagonals (they may
     // be null for storage without entries)
@@ -897,25 +1123,43 @@ spmv_status spmv_jds_blocked_tiled(int32_t n, const int32_t *perm, int32_t C, in
     a.alpha = alpha;
     a.beta = beta;
     a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
-    hipStream_t s = as_stream(stream);
-    const unsigned grid = (unsigned)(8 * widest), threads = (unsigned)(waves * WAVE);
-    const int u = unroll ? unroll : 4;
-#define JTILE_CASE(VDT, VT, XDT, XT)                                                                         \
-    if (val_dt == VDT && vec_dt == XDT) {                                                                    \
-        if (u == 2) jds_tiles_kernel<2, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);                   \
-        else if (u == 8) jds_tiles_kernel<8, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);              \
-        else jds_tiles_kernel<4, VT, XT><<<grid, threads, 0, s>>>(a, tiles, xb);                          \
-    } else
-    JTILE_CASE(SPMV_F64, double, SPMV_F64, double)
-    JTILE_CASE(SPMV_F32, float, SPMV_F64, double)
-    JTILE_CASE(SPMV_BF16, bf16, SPMV_F64, double)
-    JTILE_CASE(SPMV_F32, float, SPMV_F32, float)
-    JTILE_CASE(SPMV_BF16, bf16, SPMV_F32, float)
-    JTILE_CASE(SPMV_F64, double, SPMV_F32, float)
-    return fail(SPMV_ERR_UNSUPPORTED, "spmv_jds_blocked_tiled: dtype combination");
-#undef JTILE_CASE
-    SPMV_CHECK_LAUNCH("spmv_jds_blocked_tiled");
-    return SPMV_OK;
+    return launch_tiles<FMT_BLOCKED>(a, tiles, xb, widest, h_plan[9], unroll, val_dt, vec_dt, as_stream(stream),
+                                     "spmv_jds_blocked_tiled");
+}
+
+spmv_status spmv_jds_tiled(int32_t n, const int32_t *perm, const int32_t *jd_ptr, int32_t ndiag, const int32_t *jd_col,
+                           const void *jd_val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
+                           double alpha, double beta, const int32_t *tiles, int64_t n_tiles, const int64_t *h_plan,
+                           int32_t unroll, unsigned flags, void *stream)
+{
+    SPMV_REQUIRE(n >= 0 && ndiag >= 0 && n_tiles >= 0, "spmv_jds_tiled: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_jds_tiled: bad dtype");
+    SPMV_REQUIRE(unroll_ok(unroll), "spmv_jds_tiled: unroll must be 0, 2, 4 or 8");
+    SPMV_REQUIRE((flags & ~SPMV_SYMPERM) == 0, "spmv_jds_tiled: unknown flag");
+    TileBounds xb;
+    int64_t widest = 0;
+    spmv_status st = check_tile_plan(h_plan, n_tiles, xb, &widest,
+                                     "spmv_jds_tiled: h_plan bounds or wavefront count invalid");
+    if (st != SPMV_OK) return st;
+    if (n == 0 || n_tiles == 0) return SPMV_OK;
+    SPMV_REQUIRE(y && jd_ptr && tiles, "spmv_jds_tiled: null y, jd_ptr or tiles");
+    SPMV_REQUIRE((flags & SPMV_SYMPERM) || perm, "spmv_jds_tiled: null perm");
+    SPMV_REQUIRE(ndiag == 0 || (jd_col && jd_val && x), "spmv_jds_tiled: null col, val or x");
+    JdsArgs a{};
+    a.n = n;
+    a.perm = perm;
+    a.jd_ptr = jd_ptr;
+    a.ndiag = ndiag;
+    a.C = 64;
+    a.col = jd_col;
+    a.val = jd_val;
+    a.x = x;
+    a.y = y;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.symperm = (flags & SPMV_SYMPERM) ? 1 : 0;
+    return launch_tiles<FMT_JDS>(a, tiles, xb, widest, h_plan[9], unroll, val_dt, vec_dt, as_stream(stream),
+                                 "spmv_jds_tiled");
 }
 
 }  // extern "C"

@@ -113,6 +113,7 @@ class JDS:
     jd_col: torch.Tensor
     jd_val: torch.Tensor
     symperm: bool = False
+    tile_plans: dict = field(default_factory=dict, repr=False)   # (max_iters, rows_per_wave, wg_waves) -> plan
 
     @property
     def ndiag(self) -> int:
@@ -128,7 +129,7 @@ class JDS:
 
     def with_values(self, val: torch.Tensor) -> "JDS":
         return JDS(self.n, self.n_cols, self.perm, self.iperm, self.jd_ptr, self.h_jd_ptr, self.jd_col, val,
-                   self.symperm)
+                   self.symperm, self.tile_plans)
 
 
 @dataclass
@@ -162,6 +163,12 @@ class Blocked:
 
 def csr_from_coo(n_rows: int, n_cols: int, row: torch.Tensor, col: torch.Tensor, val: torch.Tensor) -> CSR:
     """COO -> CRS on the GPU (spmv_csr_from_coo): sorted, duplicates summed in input order."""
+    if row.dtype != _I32 or col.dtype != _I32:
+        # the library reads 4-byte indices: an int64 tensor would be read as
+        # pairs of int32 halves, a different matrix without an error
+        raise TypeError(f"row and col must be int32, got {row.dtype} and {col.dtype}")
+    if row.numel() != col.numel() or row.numel() != val.numel():
+        raise ValueError(f"row, col and val must have one length, got {row.numel()}, {col.numel()}, {val.numel()}")
     _check_dev(row, col, val)
     dev = row.device
     nnz = int(row.numel())
@@ -389,6 +396,37 @@ def spmv_jds(J: JDS, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: f
     call("spmv_jds", J.n, _p(J.perm), _p(J.jd_ptr), _h_i32(J.h_jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val),
          dtype_code(J.jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), unroll, max_iters,
          wg_waves, J.flags, _stream())
+    return y
+
+
+def spmv_jds_tiles(J: JDS, max_iters: int = 0, rows_per_wave: int = 0, wg_waves: int = 0):
+    """The XCD-local tile plan of J for spmv_jds_tiled (spmv_jds_tiles), built
+    once per launch shape and kept on J: (tiles, n_tiles, h_plan)."""
+    key = (max_iters, rows_per_wave, wg_waves)
+    if key not in J.tile_plans:
+        lib = _lib.load()
+        nt = C.c_int64(0)
+        h_plan = np.zeros(10, dtype=np.int64)
+        args = lambda t, cap: (J.n, _h_i32(J.h_jd_ptr), J.ndiag, max_iters, rows_per_wave, wg_waves, t, cap,
+                               C.byref(nt), _h_i64(h_plan), _stream())
+        st = lib.spmv_jds_tiles(*args(None, 0))
+        if st not in (0, 3):
+            call("spmv_jds_tiles", *args(None, 0))
+        tiles = torch.empty(max(2 * nt.value, 1), dtype=_I32, device=J.jd_ptr.device)
+        call("spmv_jds_tiles", *args(_p(tiles), tiles.numel()))
+        J.tile_plans[key] = (tiles, nt.value, h_plan)
+    return J.tile_plans[key]
+
+
+def spmv_jds_tiled(J: JDS, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
+                   unroll: int = 0, max_iters: int = 0, rows_per_wave: int = 0, wg_waves: int = 0) -> torch.Tensor:
+    """y = alpha*A x + beta*y with the JDS kernel launched from J's XCD-local
+    tile plan (spmv_jds_tiled)."""
+    y = _out_vec(y, J.n, x, beta, J.n_cols)
+    tiles, nt, h_plan = spmv_jds_tiles(J, max_iters, rows_per_wave, wg_waves)
+    call("spmv_jds_tiled", J.n, _p(J.perm), _p(J.jd_ptr), J.ndiag, _p(J.jd_col), _p(J.jd_val),
+         dtype_code(J.jd_val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), _p(tiles), nt,
+         _h_i64(h_plan), unroll, J.flags, _stream())
     return y
 
 

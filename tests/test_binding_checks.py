@@ -116,3 +116,14 @@ def test_blocked_multi_vector_refuses_symmetric_permutation():
     B.symperm = True
     with pytest.raises(ValueError, match="symmetric-permutation"):
         S.spmm_jds_blocked(B, torch.zeros(3, N_COLS, dtype=torch.float64).t())
+
+
+def test_coo_indices_must_be_int32():
+    """int64 indices would be read as pairs of int32 halves: refused."""
+    r = torch.zeros(3, dtype=torch.int64)
+    c = torch.zeros(3, dtype=torch.int32)
+    v = torch.ones(3, dtype=torch.float64)
+    with pytest.raises(TypeError, match="int32"):
+        S.csr_from_coo(4, 4, r, c, v)
+    with pytest.raises(ValueError, match="one length"):
+        S.csr_from_coo(4, 4, c, c, torch.ones(2, dtype=torch.float64))

@@ -356,8 +356,16 @@ def test_autotuner_batched_and_cache(tmp_path):
     bn = autotune.tune_crs(tuner, A, xd, J.ndiag)
     assert bn in autotune.BLOCK_NNZ_CANDIDATES and A.block_nnz == bn
     assert max_err(sp.spmv_crs(A, xd), want, D) <= FP64_TOL
+    # class plan or XCD-local tile plan: a cached boolean, either launch the same y
+    jt = tuner.tune_jds_launch(J, xd, U, mi, Wj)
+    bt = tuner.tune_blocked_launch(B, xd, R_, U2, Wb)
+    assert isinstance(jt, bool) and isinstance(bt, bool)
+    assert max_err(sp.spmv_jds_tiled(J, xd, unroll=U, max_iters=mi, wg_waves=Wj), want, D) <= FP64_TOL
+    assert max_err(sp.spmv_jds_blocked_tiled(B, xd, unroll=U2, rows_per_wave=R_, wg_waves=Wb), want, D) <= FP64_TOL
     t3 = autotune.Autotuner(cache, cs=(64, 128), rs=(64, 16), us=(2, 4))
     assert t3.tune_jds(J, xd) == (U, mi, Wj) and t3.tune_blocked(J, xd) == (C_, R_, U2, Wb) and not t3.log
+    assert t3.tune_jds_launch(J, xd, U, mi, Wj) == jt and t3.tune_blocked_launch(B, xd, R_, U2, Wb) == bt
+    assert not t3.log
     assert autotune.tune_crs(t3, A, xd, J.ndiag) == bn and not t3.log
     # multi-vector CRS plan: its own copy of the structure, A's plan untouched
     Am = autotune.tune_spmm_crs(tuner, A, 8, torch.float64, J.ndiag)

@@ -57,6 +57,8 @@ def kernels(A, vt):
         "crs_wave": lambda x: sp.spmv_crs(A, x, use_plan=False),
         "jds": lambda x: sp.spmv_jds(J, x),
         "jds_mi4": lambda x: sp.spmv_jds(J, x, max_iters=4),
+        "jds_tiled": lambda x: sp.spmv_jds_tiled(J, x),
+        "blocked_tiled": lambda x: sp.spmv_jds_blocked_tiled(B, x),
         "blocked": lambda x: sp.spmv_jds_blocked(B, x),
         "blocked_r16": lambda x: sp.spmv_jds_blocked(B, x, rows_per_wave=16),
     }

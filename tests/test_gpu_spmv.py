@@ -40,6 +40,11 @@ def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_
             for w in waves:
                 yield f"jds_u{u}_mi{mi}_w{w}", (lambda J=J, u=u, mi=mi, w=w:
                                                 lambda x, y, a, b: sp.spmv_jds(J, x, y, a, b, u, mi, w))()
+    # the XCD-local tile plan
+    for R in rows_per_wave:
+        for w in waves:
+            yield f"jds_tiled_R{R}_w{w}", (lambda J=J, R=R, w=w: lambda x, y, a, b: sp.spmv_jds_tiled(
+                J, x, y, a, b, max_iters=max_iters[-1], rows_per_wave=R, wg_waves=w))()
     for C in Cs:
         B = sp.jds_blocked_from_jds(J, C)
         for R in rows_per_wave:
@@ -355,3 +360,64 @@ def test_row_shard_local_then_remote(g):
     y = sp.spmv_jds(JL, xd[r0:r1])
     sp.spmv_jds(JR, xd, y, beta=1.0)
     assert max_err(y, want, D) <= FP64_TOL
+
+
+def tile_rows(tiles, nt):
+    """Rows covered by each record of a tile plan (first row, row count)."""
+    T = to_np(tiles[:2 * nt]).reshape(-1, 2).astype(np.int64)
+    return T[:, 0], T[:, 1] >> 8
+
+
+@pytest.mark.parametrize("symperm", [False, True])
+def test_xcd_local_tile_plans(symperm):
+    """Long runs of one row length (here 1, 2 and 3 entries, over 10,000 rows
+    each) are cut into XCD pieces, the rest dealt: every row is covered by
+    exactly one record, blocked records stay inside one slice, and the tiled
+    launches agree with the oracle (FP64, FP32 values, FP32 vectors)."""
+    rng = np.random.default_rng(41)
+    n = 60000
+    lengths = rng.choice([0, 1, 2, 3, 5], size=n, p=[0.05, 0.3, 0.3, 0.3, 0.05])
+    lengths[rng.choice(n, 30, replace=False)] = rng.integers(100, 3000, 30)      # rows beyond max_iters
+    rows = np.repeat(np.arange(n), lengths).astype(np.int32)
+    cols = np.concatenate([rng.choice(n, L, replace=False) for L in lengths if L]).astype(np.int32)
+    vals = rng.standard_normal(len(rows))
+    R = oracle.csr_from_coo(n, n, rows, cols, vals)
+    A = gpu_csr(sp, rows, cols, vals, n, n)
+    J = sp.jds_from_csr(A, symperm=symperm)
+    x = rng.uniform(-1, 1, n)
+    xp = x[to_np(J.perm)] if symperm else x
+    want = oracle.spmv_crs(R, x)
+    D = oracle.row_absdot(R, x)
+    unperm = (lambda y: y[np.argsort(to_np(J.perm))]) if symperm else (lambda y: y)
+    for mi, rpw, w in ((0, 0, 0), (32, 0, 4), (64, 16, 8)):
+        tiles, nt, h_plan = sp.spmv_jds_tiles(J, mi, rpw, w)
+        r0, cnt = tile_rows(tiles, nt)
+        cover = np.zeros(n, np.int64)
+        np.add.at(cover, np.concatenate([np.arange(a, a + m) for a, m in zip(r0, cnt)]), 1)
+        assert (cover == 1).all() and h_plan[0] == 0 and h_plan[8] == nt
+        got = unperm(to_np(sp.spmv_jds_tiled(J, to_dev(xp), max_iters=mi, rows_per_wave=rpw, wg_waves=w)))
+        assert oracle.rel_err(got, want, D).max() <= FP64_TOL, (mi, rpw, w)
+        for C in (64, 256):
+            B = sp.jds_blocked_from_jds(J, C)
+            tiles, nt, h_plan = sp.spmv_jds_blocked_tiles(B, mi, rpw, w)
+            r0, cnt = tile_rows(tiles, nt)
+            assert np.all(r0 // C == (r0 + cnt - 1) // C)                     # inside one slice
+            cover = np.zeros(n, np.int64)
+            np.add.at(cover, np.concatenate([np.arange(a, a + m) for a, m in zip(r0, cnt)]), 1)
+            assert (cover == 1).all()
+            got = unperm(to_np(sp.spmv_jds_blocked_tiled(B, to_dev(xp), max_iters=mi, rows_per_wave=rpw,
+                                                         wg_waves=w)))
+            assert oracle.rel_err(got, want, D).max() <= FP64_TOL, (C, mi, rpw, w)
+    # FP32 values with FP64 and FP32 vectors, against the oracle on the
+    # rounded values and vectors: gamma_{L+1}(2^-24) D (+ 2^-24 D for FP32 y)
+    Jq = J.with_values(sp.spmv_convert_values(J.jd_val, torch.float32))
+    Rq = oracle.CSR(n, n, R.row_ptr, R.col, oracle.round_f32(R.val).astype(np.float64))
+    u = 2.0 ** -24
+    for f32x in (False, True):
+        xq = oracle.round_f32(x).astype(np.float64) if f32x else x
+        wq, Dq = oracle.spmv_crs(Rq, xq), oracle.row_absdot(Rq, xq)
+        L = Rq.row_lengths() + 1
+        lim = (L * u / (1 - L * u)) * Dq + (u * Dq if f32x else 0)
+        xd = to_dev((xq[to_np(J.perm)] if symperm else xq).astype(np.float32 if f32x else np.float64))
+        got = unperm(to_np(sp.spmv_jds_tiled(Jq, xd)).astype(np.float64))
+        assert np.all(np.abs(got - wq) <= lim), f32x
