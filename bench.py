@@ -872,14 +872,14 @@ def hamiltonian_kernels(sp, H, y):
             ("dia_sym_sliced_remainder", lambda: sp.spmv_dia(Dy, x, y), bytes_dia(Dy, 8, 8))]
 
 
-def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000, sweep=False):
+def suite_hamiltonian(torch, sp, dev, steps, keep=None, n_sample=4000, sweep=False, tune_cache=""):
     """The Hamiltonian-shaped products: time, rate, and agreement with the
     library's FP64 CRS product.  With `keep` (a dict), each product's output
     on a seeded sample of rows and the host triplets are left there for the
     oracle check of the CPU leg.  With `sweep`, blocked JDS in slice order
     (RBJDS) and in SOJDS order over slice heights 64..4096 (the paper's
     block-size dependence, Fig. 7), same launch parameters."""
-    H = load_hamiltonian(torch, sp, dev)
+    H = load_hamiltonian(torch, sp, dev, tune_cache)
     n, nnz, A, D, Ds, Dy = H["n"], H["nnz"], H["A"], H["D"], H["Ds"], H["Dy"]
     y = torch.empty(n, dtype=torch.float64, device=dev)
     ks = hamiltonian_kernels(sp, H, y)
@@ -1394,7 +1394,8 @@ def main():
     HH = {}
     if not args.only and not args.no_hamiltonian:
         print("# DIA hybrid block: Hamiltonian-shaped matrix", file=sys.stderr, flush=True)
-        out["dia_hybrid_hamiltonian"] = suite_hamiltonian(torch, sp, dev, args.steps, keep=HH)
+        out["dia_hybrid_hamiltonian"] = suite_hamiltonian(torch, sp, dev, args.steps, keep=HH,
+                                                           tune_cache=args.tune_cache)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         print("# CPU oracle baseline", file=sys.stderr, flush=True)
