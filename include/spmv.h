@@ -193,7 +193,7 @@ spmv_status spmv_jds_blocked_windowed_from_csr(int32_t n, int64_t nnz, const int
  * by workgroups of (wg_waves / S) * R rows, one record of two int32 each
  * (first row; R, S and row count packed).  When the depths never increase
  * (the globally sorted order) the records are dealt as in spmv_jds_tiles,
- * with slices for rows: each run of equal-depth slices of at least 4,096
+ * with slices for rows: each run of equal-depth slices of at least 1,024
  * rows in 8 contiguous pieces, one per XCD, the rest for equal cost.
  * Otherwise (e.g. the windowed order, whose windows already keep
  * neighbouring rows together) they are cut into 8 contiguous ranges of about
@@ -299,7 +299,7 @@ spmv_status spmv_jds_blocked_tiled(int32_t n, const int32_t *perm, int32_t C, in
  * length sort (stable) keeps the rows of one length in original order, and a
  * length class draws its rows from the whole matrix; dealt round robin, the
  * rows of one region of the matrix land on every XCD, each fetching that
- * region's band of x into its own L2.  Here each run of at least 4,096 rows
+ * region's band of x into its own L2.  Here each run of at least 1,024 rows
  * of one length is cut into 8 contiguous pieces, piece k for XCD k (one
  * eighth of those rows each, neighbours in the original order); every other
  * row group (rows longer than max_iters diagonals, in 64-row chunks wanting

@@ -712,8 +712,9 @@ static spmv_status launch_jds_t(const JdsArgs &a, const JdsPlan &P, int unroll, 
 //   U: rows per unit (1 for JDS rows, C for slices); chunk: rows per split
 //     decision (64 for JDS, C for slices: a record never crosses a slice).
 // Runs of at least this many rows of one length are cut into 8 XCD pieces
-// (measured on the power-law matrix: 4,096 against 16,384).
-constexpr int64_t TILE_LOCAL_MIN_RUN = 4096;
+// (JDS on the power-law matrix: 512 and 1,024 rows 342 µs, 2,048 and 4,096
+// rows 348 µs, 16,384 rows 353 µs, the class plan 360 µs).
+constexpr int64_t TILE_LOCAL_MIN_RUN = 1024;
 
 template <typename F>
 static void plan_tiles_local(int32_t n, int32_t U, int64_t n_units, F unit_len, int32_t max_iters, int forced_rlog,
