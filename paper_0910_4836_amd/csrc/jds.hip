@@ -706,7 +706,9 @@ static spmv_status launch_jds_t(const JdsArgs &a, const JdsPlan &P, int unroll, 
 // to XCD k, so each XCD's short rows come from one eighth of the original
 // rows; the remaining records (long rows, short runs) are dealt to the XCDs
 // for equal cost, longest first.  Each XCD walks its dealt records (in
-// sorted order), then its pieces.
+// sorted order), then its pieces ordered by their place inside their runs
+// (all lengths side by side), so that it moves through its eighth of the
+// original rows once instead of once per length.
 //   unit_len(u): length of unit u (a row, or a slice's depth); units are
 //     non-increasing in length; unit u spans rows [u*U, min((u+1)*U, n)).
 //   U: rows per unit (1 for JDS rows, C for slices); chunk: rows per split
@@ -722,18 +724,19 @@ static void plan_tiles_local(int32_t n, int32_t U, int64_t n_units, F unit_len, 
 {
     struct Rec {
         int32_t row0, code;
-        double cost;
+        double cost, pos;   // pos: place of the record's first unit inside its length run, in [0, 1)
     };
     auto split_of = [&](int64_t L, int &rlog, int &slog) {
         int W = 1;
         while (W < 128 && (int64_t)W * max_iters < L) W <<= 1;
         split_for(W, forced_rlog, waves, rlog, slog);
     };
-    auto records = [&](int64_t a0, int64_t a1, int rlog, int slog, int64_t L, std::vector<Rec> &out) {
+    auto records = [&](int64_t a0, int64_t a1, int rlog, int slog, int64_t L, std::vector<Rec> &out,
+                       double pos = 0.0) {
         const int64_t rpw = (int64_t)(waves >> slog) << rlog;
         for (int64_t r = a0; r < a1; r += rpw) {
             const int64_t nr = std::min<int64_t>(rpw, a1 - r);
-            out.push_back({(int32_t)r, rlog | (slog << 4) | (int32_t)(nr << 8), (double)nr * L + 64.0 * waves});
+            out.push_back({(int32_t)r, rlog | (slog << 4) | (int32_t)(nr << 8), (double)nr * L + 64.0 * waves, pos});
         }
     };
     auto row_end = [&](int64_t u) { return std::min<int64_t>(u * U, n); };
@@ -778,9 +781,12 @@ static void plan_tiles_local(int32_t n, int32_t U, int64_t n_units, F unit_len, 
         if (row_end(j) - i * U >= min_run_rows) {
             for (int k = 0; k < 8; ++k) {
                 const int64_t u0 = i + (j - i) * k / 8, u1 = i + (j - i) * (k + 1) / 8;
+                const size_t first = pieces[k].size();
                 if (U == 1) records(u0, u1, rlog, slog, L, pieces[k]);
                 else
                     for (int64_t u = u0; u < u1; ++u) records(u * U, row_end(u + 1), rlog, slog, L, pieces[k]);
+                for (size_t t = first; t < pieces[k].size(); ++t)
+                    pieces[k][t].pos = (double)(pieces[k][t].row0 / U - i) / (double)(j - i);
             }
         } else if (U == 1) {
             records(i, j, rlog, slog, L, others);
@@ -789,8 +795,11 @@ static void plan_tiles_local(int32_t n, int32_t U, int64_t n_units, F unit_len, 
         }
         i = j;
     }
+    // pieces at one place of their runs come from the same stretch of
+    // original rows, so their band gathers meet in L2
     double load[8];
     for (int k = 0; k < 8; ++k) {
+        std::stable_sort(pieces[k].begin(), pieces[k].end(), [](const Rec &a, const Rec &b) { return a.pos < b.pos; });
         load[k] = 0;
         for (const Rec &r : pieces[k]) load[k] += r.cost;
     }

@@ -371,9 +371,10 @@ def tile_rows(tiles, nt):
 @pytest.mark.parametrize("symperm", [False, True])
 def test_xcd_local_tile_plans(symperm):
     """Long runs of one row length (here 1, 2 and 3 entries, over 10,000 rows
-    each) are cut into XCD pieces, the rest dealt: every row is covered by
-    exactly one record, blocked records stay inside one slice, and the tiled
-    launches agree with the oracle (FP64, FP32 values, FP32 vectors)."""
+    each) are cut into XCD pieces, walked by place in their run, the rest
+    dealt: every row is covered by exactly one record, blocked records stay
+    inside one slice, and the tiled launches agree with the oracle (FP64,
+    FP32 values, FP32 vectors)."""
     rng = np.random.default_rng(41)
     n = 60000
     lengths = rng.choice([0, 1, 2, 3, 5], size=n, p=[0.05, 0.3, 0.3, 0.3, 0.05])
@@ -389,12 +390,27 @@ def test_xcd_local_tile_plans(symperm):
     want = oracle.spmv_crs(R, x)
     D = oracle.row_absdot(R, x)
     unperm = (lambda y: y[np.argsort(to_np(J.perm))]) if symperm else (lambda y: y)
+    lens = np.diff(J.h_jd_ptr)
+    rl = np.searchsorted(-lens, -np.arange(n), side="left")      # length of the r-th sorted row
     for mi, rpw, w in ((0, 0, 0), (32, 0, 4), (64, 16, 8)):
         tiles, nt, h_plan = sp.spmv_jds_tiles(J, mi, rpw, w)
         r0, cnt = tile_rows(tiles, nt)
         cover = np.zeros(n, np.int64)
         np.add.at(cover, np.concatenate([np.arange(a, a + m) for a, m in zip(r0, cnt)]), 1)
         assert (cover == 1).all() and h_plan[0] == 0 and h_plan[8] == nt
+        # pieces (rows up to max_iters long, in runs of >= 1,024 of one
+        # length): XCD k holds the k-th eighth of each run and walks its
+        # pieces by their place in the run
+        Lr = rl[r0]
+        start, end = np.searchsorted(-rl, -Lr, side="left"), np.searchsorted(-rl, -Lr, side="right")
+        place = (r0 - start) / (end - start)
+        piece = (Lr <= (mi or 32)) & (end - start >= 1024)
+        assert piece.sum() >= 8 * 5                  # five short lengths, each cut in 8
+        for k in range(8):
+            p, e = place[h_plan[k]:h_plan[k + 1]], (end - start)[h_plan[k]:h_plan[k + 1]]
+            sel = piece[h_plan[k]:h_plan[k + 1]]
+            assert np.all(np.diff(p[sel]) >= 0), (mi, rpw, w, k)
+            assert np.all(p[sel] > k / 8 - 1 / e[sel]) and np.all(p[sel] < (k + 1) / 8), (mi, rpw, w, k)
         got = unperm(to_np(sp.spmv_jds_tiled(J, to_dev(xp), max_iters=mi, rows_per_wave=rpw, wg_waves=w)))
         assert oracle.rel_err(got, want, D).max() <= FP64_TOL, (mi, rpw, w)
         for C in (64, 256):
