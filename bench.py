@@ -431,7 +431,7 @@ def load_powerlaw(torch, sp, dev, tune_cache=""):
     BW = timed("jds_blocked_windowed_from_csr_ms", lambda: sp.jds_blocked_windowed_from_csr(A, wC, wS))
     timed("windowed_tile_plan_ms", lambda: sp.spmv_jds_blocked_tiles(BW, 32, 0, wW))
     host = (r, c, v, n, x)
-    tune = {"crs_block_nnz": crs_bn, "jds_unroll": jds_u, "jds_max_iters": jds_mi, "jds_wg_waves": jds_w,
+    tune = {"crs_block_nnz": crs_bn, "crs_staged": A.staged, "jds_unroll": jds_u, "jds_max_iters": jds_mi, "jds_wg_waves": jds_w,
             "jds_tiled": jds_tiled, "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU,
             "blocked_wg_waves": bW, "blocked_tiled": blk_tiled, "windowed_sigma": wS, "windowed_C": wC,
             "windowed_unroll": wU, "windowed_wg_waves": wW}
@@ -706,7 +706,7 @@ def load_symdiag(torch, sp, dev, tune_cache=""):
     torch.cuda.synchronize()
     setup["crs_sym_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
     sym_bn = autotune.tune_crs_sym(tuner, S, x, J.ndiag // 2 + 1)
-    tune = {"crs_block_nnz": crs_bn, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw,
+    tune = {"crs_block_nnz": crs_bn, "crs_staged": A.staged, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw,
             "jds_tiled": jds_tiled, "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU,
             "blocked_wg_waves": bW, "blocked_tiled": blk_tiled, "crs_sym_block_nnz": sym_bn}
     return dict(A=A, J=J, B=B, D=Dd, Ds=Ds, S=S, x=x, n=n, nnz=A.nnz, tune=tune, setup=setup, host=(r, c, v, n))
@@ -852,7 +852,8 @@ def load_hamiltonian(torch, sp, dev, tune_cache=""):
     ju, jm, jw = tuner.tune_jds(J, x)
     bC, bR, bU, bW = tuner.tune_blocked(J, x)
     B = sp.jds_blocked_from_jds(J, bC)
-    T = {"jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw, "jds_tiled": tuner.tune_jds_launch(J, x, ju, jm, jw),
+    T = {"crs_staged": A.staged, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw,
+         "jds_tiled": tuner.tune_jds_launch(J, x, ju, jm, jw),
          "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU, "blocked_wg_waves": bW,
          "blocked_tiled": tuner.tune_blocked_launch(B, x, bR, bU, bW)}
     return {"n": n, "nnz": nnz, "x": x, "A": A, "J": J, "B": B, "D": sp.dia_from_csr(A),

@@ -252,6 +252,24 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
                      double alpha, double beta, const int32_t *plan, int32_t n_blocks,
                      int32_t block_nnz, void *stream);
 
+/* CRS kernel, staged (paper Section 2, CRS kernel): the same product over the
+ * same plan as spmv_crs, with the gathers issued in row order.  A block's
+ * col/val are first copied to LDS in entry order; then each row's entries
+ * are walked by G lanes (G = the largest power of two with G * rows <= 256,
+ * at most 64; one lane per row in a block of more than 256 rows), so that a
+ * wavefront's gather touches the same entry position of consecutive rows.
+ * Rows of a multi-row block are summed per lane in entry order with fused
+ * multiply-adds, then by a fixed shuffle tree over the G lanes; single-row
+ * blocks are summed as in spmv_crs.  Accumulator types, argument meaning and
+ * errors as for spmv_crs, except that plan is required (NULL ->
+ * SPMV_ERR_INVALID_ARG).  The kernel trusts the plan: every multi-row block holds
+ * at most block_nnz entries (LDS holds ceil(block_nnz / 1024) * 1024 entries
+ * of values and indices).  Asynchronous. */
+spmv_status spmv_crs_staged(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
+                            const void *val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
+                            double alpha, double beta, const int32_t *plan, int32_t n_blocks,
+                            int32_t block_nnz, void *stream);
+
 /* JDS kernel (paper Section 2, JDS listing; NBJDS/NUJDS refinements): each
  * lane owns one permuted row and walks the jagged diagonals that reach it,
  * `unroll` diagonals at a time (2, 4 or 8; 0 = default).  Rows whose length

@@ -64,6 +64,7 @@ SIGNATURES = {
     "spmv_transpose_workspace_size": (_sz, [_i32, _i32, _i64]),
     "spmv_transpose_csr": (_int, [_i32, _i32, _i64, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "spmv_crs": (_int, [_i32, _i32, _p, _p, _p, _int, _p, _p, _int, _f64, _f64, _p, _i32, _i32, _p]),
+    "spmv_crs_staged": (_int, [_i32, _i32, _p, _p, _p, _int, _p, _p, _int, _f64, _f64, _p, _i32, _i32, _p]),
     "spmv_jds": (_int, [_i32, _p, _p, _i32p, _i32, _p, _p, _int, _p, _p, _int, _f64, _f64, _i32, _i32, _i32, _u32,
                         _p]),
     "spmv_jds_blocked": (_int, [_i32, _p, _i32, _i32, _p, _p, _i32p, _p, _p, _int, _p, _p, _int, _f64, _f64, _i32,

@@ -33,6 +33,7 @@ U_CANDIDATES = (2, 4, 8)
 MAX_ITERS_CANDIDATES = (0, 64, 128)  # 0: the library default
 W_CANDIDATES = (16, 8, 4)            # wavefronts per workgroup
 BLOCK_NNZ_CANDIDATES = (512, 1024, 2048)
+STAGED_BLOCK_NNZ_CANDIDATES = (512, 1024, 2048, 4096)
 SIGMA_CANDIDATES = (16384, 65536, 262144)   # windowed order: rows per window
 
 
@@ -246,24 +247,30 @@ class Autotuner:
 
 
 def tune_crs(tuner: "Autotuner", A: S.CSR, x: torch.Tensor, longest: int,
-             candidates=BLOCK_NNZ_CANDIDATES) -> int:
-    """Best entries-per-block of the CRS plan for one large matrix (its
-    longest row passed by the caller); A's plan is rebuilt with it."""
-    sig = "crs:" + signature(A.n_rows, longest, A.nnz)
+             candidates=BLOCK_NNZ_CANDIDATES, staged_candidates=STAGED_BLOCK_NNZ_CANDIDATES) -> int:
+    """Best CRS plan for one large matrix (its longest row passed by the
+    caller): entries per block, and whether the gathers go in entry order
+    (spmv_crs) or row order (spmv_crs_staged).  A's plan is rebuilt with the
+    choice and A.staged set; the block size is returned."""
+    sig = "crs2:" + signature(A.n_rows, longest, A.nnz)
     ent = tuner.cache.get(_device_key(), {}).get(sig)
     if ent is None:
         timings = {}
         y = torch.empty(A.n_rows, dtype=x.dtype, device=x.device)
-        for bn in candidates:
-            Ab = S.spmv_crs_plan(S.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
-            timings[bn] = _time(lambda: S.spmv_crs(Ab, x, y))
-            del Ab
+        for staged, cands in ((False, candidates), (True, staged_candidates)):
+            for bn in cands:
+                Ab = S.spmv_crs_plan(S.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
+                Ab.staged = staged
+                timings[(staged, bn)] = _time(lambda: S.spmv_crs(Ab, x, y))
+                del Ab
         best = min(timings, key=timings.get)
-        tuner.log.append({"signature": sig, "timings_ms": {f"block{b}": round(t, 5) for b, t in timings.items()}})
-        ent = {"block_nnz": best, "ms": round(timings[best], 5)}
+        tuner.log.append({"signature": sig, "timings_ms": {("staged" if st else "block") + str(b): round(t, 5)
+                                                            for (st, b), t in timings.items()}})
+        ent = {"block_nnz": best[1], "staged": best[0], "ms": round(timings[best], 5)}
         tuner.cache.setdefault(_device_key(), {})[sig] = ent
         _store(tuner.cache_path, tuner.cache)
     S.spmv_crs_plan(A, ent["block_nnz"])
+    A.staged = bool(ent["staged"])
     return ent["block_nnz"]
 
 

@@ -17,6 +17,12 @@
 //   * single-row block ("vector" mode): all 256 lanes stride over the row with
 //     fused multiply-adds, then a fixed wave tree and an ordered sum over the
 //     four waves.
+//   * staged kernel (a separate entry point over the same plans): the block's
+//     col/val are copied to LDS in entry order, then the lanes walk the rows
+//     and gather in row order, so that a wavefront's gather holds the same
+//     entry position of consecutive rows.  It pays on banded and diagonal
+//     matrices (fewer x lines per gather instruction for the address units),
+//     not on the power-law rows; the autotuner picks per matrix.
 // Every y element is written once by one lane; no atomics; the summation order
 // depends only on the plan, so results are reproducible.
 // Blocks are remapped so that each XCD walks a contiguous range of rows: the
@@ -196,6 +202,138 @@ __global__ __launch_bounds__(CRS_THREADS) void crs_block_kernel(const int32_t *_
     __shared__ double red[CRS_THREADS / WAVE];
     crs_block_body<VT, XT, XT>(row_ptr, col, val, x, y, plan, xcd_remap(blockIdx.x, gridDim.x), alpha, beta, smem_d,
                                red);
+}
+
+// Staged CRS: the same plan blocks, with the gathers issued in row order
+// instead of entry order.  The block's col/val stream into LDS first
+// (coalesced, as in stream mode); then G lanes per row (one lane per row in a
+// block of more than 256 short rows) walk their row's staged entries, keep
+// CRS_STAGE_U gathers in flight, and accumulate with fused multiply-adds.  A
+// wavefront's gather instruction then holds the same entry position of
+// consecutive rows: on banded and diagonal patterns those are neighbouring
+// columns, a few x lines per instruction instead of one per diagonal the
+// entry-order walk crosses, which is what the address units pay for.
+constexpr int CRS_STAGE_U = 8;
+
+// LDS of the staged kernel: values then column indices of block_nnz entries,
+// each array rounded up to whole trips of the staging loop.
+inline size_t crs_staged_lds_bytes(int32_t block_nnz, size_t val_bytes)
+{
+    return (size_t)ceil_div(block_nnz, CRS_LDS_ROUND) * CRS_LDS_ROUND * (val_bytes + sizeof(int32_t));
+}
+
+template <typename acc_t, bool F64, typename VT, typename XT>
+__device__ __forceinline__ acc_t crs_staged_row(const VT *vs, const int32_t *cs, const XT *__restrict__ x,
+                                                int32_t a, int32_t z, int l, int G)
+{
+    acc_t s = 0;
+    for (int32_t k = a + l; k < z; k += CRS_STAGE_U * G) {
+        int32_t c[CRS_STAGE_U];
+        VT v[CRS_STAGE_U];
+#pragma unroll
+        for (int u = 0; u < CRS_STAGE_U; ++u) {
+            const int32_t kk = min(k + u * G, z - 1);
+            c[u] = cs[kk];
+            v[u] = vs[kk];
+        }
+        XT xv[CRS_STAGE_U];
+#pragma unroll
+        for (int u = 0; u < CRS_STAGE_U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < CRS_STAGE_U; ++u)
+            if (k + u * G < z) s = Acc<F64>::mac(s, v[u], xv[u]);
+    }
+    return s;
+}
+
+template <typename VT, typename XT>
+__global__ __launch_bounds__(CRS_THREADS) void crs_staged_kernel(const int32_t *__restrict__ row_ptr,
+                                                                 const int32_t *__restrict__ col,
+                                                                 const VT *__restrict__ val,
+                                                                 const XT *__restrict__ x, XT *__restrict__ y,
+                                                                 const int32_t *__restrict__ plan, int32_t lds_cap,
+                                                                 double alpha, double beta)
+{
+    extern __shared__ double smem_d[];
+    __shared__ double red[CRS_THREADS / WAVE];
+    constexpr bool F64 = IsF64<VT>::value;
+    typedef typename Acc<F64>::T acc_t;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t r0 = plan[b], r1 = plan[b + 1];
+    const int32_t e0 = row_ptr[r0], e1 = row_ptr[r1];
+    const int32_t nr = r1 - r0, ne = e1 - e0;
+    const int t = (int)threadIdx.x;
+
+    if (nr == 1) {
+        if (!F64 && ne > SPMV_WIDE_ROW_NNZ)
+            crs_vector_row<true, VT, XT, XT>(col, val, x, y, r0, e0, e1, alpha, beta, red, nullptr);
+        else
+            crs_vector_row<F64, VT, XT, XT>(col, val, x, y, r0, e0, e1, alpha, beta, red, nullptr);
+        return;
+    }
+
+    // row bounds, loaded before the staging so that their latency overlaps it:
+    // for at most 256 rows, row g = t / G of the G-lane groups; for more (all
+    // of at most 16 entries, at most 2048 rows), rows t + 256 j, j < 8
+    constexpr int MAXJ = CRS_MAX_SHORT_BLOCK_ROWS / CRS_THREADS;
+    int G = 64;
+    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
+    const int g = t / G, l = t % G;
+    int32_t lo[MAXJ], hi[MAXJ];
+    if (nr <= CRS_THREADS) {
+        lo[0] = g < nr ? row_ptr[r0 + g] : 0;
+        hi[0] = g < nr ? row_ptr[r0 + g + 1] : 0;
+    } else {
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j) {
+            const int32_t q = t + j * CRS_THREADS;
+            lo[j] = q < nr ? row_ptr[r0 + q] : 0;
+            hi[j] = q < nr ? row_ptr[r0 + q + 1] : 0;
+        }
+    }
+
+    // stage the block's entries (ne <= lds_cap; lanes past the end reload
+    // the last entry into slots past ne, which lds_cap covers)
+    VT *vs = reinterpret_cast<VT *>(smem_d);
+    int32_t *cs = reinterpret_cast<int32_t *>(vs + lds_cap);
+    constexpr int U = CRS_STREAM_U;
+    for (int32_t k0 = 0; k0 < ne; k0 += U * CRS_THREADS) {
+        int32_t c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t k = min(k0 + u * CRS_THREADS + t, ne - 1);
+            c[u] = ld_stream(col + e0 + k);
+            v[u] = ld_stream(val + e0 + k);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cs[k0 + u * CRS_THREADS + t] = c[u];
+            vs[k0 + u * CRS_THREADS + t] = v[u];
+        }
+    }
+    __syncthreads();
+
+    if (nr <= CRS_THREADS) {
+        acc_t s = 0;
+        if (g < nr) s = crs_staged_row<acc_t, F64>(vs, cs, x, lo[0] - e0, hi[0] - e0, l, G);
+        s = group_sum(s, G);
+        if (g < nr && l == 0) write_y(y, (int64_t)r0 + g, (double)s, alpha, beta);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j) {
+        const int32_t q = t + j * CRS_THREADS;
+        if (q < nr) {
+            const acc_t s = crs_staged_row<acc_t, F64>(vs, cs, x, lo[j] - e0, hi[j] - e0, 0, 1);
+            write_y(y, (int64_t)r0 + q, (double)s, alpha, beta);
+        }
+    }
+    // rows past 2048 (a caller's plan may hold more rows than the planner's)
+    for (int32_t q = t + MAXJ * CRS_THREADS; q < nr; q += CRS_THREADS) {
+        const acc_t s = crs_staged_row<acc_t, F64>(vs, cs, x, row_ptr[r0 + q] - e0, row_ptr[r0 + q + 1] - e0, 0, 1);
+        write_y(y, (int64_t)r0 + q, (double)s, alpha, beta);
+    }
 }
 
 // Column-split CRS: part k (columns of the k-th eighth, compressed to the rows
@@ -522,6 +660,19 @@ static spmv_status launch_crs(int32_t n_rows, const int32_t *row_ptr, const int3
     return SPMV_OK;
 }
 
+template <typename VT, typename XT>
+static spmv_status launch_crs_staged(const int32_t *row_ptr, const int32_t *col, const void *val, const void *x,
+                                     void *y, double alpha, double beta, const int32_t *plan, int32_t n_blocks,
+                                     int32_t block_nnz, hipStream_t s)
+{
+    if (n_blocks == 0) return SPMV_OK;
+    const int32_t cap = (int32_t)(ceil_div(block_nnz, CRS_LDS_ROUND) * CRS_LDS_ROUND);
+    crs_staged_kernel<VT, XT><<<n_blocks, CRS_THREADS, crs_staged_lds_bytes(block_nnz, sizeof(VT)), s>>>(
+        row_ptr, col, (const VT *)val, (const XT *)x, (XT *)y, plan, cap, alpha, beta);
+    SPMV_CHECK_LAUNCH("spmv_crs_staged");
+    return SPMV_OK;
+}
+
 int32_t crs_default_block_nnz() { return CRS_DEFAULT_BLOCK_NNZ; }
 
 // Greedy host planner shared by spmv_crs_plan and the multi-vector planner.
@@ -612,6 +763,33 @@ spmv_status spmv_crs(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, con
     CRS_CASE(SPMV_F64, double, SPMV_F32, float)
 #undef CRS_CASE
     return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs: dtype combination");
+}
+
+spmv_status spmv_crs_staged(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
+                            const void *val, spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt,
+                            double alpha, double beta, const int32_t *plan, int32_t n_blocks, int32_t block_nnz,
+                            void *stream)
+{
+    SPMV_REQUIRE(n_rows >= 0 && n_cols >= 0, "spmv_crs_staged: negative size");
+    SPMV_REQUIRE(valid_dtype(val_dt) && valid_vec_dtype(vec_dt), "spmv_crs_staged: bad dtype");
+    if (n_rows == 0) return SPMV_OK;
+    SPMV_REQUIRE(row_ptr && y && plan, "spmv_crs_staged: null row_ptr, y or plan");
+    SPMV_REQUIRE(n_blocks >= 0, "spmv_crs_staged: n_blocks < 0");
+    if (block_nnz == 0) block_nnz = CRS_DEFAULT_BLOCK_NNZ;
+    SPMV_REQUIRE(block_nnz >= CRS_THREADS && block_nnz <= CRS_MAX_BLOCK_NNZ,
+                 "spmv_crs_staged: block_nnz must be in [256, 4096]");
+    hipStream_t s = as_stream(stream);
+#define CRSS_CASE(VDT, VT, XDT, XT)                                                                          \
+    if (val_dt == VDT && vec_dt == XDT)                                                                      \
+        return launch_crs_staged<VT, XT>(row_ptr, col_idx, val, x, y, alpha, beta, plan, n_blocks, block_nnz, s);
+    CRSS_CASE(SPMV_F64, double, SPMV_F64, double)
+    CRSS_CASE(SPMV_F32, float, SPMV_F64, double)
+    CRSS_CASE(SPMV_BF16, bf16, SPMV_F64, double)
+    CRSS_CASE(SPMV_F32, float, SPMV_F32, float)
+    CRSS_CASE(SPMV_BF16, bf16, SPMV_F32, float)
+    CRSS_CASE(SPMV_F64, double, SPMV_F32, float)
+#undef CRSS_CASE
+    return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs_staged: dtype combination");
 }
 
 spmv_status spmv_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,

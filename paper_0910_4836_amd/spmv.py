@@ -88,6 +88,7 @@ class CSR:
     plan: Optional[torch.Tensor] = None
     n_blocks: int = 0
     block_nnz: int = 0
+    staged: bool = False        # spmv_crs runs the staged kernel (spmv_crs_staged) over the plan
 
     @property
     def nnz(self) -> int:
@@ -99,7 +100,7 @@ class CSR:
 
     def with_values(self, val: torch.Tensor) -> "CSR":
         return CSR(self.n_rows, self.n_cols, self.row_ptr, self.col_idx, val, self.plan, self.n_blocks,
-                   self.block_nnz)
+                   self.block_nnz, self.staged)
 
 
 @dataclass
@@ -378,12 +379,13 @@ def _out_vec(y, n, x, beta, n_cols):
 
 def spmv_crs(A: CSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
              use_plan: bool = True) -> torch.Tensor:
-    """y = alpha*A x + beta*y with the CRS kernels (spmv_crs)."""
+    """y = alpha*A x + beta*y with the CRS kernels (spmv_crs; spmv_crs_staged
+    when A.staged is set and the plan is used)."""
     y = _out_vec(y, A.n_rows, x, beta, A.n_cols)
     if use_plan and A.plan is None:
         spmv_crs_plan(A)
     plan = A.plan if use_plan else None
-    call("spmv_crs", A.n_rows, A.n_cols, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(x),
+    call("spmv_crs_staged" if (use_plan and A.staged) else "spmv_crs", A.n_rows, A.n_cols, _p(A.row_ptr), _p(A.col_idx), _p(A.val), dtype_code(A.val.dtype), _p(x),
          _p(y), dtype_code(x.dtype), float(alpha), float(beta), _p(plan), A.n_blocks if use_plan else 0,
          A.block_nnz if use_plan else 0, _stream())
     return y

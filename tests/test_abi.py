@@ -54,6 +54,15 @@ def test_host_side_validation_without_gpu():
     assert st == 1 and b"multiple of 64" in lib.spmv_last_error()
     st = lib.spmv_crs(10, 10, None, None, None, 7, None, None, 0, 1.0, 0.0, None, 0, 0, None)
     assert st == 1 and b"dtype" in lib.spmv_last_error()
+    # the staged CRS kernel needs a plan and a block size within [256, 4096]
+    p = ctypes.c_void_p(16)           # a non-null stand-in, never dereferenced (the checks fail first)
+    st = lib.spmv_crs_staged(10, 10, p, p, p, 0, p, p, 0, 1.0, 0.0, None, 1, 1024, None)
+    assert st == 1 and b"plan" in lib.spmv_last_error()
+    st = lib.spmv_crs_staged(10, 10, p, p, p, 0, p, p, 0, 1.0, 0.0, p, 1, 8192, None)
+    assert st == 1 and b"block_nnz" in lib.spmv_last_error()
+    st = lib.spmv_crs_staged(10, 10, p, p, p, 9, p, p, 0, 1.0, 0.0, p, 1, 1024, None)
+    assert st == 1 and b"dtype" in lib.spmv_last_error()
+    assert lib.spmv_crs_staged(0, 10, None, None, None, 0, None, None, 0, 1.0, 0.0, None, 0, 0, None) == 0
     # row-split bounds must run from 0 to n without decreasing
     import numpy as np
     from paper_0910_4836_amd import spmv as spmv_mod

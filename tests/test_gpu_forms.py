@@ -354,7 +354,7 @@ def test_autotuner_batched_and_cache(tmp_path):
     B = sp.jds_blocked_from_jds(J, C_)
     assert max_err(sp.spmv_jds_blocked(B, xd, rows_per_wave=R_, unroll=U2, wg_waves=Wb), want, D) <= FP64_TOL
     bn = autotune.tune_crs(tuner, A, xd, J.ndiag)
-    assert bn in autotune.BLOCK_NNZ_CANDIDATES and A.block_nnz == bn
+    assert bn in autotune.BLOCK_NNZ_CANDIDATES + autotune.STAGED_BLOCK_NNZ_CANDIDATES and A.block_nnz == bn
     assert max_err(sp.spmv_crs(A, xd), want, D) <= FP64_TOL
     # class plan or XCD-local tile plan: a cached boolean, either launch the same y
     jt = tuner.tune_jds_launch(J, xd, U, mi, Wj)

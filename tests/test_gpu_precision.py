@@ -47,7 +47,12 @@ def kernels(A, vt):
     B = sp.jds_blocked_from_jds(J, 64)
     S = sp.Split(A)
     RS = sp.RowSplit(A)
+    As = A.with_values(A.val)
+    if As.plan is None:
+        sp.spmv_crs_plan(As)
+    As.staged = True
     return {
+        "crs_staged": lambda x: sp.spmv_crs(As, x),
         "jds_row_split": lambda x: sp.spmv_jds_row_split(RS, x),
         "blocked_row_split": lambda x: sp.spmv_jds_blocked_row_split(RS, x, rows_per_wave=16),
         "crs_split": lambda x: sp.spmv_crs_split(S, x),

@@ -23,6 +23,11 @@ def all_forms(A, rows_per_wave=(0,), unrolls=(0,), Cs=(64,), symperm=False, max_
     for bn in (256, 4096):
         Ab = sp.spmv_crs_plan(sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
         yield f"crs_b{bn}", (lambda Ab=Ab: lambda x, y, a, b: sp.spmv_crs(Ab, x, y, a, b))()
+    # the staged kernel (gathers in row order) over plans of every block size
+    for bn in (256, 1024, 4096):
+        As = sp.spmv_crs_plan(sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
+        As.staged = True
+        yield f"crs_staged_b{bn}", (lambda As=As: lambda x, y, a, b: sp.spmv_crs(As, x, y, a, b))()
     if split and not symperm:
         S = sp.Split(A)
         w = waves[-1]
@@ -204,6 +209,9 @@ def test_blocks_of_many_short_rows(block_nnz):
     multi = sizes > 1
     assert np.all(rp[plan[1:]][multi] - rp[plan[:-1]][multi] <= block_nnz)
     assert max_err(sp.spmv_crs(A, to_dev(x)), want, D) <= FP64_TOL
+    As = A.with_values(A.val)
+    As.staged = True
+    assert max_err(sp.spmv_crs(As, to_dev(x)), want, D) <= FP64_TOL
     X = rng.uniform(-1, 1, (nc, 9))
     Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda").t()        # column-major (n, k)
     want_X = oracle.spmm_crs(R, X)
@@ -216,7 +224,10 @@ def test_blocks_of_many_short_rows(block_nnz):
     vi = rng.integers(-8, 9, len(r)).astype(np.float64)
     xi = synth.integer_vector(nc, rng)
     Ai = sp.spmv_crs_plan(gpu_csr(sp, r, c, vi, nr, nc), block_nnz)
-    assert np.array_equal(to_np(sp.spmv_crs(Ai, to_dev(xi))), oracle.spmv_crs(oracle.csr_from_coo(nr, nc, r, c, vi), xi))
+    want_i = oracle.spmv_crs(oracle.csr_from_coo(nr, nc, r, c, vi), xi)
+    assert np.array_equal(to_np(sp.spmv_crs(Ai, to_dev(xi))), want_i)
+    Ai.staged = True
+    assert np.array_equal(to_np(sp.spmv_crs(Ai, to_dev(xi))), want_i)
 
 
 def test_split_structure_is_a_column_partition():
