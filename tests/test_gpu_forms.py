@@ -242,7 +242,7 @@ def test_graph_replay_of_single_matrix_kernels():
 
 def test_graph_replay_of_split_dia_and_multivector_calls():
     """The other compute calls are capturable too: column and row split,
-    DIA (full and symmetric) and the interleaved multi-vector products
+    DIA (full and symmetric), the staged CRS kernel and the interleaved multi-vector products
     (staging kernel + product) replay bit-identically to their eager runs,
     with eager work between the replays."""
     r, c, v, n, _, rng = rand_coo(81, 12000, 12000, 0.001, long_rows=6, long_len=2500)
@@ -256,11 +256,13 @@ def test_graph_replay_of_split_dia_and_multivector_calls():
     x = to_dev(rng.uniform(-1, 1, n))
     X = colmajor_from(rng.uniform(-1, 1, (n, 8)), torch.float64)
     ws = sp.spmm_workspace(n, 8, torch.float64, "cuda")
+    Ast = A.with_values(A.val)
+    Ast.staged = True                                                 # the staged CRS kernel
     calls = [lambda y: sp.spmv_crs_split(S, x, y), lambda y: sp.spmv_jds_split(S, x, y),
              lambda y: sp.spmv_jds_row_split(RS, x, y), lambda y: sp.spmv_dia(D, x, y),
-             lambda y: sp.spmv_dia(Ds, x, y), lambda Y: sp.spmm_crs(A, X, Y, ws=ws),
-             lambda Y: sp.spmm_jds(J, X, Y, ws=ws)]
-    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(5)] + \
+             lambda y: sp.spmv_dia(Ds, x, y), lambda y: sp.spmv_crs(Ast, x, y),
+             lambda Y: sp.spmm_crs(A, X, Y, ws=ws), lambda Y: sp.spmm_jds(J, X, Y, ws=ws)]
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(6)] + \
            [sp.colmajor(n, 8, torch.float64, "cuda") for _ in range(2)]
     eager = []
     for fn, o in zip(calls, outs):

@@ -190,7 +190,18 @@ def test_symmetric_diagonals_sampled():
     ju, jm, jw = tuner.tune_jds(J, xd)
     bC, bR, bU, bW = tuner.tune_blocked(J, xd)
     Bt = sp.jds_blocked_from_jds(J, bC)
-    for name, fn in (("crs", lambda: sp.spmv_crs(A, xd)), ("jds", lambda: sp.spmv_jds(J, xd)),
+    # CRS as the bench runs it (autotuned plan and kernel), and the staged
+    # kernel at the block sizes the autotuner picks from on this matrix
+    At = sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val)
+    autotune.tune_crs(tuner, At, xd, J.ndiag)
+    staged = {}
+    for bn in (2048, 4096):
+        staged[bn] = sp.spmv_crs_plan(sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
+        staged[bn].staged = True
+    for name, fn in (("crs_tuned", lambda: sp.spmv_crs(At, xd)),
+                     ("crs_staged_2048", lambda: sp.spmv_crs(staged[2048], xd)),
+                     ("crs_staged_4096", lambda: sp.spmv_crs(staged[4096], xd)),
+                     ("crs", lambda: sp.spmv_crs(A, xd)), ("jds", lambda: sp.spmv_jds(J, xd)),
                      ("blocked", lambda: sp.spmv_jds_blocked(B, xd)),
                      ("jds_tuned", lambda: sp.spmv_jds(J, xd, unroll=ju, max_iters=jm, wg_waves=jw)),
                      ("blocked_tuned", lambda: sp.spmv_jds_blocked(Bt, xd, rows_per_wave=bR, unroll=bU,
@@ -221,7 +232,9 @@ def test_symmetric_diagonals_sampled():
         lim = gamma(subq.row_lengths() + 1, U32) * oracle.row_absdot(subq, x)
         Jq = J.with_values(sp.spmv_convert_values(J.jd_val, vdt))
         Bq = B.with_values(sp.spmv_convert_values(B.bl_val, vdt))
-        for name, fn in (("jds", lambda: sp.spmv_jds(Jq, xd)), ("blocked", lambda: sp.spmv_jds_blocked(Bq, xd))):
+        Aq = staged[4096].with_values(sp.spmv_convert_values(A.val, vdt))
+        for name, fn in (("jds", lambda: sp.spmv_jds(Jq, xd)), ("blocked", lambda: sp.spmv_jds_blocked(Bq, xd)),
+                         ("crs_staged", lambda: sp.spmv_crs(Aq, xd))):
             assert np.all(np.abs(to_np(fn())[rows] - wq) <= lim), (vdt, name)
 
 
@@ -241,6 +254,12 @@ def test_hamiltonian_shaped_dia_sampled():
     xd = to_dev(x)
     e = oracle.rel_err(to_np(sp.spmv_crs(A, xd))[rows], want, D).max()
     assert e <= FP64_TOL, f"crs: {e:.3e}"
+    for bn in (2048, 4096):                          # the staged CRS kernel
+        As = sp.spmv_crs_plan(sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val), bn)
+        As.staged = True
+        e = oracle.rel_err(to_np(sp.spmv_crs(As, xd))[rows], want, D).max()
+        assert e <= FP64_TOL, f"crs staged {bn}: {e:.3e}"
+        del As
     for sym in (False, True):
         Dc = sp.dia_from_csr(A, symmetric=sym)
         Ds = sp.dia_from_csr(A, symmetric=sym, sliced=True)
