@@ -369,6 +369,10 @@ def test_autotuner_batched_and_cache(tmp_path):
     assert t3.tune_jds_launch(J, xd, U, mi, Wj) == jt and t3.tune_blocked_launch(B, xd, R_, U2, Wb) == bt
     assert not t3.log
     assert autotune.tune_crs(t3, A, xd, J.ndiag) == bn and not t3.log
+    # the kernel choice (entry or row order) comes back from the cache too
+    A2 = sp.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val)
+    assert autotune.tune_crs(t3, A2, xd, J.ndiag) == bn and A2.staged == A.staged and not t3.log
+    assert max_err(sp.spmv_crs(A2, xd), want, D) <= FP64_TOL
     # multi-vector CRS plan: its own copy of the structure, A's plan untouched
     Am = autotune.tune_spmm_crs(tuner, A, 8, torch.float64, J.ndiag)
     assert Am.block_nnz in (256, 512, 1024) and A.block_nnz == bn and Am.plan is not A.plan
