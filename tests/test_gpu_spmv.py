@@ -448,3 +448,29 @@ def test_xcd_local_tile_plans(symperm):
         xd = to_dev((xq[to_np(J.perm)] if symperm else xq).astype(np.float32 if f32x else np.float64))
         got = unperm(to_np(sp.spmv_jds_tiled(Jq, xd)).astype(np.float64))
         assert np.all(np.abs(got - wq) <= lim), f32x
+
+
+def test_caller_plan_with_more_rows_than_the_planner_makes():
+    """A caller's plan may hold more than 2,048 rows in one block (the planner
+    never does): both CRS kernels accept any plan whose multi-row blocks stay
+    within block_nnz entries; the staged kernel walks rows past 2,048 in its
+    tail loop.  Rows of 0-2 entries, blocks of 3,000 and 2,000 rows."""
+    rng = np.random.default_rng(77)
+    nr, nc = 5000, 3000
+    lens = rng.integers(0, 3, nr)
+    assert lens[:3000].sum() <= 4096 and lens[3000:].sum() <= 4096
+    r = np.repeat(np.arange(nr, dtype=np.int32), lens)
+    c = np.concatenate([rng.choice(nc, L, replace=False) for L in lens]).astype(np.int32)
+    v = rng.standard_normal(len(r))
+    x = rng.uniform(-1, 1, nc)
+    y0 = rng.uniform(-1, 1, nr)
+    R = oracle.csr_from_coo(nr, nc, r, c, v)
+    want = oracle.spmv_crs(R, x, y0, 1.5, -0.25)
+    D = 1.5 * oracle.row_absdot(R, x) + 0.25 * np.abs(y0)
+    A = gpu_csr(sp, r, c, v, nr, nc)
+    A.plan = torch.tensor([0, 3000, nr], dtype=torch.int32, device="cuda")
+    A.n_blocks, A.block_nnz = 2, 4096
+    for staged in (False, True):
+        A.staged = staged
+        got = sp.spmv_crs(A, to_dev(x), to_dev(y0.copy()), 1.5, -0.25)
+        assert max_err(got, want, D) <= FP64_TOL, staged
