@@ -29,7 +29,7 @@
  *    message for the calling thread.  No C++ exception crosses this boundary.
  *  - Results are deterministic: every output element is produced by one
  *    fixed sequence of operations for a given argument set.  The one
- *    exception is spmv_crs_sym (one-triangle storage), whose mirrored terms
+ *    exception is spmv_crs_sym / spmv_crs_sym_staged (one-triangle storage), whose mirrored terms
  *    are added with floating-point atomics.
  *  - Vectors x and y of one call must not overlap (except where stated).
  */
@@ -710,6 +710,20 @@ spmv_status spmv_csr_upper_from_csr(int32_t n, int64_t nnz, const int32_t *row_p
 spmv_status spmv_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
                          spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
                          const int32_t *plan, int32_t n_blocks, int32_t block_nnz, void *stream);
+
+/* One triangle, staged (paper Section 4.2, symmetric storage): the product of
+ * spmv_crs_sym with the gathers and the mirrored-term atomics issued in row
+ * order, as spmv_crs_staged issues its gathers: a block's col/val are copied
+ * to LDS, then G lanes per row (one lane per row above 256 rows) walk the
+ * row's entries, so that a wavefront's atomic adds target neighbouring y
+ * elements on banded and diagonal patterns.  Arguments, dtypes, plan
+ * requirements (multi-row blocks hold at most block_nnz entries), errors and
+ * the atomic (not bit-reproducible) summation as for spmv_crs_sym.
+ * Asynchronous. */
+spmv_status spmv_crs_sym_staged(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                                spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
+                                double beta, const int32_t *plan, int32_t n_blocks, int32_t block_nnz,
+                                void *stream);
 
 /* ======================================================================== */
 /* Many matrices in one launch                                               */

@@ -115,6 +115,7 @@ SIGNATURES = {
     "spmv_csr_upper_workspace_size": (_sz, [_i32]),
     "spmv_csr_upper_from_csr": (_int, [_i32, _i64, _p, _p, _p, _int, _i64p, _p, _p, _p, _p, _sz, _p]),
     "spmv_crs_sym": (_int, [_i32, _p, _p, _p, _int, _p, _p, _int, _f64, _f64, _p, _i32, _i32, _p]),
+    "spmv_crs_sym_staged": (_int, [_i32, _p, _p, _p, _int, _p, _p, _int, _f64, _f64, _p, _i32, _i32, _p]),
     "spmv_batched_plan": (_int, [_i32, _i32p, _i32p, _i64p, _i64p, _i64p, _i64p, _i32p, _i32, _p, _i64, _i64p,
                                  _p]),
     "spmv_batched": (_int, [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _p]),

@@ -275,26 +275,32 @@ def tune_crs(tuner: "Autotuner", A: S.CSR, x: torch.Tensor, longest: int,
 
 
 def tune_crs_sym(tuner: "Autotuner", M: S.SymCSR, x: torch.Tensor, longest: int,
-                 candidates=BLOCK_NNZ_CANDIDATES) -> int:
-    """Best entries-per-block of the plan of a one-triangle matrix (longest
-    row of its upper triangle passed by the caller); M's plan is rebuilt
-    with it."""
+                 candidates=BLOCK_NNZ_CANDIDATES, staged_candidates=STAGED_BLOCK_NNZ_CANDIDATES) -> int:
+    """Best plan of a one-triangle matrix (longest row of its upper triangle
+    passed by the caller): entries per block, and whether the kernel walks
+    the entries in entry order (spmv_crs_sym) or row order
+    (spmv_crs_sym_staged).  M's plan is rebuilt with the choice and
+    M.upper.staged set; the block size is returned."""
     U = M.upper
-    sig = "crs_sym:" + signature(U.n_rows, longest, U.nnz)
+    sig = "crs_sym2:" + signature(U.n_rows, longest, U.nnz)
     ent = tuner.cache.get(_device_key(), {}).get(sig)
     if ent is None:
         timings = {}
         y = torch.empty(U.n_rows, dtype=x.dtype, device=x.device)
-        for bn in candidates:
-            Mb = S.SymCSR(S.spmv_crs_plan(S.CSR(U.n_rows, U.n_cols, U.row_ptr, U.col_idx, U.val), bn))
-            timings[bn] = _time(lambda: S.spmv_crs_sym(Mb, x, y))
-            del Mb
+        for staged, cands in ((False, candidates), (True, staged_candidates)):
+            for bn in cands:
+                Mb = S.SymCSR(S.spmv_crs_plan(S.CSR(U.n_rows, U.n_cols, U.row_ptr, U.col_idx, U.val), bn))
+                Mb.upper.staged = staged
+                timings[(staged, bn)] = _time(lambda: S.spmv_crs_sym(Mb, x, y))
+                del Mb
         best = min(timings, key=timings.get)
-        tuner.log.append({"signature": sig, "timings_ms": {f"block{b}": round(t, 5) for b, t in timings.items()}})
-        ent = {"block_nnz": best, "ms": round(timings[best], 5)}
+        tuner.log.append({"signature": sig, "timings_ms": {("staged" if st else "block") + str(b): round(t, 5)
+                                                            for (st, b), t in timings.items()}})
+        ent = {"block_nnz": best[1], "staged": best[0], "ms": round(timings[best], 5)}
         tuner.cache.setdefault(_device_key(), {})[sig] = ent
         _store(tuner.cache_path, tuner.cache)
     S.spmv_crs_plan(U, ent["block_nnz"])
+    U.staged = bool(ent["staged"])
     return ent["block_nnz"]
 
 

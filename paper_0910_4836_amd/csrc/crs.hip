@@ -613,17 +613,153 @@ __global__ __launch_bounds__(CRS_THREADS) void crs_sym_kernel(const int32_t *__r
     if (g < nr && l == 0) unsafeAtomicAdd(y + r0 + g, alpha * acc);
 }
 
+// One triangle, staged: the block's col/val copied to LDS as in the staged
+// CRS kernel, then G lanes per row (one lane per row above 256 rows) walk
+// their row's entries in row order.  Each lane adds its products into its
+// row's sum and sends the mirrored terms (col > row) to y with FP64 atomics;
+// a wavefront's atomic instruction then targets the same entry position of
+// consecutive rows, i.e. neighbouring y elements on banded and diagonal
+// patterns, instead of one y window per diagonal the entry-order walk
+// crosses.  Each row's own sum goes to y with one more atomic add.
+template <typename VT>
+__device__ __forceinline__ void crs_sym_staged_row(const VT *vs, const int32_t *cs, const double *__restrict__ x,
+                                                   double *__restrict__ y, int32_t i, int32_t a, int32_t z,
+                                                   int l, int G, double alpha, double &s)
+{
+    const double axi = alpha * x[i];
+    for (int32_t k = a + l; k < z; k += CRS_STAGE_U * G) {
+        int32_t c[CRS_STAGE_U];
+        VT v[CRS_STAGE_U];
+#pragma unroll
+        for (int u = 0; u < CRS_STAGE_U; ++u) {
+            const int32_t kk = min(k + u * G, z - 1);
+            c[u] = cs[kk];
+            v[u] = vs[kk];
+        }
+        double xj[CRS_STAGE_U];
+#pragma unroll
+        for (int u = 0; u < CRS_STAGE_U; ++u) xj[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < CRS_STAGE_U; ++u)
+            if (k + u * G < z) {
+                const double av = to_f64(v[u]);
+                s = fma(av, xj[u], s);
+                if (c[u] > i) unsafeAtomicAdd(y + c[u], av * axi);
+            }
+    }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(CRS_THREADS) void crs_sym_staged_kernel(const int32_t *__restrict__ row_ptr,
+                                                                     const int32_t *__restrict__ col,
+                                                                     const VT *__restrict__ val,
+                                                                     const double *__restrict__ x,
+                                                                     double *__restrict__ y,
+                                                                     const int32_t *__restrict__ plan,
+                                                                     int32_t lds_cap, double alpha)
+{
+    extern __shared__ double smem_d[];
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t r0 = plan[b], r1 = plan[b + 1];
+    const int32_t e0 = row_ptr[r0], e1 = row_ptr[r1];
+    const int32_t nr = r1 - r0, ne = e1 - e0;
+    const int t = (int)threadIdx.x;
+    if (nr == 1) {
+        // one (long) row: lanes stride over its entries, straight from memory
+        __shared__ double red[CRS_THREADS / WAVE];
+        const double xi = x[r0];
+        double s = 0.0;
+        for (int32_t e = e0 + t; e < e1; e += CRS_THREADS) {
+            const int32_t c = ld_stream(col + e);
+            const double a = to_f64(ld_stream(val + e));
+            s = fma(a, x[c], s);
+            if (c > r0) unsafeAtomicAdd(y + c, alpha * (a * xi));
+        }
+        s = group_sum(s, WAVE);
+        if (lane_id() == 0) red[t / WAVE] = s;
+        __syncthreads();
+        if (t == 0) {
+            double tot = red[0];
+            for (int w = 1; w < CRS_THREADS / WAVE; ++w) tot += red[w];
+            unsafeAtomicAdd(y + r0, alpha * tot);
+        }
+        return;
+    }
+    constexpr int MAXJ = CRS_MAX_SHORT_BLOCK_ROWS / CRS_THREADS;
+    int G = 64;
+    while (G > 1 && G * nr > CRS_THREADS) G >>= 1;
+    const int g = t / G, l = t % G;
+    int32_t lo[MAXJ], hi[MAXJ];
+    if (nr <= CRS_THREADS) {
+        lo[0] = g < nr ? row_ptr[r0 + g] : 0;
+        hi[0] = g < nr ? row_ptr[r0 + g + 1] : 0;
+    } else {
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j) {
+            const int32_t q = t + j * CRS_THREADS;
+            lo[j] = q < nr ? row_ptr[r0 + q] : 0;
+            hi[j] = q < nr ? row_ptr[r0 + q + 1] : 0;
+        }
+    }
+    VT *vs = reinterpret_cast<VT *>(smem_d);
+    int32_t *cs = reinterpret_cast<int32_t *>(vs + lds_cap);
+    constexpr int U = CRS_STREAM_U;
+    for (int32_t k0 = 0; k0 < ne; k0 += U * CRS_THREADS) {
+        int32_t c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t k = min(k0 + u * CRS_THREADS + t, ne - 1);
+            c[u] = ld_stream(col + e0 + k);
+            v[u] = ld_stream(val + e0 + k);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cs[k0 + u * CRS_THREADS + t] = c[u];
+            vs[k0 + u * CRS_THREADS + t] = v[u];
+        }
+    }
+    __syncthreads();
+    if (nr <= CRS_THREADS) {
+        double s = 0.0;
+        if (g < nr) crs_sym_staged_row(vs, cs, x, y, r0 + g, lo[0] - e0, hi[0] - e0, l, G, alpha, s);
+        s = group_sum(s, G);
+        if (g < nr && l == 0) unsafeAtomicAdd(y + r0 + g, alpha * s);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j) {
+        const int32_t q = t + j * CRS_THREADS;
+        if (q < nr) {
+            double s = 0.0;
+            crs_sym_staged_row(vs, cs, x, y, r0 + q, lo[j] - e0, hi[j] - e0, 0, 1, alpha, s);
+            unsafeAtomicAdd(y + r0 + q, alpha * s);
+        }
+    }
+    for (int32_t q = t + MAXJ * CRS_THREADS; q < nr; q += CRS_THREADS) {
+        double s = 0.0;
+        crs_sym_staged_row(vs, cs, x, y, r0 + q, row_ptr[r0 + q] - e0, row_ptr[r0 + q + 1] - e0, 0, 1, alpha, s);
+        unsafeAtomicAdd(y + r0 + q, alpha * s);
+    }
+}
+
 template <typename VT>
 static spmv_status launch_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col, const void *val,
                                   const double *x, double *y, double alpha, double beta, const int32_t *plan,
-                                  int32_t n_blocks, int32_t block_nnz, hipStream_t s)
+                                  int32_t n_blocks, int32_t block_nnz, bool staged, hipStream_t s)
 {
     const int64_t sgrid = std::min<int64_t>(ceil_div(n, 256), 8192);
     sym_scale_kernel<<<(unsigned)sgrid, 256, 0, s>>>(y, n, beta);
     SPMV_CHECK_LAUNCH("spmv_crs_sym scale");
     if (n_blocks == 0) return SPMV_OK;
-    crs_sym_kernel<VT><<<n_blocks, CRS_THREADS, crs_sym_lds_bytes(block_nnz), s>>>(
-        row_ptr, col, (const VT *)val, x, y, plan, block_nnz, alpha);
+    if (staged) {
+        const int32_t cap = (int32_t)(ceil_div(block_nnz, CRS_LDS_ROUND) * CRS_LDS_ROUND);
+        crs_sym_staged_kernel<VT><<<n_blocks, CRS_THREADS, crs_staged_lds_bytes(block_nnz, sizeof(VT)), s>>>(
+            row_ptr, col, (const VT *)val, x, y, plan, cap, alpha);
+    } else {
+        crs_sym_kernel<VT><<<n_blocks, CRS_THREADS, crs_sym_lds_bytes(block_nnz), s>>>(
+            row_ptr, col, (const VT *)val, x, y, plan, block_nnz, alpha);
+    }
     SPMV_CHECK_LAUNCH("spmv_crs_sym");
     return SPMV_OK;
 }
@@ -792,9 +928,10 @@ spmv_status spmv_crs_staged(int32_t n_rows, int32_t n_cols, const int32_t *row_p
     return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs_staged: dtype combination");
 }
 
-spmv_status spmv_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
-                         spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
-                         const int32_t *plan, int32_t n_blocks, int32_t block_nnz, void *stream)
+static spmv_status crs_sym_entry(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                                 spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
+                                 double beta, const int32_t *plan, int32_t n_blocks, int32_t block_nnz, bool staged,
+                                 void *stream)
 {
     SPMV_REQUIRE(n >= 0, "spmv_crs_sym: negative size");
     SPMV_REQUIRE(valid_dtype(val_dt), "spmv_crs_sym: bad value dtype");
@@ -810,13 +947,29 @@ spmv_status spmv_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col_i
     double *yd = (double *)y;
     switch (val_dt) {
     case SPMV_F64: return launch_crs_sym<double>(n, row_ptr, col_idx, val, xd, yd, alpha, beta, plan, n_blocks,
-                                                 block_nnz, s);
+                                                 block_nnz, staged, s);
     case SPMV_F32: return launch_crs_sym<float>(n, row_ptr, col_idx, val, xd, yd, alpha, beta, plan, n_blocks,
-                                                block_nnz, s);
+                                                block_nnz, staged, s);
     case SPMV_BF16: return launch_crs_sym<bf16>(n, row_ptr, col_idx, val, xd, yd, alpha, beta, plan, n_blocks,
-                                                block_nnz, s);
+                                                block_nnz, staged, s);
     default: return fail(SPMV_ERR_UNSUPPORTED, "spmv_crs_sym: value dtype");
     }
+}
+
+spmv_status spmv_crs_sym(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                         spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha, double beta,
+                         const int32_t *plan, int32_t n_blocks, int32_t block_nnz, void *stream)
+{
+    return crs_sym_entry(n, row_ptr, col_idx, val, val_dt, x, y, vec_dt, alpha, beta, plan, n_blocks, block_nnz,
+                         false, stream);
+}
+
+spmv_status spmv_crs_sym_staged(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                                spmv_dtype val_dt, const void *x, void *y, spmv_dtype vec_dt, double alpha,
+                                double beta, const int32_t *plan, int32_t n_blocks, int32_t block_nnz, void *stream)
+{
+    return crs_sym_entry(n, row_ptr, col_idx, val, val_dt, x, y, vec_dt, alpha, beta, plan, n_blocks, block_nnz,
+                         true, stream);
 }
 
 spmv_status spmv_crs_split(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr_all, const int32_t *dest_all,

@@ -936,17 +936,18 @@ def csr_upper_from_csr(A: CSR) -> SymCSR:
 
 def spmv_crs_sym(S: SymCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0,
                  beta: float = 0.0) -> torch.Tensor:
-    """y = alpha*A x + beta*y from the upper triangle (spmv_crs_sym; FP64 x
-    and y; the mirrored terms are added with atomics, so y may differ in the
-    last bits between runs)."""
+    """y = alpha*A x + beta*y from the upper triangle (spmv_crs_sym, or
+    spmv_crs_sym_staged when S.upper.staged is set; FP64 x and y; the
+    mirrored terms are added with atomics, so y may differ in the last bits
+    between runs)."""
     U = S.upper
     if x.dtype != torch.float64:
         raise TypeError("spmv_crs_sym: x must be float64")
     y = _out_vec(y, U.n_rows, x, beta, U.n_cols)
     if U.plan is None:
         spmv_crs_plan(U)
-    call("spmv_crs_sym", U.n_rows, _p(U.row_ptr), _p(U.col_idx), _p(U.val), dtype_code(U.val.dtype), _p(x), _p(y),
-         dtype_code(x.dtype), float(alpha), float(beta), _p(U.plan), U.n_blocks, U.block_nnz, _stream())
+    call("spmv_crs_sym_staged" if U.staged else "spmv_crs_sym", U.n_rows, _p(U.row_ptr), _p(U.col_idx), _p(U.val),
+         dtype_code(U.val.dtype), _p(x), _p(y), dtype_code(x.dtype), float(alpha), float(beta), _p(U.plan), U.n_blocks, U.block_nnz, _stream())
     return y
 
 

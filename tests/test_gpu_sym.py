@@ -78,15 +78,17 @@ def test_csr_upper_bit_exact(case, dt):
     assert np.array_equal(to_np(S.upper.col_idx), Uo.col)
 
 
+@pytest.mark.parametrize("staged", [False, True])
 @pytest.mark.parametrize("block_nnz", [256, 1024, 4096])
 @pytest.mark.parametrize("case", CASES)
-def test_crs_sym_fp64_parity(case, block_nnz):
+def test_crs_sym_fp64_parity(case, block_nnz, staged):
     r, c, v, n, rng = sym_case(case)
     R = oracle.csr_from_coo(n, n, r, c, v)
     Uo = oracle.csr_upper(R)
     A = gpu_csr(sp, r, c, v, n, n)
     S = sp.csr_upper_from_csr(A)
     sp.spmv_crs_plan(S.upper, block_nnz)
+    S.upper.staged = staged                 # spmv_crs_sym_staged: entries walked in row order
     x = rng.uniform(-1, 1, n)
     y0 = rng.uniform(-1, 1, n)
     D = oracle.row_absdot(R, x) + np.abs(y0)
@@ -101,22 +103,25 @@ def test_crs_sym_fp64_parity(case, block_nnz):
     assert torch.isfinite(got).all()
 
 
+@pytest.mark.parametrize("staged", [False, True])
 @pytest.mark.parametrize("case", ["random", "arrow", "tridiag"])
-def test_crs_sym_integer_exact(case):
+def test_crs_sym_integer_exact(case, staged):
     r, c, v, n, rng = sym_case(case)
     vi = np.where(v > 0, np.ceil(v * 4), np.floor(v * 4))              # integers, symmetric like v
     vi[vi == 0] = 1.0
     R = oracle.csr_from_coo(n, n, r, c, vi)
     A = gpu_csr(sp, r, c, vi, n, n)
     S = sp.csr_upper_from_csr(A)
+    S.upper.staged = staged
     x = synth.integer_vector(n, rng)
     want = oracle.spmv_crs(R, x)
     for _ in range(2):
         assert np.array_equal(to_np(sp.spmv_crs_sym(S, to_dev(x))), want)
 
 
+@pytest.mark.parametrize("staged", [False, True])
 @pytest.mark.parametrize("vdt", [torch.float32, torch.bfloat16])
-def test_crs_sym_reduced_values(vdt):
+def test_crs_sym_reduced_values(vdt, staged):
     r, c, v, n, rng = sym_case("diagonals")
     if vdt == torch.float32:
         vq = oracle.round_f32(v).astype(np.float64)
@@ -126,6 +131,7 @@ def test_crs_sym_reduced_values(vdt):
     A = gpu_csr(sp, r, c, v, n, n)
     S = sp.csr_upper_from_csr(A)
     Sq = S.with_values(sp.spmv_convert_values(S.upper.val, vdt))
+    Sq.upper.staged = staged
     x = rng.uniform(-1, 1, n)
     got = sp.spmv_crs_sym(Sq, to_dev(x))
     assert max_err(got, oracle.spmv_crs(R, x), oracle.row_absdot(R, x)) <= FP64_TOL
@@ -138,9 +144,11 @@ def test_crs_sym_empty_and_errors():
                torch.zeros(0, dtype=torch.float64, device=dev))
     S = sp.csr_upper_from_csr(A)
     assert S.nnz == 0
-    y = torch.full((n,), 3.0, dtype=torch.float64, device=dev)
-    out = sp.spmv_crs_sym(S, torch.ones(n, dtype=torch.float64, device=dev), y, 1.0, 0.5)
-    assert torch.equal(out, torch.full((n,), 1.5, dtype=torch.float64, device=dev))
+    for staged in (False, True):
+        S.upper.staged = staged
+        y = torch.full((n,), 3.0, dtype=torch.float64, device=dev)
+        out = sp.spmv_crs_sym(S, torch.ones(n, dtype=torch.float64, device=dev), y, 1.0, 0.5)
+        assert torch.equal(out, torch.full((n,), 1.5, dtype=torch.float64, device=dev))
     r, c, v, n, rng = sym_case("random")
     S = sp.csr_upper_from_csr(gpu_csr(sp, r, c, v, n, n))
     with pytest.raises(TypeError):
