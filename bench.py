@@ -708,7 +708,8 @@ def load_symdiag(torch, sp, dev, tune_cache=""):
     sym_bn = autotune.tune_crs_sym(tuner, S, x, J.ndiag // 2 + 1)
     tune = {"crs_block_nnz": crs_bn, "crs_staged": A.staged, "jds_unroll": ju, "jds_max_iters": jm, "jds_wg_waves": jw,
             "jds_tiled": jds_tiled, "blocked_C": bC, "blocked_rows_per_wave": bR, "blocked_unroll": bU,
-            "blocked_wg_waves": bW, "blocked_tiled": blk_tiled, "crs_sym_block_nnz": sym_bn}
+            "blocked_wg_waves": bW, "blocked_tiled": blk_tiled, "crs_sym_block_nnz": sym_bn,
+            "crs_sym_staged": S.upper.staged}
     return dict(A=A, J=J, B=B, D=Dd, Ds=Ds, S=S, x=x, n=n, nnz=A.nnz, tune=tune, setup=setup, host=(r, c, v, n))
 
 
